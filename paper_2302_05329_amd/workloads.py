@@ -1,0 +1,215 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module draws parameter points, builds frequency grids, evaluates the analytic
+PSD stand-in and draws coloured Gaussian noise.  It is shared by the GPU path, the
+tests and the CPU oracle's timing, and it deliberately contains none of the
+waveform model's arithmetic: it only produces inputs.
+
+Parameter rows are returned in the (m1, m2, chi1, chi2, D, tc, phic) layout
+(masses in solar masses, D in Mpc, tc in s, phic in rad); `to_param` re-expresses
+them in the other supported parameterisations.
+
+The paper's data (detector PSD files, NR waveforms) are not available, so:
+  * the PSD is the analytic zero-detuned high-power advanced-LIGO fit of Ajith (2011),
+    standing in for the design curves the paper uses for Fisher forecasts and HMC
+    (Sec. 3.2, Sec. 3.3);
+  * noise follows the paper's Sec. 3.3 recipe: Gaussian, consistent with the PSD
+    (real and imaginary parts i.i.d. N(0, S_n / (4 df)));
+  * coefficient-fit targets (Sec. 3.1) are model waveforms built from a perturbed
+    coefficient table instead of NR simulations.
+"""
+import os
+
+import numpy as np
+
+PARAM_MC_ETA = 0
+PARAM_LNMC_ETA_LND = 1
+PARAM_MC_Q = 2
+PARAM_M1M2 = 3
+
+# Solar-mass time GM_sun/c^3 in seconds (IAU 2015 nominal GM_sun); used only to lay out
+# the mass-scaled grid of the coefficient-fit workload (Mf spacing fixed, Sec. 3.1).
+_T_SUN_S = 1.3271244e20 / 299792458.0**3
+
+_DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+def load_lambda(path=None):
+    """The 19x11 coefficient table as a flat float64 array of 209 (row-major)."""
+    if path is None:
+        path = os.path.join(_DATA_DIR, "phenomd_lambda_placeholder.txt")
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(t) for t in line.split()])
+    table = np.asarray(rows, dtype=np.float64)
+    if table.shape != (19, 11):
+        raise ValueError(f"coefficient table {path} has shape {table.shape}, want (19, 11)")
+    return table.reshape(-1).copy()
+
+
+def psd_aligo_zdhp_fit(f):
+    """Analytic one-sided aLIGO zero-detuned high-power PSD fit (Ajith 2011), 1/Hz."""
+    x = np.asarray(f, dtype=np.float64) / 215.0
+    return 1e-49 * (x**-4.14 - 5.0 * x**-2 + 111.0 * (1.0 - x**2 + 0.5 * x**4) / (1.0 + 0.5 * x**2))
+
+
+class Grid:
+    """Uniform frequency grid f_k = f0 + k*df, k < n_bins.
+
+    Bins with f_k < f_min carry no signal; f_ref is the physical frequency at which
+    the phase is referenced.
+    """
+
+    def __init__(self, f0, df, n_bins, f_min=None, f_ref=20.0):
+        self.f0 = float(f0)
+        self.df = float(df)
+        self.n_bins = int(n_bins)
+        self.f_min = float(f0 if f_min is None else f_min)
+        self.f_ref = float(f_ref)
+
+    def freqs(self):
+        k = np.arange(self.n_bins, dtype=np.float64)
+        return self.f0 + k * self.df
+
+    def as_tuple(self):
+        return (self.f0, self.df, self.n_bins, self.f_min, self.f_ref)
+
+    def __repr__(self):
+        return (f"Grid(f0={self.f0}, df={self.df}, n_bins={self.n_bins}, "
+                f"f_min={self.f_min}, f_ref={self.f_ref})")
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def draw_masses(rng, n, lo=5.0, hi=50.0):
+    a = rng.uniform(lo, hi, n)
+    b = rng.uniform(lo, hi, n)
+    return np.maximum(a, b), np.minimum(a, b)
+
+
+def draw_sources(n, seed, *, d_range=None, d_fixed=440.0, tc_range=None, phic_random=False,
+                 chi_max=0.9):
+    """n parameter rows (m1, m2, chi1, chi2, D, tc, phic) with the configs' priors."""
+    rng = _rng(seed)
+    m1, m2 = draw_masses(rng, n)
+    chi1 = rng.uniform(-chi_max, chi_max, n)
+    chi2 = rng.uniform(-chi_max, chi_max, n)
+    if d_range is not None:
+        dist = rng.uniform(d_range[0], d_range[1], n)
+    else:
+        dist = np.full(n, float(d_fixed))
+    tc = rng.uniform(tc_range[0], tc_range[1], n) if tc_range is not None else np.zeros(n)
+    phic = rng.uniform(0.0, 2.0 * np.pi, n) if phic_random else np.zeros(n)
+    return np.stack([m1, m2, chi1, chi2, dist, tc, phic], axis=1)
+
+
+def to_param(rows, param):
+    """Re-express (m1, m2, ...) rows in another parameterisation (input preparation)."""
+    rows = np.asarray(rows, dtype=np.float64)
+    out = rows.copy()
+    m1, m2 = rows[:, 0], rows[:, 1]
+    mt = m1 + m2
+    eta = m1 * m2 / mt**2
+    mc = (m1 * m2) ** 0.6 / mt**0.2
+    if param == PARAM_M1M2:
+        return out
+    if param == PARAM_MC_ETA:
+        out[:, 0], out[:, 1] = mc, eta
+    elif param == PARAM_LNMC_ETA_LND:
+        out[:, 0], out[:, 1], out[:, 4] = np.log(mc), eta, np.log(rows[:, 4])
+    elif param == PARAM_MC_Q:
+        out[:, 0], out[:, 1] = mc, m2 / m1
+    else:
+        raise ValueError(f"unknown parameterisation {param}")
+    return out
+
+
+def complex_noise(psd, df, seed):
+    """Gaussian noise consistent with a one-sided PSD: Re, Im i.i.d. N(0, S/(4 df))."""
+    rng = _rng(seed)
+    sigma = np.sqrt(np.asarray(psd) / (4.0 * df))
+    n = len(sigma)
+    return sigma * rng.standard_normal(n) + 1j * sigma * rng.standard_normal(n)
+
+
+# ----------------------------------------------------------------------------------
+# The five workloads.  Sizes are the full ones; `small=True` gives a shrunken copy
+# with the same structure (for quick parity runs).
+# ----------------------------------------------------------------------------------
+
+def config1(n=1024, seed=1001):
+    """Plain waveform evaluation: 20-1024 Hz, df = 0.25 Hz (4017 bins), D = 440 Mpc."""
+    grid = Grid(20.0, 0.25, 4017, f_min=20.0, f_ref=20.0)
+    theta = draw_sources(n, seed, d_fixed=440.0)
+    return dict(name="C1 waveform_eval 1024x4017", theta=theta, grid=grid)
+
+
+def config2(n=65536, seed=1002):
+    """Batched fused log-likelihood: 20-2048 Hz, df = 0.125 Hz (16225 bins)."""
+    grid = Grid(20.0, 0.125, 16225, f_min=20.0, f_ref=20.0)
+    theta = draw_sources(n, seed, d_range=(100.0, 2000.0), tc_range=(-0.1, 0.1), phic_random=True)
+    f = grid.freqs()
+    psd = psd_aligo_zdhp_fit(f)
+    data = complex_noise(psd, grid.df, seed)
+    return dict(name="C2 loglike+grad 65536x16225", theta=theta, grid=grid, psd=psd,
+                inv_psd=1.0 / psd, data=data)
+
+
+def config3(n=16384, seed=1003):
+    """7x7 Fisher matrices: 20-1024 Hz, df = 0.0625 Hz (16065 bins), config-1 priors."""
+    grid = Grid(20.0, 0.0625, 16065, f_min=20.0, f_ref=20.0)
+    theta = draw_sources(n, seed, d_fixed=440.0)
+    psd = psd_aligo_zdhp_fit(grid.freqs())
+    return dict(name="C3 fisher 16384x16065", theta=theta, grid=grid, psd=psd, inv_psd=1.0 / psd)
+
+
+def config4(n=512, seed=1004, n_fft=65536, lam0=None, rel_sigma=0.01):
+    """Mismatch gradient over the fit coefficients.
+
+    Total mass fixed at 50 Msun, flat PSD, grid uniform in Mf from 0 to 0.2 with n_fft
+    bins; bins below Mf = 2.5e-3 carry no signal (Sec. 3.1 and its footnote).  Targets
+    share one perturbed table lam* = lam0 * (1 + rel_sigma * xi), xi ~ N(0, I).
+    """
+    rng = _rng(seed)
+    a, b = draw_masses(rng, n)
+    q = b / a
+    mt = 50.0
+    m1 = mt / (1.0 + q)
+    m2 = mt - m1
+    chi1 = rng.uniform(-0.9, 0.9, n)
+    chi2 = rng.uniform(-0.9, 0.9, n)
+    theta = np.stack([m1, m2, chi1, chi2, np.full(n, 440.0), np.zeros(n), np.zeros(n)], axis=1)
+    ms = mt * _T_SUN_S
+    df = 0.2 / (n_fft * ms)
+    grid = Grid(0.0, df, n_fft, f_min=2.5e-3 / ms, f_ref=20.0)
+    if lam0 is None:
+        lam0 = load_lambda()
+    xi = rng.standard_normal(lam0.shape)
+    lam_star = lam0 * (1.0 + rel_sigma * xi)
+    return dict(name="C4 mismatch_grad 512x65536", theta=theta, grid=grid,
+                inv_psd=np.ones(n_fft), lam0=lam0, lam_star=lam_star)
+
+
+def config5(seed=1005):
+    """Learned-proposal sampling: one injection, 20-1024 Hz, df = 0.125 Hz (8033 bins)."""
+    grid = Grid(20.0, 0.125, 8033, f_min=20.0, f_ref=20.0)
+    mc, q = 30.0, 0.8
+    eta = q / (1.0 + q) ** 2
+    mt = mc * eta ** -0.6
+    m1 = mt / (1.0 + q)
+    m2 = mt - m1
+    inj = np.array([m1, m2, 0.3, -0.2, 1.0, 0.0, 0.0])  # D set later for SNR 20
+    psd = psd_aligo_zdhp_fit(grid.freqs())
+    noise = complex_noise(psd, grid.df, seed)
+    return dict(name="C5 flow-MH vs HMC 4096 chains x 8033", inj_unit_distance=inj, grid=grid,
+                psd=psd, inv_psd=1.0 / psd, noise=noise, n_chains=4096, snr=20.0)
+
+
+def paper_timing_grid():
+    """The paper's waveform-timing grid: 24-512 Hz, df = 0.2 Hz (2441 bins)."""
+    return Grid(24.0, 0.2, 2441, f_min=24.0, f_ref=24.0)
