@@ -1,0 +1,144 @@
+/*
+ * phenomd.h — C ABI of the MI355X (gfx950) library for batched IMRPhenomD-structured
+ * waveforms and the noise-weighted products built on them.
+ *
+ * Paper: "ripple: Differentiable and Hardware-Accelerated Waveforms for Gravitational
+ * Wave Data Analysis" (arXiv:2302.05329).  The waveform is the aligned-spin IMRPhenomD
+ * model the paper re-implements (Sec. 2); the products are the noise-weighted inner
+ * product (Eq. 1), the Gaussian likelihood of the HMC study (Sec. 3.3), the Fisher matrix
+ * (Sec. 3.2, Eq. fisher) and the mismatch over the 209 fit coefficients (Sec. 3.1,
+ * Eqs. mismatch and multi_loss).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless stated.
+ *     Arrays are dense, row-major, float64; complex arrays are interleaved (re, im).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and is
+ *     asynchronous: outputs are valid once the stream has synchronised.
+ *   - The library allocates no device memory.  Calls that need scratch take a
+ *     caller-owned `workspace` of at least the size the matching *_workspace_bytes()
+ *     query returns; two calls that run concurrently must not share a workspace.
+ *   - A negative return value is a batch-level error (bad pointer, size, grid or
+ *     enum); nothing is launched and pd_last_error() describes it.  Nothing throws.
+ *   - Per-point physical-domain errors (non-finite input, masses <= 0, eta outside
+ *     (0, 1/4], |chi| > 1, D <= 0, or a source whose model transition frequencies are
+ *     out of order) do not fail the call: the point's outputs are NaN and, when a
+ *     `status` array is given, status[i] = PD_EDOMAIN (else PD_OK).
+ *   - The model is zero outside f_min <= f and M f <= 0.2 (M in seconds).
+ */
+#ifndef PHENOMD_H
+#define PHENOMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PD_OK = 0,
+    PD_EINVAL = -1,       /* bad argument: null pointer, size, grid, enum */
+    PD_EDOMAIN = -2,      /* per-point: parameters outside the model's domain */
+    PD_EHIP = -3,         /* a HIP runtime call failed */
+    PD_ENOMEM = -4,       /* workspace too small */
+    PD_EUNSUPPORTED = -5  /* valid but not supported (e.g. n_fft not 2^16) */
+} pd_status;
+
+typedef enum {
+    PD_FP64 = 0,   /* everything in FP64 */
+    PD_MIXED = 1   /* FP64 phase, shifts, derivatives and accumulation; FP32 amplitude ratio */
+} pd_precision;
+
+/* Layout of one parameter row theta[7]; derivatives are taken w.r.t. the same 7 numbers.
+ * Masses in solar masses, D in Mpc, tc in s, phic in rad (orbital phase: h ~ exp(+2 i phic)). */
+typedef enum {
+    PD_PARAM_MC_ETA = 0,       /* (Mc, eta, chi1, chi2, D, tc, phic)           Sec. 3.3 set  */
+    PD_PARAM_LNMC_ETA_LND = 1, /* (ln Mc, eta, chi1, chi2, ln D, tc, phic)     Fisher set    */
+    PD_PARAM_MC_Q = 2,         /* (Mc, q = m2/m1, chi1, chi2, D, tc, phic)     sampler set   */
+    PD_PARAM_M1M2 = 3          /* (m1, m2, chi1, chi2, D, tc, phic), unsorted               */
+} pd_param;
+
+/* Uniform frequency grid f_k = f0 + k*df (k < n_bins), f in Hz.  Bins with f_k < f_min
+ * carry no signal; f_ref is the physical frequency where the phase is referenced. */
+typedef struct {
+    double f0;
+    double df;
+    int64_t n_bins;
+    double f_min;
+    double f_ref;
+} pd_grid;
+
+/* Operations for the workspace queries. */
+typedef enum {
+    PD_OP_WAVEFORM = 0,
+    PD_OP_LOGLIKE = 1,        /* value only */
+    PD_OP_LOGLIKE_GRAD = 2,
+    PD_OP_FISHER = 3,
+    PD_OP_MISMATCH_GRAD = 4
+} pd_op;
+
+/* Bytes of workspace an operation needs for n points (targets) on an n_bins grid. */
+size_t pd_workspace_bytes(int op, int64_t n, int64_t n_bins);
+
+/* Frequency-domain strain, Sec. 2 (the model the paper implements):
+ *   h_k = A(f_k) exp(-i Psi(f_k)) for each parameter row.
+ * theta   [n][7]              parameter rows, layout `param`
+ * lambda  [209]               fit coefficients, 19 rows x 11 columns (Sec. 3.1)
+ * h_out   [n][n_bins][2]      output, complex128 (zeros on inactive bins)
+ * status  [n] int32 or NULL   per-point status (PD_OK / PD_EDOMAIN)
+ */
+int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* grid,
+                     const double* lambda, int precision, double* h_out, int32_t* status,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Gaussian log-likelihood of Sec. 3.3 with the inner product of Eq. (1) as a Riemann sum:
+ *   lnL = (d|h) - (h|h)/2,  (a|b) = 4 df Re sum_k conj(a_k) b_k / S_k,
+ * fused so the strain is never written, and optionally its gradient w.r.t. theta
+ * (hand-written forward-mode tangents of the per-point coefficients contracted with
+ * per-bin moments; Sec. 2 on derivatives).
+ * data    [n_bins][2]         complex128 data d_k (shared by all points)
+ * inv_psd [n_bins]            1 / S_n(f_k), one-sided PSD in 1/Hz
+ * lnl     [n]                 output
+ * grad    [n][7] or NULL      output d lnL / d theta (NULL: value only)
+ */
+int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid,
+                        const double* lambda, const double* data, const double* inv_psd,
+                        int precision, double* lnl, double* grad, int32_t* status,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Fisher information of one detector, Sec. 3.2 Eq. (fisher): F_pq = (d_p h | d_q h),
+ * p, q over the 7 entries of theta in layout `param`.
+ * F       [n][7][7]           output, symmetric
+ */
+int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid,
+              const double* lambda, const double* inv_psd, double* F, int32_t* status,
+              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Mismatch against fixed targets and its gradient w.r.t. the 209 fit coefficients,
+ * Sec. 3.1 Eqs. (mismatch) and (multi_loss):
+ *   z_j = sum_k w_k conj(h_k) t_k exp(+2 pi i k j / N), j < N = n_bins = 65536,
+ *   m = max_j |z_j| / sqrt((h|h)(t|t)),  M = 1 - m   (max over lag and phase),
+ *   dsum_dlambda = sum over targets of dM / dlambda at the maximising lag.
+ * theta        [nt][7]           source of each target (layout `param`)
+ * targets      [nt][n_bins][2]   target strains t_k, complex128
+ * inv_psd      [n_bins]          1 / S_n (use ones for a flat PSD)
+ * mismatch     [nt]              output
+ * dsum_dlambda [209] or NULL     output (NULL: mismatch only)
+ * lag          [nt] int32 or NULL  output, maximising lag j* (ties: lowest j)
+ */
+int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* grid,
+                     const double* lambda, const double* targets, const double* inv_psd,
+                     double* mismatch, double* dsum_dlambda, int32_t* lag,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Text of the last batch-level error on the calling thread (library-owned, never NULL). */
+const char* pd_last_error(void);
+
+/* Library version string (library-owned). */
+const char* pd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHENOMD_H */

@@ -1,0 +1,97 @@
+"""ctypes binding of libphenomd_hip.so (the C ABI declared in include/phenomd.h).
+
+Argument marshalling only.  The library must have been built (see build.py); a missing
+library is an error, never a silent fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphenomd_hip.so")
+
+PD_OK = 0
+PD_EINVAL = -1
+PD_EDOMAIN = -2
+PD_EHIP = -3
+PD_ENOMEM = -4
+PD_EUNSUPPORTED = -5
+
+PD_FP64 = 0
+PD_MIXED = 1
+
+PD_PARAM_MC_ETA = 0
+PD_PARAM_LNMC_ETA_LND = 1
+PD_PARAM_MC_Q = 2
+PD_PARAM_M1M2 = 3
+
+PD_OP_WAVEFORM = 0
+PD_OP_LOGLIKE = 1
+PD_OP_LOGLIKE_GRAD = 2
+PD_OP_FISHER = 3
+PD_OP_MISMATCH_GRAD = 4
+
+
+class PdGrid(ctypes.Structure):
+    _fields_ = [("f0", ctypes.c_double), ("df", ctypes.c_double), ("n_bins", ctypes.c_int64),
+                ("f_min", ctypes.c_double), ("f_ref", ctypes.c_double)]
+
+
+class PdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"phenomd error {code}: {msg}")
+        self.code = code
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_INT = ctypes.c_int
+_SZ = ctypes.c_size_t
+_GRID = ctypes.POINTER(PdGrid)
+
+# name -> (restype, argtypes); mirrors include/phenomd.h
+SIGNATURES = {
+    "pd_workspace_bytes": (_SZ, [_INT, _I64, _I64]),
+    "pd_waveform_eval": (_INT, [_P, _I64, _INT, _GRID, _P, _INT, _P, _P, _P, _SZ, _P]),
+    "pd_loglike_and_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _INT, _P, _P, _P, _P, _SZ, _P]),
+    "pd_fisher": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pd_mismatch_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pd_hmc_leapfrog": (_INT, [_P, _P, _P, _P, _I64, _INT, ctypes.c_double, _P]),
+    "pd_mh_accept": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _INT, _P, _P]),
+    "pd_flow_forward": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P]),
+    "pd_flow_inverse": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P]),
+    "pd_flow_backward": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pd_adam_step": (_INT, [_P, _P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, _I64, _P]),
+    "pd_flow_param_count": (_I64, [_INT]),
+    "pd_last_error": (ctypes.c_char_p, []),
+    "pd_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2302_05329_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(code):
+    if code != PD_OK:
+        raise PdError(code, lib().pd_last_error().decode())
+    return code
+
+
+def make_grid(f0, df, n_bins, f_min, f_ref):
+    return PdGrid(float(f0), float(df), int(n_bins), float(f_min), float(f_ref))

@@ -1,0 +1,172 @@
+"""Torch-facing wrappers of the C ABI (marshalling only; every step runs in the HIP kernels).
+
+Tensors live on the GPU; calls are enqueued on torch's current stream.
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+FP64 = L.PD_FP64
+MIXED = L.PD_MIXED
+PARAM_MC_ETA = L.PD_PARAM_MC_ETA
+PARAM_LNMC_ETA_LND = L.PD_PARAM_LNMC_ETA_LND
+PARAM_MC_Q = L.PD_PARAM_MC_Q
+PARAM_M1M2 = L.PD_PARAM_M1M2
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype=torch.float64):
+    """Contiguous float64 tensor on the GPU (copies host data)."""
+    if not torch.is_tensor(t):
+        t = torch.as_tensor(t)
+    if t.is_complex():
+        t = torch.view_as_real(t.to(torch.complex128))
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def _need(cond, msg):
+    if not cond:
+        raise ValueError(msg)
+
+
+def _check_shapes(th, lam, nb, data=None, inv_psd=None, targets=None):
+    """Host-side shape checks: the kernels index these arrays without bounds checks."""
+    _need(th.dim() == 2 and th.shape[1] == 7 and th.shape[0] > 0, f"theta must be [n, 7], got {tuple(th.shape)}")
+    _need(lam.numel() == 209, f"lambda must hold 209 coefficients, got {lam.numel()}")
+    if data is not None:
+        _need(tuple(data.shape) == (nb, 2), f"data must be complex [{nb}], got {tuple(data.shape)}")
+    if inv_psd is not None:
+        _need(tuple(inv_psd.shape) == (nb,), f"inv_psd must be [{nb}], got {tuple(inv_psd.shape)}")
+    if targets is not None:
+        _need(tuple(targets.shape) == (th.shape[0], nb, 2),
+              f"targets must be complex [{th.shape[0]}, {nb}], got {tuple(targets.shape)}")
+
+
+def _grid(grid):
+    if isinstance(grid, L.PdGrid):
+        return grid
+    if hasattr(grid, "as_tuple"):
+        grid = grid.as_tuple()
+    return L.make_grid(*grid)
+
+
+class Workspace:
+    """Caller-owned, reusable device scratch (grown on demand, 256-byte aligned)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device="cuda"):
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes + 256:
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        addr = self.buf.data_ptr()
+        off = (-addr) % 256
+        return ctypes.c_void_p(addr + off), nbytes
+
+
+_default_ws = Workspace()
+
+
+def workspace_bytes(op, n, n_bins):
+    return L.lib().pd_workspace_bytes(op, int(n), int(n_bins))
+
+
+def waveform_eval(theta, param, grid, lam, precision=FP64, ws=None):
+    """Complex128 strain [n, n_bins] and int32 status [n]."""
+    ws = ws or _default_ws
+    g = _grid(grid)
+    th = _dev(theta)
+    lam = _dev(lam)
+    _check_shapes(th, lam, g.n_bins)
+    n = th.shape[0]
+    h = torch.empty((n, g.n_bins, 2), dtype=torch.float64, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    wp, wb = ws.get(workspace_bytes(L.PD_OP_WAVEFORM, n, g.n_bins))
+    L.check(L.lib().pd_waveform_eval(_ptr(th), n, param, ctypes.byref(g), _ptr(lam), precision, _ptr(h),
+                                     _ptr(status), wp, wb, _stream()))
+    return torch.view_as_complex(h), status
+
+
+def loglike_and_grad(theta, param, grid, lam, data, inv_psd, want_grad=True, precision=FP64, ws=None):
+    """ln L [n], d lnL / d theta [n, 7] (or None), status [n]."""
+    ws = ws or _default_ws
+    g = _grid(grid)
+    th = _dev(theta)
+    lam = _dev(lam)
+    d = _dev(data)
+    ip = _dev(inv_psd)
+    _check_shapes(th, lam, g.n_bins, data=d, inv_psd=ip)
+    n = th.shape[0]
+    lnl = torch.empty(n, dtype=torch.float64, device="cuda")
+    grad = torch.empty((n, 7), dtype=torch.float64, device="cuda") if want_grad else None
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    op = L.PD_OP_LOGLIKE_GRAD if want_grad else L.PD_OP_LOGLIKE
+    wp, wb = ws.get(workspace_bytes(op, n, g.n_bins))
+    L.check(L.lib().pd_loglike_and_grad(_ptr(th), n, param, ctypes.byref(g), _ptr(lam), _ptr(d), _ptr(ip),
+                                        precision, _ptr(lnl), _ptr(grad), _ptr(status), wp, wb, _stream()))
+    return lnl, grad, status
+
+
+def fisher(theta, param, grid, lam, inv_psd, ws=None):
+    """Fisher matrices [n, 7, 7] and status [n]."""
+    ws = ws or _default_ws
+    g = _grid(grid)
+    th = _dev(theta)
+    lam = _dev(lam)
+    ip = _dev(inv_psd)
+    _check_shapes(th, lam, g.n_bins, inv_psd=ip)
+    n = th.shape[0]
+    F = torch.empty((n, 7, 7), dtype=torch.float64, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    wp, wb = ws.get(workspace_bytes(L.PD_OP_FISHER, n, g.n_bins))
+    L.check(L.lib().pd_fisher(_ptr(th), n, param, ctypes.byref(g), _ptr(lam), _ptr(ip), _ptr(F), _ptr(status),
+                              wp, wb, _stream()))
+    return F, status
+
+
+def mismatch_grad(theta, param, grid, lam, targets, inv_psd, want_grad=True, ws=None):
+    """Mismatch [nt], sum over targets of d M / d lambda [209] (or None), lag [nt]."""
+    ws = ws or _default_ws
+    g = _grid(grid)
+    th = _dev(theta)
+    lam = _dev(lam)
+    tg = _dev(targets)
+    ip = _dev(inv_psd)
+    _check_shapes(th, lam, g.n_bins, inv_psd=ip, targets=tg)
+    nt = th.shape[0]
+    mm = torch.empty(nt, dtype=torch.float64, device="cuda")
+    dl = torch.empty(209, dtype=torch.float64, device="cuda") if want_grad else None
+    lag = torch.empty(nt, dtype=torch.int32, device="cuda")
+    wp, wb = ws.get(workspace_bytes(L.PD_OP_MISMATCH_GRAD, nt, g.n_bins))
+    L.check(L.lib().pd_mismatch_grad(_ptr(th), nt, param, ctypes.byref(g), _ptr(lam), _ptr(tg), _ptr(ip),
+                                     _ptr(mm), _ptr(dl), _ptr(lag), wp, wb, _stream()))
+    return mm, dl, lag
+
+
+class LogLike(torch.autograd.Function):
+    """ln L(theta) with its gradient from the hand-written forward-mode kernels.
+
+    forward computes value and gradient in one fused pass and saves the gradient;
+    backward scales it by the incoming gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, param, grid, lam, data, inv_psd):
+        lnl, grad, _ = loglike_and_grad(theta.detach(), param, grid, lam, data, inv_psd, want_grad=True)
+        ctx.save_for_backward(grad)
+        return lnl
+
+    @staticmethod
+    def backward(ctx, g_out):
+        (grad,) = ctx.saved_tensors
+        return g_out[:, None] * grad, None, None, None, None, None

@@ -1,0 +1,227 @@
+// C ABI entry points (declared in include/phenomd.h): argument validation, workspace
+// carving and kernel launches.  No entry point allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "../../include/phenomd.h"
+#include "pd_launch.h"
+#include "pd_mismatch.h"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const char* msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char* where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return PD_EHIP;
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t rec = 0, tan = 0, partial = 0, extra = 0, total = 0;
+    int chunks = 1;
+};
+
+Layout layout_for(int op, int64_t n, int64_t nb) {
+    Layout L;
+    const size_t N = static_cast<size_t>(n);
+    size_t off = 0;
+    L.rec = off;
+    off = align_up(off + N * pd::REC_N * sizeof(double));
+    switch (op) {
+        case PD_OP_WAVEFORM:
+            break;
+        case PD_OP_LOGLIKE:
+            L.chunks = pd::chunks_for(n, nb);
+            L.partial = off;
+            off = align_up(off + N * L.chunks * 2 * sizeof(double));
+            break;
+        case PD_OP_LOGLIKE_GRAD:
+            L.chunks = pd::chunks_for(n, nb);
+            L.tan = off;
+            off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
+            L.partial = off;
+            off = align_up(off + N * L.chunks * pd::kNSlot * sizeof(double));
+            break;
+        case PD_OP_FISHER:
+            L.chunks = pd::chunks_for(n, nb);
+            L.tan = off;
+            off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
+            L.partial = off;
+            off = align_up(off + N * L.chunks * 28 * sizeof(double));
+            break;
+        case PD_OP_MISMATCH_GRAD:
+            L.tan = off;
+            off = align_up(off + N * pd::kNumFit * pd::REC_N * sizeof(double));
+            L.extra = off;
+            off = align_up(off + pd::mismatch_scratch_bytes(n, nb));
+            break;
+        default:
+            break;
+    }
+    L.total = off;
+    return L;
+}
+
+int check_common(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                 pd::GridArgs* g) {
+    if (!theta) return fail(PD_EINVAL, "theta is NULL");
+    if (!lambda) return fail(PD_EINVAL, "lambda is NULL");
+    if (!grid) return fail(PD_EINVAL, "grid is NULL");
+    if (n <= 0) return fail(PD_EINVAL, "n must be > 0");
+    if (n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "n too large");
+    if (param < 0 || param > 3) return fail(PD_EINVAL, "unknown parameterisation");
+    if (!(grid->df > 0.0) || !std::isfinite(grid->df)) return fail(PD_EINVAL, "grid df must be finite and > 0");
+    if (!std::isfinite(grid->f0) || grid->f0 < 0.0) return fail(PD_EINVAL, "grid f0 must be finite and >= 0");
+    if (grid->n_bins <= 0) return fail(PD_EINVAL, "grid n_bins must be > 0");
+    if (!std::isfinite(grid->f_min) || !(grid->f_min > 0.0))
+        return fail(PD_EINVAL, "grid f_min must be finite and > 0");
+    if (!std::isfinite(grid->f_ref) || !(grid->f_ref > 0.0))
+        return fail(PD_EINVAL, "grid f_ref must be finite and > 0");
+    g->f0 = grid->f0;
+    g->df = grid->df;
+    g->nb = grid->n_bins;
+    g->fmin = grid->f_min;
+    g->fref = grid->f_ref;
+    return PD_OK;
+}
+
+int check_ws(int op, int64_t n, int64_t nb, void* ws, size_t ws_bytes, Layout* L) {
+    *L = layout_for(op, n, nb);
+    if (!ws) return fail(PD_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return fail(PD_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L->total) return fail(PD_ENOMEM, "workspace too small (see pd_workspace_bytes)");
+    return PD_OK;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pd_workspace_bytes(int op, int64_t n, int64_t n_bins) {
+    if (n <= 0 || n_bins <= 0 || op < 0 || op > PD_OP_MISMATCH_GRAD) return 0;
+    return layout_for(op, n, n_bins).total;
+}
+
+const char* pd_last_error(void) { return g_last_error.c_str(); }
+
+const char* pd_version(void) { return "phenomd-mi355x 0.1 (gfx950)"; }
+
+int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                     int precision, double* h_out, int32_t* status, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+    pd::GridArgs g;
+    int rc = check_common(theta, n, param, grid, lambda, &g);
+    if (rc) return rc;
+    if (!h_out) return fail(PD_EINVAL, "h_out is NULL");
+    if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision");
+    Layout L;
+    rc = check_ws(PD_OP_WAVEFORM, n, g.nb, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* recs = at<double>(workspace, L.rec);
+    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
+    if (e != hipSuccess) return fail_hip(e, "setup");
+    e = pd::launch_waveform(recs, n, g, precision, h_out, s);
+    if (e != hipSuccess) return fail_hip(e, "waveform");
+    return PD_OK;
+}
+
+int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                        const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
+                        int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    pd::GridArgs g;
+    int rc = check_common(theta, n, param, grid, lambda, &g);
+    if (rc) return rc;
+    if (!data) return fail(PD_EINVAL, "data is NULL");
+    if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
+    if (!lnl) return fail(PD_EINVAL, "lnl is NULL");
+    if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision");
+    const int op = grad ? PD_OP_LOGLIKE_GRAD : PD_OP_LOGLIKE;
+    Layout L;
+    rc = check_ws(op, n, g.nb, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* recs = at<double>(workspace, L.rec);
+    double* tans = grad ? at<double>(workspace, L.tan) : nullptr;
+    double* partial = at<double>(workspace, L.partial);
+    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
+    if (e != hipSuccess) return fail_hip(e, "setup");
+    if (grad) {
+        e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, recs, tans, s);
+        if (e != hipSuccess) return fail_hip(e, "setup tangents");
+    }
+    e = pd::launch_loglike(recs, tans, n, L.chunks, g, data, inv_psd, partial, lnl, grad, s);
+    if (e != hipSuccess) return fail_hip(e, "loglike");
+    return PD_OK;
+}
+
+int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+              const double* inv_psd, double* F, int32_t* status, void* workspace, size_t workspace_bytes,
+              void* stream) {
+    pd::GridArgs g;
+    int rc = check_common(theta, n, param, grid, lambda, &g);
+    if (rc) return rc;
+    if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
+    if (!F) return fail(PD_EINVAL, "F is NULL");
+    Layout L;
+    rc = check_ws(PD_OP_FISHER, n, g.nb, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* recs = at<double>(workspace, L.rec);
+    double* tans = at<double>(workspace, L.tan);
+    double* partial = at<double>(workspace, L.partial);
+    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
+    if (e != hipSuccess) return fail_hip(e, "setup");
+    e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, recs, tans, s);
+    if (e != hipSuccess) return fail_hip(e, "setup tangents");
+    e = pd::launch_fisher(recs, tans, n, L.chunks, g, inv_psd, partial, F, s);
+    if (e != hipSuccess) return fail_hip(e, "fisher");
+    return PD_OK;
+}
+
+int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* grid, const double* lambda,
+                     const double* targets, const double* inv_psd, double* mismatch, double* dsum_dlambda,
+                     int32_t* lag, void* workspace, size_t workspace_bytes, void* stream) {
+    pd::GridArgs g;
+    int rc = check_common(theta, nt, param, grid, lambda, &g);
+    if (rc) return rc;
+    if (!targets) return fail(PD_EINVAL, "targets is NULL");
+    if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
+    if (!mismatch) return fail(PD_EINVAL, "mismatch is NULL");
+    if (g.nb != pd::kFFTN) return fail(PD_EUNSUPPORTED, "mismatch needs n_bins = 65536 (the FFT length)");
+    Layout L;
+    rc = check_ws(PD_OP_MISMATCH_GRAD, nt, g.nb, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* recs = at<double>(workspace, L.rec);
+    double* tans = at<double>(workspace, L.tan);
+    void* scratch = at<void>(workspace, L.extra);
+    hipError_t e = pd::launch_setup_value(theta, nt, param, g.fref, lambda, recs, nullptr, s);
+    if (e != hipSuccess) return fail_hip(e, "setup");
+    if (dsum_dlambda) {
+        e = pd::launch_setup_fit_tangent(theta, nt, param, g.fref, lambda, recs, tans, s);
+        if (e != hipSuccess) return fail_hip(e, "setup fit tangents");
+    }
+    e = pd::launch_mismatch(recs, dsum_dlambda ? tans : nullptr, nt, g, targets, inv_psd, scratch, mismatch,
+                            dsum_dlambda, lag, s);
+    if (e != hipSuccess) return fail_hip(e, "mismatch");
+    return PD_OK;
+}
+
+}  // extern "C"

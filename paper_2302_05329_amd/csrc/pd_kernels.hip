@@ -1,0 +1,442 @@
+// HIP kernels for gfx950: per-point setup, strain output, fused likelihood (+gradient),
+// Fisher matrices.
+//
+// Launch shapes
+//   setup      one thread per point (value record, or record + 7 theta tangents), or one
+//              thread per (point, fit parameter) for the 19 coefficient tangents.
+//   waveform   one thread per bin, 256-bin blocks, point-major: writes complex128.
+//   moments    one wavefront per (point, bin chunk); consecutive bins across the 64 lanes
+//              so a wavefront sits in one model region except at the joins.  Per-lane
+//              accumulators, one fixed-order butterfly reduction, one row of partial sums.
+//   epilogue   one thread per point: sums the chunks in order, contracts moments with
+//              record tangents.
+// No atomics anywhere: results are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "pd_bin.h"
+#include "pd_launch.h"
+
+namespace pd {
+
+// ==================================================================================
+// setup
+// ==================================================================================
+
+__device__ __forceinline__ void load_row(const double* __restrict__ theta, int64_t i, double th[7]) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) th[j] = theta[i * 7 + j];
+}
+
+template <class T>
+__device__ __forceinline__ void fit_params(const double* __restrict__ lam, const T& eta, const T& chi_pn,
+                                           T out[kNumFit]) {
+    T b[11];
+    fit_basis(eta, chi_pn, b);
+    for (int i = 0; i < kNumFit; ++i) {
+        T acc = b[0] * lam[i * 11 + 0];
+        for (int k = 1; k < 11; ++k) acc = acc + b[k] * lam[i * 11 + k];
+        out[i] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(128) k_setup_value(const double* __restrict__ theta, int64_t n, int param,
+                                                     double f_ref, const double* __restrict__ lam,
+                                                     double* __restrict__ recs, int32_t* __restrict__ status) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double th[7];
+    load_row(theta, i, th);
+    double rec[REC_N];
+    bool ok = domain_ok(th, param);
+    if (ok) {
+        const Source<double> s = source_map(th, param);
+        double fit[kNumFit];
+        fit_params(lam, s.eta, s.chi_pn, fit);
+        ok = build_record(s, fit, f_ref, rec);
+        for (int j = 0; j < REC_N; ++j) ok = ok && isfinite(rec[j]);
+    }
+    if (!ok) {
+        for (int j = 0; j < REC_N; ++j) rec[j] = 0.0;
+        rec[R_MS] = 1.0;
+    }
+    rec[R_VALID] = ok ? 1.0 : 0.0;
+    double* out = recs + i * REC_N;
+    for (int j = 0; j < REC_N; ++j) out[j] = rec[j];
+    if (status) status[i] = ok ? 0 : -2;
+}
+
+// Record tangents along the 7 entries of theta (forward mode, Dual<7>).
+__global__ void __launch_bounds__(64) k_setup_theta_tangent(const double* __restrict__ theta, int64_t n,
+                                                            int param, double f_ref,
+                                                            const double* __restrict__ lam,
+                                                            const double* __restrict__ recs,
+                                                            double* __restrict__ tans) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* out = tans + i * 7 * REC_N;
+    if (recs[i * REC_N + R_VALID] == 0.0) {
+        for (int j = 0; j < 7 * REC_N; ++j) out[j] = 0.0;
+        return;
+    }
+    using D = Dual<7>;
+    D th[7];
+    for (int j = 0; j < 7; ++j) {
+        th[j] = dconst<7>(theta[i * 7 + j]);
+        th[j].d[j] = 1.0;
+    }
+    const Source<D> s = source_map(th, param);
+    D fit[kNumFit];
+    fit_params(lam, s.eta, s.chi_pn, fit);
+    D rec[REC_N];
+    build_record(s, fit, f_ref, rec);
+    for (int p = 0; p < 7; ++p)
+        for (int j = 0; j < REC_N; ++j) out[p * REC_N + j] = rec[j].d[p];
+}
+
+// Record tangents along the 19 fitted parameters: thread (point, l) seeds parameter l.
+__global__ void __launch_bounds__(64) k_setup_fit_tangent(const double* __restrict__ theta, int64_t n, int param,
+                                                          double f_ref, const double* __restrict__ lam,
+                                                          const double* __restrict__ recs,
+                                                          double* __restrict__ tans) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * kNumFit) return;
+    const int64_t i = t / kNumFit;
+    const int l = static_cast<int>(t % kNumFit);
+    double* out = tans + (i * kNumFit + l) * REC_N;
+    if (recs[i * REC_N + R_VALID] == 0.0) {
+        for (int j = 0; j < REC_N; ++j) out[j] = 0.0;
+        return;
+    }
+    using D = Dual<1>;
+    D th[7];
+    for (int j = 0; j < 7; ++j) th[j] = dconst<1>(theta[i * 7 + j]);
+    const Source<D> s = source_map(th, param);
+    D fit[kNumFit];
+    fit_params(lam, s.eta, s.chi_pn, fit);
+    fit[l].d[0] = 1.0;
+    D rec[REC_N];
+    build_record(s, fit, f_ref, rec);
+    for (int j = 0; j < REC_N; ++j) out[j] = rec[j].d[0];
+}
+
+// ==================================================================================
+// strain output
+// ==================================================================================
+
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ recs, int64_t n, int64_t blocks_per_point,
+                                                  GridArgs g, double* __restrict__ h) {
+    const int64_t b = blockIdx.x;
+    const int64_t p = b / blocks_per_point;
+    const int64_t k = (b % blocks_per_point) * 256 + threadIdx.x;
+    if (p >= n || k >= g.nb) return;
+    const double* __restrict__ rec = recs + p * REC_N;
+    double2 out = make_double2(0.0, 0.0);
+    if (rec[R_VALID] == 0.0) {
+        out = make_double2(__builtin_nan(""), __builtin_nan(""));
+    } else {
+        const double f = bin_freq(g, k);
+        const double mf = rec[R_MS] * f;
+        if (bin_active(g, f, mf)) {
+            BinVals bv;
+            eval_bin(rec, mf, bv);
+            const double A = rec[R_A0] * bv.pf * bv.ahat;
+            double s, c;
+            sincos(bv.psi, &s, &c);
+            out = make_double2(A * c, -A * s);
+        }
+    }
+    reinterpret_cast<double2*>(h)[p * g.nb + k] = out;
+}
+
+// ==================================================================================
+// fused likelihood / gradient moments
+// ==================================================================================
+
+struct MomVis {
+    double* mom;
+    double zr, zi;
+    __device__ __forceinline__ void ph(int s, double b) { mom[s] += zi * b; }
+    __device__ __forceinline__ void am(int s, double b) { mom[s] += zr * b; }
+    __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] += zi * fpsi + zr * fa; }
+};
+
+// MODE 0: (d|h), (h|h).  MODE 1: + moments of the gradient.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
+                                                         GridArgs g, const double* __restrict__ data,
+                                                         const double* __restrict__ inv_psd,
+                                                         double* __restrict__ partial) {
+    constexpr int NS = (MODE == 0) ? 2 : kNSlot;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t p = wave / chunks;
+    const int c = static_cast<int>(wave - p * chunks);
+    if (p >= n) return;
+    const double* __restrict__ rec = recs + p * REC_N;
+    double* __restrict__ out = partial + (p * chunks + c) * NS;
+    if (rec[R_VALID] == 0.0) {
+        for (int s = lane; s < NS; s += 64) out[s] = 0.0;
+        return;
+    }
+    const double ms = rec[R_MS];
+    const double a0 = rec[R_A0];
+    int64_t kb, ke;
+    chunk_range(ms, g, c, chunks, kb, ke);
+    const double w4 = 4.0 * g.df;
+
+    double dh = 0.0, hh = 0.0;
+    double mom[REC_N];
+#pragma unroll
+    for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
+
+    for (int64_t k = kb + lane; k < ke; k += 64) {
+        const double f = bin_freq(g, k);
+        const double mf = ms * f;
+        if (!bin_active(g, f, mf)) continue;
+        BinVals bv;
+        eval_bin(rec, mf, bv);
+        const double A = a0 * bv.pf * bv.ahat;
+        double sn, cs;
+        sincos(bv.psi, &sn, &cs);
+        const double hr = A * cs, hi = -A * sn;
+        const double w = w4 * inv_psd[k];
+        const double2 d = reinterpret_cast<const double2*>(data)[k];
+        dh += w * (d.x * hr + d.y * hi);
+        hh += w * (hr * hr + hi * hi);
+        if (MODE == 1) {
+            const double rr = d.x - hr, ri = d.y - hi;
+            MomVis vis{mom, w * (rr * hr + ri * hi), w * (rr * hi - ri * hr)};
+            visit_bin(rec, bv, vis);
+        }
+    }
+    const double sdh = wave_sum(dh);
+    const double shh = wave_sum(hh);
+    if (lane == 0) {
+        out[0] = sdh;
+        out[1] = shh;
+    }
+    if (MODE == 1) {
+#pragma unroll
+        for (int s = 0; s < REC_N; ++s) {
+            const double t = wave_sum(mom[s]);
+            if (lane == 0) out[2 + s] = t;
+        }
+    }
+}
+
+// One thread per point: sum the chunks, write lnL and (MODE 1) the gradient.
+template <int MODE>
+__global__ void __launch_bounds__(128) k_loglike_epilogue(const double* __restrict__ recs,
+                                                          const double* __restrict__ tans, int64_t n,
+                                                          int chunks, const double* __restrict__ partial,
+                                                          double* __restrict__ lnl, double* __restrict__ grad) {
+    constexpr int NS = (MODE == 0) ? 2 : kNSlot;
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double* rec = recs + p * REC_N;
+    const double nan = __builtin_nan("");
+    if (rec[R_VALID] == 0.0) {
+        lnl[p] = nan;
+        if (MODE == 1)
+            for (int q = 0; q < 7; ++q) grad[p * 7 + q] = nan;
+        return;
+    }
+    double acc[NS];
+    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        const double* src = partial + (p * chunks + c) * NS;
+        for (int s = 0; s < NS; ++s) acc[s] += src[s];
+    }
+    lnl[p] = acc[0] - 0.5 * acc[1];
+    if (MODE == 1) {
+        const double* mom = acc + 2;
+        const double ms = rec[R_MS];
+        for (int q = 0; q < 7; ++q) {
+            const double* t = tans + (p * 7 + q) * REC_N;
+            double gq = t[R_MS] / ms * mom[R_MS] + t[R_LNA0] * mom[R_LNA0];
+            for (int s = R_PH1; s < R_VALID; ++s) gq += t[s] * mom[s];
+            grad[p * 7 + q] = gq;
+        }
+    }
+}
+
+// ==================================================================================
+// Fisher matrices
+// ==================================================================================
+
+struct FisherVis {
+    const double* T;   // [7][REC_N] tangents in LDS
+    double ms;
+    double dpsi[7], dlna[7];
+    __device__ __forceinline__ void ph(int s, double b) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) dpsi[q] += T[q * REC_N + s] * b;
+    }
+    __device__ __forceinline__ void am(int s, double b) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) dlna[q] += T[q * REC_N + s] * b;
+    }
+    __device__ __forceinline__ void fd(double fpsi, double fa) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double m = T[q * REC_N + R_MS] / ms;
+            dpsi[q] += m * fpsi;
+            dlna[q] += m * fa;
+        }
+    }
+};
+
+__global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict__ recs,
+                                                        const double* __restrict__ tans, int64_t n, int chunks,
+                                                        GridArgs g, const double* __restrict__ inv_psd,
+                                                        double* __restrict__ partial) {
+    __shared__ double lds[4][7 * REC_N];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + wib));
+    const int64_t p = wave / chunks;
+    const int c = static_cast<int>(wave - p * chunks);
+    const bool live = p < n;
+    double* T = lds[wib];
+    if (live) {
+        for (int j = lane; j < 7 * REC_N; j += 64) T[j] = tans[p * 7 * REC_N + j];
+    }
+    __syncthreads();
+    if (!live) return;
+    const double* __restrict__ rec = recs + p * REC_N;
+    double* __restrict__ out = partial + (p * chunks + c) * 28;
+    if (rec[R_VALID] == 0.0) {
+        if (lane < 28) out[lane] = 0.0;
+        return;
+    }
+    const double ms = rec[R_MS];
+    const double a0 = rec[R_A0];
+    int64_t kb, ke;
+    chunk_range(ms, g, c, chunks, kb, ke);
+    const double w4 = 4.0 * g.df;
+    double F[28];
+#pragma unroll
+    for (int s = 0; s < 28; ++s) F[s] = 0.0;
+    for (int64_t k = kb + lane; k < ke; k += 64) {
+        const double f = bin_freq(g, k);
+        const double mf = ms * f;
+        if (!bin_active(g, f, mf)) continue;
+        BinVals bv;
+        eval_bin(rec, mf, bv);
+        const double A = a0 * bv.pf * bv.ahat;
+        const double W = w4 * inv_psd[k] * A * A;
+        FisherVis vis;
+        vis.T = T;
+        vis.ms = ms;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) vis.dpsi[q] = vis.dlna[q] = 0.0;
+        visit_bin(rec, bv, vis);
+        int s = 0;
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+            const double wa = W * vis.dlna[a], wp = W * vis.dpsi[a];
+#pragma unroll
+            for (int b = a; b < 7; ++b) {
+                F[s] += wa * vis.dlna[b] + wp * vis.dpsi[b];
+                ++s;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 28; ++s) {
+        const double t = wave_sum(F[s]);
+        if (lane == 0) out[s] = t;
+    }
+}
+
+__global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restrict__ recs, int64_t n, int chunks,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ F) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double* out = F + p * 49;
+    if (recs[p * REC_N + R_VALID] == 0.0) {
+        for (int j = 0; j < 49; ++j) out[j] = __builtin_nan("");
+        return;
+    }
+    double acc[28];
+    for (int s = 0; s < 28; ++s) acc[s] = 0.0;
+    for (int c = 0; c < chunks; ++c)
+        for (int s = 0; s < 28; ++s) acc[s] += partial[(p * chunks + c) * 28 + s];
+    int s = 0;
+    for (int a = 0; a < 7; ++a)
+        for (int b = a; b < 7; ++b) {
+            out[a * 7 + b] = acc[s];
+            out[b * 7 + a] = acc[s];
+            ++s;
+        }
+}
+
+// ==================================================================================
+// host-side launchers
+// ==================================================================================
+
+static inline unsigned blocks_for(int64_t threads, int per_block) {
+    return static_cast<unsigned>((threads + per_block - 1) / per_block);
+}
+
+hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
+                              double* recs, int32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup_value, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, n, param, f_ref, lam,
+                       recs, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param, double f_ref,
+                                      const double* lam, const double* recs, double* tans, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup_theta_tangent, dim3(blocks_for(n, 64)), dim3(64), 0, s, theta, n, param, f_ref,
+                       lam, recs, tans);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, double f_ref, const double* lam,
+                                    const double* recs, double* tans, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup_fit_tangent, dim3(blocks_for(n * kNumFit, 64)), dim3(64), 0, s, theta, n, param,
+                       f_ref, lam, recs, tans);
+    return hipGetLastError();
+}
+
+hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, int precision, double* h,
+                           hipStream_t s) {
+    const int64_t bpp = (g.nb + 255) / 256;
+    hipLaunchKernelGGL(k_waveform<false>, dim3(static_cast<unsigned>(bpp * n)), dim3(256), 0, s, recs, n, bpp, g,
+                       h);
+    (void)precision;
+    return hipGetLastError();
+}
+
+hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
+                          const double* data, const double* inv_psd, double* partial, double* lnl, double* grad,
+                          hipStream_t s) {
+    const int64_t waves = n * chunks;
+    const unsigned nblk = blocks_for(waves, 4);
+    if (grad) {
+        hipLaunchKernelGGL(k_loglike_moments<1>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, data, inv_psd,
+                           partial);
+        hipLaunchKernelGGL(k_loglike_epilogue<1>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
+                           partial, lnl, grad);
+    } else {
+        hipLaunchKernelGGL(k_loglike_moments<0>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, data, inv_psd,
+                           partial);
+        hipLaunchKernelGGL(k_loglike_epilogue<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
+                           partial, lnl, grad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
+                         const double* inv_psd, double* partial, double* F, hipStream_t s) {
+    const int64_t waves = n * chunks;
+    hipLaunchKernelGGL(k_fisher_partial, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks, g,
+                       inv_psd, partial);
+    hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks, partial, F);
+    return hipGetLastError();
+}
+
+}  // namespace pd

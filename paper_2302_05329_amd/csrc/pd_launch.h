@@ -1,0 +1,38 @@
+// Internal host-side launch interface between the C ABI and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pd_bin.h"
+
+namespace pd {
+
+constexpr int kNSlot = 2 + REC_N;   // (d|h), (h|h), then one moment per record entry
+
+// Bin-chunking policy: enough wavefronts to fill the chip even for small batches.
+inline int chunks_for(int64_t n, int64_t n_bins) {
+    const int64_t want = (16384 + n - 1) / n;
+    int64_t cap = n_bins / 512;
+    if (cap < 1) cap = 1;
+    int64_t c = want < cap ? want : cap;
+    if (c < 1) c = 1;
+    if (c > 64) c = 64;
+    return static_cast<int>(c);
+}
+
+hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
+                              double* recs, int32_t* status, hipStream_t s);
+hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param, double f_ref,
+                                      const double* lam, const double* recs, double* tans, hipStream_t s);
+hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, double f_ref, const double* lam,
+                                    const double* recs, double* tans, hipStream_t s);
+hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, int precision, double* h,
+                           hipStream_t s);
+hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
+                          const double* data, const double* inv_psd, double* partial, double* lnl, double* grad,
+                          hipStream_t s);
+hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
+                         const double* inv_psd, double* partial, double* F, hipStream_t s);
+
+}  // namespace pd

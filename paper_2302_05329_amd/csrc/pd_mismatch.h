@@ -1,0 +1,24 @@
+// Internal interface of the mismatch pipeline (Sec. 3.1): overlap series by FFT, maximum
+// over lag and phase, adjoint of the mismatch w.r.t. the 209 fit coefficients.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "pd_bin.h"
+
+namespace pd {
+
+constexpr int64_t kFFTN = 65536;   // overlap length: 256 x 256 four-step
+constexpr int kFFTR = 256;
+constexpr int kFFTCols = 16;       // columns per FFT block
+constexpr int kSlotMM = 8;         // per-target scalars: A, B, |z|, zr, zi, lag, mismatch, pad
+
+size_t mismatch_scratch_bytes(int64_t nt, int64_t nb);
+
+hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t nt, const GridArgs& g,
+                           const double* targets, const double* inv_psd, void* scratch, double* mismatch,
+                           double* dsum_dlambda, int32_t* lag, hipStream_t s);
+
+}  // namespace pd

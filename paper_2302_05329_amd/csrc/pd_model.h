@@ -1,0 +1,470 @@
+// Per-point setup of the IMRPhenomD-structured model on the GPU.
+//
+// For one parameter row this builds the "coefficient record": everything the per-bin
+// kernels need, laid out so that in every frequency region the phase and the amplitude
+// ratio are plain linear combinations of a few basis functions of Mf (plus one arctan
+// term and one Lorentzian in the merger-ringdown region).  Time and phase alignment,
+// tc, phic and the C1 connection constants are folded into the linear coefficients, so
+// a bin costs one basis evaluation and a dot product.
+//
+// The setup is a template over the scalar type: `double` gives the record, Dual<N>
+// gives the record together with its derivatives along N input directions.  The
+// per-bin kernels contract those record tangents with per-bin moments to obtain
+// likelihood gradients, Fisher matrices and the mismatch adjoint.
+//
+// Model structure (aligned-spin IMRPhenomD, Husa et al. 2016 / Khan et al. 2016; the
+// paper uses it in Sec. 2 and fits its 209 coefficients in Sec. 3.1):
+//   phase     : inspiral TaylorF2 3.5PN + pseudo-PN sigma_1..4 terms for Mf < 0.018,
+//               intermediate beta_1..3 terms up to f_RD/2, merger-ringdown alpha_1..5 terms;
+//               joined continuously with continuous first derivative.
+//   amplitude : PN amplitude + rho_1..3 terms for Mf < 0.014, quartic through five
+//               conditions up to f_peak, Lorentzian x exponential (gamma_1..3) beyond.
+//   alignment : Psi = Phi(Mf) - t0 (Mf - Mf_ref) - Phi(Mf_ref) + 2 pi f tc - 2 phic,
+//               t0 = Phi'_MRD(f_peak).
+//   final state (stand-ins): final spin of Barausse & Rezzolla (2009), radiated energy
+//               eta (1 - 2 sqrt(2)/3) + eta^2 (0.55 + 0.5 chi_eff), ring-down and damping
+//               frequencies from the l=m=2, n=0 fit of Berti, Cardoso & Will (2006).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pd_dual.h"
+
+namespace pd {
+
+// ---- physical constants (IAU 2015 nominal solar mass parameter) --------------------
+constexpr double kC = 299792458.0;
+constexpr double kGMsun = 1.3271244e20;
+constexpr double kTsun = kGMsun / (kC * kC * kC);
+constexpr double kMpc = 3.0856775814913673e22;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kEulerGamma = 0.57721566490153286061;
+constexpr double kLn4 = 1.38629436111989061883;
+
+constexpr double kFAmpJoin = 0.014;
+constexpr double kFPhaseJoin = 0.018;
+constexpr double kFCut = 0.2;
+
+// ---- record layout (doubles) ------------------------------------------------------
+enum : int {
+    R_MS = 0,     // M * T_sun  [s]
+    R_FP2 = 1,    // phase join intermediate -> merger-ringdown (f_RD / 2)
+    R_FA2 = 2,    // amplitude join intermediate -> merger-ringdown (f_peak)
+    R_LNA0 = 3,   // ln of the prefactor: A(f) = exp(lnA0) (Mf)^(-7/6) Ahat(Mf)
+    R_A0 = 4,     // exp(lnA0)
+    R_PH1 = 5,    // 13 coefficients on {v^-5, v^-3, v^-2, v^-1, 1, ln v, v, v ln v, v^2, ..., v^6}, v = (pi Mf)^(1/3)
+    R_PH2 = 18,   // 4 coefficients on {1, f, ln f, f^-3}
+    R_PH3 = 22,   // {c0, c1 (f), c2 (1/f), c3 (f^3/4), c4 (atan), q, d}: + c4 atan((f - q)/d)
+    R_AM1 = 29,   // 10 coefficients on {v^0 .. v^9}
+    R_AM2 = 39,   // 5 coefficients on {1, f, f^2, f^3, f^4}
+    R_AM3 = 44,   // {a, f_RD, g, r}: Ahat = a / ((f - f_RD)^2 + g^2) exp(-r (f - f_RD))
+    R_VALID = 48, // 1.0 if the point is inside the model's domain, else 0.0
+    R_ETA = 49,   // eta and chi_PN (values), for the chain rule to the 209 coefficients
+    R_CHIPN = 50,
+    REC_N = 52
+};
+
+constexpr int kNumLambda = 209;
+constexpr int kNumFit = 19;   // rho1..3 v2 gamma1..3 sigma1..4 beta1..3 alpha1..5
+enum : int {
+    L_RHO1 = 0, L_RHO2, L_RHO3, L_V2, L_G1, L_G2, L_G3, L_S1, L_S2, L_S3, L_S4,
+    L_B1, L_B2, L_B3, L_A1, L_A2, L_A3, L_A4, L_A5
+};
+
+template <class T>
+__device__ __forceinline__ T sq(const T& x) { return x * x; }
+
+// ---- source quantities from one parameter row --------------------------------------
+template <class T>
+struct Source {
+    T M, eta, delta, Mc, chi1, chi2, D, tc, phic;
+    T chis, chia, chi_eff, chi_pn;
+};
+
+// param: 0 (Mc, eta), 1 (ln Mc, eta, ln D), 2 (Mc, q), 3 (m1, m2)
+template <class T>
+__device__ __forceinline__ Source<T> source_map(const T th[7], int param) {
+    Source<T> s;
+    if (param == 3) {
+        s.M = th[0] + th[1];
+        s.eta = th[0] * th[1] / sq(s.M);
+        s.delta = (th[0] - th[1]) / s.M;
+        s.Mc = s.M * dpow(s.eta, 0.6);
+        s.D = th[4];
+    } else if (param == 2) {
+        const T q = th[1];
+        s.Mc = th[0];
+        s.eta = q / sq(1.0 + q);
+        s.M = s.Mc * dpow(s.eta, -0.6);
+        s.delta = (1.0 - q) / (1.0 + q);
+        s.D = th[4];
+    } else {
+        s.Mc = (param == 1) ? dexp(th[0]) : th[0];
+        s.eta = th[1];
+        s.M = s.Mc * dpow(s.eta, -0.6);
+        s.delta = dsqrt(1.0 - 4.0 * s.eta);
+        s.D = (param == 1) ? dexp(th[4]) : th[4];
+    }
+    s.chi1 = th[2];
+    s.chi2 = th[3];
+    s.tc = th[5];
+    s.phic = th[6];
+    s.chis = 0.5 * (s.chi1 + s.chi2);
+    s.chia = 0.5 * (s.chi1 - s.chi2);
+    s.chi_eff = s.chis + s.delta * s.chia;
+    s.chi_pn = s.chi_eff - (38.0 / 113.0) * s.eta * (s.chi1 + s.chi2);
+    return s;
+}
+
+// Domain check on the raw row (plain doubles).
+__device__ __forceinline__ bool domain_ok(const double th[7], int param) {
+    for (int i = 0; i < 7; ++i)
+        if (!isfinite(th[i])) return false;
+    if (param == 0 || param == 1) {
+        if (param == 0 && !(th[0] > 0.0)) return false;
+        if (!(th[1] > 0.0 && th[1] <= 0.25)) return false;
+    } else {
+        if (!(th[0] > 0.0 && th[1] > 0.0)) return false;
+    }
+    if (fabs(th[2]) > 1.0 || fabs(th[3]) > 1.0) return false;
+    if (param != 1 && !(th[4] > 0.0)) return false;
+    return true;
+}
+
+// 11-term fit basis in (eta, x = chi_PN - 1), written out as the column order of the table.
+template <class T>
+__device__ __forceinline__ void fit_basis(const T& eta, const T& chi_pn, T b[11]) {
+    const T x = chi_pn - 1.0;
+    const T e2 = eta * eta;
+    const T x2 = x * x;
+    const T x3 = x2 * x;
+    b[0] = K<T>(1.0);
+    b[1] = eta;
+    b[2] = x;
+    b[3] = x * eta;
+    b[4] = x * e2;
+    b[5] = x2;
+    b[6] = x2 * eta;
+    b[7] = x2 * e2;
+    b[8] = x3;
+    b[9] = x3 * eta;
+    b[10] = x3 * e2;
+}
+
+// Linear solve of a 5x5 system by Gaussian elimination with partial pivoting (on values).
+template <class T>
+__device__ __forceinline__ void solve5(T a[5][5], T b[5], T x[5]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        int piv = c;
+        double best = fabs(val(a[c][c]));
+        for (int r = c + 1; r < 5; ++r) {
+            const double m = fabs(val(a[r][c]));
+            if (m > best) { best = m; piv = r; }
+        }
+        if (piv != c) {
+            for (int k = 0; k < 5; ++k) { T t = a[c][k]; a[c][k] = a[piv][k]; a[piv][k] = t; }
+            T t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < 5; ++r) {
+            const T m = a[r][c] / a[c][c];
+            for (int k = c; k < 5; ++k) a[r][k] = a[r][k] - m * a[c][k];
+            b[r] = b[r] - m * b[c];
+        }
+    }
+    for (int r = 4; r >= 0; --r) {
+        T acc = b[r];
+        for (int k = r + 1; k < 5; ++k) acc = acc - a[r][k] * x[k];
+        x[r] = acc / a[r][r];
+    }
+}
+
+// Exponents of the 13 inspiral phase basis functions in v (ln-terms get special handling).
+__device__ constexpr double kPh1Pow[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
+
+// Inspiral phase and Mf * dPhi/dMf from the raw (unaligned) basis coefficients.
+template <class T>
+__device__ __forceinline__ void phase_ins_eval(const T c[13], const T& mf, T& phi, T& fdphi) {
+    const T v = dcbrt(kPi * mf);
+    const T lv = dlog(v);
+    const T w = 1.0 / v;
+    T b[13];
+    const T w2 = w * w;
+    b[0] = w2 * w2 * w;
+    b[1] = w2 * w;
+    b[2] = w2;
+    b[3] = w;
+    b[4] = K<T>(1.0);
+    b[5] = lv;
+    b[6] = v;
+    b[7] = v * lv;
+    b[8] = v * v;
+    b[9] = b[8] * v;
+    b[10] = b[9] * v;
+    b[11] = b[10] * v;
+    b[12] = b[11] * v;
+    phi = c[0] * b[0];
+    fdphi = c[0] * b[0] * (kPh1Pow[0] / 3.0);
+#pragma unroll
+    for (int j = 1; j < 13; ++j) {
+        phi = phi + c[j] * b[j];
+        fdphi = fdphi + c[j] * b[j] * (kPh1Pow[j] / 3.0);
+    }
+    // d(ln v)/d ln f = 1/3 and d(v ln v)/d ln f = (v ln v + v)/3
+    fdphi = fdphi + (c[5] + c[7] * v) * (1.0 / 3.0);
+}
+
+// Inspiral amplitude ratio and Mf * dAhat/dMf from its 10 coefficients on v^0..v^9.
+template <class T>
+__device__ __forceinline__ void amp_ins_eval(const T c[10], const T& mf, T& a, T& fda) {
+    const T v = dcbrt(kPi * mf);
+    T p = K<T>(1.0);
+    a = c[0] * p;
+    fda = K<T>(0.0);
+#pragma unroll
+    for (int i = 1; i < 10; ++i) {
+        p = p * v;
+        a = a + c[i] * p;
+        fda = fda + c[i] * p * (i / 3.0);
+    }
+}
+
+// Build the coefficient record from the source and the 19 fitted parameters.
+// Returns false if the transition frequencies come out of order.
+template <class T>
+__device__ __forceinline__ bool build_record(const Source<T>& s, const T lam[kNumFit], double f_ref,
+                                             T rec[REC_N]) {
+    const T eta = s.eta, delta = s.delta, chis = s.chis, chia = s.chia;
+    const T eta2 = eta * eta, eta3 = eta2 * eta;
+    const double pi = kPi, pi2 = kPi * kPi;
+
+    // ---- TaylorF2 phase coefficients (3.5PN, aligned spins) -------------------------
+    T phi[8], phil5, phi6l;
+    phi[0] = K<T>(1.0);
+    phi[1] = K<T>(0.0);
+    phi[2] = 3715.0 / 756.0 + (55.0 / 9.0) * eta;
+    phi[3] = -16.0 * pi + (113.0 / 3.0) * delta * chia + (113.0 / 3.0 - (76.0 / 3.0) * eta) * chis;
+    phi[4] = 15293365.0 / 508032.0 + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * eta2 +
+             (-405.0 / 8.0 + 200.0 * eta) * chia * chia - (405.0 / 4.0) * delta * chia * chis +
+             (-405.0 / 8.0 + 2.5 * eta) * chis * chis;
+    phi[5] = (38645.0 / 756.0) * pi - (65.0 / 9.0) * pi * eta +
+             delta * (-732985.0 / 2268.0 - (140.0 / 9.0) * eta) * chia +
+             (-732985.0 / 2268.0 + (24260.0 / 81.0) * eta + (340.0 / 9.0) * eta2) * chis;
+    phil5 = 3.0 * phi[5];
+    phi[6] = 11583231236531.0 / 4694215680.0 - (6848.0 / 21.0) * kEulerGamma - (640.0 / 3.0) * pi2 +
+             (-15737765635.0 / 3048192.0 + (2255.0 / 12.0) * pi2) * eta + (76055.0 / 1728.0) * eta2 -
+             (127825.0 / 1296.0) * eta3 - (6848.0 / 21.0) * kLn4 + pi * (2270.0 / 3.0) * delta * chia +
+             pi * (2270.0 / 3.0 - 520.0 * eta) * chis +
+             (75515.0 / 144.0 - (8225.0 / 18.0) * eta) * delta * chia * chis +
+             (75515.0 / 288.0 - (263245.0 / 252.0) * eta - 480.0 * eta2) * chia * chia +
+             (75515.0 / 288.0 - (232415.0 / 504.0) * eta + (1255.0 / 9.0) * eta2) * chis * chis;
+    phi6l = K<T>(-6848.0 / 21.0);
+    phi[7] = (77096675.0 / 254016.0) * pi + (378515.0 / 1512.0) * pi * eta - (74045.0 / 756.0) * pi * eta2 +
+             delta * (-25150083775.0 / 3048192.0 + (26804935.0 / 6048.0) * eta - (1985.0 / 48.0) * eta2) * chia +
+             (-25150083775.0 / 3048192.0 + (10566655595.0 / 762048.0) * eta - (1042165.0 / 3024.0) * eta2 +
+              (5345.0 / 36.0) * eta3) *
+                 chis;
+
+    // ---- PN amplitude coefficients ----------------------------------------------------
+    T amp[7];
+    amp[0] = K<T>(1.0);
+    amp[1] = K<T>(0.0);
+    amp[2] = -323.0 / 224.0 + (451.0 / 168.0) * eta;
+    amp[3] = (27.0 / 8.0) * delta * chia + (27.0 / 8.0 - (11.0 / 6.0) * eta) * chis;
+    amp[4] = -27312085.0 / 8128512.0 - (1975055.0 / 338688.0) * eta + (105271.0 / 24192.0) * eta2 +
+             (-81.0 / 32.0 + 8.0 * eta) * chia * chia - (81.0 / 16.0) * delta * chia * chis +
+             (-81.0 / 32.0 + (17.0 / 8.0) * eta) * chis * chis;
+    amp[5] = -(85.0 / 64.0) * pi + (85.0 / 16.0) * pi * eta +
+             delta * (285197.0 / 16128.0 - (1579.0 / 4032.0) * eta) * chia +
+             (285197.0 / 16128.0 - (15211.0 / 1008.0) * eta + (2351.0 / 4032.0) * eta2) * chis;
+    amp[6] = -177520268561.0 / 8583708672.0 +
+             (545384828789.0 / 5007163392.0 - (205.0 / 48.0) * pi2) * eta -
+             (3248849057.0 / 178827264.0) * eta2 + (34473079.0 / 6386688.0) * eta3 +
+             (1614569.0 / 64512.0 - (1873643.0 / 16128.0) * eta + (2167.0 / 42.0) * eta2) * chia * chia +
+             ((31.0 / 12.0) * pi - (7.0 / 3.0) * pi * eta) * chis +
+             (1614569.0 / 64512.0 - (61391.0 / 1344.0) * eta + (57451.0 / 4032.0) * eta2) * chis * chis +
+             delta * chia * ((31.0 / 12.0) * pi + (1614569.0 / 32256.0 - (165961.0 / 2688.0) * eta) * chis);
+
+    // ---- final state and ring-down -----------------------------------------------------
+    const T m1 = 0.5 * s.M * (1.0 + delta);
+    const T m2 = 0.5 * s.M * (1.0 - delta);
+    const T a_tilde = (m1 * m1 * s.chi1 + m2 * m2 * s.chi2) / (m1 * m1 + m2 * m2);
+    const T a_f = a_tilde - 0.1229 * a_tilde * a_tilde * eta + 0.4537 * a_tilde * eta2 -
+                  2.8904 * a_tilde * eta + 2.0 * 1.7320508075688772935 * eta - 3.5171 * eta2 +
+                  2.5763 * eta3;
+    const T e_rad = (1.0 - 2.0 * 1.4142135623730950488 / 3.0) * eta + eta2 * (0.55 + 0.5 * s.chi_eff);
+    const T om = 1.0 - a_f;
+    const T omega_r = 1.5251 - 1.1568 * dpow(om, 0.1292);
+    const T qual = 0.7 + 1.4187 * dpow(om, -0.4990);
+    const T omega_i = omega_r / (2.0 * qual);
+    const T rscale = 1.0 / (2.0 * pi * (1.0 - e_rad));
+    const T f_rd = omega_r * rscale;
+    const T f_damp = omega_i * rscale;
+
+    // ---- amplitude peak (gamma2 <= 1: stationary point; else real part of the complex root)
+    const T g1 = lam[L_G1], g2 = lam[L_G2], g3 = lam[L_G3];
+    const T gd = g3 * f_damp;
+    T f_peak;
+    if (val(g2) <= 1.0)
+        f_peak = f_rd + gd * (dsqrt(1.0 - g2 * g2) - 1.0) / g2;
+    else
+        f_peak = f_rd - gd / g2;
+
+    const T f_p2 = 0.5 * f_rd;
+    const bool ok = (val(f_peak) > kFAmpJoin) && (val(f_p2) > kFPhaseJoin);
+
+    // ---- raw phase coefficients -------------------------------------------------------
+    const T inv_eta = 1.0 / eta;
+    const T k128 = (3.0 / 128.0) * inv_eta;
+    T ph1[13];
+    ph1[0] = k128 * phi[0];
+    ph1[1] = k128 * phi[2];
+    ph1[2] = k128 * phi[3];
+    ph1[3] = k128 * phi[4];
+    ph1[4] = k128 * phi[5];
+    ph1[5] = k128 * phil5;
+    ph1[6] = k128 * phi[6];
+    ph1[7] = k128 * phi6l;
+    ph1[8] = k128 * phi[7];
+    // (1/eta)(s1 f + 3/4 s2 f^(4/3) + 3/5 s3 f^(5/3) + 1/2 s4 f^2) with f = v^3 / pi
+    ph1[9] = lam[L_S1] * inv_eta * (1.0 / pi);
+    ph1[10] = 0.75 * lam[L_S2] * inv_eta * (1.0 / pow(pi, 4.0 / 3.0));
+    ph1[11] = 0.6 * lam[L_S3] * inv_eta * (1.0 / pow(pi, 5.0 / 3.0));
+    ph1[12] = 0.5 * lam[L_S4] * inv_eta * (1.0 / pi2);
+
+    const T b1 = lam[L_B1] * inv_eta, b2 = lam[L_B2] * inv_eta, b3 = lam[L_B3] * inv_eta;
+    const T a1 = lam[L_A1] * inv_eta, a2 = lam[L_A2] * inv_eta, a3 = lam[L_A3] * inv_eta,
+            a4 = lam[L_A4] * inv_eta;
+    const T q_at = lam[L_A5] * f_rd;
+
+    // intermediate raw: b1 f + b2 ln f - b3 / (3 f^3); derivative b1 + b2/f + b3/f^4
+    auto phi_int_raw = [&](const T& f) { return b1 * f + b2 * dlog(f) - b3 / (3.0 * f * f * f); };
+    auto dphi_int_raw = [&](const T& f) { return b1 + b2 / f + b3 / sq(sq(f)); };
+    // merger-ringdown raw
+    auto phi_mrd_raw = [&](const T& f) {
+        return a1 * f - a2 / f + (4.0 / 3.0) * a3 * dpow(f, 0.75) + a4 * datan((f - q_at) / f_damp);
+    };
+    auto dphi_mrd_raw = [&](const T& f) {
+        return a1 + a2 / (f * f) + a3 * dpow(f, -0.25) + a4 * f_damp / (f_damp * f_damp + sq(f - q_at));
+    };
+
+    // ---- C1 connection of the phase ---------------------------------------------------
+    const T f1 = K<T>(kFPhaseJoin);
+    T pins, fdpins;
+    phase_ins_eval(ph1, f1, pins, fdpins);
+    const T c2_int = fdpins / f1 - dphi_int_raw(f1);
+    const T c1_int = pins - phi_int_raw(f1) - c2_int * f1;
+    const T pint2 = phi_int_raw(f_p2) + c1_int + c2_int * f_p2;
+    const T dpint2 = dphi_int_raw(f_p2) + c2_int;
+    const T c2_mrd = dpint2 - dphi_mrd_raw(f_p2);
+    const T c1_mrd = pint2 - phi_mrd_raw(f_p2) - c2_mrd * f_p2;
+
+    // ---- amplitude pieces -------------------------------------------------------------
+    T am1[10];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) am1[i] = amp[i];
+    am1[7] = lam[L_RHO1] * (1.0 / pow(pi, 7.0 / 3.0));
+    am1[8] = lam[L_RHO2] * (1.0 / pow(pi, 8.0 / 3.0));
+    am1[9] = lam[L_RHO3] * (1.0 / (pi * pi * pi));
+
+    auto amp_mrd = [&](const T& f) {
+        const T x = f - f_rd;
+        return g1 * gd / (x * x + gd * gd) * dexp(-g2 * x / gd);
+    };
+    auto damp_mrd = [&](const T& f) {
+        const T x = f - f_rd;
+        return amp_mrd(f) * (-2.0 * x / (x * x + gd * gd) - g2 / gd);
+    };
+
+    const T fa1 = K<T>(kFAmpJoin);
+    const T fa3 = f_peak;
+    const T fa2 = 0.5 * (fa1 + fa3);
+    T ains, fdains;
+    amp_ins_eval(am1, fa1, ains, fdains);
+    T A[5][5], rhs[5], dl[5];
+    {
+        const T* fs[3] = {&fa1, &fa2, &fa3};
+        // rows: value at fa1, slope at fa1, value at fa2, value at fa3, slope at fa3
+        const int kind[5] = {0, 1, 0, 0, 1};
+        const int which[5] = {0, 0, 1, 2, 2};
+        for (int r = 0; r < 5; ++r) {
+            const T f = *fs[which[r]];
+            if (kind[r] == 0) {
+                A[r][0] = K<T>(1.0);
+                A[r][1] = f;
+                A[r][2] = f * f;
+                A[r][3] = A[r][2] * f;
+                A[r][4] = A[r][3] * f;
+            } else {
+                A[r][0] = K<T>(0.0);
+                A[r][1] = K<T>(1.0);
+                A[r][2] = 2.0 * f;
+                A[r][3] = 3.0 * f * f;
+                A[r][4] = 4.0 * f * f * f;
+            }
+        }
+        rhs[0] = ains;
+        rhs[1] = fdains / fa1;
+        rhs[2] = lam[L_V2];
+        rhs[3] = amp_mrd(fa3);
+        rhs[4] = damp_mrd(fa3);
+    }
+    solve5(A, rhs, dl);
+
+    // ---- alignment ----------------------------------------------------------------------
+    const T t0 = dphi_mrd_raw(f_peak) + c2_mrd;
+    const T ms = s.M * kTsun;
+    const T mf_ref = ms * f_ref;
+    T phi_ref;
+    const double mfr = val(mf_ref);
+    if (mfr < kFPhaseJoin) {
+        T tmp;
+        phase_ins_eval(ph1, mf_ref, phi_ref, tmp);
+    } else if (mfr < val(f_p2)) {
+        phi_ref = phi_int_raw(mf_ref) + c1_int + c2_int * mf_ref;
+    } else {
+        phi_ref = phi_mrd_raw(mf_ref) + c1_mrd + c2_mrd * mf_ref;
+    }
+    const T lin = 2.0 * pi * s.tc / ms - t0;                 // coefficient of Mf
+    const T cst = t0 * mf_ref - phi_ref - 2.0 * s.phic;     // constant
+
+    // ---- overall amplitude: face-on Newtonian SPA prefactor, written per unit (Mf)^(-7/6)
+    const double ln_pref = 0.5 * log(5.0 / 24.0) - (2.0 / 3.0) * log(pi) + log(kC / kMpc);
+    const T lna0 = ln_pref + (5.0 / 6.0) * dlog(s.Mc * kTsun) - dlog(s.D) + (7.0 / 6.0) * dlog(ms);
+
+    // ---- write the record ---------------------------------------------------------------
+    rec[R_MS] = ms;
+    rec[R_FP2] = f_p2;
+    rec[R_FA2] = f_peak;
+    rec[R_LNA0] = lna0;
+    rec[R_A0] = dexp(lna0);
+#pragma unroll
+    for (int j = 0; j < 13; ++j) rec[R_PH1 + j] = ph1[j];
+    rec[R_PH1 + 4] = ph1[4] + cst;
+    rec[R_PH1 + 9] = ph1[9] + lin * (1.0 / pi);
+    rec[R_PH2 + 0] = c1_int + cst;
+    rec[R_PH2 + 1] = b1 + c2_int + lin;
+    rec[R_PH2 + 2] = b2;
+    rec[R_PH2 + 3] = -b3 * (1.0 / 3.0);
+    rec[R_PH3 + 0] = c1_mrd + cst;
+    rec[R_PH3 + 1] = a1 + c2_mrd + lin;
+    rec[R_PH3 + 2] = -a2;
+    rec[R_PH3 + 3] = (4.0 / 3.0) * a3;
+    rec[R_PH3 + 4] = a4;
+    rec[R_PH3 + 5] = q_at;
+    rec[R_PH3 + 6] = f_damp;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) rec[R_AM1 + i] = am1[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) rec[R_AM2 + i] = dl[i];
+    rec[R_AM3 + 0] = g1 * gd;
+    rec[R_AM3 + 1] = f_rd;
+    rec[R_AM3 + 2] = gd;
+    rec[R_AM3 + 3] = g2 / gd;
+    rec[R_VALID] = K<T>(ok ? 1.0 : 0.0);
+    rec[R_ETA] = eta;
+    rec[R_CHIPN] = s.chi_pn;
+    rec[51] = K<T>(0.0);
+    return ok;
+}
+
+}  // namespace pd

@@ -1,0 +1,216 @@
+"""GPU (HIP, gfx950) against the CPU oracle on identical seeded inputs.
+
+Tolerances (FP64 mode):
+  strain       max_k |dh_k| / max_k |h_k| <= 1e-10 per point
+  ln L         |d lnL| <= 1e-10 * max(1, (h|h) / 4e4)   (FP64 rounding of a ~1e4 rad phase
+               times the per-bin terms of a loud source exceeds 1e-10 absolute)
+  gradient     |d g_p| <= 1e-10 * sqrt((d-h|d-h) F_pp)  (Cauchy-Schwarz bound of |g_p|)
+  Fisher       |d F_pq| <= 1e-10 * sqrt(F_pp F_qq)
+  mismatch     |d M| <= 1e-12; lag identical unless the top two |z_j| are within 1e-12;
+               gradient normwise max|d g| <= 1e-8 * max|g|
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import phenomd_oracle as O
+from paper_2302_05329_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P = O.PARAM_M1M2
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _strain_err(hg, hr):
+    return np.max(np.abs(hg - hr)) / np.max(np.abs(hr))
+
+
+def test_waveform_parity_config1(gpu, lam0):
+    import torch
+    cfg = W.config1(n=1024)
+    g = cfg["grid"].as_tuple()
+    _say(f"waveform_eval C1 n=1024 nb={g[2]}")
+    h, st = gpu.api.waveform_eval(cfg["theta"], P, cfg["grid"], lam0)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    idx = np.linspace(0, 1023, 40).astype(int)
+    for i in idx:
+        ref = O.waveform(cfg["theta"][i], P, lam0, g)
+        assert _strain_err(h[i], ref) <= 1e-10, i
+        big = np.abs(ref) > 1e-6 * np.max(np.abs(ref))
+        assert np.max(np.abs(h[i][big] - ref[big]) / np.abs(ref[big])) <= 1e-10, i
+        assert np.all(h[i][ref == 0] == 0)
+
+
+@pytest.mark.parametrize("param", [O.PARAM_MC_ETA, O.PARAM_LNMC_ETA_LND, O.PARAM_MC_Q])
+def test_waveform_parity_parameterisations(gpu, lam0, param):
+    import torch
+    rows = W.draw_sources(12, 77, d_range=(100, 2000), tc_range=(-0.1, 0.1), phic_random=True)
+    th = W.to_param(rows, param)
+    grid = W.Grid(20.0, 0.125, 16225)
+    _say(f"waveform_eval param={param} n=12 nb=16225")
+    h, st = gpu.api.waveform_eval(th, param, grid, lam0)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy()
+    for i in range(len(th)):
+        ref = O.waveform(th[i], param, lam0, grid.as_tuple())
+        assert _strain_err(h[i], ref) <= 1e-10, i
+
+
+def test_loglike_and_grad_parity_config2_grid(gpu, lam0):
+    import torch
+    cfg = W.config2(n=24)
+    g = cfg["grid"].as_tuple()
+    data, ip = cfg["data"], cfg["inv_psd"]
+    # add a loud injection so that the likelihood surface has structure
+    data = data + O.waveform(cfg["theta"][0] * np.array([1.002, 0.998, 1, 1, 1, 1, 1]), P, lam0, g)
+    _say(f"loglike_and_grad C2-grid n=24 nb={g[2]}")
+    lnl, grad, st = gpu.api.loglike_and_grad(cfg["theta"], P, cfg["grid"], lam0, data, ip)
+    lnl0, _, _ = gpu.api.loglike_and_grad(cfg["theta"], P, cfg["grid"], lam0, data, ip, want_grad=False)
+    torch.cuda.synchronize()
+    lnl, grad, lnl0 = lnl.cpu().numpy(), grad.cpu().numpy(), lnl0.cpu().numpy()
+    for i in range(len(cfg["theta"])):
+        th = cfg["theta"][i]
+        h = O.waveform(th, P, lam0, g)
+        hh = O.inner(h, h, ip, g[1])
+        ref = O.loglike(th, P, lam0, g, data, ip)
+        tol = 1e-10 * max(1.0, hh / 4e4)
+        assert abs(lnl[i] - ref) <= tol, (i, lnl[i], ref)
+        assert abs(lnl0[i] - ref) <= tol, (i, lnl0[i], ref)
+        gref = O.loglike_grad(th, P, lam0, g, data, ip)
+        F = O.fisher(th, P, lam0, g, ip)
+        r = data - h
+        scale = np.sqrt(O.inner(r, r, ip, g[1]) * np.diag(F))
+        assert np.all(np.abs(grad[i] - gref) <= 1e-10 * scale), (i, grad[i], gref, scale)
+
+
+@pytest.mark.parametrize("param", [O.PARAM_LNMC_ETA_LND, O.PARAM_MC_Q, O.PARAM_MC_ETA])
+def test_fisher_parity_config3_grid(gpu, lam0, param):
+    import torch
+    cfg = W.config3(n=10)
+    g = cfg["grid"].as_tuple()
+    th = W.to_param(cfg["theta"], param)
+    _say(f"fisher C3-grid param={param} n=10 nb={g[2]}")
+    F, st = gpu.api.fisher(th, param, cfg["grid"], lam0, cfg["inv_psd"])
+    torch.cuda.synchronize()
+    F = F.cpu().numpy()
+    for i in range(len(th)):
+        ref = O.fisher(th[i], param, lam0, g, cfg["inv_psd"])
+        scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+        assert np.all(np.abs(F[i] - ref) <= 1e-10 * scale), (i, np.max(np.abs(F[i] - ref) / scale))
+        assert np.array_equal(F[i], F[i].T)
+
+
+def test_mismatch_grad_parity_config4_shape(gpu, lam0):
+    import torch
+    cfg = W.config4(n=4)
+    g = cfg["grid"].as_tuple()
+    th = cfg["theta"]
+    w = cfg["inv_psd"]
+    targets = np.stack([O.waveform(t, P, cfg["lam_star"], g) for t in th])
+    _say(f"mismatch_grad C4-shape nt=4 nb={g[2]}")
+    mm, dl, lag = gpu.api.mismatch_grad(th, P, cfg["grid"], lam0, targets, w)
+    torch.cuda.synchronize()
+    mm, dl, lag = mm.cpu().numpy(), dl.cpu().numpy(), lag.cpu().numpy()
+    gsum = np.zeros(209)
+    for i in range(len(th)):
+        m_ref, j_ref, gap, gref = O.mismatch_grad_lambda(th[i], P, lam0, g, targets[i], 4 * g[1] * w)
+        assert gap > 1e-12, "ambiguous lag in the fixture"
+        assert lag[i] == j_ref
+        assert abs(mm[i] - m_ref) <= 1e-12, (mm[i], m_ref)
+        gsum += gref
+    assert np.max(np.abs(dl - gsum)) <= 1e-8 * np.max(np.abs(gsum)), np.max(np.abs(dl - gsum)) / np.max(np.abs(gsum))
+
+
+def test_domain_errors_give_nan_and_status(gpu, lam0):
+    import torch
+    rows = W.draw_sources(6, 5)
+    rows[1, 0] = -3.0                      # negative mass
+    rows[2, 4] = 0.0                       # D = 0
+    rows[3, 2] = 1.5                       # |chi| > 1
+    rows[4, 5] = np.nan                    # non-finite
+    grid = W.Grid(20.0, 0.25, 4017)
+    _say("domain errors waveform/loglike n=6")
+    h, st = gpu.api.waveform_eval(rows, P, grid, lam0)
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    data = W.complex_noise(psd, grid.df, 3)
+    lnl, grad, st2 = gpu.api.loglike_and_grad(rows, P, grid, lam0, data, 1 / psd)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert list(st) == [0, -2, -2, -2, -2, 0]
+    assert np.array_equal(st, st2.cpu().numpy())
+    h = h.cpu().numpy()
+    for i in (1, 2, 3, 4):
+        assert np.all(np.isnan(h[i]))
+        assert np.isnan(lnl[i].item()) and np.all(np.isnan(grad[i].cpu().numpy()))
+    for i in (0, 5):
+        ref = O.waveform(rows[i], P, lam0, grid.as_tuple())
+        assert _strain_err(h[i], ref) <= 1e-10
+
+
+def test_eta_quarter_mc_eta_is_domain_ok(gpu, lam0):
+    import torch
+    th = np.array([[20.0, 0.25, 0.1, -0.2, 500.0, 0.0, 0.0]])
+    grid = W.Grid(20.0, 0.25, 4017)
+    _say("eta = 1/4 in (Mc, eta)")
+    h, st = gpu.api.waveform_eval(th, O.PARAM_MC_ETA, grid, lam0)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    ref = O.waveform(th[0], O.PARAM_MC_ETA, lam0, grid.as_tuple())
+    assert _strain_err(h[0].cpu().numpy(), ref) <= 1e-10
+
+
+def test_empty_and_short_active_ranges(gpu, lam0):
+    """A source whose cutoff lies below the grid gives zero strain, lnL = 0, grad = 0; a source
+    with a handful of active bins matches the oracle."""
+    import torch
+    rows = np.array([[3000.0, 2500.0, 0.1, 0.2, 500.0, 0.0, 0.0],     # f_cut ~ 7 Hz < 20 Hz
+                     [1100.0, 900.0, 0.1, 0.2, 500.0, 0.0, 0.0],      # f_cut ~ 20.3 Hz
+                     [30.0, 20.0, 0.1, 0.2, 500.0, 0.0, 0.0]])
+    grid = W.Grid(20.0, 0.125, 8033)
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    data = W.complex_noise(psd, grid.df, 9)
+    _say("short active ranges n=3")
+    h, st = gpu.api.waveform_eval(rows, P, grid, lam0)
+    lnl, grad, _ = gpu.api.loglike_and_grad(rows, P, grid, lam0, data, 1 / psd)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy()
+    assert np.all(h[0] == 0) and lnl[0].item() == 0.0 and np.all(grad[0].cpu().numpy() == 0.0)
+    for i in (1, 2):
+        ref = O.waveform(rows[i], P, lam0, grid.as_tuple())
+        assert np.count_nonzero(ref) == np.count_nonzero(h[i])
+        assert _strain_err(h[i], ref) <= 1e-10
+        lref = O.loglike(rows[i], P, lam0, grid.as_tuple(), data, 1 / psd)
+        assert abs(lnl[i].item() - lref) <= 1e-10 * max(1.0, abs(lref))
+
+
+def test_batch_errors_raise_without_launch(gpu, lam0):
+    import ctypes
+    from paper_2302_05329_amd import _lib as L
+    g = L.make_grid(20.0, 0.25, 100, 20.0, 20.0)
+    rc = L.lib().pd_waveform_eval(None, 1, 3, ctypes.byref(g), None, 0, None, None, None, 0, None)
+    assert rc == L.PD_EINVAL
+    assert b"NULL" in L.lib().pd_last_error()
+    bad = L.make_grid(20.0, -1.0, 100, 20.0, 20.0)
+    with pytest.raises(L.PdError):
+        gpu.api.waveform_eval(np.array([[30.0, 20.0, 0, 0, 400, 0, 0]]), P, bad, lam0)
+    with pytest.raises(ValueError):
+        gpu.api.waveform_eval(np.zeros((2, 6)), P, W.Grid(20, 0.25, 100), lam0)
+
+
+def test_results_are_bitwise_reproducible(gpu, lam0):
+    import torch
+    cfg = W.config2(n=256)
+    _say("determinism loglike_and_grad n=256")
+    a = gpu.api.loglike_and_grad(cfg["theta"], P, cfg["grid"], lam0, cfg["data"], cfg["inv_psd"])
+    b = gpu.api.loglike_and_grad(cfg["theta"], P, cfg["grid"], lam0, cfg["data"], cfg["inv_psd"])
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
