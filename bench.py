@@ -1,0 +1,238 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = one fused log-likelihood + gradient evaluation (pd_loglike_and_grad) over the
+full batched-throughput workload: 65536 aligned-spin binaries on a 20-2048 Hz grid with
+df = 0.125 Hz (16225 bins), seeded Gaussian data coloured by the analytic PSD.  That pass
+runs every per-point and per-bin step of the likelihood path: parameter map, coefficient
+fits, final state, transitions and C1 stitching, phase and amplitude per bin, fused inner
+products, forward-mode gradient.
+
+Prints ONE JSON line.  Extra workloads (strain output, Fisher matrices, mismatch
+gradient, the paper's timing grid) are timed after the main loop and reported under
+"extra".  The CPU oracle is timed on a bounded sample under "cpu_baseline".
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-extra] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_calls(fn, iters, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / iters
+
+
+def kernel_avg_ms(api, kid):
+    ms, cnt = api.profile_read(kid)
+    return (ms / cnt) if cnt else float("nan"), cnt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "the path shards by parameter points without communication, see the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2302_05329_amd import api, flops, workloads as W
+    from paper_2302_05329_amd import _lib as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda"
+    lam = torch.as_tensor(W.load_lambda(), device=dev)
+    P = api.PARAM_M1M2
+
+    # ---------------- main workload: fused lnL + gradient, 65536 x 16225 ----------------
+    log("[bench] building C2 inputs")
+    c2 = W.config2()
+    g2 = c2["grid"]
+    th2 = torch.as_tensor(c2["theta"], device=dev)
+    d2 = torch.view_as_real(torch.as_tensor(c2["data"], device=dev)).contiguous()
+    ip2 = torch.as_tensor(c2["inv_psd"], device=dev)
+    ws = api.Workspace()
+    n2 = th2.shape[0]
+
+    def step():
+        return api.loglike_and_grad(th2, P, g2, lam, d2, ip2, want_grad=True, ws=ws)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        lnl, grad, st = step()
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    assert bool(torch.isfinite(lnl).all()) and bool(torch.isfinite(grad).all())
+
+    api.profile_enable(True)
+    api.profile_read(L.PD_K_LOGLIKE_GRAD)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms, kcnt = kernel_avg_ms(api, L.PD_K_LOGLIKE_GRAD)
+    api.profile_enable(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n2 * args.steps / elapsed
+
+    trans2 = api.transition_frequencies(th2, P, g2, lam, ws=ws).cpu().numpy()
+    fl, units = flops.batch_flops("loglike_grad", trans2, g2.as_tuple())
+    achieved_tf = fl / (kms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "k_loglike_moments<1>", "kernel_ms": round(kms, 4), "launches": kcnt,
+                "flops_per_launch": fl, "active_units": units, "flops_per_unit": round(fl / units, 2)}
+    log(f"[bench] C2 lnL+grad: {value:.4g} evals/s, {ms_per_step:.3f} ms/step, kernel {kms:.3f} ms, "
+        f"{achieved_tf:.2f} TFLOP/s algorithmic")
+
+    extra = {}
+    if not args.no_extra:
+        extra = run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(W, c2, args.cpu_seconds)
+
+    out = {
+        "metric": "IMRPhenomD loglike+grad evals/s (FP64 phase)",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "C2 fused lnL+grad: 65536 aligned-spin binaries x 16225 bins (20-2048 Hz, "
+                               "df=0.125 Hz), seeded noise, analytic aLIGO-like PSD",
+                   "points": n2, "n_bins": g2.n_bins, "precision": "FP64", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
+    import torch
+    dev = "cuda"
+    extra = {}
+    iters = 5
+
+    # value-only likelihood on the same batch
+    api.profile_enable(True)
+    api.profile_read(L.PD_K_LOGLIKE)
+    t = timed_calls(lambda: api.loglike_and_grad(th2, P, g2, lam, d2, ip2, want_grad=False, ws=ws), iters, 1)
+    kms, _ = kernel_avg_ms(api, L.PD_K_LOGLIKE)
+    fl, _ = flops.batch_flops("loglike", trans2, g2.as_tuple())
+    extra["C2_loglike_value"] = {"evals_per_s": th2.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
+                                 "tflops_algorithmic": fl / (kms * 1e-3) / 1e12}
+
+    # strain output, C1: 1024 x 4017 complex128
+    c1 = W.config1()
+    th1 = torch.as_tensor(c1["theta"], device=dev)
+    api.profile_read(L.PD_K_WAVEFORM)
+    t = timed_calls(lambda: api.waveform_eval(th1, P, c1["grid"], lam, ws=ws), iters, 1)
+    kms, _ = kernel_avg_ms(api, L.PD_K_WAVEFORM)
+    trans1 = api.transition_frequencies(th1, P, c1["grid"], lam, ws=ws).cpu().numpy()
+    fl, _ = flops.batch_flops("waveform", trans1, c1["grid"].as_tuple())
+    nbytes = th1.shape[0] * c1["grid"].n_bins * 16
+    extra["C1_waveform"] = {"waveforms_per_s": th1.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
+                            "hbm_write_GBs": nbytes / (kms * 1e-3) / 1e9,
+                            "tflops_algorithmic": fl / (kms * 1e-3) / 1e12}
+
+    # the paper's timing grid (24-512 Hz, df = 0.2 Hz, 2441 bins), same 1024 sources
+    gp = W.paper_timing_grid()
+    t = timed_calls(lambda: api.waveform_eval(th1, P, gp, lam, ws=ws), iters, 1)
+    api.profile_read(L.PD_K_WAVEFORM)
+    extra["paper_grid_waveform"] = {"waveforms_per_s": th1.shape[0] / t, "ms_per_waveform": 1e3 * t / th1.shape[0],
+                                    "paper_gpu_ms_per_waveform": 0.02, "paper_gpu": "NVIDIA Quadro 6000 (JAX)"}
+    del th1
+
+    # Fisher matrices, C3: 16384 x 16065 in (ln Mc, eta, chi1, chi2, ln D, tc, phic)
+    c3 = W.config3()
+    th3 = torch.as_tensor(W.to_param(c3["theta"], api.PARAM_LNMC_ETA_LND), device=dev)
+    ip3 = torch.as_tensor(c3["inv_psd"], device=dev)
+    api.profile_read(L.PD_K_FISHER)
+    t = timed_calls(lambda: api.fisher(th3, api.PARAM_LNMC_ETA_LND, c3["grid"], lam, ip3, ws=ws), 3, 1)
+    kms, _ = kernel_avg_ms(api, L.PD_K_FISHER)
+    trans3 = api.transition_frequencies(th3, api.PARAM_LNMC_ETA_LND, c3["grid"], lam, ws=ws).cpu().numpy()
+    fl, _ = flops.batch_flops("fisher", trans3, c3["grid"].as_tuple())
+    extra["C3_fisher"] = {"fishers_per_s": th3.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
+                          "tflops_algorithmic": fl / (kms * 1e-3) / 1e12}
+    del th3
+
+    # mismatch + gradient over the 209 coefficients, C4: 512 targets x 65536
+    c4 = W.config4()
+    th4 = torch.as_tensor(c4["theta"], device=dev)
+    lam_star = torch.as_tensor(c4["lam_star"], device=dev)
+    targets, _ = api.waveform_eval(th4, P, c4["grid"], lam_star, ws=ws)
+    targets = torch.view_as_real(targets).contiguous()
+    ip4 = torch.as_tensor(c4["inv_psd"], device=dev)
+    ws4 = api.Workspace()
+    for k in (L.PD_K_MISMATCH_INPUT, L.PD_K_MISMATCH_FFT, L.PD_K_MISMATCH_ADJ):
+        api.profile_read(k)
+    t = timed_calls(lambda: api.mismatch_grad(th4, P, c4["grid"], lam, targets, ip4, ws=ws4), 3, 1)
+    ks = {name: kernel_avg_ms(api, k)[0] for name, k in (("input", L.PD_K_MISMATCH_INPUT),
+                                                           ("fft", L.PD_K_MISMATCH_FFT),
+                                                           ("adjoint", L.PD_K_MISMATCH_ADJ))}
+    extra["C4_mismatch_grad"] = {"targets_per_s": th4.shape[0] / t, "ms": 1e3 * t, "kernel_ms": ks}
+    api.profile_enable(False)
+    return extra
+
+
+def cpu_baseline(W, c2, seconds):
+    """The CPU oracle (as it stands) on a bounded sample of the same C2 workload."""
+    from oracle import phenomd_oracle as O
+    g = c2["grid"].as_tuple()
+    th, data, ip = c2["theta"], c2["data"], c2["inv_psd"]
+    lam = W.load_lambda()
+    t0 = time.perf_counter()
+    n = 0
+    while n < 512 and (time.perf_counter() - t0) < seconds:
+        O.loglike(th[n], O.PARAM_M1M2, lam, g, data, ip)
+        O.loglike_grad(th[n], O.PARAM_M1M2, lam, g, data, ip)
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {th.shape[0]} C2 sources, full 16225-bin grid, lnL + complex-step "
+                      f"gradient (numpy, one process), {el:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

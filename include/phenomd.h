@@ -131,6 +131,33 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
                      double* mismatch, double* dsum_dlambda, int32_t* lag,
                      void* workspace, size_t workspace_bytes, void* stream);
 
+/* Per-point model quantities used to account the work of a batch (Sec. 2): for each row,
+ * out[i] = {M T_sun [s], Mf of the phase join intermediate->merger-ringdown (f_RD / 2),
+ *           Mf of the amplitude join intermediate->merger-ringdown (f_peak), valid (1/0)}.
+ * out     [n][4]              output
+ * Workspace as for PD_OP_WAVEFORM.
+ */
+int pd_transition_frequencies(const double* theta, int64_t n, int param, const pd_grid* grid,
+                              const double* lambda, double* out, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/* Kernel timing for benchmarks.  While enabled, every call brackets its dominant per-bin
+ * kernel with HIP events recorded on the call's own stream.  pd_profile_read() waits for
+ * the recorded events, returns the summed elapsed time (ms) and launch count of one kernel
+ * and clears its record.  Kernel ids: */
+enum {
+    PD_K_LOGLIKE_GRAD = 0,    /* fused lnL + gradient moments */
+    PD_K_LOGLIKE = 1,         /* fused lnL (value only) */
+    PD_K_FISHER = 2,          /* Fisher accumulation */
+    PD_K_WAVEFORM = 3,        /* strain output */
+    PD_K_MISMATCH_INPUT = 4,  /* overlap input (model per bin) */
+    PD_K_MISMATCH_FFT = 5,    /* both FFT passes with the fused arg-max */
+    PD_K_MISMATCH_ADJ = 6,    /* mismatch adjoint moments */
+    PD_K_COUNT = 7
+};
+int pd_profile_enable(int on);
+int pd_profile_read(int kernel, double* total_ms, int64_t* launches);
+
 /* Text of the last batch-level error on the calling thread (library-owned, never NULL). */
 const char* pd_last_error(void);
 

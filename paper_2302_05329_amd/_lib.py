@@ -30,6 +30,14 @@ PD_OP_LOGLIKE_GRAD = 2
 PD_OP_FISHER = 3
 PD_OP_MISMATCH_GRAD = 4
 
+PD_K_LOGLIKE_GRAD = 0
+PD_K_LOGLIKE = 1
+PD_K_FISHER = 2
+PD_K_WAVEFORM = 3
+PD_K_MISMATCH_INPUT = 4
+PD_K_MISMATCH_FFT = 5
+PD_K_MISMATCH_ADJ = 6
+
 
 class PdGrid(ctypes.Structure):
     _fields_ = [("f0", ctypes.c_double), ("df", ctypes.c_double), ("n_bins", ctypes.c_int64),
@@ -63,6 +71,9 @@ SIGNATURES = {
     "pd_adam_step": (_INT, [_P, _P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double, _I64, _P]),
     "pd_flow_param_count": (_I64, [_INT]),
+    "pd_transition_frequencies": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _SZ, _P]),
+    "pd_profile_enable": (_INT, [_INT]),
+    "pd_profile_read": (_INT, [_INT, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "pd_last_error": (ctypes.c_char_p, []),
     "pd_version": (ctypes.c_char_p, []),
 }

@@ -170,3 +170,30 @@ class LogLike(torch.autograd.Function):
     def backward(ctx, g_out):
         (grad,) = ctx.saved_tensors
         return g_out[:, None] * grad, None, None, None, None, None
+
+
+def transition_frequencies(theta, param, grid, lam, ws=None):
+    """Per point: (M T_sun [s], Mf of the phase join f_RD/2, Mf of the amplitude join f_peak, valid)."""
+    ws = ws or _default_ws
+    g = _grid(grid)
+    th = _dev(theta)
+    lam = _dev(lam)
+    _check_shapes(th, lam, g.n_bins)
+    n = th.shape[0]
+    out = torch.empty((n, 4), dtype=torch.float64, device="cuda")
+    wp, wb = ws.get(workspace_bytes(L.PD_OP_WAVEFORM, n, g.n_bins))
+    L.check(L.lib().pd_transition_frequencies(_ptr(th), n, param, ctypes.byref(g), _ptr(lam), _ptr(out), wp, wb,
+                                              _stream()))
+    return out
+
+
+def profile_enable(on=True):
+    L.check(L.lib().pd_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel):
+    """(total ms, launches) of one kernel id since the last read (waits for its events)."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    L.check(L.lib().pd_profile_read(int(kernel), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

@@ -1,14 +1,23 @@
-// Per-bin evaluation of the model from a coefficient record, and the "basis visitor"
-// that exposes, for every record entry that influences the bin, the partial derivative
-// of the phase Psi or of ln(amplitude) with respect to that entry.
+// Per-bin evaluation of the model from a coefficient record.
 //
-// The same visitor drives three reductions:
-//   * likelihood gradient and mismatch adjoint: moments  sum_k weight_k * partial_k
-//     (later contracted with the record's tangents per point);
-//   * Fisher matrix: per-bin tangents  sum_j tangent_j * partial_j  along 7 directions.
+// Two things keep a bin cheap:
+//  * source-independent per-bin factors are tabulated once per grid (per call):
+//    cbrt f, 1/cbrt f, ln f, f^(3/4), 1/f, f^(-7/6), and the noise-weighted data
+//    w f^(-7/6) d and weight w f^(-7/3) (w = 4 df / S_n).  With the per-point factors
+//    stored in the record (cbrt(pi Ms), ln Ms, Ms^(3/4), ...), v = (pi Mf)^(1/3), ln Mf,
+//    Mf^(3/4), 1/Mf and Mf^(-7/6) cost one multiply each; only sincos, atan and exp remain.
+//  * the model regions are contiguous in k, so loops run over region segments with the
+//    region fixed at compile time: no per-bin region branches and only that region's
+//    accumulators live.
+//
+// The "basis visitor" exposes, for every record entry that influences a bin, the partial
+// derivative of the phase Psi or of ln(amplitude) w.r.t. that entry.  It drives the
+// gradient and mismatch-adjoint moments (sum_k weight_k * partial_k, contracted with the
+// record tangents per point) and the per-bin tangents of the Fisher matrix.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "pd_math.h"
 #include "pd_model.h"
 
 namespace pd {
@@ -18,130 +27,222 @@ struct GridArgs {
     int64_t nb;
 };
 
-constexpr double kPi76 = 3.80196561521497470042;  // pi^(7/6)
+// Per-bin tables (structure of arrays, each n_bins long).
+enum : int { T_CB = 0, T_ICB, T_LF, T_F34, T_INF, T_F76, T_DWR, T_DWI, T_WW, T_N };
+
+struct Tabs {
+    const double* __restrict__ t;
+    int64_t nb;
+    __device__ __forceinline__ double at(int which, int64_t k) const { return t[which * nb + k]; }
+};
 
 // Frequency of bin k, rounded exactly as f0 + k*df (two roundings, no fused multiply-add).
 __device__ __forceinline__ double bin_freq(const GridArgs& g, int64_t k) {
     return __dadd_rn(g.f0, __dmul_rn(static_cast<double>(k), g.df));
 }
 
-// Conservative range [klo, khi) of bins that can carry signal for a source of mass Ms;
-// the exact test (f >= f_min and Ms f <= 0.2) is still applied to every bin.
-__device__ __forceinline__ void active_range(double ms, const GridArgs& g, int64_t& klo, int64_t& khi) {
-    const double kh = floor((kFCut / ms - g.f0) / g.df) + 2.0;
-    const double kl = ceil((g.fmin - g.f0) / g.df) - 1.0;
-    khi = (kh < 0.0) ? 0 : ((kh > static_cast<double>(g.nb)) ? g.nb : static_cast<int64_t>(kh));
-    klo = (kl < 0.0) ? 0 : ((kl > static_cast<double>(g.nb)) ? g.nb : static_cast<int64_t>(kl));
-    if (klo > khi) klo = khi;
-}
-
 __device__ __forceinline__ bool bin_active(const GridArgs& g, double f, double mf) {
     return (f >= g.fmin) && (mf <= kFCut);
 }
 
-// Everything one bin computes on the way to A and Psi, kept for the visitors.
+// First k in [lo, hi] with pred(k) true, for a predicate monotone in k (false ... true),
+// starting from an estimate and stepping to the exact bin.  Wave-uniform.
+template <class Pred>
+__device__ __forceinline__ int64_t first_true(Pred pred, int64_t est, int64_t lo, int64_t hi) {
+    int64_t k = est < lo ? lo : (est > hi ? hi : est);
+    while (k > lo && pred(k - 1)) --k;
+    while (k < hi && !pred(k)) ++k;
+    return k;
+}
+
+__device__ __forceinline__ int64_t clamp_est(double x, int64_t lo, int64_t hi) {
+    if (!(x > static_cast<double>(lo))) return lo;
+    if (x > static_cast<double>(hi)) return hi;
+    return static_cast<int64_t>(x);
+}
+
+// Exact active range [ka, kz) of a source: f_k >= f_min and Ms f_k <= 0.2.
+__device__ __forceinline__ void active_range(double ms, const GridArgs& g, int64_t& ka, int64_t& kz) {
+    auto ge_min = [&](int64_t k) { return bin_freq(g, k) >= g.fmin; };
+    auto above_cut = [&](int64_t k) { return ms * bin_freq(g, k) > kFCut; };
+    ka = first_true(ge_min, clamp_est(ceil((g.fmin - g.f0) / g.df), 0, g.nb), 0, g.nb);
+    kz = first_true(above_cut, clamp_est(floor((kFCut / ms - g.f0) / g.df), 0, g.nb), 0, g.nb);
+    if (kz < ka) kz = ka;
+}
+
+// Wave-uniform copy of a value every lane already agrees on (bin indices fit in 32 bits).
+__device__ __forceinline__ int uniform_i(int64_t x) { return __builtin_amdgcn_readfirstlane(static_cast<int>(x)); }
+
+// Region segments of [kb, ke) (already inside the active range).
+struct Segs {
+    int64_t k[6];
+    int pr[5], ar[5];
+    int n;
+};
+
+__device__ __forceinline__ void make_segments(const double* __restrict__ rec, const GridArgs& g, int64_t kb,
+                                              int64_t ke, Segs& S) {
+    const double ms = rec[R_MS];
+    const double th[4] = {kFAmpJoin, kFPhaseJoin, rec[R_FP2], rec[R_FA2]};
+    int64_t b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double t = th[i];
+        auto ge = [&](int64_t k) { return ms * bin_freq(g, k) >= t; };
+        b[i] = first_true(ge, clamp_est(ceil((t / ms - g.f0) / g.df), kb, ke), kb, ke);
+    }
+    // sort the four boundaries (tiny network)
+#define PD_SW(i, j)                 \
+    if (b[i] > b[j]) {              \
+        const int64_t _t = b[i];    \
+        b[i] = b[j];                \
+        b[j] = _t;                  \
+    }
+    PD_SW(0, 1) PD_SW(2, 3) PD_SW(0, 2) PD_SW(1, 3) PD_SW(1, 2)
+#undef PD_SW
+    int64_t pts[6] = {kb, b[0], b[1], b[2], b[3], ke};
+    S.n = 0;
+    for (int i = 0; i < 5; ++i) {
+        const int64_t s = pts[i], e = pts[i + 1];
+        if (e <= s) continue;
+        const double mf = ms * bin_freq(g, s);
+        S.k[S.n] = s;
+        S.k[S.n + 1] = e;
+        S.pr[S.n] = (mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3);
+        S.ar[S.n] = (mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3);
+        ++S.n;
+    }
+}
+
+// Everything one bin computes on the way to Ahat and Psi, kept for the visitors.
 struct BinVals {
     double mf;
-    int preg, areg;          // phase / amplitude region: 1 inspiral, 2 intermediate, 3 merger-ringdown
     double v, w, lv;         // v = (pi Mf)^(1/3), w = 1/v, ln v        (phase region 1)
     double lnf, invf;        // ln Mf, 1/Mf                              (phase regions 2, 3)
-    double f34, u, at, iu2;  // Mf^(3/4), (Mf - q)/d, atan(u), 1/(1+u^2) (phase region 3)
-    double x, den;           // Mf - f_RD, x^2 + g^2                     (amplitude region 3)
+    double f34, u, at;       // Mf^(3/4), (Mf - q)/d, atan(u)            (phase region 3)
+    double x, iden;          // Mf - f_RD, 1/(x^2 + g^2)                 (amplitude region 3)
     double ahat;             // amplitude ratio
-    double pf;               // Mf^(-7/6)
     double psi;              // phase
 };
 
-__device__ __forceinline__ void eval_bin(const double* __restrict__ rec, double mf, BinVals& b) {
+template <int PR, int AR>
+__device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const Tabs& T, int64_t k, double mf,
+                                           BinVals& b) {
     b.mf = mf;
-    b.preg = (mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3);
-    b.areg = (mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3);
-    const double* c = rec;
-    if (b.preg == 1) {
-        const double v = cbrt(kPi * mf);
-        const double w = 1.0 / v;
-        const double lv = log(v);
-        b.v = v;
-        b.w = w;
+    if (PR == 1 || AR == 1) {
+        b.v = c[R_CS] * T.at(T_CB, k);
+        b.w = c[R_ICS] * T.at(T_ICB, k);
+    }
+    if (PR == 1) {
+        const double v = b.v, w = b.w;
+        const double lv = fma(T.at(T_LF, k), 1.0 / 3.0, c[R_LCS]);
         b.lv = lv;
         const double w2 = w * w;
-        const double neg = w * (c[R_PH1 + 3] + w * (c[R_PH1 + 2] + w * (c[R_PH1 + 1] + w2 * c[R_PH1 + 0])));
-        const double pos =
-            c[R_PH1 + 4] +
-            v * (c[R_PH1 + 6] +
-                 v * (c[R_PH1 + 8] +
-                      v * (c[R_PH1 + 9] + v * (c[R_PH1 + 10] + v * (c[R_PH1 + 11] + v * c[R_PH1 + 12])))));
-        b.psi = neg + pos + lv * (c[R_PH1 + 5] + c[R_PH1 + 7] * v);
-        b.pf = kPi76 * (w2 * w) * sqrt(w);
-    } else if (b.preg == 2) {
-        const double lnf = log(mf);
-        const double invf = 1.0 / mf;
+        const double neg = w * fma(w, fma(w, fma(w2, c[R_PH1 + 0], c[R_PH1 + 1]), c[R_PH1 + 2]), c[R_PH1 + 3]);
+        double pos = fma(v, c[R_PH1 + 12], c[R_PH1 + 11]);
+        pos = fma(v, pos, c[R_PH1 + 10]);
+        pos = fma(v, pos, c[R_PH1 + 9]);
+        pos = fma(v, pos, c[R_PH1 + 8]);
+        pos = fma(v, pos, c[R_PH1 + 6]);
+        pos = fma(v, pos, c[R_PH1 + 4]);
+        b.psi = neg + pos + lv * fma(c[R_PH1 + 7], v, c[R_PH1 + 5]);
+    } else if (PR == 2) {
+        const double lnf = c[R_LMS] + T.at(T_LF, k);
+        const double invf = c[R_IMS] * T.at(T_INF, k);
         b.lnf = lnf;
         b.invf = invf;
-        b.psi = c[R_PH2 + 0] + c[R_PH2 + 1] * mf + c[R_PH2 + 2] * lnf + c[R_PH2 + 3] * (invf * invf * invf);
-        b.pf = exp(-(7.0 / 6.0) * lnf);
+        b.psi = fma(c[R_PH2 + 3], invf * invf * invf, fma(c[R_PH2 + 2], lnf, fma(c[R_PH2 + 1], mf, c[R_PH2 + 0])));
     } else {
-        const double invf = 1.0 / mf;
-        const double s = sqrt(mf);
-        const double f34 = s * sqrt(s);
-        const double u = (mf - c[R_PH3 + 5]) / c[R_PH3 + 6];
-        const double at = atan(u);
+        const double invf = c[R_IMS] * T.at(T_INF, k);
+        const double f34 = c[R_MS34] * T.at(T_F34, k);
+        const double u = (mf - c[R_PH3 + 5]) * c[R_ID];
+        const double at = pd_atan(u);
         b.invf = invf;
         b.f34 = f34;
         b.u = u;
         b.at = at;
-        b.iu2 = 1.0 / (1.0 + u * u);
-        b.psi = c[R_PH3 + 0] + c[R_PH3 + 1] * mf + c[R_PH3 + 2] * invf + c[R_PH3 + 3] * f34 + c[R_PH3 + 4] * at;
-        b.lnf = log(mf);
-        b.pf = exp(-(7.0 / 6.0) * b.lnf);
+        b.psi = fma(c[R_PH3 + 4], at,
+                    fma(c[R_PH3 + 3], f34, fma(c[R_PH3 + 2], invf, fma(c[R_PH3 + 1], mf, c[R_PH3 + 0]))));
     }
-    if (b.areg == 1) {
+    if (AR == 1) {
         const double v = b.v;
         double a = c[R_AM1 + 9];
 #pragma unroll
-        for (int i = 8; i >= 0; --i) a = a * v + c[R_AM1 + i];
+        for (int i = 8; i >= 0; --i) a = fma(a, v, c[R_AM1 + i]);
         b.ahat = a;
-    } else if (b.areg == 2) {
-        b.ahat = c[R_AM2 + 0] + mf * (c[R_AM2 + 1] + mf * (c[R_AM2 + 2] + mf * (c[R_AM2 + 3] + mf * c[R_AM2 + 4])));
+    } else if (AR == 2) {
+        b.ahat = fma(mf, fma(mf, fma(mf, fma(mf, c[R_AM2 + 4], c[R_AM2 + 3]), c[R_AM2 + 2]), c[R_AM2 + 1]),
+                     c[R_AM2 + 0]);
     } else {
         const double x = mf - c[R_AM3 + 1];
         const double g = c[R_AM3 + 2];
-        const double den = x * x + g * g;
+        const double iden = 1.0 / fma(x, x, g * g);
         b.x = x;
-        b.den = den;
-        b.ahat = c[R_AM3 + 0] / den * exp(-c[R_AM3 + 3] * x);
+        b.iden = iden;
+        b.ahat = c[R_AM3 + 0] * iden * pd_exp(-c[R_AM3 + 3] * x);
     }
+}
+
+// Runtime region dispatch for one-bin-per-thread kernels.
+__device__ __forceinline__ void eval_bin_rt(const double* __restrict__ rec, const Tabs& T, int64_t k, double mf,
+                                            BinVals& b) {
+    const int pr = (mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3);
+    const int ar = (mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3);
+    if (pr == 1) {
+        if (ar == 1)
+            eval_bin_t<1, 1>(rec, T, k, mf, b);
+        else if (ar == 2)
+            eval_bin_t<1, 2>(rec, T, k, mf, b);
+        else
+            eval_bin_t<1, 3>(rec, T, k, mf, b);
+    } else if (pr == 2) {
+        if (ar == 3)
+            eval_bin_t<2, 3>(rec, T, k, mf, b);
+        else
+            eval_bin_t<2, 2>(rec, T, k, mf, b);
+    } else {
+        if (ar == 3)
+            eval_bin_t<3, 3>(rec, T, k, mf, b);
+        else
+            eval_bin_t<3, 2>(rec, T, k, mf, b);
+    }
+}
+
+// Record entries a (phase region, amplitude region) pair touches.
+__host__ __device__ constexpr bool slot_touched(int pr, int ar, int s) {
+    return s == R_MS || s == R_LNA0 || (pr == 1 && s >= R_PH1 && s < R_PH1 + 13) ||
+           (pr == 2 && s >= R_PH2 && s < R_PH2 + 4) || (pr == 3 && s >= R_PH3 && s < R_PH3 + 7) ||
+           (ar == 1 && s >= R_AM1 && s < R_AM1 + 10) || (ar == 2 && s >= R_AM2 && s < R_AM2 + 5) ||
+           (ar == 3 && s >= R_AM3 && s < R_AM3 + 4);
 }
 
 // Visit d Psi / d rec[s] (vis.ph), d ln A / d rec[s] (vis.am) and the explicit
 // Mf-dependence: Mf dPsi/dMf and Mf d lnA/dMf (vis.fd), for one bin.
-template <class V>
-__device__ __forceinline__ void visit_bin(const double* __restrict__ rec, const BinVals& b, V& vis) {
-    const double* c = rec;
+template <int PR, int AR, class V>
+__device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const BinVals& b, V& vis) {
     double fpsi;
-    if (b.preg == 1) {
+    if (PR == 1) {
         const double v = b.v, w = b.w, lv = b.lv;
         const double w2 = w * w, w3 = w2 * w, w5 = w3 * w2;
         const double v2 = v * v, v3 = v2 * v, v4 = v3 * v, v5 = v4 * v, v6 = v5 * v;
         const double bs[13] = {w5, w3, w2, w, 1.0, lv, v, v * lv, v2, v3, v4, v5, v6};
         const double pw[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
-        fpsi = (c[R_PH1 + 5] + c[R_PH1 + 7] * v) * (1.0 / 3.0);
+        fpsi = fma(c[R_PH1 + 7], v, c[R_PH1 + 5]) * (1.0 / 3.0);
 #pragma unroll
         for (int j = 0; j < 13; ++j) {
             vis.ph(R_PH1 + j, bs[j]);
-            fpsi += c[R_PH1 + j] * bs[j] * (pw[j] * (1.0 / 3.0));
+            if (pw[j] != 0.0) fpsi = fma(c[R_PH1 + j] * (pw[j] * (1.0 / 3.0)), bs[j], fpsi);
         }
-    } else if (b.preg == 2) {
+    } else if (PR == 2) {
         const double i3 = b.invf * b.invf * b.invf;
         vis.ph(R_PH2 + 0, 1.0);
         vis.ph(R_PH2 + 1, b.mf);
         vis.ph(R_PH2 + 2, b.lnf);
         vis.ph(R_PH2 + 3, i3);
-        fpsi = c[R_PH2 + 1] * b.mf + c[R_PH2 + 2] - 3.0 * c[R_PH2 + 3] * i3;
+        fpsi = fma(c[R_PH2 + 1], b.mf, fma(-3.0 * c[R_PH2 + 3], i3, c[R_PH2 + 2]));
     } else {
-        const double d = c[R_PH3 + 6];
-        const double c4 = c[R_PH3 + 4];
-        const double t = c4 * b.iu2 / d;
+        const double iu2 = 1.0 / fma(b.u, b.u, 1.0);
+        const double t = c[R_PH3 + 4] * iu2 * c[R_ID];
         vis.ph(R_PH3 + 0, 1.0);
         vis.ph(R_PH3 + 1, b.mf);
         vis.ph(R_PH3 + 2, b.invf);
@@ -149,11 +250,11 @@ __device__ __forceinline__ void visit_bin(const double* __restrict__ rec, const 
         vis.ph(R_PH3 + 4, b.at);
         vis.ph(R_PH3 + 5, -t);
         vis.ph(R_PH3 + 6, -t * b.u);
-        fpsi = c[R_PH3 + 1] * b.mf - c[R_PH3 + 2] * b.invf + 0.75 * c[R_PH3 + 3] * b.f34 + t * b.mf;
+        fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(0.75 * c[R_PH3 + 3], b.f34, t * b.mf)));
     }
     double fa;
     vis.am(R_LNA0, 1.0);
-    if (b.areg == 1) {
+    if (AR == 1) {
         const double ia = 1.0 / b.ahat;
         double p = ia;
         double acc = 0.0;
@@ -162,10 +263,10 @@ __device__ __forceinline__ void visit_bin(const double* __restrict__ rec, const 
         for (int i = 1; i < 10; ++i) {
             p *= b.v;
             vis.am(R_AM1 + i, p);
-            acc += c[R_AM1 + i] * p * (i * (1.0 / 3.0));
+            acc = fma(c[R_AM1 + i] * (i * (1.0 / 3.0)), p, acc);
         }
         fa = acc;
-    } else if (b.areg == 2) {
+    } else if (AR == 2) {
         const double ia = 1.0 / b.ahat;
         const double f = b.mf;
         double p = ia;
@@ -175,33 +276,33 @@ __device__ __forceinline__ void visit_bin(const double* __restrict__ rec, const 
         for (int i = 1; i < 5; ++i) {
             p *= f;
             vis.am(R_AM2 + i, p);
-            acc += c[R_AM2 + i] * p * i;
+            acc = fma(c[R_AM2 + i] * i, p, acc);
         }
         fa = acc;
     } else {
-        const double x = b.x, den = b.den, g = c[R_AM3 + 2], r = c[R_AM3 + 3];
-        const double tx = 2.0 * x / den;
+        const double x = b.x, g = c[R_AM3 + 2], r = c[R_AM3 + 3];
+        const double tx = 2.0 * x * b.iden;
         vis.am(R_AM3 + 0, 1.0 / c[R_AM3 + 0]);
         vis.am(R_AM3 + 1, tx + r);
-        vis.am(R_AM3 + 2, -2.0 * g / den);
+        vis.am(R_AM3 + 2, -2.0 * g * b.iden);
         vis.am(R_AM3 + 3, -x);
-        fa = b.mf * (-tx - r);
+        fa = -b.mf * (tx + r);
     }
     vis.fd(fpsi, fa - 7.0 / 6.0);
 }
 
-// Chunk of bins [kb, ke) handled by wavefront `c` of `chunks` for one point.
+// Chunk of the active range [kb, ke) handled by wavefront `c` of `chunks` for one point.
 __device__ __forceinline__ void chunk_range(double ms, const GridArgs& g, int c, int chunks, int64_t& kb,
                                             int64_t& ke) {
-    int64_t klo, khi;
-    active_range(ms, g, klo, khi);
-    const int64_t len = khi - klo;
+    int64_t ka, kz;
+    active_range(ms, g, ka, kz);
+    const int64_t len = kz - ka;
     int64_t per = (len + chunks - 1) / chunks;
     per = (per + 63) & ~static_cast<int64_t>(63);
-    kb = klo + static_cast<int64_t>(c) * per;
+    kb = ka + static_cast<int64_t>(c) * per;
     ke = kb + per;
-    if (kb > khi) kb = khi;
-    if (ke > khi) ke = khi;
+    if (kb > kz) kb = kz;
+    if (ke > kz) ke = kz;
 }
 
 // ---- deterministic wavefront reduction (fixed butterfly order) ---------------------
@@ -209,6 +310,29 @@ __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     return x;
+}
+
+// Dispatch a functor templated on the (phase, amplitude) region pair.
+template <class F>
+__device__ __forceinline__ void dispatch_region(int pr, int ar, F& f) {
+    if (pr == 1) {
+        if (ar == 1)
+            f.template run<1, 1>();
+        else if (ar == 2)
+            f.template run<1, 2>();
+        else
+            f.template run<1, 3>();
+    } else if (pr == 2) {
+        if (ar == 3)
+            f.template run<2, 3>();
+        else
+            f.template run<2, 2>();
+    } else {
+        if (ar == 3)
+            f.template run<3, 3>();
+        else
+            f.template run<3, 2>();
+    }
 }
 
 }  // namespace pd

@@ -4,11 +4,45 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/phenomd.h"
 #include "pd_launch.h"
 #include "pd_mismatch.h"
+#include "pd_profile.h"
+
+// ---- kernel timing ------------------------------------------------------------------------
+namespace pd {
+namespace {
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_ev[PD_K_COUNT];
+}  // namespace
+
+ProfRange::ProfRange(int id, hipStream_t s) : id_(id), s_(s) {
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on_ = g_prof_on && id >= 0 && id < PD_K_COUNT;
+    }
+    if (on_ && hipEventCreate(&e0_) == hipSuccess) {
+        if (hipEventRecord(e0_, s_) != hipSuccess) on_ = false;
+    } else {
+        on_ = false;
+    }
+}
+
+ProfRange::~ProfRange() {
+    if (!on_) return;
+    hipEvent_t e1 = nullptr;
+    if (hipEventCreate(&e1) != hipSuccess) return;
+    if (hipEventRecord(e1, s_) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_ev[id_].emplace_back(e0_, e1);
+}
+}  // namespace pd
 
 namespace {
 
@@ -28,7 +62,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec = 0, tan = 0, partial = 0, extra = 0, total = 0;
+    size_t rec = 0, tab = 0, tan = 0, partial = 0, extra = 0, total = 0;
     int chunks = 1;
 };
 
@@ -38,6 +72,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
     size_t off = 0;
     L.rec = off;
     off = align_up(off + N * pd::REC_N * sizeof(double));
+    L.tab = off;
+    off = align_up(off + static_cast<size_t>(nb) * pd::T_N * sizeof(double));
     switch (op) {
         case PD_OP_WAVEFORM:
             break;
@@ -120,6 +156,34 @@ size_t pd_workspace_bytes(int op, int64_t n, int64_t n_bins) {
 
 const char* pd_last_error(void) { return g_last_error.c_str(); }
 
+int pd_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(pd::g_prof_mu);
+    pd::g_prof_on = (on != 0);
+    return PD_OK;
+}
+
+int pd_profile_read(int kernel, double* total_ms, int64_t* launches) {
+    if (kernel < 0 || kernel >= PD_K_COUNT) return fail(PD_EINVAL, "unknown kernel id");
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(pd::g_prof_mu);
+        ev.swap(pd::g_prof_ev[kernel]);
+    }
+    double sum = 0.0;
+    int rc = PD_OK;
+    for (auto& pr : ev) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(pr.second) != hipSuccess || hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+            rc = fail(PD_EHIP, "event timing failed");
+        sum += ms;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = static_cast<int64_t>(ev.size());
+    return rc;
+}
+
 const char* pd_version(void) { return "phenomd-mi355x 0.1 (gfx950)"; }
 
 int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
@@ -135,9 +199,12 @@ int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* g
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* recs = at<double>(workspace, L.rec);
+    double* tab = at<double>(workspace, L.tab);
     hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
     if (e != hipSuccess) return fail_hip(e, "setup");
-    e = pd::launch_waveform(recs, n, g, precision, h_out, s);
+    e = pd::launch_tables(g, nullptr, nullptr, tab, s);
+    if (e != hipSuccess) return fail_hip(e, "tables");
+    e = pd::launch_waveform(recs, n, g, tab, precision, h_out, s);
     if (e != hipSuccess) return fail_hip(e, "waveform");
     return PD_OK;
 }
@@ -160,13 +227,16 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
     double* recs = at<double>(workspace, L.rec);
     double* tans = grad ? at<double>(workspace, L.tan) : nullptr;
     double* partial = at<double>(workspace, L.partial);
+    double* tab = at<double>(workspace, L.tab);
     hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
     if (e != hipSuccess) return fail_hip(e, "setup");
     if (grad) {
         e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, recs, tans, s);
         if (e != hipSuccess) return fail_hip(e, "setup tangents");
     }
-    e = pd::launch_loglike(recs, tans, n, L.chunks, g, data, inv_psd, partial, lnl, grad, s);
+    e = pd::launch_tables(g, data, inv_psd, tab, s);
+    if (e != hipSuccess) return fail_hip(e, "tables");
+    e = pd::launch_loglike(recs, tans, n, L.chunks, g, tab, partial, lnl, grad, s);
     if (e != hipSuccess) return fail_hip(e, "loglike");
     return PD_OK;
 }
@@ -186,12 +256,33 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, co
     double* recs = at<double>(workspace, L.rec);
     double* tans = at<double>(workspace, L.tan);
     double* partial = at<double>(workspace, L.partial);
+    double* tab = at<double>(workspace, L.tab);
     hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
     if (e != hipSuccess) return fail_hip(e, "setup");
     e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, recs, tans, s);
     if (e != hipSuccess) return fail_hip(e, "setup tangents");
-    e = pd::launch_fisher(recs, tans, n, L.chunks, g, inv_psd, partial, F, s);
+    e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
+    if (e != hipSuccess) return fail_hip(e, "tables");
+    e = pd::launch_fisher(recs, tans, n, L.chunks, g, tab, partial, F, s);
     if (e != hipSuccess) return fail_hip(e, "fisher");
+    return PD_OK;
+}
+
+int pd_transition_frequencies(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                              double* out, void* workspace, size_t workspace_bytes, void* stream) {
+    pd::GridArgs g;
+    int rc = check_common(theta, n, param, grid, lambda, &g);
+    if (rc) return rc;
+    if (!out) return fail(PD_EINVAL, "out is NULL");
+    Layout L;
+    rc = check_ws(PD_OP_WAVEFORM, n, g.nb, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* recs = at<double>(workspace, L.rec);
+    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, nullptr, s);
+    if (e != hipSuccess) return fail_hip(e, "setup");
+    e = pd::launch_transitions(recs, n, out, s);
+    if (e != hipSuccess) return fail_hip(e, "transitions");
     return PD_OK;
 }
 
@@ -212,13 +303,16 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
     double* recs = at<double>(workspace, L.rec);
     double* tans = at<double>(workspace, L.tan);
     void* scratch = at<void>(workspace, L.extra);
+    double* tab = at<double>(workspace, L.tab);
     hipError_t e = pd::launch_setup_value(theta, nt, param, g.fref, lambda, recs, nullptr, s);
     if (e != hipSuccess) return fail_hip(e, "setup");
+    e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
+    if (e != hipSuccess) return fail_hip(e, "tables");
     if (dsum_dlambda) {
         e = pd::launch_setup_fit_tangent(theta, nt, param, g.fref, lambda, recs, tans, s);
         if (e != hipSuccess) return fail_hip(e, "setup fit tangents");
     }
-    e = pd::launch_mismatch(recs, dsum_dlambda ? tans : nullptr, nt, g, targets, inv_psd, scratch, mismatch,
+    e = pd::launch_mismatch(recs, dsum_dlambda ? tans : nullptr, nt, g, tab, targets, inv_psd, scratch, mismatch,
                             dsum_dlambda, lag, s);
     if (e != hipSuccess) return fail_hip(e, "mismatch");
     return PD_OK;

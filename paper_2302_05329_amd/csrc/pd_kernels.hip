@@ -1,20 +1,24 @@
-// HIP kernels for gfx950: per-point setup, strain output, fused likelihood (+gradient),
-// Fisher matrices.
+// HIP kernels for gfx950: per-point setup, per-grid tables, strain output, fused
+// likelihood (+gradient), Fisher matrices.
 //
 // Launch shapes
 //   setup      one thread per point (value record, or record + 7 theta tangents), or one
 //              thread per (point, fit parameter) for the 19 coefficient tangents.
+//   tables     one thread per bin: source-independent factors of the grid, once per call.
 //   waveform   one thread per bin, 256-bin blocks, point-major: writes complex128.
-//   moments    one wavefront per (point, bin chunk); consecutive bins across the 64 lanes
-//              so a wavefront sits in one model region except at the joins.  Per-lane
-//              accumulators, one fixed-order butterfly reduction, one row of partial sums.
+//   moments    one wavefront per (point, bin chunk).  The chunk is split into model-region
+//              segments; each segment loop has its region fixed at compile time.  Lanes
+//              take consecutive bins (coalesced table reads), accumulate per lane, and a
+//              fixed-order butterfly reduces each segment's moments; lane s keeps slot s.
 //   epilogue   one thread per point: sums the chunks in order, contracts moments with
 //              record tangents.
 // No atomics anywhere: results are bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include "../../include/phenomd.h"
 #include "pd_bin.h"
 #include "pd_launch.h"
+#include "pd_profile.h"
 
 namespace pd {
 
@@ -120,17 +124,57 @@ __global__ void __launch_bounds__(64) k_setup_fit_tangent(const double* __restri
 }
 
 // ==================================================================================
+// per-grid tables
+// ==================================================================================
+
+__global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __restrict__ data,
+                                                const double* __restrict__ inv_psd, double* __restrict__ tab) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= g.nb) return;
+    const double f = bin_freq(g, k);
+    double cb = 0.0, icb = 0.0, lf = 0.0, f34 = 0.0, inf = 0.0, f76 = 0.0;
+    if (f > 0.0) {
+        cb = cbrt(f);
+        icb = 1.0 / cb;
+        lf = log(f);
+        f34 = pow(f, 0.75);
+        inf = 1.0 / f;
+        f76 = pow(f, -7.0 / 6.0);
+    }
+    const int64_t nb = g.nb;
+    tab[T_CB * nb + k] = cb;
+    tab[T_ICB * nb + k] = icb;
+    tab[T_LF * nb + k] = lf;
+    tab[T_F34 * nb + k] = f34;
+    tab[T_INF * nb + k] = inf;
+    tab[T_F76 * nb + k] = f76;
+    double dwr = 0.0, dwi = 0.0, ww = 0.0;
+    if (inv_psd) {
+        const double w = 4.0 * g.df * inv_psd[k];
+        ww = w * f76 * f76;
+        if (data) {
+            const double2 d = reinterpret_cast<const double2*>(data)[k];
+            dwr = w * f76 * d.x;
+            dwi = w * f76 * d.y;
+        }
+    }
+    tab[T_DWR * nb + k] = dwr;
+    tab[T_DWI * nb + k] = dwi;
+    tab[T_WW * nb + k] = ww;
+}
+
+// ==================================================================================
 // strain output
 // ==================================================================================
 
-template <bool MIXED>
 __global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ recs, int64_t n, int64_t blocks_per_point,
-                                                  GridArgs g, double* __restrict__ h) {
+                                                  GridArgs g, const double* __restrict__ tab, double* __restrict__ h) {
     const int64_t b = blockIdx.x;
     const int64_t p = b / blocks_per_point;
     const int64_t k = (b % blocks_per_point) * 256 + threadIdx.x;
     if (p >= n || k >= g.nb) return;
     const double* __restrict__ rec = recs + p * REC_N;
+    const Tabs T{tab, g.nb};
     double2 out = make_double2(0.0, 0.0);
     if (rec[R_VALID] == 0.0) {
         out = make_double2(__builtin_nan(""), __builtin_nan(""));
@@ -139,10 +183,10 @@ __global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ rec
         const double mf = rec[R_MS] * f;
         if (bin_active(g, f, mf)) {
             BinVals bv;
-            eval_bin(rec, mf, bv);
-            const double A = rec[R_A0] * bv.pf * bv.ahat;
+            eval_bin_rt(rec, T, k, mf, bv);
+            const double A = rec[R_A0P] * T.at(T_F76, k) * bv.ahat;
             double s, c;
-            sincos(bv.psi, &s, &c);
+            pd_sincos(bv.psi, &s, &c);
             out = make_double2(A * c, -A * s);
         }
     }
@@ -156,16 +200,65 @@ __global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ rec
 struct MomVis {
     double* mom;
     double zr, zi;
-    __device__ __forceinline__ void ph(int s, double b) { mom[s] += zi * b; }
-    __device__ __forceinline__ void am(int s, double b) { mom[s] += zr * b; }
-    __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] += zi * fpsi + zr * fa; }
+    __device__ __forceinline__ void ph(int s, double b) { mom[s] = fma(zi, b, mom[s]); }
+    __device__ __forceinline__ void am(int s, double b) { mom[s] = fma(zr, b, mom[s]); }
+    __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] = fma(zi, fpsi, fma(zr, fa, mom[R_MS])); }
 };
 
-// MODE 0: (d|h), (h|h).  MODE 1: + moments of the gradient.
+// Fold a segment's per-lane moments into the per-lane slot totals (lane s keeps slot s).
+template <int PR, int AR>
+__device__ __forceinline__ void flush_moments(const double (&mom)[REC_N], int lane, double& tot) {
+#pragma unroll
+    for (int s = 0; s < REC_N; ++s) {
+        if (slot_touched(PR, AR, s)) {
+            const double t = wave_sum(mom[s]);
+            if (lane == s) tot += t;
+        }
+    }
+}
+
+// One region segment of the likelihood loop.  MODE 0: (d|h), (h|h); MODE 1: + moments.
+template <int MODE>
+struct LnlSegment {
+    const double* __restrict__ rec;
+    Tabs T;
+    GridArgs g;
+    int64_t k0, k1;
+    int lane;
+    double dh, hh, tot;
+
+    template <int PR, int AR>
+    __device__ __forceinline__ void run() {
+        const double ms = rec[R_MS];
+        const double a0p = rec[R_A0P];
+        double mom[REC_N];
+#pragma unroll
+        for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
+        for (int64_t k = k0 + lane; k < k1; k += 64) {
+            const double mf = ms * bin_freq(g, k);
+            BinVals bv;
+            eval_bin_t<PR, AR>(rec, T, k, mf, bv);
+            double sn, cs;
+            pd_sincos(bv.psi, &sn, &cs);
+            const double hr = bv.ahat * cs, hi = -bv.ahat * sn;
+            const double dwr = T.at(T_DWR, k), dwi = T.at(T_DWI, k);
+            const double px = fma(dwr, hr, dwi * hi);
+            const double q = T.at(T_WW, k) * bv.ahat * bv.ahat;
+            dh += px;
+            hh += q;
+            if (MODE == 1) {
+                const double py = fma(dwr, hi, -dwi * hr);
+                MomVis vis{mom, a0p * fma(-a0p, q, px), a0p * py};
+                visit_bin_t<PR, AR>(rec, bv, vis);
+            }
+        }
+        if (MODE == 1) flush_moments<PR, AR>(mom, lane, tot);
+    }
+};
+
 template <int MODE>
 __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
-                                                         GridArgs g, const double* __restrict__ data,
-                                                         const double* __restrict__ inv_psd,
+                                                         GridArgs g, const double* __restrict__ tab,
                                                          double* __restrict__ partial) {
     constexpr int NS = (MODE == 0) ? 2 : kNSlot;
     const int lane = threadIdx.x & 63;
@@ -179,50 +272,27 @@ __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restric
         for (int s = lane; s < NS; s += 64) out[s] = 0.0;
         return;
     }
-    const double ms = rec[R_MS];
-    const double a0 = rec[R_A0];
     int64_t kb, ke;
-    chunk_range(ms, g, c, chunks, kb, ke);
-    const double w4 = 4.0 * g.df;
-
-    double dh = 0.0, hh = 0.0;
-    double mom[REC_N];
+    chunk_range(rec[R_MS], g, c, chunks, kb, ke);
+    Segs S;
+    make_segments(rec, g, kb, ke, S);
+    LnlSegment<MODE> seg{rec, Tabs{tab, g.nb}, g, 0, 0, lane, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
-
-    for (int64_t k = kb + lane; k < ke; k += 64) {
-        const double f = bin_freq(g, k);
-        const double mf = ms * f;
-        if (!bin_active(g, f, mf)) continue;
-        BinVals bv;
-        eval_bin(rec, mf, bv);
-        const double A = a0 * bv.pf * bv.ahat;
-        double sn, cs;
-        sincos(bv.psi, &sn, &cs);
-        const double hr = A * cs, hi = -A * sn;
-        const double w = w4 * inv_psd[k];
-        const double2 d = reinterpret_cast<const double2*>(data)[k];
-        dh += w * (d.x * hr + d.y * hi);
-        hh += w * (hr * hr + hi * hi);
-        if (MODE == 1) {
-            const double rr = d.x - hr, ri = d.y - hi;
-            MomVis vis{mom, w * (rr * hr + ri * hi), w * (rr * hi - ri * hr)};
-            visit_bin(rec, bv, vis);
+    for (int i = 0; i < 5; ++i) {
+        if (i < S.n) {
+            seg.k0 = uniform_i(S.k[i]);
+            seg.k1 = uniform_i(S.k[i + 1]);
+            dispatch_region(uniform_i(S.pr[i]), uniform_i(S.ar[i]), seg);
         }
     }
-    const double sdh = wave_sum(dh);
-    const double shh = wave_sum(hh);
+    const double a0p = rec[R_A0P];
+    const double sdh = wave_sum(seg.dh) * a0p;
+    const double shh = wave_sum(seg.hh) * (a0p * a0p);
     if (lane == 0) {
         out[0] = sdh;
         out[1] = shh;
     }
-    if (MODE == 1) {
-#pragma unroll
-        for (int s = 0; s < REC_N; ++s) {
-            const double t = wave_sum(mom[s]);
-            if (lane == 0) out[2 + s] = t;
-        }
-    }
+    if (MODE == 1 && lane < REC_N) out[2 + lane] = seg.tot;
 }
 
 // One thread per point: sum the chunks, write lnL and (MODE 1) the gradient.
@@ -267,29 +337,67 @@ __global__ void __launch_bounds__(128) k_loglike_epilogue(const double* __restri
 
 struct FisherVis {
     const double* T;   // [7][REC_N] tangents in LDS
-    double ms;
+    double ims;
     double dpsi[7], dlna[7];
     __device__ __forceinline__ void ph(int s, double b) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) dpsi[q] += T[q * REC_N + s] * b;
+        for (int q = 0; q < 7; ++q) dpsi[q] = fma(T[q * REC_N + s], b, dpsi[q]);
     }
     __device__ __forceinline__ void am(int s, double b) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) dlna[q] += T[q * REC_N + s] * b;
+        for (int q = 0; q < 7; ++q) dlna[q] = fma(T[q * REC_N + s], b, dlna[q]);
     }
     __device__ __forceinline__ void fd(double fpsi, double fa) {
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
-            const double m = T[q * REC_N + R_MS] / ms;
-            dpsi[q] += m * fpsi;
-            dlna[q] += m * fa;
+            const double m = T[q * REC_N + R_MS] * ims;
+            dpsi[q] = fma(m, fpsi, dpsi[q]);
+            dlna[q] = fma(m, fa, dlna[q]);
+        }
+    }
+};
+
+struct FisherSegment {
+    const double* __restrict__ rec;
+    const double* Tl;
+    Tabs T;
+    GridArgs g;
+    int64_t k0, k1;
+    int lane;
+    double F[28];
+
+    template <int PR, int AR>
+    __device__ __forceinline__ void run() {
+        const double ms = rec[R_MS];
+        const double a0p = rec[R_A0P];
+        for (int64_t k = k0 + lane; k < k1; k += 64) {
+            const double mf = ms * bin_freq(g, k);
+            BinVals bv;
+            eval_bin_t<PR, AR>(rec, T, k, mf, bv);
+            const double W = (a0p * a0p) * T.at(T_WW, k) * bv.ahat * bv.ahat;
+            FisherVis vis;
+            vis.T = Tl;
+            vis.ims = rec[R_IMS];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) vis.dpsi[q] = vis.dlna[q] = 0.0;
+            visit_bin_t<PR, AR>(rec, bv, vis);
+            int s = 0;
+#pragma unroll
+            for (int a = 0; a < 7; ++a) {
+                const double wa = W * vis.dlna[a], wp = W * vis.dpsi[a];
+#pragma unroll
+                for (int b = a; b < 7; ++b) {
+                    F[s] = fma(wa, vis.dlna[b], fma(wp, vis.dpsi[b], F[s]));
+                    ++s;
+                }
+            }
         }
     }
 };
 
 __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict__ recs,
                                                         const double* __restrict__ tans, int64_t n, int chunks,
-                                                        GridArgs g, const double* __restrict__ inv_psd,
+                                                        GridArgs g, const double* __restrict__ tab,
                                                         double* __restrict__ partial) {
     __shared__ double lds[4][7 * REC_N];
     const int lane = threadIdx.x & 63;
@@ -310,42 +418,29 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
         if (lane < 28) out[lane] = 0.0;
         return;
     }
-    const double ms = rec[R_MS];
-    const double a0 = rec[R_A0];
     int64_t kb, ke;
-    chunk_range(ms, g, c, chunks, kb, ke);
-    const double w4 = 4.0 * g.df;
-    double F[28];
+    chunk_range(rec[R_MS], g, c, chunks, kb, ke);
+    Segs S;
+    make_segments(rec, g, kb, ke, S);
+    FisherSegment seg;
+    seg.rec = rec;
+    seg.Tl = T;
+    seg.T = Tabs{tab, g.nb};
+    seg.g = g;
+    seg.lane = lane;
 #pragma unroll
-    for (int s = 0; s < 28; ++s) F[s] = 0.0;
-    for (int64_t k = kb + lane; k < ke; k += 64) {
-        const double f = bin_freq(g, k);
-        const double mf = ms * f;
-        if (!bin_active(g, f, mf)) continue;
-        BinVals bv;
-        eval_bin(rec, mf, bv);
-        const double A = a0 * bv.pf * bv.ahat;
-        const double W = w4 * inv_psd[k] * A * A;
-        FisherVis vis;
-        vis.T = T;
-        vis.ms = ms;
+    for (int s = 0; s < 28; ++s) seg.F[s] = 0.0;
 #pragma unroll
-        for (int q = 0; q < 7; ++q) vis.dpsi[q] = vis.dlna[q] = 0.0;
-        visit_bin(rec, bv, vis);
-        int s = 0;
-#pragma unroll
-        for (int a = 0; a < 7; ++a) {
-            const double wa = W * vis.dlna[a], wp = W * vis.dpsi[a];
-#pragma unroll
-            for (int b = a; b < 7; ++b) {
-                F[s] += wa * vis.dlna[b] + wp * vis.dpsi[b];
-                ++s;
-            }
+    for (int i = 0; i < 5; ++i) {
+        if (i < S.n) {
+            seg.k0 = uniform_i(S.k[i]);
+            seg.k1 = uniform_i(S.k[i + 1]);
+            dispatch_region(uniform_i(S.pr[i]), uniform_i(S.ar[i]), seg);
         }
     }
 #pragma unroll
     for (int s = 0; s < 28; ++s) {
-        const double t = wave_sum(F[s]);
+        const double t = wave_sum(seg.F[s]);
         if (lane == 0) out[s] = t;
     }
 }
@@ -371,6 +466,16 @@ __global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restric
             out[b * 7 + a] = acc[s];
             ++s;
         }
+}
+
+__global__ void k_transitions(const double* __restrict__ recs, int64_t n, double* __restrict__ out) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double* rec = recs + p * REC_N;
+    out[p * 4 + 0] = rec[R_MS];
+    out[p * 4 + 1] = rec[R_FP2];
+    out[p * 4 + 2] = rec[R_FA2];
+    out[p * 4 + 3] = rec[R_VALID];
 }
 
 // ==================================================================================
@@ -402,28 +507,42 @@ hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, d
     return hipGetLastError();
 }
 
-hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, int precision, double* h,
-                           hipStream_t s) {
+hipError_t launch_tables(const GridArgs& g, const double* data, const double* inv_psd, double* tab,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_tables, dim3(blocks_for(g.nb, 256)), dim3(256), 0, s, g, data, inv_psd, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_transitions, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
+                           double* h, hipStream_t s) {
     const int64_t bpp = (g.nb + 255) / 256;
-    hipLaunchKernelGGL(k_waveform<false>, dim3(static_cast<unsigned>(bpp * n)), dim3(256), 0, s, recs, n, bpp, g,
-                       h);
+    ProfRange pr(PD_K_WAVEFORM, s);
+    hipLaunchKernelGGL(k_waveform, dim3(static_cast<unsigned>(bpp * n)), dim3(256), 0, s, recs, n, bpp, g, tab, h);
     (void)precision;
     return hipGetLastError();
 }
 
 hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                          const double* data, const double* inv_psd, double* partial, double* lnl, double* grad,
-                          hipStream_t s) {
+                          const double* tab, double* partial, double* lnl, double* grad, hipStream_t s) {
     const int64_t waves = n * chunks;
     const unsigned nblk = blocks_for(waves, 4);
     if (grad) {
-        hipLaunchKernelGGL(k_loglike_moments<1>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, data, inv_psd,
-                           partial);
+        {
+            ProfRange pr(PD_K_LOGLIKE_GRAD, s);
+            hipLaunchKernelGGL(k_loglike_moments<1>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+        }
         hipLaunchKernelGGL(k_loglike_epilogue<1>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
                            partial, lnl, grad);
     } else {
-        hipLaunchKernelGGL(k_loglike_moments<0>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, data, inv_psd,
-                           partial);
+        {
+            ProfRange pr(PD_K_LOGLIKE, s);
+            hipLaunchKernelGGL(k_loglike_moments<0>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+        }
         hipLaunchKernelGGL(k_loglike_epilogue<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
                            partial, lnl, grad);
     }
@@ -431,10 +550,13 @@ hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int
 }
 
 hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                         const double* inv_psd, double* partial, double* F, hipStream_t s) {
+                         const double* tab, double* partial, double* F, hipStream_t s) {
     const int64_t waves = n * chunks;
-    hipLaunchKernelGGL(k_fisher_partial, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks, g,
-                       inv_psd, partial);
+    {
+        ProfRange pr(PD_K_FISHER, s);
+        hipLaunchKernelGGL(k_fisher_partial, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks, g,
+                           tab, partial);
+    }
     hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks, partial, F);
     return hipGetLastError();
 }

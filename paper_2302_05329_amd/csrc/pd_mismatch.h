@@ -18,7 +18,7 @@ constexpr int kSlotMM = 8;         // per-target scalars: A, B, |z|, zr, zi, lag
 size_t mismatch_scratch_bytes(int64_t nt, int64_t nb);
 
 hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t nt, const GridArgs& g,
-                           const double* targets, const double* inv_psd, void* scratch, double* mismatch,
+                           const double* tab, const double* targets, const double* inv_psd, void* scratch, double* mismatch,
                            double* dsum_dlambda, int32_t* lag, hipStream_t s);
 
 }  // namespace pd

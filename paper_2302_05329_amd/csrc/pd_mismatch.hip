@@ -18,8 +18,10 @@
 //                      targets in a fixed order
 #include <hip/hip_runtime.h>
 
+#include "../../include/phenomd.h"
 #include "pd_launch.h"
 #include "pd_mismatch.h"
+#include "pd_profile.h"
 
 namespace pd {
 
@@ -91,6 +93,7 @@ __device__ __forceinline__ double2 expi_ratio(int64_t num, int64_t den) {
 
 // ---- 1. overlap input -----------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ recs, int64_t nt, GridArgs g,
+                                                  const double* __restrict__ tab,
                                                   const double* __restrict__ targets,
                                                   const double* __restrict__ inv_psd, double2* __restrict__ X,
                                                   double* __restrict__ ab) {
@@ -100,6 +103,7 @@ __global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ rec
     const int64_t kb = (blockIdx.x % blocks) * 256;
     const int64_t k = kb + threadIdx.x;
     const double* __restrict__ rec = recs + p * REC_N;
+    const Tabs T{tab, g.nb};
     const double2 t = reinterpret_cast<const double2*>(targets)[p * kFFTN + k];
     const double w = 4.0 * g.df * inv_psd[k];
     double2 h = make_double2(0.0, 0.0);
@@ -108,10 +112,10 @@ __global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ rec
         const double mf = rec[R_MS] * f;
         if (bin_active(g, f, mf)) {
             BinVals bv;
-            eval_bin(rec, mf, bv);
-            const double A = rec[R_A0] * bv.pf * bv.ahat;
+            eval_bin_rt(rec, T, k, mf, bv);
+            const double A = rec[R_A0P] * T.at(T_F76, k) * bv.ahat;
             double sn, cs;
-            sincos(bv.psi, &sn, &cs);
+            pd_sincos(bv.psi, &sn, &cs);
             h = make_double2(A * cs, -A * sn);
         }
     }
@@ -316,13 +320,66 @@ __global__ void k_mm_finalize(const double* __restrict__ recs, int64_t nt, const
 struct MMVis {
     double* mom;
     double zr, zi;
-    __device__ __forceinline__ void ph(int s, double b) { mom[s] += zi * b; }
-    __device__ __forceinline__ void am(int s, double b) { mom[s] += zr * b; }
-    __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] += zi * fpsi + zr * fa; }
+    __device__ __forceinline__ void ph(int s, double b) { mom[s] = fma(zi, b, mom[s]); }
+    __device__ __forceinline__ void am(int s, double b) { mom[s] = fma(zr, b, mom[s]); }
+    __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] = fma(zi, fpsi, fma(zr, fa, mom[R_MS])); }
+};
+
+struct AdjSegment {
+    const double* __restrict__ rec;
+    Tabs T;
+    GridArgs g;
+    const double2* __restrict__ tgt;
+    const double* __restrict__ inv_psd;
+    double ur, ui, inv_sab, cfa;
+    int64_t j;
+    int64_t k0, k1;
+    int lane;
+    double tot;
+
+    template <int PR, int AR>
+    __device__ __forceinline__ void run() {
+        const double ms = rec[R_MS];
+        const double a0p = rec[R_A0P];
+        const double w4 = 4.0 * g.df;
+        double mom[REC_N];
+#pragma unroll
+        for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
+        for (int64_t k = k0 + lane; k < k1; k += 64) {
+            const double mf = ms * bin_freq(g, k);
+            BinVals bv;
+            eval_bin_t<PR, AR>(rec, T, k, mf, bv);
+            const double Aamp = a0p * T.at(T_F76, k) * bv.ahat;
+            double sn, cs;
+            pd_sincos(bv.psi, &sn, &cs);
+            const double hr = Aamp * cs, hi = -Aamp * sn;
+            const double w = w4 * inv_psd[k];
+            const double2 t = tgt[k];
+            const double2 e = expi_ratio((k * j) % kFFTN, kFFTN);
+            const double2 x = cmul(make_double2(w * t.x, w * t.y), e);
+            // G = conj(u) x
+            const double gr = ur * x.x + ui * x.y, gi = ur * x.y - ui * x.x;
+            // R = -G / sqrt(AB) + |z| w h / (A^(3/2) B^(1/2))
+            const double rr = -gr * inv_sab + cfa * w * hr;
+            const double ri = -gi * inv_sab + cfa * w * hi;
+            // conj(h) R: weight of d ln A is Re, weight of d Psi is -Im
+            const double cr = hr * rr + hi * ri, ci = hr * ri - hi * rr;
+            MMVis vis{mom, cr, -ci};
+            visit_bin_t<PR, AR>(rec, bv, vis);
+        }
+#pragma unroll
+        for (int s = 0; s < REC_N; ++s) {
+            if (slot_touched(PR, AR, s)) {
+                const double t = wave_sum(mom[s]);
+                if (lane == s) tot += t;
+            }
+        }
+    }
 };
 
 __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ recs, int64_t nt, int chunks,
-                                                    GridArgs g, const double* __restrict__ targets,
+                                                    GridArgs g, const double* __restrict__ tab,
+                                                    const double* __restrict__ targets,
                                                     const double* __restrict__ inv_psd,
                                                     const double* __restrict__ scal, double* __restrict__ part) {
     const int lane = threadIdx.x & 63;
@@ -338,52 +395,37 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     }
     const double* sc = scal + p * kSlotMM;
     const double A = sc[0], B = sc[1], az = sc[2];
-    const int64_t j = static_cast<int64_t>(sc[5]);
+    AdjSegment seg;
+    seg.rec = rec;
+    seg.T = Tabs{tab, g.nb};
+    seg.g = g;
+    seg.tgt = reinterpret_cast<const double2*>(targets) + p * kFFTN;
+    seg.inv_psd = inv_psd;
     // unit phase u = z / |z|; G_k = conj(u) x_k with x_k = w t_k exp(2 pi i k j / N)
-    const double ur = sc[3] / az, ui = sc[4] / az;
-    const double inv_sab = 1.0 / sqrt(A * B);
-    const double cfa = az / (A * sqrt(A * B));   // |z| / (A^(3/2) B^(1/2))
-    const double ms = rec[R_MS], a0 = rec[R_A0];
+    seg.ur = sc[3] / az;
+    seg.ui = sc[4] / az;
+    seg.inv_sab = 1.0 / sqrt(A * B);
+    seg.cfa = az / (A * sqrt(A * B));   // |z| / (A^(3/2) B^(1/2))
+    seg.j = static_cast<int64_t>(sc[5]);
+    seg.lane = lane;
+    seg.tot = 0.0;
     int64_t kb, ke;
-    chunk_range(ms, g, c, chunks, kb, ke);
-    const double w4 = 4.0 * g.df;
-    double mom[REC_N];
+    chunk_range(rec[R_MS], g, c, chunks, kb, ke);
+    Segs S;
+    make_segments(rec, g, kb, ke, S);
 #pragma unroll
-    for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
-    const double2* __restrict__ tgt = reinterpret_cast<const double2*>(targets) + p * kFFTN;
-    for (int64_t k = kb + lane; k < ke; k += 64) {
-        const double f = bin_freq(g, k);
-        const double mf = ms * f;
-        if (!bin_active(g, f, mf)) continue;
-        BinVals bv;
-        eval_bin(rec, mf, bv);
-        const double Aamp = a0 * bv.pf * bv.ahat;
-        double sn, cs;
-        sincos(bv.psi, &sn, &cs);
-        const double hr = Aamp * cs, hi = -Aamp * sn;
-        const double w = w4 * inv_psd[k];
-        const double2 t = tgt[k];
-        const double2 e = expi_ratio((k * j) % kFFTN, kFFTN);
-        const double2 x = cmul(make_double2(w * t.x, w * t.y), e);
-        // G = conj(u) x
-        const double gr = ur * x.x + ui * x.y, gi = ur * x.y - ui * x.x;
-        // R = -G / sqrt(AB) + |z| w h / (A^(3/2) B^(1/2))
-        const double rr = -gr * inv_sab + cfa * w * hr;
-        const double ri = -gi * inv_sab + cfa * w * hi;
-        // conj(h) R
-        const double cr = hr * rr + hi * ri, ci = hr * ri - hi * rr;
-        MMVis vis{mom, cr, -ci};
-        visit_bin(rec, bv, vis);
+    for (int i = 0; i < 5; ++i) {
+        if (i < S.n) {
+            seg.k0 = uniform_i(S.k[i]);
+            seg.k1 = uniform_i(S.k[i + 1]);
+            dispatch_region(uniform_i(S.pr[i]), uniform_i(S.ar[i]), seg);
+        }
     }
     if (lane == 0) {
         out[0] = 0.0;
         out[1] = 0.0;
     }
-#pragma unroll
-    for (int s = 0; s < REC_N; ++s) {
-        const double t = wave_sum(mom[s]);
-        if (lane == 0) out[2 + s] = t;
-    }
+    if (lane < REC_N) out[2 + lane] = seg.tot;
 }
 
 // ---- 6. chain rule to the fit parameters and to the 209 coefficients ------------------------
@@ -431,20 +473,30 @@ __global__ void k_mm_lambda_sum(const double* __restrict__ recs, int64_t nt, con
 size_t mismatch_scratch_bytes(int64_t nt, int64_t nb) { return carve_size(nt, nb); }
 
 hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t nt, const GridArgs& g,
-                           const double* targets, const double* inv_psd, void* scratch, double* mismatch,
+                           const double* tab, const double* targets, const double* inv_psd, void* scratch, double* mismatch,
                            double* dsum_dlambda, int32_t* lag, hipStream_t s) {
     MMScratch m = carve(scratch, nt, g.nb);
     const unsigned bin_blocks = static_cast<unsigned>(nt * (kFFTN / 256));
-    hipLaunchKernelGGL(k_mm_input, dim3(bin_blocks), dim3(256), 0, s, recs, nt, g, targets, inv_psd, m.X, m.ab);
+    {
+        ProfRange pr(PD_K_MISMATCH_INPUT, s);
+        hipLaunchKernelGGL(k_mm_input, dim3(bin_blocks), dim3(256), 0, s, recs, nt, g, tab, targets, inv_psd, m.X,
+                           m.ab);
+    }
     const unsigned fft_blocks = static_cast<unsigned>(nt * (kFFTR / kCols));
-    hipLaunchKernelGGL(k_mm_fft_cols, dim3(fft_blocks), dim3(256), 0, s, m.X, m.Y);
-    hipLaunchKernelGGL(k_mm_fft_rows_max, dim3(fft_blocks), dim3(256), 0, s, m.Y, m.mx);
+    {
+        ProfRange pr(PD_K_MISMATCH_FFT, s);
+        hipLaunchKernelGGL(k_mm_fft_cols, dim3(fft_blocks), dim3(256), 0, s, m.X, m.Y);
+        hipLaunchKernelGGL(k_mm_fft_rows_max, dim3(fft_blocks), dim3(256), 0, s, m.Y, m.mx);
+    }
     hipLaunchKernelGGL(k_mm_finalize, dim3(static_cast<unsigned>((nt + 127) / 128)), dim3(128), 0, s, recs, nt,
                        m.ab, m.mx, m.scal, mismatch, lag);
     if (dsum_dlambda) {
         const int64_t waves = nt * m.chunks;
-        hipLaunchKernelGGL(k_mm_adjoint, dim3(static_cast<unsigned>((waves + 3) / 4)), dim3(256), 0, s, recs, nt,
-                           m.chunks, g, targets, inv_psd, m.scal, m.mom);
+        {
+            ProfRange pr(PD_K_MISMATCH_ADJ, s);
+            hipLaunchKernelGGL(k_mm_adjoint, dim3(static_cast<unsigned>((waves + 3) / 4)), dim3(256), 0, s, recs,
+                               nt, m.chunks, g, tab, targets, inv_psd, m.scal, m.mom);
+        }
         hipLaunchKernelGGL(k_mm_contract, dim3(static_cast<unsigned>((nt * kNumFit + 127) / 128)), dim3(128), 0,
                            s, recs, fit_tans, nt, m.chunks, m.mom, m.dlam);
         hipLaunchKernelGGL(k_mm_lambda_sum, dim3(1), dim3(256), 0, s, recs, nt, m.dlam, dsum_dlambda);

@@ -60,7 +60,16 @@ enum : int {
     R_VALID = 48, // 1.0 if the point is inside the model's domain, else 0.0
     R_ETA = 49,   // eta and chi_PN (values), for the chain rule to the 209 coefficients
     R_CHIPN = 50,
-    REC_N = 52
+    // per-point factors that turn the per-bin tables into functions of Mf (values only)
+    R_CS = 51,    // cbrt(pi Ms):  v = (pi Mf)^(1/3) = R_CS * cbrt(f)
+    R_ICS = 52,   // 1 / R_CS
+    R_LCS = 53,   // ln R_CS:      ln v = R_LCS + ln(f) / 3
+    R_LMS = 54,   // ln Ms:        ln Mf = R_LMS + ln f
+    R_IMS = 55,   // 1 / Ms
+    R_MS34 = 56,  // Ms^(3/4)
+    R_A0P = 57,   // exp(lnA0) Ms^(-7/6): A(f) = R_A0P f^(-7/6) Ahat(Mf)
+    R_ID = 58,    // 1 / f_damp (the arctan width)
+    REC_N = 60
 };
 
 constexpr int kNumLambda = 209;
@@ -463,7 +472,16 @@ __device__ __forceinline__ bool build_record(const Source<T>& s, const T lam[kNu
     rec[R_VALID] = K<T>(ok ? 1.0 : 0.0);
     rec[R_ETA] = eta;
     rec[R_CHIPN] = s.chi_pn;
-    rec[51] = K<T>(0.0);
+    const T cs = dcbrt(pi * ms);
+    rec[R_CS] = cs;
+    rec[R_ICS] = 1.0 / cs;
+    rec[R_LCS] = dlog(cs);
+    rec[R_LMS] = dlog(ms);
+    rec[R_IMS] = 1.0 / ms;
+    rec[R_MS34] = dpow(ms, 0.75);
+    rec[R_A0P] = dexp(lna0 - (7.0 / 6.0) * dlog(ms));
+    rec[R_ID] = 1.0 / f_damp;
+    rec[59] = K<T>(0.0);
     return ok;
 }
 
