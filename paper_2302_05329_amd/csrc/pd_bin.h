@@ -30,14 +30,23 @@ struct GridArgs {
 // Per-bin tables (structure of arrays, each n_bins long).
 enum : int { T_CB = 0, T_ICB, T_LF, T_F34, T_INF, T_F76, T_DWR, T_DWI, T_WW, T_N };
 
+// One wave-uniform base pointer per table; bins are indexed with 32-bit offsets.
 struct Tabs {
-    const double* __restrict__ t;
-    int64_t nb;
-    __device__ __forceinline__ double at(int which, int64_t k) const { return t[which * nb + k]; }
+    const double* p[T_N];
+    Tabs() = default;
+    __device__ __forceinline__ Tabs(const double* __restrict__ t, int64_t nb) {
+#pragma unroll
+        for (int i = 0; i < T_N; ++i) p[i] = t + i * nb;
+    }
+    __device__ __forceinline__ double at(int which, int64_t k) const { return p[which][k]; }
+    __device__ __forceinline__ double at(int which, unsigned k) const { return p[which][k]; }
 };
 
 // Frequency of bin k, rounded exactly as f0 + k*df (two roundings, no fused multiply-add).
 __device__ __forceinline__ double bin_freq(const GridArgs& g, int64_t k) {
+    return __dadd_rn(g.f0, __dmul_rn(static_cast<double>(k), g.df));
+}
+__device__ __forceinline__ double bin_freq(const GridArgs& g, unsigned k) {
     return __dadd_rn(g.f0, __dmul_rn(static_cast<double>(k), g.df));
 }
 
@@ -125,8 +134,8 @@ struct BinVals {
     double psi;              // phase
 };
 
-template <int PR, int AR>
-__device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const Tabs& T, int64_t k, double mf,
+template <int PR, int AR, class KI>
+__device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const Tabs& T, KI k, double mf,
                                            BinVals& b) {
     b.mf = mf;
     if (PR == 1 || AR == 1) {
@@ -135,7 +144,7 @@ __device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const T
     }
     if (PR == 1) {
         const double v = b.v, w = b.w;
-        const double lv = fma(T.at(T_LF, k), 1.0 / 3.0, c[R_LCS]);
+        const double lv = fma(T.at(T_LF, k), sk(1.0 / 3.0), c[R_LCS]);
         b.lv = lv;
         const double w2 = w * w;
         const double neg = w * fma(w, fma(w, fma(w2, c[R_PH1 + 0], c[R_PH1 + 1]), c[R_PH1 + 2]), c[R_PH1 + 3]);
@@ -176,7 +185,7 @@ __device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const T
     } else {
         const double x = mf - c[R_AM3 + 1];
         const double g = c[R_AM3 + 2];
-        const double iden = 1.0 / fma(x, x, g * g);
+        const double iden = pd_rcp(fma(x, x, g * g));
         b.x = x;
         b.iden = iden;
         b.ahat = c[R_AM3 + 0] * iden * pd_exp(-c[R_AM3 + 3] * x);
@@ -227,11 +236,11 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         const double v2 = v * v, v3 = v2 * v, v4 = v3 * v, v5 = v4 * v, v6 = v5 * v;
         const double bs[13] = {w5, w3, w2, w, 1.0, lv, v, v * lv, v2, v3, v4, v5, v6};
         const double pw[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
-        fpsi = fma(c[R_PH1 + 7], v, c[R_PH1 + 5]) * (1.0 / 3.0);
+        fpsi = fma(c[R_PH1 + 7], v, c[R_PH1 + 5]) * sk(1.0 / 3.0);
 #pragma unroll
         for (int j = 0; j < 13; ++j) {
             vis.ph(R_PH1 + j, bs[j]);
-            if (pw[j] != 0.0) fpsi = fma(c[R_PH1 + j] * (pw[j] * (1.0 / 3.0)), bs[j], fpsi);
+            if (pw[j] != 0.0) fpsi = fma(c[R_PH1 + j] * sk(pw[j] * (1.0 / 3.0)), bs[j], fpsi);
         }
     } else if (PR == 2) {
         const double i3 = b.invf * b.invf * b.invf;
@@ -239,9 +248,9 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         vis.ph(R_PH2 + 1, b.mf);
         vis.ph(R_PH2 + 2, b.lnf);
         vis.ph(R_PH2 + 3, i3);
-        fpsi = fma(c[R_PH2 + 1], b.mf, fma(-3.0 * c[R_PH2 + 3], i3, c[R_PH2 + 2]));
+        fpsi = fma(c[R_PH2 + 1], b.mf, fma(sk(-3.0) * c[R_PH2 + 3], i3, c[R_PH2 + 2]));
     } else {
-        const double iu2 = 1.0 / fma(b.u, b.u, 1.0);
+        const double iu2 = pd_rcp(fma(b.u, b.u, 1.0));
         const double t = c[R_PH3 + 4] * iu2 * c[R_ID];
         vis.ph(R_PH3 + 0, 1.0);
         vis.ph(R_PH3 + 1, b.mf);
@@ -250,12 +259,12 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         vis.ph(R_PH3 + 4, b.at);
         vis.ph(R_PH3 + 5, -t);
         vis.ph(R_PH3 + 6, -t * b.u);
-        fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(0.75 * c[R_PH3 + 3], b.f34, t * b.mf)));
+        fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(sk(0.75) * c[R_PH3 + 3], b.f34, t * b.mf)));
     }
     double fa;
     vis.am(R_LNA0, 1.0);
     if (AR == 1) {
-        const double ia = 1.0 / b.ahat;
+        const double ia = pd_rcp(b.ahat);
         double p = ia;
         double acc = 0.0;
         vis.am(R_AM1 + 0, p);
@@ -263,11 +272,11 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         for (int i = 1; i < 10; ++i) {
             p *= b.v;
             vis.am(R_AM1 + i, p);
-            acc = fma(c[R_AM1 + i] * (i * (1.0 / 3.0)), p, acc);
+            acc = fma(c[R_AM1 + i] * sk(i * (1.0 / 3.0)), p, acc);
         }
         fa = acc;
     } else if (AR == 2) {
-        const double ia = 1.0 / b.ahat;
+        const double ia = pd_rcp(b.ahat);
         const double f = b.mf;
         double p = ia;
         double acc = 0.0;
@@ -276,19 +285,19 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         for (int i = 1; i < 5; ++i) {
             p *= f;
             vis.am(R_AM2 + i, p);
-            acc = fma(c[R_AM2 + i] * i, p, acc);
+            acc = fma(c[R_AM2 + i] * sk(static_cast<double>(i)), p, acc);
         }
         fa = acc;
     } else {
         const double x = b.x, g = c[R_AM3 + 2], r = c[R_AM3 + 3];
         const double tx = 2.0 * x * b.iden;
-        vis.am(R_AM3 + 0, 1.0 / c[R_AM3 + 0]);
+        vis.am(R_AM3 + 0, c[R_IANUM]);
         vis.am(R_AM3 + 1, tx + r);
         vis.am(R_AM3 + 2, -2.0 * g * b.iden);
         vis.am(R_AM3 + 3, -x);
         fa = -b.mf * (tx + r);
     }
-    vis.fd(fpsi, fa - 7.0 / 6.0);
+    vis.fd(fpsi, fa - sk(7.0 / 6.0));
 }
 
 // Chunk of the active range [kb, ke) handled by wavefront `c` of `chunks` for one point.
@@ -332,6 +341,24 @@ __device__ __forceinline__ void dispatch_region(int pr, int ar, F& f) {
             f.template run<3, 3>();
         else
             f.template run<3, 2>();
+    }
+}
+
+// Dispatch over the amplitude region for a fixed phase region.
+template <int PR, class F>
+__device__ __forceinline__ void dispatch_amp_region(int ar, F& f) {
+    if (PR == 1) {
+        if (ar == 1)
+            f.template run<1, 1>();
+        else if (ar == 2)
+            f.template run<1, 2>();
+        else
+            f.template run<1, 3>();
+    } else {
+        if (ar == 3)
+            f.template run<PR, 3>();
+        else
+            f.template run<PR, 2>();
     }
 }
 

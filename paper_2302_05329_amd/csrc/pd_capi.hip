@@ -80,21 +80,21 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
         case PD_OP_LOGLIKE:
             L.chunks = pd::chunks_for(n, nb);
             L.partial = off;
-            off = align_up(off + N * L.chunks * 2 * sizeof(double));
+            off = align_up(off + 3 * N * L.chunks * 2 * sizeof(double));
             break;
         case PD_OP_LOGLIKE_GRAD:
             L.chunks = pd::chunks_for(n, nb);
             L.tan = off;
             off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
             L.partial = off;
-            off = align_up(off + N * L.chunks * pd::kNSlot * sizeof(double));
+            off = align_up(off + 3 * N * L.chunks * pd::kNSlot * sizeof(double));
             break;
         case PD_OP_FISHER:
             L.chunks = pd::chunks_for(n, nb);
             L.tan = off;
             off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
             L.partial = off;
-            off = align_up(off + N * L.chunks * 28 * sizeof(double));
+            off = align_up(off + 3 * N * L.chunks * 28 * sizeof(double));
             break;
         case PD_OP_MISMATCH_GRAD:
             L.tan = off;

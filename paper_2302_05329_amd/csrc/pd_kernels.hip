@@ -69,7 +69,11 @@ __global__ void __launch_bounds__(128) k_setup_value(const double* __restrict__ 
     if (status) status[i] = ok ? 0 : -2;
 }
 
-// Record tangents along the 7 entries of theta (forward mode, Dual<7>).
+// Record tangents along the 7 entries of theta.  The four intrinsic entries (masses or
+// chirp mass and mass ratio, two spins) go through the setup in forward mode (Dual<4>);
+// the extrinsic ones enter the record in closed form: D (or ln D) only through ln A0,
+// tc only through the Mf-linear phase coefficient (2 pi tc / Ms), phic only through the
+// constant phase term (-2 phic).
 __global__ void __launch_bounds__(64) k_setup_theta_tangent(const double* __restrict__ theta, int64_t n,
                                                             int param, double f_ref,
                                                             const double* __restrict__ lam,
@@ -78,23 +82,30 @@ __global__ void __launch_bounds__(64) k_setup_theta_tangent(const double* __rest
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double* out = tans + i * 7 * REC_N;
-    if (recs[i * REC_N + R_VALID] == 0.0) {
-        for (int j = 0; j < 7 * REC_N; ++j) out[j] = 0.0;
-        return;
-    }
-    using D = Dual<7>;
+    for (int j = 0; j < 7 * REC_N; ++j) out[j] = 0.0;
+    if (recs[i * REC_N + R_VALID] == 0.0) return;
+    using D = Dual<4>;
     D th[7];
     for (int j = 0; j < 7; ++j) {
-        th[j] = dconst<7>(theta[i * 7 + j]);
-        th[j].d[j] = 1.0;
+        th[j] = dconst<4>(theta[i * 7 + j]);
+        if (j < 4) th[j].d[j] = 1.0;
     }
     const Source<D> s = source_map(th, param);
     D fit[kNumFit];
     fit_params(lam, s.eta, s.chi_pn, fit);
     D rec[REC_N];
     build_record(s, fit, f_ref, rec);
-    for (int p = 0; p < 7; ++p)
+    for (int p = 0; p < 4; ++p)
         for (int j = 0; j < REC_N; ++j) out[p * REC_N + j] = rec[j].d[p];
+    const double ms = rec[R_MS].v;
+    out[4 * REC_N + R_LNA0] = (param == 1) ? -1.0 : -1.0 / theta[i * 7 + 4];
+    const double dlin = 2.0 * kPi / ms;
+    out[5 * REC_N + R_PH1 + 9] = dlin / kPi;
+    out[5 * REC_N + R_PH2 + 1] = dlin;
+    out[5 * REC_N + R_PH3 + 1] = dlin;
+    out[6 * REC_N + R_PH1 + 4] = -2.0;
+    out[6 * REC_N + R_PH2 + 0] = -2.0;
+    out[6 * REC_N + R_PH3 + 0] = -2.0;
 }
 
 // Record tangents along the 19 fitted parameters: thread (point, l) seeds parameter l.
@@ -174,7 +185,7 @@ __global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ rec
     const int64_t k = (b % blocks_per_point) * 256 + threadIdx.x;
     if (p >= n || k >= g.nb) return;
     const double* __restrict__ rec = recs + p * REC_N;
-    const Tabs T{tab, g.nb};
+    const Tabs T(tab, g.nb);
     double2 out = make_double2(0.0, 0.0);
     if (rec[R_VALID] == 0.0) {
         out = make_double2(__builtin_nan(""), __builtin_nan(""));
@@ -234,7 +245,7 @@ struct LnlSegment {
         double mom[REC_N];
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
-        for (int64_t k = k0 + lane; k < k1; k += 64) {
+        for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
             eval_bin_t<PR, AR>(rec, T, k, mf, bv);
@@ -256,11 +267,14 @@ struct LnlSegment {
     }
 };
 
-template <int MODE>
+// PRG: the phase region (1 inspiral, 2 intermediate, 3 merger-ringdown) whose segments this
+// instantiation handles; the three are separate launches so each gets its own register budget.
+template <int MODE, int PRG>
 __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
                                                          GridArgs g, const double* __restrict__ tab,
-                                                         double* __restrict__ partial) {
+                                                         double* __restrict__ partial_all) {
     constexpr int NS = (MODE == 0) ? 2 : kNSlot;
+    double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * NS;
     const int lane = threadIdx.x & 63;
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
     const int64_t p = wave / chunks;
@@ -276,13 +290,13 @@ __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restric
     chunk_range(rec[R_MS], g, c, chunks, kb, ke);
     Segs S;
     make_segments(rec, g, kb, ke, S);
-    LnlSegment<MODE> seg{rec, Tabs{tab, g.nb}, g, 0, 0, lane, 0.0, 0.0, 0.0};
+    LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, 0, 0, lane, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        if (i < S.n) {
+        if (i < S.n && uniform_i(S.pr[i]) == PRG) {
             seg.k0 = uniform_i(S.k[i]);
             seg.k1 = uniform_i(S.k[i + 1]);
-            dispatch_region(uniform_i(S.pr[i]), uniform_i(S.ar[i]), seg);
+            dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);
         }
     }
     const double a0p = rec[R_A0P];
@@ -314,10 +328,11 @@ __global__ void __launch_bounds__(128) k_loglike_epilogue(const double* __restri
     }
     double acc[NS];
     for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-    for (int c = 0; c < chunks; ++c) {
-        const double* src = partial + (p * chunks + c) * NS;
-        for (int s = 0; s < NS; ++s) acc[s] += src[s];
-    }
+    for (int grp = 0; grp < 3; ++grp)
+        for (int c = 0; c < chunks; ++c) {
+            const double* src = partial + ((grp * n + p) * chunks + c) * NS;
+            for (int s = 0; s < NS; ++s) acc[s] += src[s];
+        }
     lnl[p] = acc[0] - 0.5 * acc[1];
     if (MODE == 1) {
         const double* mom = acc + 2;
@@ -370,7 +385,7 @@ struct FisherSegment {
     __device__ __forceinline__ void run() {
         const double ms = rec[R_MS];
         const double a0p = rec[R_A0P];
-        for (int64_t k = k0 + lane; k < k1; k += 64) {
+        for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
             eval_bin_t<PR, AR>(rec, T, k, mf, bv);
@@ -395,10 +410,12 @@ struct FisherSegment {
     }
 };
 
+template <int PRG>
 __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict__ recs,
                                                         const double* __restrict__ tans, int64_t n, int chunks,
                                                         GridArgs g, const double* __restrict__ tab,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial_all) {
+    double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * 28;
     __shared__ double lds[4][7 * REC_N];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -425,17 +442,17 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
     FisherSegment seg;
     seg.rec = rec;
     seg.Tl = T;
-    seg.T = Tabs{tab, g.nb};
+    seg.T = Tabs(tab, g.nb);
     seg.g = g;
     seg.lane = lane;
 #pragma unroll
     for (int s = 0; s < 28; ++s) seg.F[s] = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        if (i < S.n) {
+        if (i < S.n && uniform_i(S.pr[i]) == PRG) {
             seg.k0 = uniform_i(S.k[i]);
             seg.k1 = uniform_i(S.k[i + 1]);
-            dispatch_region(uniform_i(S.pr[i]), uniform_i(S.ar[i]), seg);
+            dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);
         }
     }
 #pragma unroll
@@ -457,8 +474,9 @@ __global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restric
     }
     double acc[28];
     for (int s = 0; s < 28; ++s) acc[s] = 0.0;
-    for (int c = 0; c < chunks; ++c)
-        for (int s = 0; s < 28; ++s) acc[s] += partial[(p * chunks + c) * 28 + s];
+    for (int grp = 0; grp < 3; ++grp)
+        for (int c = 0; c < chunks; ++c)
+            for (int s = 0; s < 28; ++s) acc[s] += partial[((grp * n + p) * chunks + c) * 28 + s];
     int s = 0;
     for (int a = 0; a < 7; ++a)
         for (int b = a; b < 7; ++b) {
@@ -534,14 +552,18 @@ hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int
     if (grad) {
         {
             ProfRange pr(PD_K_LOGLIKE_GRAD, s);
-            hipLaunchKernelGGL(k_loglike_moments<1>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<1, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<1, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<1, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
         }
         hipLaunchKernelGGL(k_loglike_epilogue<1>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
                            partial, lnl, grad);
     } else {
         {
             ProfRange pr(PD_K_LOGLIKE, s);
-            hipLaunchKernelGGL(k_loglike_moments<0>, dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<0, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<0, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<0, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
         }
         hipLaunchKernelGGL(k_loglike_epilogue<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
                            partial, lnl, grad);
@@ -554,8 +576,12 @@ hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int 
     const int64_t waves = n * chunks;
     {
         ProfRange pr(PD_K_FISHER, s);
-        hipLaunchKernelGGL(k_fisher_partial, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks, g,
-                           tab, partial);
+        hipLaunchKernelGGL(k_fisher_partial<3>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
+                           g, tab, partial);
+        hipLaunchKernelGGL(k_fisher_partial<2>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
+                           g, tab, partial);
+        hipLaunchKernelGGL(k_fisher_partial<1>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
+                           g, tab, partial);
     }
     hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks, partial, F);
     return hipGetLastError();

@@ -17,6 +17,15 @@
 
 namespace pd {
 
+// A polynomial coefficient materialised in scalar registers where it is used.  FP64
+// literals cannot be instruction operands; left alone the compiler hoists every
+// coefficient out of the bin loops into vector registers (two per coefficient), which
+// costs occupancy.  The empty asm pins the value to an SGPR pair at the use.
+__device__ __forceinline__ double sk(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
 constexpr double kPio2_1 = 1.5707963267948966;
 constexpr double kPio2_2 = 6.123233995736766e-17;
 constexpr double kPio2_3 = -1.4973849048591698e-33;
@@ -33,28 +42,28 @@ constexpr double kC0 = 4.1666666666666666666e-2, kC1 = -1.3888888888888887865e-3
                  kC6 = 4.7458718350640028856e-14;
 
 __device__ __forceinline__ void pd_sincos(double x, double* s_out, double* c_out) {
-    if (!(fabs(x) <= 1e8)) {
+    if (!(fabs(x) <= sk(1e8))) {
         sincos(x, s_out, c_out);
         return;
     }
-    const double q = rint(x * kTwoOverPi);
-    double r = fma(-q, kPio2_1, x);
-    r = fma(-q, kPio2_2, r);
-    r = fma(-q, kPio2_3, r);
+    const double q = rint(x * sk(kTwoOverPi));
+    double r = fma(-q, sk(kPio2_1), x);
+    r = fma(-q, sk(kPio2_2), r);
+    r = fma(-q, sk(kPio2_3), r);
     const double z = r * r;
-    double ps = fma(kS6, z, kS5);
-    ps = fma(ps, z, kS4);
-    ps = fma(ps, z, kS3);
-    ps = fma(ps, z, kS2);
-    ps = fma(ps, z, kS1);
-    ps = fma(ps, z, kS0);
+    double ps = fma(sk(kS6), z, sk(kS5));
+    ps = fma(ps, z, sk(kS4));
+    ps = fma(ps, z, sk(kS3));
+    ps = fma(ps, z, sk(kS2));
+    ps = fma(ps, z, sk(kS1));
+    ps = fma(ps, z, sk(kS0));
     const double sr = fma(r * z, ps, r);
-    double pc = fma(kC6, z, kC5);
-    pc = fma(pc, z, kC4);
-    pc = fma(pc, z, kC3);
-    pc = fma(pc, z, kC2);
-    pc = fma(pc, z, kC1);
-    pc = fma(pc, z, kC0);
+    double pc = fma(sk(kC6), z, sk(kC5));
+    pc = fma(pc, z, sk(kC4));
+    pc = fma(pc, z, sk(kC3));
+    pc = fma(pc, z, sk(kC2));
+    pc = fma(pc, z, sk(kC1));
+    pc = fma(pc, z, sk(kC0));
     const double hz = 0.5 * z;
     const double w = 1.0 - hz;
     const double cr = w + (((1.0 - w) - hz) + z * z * pc);
@@ -63,6 +72,22 @@ __device__ __forceinline__ void pd_sincos(double x, double* s_out, double* c_out
     const double b = (j & 1) ? sr : cr;
     *s_out = (j & 2) ? -a : a;
     *c_out = ((j + 1) & 2) ? -b : b;
+}
+
+// Reciprocal and quotient for normal-range operands: hardware reciprocal estimate, two
+// Newton-Raphson steps (each doubles the correct bits), and one residual correction of
+// the quotient.  Used where an IEEE-exact division is not needed.
+__device__ __forceinline__ double pd_rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+__device__ __forceinline__ double pd_div(double n, double d) {
+    const double r = pd_rcp(d);
+    const double q = n * r;
+    return fma(fma(-d, q, n), r, q);
 }
 
 // atan(t) = t + t^3 A(t^2) on 0 <= t <= tan(pi/12)
@@ -82,24 +107,24 @@ __device__ __forceinline__ double pd_atan(double u) {
     const bool inv = a > 1.0;
     const double num = inv ? 1.0 : a;
     const double den = inv ? a : 1.0;
-    const bool hi = num > kTanPi12 * den;
-    const double n2 = hi ? fma(kSqrt3, num, -den) : num;
-    const double d2 = hi ? fma(kSqrt3, den, num) : den;
-    const double t = n2 / d2;
+    const bool hi = num > sk(kTanPi12) * den;
+    const double n2 = hi ? fma(sk(kSqrt3), num, -den) : num;
+    const double d2 = hi ? fma(sk(kSqrt3), den, num) : den;
+    const double t = pd_div(n2, d2);
     const double z = t * t;
-    double p = fma(kA10, z, kA9);
-    p = fma(p, z, kA8);
-    p = fma(p, z, kA7);
-    p = fma(p, z, kA6);
-    p = fma(p, z, kA5);
-    p = fma(p, z, kA4);
-    p = fma(p, z, kA3);
-    p = fma(p, z, kA2);
-    p = fma(p, z, kA1);
-    p = fma(p, z, kA0);
+    double p = fma(sk(kA10), z, sk(kA9));
+    p = fma(p, z, sk(kA8));
+    p = fma(p, z, sk(kA7));
+    p = fma(p, z, sk(kA6));
+    p = fma(p, z, sk(kA5));
+    p = fma(p, z, sk(kA4));
+    p = fma(p, z, sk(kA3));
+    p = fma(p, z, sk(kA2));
+    p = fma(p, z, sk(kA1));
+    p = fma(p, z, sk(kA0));
     double r = fma(t * z, p, t);
-    if (hi) r = (r + kPi6_lo) + kPi6_hi;
-    if (inv) r = (kPi2_hi - r) + kPi2_lo;
+    if (hi) r = (r + sk(kPi6_lo)) + sk(kPi6_hi);
+    if (inv) r = (sk(kPi2_hi) - r) + sk(kPi2_lo);
     return (u < 0.0) ? -r : r;
 }
 
@@ -113,20 +138,20 @@ constexpr double kLn2_hi = 0.6931471805599453, kLn2_lo = 2.3190468138462996e-17;
 constexpr double kLog2e = 1.4426950408889634;
 
 __device__ __forceinline__ double pd_exp(double y) {
-    if (!(fabs(y) < 700.0)) return exp(y);
-    const double k = rint(y * kLog2e);
-    double r = fma(-k, kLn2_hi, y);
-    r = fma(-k, kLn2_lo, r);
-    double p = fma(kE10, r, kE9);
-    p = fma(p, r, kE8);
-    p = fma(p, r, kE7);
-    p = fma(p, r, kE6);
-    p = fma(p, r, kE5);
-    p = fma(p, r, kE4);
-    p = fma(p, r, kE3);
-    p = fma(p, r, kE2);
-    p = fma(p, r, kE1);
-    p = fma(p, r, kE0);
+    if (!(fabs(y) < sk(700.0))) return exp(y);
+    const double k = rint(y * sk(kLog2e));
+    double r = fma(-k, sk(kLn2_hi), y);
+    r = fma(-k, sk(kLn2_lo), r);
+    double p = fma(sk(kE10), r, sk(kE9));
+    p = fma(p, r, sk(kE8));
+    p = fma(p, r, sk(kE7));
+    p = fma(p, r, sk(kE6));
+    p = fma(p, r, sk(kE5));
+    p = fma(p, r, sk(kE4));
+    p = fma(p, r, sk(kE3));
+    p = fma(p, r, sk(kE2));
+    p = fma(p, r, sk(kE1));
+    p = fma(p, r, sk(kE0));
     const double e = 1.0 + fma(r * r, p, r);
     return ldexp(e, static_cast<int>(k));
 }

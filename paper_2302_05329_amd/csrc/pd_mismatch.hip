@@ -37,6 +37,7 @@ struct MMScratch {
     double* scal;     // [nt][kSlotMM]
     double* mom;      // [nt][chunks][kNSlot]
     double* dlam;     // [nt][19]
+    double* mred;     // [nt][REC_N]
     int chunks;
 };
 
@@ -60,9 +61,11 @@ MMScratch carve(void* base, int64_t nt, int64_t nb) {
     m.scal = reinterpret_cast<double*>(p + off);
     off = al(off + n * kSlotMM * sizeof(double));
     m.mom = reinterpret_cast<double*>(p + off);
-    off = al(off + n * m.chunks * kNSlot * sizeof(double));
+    off = al(off + 3 * n * m.chunks * kNSlot * sizeof(double));
     m.dlam = reinterpret_cast<double*>(p + off);
     off = al(off + n * kNumFit * sizeof(double));
+    m.mred = reinterpret_cast<double*>(p + off);
+    off = al(off + n * REC_N * sizeof(double));
     return m;
 }
 
@@ -75,8 +78,9 @@ size_t carve_size(int64_t nt, int64_t nb) {
     off = al(off + n * (kFFTN / 256) * 2 * sizeof(double));
     off = al(off + n * (kFFTR / kCols) * 4 * sizeof(double));
     off = al(off + n * kSlotMM * sizeof(double));
-    off = al(off + n * chunks * kNSlot * sizeof(double));
+    off = al(off + 3 * n * chunks * kNSlot * sizeof(double));
     off = al(off + n * kNumFit * sizeof(double));
+    off = al(off + n * REC_N * sizeof(double));
     return off;
 }
 
@@ -103,7 +107,7 @@ __global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ rec
     const int64_t kb = (blockIdx.x % blocks) * 256;
     const int64_t k = kb + threadIdx.x;
     const double* __restrict__ rec = recs + p * REC_N;
-    const Tabs T{tab, g.nb};
+    const Tabs T(tab, g.nb);
     const double2 t = reinterpret_cast<const double2*>(targets)[p * kFFTN + k];
     const double w = 4.0 * g.df * inv_psd[k];
     double2 h = make_double2(0.0, 0.0);
@@ -345,7 +349,7 @@ struct AdjSegment {
         double mom[REC_N];
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
-        for (int64_t k = k0 + lane; k < k1; k += 64) {
+        for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
             eval_bin_t<PR, AR>(rec, T, k, mf, bv);
@@ -377,11 +381,13 @@ struct AdjSegment {
     }
 };
 
+template <int PRG>
 __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ recs, int64_t nt, int chunks,
                                                     GridArgs g, const double* __restrict__ tab,
                                                     const double* __restrict__ targets,
                                                     const double* __restrict__ inv_psd,
-                                                    const double* __restrict__ scal, double* __restrict__ part) {
+                                                    const double* __restrict__ scal, double* __restrict__ part_all) {
+    double* __restrict__ part = part_all + static_cast<int64_t>(PRG - 1) * nt * chunks * kNSlot;
     const int lane = threadIdx.x & 63;
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + (threadIdx.x >> 6)));
     const int64_t p = wave / chunks;
@@ -397,7 +403,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     const double A = sc[0], B = sc[1], az = sc[2];
     AdjSegment seg;
     seg.rec = rec;
-    seg.T = Tabs{tab, g.nb};
+    seg.T = Tabs(tab, g.nb);
     seg.g = g;
     seg.tgt = reinterpret_cast<const double2*>(targets) + p * kFFTN;
     seg.inv_psd = inv_psd;
@@ -415,10 +421,10 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     make_segments(rec, g, kb, ke, S);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        if (i < S.n) {
+        if (i < S.n && uniform_i(S.pr[i]) == PRG) {
             seg.k0 = uniform_i(S.k[i]);
             seg.k1 = uniform_i(S.k[i + 1]);
-            dispatch_region(uniform_i(S.pr[i]), uniform_i(S.ar[i]), seg);
+            dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);
         }
     }
     if (lane == 0) {
@@ -429,43 +435,55 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
 }
 
 // ---- 6. chain rule to the fit parameters and to the 209 coefficients ------------------------
-__global__ void k_mm_contract(const double* __restrict__ recs, const double* __restrict__ tans, int64_t nt,
-                              int chunks, const double* __restrict__ part, double* __restrict__ dlam) {
+// (a) one wave per target: lane s sums slot s over the three region groups and the chunks
+__global__ void __launch_bounds__(64) k_mm_reduce(const double* __restrict__ recs, int64_t nt, int chunks,
+                                                  const double* __restrict__ part, double* __restrict__ mred) {
+    const int64_t p = blockIdx.x;
+    const int s = threadIdx.x;
+    if (p >= nt || s >= REC_N) return;
+    double m = 0.0;
+    for (int grp = 0; grp < 3; ++grp)
+        for (int c = 0; c < chunks; ++c) m += part[((grp * nt + p) * chunks + c) * kNSlot + 2 + s];
+    const double* rec = recs + p * REC_N;
+    if (s == R_MS) m /= rec[R_MS];
+    const bool used = (s == R_MS || s == R_LNA0 || (s >= R_PH1 && s < R_VALID));
+    mred[p * REC_N + s] = (used && rec[R_VALID] != 0.0) ? m : 0.0;
+}
+
+// (b) one thread per (target, fitted parameter): dM/dLambda_l = tangent_l . moments
+__global__ void k_mm_contract(const double* __restrict__ tans, int64_t nt, const double* __restrict__ mred,
+                              double* __restrict__ dlam) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= nt * kNumFit) return;
     const int64_t p = t / kNumFit;
-    const int l = static_cast<int>(t % kNumFit);
-    const double* rec = recs + p * REC_N;
-    if (rec[R_VALID] == 0.0) {
-        dlam[t] = 0.0;
-        return;
-    }
-    const double* tn = tans + (p * kNumFit + l) * REC_N;
+    const double* tn = tans + t * REC_N;
+    const double* m = mred + p * REC_N;
     double acc = 0.0;
-    for (int s = 0; s < REC_N; ++s) {
-        double m = 0.0;
-        for (int c = 0; c < chunks; ++c) m += part[(p * chunks + c) * kNSlot + 2 + s];
-        if (s == R_MS) m /= rec[R_MS];
-        if (s == R_A0 || s == R_FP2 || s == R_FA2 || s >= R_VALID) continue;
-        acc += tn[s] * m;
-    }
+    for (int s = 0; s < REC_N; ++s) acc = fma(tn[s], m[s], acc);
     dlam[t] = acc;
 }
 
-__global__ void k_mm_lambda_sum(const double* __restrict__ recs, int64_t nt, const double* __restrict__ dlam,
-                                double* __restrict__ out) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= kNumLambda) return;
+// (c) one block per coefficient: sum over targets of dM/dLambda_l * B_b(eta, chi_PN)
+__global__ void __launch_bounds__(256) k_mm_lambda_sum(const double* __restrict__ recs, int64_t nt,
+                                                       const double* __restrict__ dlam, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int m = blockIdx.x;
     const int l = m / 11, b = m % 11;
     double acc = 0.0;
-    for (int64_t p = 0; p < nt; ++p) {
+    for (int64_t p = threadIdx.x; p < nt; p += 256) {
         const double* rec = recs + p * REC_N;
         if (rec[R_VALID] == 0.0) continue;
         double basis[11];
         fit_basis(rec[R_ETA], rec[R_CHIPN], basis);
-        acc += dlam[p * kNumFit + l] * basis[b];
+        acc = fma(dlam[p * kNumFit + l], basis[b], acc);
     }
-    out[m] = acc;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[m] = red[0];
 }
 
 }  // namespace
@@ -494,12 +512,19 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
         const int64_t waves = nt * m.chunks;
         {
             ProfRange pr(PD_K_MISMATCH_ADJ, s);
-            hipLaunchKernelGGL(k_mm_adjoint, dim3(static_cast<unsigned>((waves + 3) / 4)), dim3(256), 0, s, recs,
-                               nt, m.chunks, g, tab, targets, inv_psd, m.scal, m.mom);
+            const dim3 grid(static_cast<unsigned>((waves + 3) / 4));
+            hipLaunchKernelGGL(k_mm_adjoint<3>, grid, dim3(256), 0, s, recs, nt, m.chunks, g, tab, targets, inv_psd,
+                               m.scal, m.mom);
+            hipLaunchKernelGGL(k_mm_adjoint<2>, grid, dim3(256), 0, s, recs, nt, m.chunks, g, tab, targets, inv_psd,
+                               m.scal, m.mom);
+            hipLaunchKernelGGL(k_mm_adjoint<1>, grid, dim3(256), 0, s, recs, nt, m.chunks, g, tab, targets, inv_psd,
+                               m.scal, m.mom);
         }
+        hipLaunchKernelGGL(k_mm_reduce, dim3(static_cast<unsigned>(nt)), dim3(64), 0, s, recs, nt, m.chunks, m.mom,
+                           m.mred);
         hipLaunchKernelGGL(k_mm_contract, dim3(static_cast<unsigned>((nt * kNumFit + 127) / 128)), dim3(128), 0,
-                           s, recs, fit_tans, nt, m.chunks, m.mom, m.dlam);
-        hipLaunchKernelGGL(k_mm_lambda_sum, dim3(1), dim3(256), 0, s, recs, nt, m.dlam, dsum_dlambda);
+                           s, fit_tans, nt, m.mred, m.dlam);
+        hipLaunchKernelGGL(k_mm_lambda_sum, dim3(kNumLambda), dim3(256), 0, s, recs, nt, m.dlam, dsum_dlambda);
     }
     return hipGetLastError();
 }

@@ -69,6 +69,7 @@ enum : int {
     R_MS34 = 56,  // Ms^(3/4)
     R_A0P = 57,   // exp(lnA0) Ms^(-7/6): A(f) = R_A0P f^(-7/6) Ahat(Mf)
     R_ID = 58,    // 1 / f_damp (the arctan width)
+    R_IANUM = 59, // 1 / R_AM3 (the Lorentzian numerator)
     REC_N = 60
 };
 
@@ -481,7 +482,7 @@ __device__ __forceinline__ bool build_record(const Source<T>& s, const T lam[kNu
     rec[R_MS34] = dpow(ms, 0.75);
     rec[R_A0P] = dexp(lna0 - (7.0 / 6.0) * dlog(ms));
     rec[R_ID] = 1.0 / f_damp;
-    rec[59] = K<T>(0.0);
+    rec[R_IANUM] = 1.0 / (g1 * gd);
     return ok;
 }
 
