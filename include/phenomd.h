@@ -158,6 +158,61 @@ enum {
 int pd_profile_enable(int on);
 int pd_profile_read(int kernel, double* total_ms, int64_t* launches);
 
+/* ---------------------------------------------------------------------------------------
+ * Sampling (Sec. 3.3).  A posterior in unconstrained coordinates x in R^7:
+ *   PD_TARGET_GW     theta = (Mc, q, chi1, chi2, D, tc, phic) with theta_i = lo_i +
+ *                    (hi_i - lo_i) sigmoid(x_i) for i < 6 (uniform priors) and phic = x_6;
+ *                    log pi(x) = lnL(theta(x)) + log |d theta / d x|, lnL as in
+ *                    pd_loglike_and_grad (FP64).
+ *   PD_TARGET_GAUSS  log pi(x) = -1/2 sum_j (x_j - mu_j)^2 isig2_j (tests the samplers
+ *                    against a known answer).
+ * Random numbers are inputs: every call is a deterministic function of its arguments.
+ * ------------------------------------------------------------------------------------- */
+typedef enum { PD_TARGET_GW = 0, PD_TARGET_GAUSS = 1 } pd_target;
+
+typedef struct {
+    int kind;                 /* pd_target */
+    pd_grid grid;             /* GW: frequency grid of data and inv_psd */
+    const double* lambda;     /* GW: [209] device */
+    const double* data;       /* GW: [n_bins][2] device */
+    const double* inv_psd;    /* GW: [n_bins] device */
+    double lo[6], hi[6];      /* GW: prior bounds of (Mc, q, chi1, chi2, D, tc); 0 < q <= 1 */
+    double mu[7], isig2[7];   /* GAUSS: means and inverse variances */
+} pd_posterior;
+
+size_t pd_posterior_workspace_bytes(const pd_posterior* post, int64_t n);
+
+/* log pi(x) [n] and its gradient [n][7] (or NULL) for n points x [n][7]. */
+int pd_posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+size_t pd_hmc_workspace_bytes(const pd_posterior* post, int64_t n);
+
+/* One Hamiltonian Monte Carlo transition for n independent chains (Sec. 3.3; leapfrog
+ * integrator with a diagonal mass matrix, Metropolis accept on the Hamiltonian):
+ *   p = sqrt(mass) xi;  n_leapfrog leapfrog steps of size eps;  accept if log u < -dH.
+ * x [n][7], logp [n], grad [n][7]   in/out: the chains' state with its cached log pi and
+ *                                   gradient (from pd_posterior_logp or a previous step)
+ * xi [n][7]      standard-normal momentum draws;  u [n] uniform(0,1) draws
+ * mass [7]       HOST array, diagonal mass matrix
+ * accepted [n]   out (or NULL): 1 accepted, 0 rejected, -1 rejected as divergent
+ *                (non-finite dH or |dH| > 1000)
+ * dh [n]         out (or NULL): H(end) - H(start)
+ */
+int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
+                const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted,
+                double* dh, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Independence Metropolis-Hastings accept (the learned proposal of the sampler): for each
+ * chain, accept x' (drawn from q) with probability min(1, pi(x') q(x) / (pi(x) q(x'))).
+ * x [n][7], logp [n], logq [n]   in/out current state, log pi and log q at it
+ * xp [n][7], logp_p [n], logq_p [n]  proposals with their log pi and log q
+ * u [n] uniform(0,1) draws;  accepted [n] out (or NULL)
+ */
+int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp,
+                       const double* logp_p, const double* logq_p, const double* u, int32_t* accepted,
+                       void* stream);
+
 /* Text of the last batch-level error on the calling thread (library-owned, never NULL). */
 const char* pd_last_error(void);
 

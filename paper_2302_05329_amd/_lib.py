@@ -44,6 +44,16 @@ class PdGrid(ctypes.Structure):
                 ("f_min", ctypes.c_double), ("f_ref", ctypes.c_double)]
 
 
+PD_TARGET_GW = 0
+PD_TARGET_GAUSS = 1
+
+
+class PdPosterior(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("grid", PdGrid), ("lam", ctypes.c_void_p), ("data", ctypes.c_void_p),
+                ("inv_psd", ctypes.c_void_p), ("lo", ctypes.c_double * 6), ("hi", ctypes.c_double * 6),
+                ("mu", ctypes.c_double * 7), ("isig2", ctypes.c_double * 7)]
+
+
 class PdError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"phenomd error {code}: {msg}")
@@ -63,8 +73,12 @@ SIGNATURES = {
     "pd_loglike_and_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _INT, _P, _P, _P, _P, _SZ, _P]),
     "pd_fisher": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_mismatch_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
-    "pd_hmc_leapfrog": (_INT, [_P, _P, _P, _P, _I64, _INT, ctypes.c_double, _P]),
-    "pd_mh_accept": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P, _I64, _INT, _P, _P]),
+    "pd_posterior_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
+    "pd_posterior_logp": (_INT, [ctypes.c_void_p, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "pd_hmc_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
+    "pd_hmc_step": (_INT, [ctypes.c_void_p, _I64, _P, _P, _P, _P, _P, _INT, ctypes.c_double,
+                           ctypes.POINTER(ctypes.c_double), _P, _P, _P, _SZ, _P]),
+    "pd_independence_mh": (_INT, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pd_flow_forward": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P]),
     "pd_flow_inverse": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P]),
     "pd_flow_backward": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P, _P, _SZ, _P]),

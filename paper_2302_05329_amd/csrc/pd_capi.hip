@@ -318,4 +318,54 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
     return PD_OK;
 }
 
+size_t pd_posterior_workspace_bytes(const pd_posterior* post, int64_t n) {
+    if (pd::posterior_check(post) != PD_OK || n <= 0) return 0;
+    return pd::posterior_ws_bytes(post, n);
+}
+
+size_t pd_hmc_workspace_bytes(const pd_posterior* post, int64_t n) {
+    if (pd::posterior_check(post) != PD_OK || n <= 0) return 0;
+    return pd::hmc_workspace_bytes(post, n);
+}
+
+int pd_posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+    if (pd::posterior_check(post) != PD_OK) return fail(PD_EINVAL, "invalid posterior description");
+    if (!x || !logp) return fail(PD_EINVAL, "x or logp is NULL");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    if (workspace_bytes < pd::posterior_ws_bytes(post, n)) return fail(PD_ENOMEM, "workspace too small");
+    const int rc = pd::posterior_logp(post, x, n, logp, grad, workspace, static_cast<hipStream_t>(stream));
+    if (rc != PD_OK) return fail(rc, "posterior evaluation failed");
+    return PD_OK;
+}
+
+int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
+                const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
+                void* workspace, size_t workspace_bytes, void* stream) {
+    if (pd::posterior_check(post) != PD_OK) return fail(PD_EINVAL, "invalid posterior description");
+    if (!x || !logp || !grad || !xi || !u || !mass) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    if (n_leapfrog < 1 || n_leapfrog > 100000) return fail(PD_EINVAL, "n_leapfrog out of range");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(PD_EINVAL, "eps must be finite and > 0");
+    for (int j = 0; j < 7; ++j)
+        if (!(mass[j] > 0.0) || !std::isfinite(mass[j])) return fail(PD_EINVAL, "mass must be finite and > 0");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    if (workspace_bytes < pd::hmc_workspace_bytes(post, n)) return fail(PD_ENOMEM, "workspace too small");
+    const int rc = pd::hmc_step(post, n, x, logp, grad, xi, u, n_leapfrog, eps, mass, accepted, dh, workspace,
+                                static_cast<hipStream_t>(stream));
+    if (rc != PD_OK) return fail(rc, "hmc step failed");
+    return PD_OK;
+}
+
+int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp, const double* logp_p,
+                       const double* logq_p, const double* u, int32_t* accepted, void* stream) {
+    if (!x || !logp || !logq || !xp || !logp_p || !logq_p || !u) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    const int rc = pd::independence_mh(n, x, logp, logq, xp, logp_p, logq_p, u, accepted,
+                                       static_cast<hipStream_t>(stream));
+    if (rc != PD_OK) return fail(rc, "independence MH failed");
+    return PD_OK;
+}
+
 }  // extern "C"

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 
+#include "../../include/phenomd.h"
 #include "pd_bin.h"
 
 namespace pd {
@@ -36,5 +37,16 @@ hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
                          const double* tab, double* partial, double* F, hipStream_t s);
+
+int posterior_check(const pd_posterior* post);
+size_t posterior_ws_bytes(const pd_posterior* post, int64_t n);
+size_t hmc_workspace_bytes(const pd_posterior* post, int64_t n);
+int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
+                   hipStream_t s);
+int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
+             const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
+             void* ws, hipStream_t s);
+int independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp, const double* logp_p,
+                    const double* logq_p, const double* u, int32_t* accepted, hipStream_t s);
 
 }  // namespace pd

@@ -1,0 +1,308 @@
+// Samplers on the GPU (paper Sec. 3.3): posterior log-density and gradient in
+// unconstrained coordinates, Hamiltonian Monte Carlo with a diagonal mass matrix, and
+// the Metropolis-Hastings accept step of an independence proposal (the learned flow).
+//
+// Coordinates.  The sampler moves x in R^7.  For the gravitational-wave target the
+// source parameters are theta = (Mc, q, chi1, chi2, D, tc, phic) with
+//   theta_i = lo_i + (hi_i - lo_i) * sigmoid(x_i)   for i < 6 (bounded uniform priors),
+//   phic    = x_6                                    (the likelihood is periodic in it),
+// so log pi(x) = lnL(theta(x)) + sum_i log(dtheta_i/dx_i).  The Gaussian target
+// (independent normals) exists to test the sampler machinery against a known answer.
+//
+// Random numbers are inputs (momentum draws, uniforms for the accept test): every call
+// is a deterministic function of its arguments.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/phenomd.h"
+#include "pd_launch.h"
+
+namespace pd {
+
+namespace {
+
+__device__ __forceinline__ double sigmoid(double x) {
+    return (x >= 0.0) ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x));
+}
+
+// x -> theta, d theta / d x, and the log-Jacobian with its derivative.
+__global__ void k_transform(const double* __restrict__ x, int64_t n, pd_posterior post, double* __restrict__ theta,
+                            double* __restrict__ dtdx, double* __restrict__ lj, double* __restrict__ dlj) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < 6; ++j) {
+        const double xv = x[i * 7 + j];
+        const double s = sigmoid(xv);
+        const double w = post.hi[j] - post.lo[j];
+        theta[i * 7 + j] = post.lo[j] + w * s;
+        const double d = w * s * (1.0 - s);
+        dtdx[i * 7 + j] = d;
+        // log(w s (1-s)) = log w - softplus(-x) - softplus(x)
+        const double ax = fabs(xv);
+        acc += log(w) - ax - 2.0 * log1p(exp(-ax));
+        dlj[i * 7 + j] = 1.0 - 2.0 * s;
+    }
+    theta[i * 7 + 6] = x[i * 7 + 6];
+    dtdx[i * 7 + 6] = 1.0;
+    dlj[i * 7 + 6] = 0.0;
+    lj[i] = acc;
+}
+
+__global__ void k_assemble(int64_t n, const double* __restrict__ lnl, const double* __restrict__ gth,
+                           const double* __restrict__ dtdx, const double* __restrict__ lj,
+                           const double* __restrict__ dlj, double* __restrict__ logp, double* __restrict__ grad) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool ok = isfinite(lnl[i]);
+    logp[i] = ok ? lnl[i] + lj[i] : -INFINITY;
+    if (grad) {
+        for (int j = 0; j < 7; ++j) grad[i * 7 + j] = ok ? fma(gth[i * 7 + j], dtdx[i * 7 + j], dlj[i * 7 + j]) : 0.0;
+    }
+}
+
+__global__ void k_gauss(const double* __restrict__ x, int64_t n, pd_posterior post, double* __restrict__ logp,
+                        double* __restrict__ grad) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < 7; ++j) {
+        const double r = x[i * 7 + j] - post.mu[j];
+        acc += r * r * post.isig2[j];
+        if (grad) grad[i * 7 + j] = -r * post.isig2[j];
+    }
+    logp[i] = -0.5 * acc;
+}
+
+// ---- HMC trajectory pieces ---------------------------------------------------------------
+struct HmcArgs {
+    double eps;
+    double mass[7];
+};
+
+// p = sqrt(m) xi;  H0 = -logp + sum p^2 / (2m);  first half kick.
+__global__ void k_hmc_begin(int64_t n, HmcArgs a, const double* __restrict__ xi, const double* __restrict__ logp,
+                            const double* __restrict__ grad, double* __restrict__ p, double* __restrict__ h0) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double kin = 0.0;
+    for (int j = 0; j < 7; ++j) {
+        const double pj = sqrt(a.mass[j]) * xi[i * 7 + j];
+        kin += pj * pj / a.mass[j];
+        p[i * 7 + j] = fma(0.5 * a.eps, grad[i * 7 + j], pj);
+    }
+    h0[i] = -logp[i] + 0.5 * kin;
+}
+
+// drift: x += eps p / m
+__global__ void k_hmc_drift(int64_t n, HmcArgs a, double* __restrict__ x, const double* __restrict__ p) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * 7) return;
+    const int j = static_cast<int>(t % 7);
+    x[t] = fma(a.eps / a.mass[j], p[t], x[t]);
+}
+
+// kick: p += w eps grad  (w = 1 inside the trajectory, 1/2 at its end)
+__global__ void k_hmc_kick(int64_t n, double weps, double* __restrict__ p, const double* __restrict__ grad) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * 7) return;
+    p[t] = fma(weps, grad[t], p[t]);
+}
+
+// Metropolis-Hastings on the Hamiltonian; NaN or |dH| > 1000 (a divergence) rejects.
+__global__ void k_hmc_accept(int64_t n, HmcArgs a, const double* __restrict__ u, const double* __restrict__ h0,
+                             const double* __restrict__ x1, const double* __restrict__ p1,
+                             const double* __restrict__ logp1, const double* __restrict__ grad1,
+                             double* __restrict__ x, double* __restrict__ logp, double* __restrict__ grad,
+                             int32_t* __restrict__ accepted, double* __restrict__ dh_out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double kin = 0.0;
+    for (int j = 0; j < 7; ++j) kin += p1[i * 7 + j] * p1[i * 7 + j] / a.mass[j];
+    const double h1 = -logp1[i] + 0.5 * kin;
+    const double dh = h1 - h0[i];
+    const bool finite = isfinite(dh);
+    const bool acc = finite && fabs(dh) <= 1000.0 && log(u[i]) < -dh;
+    if (acc) {
+        for (int j = 0; j < 7; ++j) {
+            x[i * 7 + j] = x1[i * 7 + j];
+            grad[i * 7 + j] = grad1[i * 7 + j];
+        }
+        logp[i] = logp1[i];
+    }
+    if (accepted) accepted[i] = acc ? 1 : ((finite && fabs(dh) <= 1000.0) ? 0 : -1);
+    if (dh_out) dh_out[i] = dh;
+}
+
+// Independence Metropolis-Hastings: accept x' ~ q with prob min(1, pi(x') q(x) / (pi(x) q(x'))).
+__global__ void k_imh(int64_t n, double* __restrict__ x, double* __restrict__ logp, double* __restrict__ logq,
+                      const double* __restrict__ xp, const double* __restrict__ logp_p,
+                      const double* __restrict__ logq_p, const double* __restrict__ u,
+                      int32_t* __restrict__ accepted) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double la = (logp_p[i] - logp[i]) + (logq[i] - logq_p[i]);
+    const bool acc = isfinite(logp_p[i]) && isfinite(logq_p[i]) && (log(u[i]) < la || !isfinite(logp[i]));
+    if (acc) {
+        for (int j = 0; j < 7; ++j) x[i * 7 + j] = xp[i * 7 + j];
+        logp[i] = logp_p[i];
+        logq[i] = logq_p[i];
+    }
+    if (accepted) accepted[i] = acc ? 1 : 0;
+}
+
+inline unsigned nblk(int64_t threads, int per) { return static_cast<unsigned>((threads + per - 1) / per); }
+
+constexpr size_t kAl = 256;
+inline size_t al(size_t x) { return (x + kAl - 1) / kAl * kAl; }
+
+// posterior workspace: theta, dtdx, dlj [n][7]; lj, lnl [n]; gth [n][7]; then loglike workspace
+struct PostWs {
+    double *theta, *dtdx, *dlj, *lj, *lnl, *gth;
+    void* ll;
+    size_t ll_bytes;
+};
+
+size_t post_ws_bytes(const pd_posterior* post, int64_t n) {
+    const size_t N = static_cast<size_t>(n);
+    size_t off = 0;
+    off = al(off + N * 7 * 8) ;
+    off = al(off + N * 7 * 8);
+    off = al(off + N * 7 * 8);
+    off = al(off + N * 8);
+    off = al(off + N * 8);
+    off = al(off + N * 7 * 8);
+    if (post->kind == PD_TARGET_GW) off = al(off + pd_workspace_bytes(PD_OP_LOGLIKE_GRAD, n, post->grid.n_bins));
+    return off;
+}
+
+PostWs post_ws(const pd_posterior* post, int64_t n, void* base) {
+    const size_t N = static_cast<size_t>(n);
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    PostWs w;
+    w.theta = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 7 * 8);
+    w.dtdx = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 7 * 8);
+    w.dlj = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 7 * 8);
+    w.lj = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 8);
+    w.lnl = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 8);
+    w.gth = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 7 * 8);
+    w.ll = p + off;
+    w.ll_bytes = (post->kind == PD_TARGET_GW) ? pd_workspace_bytes(PD_OP_LOGLIKE_GRAD, n, post->grid.n_bins) : 0;
+    return w;
+}
+
+// hmc workspace: x1, p [n][7]; h0, logp1 [n]; grad1 [n][7]; then the posterior workspace
+struct HmcWs {
+    double *x1, *p, *h0, *logp1, *grad1;
+    void* post;
+};
+
+size_t hmc_ws_bytes(const pd_posterior* post, int64_t n) {
+    const size_t N = static_cast<size_t>(n);
+    size_t off = 0;
+    off = al(off + N * 7 * 8);
+    off = al(off + N * 7 * 8);
+    off = al(off + N * 8);
+    off = al(off + N * 8);
+    off = al(off + N * 7 * 8);
+    return off + post_ws_bytes(post, n);
+}
+
+HmcWs hmc_ws(int64_t n, void* base) {
+    const size_t N = static_cast<size_t>(n);
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    HmcWs w;
+    w.x1 = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 7 * 8);
+    w.p = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 7 * 8);
+    w.h0 = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 8);
+    w.logp1 = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 8);
+    w.grad1 = reinterpret_cast<double*>(p + off);
+    off = al(off + N * 7 * 8);
+    w.post = p + off;
+    return w;
+}
+
+}  // namespace
+
+int posterior_check(const pd_posterior* post) {
+    if (!post) return PD_EINVAL;
+    if (post->kind != PD_TARGET_GW && post->kind != PD_TARGET_GAUSS) return PD_EINVAL;
+    if (post->kind == PD_TARGET_GW) {
+        if (!post->lambda || !post->data || !post->inv_psd) return PD_EINVAL;
+        for (int j = 0; j < 6; ++j)
+            if (!(post->hi[j] > post->lo[j])) return PD_EINVAL;
+        if (!(post->lo[0] > 0.0) || !(post->lo[1] > 0.0) || !(post->hi[1] <= 1.0) || !(post->lo[4] > 0.0) ||
+            post->lo[2] < -1.0 || post->hi[2] > 1.0 || post->lo[3] < -1.0 || post->hi[3] > 1.0)
+            return PD_EINVAL;
+    } else {
+        for (int j = 0; j < 7; ++j)
+            if (!(post->isig2[j] > 0.0)) return PD_EINVAL;
+    }
+    return PD_OK;
+}
+
+int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
+                   hipStream_t s) {
+    if (post->kind == PD_TARGET_GAUSS) {
+        hipLaunchKernelGGL(k_gauss, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, logp, grad);
+        return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+    }
+    PostWs w = post_ws(post, n, ws);
+    hipLaunchKernelGGL(k_transform, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx, w.lj, w.dlj);
+    if (hipGetLastError() != hipSuccess) return PD_EHIP;
+    const int rc = pd_loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data,
+                                       post->inv_psd, PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll,
+                                       w.ll_bytes, s);
+    if (rc != PD_OK) return rc;
+    hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 128)), dim3(128), 0, s, n, w.lnl, w.gth, w.dtdx, w.lj, w.dlj,
+                       logp, grad);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+size_t posterior_ws_bytes(const pd_posterior* post, int64_t n) { return post_ws_bytes(post, n); }
+size_t hmc_workspace_bytes(const pd_posterior* post, int64_t n) { return hmc_ws_bytes(post, n); }
+
+int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
+             const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
+             void* ws, hipStream_t s) {
+    HmcWs w = hmc_ws(n, ws);
+    HmcArgs a;
+    a.eps = eps;
+    for (int j = 0; j < 7; ++j) a.mass[j] = mass[j];
+    const unsigned b1 = nblk(n, 128), b7 = nblk(n * 7, 256);
+    hipLaunchKernelGGL(k_hmc_begin, dim3(b1), dim3(128), 0, s, n, a, xi, logp, grad, w.p, w.h0);
+    if (hipMemcpyAsync(w.x1, x, static_cast<size_t>(n) * 7 * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return PD_EHIP;
+    for (int l = 0; l < n_leapfrog; ++l) {
+        hipLaunchKernelGGL(k_hmc_drift, dim3(b7), dim3(256), 0, s, n, a, w.x1, w.p);
+        const int rc = posterior_logp(post, w.x1, n, w.logp1, w.grad1, w.post, s);
+        if (rc != PD_OK) return rc;
+        const double weps = (l + 1 < n_leapfrog) ? eps : 0.5 * eps;
+        hipLaunchKernelGGL(k_hmc_kick, dim3(b7), dim3(256), 0, s, n, weps, w.p, w.grad1);
+    }
+    hipLaunchKernelGGL(k_hmc_accept, dim3(b1), dim3(128), 0, s, n, a, u, w.h0, w.x1, w.p, w.logp1, w.grad1, x, logp,
+                       grad, accepted, dh);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+int independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp, const double* logp_p,
+                    const double* logq_p, const double* u, int32_t* accepted, hipStream_t s) {
+    hipLaunchKernelGGL(k_imh, dim3(nblk(n, 128)), dim3(128), 0, s, n, x, logp, logq, xp, logp_p, logq_p, u,
+                       accepted);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+}  // namespace pd

@@ -1,0 +1,111 @@
+"""Samplers of Sec. 3.3 on the GPU: posterior log-density, HMC transitions, independence
+Metropolis-Hastings.  Marshalling only; the transitions run in the HIP library.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .api import Workspace, _grid, _ptr, _stream
+
+
+class Posterior:
+    """A pd_posterior description plus the device arrays it points at."""
+
+    def __init__(self, kind, grid=None, lam=None, data=None, inv_psd=None, lo=None, hi=None, mu=None, isig2=None):
+        self.kind = kind
+        self._keep = []
+        st = L.PdPosterior()
+        st.kind = kind
+        if kind == L.PD_TARGET_GW:
+            g = _grid(grid)
+            lam = torch.as_tensor(lam, dtype=torch.float64, device="cuda").contiguous()
+            d = torch.as_tensor(data, device="cuda")
+            if d.is_complex():
+                d = torch.view_as_real(d.to(torch.complex128))
+            d = d.to(torch.float64).contiguous()
+            ip = torch.as_tensor(inv_psd, dtype=torch.float64, device="cuda").contiguous()
+            if lam.numel() != 209 or tuple(d.shape) != (g.n_bins, 2) or tuple(ip.shape) != (g.n_bins,):
+                raise ValueError("posterior arrays do not match the grid")
+            self._keep += [lam, d, ip]
+            st.grid = g
+            st.lam, st.data, st.inv_psd = lam.data_ptr(), d.data_ptr(), ip.data_ptr()
+            for j in range(6):
+                st.lo[j], st.hi[j] = float(lo[j]), float(hi[j])
+        else:
+            for j in range(7):
+                st.mu[j], st.isig2[j] = float(mu[j]), float(isig2[j])
+        self.st = st
+        self.lo = None if lo is None else np.asarray(lo, dtype=np.float64)
+        self.hi = None if hi is None else np.asarray(hi, dtype=np.float64)
+
+    def ref(self):
+        return ctypes.byref(self.st)
+
+    # ---- coordinate maps (host-side helpers for initialisation and reporting) ----------
+    def to_x(self, theta):
+        """theta rows (Mc, q, chi1, chi2, D, tc, phic) -> unconstrained x (inverse sigmoid)."""
+        th = np.asarray(theta, dtype=np.float64)
+        x = th.copy()
+        s = (th[..., :6] - self.lo) / (self.hi - self.lo)
+        x[..., :6] = np.log(s) - np.log1p(-s)
+        return x
+
+    def to_theta(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        th = x.copy()
+        th[..., :6] = self.lo + (self.hi - self.lo) / (1.0 + np.exp(-x[..., :6]))
+        return th
+
+
+def logp(post, x, want_grad=True, ws=None):
+    ws = ws or Workspace()
+    x = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    if x.dim() != 2 or x.shape[1] != 7:
+        raise ValueError("x must be [n, 7]")
+    n = x.shape[0]
+    lp = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((n, 7), dtype=torch.float64, device="cuda") if want_grad else None
+    wp, wb = ws.get(L.lib().pd_posterior_workspace_bytes(post.ref(), n))
+    L.check(L.lib().pd_posterior_logp(post.ref(), _ptr(x), n, _ptr(lp), _ptr(g), wp, wb, _stream()))
+    return lp, g
+
+
+class HMC:
+    """n parallel HMC chains with cached log-density and gradient (all tensors on the GPU)."""
+
+    def __init__(self, post, x0, eps, n_leapfrog, mass):
+        self.post = post
+        self.x = torch.as_tensor(x0, dtype=torch.float64, device="cuda").clone().contiguous()
+        self.n = self.x.shape[0]
+        self.eps = float(eps)
+        self.L = int(n_leapfrog)
+        self.mass = (ctypes.c_double * 7)(*[float(m) for m in mass])
+        self.ws = Workspace()
+        self.logp, self.grad = logp(post, self.x, ws=self.ws)
+        self.accepted = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self.dh = torch.empty(self.n, dtype=torch.float64, device="cuda")
+
+    def step(self, xi, u):
+        """One transition; xi [n, 7] standard normals, u [n] uniforms (device tensors)."""
+        if tuple(xi.shape) != (self.n, 7) or tuple(u.shape) != (self.n,):
+            raise ValueError("random draws have the wrong shape")
+        wp, wb = self.ws.get(L.lib().pd_hmc_workspace_bytes(self.post.ref(), self.n))
+        L.check(L.lib().pd_hmc_step(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(self.grad),
+                                    _ptr(xi), _ptr(u), self.L, self.eps, self.mass, _ptr(self.accepted),
+                                    _ptr(self.dh), wp, wb, _stream()))
+        return self.accepted
+
+
+def independence_mh(x, lp, lq, xp, lp_p, lq_p, u, accepted=None):
+    """In-place accept of proposals xp for the chains x (all device tensors)."""
+    n = x.shape[0]
+    for t, shape in ((x, (n, 7)), (lp, (n,)), (lq, (n,)), (xp, (n, 7)), (lp_p, (n,)), (lq_p, (n,)), (u, (n,))):
+        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("independence_mh: bad tensor")
+    if accepted is None:
+        accepted = torch.empty(n, dtype=torch.int32, device="cuda")
+    L.check(L.lib().pd_independence_mh(n, _ptr(x), _ptr(lp), _ptr(lq), _ptr(xp), _ptr(lp_p), _ptr(lq_p), _ptr(u),
+                                       _ptr(accepted), _stream()))
+    return accepted

@@ -1,0 +1,142 @@
+"""GPU samplers against the numpy sampler oracle, and exactness on a Gaussian target."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import phenomd_oracle as O
+from oracle import sampler_oracle as S
+from paper_2302_05329_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _c5_problem(lam, n_bins=8033):
+    """The learned-proposal workload's injection (SNR 20 in one face-on detector) and priors,
+    built with the oracle waveform."""
+    cfg = W.config5()
+    grid = W.Grid(20.0, 0.125, n_bins)
+    g = grid.as_tuple()
+    inj = cfg["inj_unit_distance"].copy()
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    h1 = O.waveform(inj, O.PARAM_M1M2, lam, g)
+    snr1 = math.sqrt(O.inner(h1, h1, 1 / psd, g[1]))
+    inj[4] = snr1 / 20.0
+    data = W.complex_noise(psd, grid.df, 1005) + O.waveform(inj, O.PARAM_M1M2, lam, g)
+    mc_q = W.to_param(inj[None, :], O.PARAM_MC_Q)[0]
+    lo = np.array([20.0, 0.125, -0.9, -0.9, 0.2 * inj[4], -0.1])
+    hi = np.array([40.0, 1.0, 0.9, 0.9, 3.0 * inj[4], 0.1])
+    return dict(grid=grid, data=data, inv_psd=1 / psd, lo=lo, hi=hi, theta_inj=mc_q)
+
+
+def test_posterior_logp_parity_gw(gpu, lam0):
+    import torch
+    from paper_2302_05329_amd import sampling
+    pb = _c5_problem(lam0)
+    post = sampling.Posterior(0, grid=pb["grid"], lam=lam0, data=pb["data"], inv_psd=pb["inv_psd"], lo=pb["lo"],
+                              hi=pb["hi"])
+    rng = np.random.default_rng(11)
+    x0 = post.to_x(pb["theta_inj"])
+    xs = x0 + 0.05 * rng.standard_normal((12, 7))
+    _say("posterior logp GW n=12")
+    lp, g = sampling.logp(post, xs)
+    torch.cuda.synchronize()
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    gr = pb["grid"].as_tuple()
+    for i, x in enumerate(xs):
+        ref_lp, ref_g = S.logp_gw(x, lam0, gr, pb["data"], pb["inv_psd"], pb["lo"], pb["hi"])
+        assert abs(lp[i] - ref_lp) <= 1e-10 * max(1.0, abs(ref_lp) / 1e3), (lp[i], ref_lp)
+        th, d, _, _ = S.transform(x, pb["lo"], pb["hi"])
+        F = O.fisher(th, O.PARAM_MC_Q, lam0, gr, pb["inv_psd"])
+        h = O.waveform(th, O.PARAM_MC_Q, lam0, gr)
+        r = pb["data"] - h
+        scale = np.sqrt(O.inner(r, r, pb["inv_psd"], gr[1]) * np.diag(F)) * d + 1.0
+        assert np.all(np.abs(g[i] - ref_g) <= 1e-9 * scale), (g[i], ref_g)
+
+
+def test_hmc_step_parity_gw(gpu, lam0):
+    import torch
+    from paper_2302_05329_amd import sampling
+    pb = _c5_problem(lam0, n_bins=4001)
+    post = sampling.Posterior(0, grid=pb["grid"], lam=lam0, data=pb["data"], inv_psd=pb["inv_psd"], lo=pb["lo"],
+                              hi=pb["hi"])
+    rng = np.random.default_rng(12)
+    x0 = post.to_x(pb["theta_inj"]) + 0.02 * rng.standard_normal((6, 7))
+    mass = np.array([400.0, 50.0, 20.0, 20.0, 10.0, 4e3, 4.0])
+    eps, L = 0.02, 4
+    xi = rng.standard_normal((6, 7))
+    u = rng.uniform(size=6)
+    _say("hmc step GW n=6 L=4")
+    hmc = sampling.HMC(post, x0, eps, L, mass)
+    acc = hmc.step(torch.as_tensor(xi, device="cuda"), torch.as_tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    xg, lpg, dhg, accg = hmc.x.cpu().numpy(), hmc.logp.cpu().numpy(), hmc.dh.cpu().numpy(), acc.cpu().numpy()
+    gr = pb["grid"].as_tuple()
+
+    def lpf(x):
+        return S.logp_gw(x, lam0, gr, pb["data"], pb["inv_psd"], pb["lo"], pb["hi"])
+
+    for i in range(6):
+        lp0, g0 = lpf(x0[i])
+        xr, lpr, _, ar, dhr = S.hmc_step(lpf, x0[i], lp0, g0, xi[i], u[i], L, eps, mass)
+        assert abs(dhg[i] - dhr) <= 1e-8 * max(1.0, abs(dhr)), (dhg[i], dhr)
+        if abs(-dhr - math.log(u[i])) > 1e-6:
+            assert accg[i] == ar
+            assert np.max(np.abs(xg[i] - xr)) <= 1e-9 * (1 + np.max(np.abs(xr)))
+
+
+def test_hmc_recovers_gaussian_target_on_gpu(gpu):
+    import torch
+    from paper_2302_05329_amd import sampling
+    mu = np.array([0.3, -1.0, 2.0, 0.0, 0.5, -0.2, 1.1])
+    sig = np.array([0.5, 1.0, 2.0, 0.1, 1.5, 0.7, 0.3])
+    post = sampling.Posterior(1, mu=mu, isig2=1 / sig**2)
+    n = 4096
+    rng = np.random.default_rng(13)
+    x0 = mu + 3 * sig * rng.standard_normal((n, 7))
+    hmc = sampling.HMC(post, x0, 0.2, 8, 1 / sig**2)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13)
+    draws = []
+    acc = 0
+    _say("hmc gaussian n=4096 steps=40")
+    for t in range(40):
+        xi = torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen)
+        u = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+        a = hmc.step(xi, u)
+        acc += int((a == 1).sum())
+        if t >= 10:
+            draws.append(hmc.x.cpu().numpy())
+    s = np.concatenate(draws)
+    assert acc / (40 * n) > 0.6
+    se = sig / np.sqrt(n * 5)
+    assert np.all(np.abs(s.mean(axis=0) - mu) < 5 * se)
+    assert np.all(np.abs(s.std(axis=0) / sig - 1) < 0.03)
+
+
+def test_independence_mh_matches_rule(gpu):
+    import torch
+    from paper_2302_05329_amd import sampling
+    rng = np.random.default_rng(14)
+    n = 1000
+    x = rng.standard_normal((n, 7))
+    lp = rng.normal(-5, 2, n)
+    lq = rng.normal(-5, 2, n)
+    xp = rng.standard_normal((n, 7))
+    lpp = rng.normal(-5, 2, n)
+    lqp = rng.normal(-5, 2, n)
+    lpp[:10] = -np.inf
+    u = rng.uniform(size=n)
+    t = [torch.as_tensor(a, device="cuda").contiguous() for a in (x, lp, lq, xp, lpp, lqp, u)]
+    _say("independence MH n=1000")
+    acc = sampling.independence_mh(*t).cpu().numpy()
+    for i in range(n):
+        xr, lpr, lqr, ar = S.independence_mh(x[i], lp[i], lq[i], xp[i], lpp[i], lqp[i], u[i])
+        assert acc[i] == ar
+        assert np.array_equal(t[0][i].cpu().numpy(), xr)
