@@ -207,11 +207,41 @@ int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, do
  * chain, accept x' (drawn from q) with probability min(1, pi(x') q(x) / (pi(x) q(x'))).
  * x [n][7], logp [n], logq [n]   in/out current state, log pi and log q at it
  * xp [n][7], logp_p [n], logq_p [n]  proposals with their log pi and log q
+ * grad [n][7], grad_p [n][7]  (both NULL, or both set) gradient of log pi at the current
+ *                state (in/out) and at the proposals, carried along so that HMC can continue
  * u [n] uniform(0,1) draws;  accepted [n] out (or NULL)
  */
-int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp,
-                       const double* logp_p, const double* logq_p, const double* u, int32_t* accepted,
-                       void* stream);
+int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, double* grad, const double* xp,
+                       const double* logp_p, const double* logq_p, const double* grad_p, const double* u,
+                       int32_t* accepted, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned proposal: a RealNVP normalising flow on R^7 (the flow + GPU + gradient-sampler
+ * combination announced at the end of Sec. 3.3).  Fixed architecture: standardisation
+ * y = (x - mu) isd, then 8 affine coupling layers alternately conditioning on dims {0,1,2}
+ * and {3..6}, each with an MLP 7 -> 128 -> 128 -> 14 (tanh hidden units), log-scale bounded
+ * as 2 tanh(./2).  log q(x) = log N(z; 0, I) + sum of log-determinants + sum log isd.
+ * params: float32, per layer W1[7][128] b1[128] W2[128][128] b2[128] W3[128][14] b3[14],
+ * 8 layers, then mu[7] and isd[7] (not trained).  FP32 arithmetic; x, z, log q in FP64.
+ * ------------------------------------------------------------------------------------- */
+int64_t pd_flow_param_count(void);
+size_t pd_flow_workspace_bytes(int64_t n);
+
+/* data -> latent: z [n][7] (or NULL) and log q(x) [n] for x [n][7]. */
+int pd_flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, void* stream);
+
+/* latent -> data: x [n][7] = f^-1(z) and log q(x) [n], for z [n][7] (standard-normal draws). */
+int pd_flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, void* stream);
+
+/* Maximum-likelihood training objective loss = -mean_b log q(x_b) over x [n][7] and its
+ * gradient grad [P] w.r.t. params (the 14 standardisation entries get zero); loss [1] or NULL.
+ * Workspace of pd_flow_workspace_bytes(n). */
+int pd_flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* Adam (Kingma & Ba 2015) on count float32 parameters, step t >= 1 (bias-corrected). */
+int pd_adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr,
+                 double beta1, double beta2, double eps, int64_t t, void* stream);
 
 /* Text of the last batch-level error on the calling thread (library-owned, never NULL). */
 const char* pd_last_error(void);

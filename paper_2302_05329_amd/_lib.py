@@ -78,13 +78,14 @@ SIGNATURES = {
     "pd_hmc_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
     "pd_hmc_step": (_INT, [ctypes.c_void_p, _I64, _P, _P, _P, _P, _P, _INT, ctypes.c_double,
                            ctypes.POINTER(ctypes.c_double), _P, _P, _P, _SZ, _P]),
-    "pd_independence_mh": (_INT, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
-    "pd_flow_forward": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P]),
-    "pd_flow_inverse": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P]),
-    "pd_flow_backward": (_INT, [_P, _P, _I64, _INT, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pd_independence_mh": (_INT, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pd_flow_param_count": (_I64, []),
+    "pd_flow_workspace_bytes": (_SZ, [_I64]),
+    "pd_flow_forward": (_INT, [_P, _P, _I64, _P, _P, _P]),
+    "pd_flow_sample": (_INT, [_P, _P, _I64, _P, _P, _P]),
+    "pd_flow_loss_grad": (_INT, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "pd_adam_step": (_INT, [_P, _P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double, _I64, _P]),
-    "pd_flow_param_count": (_I64, [_INT]),
     "pd_transition_frequencies": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _SZ, _P]),
     "pd_profile_enable": (_INT, [_INT]),
     "pd_profile_read": (_INT, [_INT, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),

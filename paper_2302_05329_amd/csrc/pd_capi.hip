@@ -358,14 +358,54 @@ int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, do
     return PD_OK;
 }
 
-int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp, const double* logp_p,
-                       const double* logq_p, const double* u, int32_t* accepted, void* stream) {
+int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, double* grad, const double* xp,
+                       const double* logp_p, const double* logq_p, const double* grad_p, const double* u,
+                       int32_t* accepted, void* stream) {
     if (!x || !logp || !logq || !xp || !logp_p || !logq_p || !u) return fail(PD_EINVAL, "NULL argument");
+    if ((grad == nullptr) != (grad_p == nullptr)) return fail(PD_EINVAL, "grad and grad_p must both be set or NULL");
     if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
-    const int rc = pd::independence_mh(n, x, logp, logq, xp, logp_p, logq_p, u, accepted,
+    const int rc = pd::independence_mh(n, x, logp, logq, grad, xp, logp_p, logq_p, grad_p, u, accepted,
                                        static_cast<hipStream_t>(stream));
     if (rc != PD_OK) return fail(rc, "independence MH failed");
     return PD_OK;
+}
+
+int64_t pd_flow_param_count(void) { return pd::flow_param_count(); }
+
+size_t pd_flow_workspace_bytes(int64_t n) { return n > 0 ? pd::flow_ws_bytes(n) : 0; }
+
+int pd_flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, void* stream) {
+    if (!params || !x || !logq) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    const int rc = pd::flow_forward(params, x, n, z, logq, static_cast<hipStream_t>(stream));
+    return rc == PD_OK ? PD_OK : fail(rc, "flow forward failed");
+}
+
+int pd_flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, void* stream) {
+    if (!params || !z || !x || !logq) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    const int rc = pd::flow_sample(params, z, n, x, logq, static_cast<hipStream_t>(stream));
+    return rc == PD_OK ? PD_OK : fail(rc, "flow sample failed");
+}
+
+int pd_flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+    if (!params || !x || !grad) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    if (workspace_bytes < pd::flow_ws_bytes(n)) return fail(PD_ENOMEM, "workspace too small");
+    const int rc = pd::flow_loss_grad(params, x, n, grad, loss, workspace, static_cast<hipStream_t>(stream));
+    return rc == PD_OK ? PD_OK : fail(rc, "flow gradient failed");
+}
+
+int pd_adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr, double beta1,
+                 double beta2, double eps, int64_t t, void* stream) {
+    if (!params || !grad || !m || !v) return fail(PD_EINVAL, "NULL argument");
+    if (count <= 0 || t < 1) return fail(PD_EINVAL, "bad count or step");
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return fail(PD_EINVAL, "bad Adam hyper-parameters");
+    const int rc = pd::adam_step(params, grad, m, v, count, lr, beta1, beta2, eps, t, static_cast<hipStream_t>(stream));
+    return rc == PD_OK ? PD_OK : fail(rc, "adam failed");
 }
 
 }  // extern "C"

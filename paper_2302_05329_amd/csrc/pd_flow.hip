@@ -1,0 +1,395 @@
+// RealNVP normalising flow on the GPU: the learned independence proposal for the
+// sampler (the follow-up the paper announces at the end of Sec. 3.3: normalising flows
+// + GPU + gradient-based sampler).
+//
+// Architecture (fixed): 7-D, a fixed standardisation y = (x - mu) * isd, then 8 affine
+// coupling layers (Dinh et al. 2017).  Layer l conditions on dims {0,1,2} (l even) or
+// {3,...,6} (l odd) and transforms the others:
+//   in = m * y;  h1 = tanh(W1^T in + b1);  h2 = tanh(W2^T h1 + b2);  o = W3^T h2 + b3
+//   s = 2 tanh(o[0:7] / 2) (1 - m),  t = o[7:14] (1 - m)
+//   forward (data -> latent):  y' = m y + (1 - m) (y exp(s) + t),  log det += sum s
+//   inverse:                   y  = m y' + (1 - m) (y' - t) exp(-s)
+// log q(x) = sum_d [-z_d^2/2 - log(2 pi)/2] + sum_l sum s_l + sum_d log isd_d.
+//
+// Parameter layout (float32): per layer W1[7][128], b1[128], W2[128][128], b2[128],
+// W3[128][14], b3[14] (19342 floats), 8 layers, then mu[7], isd[7].
+//
+// Kernels: one block of 256 threads per tile of samples, all 8 layers fused, activations
+// in LDS, weights read through the caches.  Training saves each layer's input, hidden
+// activations and outputs; the backward kernel writes one row of weight-gradient partial
+// sums per tile, reduced in a fixed order (no atomics).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/phenomd.h"
+#include "pd_launch.h"
+
+namespace pd {
+
+namespace {
+
+constexpr int kD = 7;
+constexpr int kH = 128;
+constexpr int kO = 14;
+constexpr int kLayers = 8;
+constexpr int kLayerP = kD * kH + kH + kH * kH + kH + kH * kO + kO;   // 19342
+constexpr int kP = kLayers * kLayerP + 2 * kD;                         // + mu, isd
+constexpr int kOffW1 = 0, kOffB1 = kD * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
+              kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH * kO;
+constexpr int kOffStd = kLayers * kLayerP;
+constexpr float kSC = 2.0f;                 // bound of the log-scale
+constexpr int kSave = 8 + kH + kH + 16;     // per sample per layer: y_in, h1, h2, o
+constexpr int kTF = 16;                     // samples per tile, forward / inverse
+constexpr int kTB = 32;                     // samples per tile, backward
+constexpr float kHalfLog2Pi = 0.91893853320467274178f;
+
+__device__ __forceinline__ bool cond_dim(int layer, int d) { return (layer & 1) ? (d >= 3) : (d < 3); }
+
+// Fused 8-layer pass over one tile.  INV: latent -> data.  SAVE: keep activations.
+template <bool INV, bool SAVE>
+__global__ void __launch_bounds__(256) k_flow(const float* __restrict__ P, const double* __restrict__ in, int64_t n,
+                                              double* __restrict__ out, double* __restrict__ logq,
+                                              float* __restrict__ saved) {
+    __shared__ float y[kTF][8];
+    __shared__ float h1[kTF][kH];
+    __shared__ float h2[kTF][kH];
+    __shared__ float o[kTF][16];
+    __shared__ float sv[kTF][8];
+    const int t = threadIdx.x;
+    const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kTF;
+    const float* mu = P + kOffStd;
+    const float* isd = mu + kD;
+    if (t < kTF * 8) {
+        const int s = t / 8, d = t % 8;
+        float v = 0.0f;
+        if (d < kD && s0 + s < n) {
+            const float xv = static_cast<float>(in[(s0 + s) * kD + d]);
+            v = INV ? xv : (xv - mu[d]) * isd[d];
+        }
+        y[s][d] = v;
+        sv[s][d] = 0.0f;
+    }
+    __syncthreads();
+    for (int step = 0; step < kLayers; ++step) {
+        const int layer = INV ? (kLayers - 1 - step) : step;
+        const float* W1 = P + layer * kLayerP + kOffW1;
+        const float* B1 = P + layer * kLayerP + kOffB1;
+        const float* W2 = P + layer * kLayerP + kOffW2;
+        const float* B2 = P + layer * kLayerP + kOffB2;
+        const float* W3 = P + layer * kLayerP + kOffW3;
+        const float* B3 = P + layer * kLayerP + kOffB3;
+        if (SAVE && t < kTF * 8) {
+            const int s = t / 8, d = t % 8;
+            if (s0 + s < n) saved[((s0 + s) * kLayers + layer) * kSave + d] = y[s][d];
+        }
+        // hidden layer 1
+        for (int idx = t; idx < kTF * kH; idx += 256) {
+            const int s = idx / kH, j = idx % kH;
+            float a = B1[j];
+#pragma unroll
+            for (int d = 0; d < kD; ++d)
+                if (cond_dim(layer, d)) a = fmaf(W1[d * kH + j], y[s][d], a);
+            h1[s][j] = tanhf(a);
+        }
+        __syncthreads();
+        // hidden layer 2: thread -> column j, 8 samples
+        {
+            const int j = t % kH, sg = (t / kH) * 8;
+            float acc[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc[r] = B2[j];
+            for (int k = 0; k < kH; ++k) {
+                const float w = W2[k * kH + j];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) acc[r] = fmaf(w, h1[sg + r][k], acc[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) h2[sg + r][j] = tanhf(acc[r]);
+        }
+        __syncthreads();
+        // output layer
+        if (t < kTF * kO) {
+            const int s = t / kO, c = t % kO;
+            float a = B3[c];
+            for (int k = 0; k < kH; ++k) a = fmaf(W3[k * kO + c], h2[s][k], a);
+            o[s][c] = a;
+        }
+        __syncthreads();
+        if (SAVE) {
+            for (int idx = t; idx < kTF * (2 * kH + 16); idx += 256) {
+                const int s = idx / (2 * kH + 16), r = idx % (2 * kH + 16);
+                if (s0 + s >= n) continue;
+                float v;
+                if (r < kH)
+                    v = h1[s][r];
+                else if (r < 2 * kH)
+                    v = h2[s][r - kH];
+                else
+                    v = (r - 2 * kH < kO) ? o[s][r - 2 * kH] : 0.0f;
+                saved[((s0 + s) * kLayers + layer) * kSave + 8 + r] = v;
+            }
+        }
+        // coupling update
+        if (t < kTF * kD) {
+            const int s = t / kD, d = t % kD;
+            if (!cond_dim(layer, d)) {
+                const float svv = kSC * tanhf(o[s][d] / kSC);
+                const float tt = o[s][kD + d];
+                y[s][d] = INV ? (y[s][d] - tt) * expf(-svv) : fmaf(y[s][d], expf(svv), tt);
+                sv[s][d] += svv;
+            }
+        }
+        __syncthreads();
+    }
+    if (t < kTF) {
+        const int s = t;
+        if (s0 + s < n) {
+            double lq = 0.0;
+            for (int d = 0; d < kD; ++d) {
+                const double z = INV ? static_cast<double>(in[(s0 + s) * kD + d]) : static_cast<double>(y[s][d]);
+                lq += -0.5 * z * z - static_cast<double>(kHalfLog2Pi) + static_cast<double>(sv[s][d]) +
+                      log(static_cast<double>(isd[d]));
+            }
+            logq[s0 + s] = lq;
+        }
+    }
+    if (t < kTF * kD) {
+        const int s = t / kD, d = t % kD;
+        if (s0 + s < n && out) {
+            out[(s0 + s) * kD + d] =
+                INV ? static_cast<double>(y[s][d] / isd[d] + mu[d]) : static_cast<double>(y[s][d]);
+        }
+    }
+}
+
+// Backward pass of loss = -mean(log q) over one tile of kTB samples; writes this tile's
+// weight-gradient partial sums partial[tile][P].
+__global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__ P, int64_t n,
+                                                       const double* __restrict__ z, const float* __restrict__ saved,
+                                                       float* __restrict__ partial) {
+    __shared__ float yin[kTB][8];
+    __shared__ float h1[kTB][kH];
+    __shared__ float h2[kTB][kH];
+    __shared__ float go[kTB][16];
+    __shared__ float gh[kTB][kH];
+    __shared__ float gy[kTB][8];
+    const int t = threadIdx.x;
+    const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kTB;
+    float* gp = partial + static_cast<int64_t>(blockIdx.x) * kP;
+    const float invB = 1.0f / static_cast<float>(n);
+    if (t < kTB * 8) {
+        const int s = t / 8, d = t % 8;
+        gy[s][d] = (d < kD && s0 + s < n) ? static_cast<float>(z[(s0 + s) * kD + d]) * invB : 0.0f;
+    }
+    for (int i = t; i < 2 * kD; i += 256) gp[kOffStd + i] = 0.0f;
+    __syncthreads();
+    for (int layer = kLayers - 1; layer >= 0; --layer) {
+        const float* W1 = P + layer * kLayerP + kOffW1;
+        const float* W2 = P + layer * kLayerP + kOffW2;
+        const float* W3 = P + layer * kLayerP + kOffW3;
+        float* G = gp + layer * kLayerP;
+        // load the saved activations of this layer
+        for (int idx = t; idx < kTB * kSave; idx += 256) {
+            const int s = idx / kSave, r = idx % kSave;
+            const float v = (s0 + s < n) ? saved[((s0 + s) * kLayers + layer) * kSave + r] : 0.0f;
+            if (r < 8)
+                yin[s][r] = v;
+            else if (r < 8 + kH)
+                h1[s][r - 8] = v;
+            else if (r < 8 + 2 * kH)
+                h2[s][r - 8 - kH] = v;
+            else
+                go[s][r - 8 - 2 * kH] = v;   // o for now
+        }
+        __syncthreads();
+        // coupling backward: go <- d loss / d o, gy <- direct part of d loss / d y_in
+        if (t < kTB * kD) {
+            const int s = t / kD, d = t % kD;
+            const bool live = s0 + s < n;
+            if (!cond_dim(layer, d)) {
+                const float svv = kSC * tanhf(go[s][d] / kSC);
+                const float e = expf(svv);
+                const float gyo = gy[s][d];
+                const float gs = live ? fmaf(gyo * yin[s][d], e, -invB) : 0.0f;
+                const float q = svv / kSC;
+                go[s][d] = gs * (1.0f - q * q);
+                go[s][kD + d] = gyo;
+                gy[s][d] = gyo * e;
+            } else {
+                go[s][d] = 0.0f;
+                go[s][kD + d] = 0.0f;
+            }
+        }
+        __syncthreads();
+        // output layer: gW3, gb3, gh2 = W3 go
+        for (int idx = t; idx < kH * kO + kO; idx += 256) {
+            float a = 0.0f;
+            if (idx < kH * kO) {
+                const int k = idx / kO, c = idx % kO;
+                for (int s = 0; s < kTB; ++s) a = fmaf(h2[s][k], go[s][c], a);
+                G[kOffW3 + idx] = a;
+            } else {
+                const int c = idx - kH * kO;
+                for (int s = 0; s < kTB; ++s) a += go[s][c];
+                G[kOffB3 + c] = a;
+            }
+        }
+        for (int idx = t; idx < kTB * kH; idx += 256) {
+            const int s = idx / kH, k = idx % kH;
+            float a = 0.0f;
+#pragma unroll
+            for (int c = 0; c < kO; ++c) a = fmaf(W3[k * kO + c], go[s][c], a);
+            gh[s][k] = a * (1.0f - h2[s][k] * h2[s][k]);   // d loss / d a2
+        }
+        __syncthreads();
+        // hidden layer 2: gW2[k][j] = sum_s h1[s][k] ga2[s][j], gb2, then gh1 = W2 ga2
+        for (int idx = t; idx < kH * kH; idx += 256) {
+            const int k = idx / kH, j = idx % kH;
+            float a = 0.0f;
+            for (int s = 0; s < kTB; ++s) a = fmaf(h1[s][k], gh[s][j], a);
+            G[kOffW2 + idx] = a;
+        }
+        if (t < kH) {
+            float a = 0.0f;
+            for (int s = 0; s < kTB; ++s) a += gh[s][t];
+            G[kOffB2 + t] = a;
+        }
+        // gh1 into h2's storage (h2 no longer needed): thread -> row k, 16 samples
+        {
+            const int k = t % kH, sg = (t / kH) * (kTB / 2);
+            float acc[kTB / 2];
+#pragma unroll
+            for (int r = 0; r < kTB / 2; ++r) acc[r] = 0.0f;
+            for (int j = 0; j < kH; ++j) {
+                const float w = W2[k * kH + j];
+#pragma unroll
+                for (int r = 0; r < kTB / 2; ++r) acc[r] = fmaf(w, gh[sg + r][j], acc[r]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kTB / 2; ++r) h2[sg + r][k] = acc[r] * (1.0f - h1[sg + r][k] * h1[sg + r][k]);
+        }
+        __syncthreads();
+        // hidden layer 1 (ga1 in h2): gW1[d][j] = sum_s in[s][d] ga1[s][j], gb1, gin = W1 ga1
+        for (int idx = t; idx < kD * kH + kH; idx += 256) {
+            float a = 0.0f;
+            if (idx < kD * kH) {
+                const int d = idx / kH, j = idx % kH;
+                if (cond_dim(layer, d))
+                    for (int s = 0; s < kTB; ++s) a = fmaf(yin[s][d], h2[s][j], a);
+                G[kOffW1 + idx] = a;
+            } else {
+                const int j = idx - kD * kH;
+                for (int s = 0; s < kTB; ++s) a += h2[s][j];
+                G[kOffB1 + j] = a;
+            }
+        }
+        if (t < kTB * kD) {
+            const int s = t / kD, d = t % kD;
+            if (cond_dim(layer, d)) {
+                float a = 0.0f;
+                for (int j = 0; j < kH; ++j) a = fmaf(W1[d * kH + j], h2[s][j], a);
+                gy[s][d] += a;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_grad_reduce(const float* __restrict__ partial, int tiles, float* __restrict__ grad) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= kP) return;
+    float a = 0.0f;
+    for (int i = 0; i < tiles; ++i) a += partial[static_cast<int64_t>(i) * kP + p];
+    grad[p] = a;
+}
+
+__global__ void k_loss(const double* __restrict__ logq, int64_t n, double* __restrict__ loss) {
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) a += logq[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = -red[0] / static_cast<double>(n);
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t count, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+constexpr size_t kAl = 256;
+inline size_t al(size_t x) { return (x + kAl - 1) / kAl * kAl; }
+
+}  // namespace
+
+int64_t flow_param_count() { return kP; }
+
+size_t flow_ws_bytes(int64_t n) {
+    const size_t N = static_cast<size_t>(n);
+    const size_t tiles = (N + kTB - 1) / kTB;
+    size_t off = 0;
+    off = al(off + N * kLayers * kSave * sizeof(float));   // saved activations
+    off = al(off + N * kD * sizeof(double));               // z
+    off = al(off + N * sizeof(double));                    // log q
+    off = al(off + tiles * kP * sizeof(float));            // gradient partials
+    return off;
+}
+
+int flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, hipStream_t s) {
+    const unsigned blocks = static_cast<unsigned>((n + kTF - 1) / kTF);
+    hipLaunchKernelGGL((k_flow<false, false>), dim3(blocks), dim3(256), 0, s, params, x, n, z, logq, nullptr);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+int flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, hipStream_t s) {
+    const unsigned blocks = static_cast<unsigned>((n + kTF - 1) / kTF);
+    hipLaunchKernelGGL((k_flow<true, false>), dim3(blocks), dim3(256), 0, s, params, z, n, x, logq, nullptr);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+int flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss, void* ws,
+                   hipStream_t s) {
+    const size_t N = static_cast<size_t>(n);
+    char* base = static_cast<char*>(ws);
+    size_t off = 0;
+    float* saved = reinterpret_cast<float*>(base + off);
+    off = al(off + N * kLayers * kSave * sizeof(float));
+    double* z = reinterpret_cast<double*>(base + off);
+    off = al(off + N * kD * sizeof(double));
+    double* lq = reinterpret_cast<double*>(base + off);
+    off = al(off + N * sizeof(double));
+    float* partial = reinterpret_cast<float*>(base + off);
+    const unsigned fblocks = static_cast<unsigned>((n + kTF - 1) / kTF);
+    const int tiles = static_cast<int>((n + kTB - 1) / kTB);
+    hipLaunchKernelGGL((k_flow<false, true>), dim3(fblocks), dim3(256), 0, s, params, x, n, z, lq, saved);
+    hipLaunchKernelGGL(k_flow_backward, dim3(tiles), dim3(256), 0, s, params, n, z, saved, partial);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((kP + 255) / 256), dim3(256), 0, s, partial, tiles, grad);
+    if (loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, lq, n, loss);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+int adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr, double b1, double b2,
+              double eps, int64_t t, hipStream_t s) {
+    const float c1 = static_cast<float>(1.0 - std::pow(b1, static_cast<double>(t)));
+    const float c2 = static_cast<float>(1.0 - std::pow(b2, static_cast<double>(t)));
+    hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, params, grad, m, v,
+                       count, static_cast<float>(lr), static_cast<float>(b1), static_cast<float>(b2),
+                       static_cast<float>(eps), c1, c2);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+}  // namespace pd

@@ -46,7 +46,17 @@ int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double*
 int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
              const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
              void* ws, hipStream_t s);
-int independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp, const double* logp_p,
-                    const double* logq_p, const double* u, int32_t* accepted, hipStream_t s);
+int independence_mh(int64_t n, double* x, double* logp, double* logq, double* grad, const double* xp,
+                    const double* logp_p, const double* logq_p, const double* grad_p, const double* u,
+                    int32_t* accepted, hipStream_t s);
+
+int64_t flow_param_count();
+size_t flow_ws_bytes(int64_t n);
+int flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, hipStream_t s);
+int flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, hipStream_t s);
+int flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss, void* ws,
+                   hipStream_t s);
+int adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr, double b1, double b2,
+              double eps, int64_t t, hipStream_t s);
 
 }  // namespace pd

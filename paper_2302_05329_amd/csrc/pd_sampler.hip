@@ -137,15 +137,17 @@ __global__ void k_hmc_accept(int64_t n, HmcArgs a, const double* __restrict__ u,
 
 // Independence Metropolis-Hastings: accept x' ~ q with prob min(1, pi(x') q(x) / (pi(x) q(x'))).
 __global__ void k_imh(int64_t n, double* __restrict__ x, double* __restrict__ logp, double* __restrict__ logq,
-                      const double* __restrict__ xp, const double* __restrict__ logp_p,
-                      const double* __restrict__ logq_p, const double* __restrict__ u,
-                      int32_t* __restrict__ accepted) {
+                      double* __restrict__ grad, const double* __restrict__ xp, const double* __restrict__ logp_p,
+                      const double* __restrict__ logq_p, const double* __restrict__ grad_p,
+                      const double* __restrict__ u, int32_t* __restrict__ accepted) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double la = (logp_p[i] - logp[i]) + (logq[i] - logq_p[i]);
     const bool acc = isfinite(logp_p[i]) && isfinite(logq_p[i]) && (log(u[i]) < la || !isfinite(logp[i]));
     if (acc) {
         for (int j = 0; j < 7; ++j) x[i * 7 + j] = xp[i * 7 + j];
+        if (grad)
+            for (int j = 0; j < 7; ++j) grad[i * 7 + j] = grad_p[i * 7 + j];
         logp[i] = logp_p[i];
         logq[i] = logq_p[i];
     }
@@ -298,10 +300,11 @@ int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, doubl
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
 }
 
-int independence_mh(int64_t n, double* x, double* logp, double* logq, const double* xp, const double* logp_p,
-                    const double* logq_p, const double* u, int32_t* accepted, hipStream_t s) {
-    hipLaunchKernelGGL(k_imh, dim3(nblk(n, 128)), dim3(128), 0, s, n, x, logp, logq, xp, logp_p, logq_p, u,
-                       accepted);
+int independence_mh(int64_t n, double* x, double* logp, double* logq, double* grad, const double* xp,
+                    const double* logp_p, const double* logq_p, const double* grad_p, const double* u,
+                    int32_t* accepted, hipStream_t s) {
+    hipLaunchKernelGGL(k_imh, dim3(nblk(n, 128)), dim3(128), 0, s, n, x, logp, logq, grad, xp, logp_p, logq_p,
+                       grad_p, u, accepted);
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
 }
 

@@ -98,14 +98,20 @@ class HMC:
         return self.accepted
 
 
-def independence_mh(x, lp, lq, xp, lp_p, lq_p, u, accepted=None):
-    """In-place accept of proposals xp for the chains x (all device tensors)."""
+def independence_mh(x, lp, lq, xp, lp_p, lq_p, u, accepted=None, grad=None, grad_p=None):
+    """In-place accept of proposals xp for the chains x (all device tensors); grad / grad_p, if
+    given, are carried along with the state."""
     n = x.shape[0]
-    for t, shape in ((x, (n, 7)), (lp, (n,)), (lq, (n,)), (xp, (n, 7)), (lp_p, (n,)), (lq_p, (n,)), (u, (n,))):
-        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous():
+    if (grad is None) != (grad_p is None):
+        raise ValueError("independence_mh: give both grad and grad_p or neither")
+    checks = [(x, (n, 7)), (lp, (n,)), (lq, (n,)), (xp, (n, 7)), (lp_p, (n,)), (lq_p, (n,)), (u, (n,))]
+    if grad is not None:
+        checks += [(grad, (n, 7)), (grad_p, (n, 7))]
+    for t, shape in checks:
+        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
             raise ValueError("independence_mh: bad tensor")
     if accepted is None:
         accepted = torch.empty(n, dtype=torch.int32, device="cuda")
-    L.check(L.lib().pd_independence_mh(n, _ptr(x), _ptr(lp), _ptr(lq), _ptr(xp), _ptr(lp_p), _ptr(lq_p), _ptr(u),
-                                       _ptr(accepted), _stream()))
+    L.check(L.lib().pd_independence_mh(n, _ptr(x), _ptr(lp), _ptr(lq), _ptr(grad), _ptr(xp), _ptr(lp_p), _ptr(lq_p),
+                                       _ptr(grad_p), _ptr(u), _ptr(accepted), _stream()))
     return accepted

@@ -213,3 +213,46 @@ def config5(seed=1005):
 def paper_timing_grid():
     """The paper's waveform-timing grid: 24-512 Hz, df = 0.2 Hz (2441 bins)."""
     return Grid(24.0, 0.2, 2441, f_min=24.0, f_ref=24.0)
+
+
+# ----------------------------------------------------------------------------------
+# Learned-proposal flow: random parameter vectors in the RealNVP layout (8 layers of
+# W1[7][128] b1[128] W2[128][128] b2[128] W3[128][14] b3[14], then mu[7], isd[7]).
+# ----------------------------------------------------------------------------------
+FLOW_DIM, FLOW_HIDDEN, FLOW_OUT, FLOW_LAYERS = 7, 128, 14, 8
+
+
+def flow_init_params(seed, mu=None, sd=None, out_scale=0.0, bias_scale=0.0):
+    """float32 parameters: hidden weights ~ N(0, 1/fan_in), output weights ~ N(0, out_scale^2/128)
+    (0 gives the identity map after standardisation, the usual start of training), biases
+    ~ N(0, bias_scale^2); standardisation mu, isd = 1/sd."""
+    rng = _rng(seed)
+    d, h, o = FLOW_DIM, FLOW_HIDDEN, FLOW_OUT
+    parts = []
+    for _ in range(FLOW_LAYERS):
+        parts += [rng.standard_normal(d * h) / np.sqrt(d), bias_scale * rng.standard_normal(h),
+                  rng.standard_normal(h * h) / np.sqrt(h), bias_scale * rng.standard_normal(h),
+                  out_scale * rng.standard_normal(h * o) / np.sqrt(h), bias_scale * rng.standard_normal(o)]
+    mu = np.zeros(d) if mu is None else np.asarray(mu, dtype=np.float64)
+    sd = np.ones(d) if sd is None else np.asarray(sd, dtype=np.float64)
+    parts += [mu, 1.0 / sd]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def correlated_gaussian(n, seed, dim=7, rho=0.45):
+    """n draws of a dim-D Gaussian with unequal scales and a banded correlation (mean, cov, draws)."""
+    rng = _rng(seed)
+    mean = rng.uniform(-2.0, 2.0, dim)
+    scale = np.exp(rng.uniform(-1.5, 1.0, dim))
+    corr = np.eye(dim) + rho * (np.eye(dim, k=1) + np.eye(dim, k=-1))
+    cov = corr * np.outer(scale, scale)
+    x = rng.multivariate_normal(mean, cov, size=n)
+    return mean, cov, x
+
+
+def banana(n, seed, dim=7, b=0.5):
+    """n draws of a curved ('banana') density: x1 += b (x0^2 - 1) on a standard Gaussian."""
+    rng = _rng(seed)
+    x = rng.standard_normal((n, dim))
+    x[:, 1] += b * (x[:, 0] ** 2 - 1.0)
+    return x

@@ -133,10 +133,14 @@ def test_independence_mh_matches_rule(gpu):
     lqp = rng.normal(-5, 2, n)
     lpp[:10] = -np.inf
     u = rng.uniform(size=n)
-    t = [torch.as_tensor(a, device="cuda").contiguous() for a in (x, lp, lq, xp, lpp, lqp, u)]
+    g = rng.standard_normal((n, 7))
+    gp = rng.standard_normal((n, 7))
+    t = [torch.as_tensor(a, device="cuda").contiguous() for a in (x, lp, lq, xp, lpp, lqp, u, g, gp)]
     _say("independence MH n=1000")
-    acc = sampling.independence_mh(*t).cpu().numpy()
+    acc = sampling.independence_mh(*t[:7], grad=t[7], grad_p=t[8]).cpu().numpy()
+    xs, lps, lqs, gs = (t[i].cpu().numpy() for i in (0, 1, 2, 7))
     for i in range(n):
         xr, lpr, lqr, ar = S.independence_mh(x[i], lp[i], lq[i], xp[i], lpp[i], lqp[i], u[i])
         assert acc[i] == ar
-        assert np.array_equal(t[0][i].cpu().numpy(), xr)
+        assert np.array_equal(xs[i], xr) and lps[i] == lpr and lqs[i] == lqr
+        assert np.array_equal(gs[i], gp[i] if ar else g[i])
