@@ -44,6 +44,37 @@ def timed_calls(fn, iters, warmup):
     return (time.perf_counter() - t0) / iters
 
 
+HOT_SOURCES = ["pd_kernels.hip", "pd_bin.h", "pd_math.h", "pd_model.h", "pd_dual.h", "pd_launch.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_loglike_moments_c2_hbm_counters.txt")
+
+
+def hot_source_hash():
+    """sha256 over the sources the fused likelihood kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in HOT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2302_05329_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per call of the fused pass from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    kv = dict(l.split(":", 1) for l in lines if ":" in l and not l.startswith("#"))
+    if kv.get("source_sha256", "").strip() != hot_source_hash():
+        return None
+    try:
+        return int(kv["traffic_bytes_per_call"].strip())
+    except (KeyError, ValueError):
+        return None
+
+
 def kernel_avg_ms(api, kid):
     ms, cnt = api.profile_read(kid)
     return (ms / cnt) if cnt else float("nan"), cnt
@@ -57,6 +88,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one plain 1 GiB device-to-device copy (the reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
@@ -65,6 +98,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = 1 << 27
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8}), flush=True)
+        return
     from paper_2302_05329_amd import api, flops, workloads as W
     from paper_2302_05329_amd import _lib as L
 
@@ -111,8 +153,8 @@ def main():
     fl, units = flops.batch_flops("loglike_grad", trans2, g2.as_tuple())
     achieved_tf = fl / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "k_loglike_moments<1>", "kernel_ms": round(kms, 4), "launches": kcnt,
+                "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4), "traffic": recorded_traffic(),
+                "kernel": "k_loglike_moments<1,1|2|3> (one fused pass, three phase-region launches)", "kernel_ms": round(kms, 4), "launches": kcnt,
                 "flops_per_launch": fl, "active_units": units, "flops_per_unit": round(fl / units, 2)}
     log(f"[bench] C2 lnL+grad: {value:.4g} evals/s, {ms_per_step:.3f} ms/step, kernel {kms:.3f} ms, "
         f"{achieved_tf:.2f} TFLOP/s algorithmic")
@@ -213,6 +255,21 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
                                                            ("adjoint", L.PD_K_MISMATCH_ADJ))}
     extra["C4_mismatch_grad"] = {"targets_per_s": th4.shape[0] / t, "ms": 1e3 * t, "kernel_ms": ks}
     api.profile_enable(False)
+
+    # learned proposal, C5: 4096 chains on one SNR-20 injection, 8033 bins
+    from paper_2302_05329_amd import learned_proposal as LP
+    log("[bench] C5 flow-MH vs HMC")
+    r = LP.compare(lam, n_chains=4096, log=log)
+    extra["C5_flow_mh_vs_hmc"] = {
+        "ess_per_s_hmc": r["hmc"]["ess_per_s"], "ess_per_s_flow_mh": r["flow_hmc"]["ess_per_s"],
+        "ess_per_s_flow_mh_incl_training": r["flow_hmc"]["ess_per_s_incl_training"],
+        "speedup": r["flow_hmc"]["ess_per_s"] / r["hmc"]["ess_per_s"],
+        "speedup_incl_training": r["flow_hmc"]["ess_per_s_incl_training"] / r["hmc"]["ess_per_s"],
+        "min_ess_hmc": r["hmc"]["ess"], "min_ess_flow_mh": r["flow_hmc"]["ess"],
+        "acceptance_hmc": r["hmc"]["acceptance"], "acceptance_flow_mh": r["flow_hmc"]["acceptance_flow"],
+        "max_mean_diff_sigma": max(r["mean_diff_sigma"]), "max_std_diff_sigma": max(r["std_diff_sigma"]),
+        "chains": r["n_chains"], "steps": r["steps"], "n_leapfrog": r["n_leapfrog"],
+        "training_phase_s": r["flow_hmc"]["training_phase_seconds"]}
     return extra
 
 
@@ -224,7 +281,7 @@ def cpu_baseline(W, c2, seconds):
     lam = W.load_lambda()
     t0 = time.perf_counter()
     n = 0
-    while n < 512 and (time.perf_counter() - t0) < seconds:
+    while n < 4096 and (time.perf_counter() - t0) < seconds:
         O.loglike(th[n], O.PARAM_M1M2, lam, g, data, ip)
         O.loglike_grad(th[n], O.PARAM_M1M2, lam, g, data, ip)
         n += 1

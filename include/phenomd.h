@@ -176,7 +176,9 @@ typedef struct {
     const double* lambda;     /* GW: [209] device */
     const double* data;       /* GW: [n_bins][2] device */
     const double* inv_psd;    /* GW: [n_bins] device */
-    double lo[6], hi[6];      /* GW: prior bounds of (Mc, q, chi1, chi2, D, tc); 0 < q <= 1 */
+    double lo[7], hi[7];      /* GW: prior bounds of (Mc, q, chi1, chi2, D, tc, phic); 0 < q <= 1.
+                                 The likelihood has period pi in phic, so a phic interval of
+                                 length pi is the whole circle. */
     double mu[7], isig2[7];   /* GAUSS: means and inverse variances */
 } pd_posterior;
 
@@ -242,6 +244,14 @@ int pd_flow_loss_grad(const float* params, const double* x, int64_t n, float* gr
 /* Adam (Kingma & Ba 2015) on count float32 parameters, step t >= 1 (bias-corrected). */
 int pd_adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr,
                  double beta1, double beta2, double eps, int64_t t, void* stream);
+
+/* Diagnostic: the kernels' own FP64 elementary functions applied elementwise, out[i] = fn(x[i])
+ * for x [n], out [n] (device).  fn: PD_FN_SIN, PD_FN_COS (one shared argument reduction,
+ * Cody-Waite with a three-part pi/2), PD_FN_ATAN, PD_FN_EXP, PD_FN_RCP (hardware estimate +
+ * two Newton steps).  Exposed so that their ulp error can be measured against a
+ * high-precision reference. */
+typedef enum { PD_FN_SIN = 0, PD_FN_COS = 1, PD_FN_ATAN = 2, PD_FN_EXP = 3, PD_FN_RCP = 4 } pd_fn;
+int pd_elementary_eval(int fn, const double* x, int64_t n, double* out, void* stream);
 
 /* Text of the last batch-level error on the calling thread (library-owned, never NULL). */
 const char* pd_last_error(void);

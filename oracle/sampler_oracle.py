@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY: used by the tests (and nothing in the product path).
 
 Sec. 3.3 of the paper samples the 7-parameter posterior with Hamiltonian Monte Carlo
 (leapfrog, hand-tuned diagonal mass matrix, Metropolis accept).  Here:
-  * coordinates: theta_i = lo_i + (hi_i - lo_i) sigmoid(x_i) for the six bounded
-    parameters (Mc, q, chi1, chi2, D, tc), phic = x_6; log pi(x) = lnL(theta(x)) +
-    log|d theta / d x| (uniform priors);
+  * coordinates: theta_i = lo_i + (hi_i - lo_i) sigmoid(x_i) for all seven parameters
+    (Mc, q, chi1, chi2, D, tc, phic) under uniform priors; phic enters the strain as
+    exp(2 i phic), so an interval of length pi is one whole period of the likelihood;
+    log pi(x) = lnL(theta(x)) + log|d theta / d x|;
   * HMC (Neal 2011): p = sqrt(m) xi, H = -log pi(x) + p^2/(2m) summed, leapfrog with a half
     kick at each end, accept if log u < -(H_end - H_start); non-finite or |dH| > 1000 is
     rejected as divergent;
@@ -33,7 +34,7 @@ def transform(x, lo, hi):
     d = np.ones(7)
     dl = np.zeros(7)
     lj = 0.0
-    for j in range(6):
+    for j in range(7):
         s = sigmoid(x[j])
         w = hi[j] - lo[j]
         theta[j] = lo[j] + w * s

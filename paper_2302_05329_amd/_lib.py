@@ -16,6 +16,8 @@ PD_EHIP = -3
 PD_ENOMEM = -4
 PD_EUNSUPPORTED = -5
 
+PD_FN_SIN, PD_FN_COS, PD_FN_ATAN, PD_FN_EXP, PD_FN_RCP = 0, 1, 2, 3, 4
+
 PD_FP64 = 0
 PD_MIXED = 1
 
@@ -50,7 +52,7 @@ PD_TARGET_GAUSS = 1
 
 class PdPosterior(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("grid", PdGrid), ("lam", ctypes.c_void_p), ("data", ctypes.c_void_p),
-                ("inv_psd", ctypes.c_void_p), ("lo", ctypes.c_double * 6), ("hi", ctypes.c_double * 6),
+                ("inv_psd", ctypes.c_void_p), ("lo", ctypes.c_double * 7), ("hi", ctypes.c_double * 7),
                 ("mu", ctypes.c_double * 7), ("isig2", ctypes.c_double * 7)]
 
 
@@ -79,6 +81,7 @@ SIGNATURES = {
     "pd_hmc_step": (_INT, [ctypes.c_void_p, _I64, _P, _P, _P, _P, _P, _INT, ctypes.c_double,
                            ctypes.POINTER(ctypes.c_double), _P, _P, _P, _SZ, _P]),
     "pd_independence_mh": (_INT, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pd_elementary_eval": (_INT, [_INT, _P, _I64, _P, _P]),
     "pd_flow_param_count": (_I64, []),
     "pd_flow_workspace_bytes": (_SZ, [_I64]),
     "pd_flow_forward": (_INT, [_P, _P, _I64, _P, _P, _P]),

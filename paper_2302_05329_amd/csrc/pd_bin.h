@@ -82,11 +82,13 @@ __device__ __forceinline__ void active_range(double ms, const GridArgs& g, int64
 // Wave-uniform copy of a value every lane already agrees on (bin indices fit in 32 bits).
 __device__ __forceinline__ int uniform_i(int64_t x) { return __builtin_amdgcn_readfirstlane(static_cast<int>(x)); }
 
-// Region segments of [kb, ke) (already inside the active range).
+// Region segments of [kb, ke) (already inside the active range): segment i is
+// [k[i], k[i+1]) (possibly empty) with phase region pr[i] and amplitude region ar[i].  Every
+// index is a compile-time constant after unrolling and every value is wave-uniform (read
+// from lane 0), so the struct lives in scalar registers.
 struct Segs {
-    int64_t k[6];
+    int k[6];
     int pr[5], ar[5];
-    int n;
 };
 
 __device__ __forceinline__ void make_segments(const double* __restrict__ rec, const GridArgs& g, int64_t kb,
@@ -109,17 +111,15 @@ __device__ __forceinline__ void make_segments(const double* __restrict__ rec, co
     }
     PD_SW(0, 1) PD_SW(2, 3) PD_SW(0, 2) PD_SW(1, 3) PD_SW(1, 2)
 #undef PD_SW
-    int64_t pts[6] = {kb, b[0], b[1], b[2], b[3], ke};
-    S.n = 0;
+    S.k[0] = uniform_i(kb);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.k[i + 1] = uniform_i(b[i]);
+    S.k[5] = uniform_i(ke);
+#pragma unroll
     for (int i = 0; i < 5; ++i) {
-        const int64_t s = pts[i], e = pts[i + 1];
-        if (e <= s) continue;
-        const double mf = ms * bin_freq(g, s);
-        S.k[S.n] = s;
-        S.k[S.n + 1] = e;
-        S.pr[S.n] = (mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3);
-        S.ar[S.n] = (mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3);
-        ++S.n;
+        const double mf = ms * bin_freq(g, static_cast<int64_t>(S.k[i]));
+        S.pr[i] = uniform_i((mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3));
+        S.ar[i] = uniform_i((mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3));
     }
 }
 

@@ -370,6 +370,15 @@ int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, double*
     return PD_OK;
 }
 
+int pd_elementary_eval(int fn, const double* x, int64_t n, double* out, void* stream) {
+    if (!x || !out) return fail(PD_EINVAL, "NULL argument");
+    if (fn < PD_FN_SIN || fn > PD_FN_RCP) return fail(PD_EINVAL, "unknown function");
+    if (n <= 0 || n > (int64_t(1) << 31)) return fail(PD_EINVAL, "bad n");
+    if (pd::launch_elementary(fn, x, n, out, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(PD_EHIP, "launch failed");
+    return PD_OK;
+}
+
 int64_t pd_flow_param_count(void) { return pd::flow_param_count(); }
 
 size_t pd_flow_workspace_bytes(int64_t n) { return n > 0 ? pd::flow_ws_bytes(n) : 0; }

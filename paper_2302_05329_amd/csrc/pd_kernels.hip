@@ -70,33 +70,39 @@ __global__ void __launch_bounds__(128) k_setup_value(const double* __restrict__ 
 }
 
 // Record tangents along the 7 entries of theta.  The four intrinsic entries (masses or
-// chirp mass and mass ratio, two spins) go through the setup in forward mode (Dual<4>);
-// the extrinsic ones enter the record in closed form: D (or ln D) only through ln A0,
-// tc only through the Mf-linear phase coefficient (2 pi tc / Ms), phic only through the
-// constant phase term (-2 phic).
+// chirp mass and mass ratio, two spins) go through the setup in forward mode, one thread per
+// (point, direction) with a single tangent (Dual<1>) so the live state stays small; the
+// extrinsic ones enter the record in closed form: D (or ln D) only through ln A0, tc only
+// through the Mf-linear phase coefficient (2 pi tc / Ms), phic only through the constant
+// phase term (-2 phic).  Thread (point, 0) also writes the three extrinsic rows.
 __global__ void __launch_bounds__(64) k_setup_theta_tangent(const double* __restrict__ theta, int64_t n,
                                                             int param, double f_ref,
                                                             const double* __restrict__ lam,
                                                             const double* __restrict__ recs,
                                                             double* __restrict__ tans) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * 4) return;
+    const int64_t i = t >> 2;
+    const int dir = static_cast<int>(t & 3);
     double* out = tans + i * 7 * REC_N;
-    for (int j = 0; j < 7 * REC_N; ++j) out[j] = 0.0;
-    if (recs[i * REC_N + R_VALID] == 0.0) return;
-    using D = Dual<4>;
-    D th[7];
-    for (int j = 0; j < 7; ++j) {
-        th[j] = dconst<4>(theta[i * 7 + j]);
-        if (j < 4) th[j].d[j] = 1.0;
+    const bool valid = recs[i * REC_N + R_VALID] != 0.0;
+    if (dir == 0)
+        for (int j = 4 * REC_N; j < 7 * REC_N; ++j) out[j] = 0.0;
+    if (!valid) {
+        for (int j = 0; j < REC_N; ++j) out[dir * REC_N + j] = 0.0;
+        return;
     }
+    using D = Dual<1>;
+    D th[7];
+    for (int j = 0; j < 7; ++j) th[j] = dconst<1>(theta[i * 7 + j]);
+    th[dir].d[0] = 1.0;
     const Source<D> s = source_map(th, param);
     D fit[kNumFit];
     fit_params(lam, s.eta, s.chi_pn, fit);
     D rec[REC_N];
     build_record(s, fit, f_ref, rec);
-    for (int p = 0; p < 4; ++p)
-        for (int j = 0; j < REC_N; ++j) out[p * REC_N + j] = rec[j].d[p];
+    for (int j = 0; j < REC_N; ++j) out[dir * REC_N + j] = rec[j].d[0];
+    if (dir != 0) return;
     const double ms = rec[R_MS].v;
     out[4 * REC_N + R_LNA0] = (param == 1) ? -1.0 : -1.0 / theta[i * 7 + 4];
     const double dlin = 2.0 * kPi / ms;
@@ -293,7 +299,7 @@ __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restric
     LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, 0, 0, lane, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        if (i < S.n && uniform_i(S.pr[i]) == PRG) {
+        if (uniform_i(S.k[i + 1]) > uniform_i(S.k[i]) && uniform_i(S.pr[i]) == PRG) {
             seg.k0 = uniform_i(S.k[i]);
             seg.k1 = uniform_i(S.k[i + 1]);
             dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);
@@ -449,7 +455,7 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
     for (int s = 0; s < 28; ++s) seg.F[s] = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        if (i < S.n && uniform_i(S.pr[i]) == PRG) {
+        if (uniform_i(S.k[i + 1]) > uniform_i(S.k[i]) && uniform_i(S.pr[i]) == PRG) {
             seg.k0 = uniform_i(S.k[i]);
             seg.k1 = uniform_i(S.k[i + 1]);
             dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);
@@ -513,7 +519,7 @@ hipError_t launch_setup_value(const double* theta, int64_t n, int param, double 
 
 hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param, double f_ref,
                                       const double* lam, const double* recs, double* tans, hipStream_t s) {
-    hipLaunchKernelGGL(k_setup_theta_tangent, dim3(blocks_for(n, 64)), dim3(64), 0, s, theta, n, param, f_ref,
+    hipLaunchKernelGGL(k_setup_theta_tangent, dim3(blocks_for(4 * n, 64)), dim3(64), 0, s, theta, n, param, f_ref,
                        lam, recs, tans);
     return hipGetLastError();
 }
@@ -584,6 +590,30 @@ hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int 
                            g, tab, partial);
     }
     hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks, partial, F);
+    return hipGetLastError();
+}
+
+__global__ void k_elementary(int fn, const double* __restrict__ x, int64_t n, double* __restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = x[i];
+    double r;
+    if (fn == PD_FN_SIN || fn == PD_FN_COS) {
+        double sn, cs;
+        pd_sincos(v, &sn, &cs);
+        r = (fn == PD_FN_SIN) ? sn : cs;
+    } else if (fn == PD_FN_ATAN) {
+        r = pd_atan(v);
+    } else if (fn == PD_FN_EXP) {
+        r = pd_exp(v);
+    } else {
+        r = pd_rcp(v);
+    }
+    out[i] = r;
+}
+
+hipError_t launch_elementary(int fn, const double* x, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_elementary, dim3(blocks_for(n, 256)), dim3(256), 0, s, fn, x, n, out);
     return hipGetLastError();
 }
 

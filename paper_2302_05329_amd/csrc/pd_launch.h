@@ -50,6 +50,8 @@ int independence_mh(int64_t n, double* x, double* logp, double* logq, double* gr
                     const double* logp_p, const double* logq_p, const double* grad_p, const double* u,
                     int32_t* accepted, hipStream_t s);
 
+hipError_t launch_elementary(int fn, const double* x, int64_t n, double* out, hipStream_t s);
+
 int64_t flow_param_count();
 size_t flow_ws_bytes(int64_t n);
 int flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, hipStream_t s);

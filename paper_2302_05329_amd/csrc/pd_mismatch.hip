@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     make_segments(rec, g, kb, ke, S);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        if (i < S.n && uniform_i(S.pr[i]) == PRG) {
+        if (uniform_i(S.k[i + 1]) > uniform_i(S.k[i]) && uniform_i(S.pr[i]) == PRG) {
             seg.k0 = uniform_i(S.k[i]);
             seg.k1 = uniform_i(S.k[i + 1]);
             dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);

@@ -4,8 +4,8 @@
 //
 // Coordinates.  The sampler moves x in R^7.  For the gravitational-wave target the
 // source parameters are theta = (Mc, q, chi1, chi2, D, tc, phic) with
-//   theta_i = lo_i + (hi_i - lo_i) * sigmoid(x_i)   for i < 6 (bounded uniform priors),
-//   phic    = x_6                                    (the likelihood is periodic in it),
+//   theta_i = lo_i + (hi_i - lo_i) * sigmoid(x_i)   (bounded uniform priors; for phic an
+//   interval of length pi is one full period of the likelihood),
 // so log pi(x) = lnL(theta(x)) + sum_i log(dtheta_i/dx_i).  The Gaussian target
 // (independent normals) exists to test the sampler machinery against a known answer.
 //
@@ -32,7 +32,7 @@ __global__ void k_transform(const double* __restrict__ x, int64_t n, pd_posterio
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
-    for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < 7; ++j) {
         const double xv = x[i * 7 + j];
         const double s = sigmoid(xv);
         const double w = post.hi[j] - post.lo[j];
@@ -44,9 +44,6 @@ __global__ void k_transform(const double* __restrict__ x, int64_t n, pd_posterio
         acc += log(w) - ax - 2.0 * log1p(exp(-ax));
         dlj[i * 7 + j] = 1.0 - 2.0 * s;
     }
-    theta[i * 7 + 6] = x[i * 7 + 6];
-    dtdx[i * 7 + 6] = 1.0;
-    dlj[i * 7 + 6] = 0.0;
     lj[i] = acc;
 }
 
@@ -244,8 +241,8 @@ int posterior_check(const pd_posterior* post) {
     if (post->kind != PD_TARGET_GW && post->kind != PD_TARGET_GAUSS) return PD_EINVAL;
     if (post->kind == PD_TARGET_GW) {
         if (!post->lambda || !post->data || !post->inv_psd) return PD_EINVAL;
-        for (int j = 0; j < 6; ++j)
-            if (!(post->hi[j] > post->lo[j])) return PD_EINVAL;
+        for (int j = 0; j < 7; ++j)
+            if (!(post->hi[j] > post->lo[j]) || !std::isfinite(post->hi[j] - post->lo[j])) return PD_EINVAL;
         if (!(post->lo[0] > 0.0) || !(post->lo[1] > 0.0) || !(post->hi[1] <= 1.0) || !(post->lo[4] > 0.0) ||
             post->lo[2] < -1.0 || post->hi[2] > 1.0 || post->lo[3] < -1.0 || post->hi[3] > 1.0)
             return PD_EINVAL;

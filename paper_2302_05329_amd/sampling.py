@@ -31,7 +31,9 @@ class Posterior:
             self._keep += [lam, d, ip]
             st.grid = g
             st.lam, st.data, st.inv_psd = lam.data_ptr(), d.data_ptr(), ip.data_ptr()
-            for j in range(6):
+            if len(lo) != 7 or len(hi) != 7:
+                raise ValueError("lo and hi bound all 7 parameters (Mc, q, chi1, chi2, D, tc, phic)")
+            for j in range(7):
                 st.lo[j], st.hi[j] = float(lo[j]), float(hi[j])
         else:
             for j in range(7):
@@ -48,14 +50,14 @@ class Posterior:
         """theta rows (Mc, q, chi1, chi2, D, tc, phic) -> unconstrained x (inverse sigmoid)."""
         th = np.asarray(theta, dtype=np.float64)
         x = th.copy()
-        s = (th[..., :6] - self.lo) / (self.hi - self.lo)
-        x[..., :6] = np.log(s) - np.log1p(-s)
+        s = (th - self.lo) / (self.hi - self.lo)
+        x = np.log(s) - np.log1p(-s)
         return x
 
     def to_theta(self, x):
         x = np.asarray(x, dtype=np.float64)
         th = x.copy()
-        th[..., :6] = self.lo + (self.hi - self.lo) / (1.0 + np.exp(-x[..., :6]))
+        th = self.lo + (self.hi - self.lo) / (1.0 + np.exp(-x))
         return th
 
 

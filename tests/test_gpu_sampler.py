@@ -30,8 +30,8 @@ def _c5_problem(lam, n_bins=8033):
     inj[4] = snr1 / 20.0
     data = W.complex_noise(psd, grid.df, 1005) + O.waveform(inj, O.PARAM_M1M2, lam, g)
     mc_q = W.to_param(inj[None, :], O.PARAM_MC_Q)[0]
-    lo = np.array([20.0, 0.125, -0.9, -0.9, 0.2 * inj[4], -0.1])
-    hi = np.array([40.0, 1.0, 0.9, 0.9, 3.0 * inj[4], 0.1])
+    lo = np.array([20.0, 0.125, -0.9, -0.9, 0.2 * inj[4], -0.1, -0.5 * math.pi])
+    hi = np.array([40.0, 1.0, 0.9, 0.9, 3.0 * inj[4], 0.1, 0.5 * math.pi])
     return dict(grid=grid, data=data, inv_psd=1 / psd, lo=lo, hi=hi, theta_inj=mc_q)
 
 
