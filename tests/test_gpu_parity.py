@@ -93,6 +93,37 @@ def test_loglike_and_grad_parity_config2_grid(gpu, lam0):
         assert np.all(np.abs(grad[i] - gref) <= 1e-10 * scale), (i, grad[i], gref, scale)
 
 
+def test_loglike_and_grad_full_c2_sampled(gpu, lam0):
+    """The full batched-throughput workload in the benchmark's launch configuration (65536
+    points x 16225 bins, one call): sampled points against the oracle one by one -- the
+    lightest and heaviest systems, the largest and smallest |lnL|, and random ones."""
+    import torch
+    cfg = W.config2()
+    g = cfg["grid"].as_tuple()
+    data, ip = cfg["data"], cfg["inv_psd"]
+    th_all = cfg["theta"]
+    _say(f"loglike_and_grad full C2 n={len(th_all)} nb={g[2]}")
+    lnl, grad, st = gpu.api.loglike_and_grad(th_all, P, cfg["grid"], lam0, data, ip)
+    torch.cuda.synchronize()
+    lnl, grad, st = lnl.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0) and np.all(np.isfinite(lnl)) and np.all(np.isfinite(grad))
+    mt = th_all[:, 0] + th_all[:, 1]
+    rng = np.random.default_rng(2)
+    pick = {int(np.argmin(mt)), int(np.argmax(mt)), int(np.argmax(np.abs(lnl))), int(np.argmin(np.abs(lnl)))}
+    pick |= set(int(i) for i in rng.choice(len(th_all), 6, replace=False))
+    for i in sorted(pick):
+        th = th_all[i]
+        h = O.waveform(th, P, lam0, g)
+        hh = O.inner(h, h, ip, g[1])
+        ref = O.loglike(th, P, lam0, g, data, ip)
+        assert abs(lnl[i] - ref) <= 1e-10 * max(1.0, abs(ref) / 1e3, hh / 4e4), (i, lnl[i], ref)
+        gref = O.loglike_grad(th, P, lam0, g, data, ip)
+        F = O.fisher(th, P, lam0, g, ip)
+        r = data - h
+        scale = np.sqrt(O.inner(r, r, ip, g[1]) * np.diag(F))
+        assert np.all(np.abs(grad[i] - gref) <= 1e-10 * scale), (i, grad[i], gref, scale)
+
+
 @pytest.mark.parametrize("param", [O.PARAM_LNMC_ETA_LND, O.PARAM_MC_Q, O.PARAM_MC_ETA])
 def test_fisher_parity_config3_grid(gpu, lam0, param):
     import torch
