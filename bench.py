@@ -256,6 +256,30 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     extra["C4_mismatch_grad"] = {"targets_per_s": th4.shape[0] / t, "ms": 1e3 * t, "kernel_ms": ks}
     api.profile_enable(False)
 
+    # template-bank overlaps on the FP64 matrix cores: the C2 bank (ordered by total mass)
+    # against 32 seeded noise streams on the 16225-bin grid
+    c2 = W.config2()
+    rows = c2["theta"][np.argsort(c2["theta"][:, 0] + c2["theta"][:, 1])]
+    thb = torch.as_tensor(rows, device=dev)
+    psd2 = W.psd_aligo_zdhp_fit(g2.freqs())
+    streams = torch.as_tensor(np.stack([W.complex_noise(psd2, g2.df, 2000 + s) for s in range(32)]), device=dev)
+    ipb = torch.as_tensor(1.0 / psd2, device=dev)
+    wsb = api.Workspace()
+    api.profile_enable(True)
+    api.profile_read(L.PD_K_OVERLAP)
+    t = timed_calls(lambda: api.overlap(thb, P, g2, lam, streams, ipb, ws=wsb), 5, 1)
+    kms = kernel_avg_ms(api, L.PD_K_OVERLAP)[0]
+    api.profile_enable(False)
+    transb = api.transition_frequencies(thb, P, g2, lam, ws=wsb).cpu().numpy()
+    gen_fl, units_b = flops.batch_flops("waveform", transb, g2.as_tuple())
+    fl = gen_fl + units_b * (8 * 32 + 3)
+    extra["overlap_bank_fp64_mfma"] = {
+        "templates": int(thb.shape[0]), "streams": 32, "n_bins": g2.n_bins,
+        "template_stream_pairs_per_s": thb.shape[0] * 32 / t, "ms": 1e3 * t, "kernel_ms": kms,
+        "active_template_bins": units_b, "flops_per_call": fl,
+        "roofline": {"bound": "mfma", "achieved": round(fl / (kms * 1e-3) / 1e12, 3), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(fl / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}}
+
     # learned proposal, C5: 4096 chains on one SNR-20 injection, 8033 bins
     from paper_2302_05329_amd import learned_proposal as LP
     log("[bench] C5 flow-MH vs HMC")

@@ -153,7 +153,8 @@ enum {
     PD_K_MISMATCH_INPUT = 4,  /* overlap input (model per bin) */
     PD_K_MISMATCH_FFT = 5,    /* both FFT passes with the fused arg-max */
     PD_K_MISMATCH_ADJ = 6,    /* mismatch adjoint moments */
-    PD_K_COUNT = 7
+    PD_K_OVERLAP = 7,         /* template-bank overlap GEMM (generation + FP64 MFMA) */
+    PD_K_COUNT = 8
 };
 int pd_profile_enable(int on);
 int pd_profile_read(int kernel, double* total_ms, int64_t* launches);
@@ -244,6 +245,24 @@ int pd_flow_loss_grad(const float* params, const double* x, int64_t n, float* gr
 /* Adam (Kingma & Ba 2015) on count float32 parameters, step t >= 1 (bias-corrected). */
 int pd_adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr,
                  double beta1, double beta2, double eps, int64_t t, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Template-bank overlaps (Eq. 1 for many templates against many data streams), the one dense
+ * contraction of the path:
+ *   overlap[t][s] = sum_k w_k conj(h_t(f_k)) d_s(f_k),  w_k = 4 df inv_psd[k],
+ * so Re overlap = (h_t | d_s), |overlap| is the phase-maximised overlap, and with
+ * hh[t] = (h_t | h_t) one has ln L[t][s] = Re overlap[t][s] - hh[t] / 2.  Templates are
+ * generated in registers/LDS and contracted on the FP64 matrix cores; they are never stored.
+ * theta [nt][7] in the pd_param parameterisation, data [ns][n_bins][2] complex, 1 <= ns <= 64;
+ * overlap [nt][ns][2] out; hh [nt] out or NULL; status [nt] out or NULL (domain errors give
+ * NaN rows).  Templates ordered by total mass run faster (each block of 64 contracts only the
+ * bins where one of its templates is active).
+ * ------------------------------------------------------------------------------------- */
+#define PD_OVERLAP_MAX_STREAMS 64
+size_t pd_overlap_workspace_bytes(int64_t nt, int64_t ns, int64_t n_bins);
+int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, const double* lambda,
+               const double* data, int64_t ns, const double* inv_psd, double* overlap, double* hh,
+               int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Diagnostic: the kernels' own FP64 elementary functions applied elementwise, out[i] = fn(x[i])
  * for x [n], out [n] (device).  fn: PD_FN_SIN, PD_FN_COS (one shared argument reduction,

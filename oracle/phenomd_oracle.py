@@ -500,6 +500,20 @@ def inner(a, b, inv_psd, df):
     return 4.0 * df * math.fsum(terms.tolist())
 
 
+def overlaps(theta, param, lam, grid, streams, inv_psd):
+    """Complex overlaps of one template with several data streams (Eq. 1 before taking the real
+    part): O_s = 4 df sum_k conj(h_k) d_s,k / S_k, real and imaginary parts each summed with
+    exact rounding; also returns (h|h).  Re O_s = (h|d_s) and |O_s| is the overlap maximised
+    over a constant phase shift."""
+    h = waveform(theta, param, lam, grid)
+    df = grid[1]
+    out = np.zeros(len(streams), dtype=np.complex128)
+    for i, d in enumerate(streams):
+        terms = np.conj(h) * np.asarray(d) * inv_psd
+        out[i] = 4.0 * df * complex(math.fsum(terms.real.tolist()), math.fsum(terms.imag.tolist()))
+    return out, inner(h, h, inv_psd, df)
+
+
 def loglike(theta, param, lam, grid, data, inv_psd):
     """Gaussian log-likelihood up to the theta-independent -(d|d)/2: (d|h) - (h|h)/2."""
     h = waveform(theta, param, lam, grid)

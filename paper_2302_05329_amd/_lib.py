@@ -39,6 +39,8 @@ PD_K_WAVEFORM = 3
 PD_K_MISMATCH_INPUT = 4
 PD_K_MISMATCH_FFT = 5
 PD_K_MISMATCH_ADJ = 6
+PD_K_OVERLAP = 7
+PD_OVERLAP_MAX_STREAMS = 64
 
 
 class PdGrid(ctypes.Structure):
@@ -82,6 +84,8 @@ SIGNATURES = {
                            ctypes.POINTER(ctypes.c_double), _P, _P, _P, _SZ, _P]),
     "pd_independence_mh": (_INT, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pd_elementary_eval": (_INT, [_INT, _P, _I64, _P, _P]),
+    "pd_overlap_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
+    "pd_overlap": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_flow_param_count": (_I64, []),
     "pd_flow_workspace_bytes": (_SZ, [_I64]),
     "pd_flow_forward": (_INT, [_P, _P, _I64, _P, _P, _P]),

@@ -153,6 +153,31 @@ def mismatch_grad(theta, param, grid, lam, targets, inv_psd, want_grad=True, ws=
     return mm, dl, lag
 
 
+def overlap(theta, param, grid, lam, streams, inv_psd, want_hh=True, ws=None):
+    """Template-bank overlaps: O [nt, ns] complex128 with O[t, s] = sum_k w_k conj(h_t,k) d_s,k,
+    (h_t|h_t) [nt] (or None) and status [nt].  streams: [ns, n_bins] complex, ns <= 64."""
+    ws = ws or _default_ws
+    g = _grid(grid)
+    th = _dev(theta)
+    lam = _dev(lam)
+    d = torch.as_tensor(streams)
+    if not d.is_complex():
+        raise ValueError("streams must be complex [ns, n_bins]")
+    d = torch.view_as_real(d.to(device="cuda", dtype=torch.complex128)).contiguous()
+    ip = _dev(inv_psd)
+    _check_shapes(th, lam, g.n_bins, inv_psd=ip)
+    _need(d.dim() == 3 and d.shape[1] == g.n_bins and 1 <= d.shape[0] <= L.PD_OVERLAP_MAX_STREAMS,
+          f"streams must be complex [ns <= {L.PD_OVERLAP_MAX_STREAMS}, {g.n_bins}], got {tuple(d.shape[:2])}")
+    nt, ns = th.shape[0], d.shape[0]
+    out = torch.empty((nt, ns, 2), dtype=torch.float64, device="cuda")
+    hh = torch.empty(nt, dtype=torch.float64, device="cuda") if want_hh else None
+    status = torch.empty(nt, dtype=torch.int32, device="cuda")
+    wp, wb = ws.get(L.lib().pd_overlap_workspace_bytes(nt, ns, g.n_bins))
+    L.check(L.lib().pd_overlap(_ptr(th), nt, param, ctypes.byref(g), _ptr(lam), _ptr(d), ns, _ptr(ip), _ptr(out),
+                               _ptr(hh), _ptr(status), wp, wb, _stream()))
+    return torch.view_as_complex(out), hh, status
+
+
 class LogLike(torch.autograd.Function):
     """ln L(theta) with its gradient from the hand-written forward-mode kernels.
 

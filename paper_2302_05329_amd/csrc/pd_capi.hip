@@ -370,6 +370,41 @@ int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, double*
     return PD_OK;
 }
 
+size_t pd_overlap_workspace_bytes(int64_t nt, int64_t ns, int64_t n_bins) {
+    if (nt <= 0 || ns <= 0 || ns > PD_OVERLAP_MAX_STREAMS || n_bins <= 0) return 0;
+    const Layout L = layout_for(PD_OP_WAVEFORM, nt, n_bins);
+    return align_up(L.total + pd::overlap_bprime_bytes(n_bins, ns));
+}
+
+int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, const double* lambda,
+               const double* data, int64_t ns, const double* inv_psd, double* overlap, double* hh,
+               int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    pd::GridArgs g;
+    int rc = check_common(theta, nt, param, grid, lambda, &g);
+    if (rc) return rc;
+    if (!data) return fail(PD_EINVAL, "data is NULL");
+    if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
+    if (!overlap) return fail(PD_EINVAL, "overlap is NULL");
+    if (ns <= 0 || ns > PD_OVERLAP_MAX_STREAMS) return fail(PD_EINVAL, "ns must be in [1, 64]");
+    if (g.nb > (int64_t(1) << 30)) return fail(PD_EINVAL, "n_bins too large");
+    Layout L;
+    rc = check_ws(PD_OP_WAVEFORM, nt, g.nb, workspace, workspace_bytes, &L);
+    if (rc) return rc;
+    if (workspace_bytes < pd_overlap_workspace_bytes(nt, ns, g.nb))
+        return fail(PD_ENOMEM, "workspace too small (see pd_overlap_workspace_bytes)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* recs = at<double>(workspace, L.rec);
+    double* tab = at<double>(workspace, L.tab);
+    double* bp = at<double>(workspace, L.total);
+    hipError_t e = pd::launch_setup_value(theta, nt, param, g.fref, lambda, recs, status, s);
+    if (e != hipSuccess) return fail_hip(e, "setup");
+    e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
+    if (e != hipSuccess) return fail_hip(e, "tables");
+    e = pd::launch_overlap(recs, nt, g, tab, data, ns, inv_psd, bp, overlap, hh, s);
+    if (e != hipSuccess) return fail_hip(e, "overlap");
+    return PD_OK;
+}
+
 int pd_elementary_eval(int fn, const double* x, int64_t n, double* out, void* stream) {
     if (!x || !out) return fail(PD_EINVAL, "NULL argument");
     if (fn < PD_FN_SIN || fn > PD_FN_RCP) return fail(PD_EINVAL, "unknown function");

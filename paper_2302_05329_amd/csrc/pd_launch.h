@@ -52,6 +52,11 @@ int independence_mh(int64_t n, double* x, double* logp, double* logq, double* gr
 
 hipError_t launch_elementary(int fn, const double* x, int64_t n, double* out, hipStream_t s);
 
+constexpr int kOverlapMaxStreams = PD_OVERLAP_MAX_STREAMS;
+size_t overlap_bprime_bytes(int64_t nb, int64_t ns);
+hipError_t launch_overlap(const double* recs, int64_t nt, const GridArgs& g, const double* tab, const double* data,
+                          int64_t ns, const double* inv_psd, double* bp, double* out, double* hh, hipStream_t s);
+
 int64_t flow_param_count();
 size_t flow_ws_bytes(int64_t n);
 int flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, hipStream_t s);

@@ -1,0 +1,192 @@
+// Template-bank overlaps on the FP64 matrix cores: for N_t templates h_t (generated from
+// their parameters) and N_s data streams d_s on one grid,
+//   O[t][s] = sum_k w_k conj(h_t,k) d_s,k,     w_k = 4 df / S_n(f_k),
+// so Re O[t][s] = (h_t | d_s) of Eq. 1 and |O| is the phase-maximised overlap.  Together with
+// (h_t | h_t) this gives ln L for every (template, stream) pair.
+//
+// As a real GEMM over the bins:  [Re O | Im O] = [a_r | a_i] * [[D_r, D_i], [D_i, -D_r]]
+// with a = h / (A0 f^-7/6) (the per-template part of the strain) and D = w f^-7/6 d (the
+// per-bin part, prepared once per call).  The template operand is never stored: each block
+// generates its 64 templates x 64 bins into LDS chunk by chunk and contracts them at once
+// with v_mfma_f64_16x16x4f64 (lane layout checked on gfx950: with A[i][k] from lane
+// (i + 16 k) and B[k][j] from lane (j + 16 k), register r of lane l holds C[l/16 + 4 r][l%16]).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/phenomd.h"
+#include "pd_bin.h"
+#include "pd_launch.h"
+#include "pd_profile.h"
+
+namespace pd {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kKC = 64;              // bins per chunk
+constexpr int kKR = 2 * kKC;         // real contraction length per chunk
+constexpr int kTT = 64;              // templates per block (4 waves x 16)
+constexpr int kMaxCT = kOverlapMaxStreams / 8;   // column tiles of 16 real columns
+
+// B' [chunk][128][2 nsp]: rows k < 64 carry (D_r | D_i) of bin chunk*64 + k, rows 64 + k carry
+// (D_i | -D_r); columns s and nsp + s belong to stream s; zero beyond n_bins and ns.
+__global__ void k_ov_prep(GridArgs g, const double* __restrict__ data, int64_t ns, int nsp,
+                          const double* __restrict__ tab, const double* __restrict__ inv_psd,
+                          double* __restrict__ bp, int64_t n_chunks) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t cols = 2 * nsp;
+    const int64_t total = n_chunks * kKR * cols;
+    if (idx >= total) return;
+    const int64_t col = idx % cols;
+    const int64_t row = (idx / cols) % kKR;
+    const int64_t ch = idx / (cols * kKR);
+    const int64_t k = ch * kKC + (row % kKC);
+    const bool im_row = row >= kKC;
+    const int64_t s = col % nsp;
+    const bool im_col = col >= nsp;
+    double v = 0.0;
+    if (k < g.nb && s < ns) {
+        const double wf = 4.0 * g.df * inv_psd[k] * tab[T_F76 * g.nb + k];
+        const double2 d = reinterpret_cast<const double2*>(data)[s * g.nb + k];
+        const double dr = wf * d.x, di = wf * d.y;
+        v = im_row ? (im_col ? -dr : di) : (im_col ? di : dr);
+    }
+    bp[idx] = v;
+}
+
+__global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs, int64_t nt, GridArgs g,
+                                                 const double* __restrict__ tab, const double* __restrict__ bp,
+                                                 int nsp, int64_t ns, double* __restrict__ out,
+                                                 double* __restrict__ hh) {
+    // per wave 16 template rows x 128 real k; element (j, kk) sits at column kk ^ (4 j), so the
+    // MFMA reads (16 rows x 4 consecutive kk) and the generation writes (one row, 64 kk) both
+    // touch 64 distinct columns
+    __shared__ double As[4][16][kKR];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTT + 16 * w;
+    const Tabs T(tab, g.nb);
+    const int ct = nsp / 8;
+
+    // the block's bin range: union of its 64 templates' active ranges (every wave computes the
+    // same wave-uniform values, so no exchange is needed)
+    int klo = static_cast<int>(g.nb), khi = 0;
+    const int64_t tb = static_cast<int64_t>(blockIdx.x) * kTT;
+    for (int j = 0; j < kTT; ++j) {
+        const int64_t t = tb + j;
+        if (t >= nt) break;
+        const double* rec = recs + t * REC_N;
+        if (rec[R_VALID] == 0.0) continue;
+        int64_t ka, kz;
+        active_range(rec[R_MS], g, ka, kz);
+        if (kz > ka) {
+            klo = min(klo, uniform_i(ka));
+            khi = max(khi, uniform_i(kz));
+        }
+    }
+    const int c0 = klo / kKC;
+    const int c1 = (khi > klo) ? (khi + kKC - 1) / kKC : c0;
+
+    d4 acc[kMaxCT];
+#pragma unroll
+    for (int c = 0; c < kMaxCT; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+    double hacc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) hacc[j] = 0.0;
+
+    const int ia = lane & 15, ka4 = lane >> 4;     // MFMA operand coordinates of this lane
+    for (int ch = c0; ch < c1; ++ch) {
+        // generate a = A0^-1 f^(7/6) h for 16 templates x 64 bins (lane = bin)
+        const int64_t k = static_cast<int64_t>(ch) * kKC + lane;
+        const bool kin = k < g.nb;
+        const double f = bin_freq(g, kin ? k : g.nb - 1);
+        const double ww = kin ? T.at(T_WW, k) : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int64_t t = t0 + j;
+            double ar = 0.0, ai = 0.0;
+            if (t < nt) {
+                const double* rec = recs + t * REC_N;
+                const double mf = rec[R_MS] * f;
+                if (kin && rec[R_VALID] != 0.0 && bin_active(g, f, mf)) {
+                    BinVals bv;
+                    eval_bin_rt(rec, T, k, mf, bv);
+                    const double amp = rec[R_A0P] * bv.ahat;
+                    double sn, cs;
+                    pd_sincos(bv.psi, &sn, &cs);
+                    ar = amp * cs;
+                    ai = -amp * sn;
+                    hacc[j] = fma(ww * amp, amp, hacc[j]);
+                }
+            }
+            As[w][j][lane ^ (4 * j)] = ar;
+            As[w][j][(kKC + lane) ^ (4 * j)] = ai;
+        }
+        __syncthreads();
+        // contract with B' of this chunk: C[16 templates][16 real columns] per column tile
+        const double* __restrict__ bch = bp + static_cast<int64_t>(ch) * kKR * (2 * nsp);
+#pragma unroll 4
+        for (int s = 0; s < kKR / 4; ++s) {
+            const int kk = 4 * s + ka4;
+            const double a = As[w][ia][kk ^ (4 * ia)];
+            const double* __restrict__ brow = bch + static_cast<int64_t>(kk) * (2 * nsp) + ia;
+#pragma unroll
+            for (int c = 0; c < kMaxCT; ++c)
+                if (c < ct) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[16 * c], acc[c], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // (h|h) per template; overlaps with the record's amplitude factor
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const double v = wave_sum(hacc[j]);
+        const int64_t t = t0 + j;
+        if (lane == 0 && t < nt && hh) hh[t] = (recs[t * REC_N + R_VALID] != 0.0) ? v : __builtin_nan("");
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCT; ++c) {
+        if (c >= ct) continue;
+        const int col = 16 * c + ia;
+        const bool im = col >= nsp;
+        const int64_t s = im ? col - nsp : col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t t = t0 + ka4 + 4 * r;
+            if (t < nt && s < ns) {
+                const bool ok = recs[t * REC_N + R_VALID] != 0.0;
+                out[(t * ns + s) * 2 + (im ? 1 : 0)] = ok ? acc[c][r] : __builtin_nan("");
+            }
+        }
+    }
+}
+
+inline unsigned nblk(int64_t threads, int per) { return static_cast<unsigned>((threads + per - 1) / per); }
+
+}  // namespace
+
+int64_t overlap_chunks(int64_t nb) { return (nb + kKC - 1) / kKC; }
+
+size_t overlap_bprime_bytes(int64_t nb, int64_t ns) {
+    const int64_t nsp = (ns + 7) / 8 * 8;
+    return static_cast<size_t>(overlap_chunks(nb)) * kKR * 2 * nsp * sizeof(double);
+}
+
+hipError_t launch_overlap(const double* recs, int64_t nt, const GridArgs& g, const double* tab,
+                          const double* data, int64_t ns, const double* inv_psd, double* bp, double* out,
+                          double* hh, hipStream_t s) {
+    const int nsp = static_cast<int>((ns + 7) / 8 * 8);
+    const int64_t n_chunks = overlap_chunks(g.nb);
+    const int64_t total = n_chunks * kKR * 2 * nsp;
+    hipLaunchKernelGGL(k_ov_prep, dim3(nblk(total, 256)), dim3(256), 0, s, g, data, ns, nsp, tab, inv_psd, bp,
+                       n_chunks);
+    {
+        ProfRange pr(PD_K_OVERLAP, s);
+        hipLaunchKernelGGL(k_ov_gemm, dim3(nblk(nt, kTT)), dim3(256), 0, s, recs, nt, g, tab, bp, nsp, ns, out, hh);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pd

@@ -465,3 +465,22 @@ def test_placeholder_table_sanity(lam0):
         mf = np.linspace(1e-4, 0.2, 3000)
         ar = m.amplitude_ratio(mf)
         assert np.all(ar > 0) and np.all(np.isfinite(ar))
+
+
+def test_overlaps_hermitian_linear_and_phase_covariant(lam0):
+    """Template-bank overlaps: O(h, h) = (h|h) with zero imaginary part; linear in the data;
+    a constant phase rotation of the data rotates O by the same phase."""
+    rows = W.draw_sources(3, 71)
+    grid = W.Grid(20.0, 0.25, 1201)
+    g = grid.as_tuple()
+    ip = 1.0 / W.psd_aligo_zdhp_fit(grid.freqs())
+    th = rows[0]
+    h = O.waveform(th, O.PARAM_M1M2, lam0, g)
+    n1 = W.complex_noise(1.0 / ip, grid.df, 5)
+    n2 = W.complex_noise(1.0 / ip, grid.df, 6)
+    phi = 0.7
+    out, hh = O.overlaps(th, O.PARAM_M1M2, lam0, g, [h, n1, n2, n1 + 2.0 * n2, h * np.exp(1j * phi)], ip)
+    assert abs(out[0].real - hh) <= 1e-13 * hh and abs(out[0].imag) <= 1e-13 * hh
+    assert abs(out[3] - (out[1] + 2.0 * out[2])) <= 1e-12 * (abs(out[1]) + 2 * abs(out[2]) + math.sqrt(hh))
+    assert abs(out[4] - hh * np.exp(1j * phi)) <= 1e-13 * hh
+    assert abs(hh - O.inner(h, h, ip, g[1])) == 0.0
