@@ -39,7 +39,10 @@ struct Tabs {
         for (int i = 0; i < T_N; ++i) p[i] = t + i * nb;
     }
     __device__ __forceinline__ double at(int which, int64_t k) const { return p[which][k]; }
-    __device__ __forceinline__ double at(int which, unsigned k) const { return p[which][k]; }
+    // 32-bit byte offset from a wave-uniform base: one shared offset register serves every table
+    __device__ __forceinline__ double at(int which, unsigned k) const {
+        return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(p[which]) + (k << 3));
+    }
 };
 
 // Frequency of bin k, rounded exactly as f0 + k*df (two roundings, no fused multiply-add).
@@ -130,13 +133,16 @@ struct BinVals {
     double lnf, invf;        // ln Mf, 1/Mf                              (phase regions 2, 3)
     double f34, u, at;       // Mf^(3/4), (Mf - q)/d, atan(u)            (phase region 3)
     double x, iden;          // Mf - f_RD, 1/(x^2 + g^2)                 (amplitude region 3)
+    double iu2;              // 1/(1 + u^2)                              (phase region 3)
     double ahat;             // amplitude ratio
     double psi;              // phase
 };
 
-template <int PR, int AR, class KI>
+// HAVE_EX: the merger-ringdown amplitude exponential exp(-c3 (Mf - f_RD)) is supplied by the
+// caller (a per-lane recurrence along a segment) instead of evaluated here.
+template <int PR, int AR, bool HAVE_EX = false, class KI>
 __device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const Tabs& T, KI k, double mf,
-                                           BinVals& b) {
+                                           BinVals& b, double ex = 0.0) {
     b.mf = mf;
     if (PR == 1 || AR == 1) {
         b.v = c[R_CS] * T.at(T_CB, k);
@@ -162,16 +168,37 @@ __device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const T
         b.invf = invf;
         b.psi = fma(c[R_PH2 + 3], invf * invf * invf, fma(c[R_PH2 + 2], lnf, fma(c[R_PH2 + 1], mf, c[R_PH2 + 0])));
     } else {
+        // merger-ringdown phase: atan(u) needs one division (after its argument reduction), the
+        // phase derivative 1/(1 + u^2), and in amplitude region 3 the Lorentzian 1/(x^2 + g^2):
+        // all three come from one reciprocal of their product
         const double invf = c[R_IMS] * T.at(T_INF, k);
         const double f34 = c[R_MS34] * T.at(T_F34, k);
         const double u = (mf - c[R_PH3 + 5]) * c[R_ID];
-        const double at = pd_atan(u);
+        AtanParts ap = pd_atan_reduce(u);
+        const double d1 = fma(u, u, 1.0);
+        double d2 = 1.0, x = 0.0;
+        if (AR == 3) {
+            x = mf - c[R_AM3 + 1];
+            const double g = c[R_AM3 + 2];
+            d2 = fma(x, x, g * g);
+        }
+        const double p12 = d1 * d2;
+        const double r = pd_rcp(ap.den * p12);
+        const double at = pd_atan_finish(ap, ap.num * (r * p12));
+        const double rd = r * ap.den;
+        b.iu2 = (AR == 3) ? rd * d2 : rd;
         b.invf = invf;
         b.f34 = f34;
         b.u = u;
         b.at = at;
         b.psi = fma(c[R_PH3 + 4], at,
                     fma(c[R_PH3 + 3], f34, fma(c[R_PH3 + 2], invf, fma(c[R_PH3 + 1], mf, c[R_PH3 + 0]))));
+        if (AR == 3) {
+            const double iden = rd * d1;
+            b.x = x;
+            b.iden = iden;
+            b.ahat = c[R_AM3 + 0] * iden * (HAVE_EX ? ex : pd_exp(-c[R_AM3 + 3] * x));
+        }
     }
     if (AR == 1) {
         const double v = b.v;
@@ -182,15 +209,33 @@ __device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const T
     } else if (AR == 2) {
         b.ahat = fma(mf, fma(mf, fma(mf, fma(mf, c[R_AM2 + 4], c[R_AM2 + 3]), c[R_AM2 + 2]), c[R_AM2 + 1]),
                      c[R_AM2 + 0]);
-    } else {
+    } else if (PR != 3) {
         const double x = mf - c[R_AM3 + 1];
         const double g = c[R_AM3 + 2];
         const double iden = pd_rcp(fma(x, x, g * g));
         b.x = x;
         b.iden = iden;
-        b.ahat = c[R_AM3 + 0] * iden * pd_exp(-c[R_AM3 + 3] * x);
+        b.ahat = c[R_AM3 + 0] * iden * (HAVE_EX ? ex : pd_exp(-c[R_AM3 + 3] * x));
     }
 }
+
+// Per-lane geometric recurrence for the merger-ringdown amplitude exponential along a segment:
+// a lane's bins are 64 apart, so exp(-c3 (Ms f_k - f_RD)) advances by the constant factor
+// exp(-c3 Ms 64 df).  One exponential per lane and one per wave at the segment start, then one
+// multiply per bin; the relative drift after n steps is at most about n ulp.
+struct ExpRec {
+    double e, r;
+    __device__ __forceinline__ void init(const double* __restrict__ c, const GridArgs& g, unsigned k_first) {
+        const double c3 = c[R_AM3 + 3];
+        e = pd_exp(-c3 * (c[R_MS] * bin_freq(g, k_first) - c[R_AM3 + 1]));
+        r = pd_exp(-c3 * (c[R_MS] * (64.0 * g.df)));
+    }
+    __device__ __forceinline__ double next() {
+        const double v = e;
+        e *= r;
+        return v;
+    }
+};
 
 // Runtime region dispatch for one-bin-per-thread kernels.
 __device__ __forceinline__ void eval_bin_rt(const double* __restrict__ rec, const Tabs& T, int64_t k, double mf,
@@ -250,8 +295,7 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         vis.ph(R_PH2 + 3, i3);
         fpsi = fma(c[R_PH2 + 1], b.mf, fma(sk(-3.0) * c[R_PH2 + 3], i3, c[R_PH2 + 2]));
     } else {
-        const double iu2 = pd_rcp(fma(b.u, b.u, 1.0));
-        const double t = c[R_PH3 + 4] * iu2 * c[R_ID];
+        const double t = c[R_PH3 + 4] * b.iu2 * c[R_ID];
         vis.ph(R_PH3 + 0, 1.0);
         vis.ph(R_PH3 + 1, b.mf);
         vis.ph(R_PH3 + 2, b.invf);

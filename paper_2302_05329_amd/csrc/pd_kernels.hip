@@ -251,10 +251,12 @@ struct LnlSegment {
         double mom[REC_N];
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
+        ExpRec er{};
+        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane));
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
-            eval_bin_t<PR, AR>(rec, T, k, mf, bv);
+            eval_bin_t<PR, AR, AR == 3>(rec, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
             double sn, cs;
             pd_sincos(bv.psi, &sn, &cs);
             const double hr = bv.ahat * cs, hi = -bv.ahat * sn;
@@ -391,10 +393,12 @@ struct FisherSegment {
     __device__ __forceinline__ void run() {
         const double ms = rec[R_MS];
         const double a0p = rec[R_A0P];
+        ExpRec er{};
+        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane));
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
-            eval_bin_t<PR, AR>(rec, T, k, mf, bv);
+            eval_bin_t<PR, AR, AR == 3>(rec, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
             const double W = (a0p * a0p) * T.at(T_WW, k) * bv.ahat * bv.ahat;
             FisherVis vis;
             vis.T = Tl;

@@ -102,6 +102,45 @@ constexpr double kSqrt3 = 1.7320508075688772;
 constexpr double kPi6_hi = 0.5235987755982989, kPi6_lo = -5.360408832255455e-17;
 constexpr double kPi2_hi = 1.5707963267948966, kPi2_lo = 6.123233995736766e-17;
 
+// atan split around its one division: pd_atan_reduce gives the reduced quotient's numerator
+// and denominator, pd_atan_finish takes the quotient t = num / den (computed by the caller,
+// possibly sharing a reciprocal with other divisions) and returns atan(u).
+struct AtanParts {
+    double num, den;
+    bool hi, inv, neg;
+};
+
+__device__ __forceinline__ AtanParts pd_atan_reduce(double u) {
+    const double a = fabs(u);
+    AtanParts p;
+    p.inv = a > 1.0;
+    const double num = p.inv ? 1.0 : a;
+    const double den = p.inv ? a : 1.0;
+    p.hi = num > sk(kTanPi12) * den;
+    p.num = p.hi ? fma(sk(kSqrt3), num, -den) : num;
+    p.den = p.hi ? fma(sk(kSqrt3), den, num) : den;
+    p.neg = u < 0.0;
+    return p;
+}
+
+__device__ __forceinline__ double pd_atan_finish(const AtanParts& p, double t) {
+    const double z = t * t;
+    double q = fma(sk(kA10), z, sk(kA9));
+    q = fma(q, z, sk(kA8));
+    q = fma(q, z, sk(kA7));
+    q = fma(q, z, sk(kA6));
+    q = fma(q, z, sk(kA5));
+    q = fma(q, z, sk(kA4));
+    q = fma(q, z, sk(kA3));
+    q = fma(q, z, sk(kA2));
+    q = fma(q, z, sk(kA1));
+    q = fma(q, z, sk(kA0));
+    double r = fma(t * z, q, t);
+    if (p.hi) r = (r + sk(kPi6_lo)) + sk(kPi6_hi);
+    if (p.inv) r = (sk(kPi2_hi) - r) + sk(kPi2_lo);
+    return p.neg ? -r : r;
+}
+
 __device__ __forceinline__ double pd_atan(double u) {
     const double a = fabs(u);
     const bool inv = a > 1.0;

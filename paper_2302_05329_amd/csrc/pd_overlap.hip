@@ -28,7 +28,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kKC = 64;              // bins per chunk
 constexpr int kKR = 2 * kKC;         // real contraction length per chunk
 constexpr int kTT = 64;              // templates per block (4 waves x 16)
-constexpr int kMaxCT = kOverlapMaxStreams / 8;   // column tiles of 16 real columns
 
 // B' [chunk][128][2 nsp]: rows k < 64 carry (D_r | D_i) of bin chunk*64 + k, rows 64 + k carry
 // (D_i | -D_r); columns s and nsp + s belong to stream s; zero beyond n_bins and ns.
@@ -56,6 +55,7 @@ __global__ void k_ov_prep(GridArgs g, const double* __restrict__ data, int64_t n
     bp[idx] = v;
 }
 
+template <int CT>
 __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs, int64_t nt, GridArgs g,
                                                  const double* __restrict__ tab, const double* __restrict__ bp,
                                                  int nsp, int64_t ns, double* __restrict__ out,
@@ -68,7 +68,6 @@ __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs
     const int w = threadIdx.x >> 6;
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTT + 16 * w;
     const Tabs T(tab, g.nb);
-    const int ct = nsp / 8;
 
     // the block's bin range: union of its 64 templates' active ranges (every wave computes the
     // same wave-uniform values, so no exchange is needed)
@@ -89,66 +88,86 @@ __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs
     const int c0 = klo / kKC;
     const int c1 = (khi > klo) ? (khi + kKC - 1) / kKC : c0;
 
-    d4 acc[kMaxCT];
+    d4 acc[CT];
 #pragma unroll
-    for (int c = 0; c < kMaxCT; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
-    double hacc[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) hacc[j] = 0.0;
+    for (int c = 0; c < CT; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+    double hsum = 0.0;                      // (h|h) terms of template ia over this lane's bins
 
     const int ia = lane & 15, ka4 = lane >> 4;     // MFMA operand coordinates of this lane
+    const int64_t bstride = 2 * nsp;
     for (int ch = c0; ch < c1; ++ch) {
-        // generate a = A0^-1 f^(7/6) h for 16 templates x 64 bins (lane = bin)
-        const int64_t k = static_cast<int64_t>(ch) * kKC + lane;
-        const bool kin = k < g.nb;
-        const double f = bin_freq(g, kin ? k : g.nb - 1);
-        const double ww = kin ? T.at(T_WW, k) : 0.0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int64_t t = t0 + j;
-            double ar = 0.0, ai = 0.0;
-            if (t < nt) {
-                const double* rec = recs + t * REC_N;
-                const double mf = rec[R_MS] * f;
-                if (kin && rec[R_VALID] != 0.0 && bin_active(g, f, mf)) {
-                    BinVals bv;
-                    eval_bin_rt(rec, T, k, mf, bv);
-                    const double amp = rec[R_A0P] * bv.ahat;
-                    double sn, cs;
-                    pd_sincos(bv.psi, &sn, &cs);
-                    ar = amp * cs;
-                    ai = -amp * sn;
-                    hacc[j] = fma(ww * amp, amp, hacc[j]);
+        // generate a = h / (A0 f^-7/6) for 16 templates x 64 bins (lane = bin)
+        {
+            const int64_t k = static_cast<int64_t>(ch) * kKC + lane;
+            const bool kin = k < g.nb;
+            const double f = bin_freq(g, kin ? k : g.nb - 1);
+#pragma unroll 1
+            for (int j = 0; j < 16; ++j) {
+                const int64_t t = t0 + j;
+                double ar = 0.0, ai = 0.0;
+                if (t < nt) {
+                    const double* rec = recs + t * REC_N;
+                    const double mf = rec[R_MS] * f;
+                    if (kin && rec[R_VALID] != 0.0 && bin_active(g, f, mf)) {
+                        BinVals bv;
+                        eval_bin_rt(rec, T, k, mf, bv);
+                        const double amp = rec[R_A0P] * bv.ahat;
+                        double sn, cs;
+                        pd_sincos(bv.psi, &sn, &cs);
+                        ar = amp * cs;
+                        ai = -amp * sn;
+                    }
                 }
+                As[w][j][lane ^ (4 * j)] = ar;
+                As[w][j][(kKC + lane) ^ (4 * j)] = ai;
             }
-            As[w][j][lane ^ (4 * j)] = ar;
-            As[w][j][(kKC + lane) ^ (4 * j)] = ai;
         }
         __syncthreads();
-        // contract with B' of this chunk: C[16 templates][16 real columns] per column tile
-        const double* __restrict__ bch = bp + static_cast<int64_t>(ch) * kKR * (2 * nsp);
-#pragma unroll 4
-        for (int s = 0; s < kKR / 4; ++s) {
-            const int kk = 4 * s + ka4;
-            const double a = As[w][ia][kk ^ (4 * ia)];
-            const double* __restrict__ brow = bch + static_cast<int64_t>(kk) * (2 * nsp) + ia;
+        // contract with B' of this chunk: C[16 templates][16 real columns] per column tile;
+        // B' values are fetched two k-steps ahead of their use
+        const double* __restrict__ bch = bp + static_cast<int64_t>(ch) * kKR * bstride + ia;
+        const double* __restrict__ wwc = T.p[T_WW] + static_cast<int64_t>(ch) * kKC;
+        const int64_t kmax = g.nb - static_cast<int64_t>(ch) * kKC;    // bins of this chunk inside the grid
+        double b0[2][CT], b1[2][CT];
+        auto fetch = [&](double (&dst)[2][CT], int sg) {
 #pragma unroll
-            for (int c = 0; c < kMaxCT; ++c)
-                if (c < ct) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[16 * c], acc[c], 0, 0, 0);
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) dst[u][c] = bch[(8 * sg + 4 * u + ka4) * bstride + 16 * c];
+        };
+        auto step = [&](const double (&src)[2][CT], int sg) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int kk = 8 * sg + 4 * u + ka4;
+                const double a = As[w][ia][kk ^ (4 * ia)];
+                const int kb = kk & (kKC - 1);
+                const double ww = (kb < kmax) ? wwc[kb] : 0.0;
+                hsum = fma(ww * a, a, hsum);
+#pragma unroll
+                for (int c = 0; c < CT; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, src[u][c], acc[c], 0, 0, 0);
+            }
+        };
+        fetch(b0, 0);
+#pragma unroll 1
+        for (int sg = 0; sg < kKR / 8; sg += 2) {
+            fetch(b1, sg + 1);
+            step(b0, sg);
+            if (sg + 2 < kKR / 8) fetch(b0, sg + 2);
+            step(b1, sg + 1);
         }
         __syncthreads();
     }
 
-    // (h|h) per template; overlaps with the record's amplitude factor
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const double v = wave_sum(hacc[j]);
-        const int64_t t = t0 + j;
-        if (lane == 0 && t < nt && hh) hh[t] = (recs[t * REC_N + R_VALID] != 0.0) ? v : __builtin_nan("");
+    // (h|h): the four lanes holding template ia (ka4 = 0..3) together saw all its bins twice
+    // (real and imaginary part)
+    hsum += __shfl_xor(hsum, 16, 64);
+    hsum += __shfl_xor(hsum, 32, 64);
+    if (ka4 == 0 && hh && t0 + ia < nt) {
+        const int64_t t = t0 + ia;
+        hh[t] = (recs[t * REC_N + R_VALID] != 0.0) ? hsum : __builtin_nan("");
     }
 #pragma unroll
-    for (int c = 0; c < kMaxCT; ++c) {
-        if (c >= ct) continue;
+    for (int c = 0; c < CT; ++c) {
         const int col = 16 * c + ia;
         const bool im = col >= nsp;
         const int64_t s = im ? col - nsp : col;
@@ -169,22 +188,34 @@ inline unsigned nblk(int64_t threads, int per) { return static_cast<unsigned>((t
 
 int64_t overlap_chunks(int64_t nb) { return (nb + kKC - 1) / kKC; }
 
+// Streams padded to 8, 16, 32 or 64 (8 x the kernel's column-tile count).
+int overlap_padded_streams(int64_t ns) { return ns <= 8 ? 8 : ns <= 16 ? 16 : ns <= 32 ? 32 : 64; }
+
 size_t overlap_bprime_bytes(int64_t nb, int64_t ns) {
-    const int64_t nsp = (ns + 7) / 8 * 8;
+    const int64_t nsp = overlap_padded_streams(ns);
     return static_cast<size_t>(overlap_chunks(nb)) * kKR * 2 * nsp * sizeof(double);
 }
 
 hipError_t launch_overlap(const double* recs, int64_t nt, const GridArgs& g, const double* tab,
                           const double* data, int64_t ns, const double* inv_psd, double* bp, double* out,
                           double* hh, hipStream_t s) {
-    const int nsp = static_cast<int>((ns + 7) / 8 * 8);
+    const int nsp = overlap_padded_streams(ns);
     const int64_t n_chunks = overlap_chunks(g.nb);
     const int64_t total = n_chunks * kKR * 2 * nsp;
     hipLaunchKernelGGL(k_ov_prep, dim3(nblk(total, 256)), dim3(256), 0, s, g, data, ns, nsp, tab, inv_psd, bp,
                        n_chunks);
     {
+        // column tiles of 16 real columns: 2 nsp / 16 = nsp / 8 of them
         ProfRange pr(PD_K_OVERLAP, s);
-        hipLaunchKernelGGL(k_ov_gemm, dim3(nblk(nt, kTT)), dim3(256), 0, s, recs, nt, g, tab, bp, nsp, ns, out, hh);
+        const dim3 grid(nblk(nt, kTT)), block(256);
+        if (nsp <= 8)
+            hipLaunchKernelGGL(k_ov_gemm<1>, grid, block, 0, s, recs, nt, g, tab, bp, nsp, ns, out, hh);
+        else if (nsp <= 16)
+            hipLaunchKernelGGL(k_ov_gemm<2>, grid, block, 0, s, recs, nt, g, tab, bp, nsp, ns, out, hh);
+        else if (nsp <= 32)
+            hipLaunchKernelGGL(k_ov_gemm<4>, grid, block, 0, s, recs, nt, g, tab, bp, nsp, ns, out, hh);
+        else
+            hipLaunchKernelGGL(k_ov_gemm<8>, grid, block, 0, s, recs, nt, g, tab, bp, nsp, ns, out, hh);
     }
     return hipGetLastError();
 }
