@@ -87,8 +87,7 @@ __device__ __forceinline__ int uniform_i(int64_t x) { return __builtin_amdgcn_re
 
 // Region segments of [kb, ke) (already inside the active range): segment i is
 // [k[i], k[i+1]) (possibly empty) with phase region pr[i] and amplitude region ar[i].  Every
-// index is a compile-time constant after unrolling and every value is wave-uniform (read
-// from lane 0), so the struct lives in scalar registers.
+// index is a compile-time constant after unrolling, so the struct lives in registers.
 struct Segs {
     int k[6];
     int pr[5], ar[5];
@@ -114,15 +113,40 @@ __device__ __forceinline__ void make_segments(const double* __restrict__ rec, co
     }
     PD_SW(0, 1) PD_SW(2, 3) PD_SW(0, 2) PD_SW(1, 3) PD_SW(1, 2)
 #undef PD_SW
-    S.k[0] = uniform_i(kb);
+    S.k[0] = static_cast<int>(kb);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) S.k[i + 1] = uniform_i(b[i]);
-    S.k[5] = uniform_i(ke);
+    for (int i = 0; i < 4; ++i) S.k[i + 1] = static_cast<int>(b[i]);
+    S.k[5] = static_cast<int>(ke);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         const double mf = ms * bin_freq(g, static_cast<int64_t>(S.k[i]));
-        S.pr[i] = uniform_i((mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3));
-        S.ar[i] = uniform_i((mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3));
+        S.pr[i] = (mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3);
+        S.ar[i] = (mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3);
+    }
+}
+
+// Segment tables are computed once per call (one thread per (point, chunk)) and read by every
+// region launch: 16 ints per entry, k[6], pr[5], ar[5].
+constexpr int kSegInts = 16;
+
+__device__ __forceinline__ void store_segments(const Segs& S, int* __restrict__ dst) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) dst[i] = S.k[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        dst[6 + i] = S.pr[i];
+        dst[11 + i] = S.ar[i];
+    }
+}
+
+// Read by a whole wavefront from a wave-uniform address (scalar loads).
+__device__ __forceinline__ void load_segments(const int* __restrict__ src, Segs& S) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.k[i] = src[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        S.pr[i] = src[6 + i];
+        S.ar[i] = src[11 + i];
     }
 }
 
@@ -363,6 +387,144 @@ __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     return x;
+}
+
+// ---- many-value wavefront reduction by recursive halving --------------------------------
+// N per-lane values are summed over the 64 lanes in 6 exchange steps (offsets 32 .. 1): at each
+// step a lane keeps one half of its current entries (the upper half if its lane bit is set),
+// receives its partner's copy of that half and adds.  About N exchanges in total instead of
+// 6 N for N separate butterflies, and still a fixed summation order.  Afterwards entry c
+// (summed over all lanes) sits in lane halving_lane<N>(c); lane l holds entry halving_entry<N>(l)
+// (>= N: nothing).
+// Exchange across lane halves (OFF 32: lanes l and l + 32; OFF 16: rows of 16) with the gfx950
+// lane-swap instructions: afterwards a holds [a_lo | b_lo] and b holds [a_hi | b_hi] by half, so
+// a + b is the halving step with no select.
+template <int OFF>
+__device__ __forceinline__ void swap_halves(double& a, double& b) {
+    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+    const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+    const unsigned alo = static_cast<unsigned>(ua), ahi = static_cast<unsigned>(ua >> 32);
+    const unsigned blo = static_cast<unsigned>(ub), bhi = static_cast<unsigned>(ub >> 32);
+    unsigned rl0, rl1, rh0, rh1;
+    if constexpr (OFF == 32) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        rl0 = rl[0], rl1 = rl[1], rh0 = rh[0], rh1 = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        rl0 = rl[0], rl1 = rl[1], rh0 = rh[0], rh1 = rh[1];
+    }
+    a = __builtin_bit_cast(double, (static_cast<unsigned long long>(rh0) << 32) | rl0);
+    b = __builtin_bit_cast(double, (static_cast<unsigned long long>(rh1) << 32) | rl1);
+}
+
+template <int N, int OFF>
+struct Halve {
+    static __device__ __forceinline__ double run(const double* v, int lane) {
+        constexpr int H = (N + 1) / 2;
+        double w[H];
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            double a = v[j];
+            double b = (H + j < N) ? v[H + j] : 0.0;
+            if constexpr (OFF == 32 || OFF == 16) {
+                swap_halves<OFF>(a, b);
+                w[j] = a + b;
+            } else {
+                const double send = up ? a : b;
+                const double keep = up ? b : a;
+                w[j] = keep + __shfl_xor(send, OFF, 64);
+            }
+        }
+        if constexpr (OFF == 1) {
+            return w[0];
+        } else {
+            return Halve<H, OFF / 2>::run(w, lane);
+        }
+    }
+};
+
+template <int N>
+__host__ __device__ constexpr int halving_lane(int c) {
+    int lane = 0, n = N;
+    for (int t = 0; t < 6; ++t) {
+        const int h = (n + 1) / 2;
+        if (c >= h) {
+            c -= h;
+            lane |= 32 >> t;
+        }
+        n = h;
+    }
+    return lane;
+}
+
+template <int N>
+__host__ __device__ constexpr int halving_entry(int lane) {
+    int hs[6] = {0, 0, 0, 0, 0, 0}, ns[6] = {0, 0, 0, 0, 0, 0};
+    int n = N;
+    for (int t = 0; t < 6; ++t) {
+        ns[t] = n;
+        hs[t] = (n + 1) / 2;
+        n = hs[t];
+    }
+    // relative index within the range entering step t; it must stay inside that range
+    int c = 0;
+    for (int t = 5; t >= 0; --t) {
+        if (lane & (32 >> t)) c += hs[t];
+        if (c >= ns[t]) return N;
+    }
+    return c;
+}
+
+template <int N>
+__device__ __forceinline__ double halving_reduce(const double (&v)[N], int lane) {
+    static_assert(N >= 1 && N <= 64, "halving_reduce handles 1..64 entries");
+    return Halve<N, 32>::run(v, lane);
+}
+
+// Record entries touched by a (phase, amplitude) region pair, in compact order:
+// R_MS, R_LNA0, the phase block, the amplitude block.
+__host__ __device__ constexpr int phase_block_len(int pr) { return pr == 1 ? 13 : (pr == 2 ? 4 : 7); }
+__host__ __device__ constexpr int phase_block_start(int pr) { return pr == 1 ? R_PH1 : (pr == 2 ? R_PH2 : R_PH3); }
+__host__ __device__ constexpr int amp_block_len(int ar) { return ar == 1 ? 10 : (ar == 2 ? 5 : 4); }
+__host__ __device__ constexpr int amp_block_start(int ar) { return ar == 1 ? R_AM1 : (ar == 2 ? R_AM2 : R_AM3); }
+
+template <int PR, int AR>
+__host__ __device__ constexpr int touched_count() { return 2 + phase_block_len(PR) + amp_block_len(AR); }
+
+template <int PR, int AR>
+__host__ __device__ constexpr int touched_slot(int c) {
+    return c == 0 ? R_MS
+                  : (c == 1 ? R_LNA0
+                            : (c < 2 + phase_block_len(PR) ? phase_block_start(PR) + c - 2
+                                                            : amp_block_start(AR) + c - 2 - phase_block_len(PR)));
+}
+
+// Compact index of record entry s for the pair, or -1 if the pair does not touch it.
+template <int PR, int AR>
+__device__ __forceinline__ int touched_index(int s) {
+    if (s == R_MS) return 0;
+    if (s == R_LNA0) return 1;
+    const int p0 = phase_block_start(PR), a0 = amp_block_start(AR);
+    if (s >= p0 && s < p0 + phase_block_len(PR)) return 2 + s - p0;
+    if (s >= a0 && s < a0 + amp_block_len(AR)) return 2 + phase_block_len(PR) + s - a0;
+    return -1;
+}
+
+// Fold a segment's per-lane moments (entries the pair touches) into per-lane totals: lane s
+// accumulates the wave sum of record entry s.
+template <int PR, int AR>
+__device__ __forceinline__ void flush_touched(const double (&mom)[REC_N], int lane, double& tot) {
+    constexpr int N = touched_count<PR, AR>();
+    double v[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[c] = mom[touched_slot<PR, AR>(c)];
+    const double r = halving_reduce<N>(v, lane);
+    const int c = touched_index<PR, AR>(lane);
+    const double got = __shfl(r, halving_lane<N>(c < 0 ? 0 : c), 64);
+    if (c >= 0) tot += got;
 }
 
 // Dispatch a functor templated on the (phase, amplitude) region pair.

@@ -62,7 +62,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec = 0, tab = 0, tan = 0, partial = 0, extra = 0, total = 0;
+    size_t rec = 0, tab = 0, tan = 0, partial = 0, seg = 0, extra = 0, total = 0;
     int chunks = 1;
 };
 
@@ -81,6 +81,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.chunks = pd::chunks_for(n, nb);
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * 2 * sizeof(double));
+            L.seg = off;
+            off = align_up(off + N * L.chunks * pd::kSegInts * sizeof(int));
             break;
         case PD_OP_LOGLIKE_GRAD:
             L.chunks = pd::chunks_for(n, nb);
@@ -88,6 +90,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * pd::kNSlot * sizeof(double));
+            L.seg = off;
+            off = align_up(off + N * L.chunks * pd::kSegInts * sizeof(int));
             break;
         case PD_OP_FISHER:
             L.chunks = pd::chunks_for(n, nb);
@@ -95,6 +99,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * 28 * sizeof(double));
+            L.seg = off;
+            off = align_up(off + N * L.chunks * pd::kSegInts * sizeof(int));
             break;
         case PD_OP_MISMATCH_GRAD:
             L.tan = off;
@@ -236,7 +242,7 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
     }
     e = pd::launch_tables(g, data, inv_psd, tab, s);
     if (e != hipSuccess) return fail_hip(e, "tables");
-    e = pd::launch_loglike(recs, tans, n, L.chunks, g, tab, partial, lnl, grad, s);
+    e = pd::launch_loglike(recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl, grad, s);
     if (e != hipSuccess) return fail_hip(e, "loglike");
     return PD_OK;
 }
@@ -263,7 +269,7 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, co
     if (e != hipSuccess) return fail_hip(e, "setup tangents");
     e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
     if (e != hipSuccess) return fail_hip(e, "tables");
-    e = pd::launch_fisher(recs, tans, n, L.chunks, g, tab, partial, F, s);
+    e = pd::launch_fisher(recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, F, s);
     if (e != hipSuccess) return fail_hip(e, "fisher");
     return PD_OK;
 }

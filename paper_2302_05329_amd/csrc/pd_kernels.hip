@@ -222,18 +222,6 @@ struct MomVis {
     __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] = fma(zi, fpsi, fma(zr, fa, mom[R_MS])); }
 };
 
-// Fold a segment's per-lane moments into the per-lane slot totals (lane s keeps slot s).
-template <int PR, int AR>
-__device__ __forceinline__ void flush_moments(const double (&mom)[REC_N], int lane, double& tot) {
-#pragma unroll
-    for (int s = 0; s < REC_N; ++s) {
-        if (slot_touched(PR, AR, s)) {
-            const double t = wave_sum(mom[s]);
-            if (lane == s) tot += t;
-        }
-    }
-}
-
 // One region segment of the likelihood loop.  MODE 0: (d|h), (h|h); MODE 1: + moments.
 template <int MODE>
 struct LnlSegment {
@@ -271,7 +259,7 @@ struct LnlSegment {
                 visit_bin_t<PR, AR>(rec, bv, vis);
             }
         }
-        if (MODE == 1) flush_moments<PR, AR>(mom, lane, tot);
+        if (MODE == 1) flush_touched<PR, AR>(mom, lane, tot);
     }
 };
 
@@ -280,6 +268,7 @@ struct LnlSegment {
 template <int MODE, int PRG>
 __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
                                                          GridArgs g, const double* __restrict__ tab,
+                                                         const int* __restrict__ segs,
                                                          double* __restrict__ partial_all) {
     constexpr int NS = (MODE == 0) ? 2 : kNSlot;
     double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * NS;
@@ -294,10 +283,8 @@ __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restric
         for (int s = lane; s < NS; s += 64) out[s] = 0.0;
         return;
     }
-    int64_t kb, ke;
-    chunk_range(rec[R_MS], g, c, chunks, kb, ke);
     Segs S;
-    make_segments(rec, g, kb, ke, S);
+    load_segments(segs + (p * chunks + c) * kSegInts, S);
     LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, 0, 0, lane, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -308,12 +295,10 @@ __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restric
         }
     }
     const double a0p = rec[R_A0P];
-    const double sdh = wave_sum(seg.dh) * a0p;
-    const double shh = wave_sum(seg.hh) * (a0p * a0p);
-    if (lane == 0) {
-        out[0] = sdh;
-        out[1] = shh;
-    }
+    const double dv[2] = {seg.dh, seg.hh};
+    const double r = halving_reduce<2>(dv, lane);
+    if (lane == halving_lane<2>(0)) out[0] = r * a0p;
+    if (lane == halving_lane<2>(1)) out[1] = r * (a0p * a0p);
     if (MODE == 1 && lane < REC_N) out[2 + lane] = seg.tot;
 }
 
@@ -424,6 +409,7 @@ template <int PRG>
 __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict__ recs,
                                                         const double* __restrict__ tans, int64_t n, int chunks,
                                                         GridArgs g, const double* __restrict__ tab,
+                                                        const int* __restrict__ segs,
                                                         double* __restrict__ partial_all) {
     double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * 28;
     __shared__ double lds[4][7 * REC_N];
@@ -445,10 +431,8 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
         if (lane < 28) out[lane] = 0.0;
         return;
     }
-    int64_t kb, ke;
-    chunk_range(rec[R_MS], g, c, chunks, kb, ke);
     Segs S;
-    make_segments(rec, g, kb, ke, S);
+    load_segments(segs + (p * chunks + c) * kSegInts, S);
     FisherSegment seg;
     seg.rec = rec;
     seg.Tl = T;
@@ -465,11 +449,9 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
             dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);
         }
     }
-#pragma unroll
-    for (int s = 0; s < 28; ++s) {
-        const double t = wave_sum(seg.F[s]);
-        if (lane == 0) out[s] = t;
-    }
+    const double r = halving_reduce<28>(seg.F, lane);
+    const int entry = halving_entry<28>(lane);
+    if (entry < 28) out[entry] = r;
 }
 
 __global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restrict__ recs, int64_t n, int chunks,
@@ -509,6 +491,28 @@ __global__ void k_transitions(const double* __restrict__ recs, int64_t n, double
 // ==================================================================================
 // host-side launchers
 // ==================================================================================
+
+// Region segments of every (point, chunk), once per call.
+__global__ void k_segments(const double* __restrict__ recs, int64_t n, int chunks, GridArgs g,
+                           int* __restrict__ segs) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * chunks) return;
+    const int64_t p = t / chunks;
+    const int c = static_cast<int>(t - p * chunks);
+    const double* __restrict__ rec = recs + p * REC_N;
+    Segs S;
+    if (rec[R_VALID] == 0.0) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) S.k[i] = 0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) S.pr[i] = S.ar[i] = 0;
+    } else {
+        int64_t kb, ke;
+        chunk_range(rec[R_MS], g, c, chunks, kb, ke);
+        make_segments(rec, g, kb, ke, S);
+    }
+    store_segments(S, segs + t * kSegInts);
+}
 
 static inline unsigned blocks_for(int64_t threads, int per_block) {
     return static_cast<unsigned>((threads + per_block - 1) / per_block);
@@ -556,24 +560,25 @@ hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, con
 }
 
 hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                          const double* tab, double* partial, double* lnl, double* grad, hipStream_t s) {
+                          const double* tab, int* segs, double* partial, double* lnl, double* grad, hipStream_t s) {
     const int64_t waves = n * chunks;
     const unsigned nblk = blocks_for(waves, 4);
+    hipLaunchKernelGGL(k_segments, dim3(blocks_for(waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
     if (grad) {
         {
             ProfRange pr(PD_K_LOGLIKE_GRAD, s);
-            hipLaunchKernelGGL((k_loglike_moments<1, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
-            hipLaunchKernelGGL((k_loglike_moments<1, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
-            hipLaunchKernelGGL((k_loglike_moments<1, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<1, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
+            hipLaunchKernelGGL((k_loglike_moments<1, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
+            hipLaunchKernelGGL((k_loglike_moments<1, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
         }
         hipLaunchKernelGGL(k_loglike_epilogue<1>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
                            partial, lnl, grad);
     } else {
         {
             ProfRange pr(PD_K_LOGLIKE, s);
-            hipLaunchKernelGGL((k_loglike_moments<0, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
-            hipLaunchKernelGGL((k_loglike_moments<0, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
-            hipLaunchKernelGGL((k_loglike_moments<0, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, partial);
+            hipLaunchKernelGGL((k_loglike_moments<0, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
+            hipLaunchKernelGGL((k_loglike_moments<0, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
+            hipLaunchKernelGGL((k_loglike_moments<0, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
         }
         hipLaunchKernelGGL(k_loglike_epilogue<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
                            partial, lnl, grad);
@@ -582,16 +587,17 @@ hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int
 }
 
 hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                         const double* tab, double* partial, double* F, hipStream_t s) {
+                         const double* tab, int* segs, double* partial, double* F, hipStream_t s) {
     const int64_t waves = n * chunks;
+    hipLaunchKernelGGL(k_segments, dim3(blocks_for(waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
     {
         ProfRange pr(PD_K_FISHER, s);
         hipLaunchKernelGGL(k_fisher_partial<3>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
-                           g, tab, partial);
+                           g, tab, segs, partial);
         hipLaunchKernelGGL(k_fisher_partial<2>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
-                           g, tab, partial);
+                           g, tab, segs, partial);
         hipLaunchKernelGGL(k_fisher_partial<1>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
-                           g, tab, partial);
+                           g, tab, segs, partial);
     }
     hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks, partial, F);
     return hipGetLastError();

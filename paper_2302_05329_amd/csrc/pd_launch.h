@@ -33,10 +33,10 @@ hipError_t launch_tables(const GridArgs& g, const double* data, const double* in
 hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
                            double* h, hipStream_t s);
 hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                          const double* tab, double* partial, double* lnl, double* grad, hipStream_t s);
+                          const double* tab, int* segs, double* partial, double* lnl, double* grad, hipStream_t s);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                         const double* tab, double* partial, double* F, hipStream_t s);
+                         const double* tab, int* segs, double* partial, double* F, hipStream_t s);
 
 int posterior_check(const pd_posterior* post);
 size_t posterior_ws_bytes(const pd_posterior* post, int64_t n);

@@ -373,13 +373,7 @@ struct AdjSegment {
             MMVis vis{mom, cr, -ci};
             visit_bin_t<PR, AR>(rec, bv, vis);
         }
-#pragma unroll
-        for (int s = 0; s < REC_N; ++s) {
-            if (slot_touched(PR, AR, s)) {
-                const double t = wave_sum(mom[s]);
-                if (lane == s) tot += t;
-            }
-        }
+        flush_touched<PR, AR>(mom, lane, tot);
     }
 };
 
