@@ -2,18 +2,21 @@
 //
 // Each is a textbook construction written for this project: Cody-Waite argument
 // reduction with split constants and fused multiply-adds, then a polynomial on the
-// reduced interval.  The polynomial coefficients are Chebyshev interpolants computed in
-// 60-digit arithmetic and rounded to double (fit_elementary.py, next to this file); the
-// measured worst error of each polynomial on its interval is about 1 ulp.
+// reduced interval.  The atan and exp polynomial coefficients are Chebyshev interpolants
+// computed in 60-digit arithmetic and rounded to double, and the sin/cos table holds
+// correctly rounded values (fit_elementary.py, next to this file, writes both); the
+// measured worst error of each function is about 1 ulp.
 //
-//   pd_sincos  |x| <= 1e8 : q = rint(2x/pi), r = x - q pi/2 (three-part pi/2), sin/cos
-//              polynomials on |r| <= pi/4, quadrant by q mod 4.  Larger |x| falls back to
-//              the device library's sincos.
+//   pd_sincos  |x| <= 1e8 : q = rint(64x/pi), r = x - q pi/64 (three-part pi/64), short
+//              polynomials on |r| <= pi/128 combined with a 128-entry (sin, cos) table.
+//              Larger |x| falls back to the device library's sincos.
 //   pd_atan    |u| > 1 uses pi/2 - atan(1/u); t > tan(pi/12) uses atan(t) = pi/6 +
 //              atan((sqrt3 t - 1)/(t + sqrt3)); both reductions share one division.
 //   pd_exp     y = k ln2 + r (two-part ln2), |r| <= ln2/2, exp(y) = 2^k exp(r).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "pd_sincos_table.h"
 
 namespace pd {
 
@@ -26,52 +29,37 @@ __device__ __forceinline__ double sk(double c) {
     return c;
 }
 
-constexpr double kPio2_1 = 1.5707963267948966;
-constexpr double kPio2_2 = 6.123233995736766e-17;
-constexpr double kPio2_3 = -1.4973849048591698e-33;
-constexpr double kTwoOverPi = 0.6366197723675814;
-
-// sin(r) = r + r^3 S(r^2), cos(r) = 1 - r^2/2 + r^4 C(r^2) on |r| <= pi/4
-constexpr double kS0 = -1.6666666666666666666e-1, kS1 = 8.3333333333333314921e-3,
-                 kS2 = -1.9841269841265064899e-4, kS3 = 2.7557319219339129399e-6,
-                 kS4 = -2.5052106232434683791e-8, kS5 = 1.6058531616942477437e-10,
-                 kS6 = -7.5866969972366332944e-13;
-constexpr double kC0 = 4.1666666666666666666e-2, kC1 = -1.3888888888888887865e-3,
-                 kC2 = 2.4801587301584646402e-5, kC3 = -2.7557319221402803758e-7,
-                 kC4 = 2.08767557910732553e-9, kC5 = -1.1470460886473720733e-11,
-                 kC6 = 4.7458718350640028856e-14;
+// Table-driven sin and cos of one argument: x = k pi/64 + r with |r| <= pi/128 (three-part
+// pi/64, fused multiply-adds), j = k mod 128, and
+//   sin x = S_j + (S_j (cos r - 1) + C_j sin r),  cos x = C_j + (C_j (cos r - 1) - S_j sin r)
+// with (S_j, C_j) = (sin, cos)(j pi/64) correctly rounded (pd_sincos_table.h) and Taylor
+// polynomials on the small interval (sin r through r^9, cos r - 1 through r^8; the first omitted
+// terms are below 1e-19 relative).  About 1 ulp.  |x| > 1e8 uses the device library.
+constexpr double kTs1 = -1.0 / 6.0, kTs2 = 1.0 / 120.0, kTs3 = -1.0 / 5040.0, kTs4 = 1.0 / 362880.0;
+constexpr double kTc1 = -0.5, kTc2 = 1.0 / 24.0, kTc3 = -1.0 / 720.0, kTc4 = 1.0 / 40320.0;
 
 __device__ __forceinline__ void pd_sincos(double x, double* s_out, double* c_out) {
     if (!(fabs(x) <= sk(1e8))) {
         sincos(x, s_out, c_out);
         return;
     }
-    const double q = rint(x * sk(kTwoOverPi));
-    double r = fma(-q, sk(kPio2_1), x);
-    r = fma(-q, sk(kPio2_2), r);
-    r = fma(-q, sk(kPio2_3), r);
+    const double q = rint(x * sk(k64OverPi));
+    double r = fma(-q, sk(kPi64_1), x);
+    r = fma(-q, sk(kPi64_2), r);
+    r = fma(-q, sk(kPi64_3), r);
+    const unsigned j = static_cast<unsigned>(static_cast<int>(q)) & 127u;
+    const double2 sc = reinterpret_cast<const double2*>(kSinCosTab)[j];
     const double z = r * r;
-    double ps = fma(sk(kS6), z, sk(kS5));
-    ps = fma(ps, z, sk(kS4));
-    ps = fma(ps, z, sk(kS3));
-    ps = fma(ps, z, sk(kS2));
-    ps = fma(ps, z, sk(kS1));
-    ps = fma(ps, z, sk(kS0));
+    double ps = fma(sk(kTs4), z, sk(kTs3));
+    ps = fma(ps, z, sk(kTs2));
+    ps = fma(ps, z, sk(kTs1));
     const double sr = fma(r * z, ps, r);
-    double pc = fma(sk(kC6), z, sk(kC5));
-    pc = fma(pc, z, sk(kC4));
-    pc = fma(pc, z, sk(kC3));
-    pc = fma(pc, z, sk(kC2));
-    pc = fma(pc, z, sk(kC1));
-    pc = fma(pc, z, sk(kC0));
-    const double hz = 0.5 * z;
-    const double w = 1.0 - hz;
-    const double cr = w + (((1.0 - w) - hz) + z * z * pc);
-    const int j = static_cast<int>(static_cast<long long>(q) & 3);
-    const double a = (j & 1) ? cr : sr;
-    const double b = (j & 1) ? sr : cr;
-    *s_out = (j & 2) ? -a : a;
-    *c_out = ((j + 1) & 2) ? -b : b;
+    double pc = fma(sk(kTc4), z, sk(kTc3));
+    pc = fma(pc, z, sk(kTc2));
+    pc = fma(pc, z, sk(kTc1));
+    const double cm = z * pc;
+    *s_out = sc.x + fma(sc.y, sr, sc.x * cm);
+    *c_out = sc.y + fma(-sc.x, sr, sc.y * cm);
 }
 
 // Reciprocal and quotient for normal-range operands: hardware reciprocal estimate, two
