@@ -292,7 +292,7 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
         "min_ess_hmc": r["hmc"]["ess"], "min_ess_flow_mh": r["flow_hmc"]["ess"],
         "acceptance_hmc": r["hmc"]["acceptance"], "acceptance_flow_mh": r["flow_hmc"]["acceptance_flow"],
         "max_mean_diff_sigma": max(r["mean_diff_sigma"]), "max_std_diff_sigma": max(r["std_diff_sigma"]),
-        "chains": r["n_chains"], "steps": r["steps"], "n_leapfrog": r["n_leapfrog"],
+        "chains": r["n_chains"], "steps": r["steps"], "n_leapfrog": r["n_leapfrog"], "flow_mode": r["flow_mode"],
         "training_phase_s": r["flow_hmc"]["training_phase_seconds"]}
     return extra
 

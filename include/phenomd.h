@@ -225,22 +225,32 @@ int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, double*
  * and {3..6}, each with an MLP 7 -> 128 -> 128 -> 14 (tanh hidden units), log-scale bounded
  * as 2 tanh(./2).  log q(x) = log N(z; 0, I) + sum of log-determinants + sum log isd.
  * params: float32, per layer W1[7][128] b1[128] W2[128][128] b2[128] W3[128][14] b3[14],
- * 8 layers, then mu[7] and isd[7] (not trained).  FP32 arithmetic; x, z, log q in FP64.
+ * 8 layers, then mu[7] and isd[7] (not trained).  x, z, log q in FP64.
+ * mode: PD_FLOW_FP32 (all FP32 arithmetic) or PD_FLOW_BF16 (the hidden and output layers,
+ * and in training their gradient products, on the bfloat16 matrix cores with FP32
+ * accumulation; the rest FP32).  In either mode a fixed parameter vector defines a bijection
+ * whose log-determinant is the sum of the log-scales (s and t depend only on the dims a layer
+ * keeps), so the flow is a valid independence proposal; use the same mode for sampling and
+ * for log q.  Inverse-then-forward reproduces z to rounding except where rounding of the data
+ * coordinates moves an operand across a bfloat16 rounding boundary (then at bfloat16 level).
  * ------------------------------------------------------------------------------------- */
+typedef enum { PD_FLOW_FP32 = 0, PD_FLOW_BF16 = 1 } pd_flow_mode;
 int64_t pd_flow_param_count(void);
 size_t pd_flow_workspace_bytes(int64_t n);
 
 /* data -> latent: z [n][7] (or NULL) and log q(x) [n] for x [n][7]. */
-int pd_flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, void* stream);
+int pd_flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, int mode,
+                    void* stream);
 
 /* latent -> data: x [n][7] = f^-1(z) and log q(x) [n], for z [n][7] (standard-normal draws). */
-int pd_flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, void* stream);
+int pd_flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, int mode,
+                   void* stream);
 
 /* Maximum-likelihood training objective loss = -mean_b log q(x_b) over x [n][7] and its
  * gradient grad [P] w.r.t. params (the 14 standardisation entries get zero); loss [1] or NULL.
  * Workspace of pd_flow_workspace_bytes(n). */
 int pd_flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss,
-                      void* workspace, size_t workspace_bytes, void* stream);
+                      void* workspace, size_t workspace_bytes, int mode, void* stream);
 
 /* Adam (Kingma & Ba 2015) on count float32 parameters, step t >= 1 (bias-corrected). */
 int pd_adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr,

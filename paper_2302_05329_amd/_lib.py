@@ -41,6 +41,7 @@ PD_K_MISMATCH_FFT = 5
 PD_K_MISMATCH_ADJ = 6
 PD_K_OVERLAP = 7
 PD_OVERLAP_MAX_STREAMS = 64
+PD_FLOW_FP32, PD_FLOW_BF16 = 0, 1
 
 
 class PdGrid(ctypes.Structure):
@@ -88,9 +89,9 @@ SIGNATURES = {
     "pd_overlap": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_flow_param_count": (_I64, []),
     "pd_flow_workspace_bytes": (_SZ, [_I64]),
-    "pd_flow_forward": (_INT, [_P, _P, _I64, _P, _P, _P]),
-    "pd_flow_sample": (_INT, [_P, _P, _I64, _P, _P, _P]),
-    "pd_flow_loss_grad": (_INT, [_P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "pd_flow_forward": (_INT, [_P, _P, _I64, _P, _P, _INT, _P]),
+    "pd_flow_sample": (_INT, [_P, _P, _I64, _P, _P, _INT, _P]),
+    "pd_flow_loss_grad": (_INT, [_P, _P, _I64, _P, _P, _P, _SZ, _INT, _P]),
     "pd_adam_step": (_INT, [_P, _P, _P, _P, _I64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double, _I64, _P]),
     "pd_transition_frequencies": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _SZ, _P]),

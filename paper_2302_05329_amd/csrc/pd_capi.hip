@@ -424,27 +424,32 @@ int64_t pd_flow_param_count(void) { return pd::flow_param_count(); }
 
 size_t pd_flow_workspace_bytes(int64_t n) { return n > 0 ? pd::flow_ws_bytes(n) : 0; }
 
-int pd_flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, void* stream) {
+int pd_flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, int mode,
+                    void* stream) {
     if (!params || !x || !logq) return fail(PD_EINVAL, "NULL argument");
+    if (mode != PD_FLOW_FP32 && mode != PD_FLOW_BF16) return fail(PD_EINVAL, "unknown flow mode");
     if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
-    const int rc = pd::flow_forward(params, x, n, z, logq, static_cast<hipStream_t>(stream));
+    const int rc = pd::flow_forward(params, x, n, z, logq, mode, static_cast<hipStream_t>(stream));
     return rc == PD_OK ? PD_OK : fail(rc, "flow forward failed");
 }
 
-int pd_flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, void* stream) {
+int pd_flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, int mode,
+                   void* stream) {
     if (!params || !z || !x || !logq) return fail(PD_EINVAL, "NULL argument");
+    if (mode != PD_FLOW_FP32 && mode != PD_FLOW_BF16) return fail(PD_EINVAL, "unknown flow mode");
     if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
-    const int rc = pd::flow_sample(params, z, n, x, logq, static_cast<hipStream_t>(stream));
+    const int rc = pd::flow_sample(params, z, n, x, logq, mode, static_cast<hipStream_t>(stream));
     return rc == PD_OK ? PD_OK : fail(rc, "flow sample failed");
 }
 
 int pd_flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss, void* workspace,
-                      size_t workspace_bytes, void* stream) {
+                      size_t workspace_bytes, int mode, void* stream) {
     if (!params || !x || !grad) return fail(PD_EINVAL, "NULL argument");
+    if (mode != PD_FLOW_FP32 && mode != PD_FLOW_BF16) return fail(PD_EINVAL, "unknown flow mode");
     if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
     if (workspace_bytes < pd::flow_ws_bytes(n)) return fail(PD_ENOMEM, "workspace too small");
-    const int rc = pd::flow_loss_grad(params, x, n, grad, loss, workspace, static_cast<hipStream_t>(stream));
+    const int rc = pd::flow_loss_grad(params, x, n, grad, loss, workspace, mode, static_cast<hipStream_t>(stream));
     return rc == PD_OK ? PD_OK : fail(rc, "flow gradient failed");
 }
 

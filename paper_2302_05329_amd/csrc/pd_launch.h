@@ -59,9 +59,9 @@ hipError_t launch_overlap(const double* recs, int64_t nt, const GridArgs& g, con
 
 int64_t flow_param_count();
 size_t flow_ws_bytes(int64_t n);
-int flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, hipStream_t s);
-int flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, hipStream_t s);
-int flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss, void* ws,
+int flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, int mode, hipStream_t s);
+int flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, int mode, hipStream_t s);
+int flow_loss_grad(const float* params, const double* x, int64_t n, float* grad, double* loss, void* ws, int mode,
                    hipStream_t s);
 int adam_step(float* params, const float* grad, float* m, float* v, int64_t count, double lr, double b1, double b2,
               double eps, int64_t t, hipStream_t s);

@@ -23,9 +23,14 @@ def _x(t):
 
 
 class Flow:
-    """Parameters (float32, device) plus Adam state; the layout is the library's."""
+    """Parameters (float32, device) plus Adam state; the layout is the library's.  mode "fp32"
+    runs every layer in FP32; "bf16" runs the hidden and output layers (and their gradient
+    products) on the bfloat16 matrix cores with FP32 accumulation."""
 
-    def __init__(self, params):
+    def __init__(self, params, mode="fp32"):
+        if mode not in ("fp32", "bf16"):
+            raise ValueError("mode must be 'fp32' or 'bf16'")
+        self.mode = L.PD_FLOW_BF16 if mode == "bf16" else L.PD_FLOW_FP32
         p = torch.as_tensor(params, dtype=torch.float32, device="cuda").contiguous()
         if p.dim() != 1 or p.numel() != param_count():
             raise ValueError(f"flow parameters must be a vector of {param_count()} floats")
@@ -43,7 +48,7 @@ class Flow:
         n = x.shape[0]
         z = torch.empty_like(x) if want_z else None
         lq = torch.empty(n, dtype=torch.float64, device="cuda")
-        L.check(L.lib().pd_flow_forward(_ptr(self.params), _ptr(x), n, _ptr(z), _ptr(lq), _stream()))
+        L.check(L.lib().pd_flow_forward(_ptr(self.params), _ptr(x), n, _ptr(z), _ptr(lq), self.mode, _stream()))
         return z, lq
 
     def sample(self, z):
@@ -52,7 +57,7 @@ class Flow:
         n = z.shape[0]
         x = torch.empty_like(z)
         lq = torch.empty(n, dtype=torch.float64, device="cuda")
-        L.check(L.lib().pd_flow_sample(_ptr(self.params), _ptr(z), n, _ptr(x), _ptr(lq), _stream()))
+        L.check(L.lib().pd_flow_sample(_ptr(self.params), _ptr(z), n, _ptr(x), _ptr(lq), self.mode, _stream()))
         return x, lq
 
     def loss_grad(self, x):
@@ -61,7 +66,7 @@ class Flow:
         n = x.shape[0]
         wp, wb = self.ws.get(L.lib().pd_flow_workspace_bytes(n))
         L.check(L.lib().pd_flow_loss_grad(_ptr(self.params), _ptr(x), n, _ptr(self.grad), _ptr(self.loss), wp, wb,
-                                          _stream()))
+                                          self.mode, _stream()))
         return self.loss
 
     def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -133,13 +133,13 @@ def run_flow_hmc(hmc, fl, gen, steps):
     return np.stack(draws, axis=1), sec, float(acc_h) / steps, float(acc_m) / steps
 
 
-def train_flow(samples_x, gen, steps=1500, batch=4096, lr=1e-3, seed=1005, fl=None):
+def train_flow(samples_x, gen, steps=1500, batch=4096, lr=1e-3, seed=1005, fl=None, mode="bf16"):
     """Fit a flow to unconstrained chain states [m, 7] (device), starting from `fl` if given
     (its standardisation is kept) or from a fresh identity flow standardised on the samples;
     returns (flow, seconds, losses)."""
     if fl is None:
         mu, sd = flow.standardisation(samples_x)
-        fl = flow.Flow(W.flow_init_params(seed, mu=mu, sd=sd))
+        fl = flow.Flow(W.flow_init_params(seed, mu=mu, sd=sd), mode=mode)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = fl.fit(samples_x, steps, batch, lr, gen, log_every=max(1, steps // 10))
@@ -147,7 +147,7 @@ def train_flow(samples_x, gen, steps=1500, batch=4096, lr=1e-3, seed=1005, fl=No
     return fl, time.perf_counter() - t0, losses
 
 
-def flow_burn_in(hmc, gen, rounds=4, per_round=50, first_steps=1500, later_steps=500, log=None):
+def flow_burn_in(hmc, gen, rounds=4, per_round=50, first_steps=1500, later_steps=500, log=None, mode="bf16"):
     """Training phase: alternate `per_round` transitions (HMC, plus flow MH once a flow exists)
     with refitting the flow on the states of the last two rounds.  Returns (flow, seconds)."""
     fl = None
@@ -167,7 +167,8 @@ def flow_burn_in(hmc, gen, rounds=4, per_round=50, first_steps=1500, later_steps
                 acc_m += (fh.mh_step(z, u2) == 1).double().mean()
             states.append(hmc.x.clone())
         pool = pool[-1:] + [torch.cat(states)]
-        fl, _, losses = train_flow(torch.cat(pool), gen, steps=first_steps if fl is None else later_steps, fl=fl)
+        fl, _, losses = train_flow(torch.cat(pool), gen, steps=first_steps if fl is None else later_steps, fl=fl,
+                                   mode=mode)
         if log:
             log(f"burn-in round {r}: flow MH acceptance {float(acc_m) / per_round:.3f}, "
                 f"loss {losses[0]:.3f} -> {losses[-1]:.3f}")
@@ -181,7 +182,7 @@ def min_ess(draws):
 
 
 def compare(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, rounds=6, per_round=50, seed=1005,
-            n_bins=None, log=None):
+            n_bins=None, log=None, flow_mode="bf16"):
     """The full comparison; returns a dict of rates, acceptance and moment agreement.
 
     Chains start in a Fisher-scaled ball around the injection and are warmed up by HMC (mass
@@ -198,7 +199,7 @@ def compare(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, rounds=6, pe
     t0 = time.perf_counter()
     x0, mass0 = fisher_ball(pb, n_chains, rng)
     hmc, eps, mass = warmup(post, x0, gen, steps=warm, n_leapfrog=n_leapfrog, mass0=mass0, log=log)
-    fl, t_train = flow_burn_in(hmc, gen, rounds=rounds, per_round=per_round, log=log)
+    fl, t_train = flow_burn_in(hmc, gen, rounds=rounds, per_round=per_round, log=log, mode=flow_mode)
     t_warm = time.perf_counter() - t0 - t_train
     x_start = hmc.x.clone()
     hmc_a = sampling.HMC(post, x_start, eps, n_leapfrog, mass)
@@ -209,7 +210,7 @@ def compare(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, rounds=6, pe
     ma, sa = da.reshape(-1, 7).mean(axis=0), da.reshape(-1, 7).std(axis=0)
     mb, sb = db.reshape(-1, 7).mean(axis=0), db.reshape(-1, 7).std(axis=0)
     return dict(
-        n_chains=n_chains, steps=steps, n_leapfrog=n_leapfrog, eps=eps, n_bins=pb["grid"].n_bins,
+        n_chains=n_chains, steps=steps, n_leapfrog=n_leapfrog, eps=eps, n_bins=pb["grid"].n_bins, flow_mode=flow_mode,
         warmup_seconds=t_warm,
         hmc=dict(ess=ess_a, seconds=ta, ess_per_s=ess_a / ta, acceptance=acc_a),
         flow_hmc=dict(ess=ess_b, seconds=tb, ess_per_s=ess_b / tb, ess_per_s_incl_training=ess_b / (tb + t_train),

@@ -166,3 +166,71 @@ def test_flow_proposal_mh_keeps_the_target(gpu):
     g = hmc.grad.cpu().numpy()
     xs = hmc.x.cpu().numpy()
     assert np.allclose(g, -(xs - mu) / sig**2, rtol=1e-12, atol=1e-12)
+
+
+# ---- bfloat16 matrix-core mode -------------------------------------------------------------
+# Operands of the hidden and output layers are rounded to bfloat16 (unit roundoff 2^-8) and
+# accumulated in FP32.  A float32 emulation of this rounding on these inputs gives relative z
+# errors up to ~1e-2 and log q errors up to ~0.3 (mean ~0.02) through the 8 layers, so parity
+# with the float64 oracle is checked at those scales; the mode's own consistency (inverse then
+# forward returns z and the same log q) is checked at float32 scale, since that is what makes
+# the bf16 flow an exact proposal.
+
+
+@pytest.mark.parametrize("n", [1, 33, 1000])
+def test_bf16_forward_sample_parity_and_self_consistency(gpu, n):
+    from paper_2302_05329_amd import flow
+    p, x, sd = _setup(n)
+    fl = flow.Flow(p, mode="bf16")
+    _say(f"bf16 flow forward/sample n={n}")
+    z, lq = fl.forward(x)
+    zr, lqr = F.forward(p, x)
+    z, lq, zr, lqr = z.cpu().numpy(), lq.cpu().numpy(), zr.numpy(), lqr.numpy()
+    assert np.all(np.abs(z - zr) <= 5e-2 * (1 + np.abs(zr)))
+    assert np.all(np.abs(lq - lqr) <= 1.0 + 0.02 * np.abs(lqr))
+    assert np.mean(np.abs(lq - lqr)) <= 0.1
+    zs = np.random.default_rng(n).standard_normal((n, 7))
+    xs, lqs = fl.sample(torch.as_tensor(zs, device="cuda"))
+    z2, lq2 = fl.forward(xs)
+    z2, lq2, lqs = z2.cpu().numpy(), lq2.cpu().numpy(), lqs.cpu().numpy()
+    # inverse then forward: the same map up to float32 rounding of the data coordinates, which can
+    # move an operand across a bfloat16 rounding boundary for a small fraction of points
+    close = np.all(np.abs(z2 - zs) <= 1e-4 * (1 + np.abs(zs)), axis=1) & (np.abs(lq2 - lqs) <= 1e-3 * (1 + np.abs(lqs) / 10))
+    _say(f"bf16 inverse/forward agreement at float32 scale: {close.mean():.4f}")
+    assert close.mean() >= 0.9
+    assert np.all(np.abs(z2 - zs) <= 5e-2 * (1 + np.abs(zs)))
+    assert np.all(np.abs(lq2 - lqs) <= 0.5)
+
+
+@pytest.mark.parametrize("n", [7, 100, 513])
+def test_bf16_loss_and_gradient_parity(gpu, n):
+    from paper_2302_05329_amd import flow
+    p, x, _ = _setup(n, seed=12, out_scale=0.7)
+    fl = flow.Flow(p, mode="bf16")
+    _say(f"bf16 flow loss/grad n={n}")
+    loss = float(fl.loss_grad(x).item())
+    g = fl.grad.cpu().numpy().astype(np.float64)
+    lr, gr = F.loss_grad(p, x)
+    assert abs(loss - lr) <= 0.1 + 0.02 * abs(lr)
+    assert np.all(g[-14:] == 0.0)
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    _say(f"bf16 gradient relative error {rel:.3e}")
+    assert rel <= 2e-2
+
+
+def test_bf16_training_fits_a_gaussian(gpu):
+    from paper_2302_05329_amd import flow
+    mean, cov, xa = W.correlated_gaussian(16384 + 4096, 21)
+    x, xt = xa[:16384], xa[16384:]
+    m0, s0 = flow.standardisation(x)
+    fl = flow.Flow(W.flow_init_params(23, mu=m0, sd=s0), mode="bf16")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(23)
+    _, lq0 = fl.forward(xt, want_z=False)
+    _say("bf16 flow training 400 steps")
+    fl.fit(x, 400, 512, 2e-3, gen)
+    _, lq1 = fl.forward(xt, want_z=False)
+    entropy = 0.5 * np.linalg.slogdet(2 * math.pi * math.e * cov)[1]
+    l0, l1 = -float(lq0.mean()), -float(lq1.mean())
+    assert l1 < l0 - 0.1
+    assert l1 - entropy < 0.1, (l0, l1, entropy)
