@@ -283,8 +283,13 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     # learned proposal, C5: 4096 chains on one SNR-20 injection, 8033 bins
     from paper_2302_05329_amd import learned_proposal as LP
     log("[bench] C5 flow-MH vs HMC")
-    r = LP.compare(lam, n_chains=4096, log=log)
-    extra["C5_flow_mh_vs_hmc"] = {
+    for key, mode in (("C5_flow_mh_vs_hmc", "bf16"), ("C5_flow_mh_vs_hmc_fp32_flow", "fp32")):
+        extra[key] = c5_summary(LP.compare(lam, n_chains=4096, log=log, flow_mode=mode))
+    return extra
+
+
+def c5_summary(r):
+    return {
         "ess_per_s_hmc": r["hmc"]["ess_per_s"], "ess_per_s_flow_mh": r["flow_hmc"]["ess_per_s"],
         "ess_per_s_flow_mh_incl_training": r["flow_hmc"]["ess_per_s_incl_training"],
         "speedup": r["flow_hmc"]["ess_per_s"] / r["hmc"]["ess_per_s"],
@@ -294,7 +299,6 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
         "max_mean_diff_sigma": max(r["mean_diff_sigma"]), "max_std_diff_sigma": max(r["std_diff_sigma"]),
         "chains": r["n_chains"], "steps": r["steps"], "n_leapfrog": r["n_leapfrog"], "flow_mode": r["flow_mode"],
         "training_phase_s": r["flow_hmc"]["training_phase_seconds"]}
-    return extra
 
 
 def cpu_baseline(W, c2, seconds):
