@@ -86,8 +86,6 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             break;
         case PD_OP_LOGLIKE_GRAD:
             L.chunks = pd::chunks_for(n, nb);
-            L.tan = off;
-            off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * pd::kNSlot * sizeof(double));
             L.seg = off;
@@ -231,18 +229,14 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* recs = at<double>(workspace, L.rec);
-    double* tans = grad ? at<double>(workspace, L.tan) : nullptr;
     double* partial = at<double>(workspace, L.partial);
     double* tab = at<double>(workspace, L.tab);
     hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
     if (e != hipSuccess) return fail_hip(e, "setup");
-    if (grad) {
-        e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, recs, tans, s);
-        if (e != hipSuccess) return fail_hip(e, "setup tangents");
-    }
     e = pd::launch_tables(g, data, inv_psd, tab, s);
     if (e != hipSuccess) return fail_hip(e, "tables");
-    e = pd::launch_loglike(recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl, grad, s);
+    e = pd::launch_loglike(theta, param, lambda, recs, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl,
+                           grad, s);
     if (e != hipSuccess) return fail_hip(e, "loglike");
     return PD_OK;
 }

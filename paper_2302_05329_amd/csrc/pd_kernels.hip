@@ -69,6 +69,23 @@ __global__ void __launch_bounds__(128) k_setup_value(const double* __restrict__ 
     if (status) status[i] = ok ? 0 : -2;
 }
 
+// d rec / d theta[dir] for one of the four intrinsic entries (dir < 4), by forward mode with a
+// single tangent; returns M_s.
+__device__ __forceinline__ double intrinsic_tangent(const double* __restrict__ th_row, int param, double f_ref,
+                                                    const double* __restrict__ lam, int dir, double tg[REC_N]) {
+    using D = Dual<1>;
+    D th[7];
+    for (int j = 0; j < 7; ++j) th[j] = dconst<1>(th_row[j]);
+    th[dir].d[0] = 1.0;
+    const Source<D> s = source_map(th, param);
+    D fit[kNumFit];
+    fit_params(lam, s.eta, s.chi_pn, fit);
+    D rec[REC_N];
+    build_record(s, fit, f_ref, rec);
+    for (int j = 0; j < REC_N; ++j) tg[j] = rec[j].d[0];
+    return rec[R_MS].v;
+}
+
 // Record tangents along the 7 entries of theta.  The four intrinsic entries (masses or
 // chirp mass and mass ratio, two spins) go through the setup in forward mode, one thread per
 // (point, direction) with a single tangent (Dual<1>) so the live state stays small; the
@@ -92,18 +109,10 @@ __global__ void __launch_bounds__(64) k_setup_theta_tangent(const double* __rest
         for (int j = 0; j < REC_N; ++j) out[dir * REC_N + j] = 0.0;
         return;
     }
-    using D = Dual<1>;
-    D th[7];
-    for (int j = 0; j < 7; ++j) th[j] = dconst<1>(theta[i * 7 + j]);
-    th[dir].d[0] = 1.0;
-    const Source<D> s = source_map(th, param);
-    D fit[kNumFit];
-    fit_params(lam, s.eta, s.chi_pn, fit);
-    D rec[REC_N];
-    build_record(s, fit, f_ref, rec);
-    for (int j = 0; j < REC_N; ++j) out[dir * REC_N + j] = rec[j].d[0];
+    double tg[REC_N];
+    const double ms = intrinsic_tangent(theta + i * 7, param, f_ref, lam, dir, tg);
+    for (int j = 0; j < REC_N; ++j) out[dir * REC_N + j] = tg[j];
     if (dir != 0) return;
-    const double ms = rec[R_MS].v;
     out[4 * REC_N + R_LNA0] = (param == 1) ? -1.0 : -1.0 / theta[i * 7 + 4];
     const double dlin = 2.0 * kPi / ms;
     out[5 * REC_N + R_PH1 + 9] = dlin / kPi;
@@ -339,6 +348,51 @@ __global__ void __launch_bounds__(128) k_loglike_epilogue(const double* __restri
     }
 }
 
+// Four threads per point (intrinsic direction dir): the record tangent along that direction is
+// computed here (forward mode) and contracted with the moment sums straight away, so no tangent
+// array is stored; thread dir 0 also writes ln L and the three extrinsic entries, whose record
+// tangents are closed-form (D or ln D only through ln A0, tc only through the Mf-linear phase
+// coefficient 2 pi tc / Ms, phic only through the constant phase term -2 phic).
+__global__ void __launch_bounds__(128) k_loglike_grad_epilogue(const double* __restrict__ theta, int64_t n,
+                                                               int param, double f_ref,
+                                                               const double* __restrict__ lam,
+                                                               const double* __restrict__ recs, int chunks,
+                                                               const double* __restrict__ partial,
+                                                               double* __restrict__ lnl, double* __restrict__ grad) {
+    constexpr int NS = kNSlot;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * 4) return;
+    const int64_t p = t >> 2;
+    const int dir = static_cast<int>(t & 3);
+    const double* rec = recs + p * REC_N;
+    if (rec[R_VALID] == 0.0) {
+        const double nan = __builtin_nan("");
+        if (dir == 0) {
+            lnl[p] = nan;
+            for (int q = 0; q < 7; ++q) grad[p * 7 + q] = nan;
+        }
+        return;
+    }
+    auto msum = [&](int slot) {
+        double a = 0.0;
+        for (int grp = 0; grp < 3; ++grp)
+            for (int c = 0; c < chunks; ++c) a += partial[((grp * n + p) * chunks + c) * NS + slot];
+        return a;
+    };
+    double tg[REC_N];
+    const double ms = intrinsic_tangent(theta + p * 7, param, f_ref, lam, dir, tg);
+    double gq = tg[R_MS] / ms * msum(2 + R_MS) + tg[R_LNA0] * msum(2 + R_LNA0);
+#pragma unroll
+    for (int s = R_PH1; s < R_VALID; ++s) gq += tg[s] * msum(2 + s);
+    grad[p * 7 + dir] = gq;
+    if (dir != 0) return;
+    lnl[p] = msum(0) - 0.5 * msum(1);
+    const double dlin = 2.0 * kPi / ms;
+    grad[p * 7 + 4] = ((param == 1) ? -1.0 : -1.0 / theta[p * 7 + 4]) * msum(2 + R_LNA0);
+    grad[p * 7 + 5] = dlin * (msum(2 + R_PH1 + 9) / kPi + msum(2 + R_PH2 + 1) + msum(2 + R_PH3 + 1));
+    grad[p * 7 + 6] = -2.0 * (msum(2 + R_PH1 + 4) + msum(2 + R_PH2 + 0) + msum(2 + R_PH3 + 0));
+}
+
 // ==================================================================================
 // Fisher matrices
 // ==================================================================================
@@ -559,8 +613,9 @@ hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, con
     return hipGetLastError();
 }
 
-hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                          const double* tab, int* segs, double* partial, double* lnl, double* grad, hipStream_t s) {
+hipError_t launch_loglike(const double* theta, int param, const double* lam, const double* recs, int64_t n, int chunks,
+                          const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl, double* grad,
+                          hipStream_t s) {
     const int64_t waves = n * chunks;
     const unsigned nblk = blocks_for(waves, 4);
     hipLaunchKernelGGL(k_segments, dim3(blocks_for(waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
@@ -571,8 +626,8 @@ hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int
             hipLaunchKernelGGL((k_loglike_moments<1, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
             hipLaunchKernelGGL((k_loglike_moments<1, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
         }
-        hipLaunchKernelGGL(k_loglike_epilogue<1>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
-                           partial, lnl, grad);
+        hipLaunchKernelGGL(k_loglike_grad_epilogue, dim3(blocks_for(4 * n, 128)), dim3(128), 0, s, theta, n, param,
+                           g.fref, lam, recs, chunks, partial, lnl, grad);
     } else {
         {
             ProfRange pr(PD_K_LOGLIKE, s);
@@ -580,8 +635,8 @@ hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int
             hipLaunchKernelGGL((k_loglike_moments<0, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
             hipLaunchKernelGGL((k_loglike_moments<0, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
         }
-        hipLaunchKernelGGL(k_loglike_epilogue<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, tans, n, chunks,
-                           partial, lnl, grad);
+        hipLaunchKernelGGL(k_loglike_epilogue<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, nullptr, n,
+                           chunks, partial, lnl, grad);
     }
     return hipGetLastError();
 }

@@ -32,8 +32,9 @@ hipError_t launch_tables(const GridArgs& g, const double* data, const double* in
                          hipStream_t s);
 hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
                            double* h, hipStream_t s);
-hipError_t launch_loglike(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                          const double* tab, int* segs, double* partial, double* lnl, double* grad, hipStream_t s);
+hipError_t launch_loglike(const double* theta, int param, const double* lam, const double* recs, int64_t n, int chunks,
+                          const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl, double* grad,
+                          hipStream_t s);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
                          const double* tab, int* segs, double* partial, double* F, hipStream_t s);

@@ -160,34 +160,6 @@ __device__ __forceinline__ void fit_basis(const T& eta, const T& chi_pn, T b[11]
     b[10] = x3 * e2;
 }
 
-// Linear solve of a 5x5 system by Gaussian elimination with partial pivoting (on values).
-template <class T>
-__device__ __forceinline__ void solve5(T a[5][5], T b[5], T x[5]) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        int piv = c;
-        double best = fabs(val(a[c][c]));
-        for (int r = c + 1; r < 5; ++r) {
-            const double m = fabs(val(a[r][c]));
-            if (m > best) { best = m; piv = r; }
-        }
-        if (piv != c) {
-            for (int k = 0; k < 5; ++k) { T t = a[c][k]; a[c][k] = a[piv][k]; a[piv][k] = t; }
-            T t = b[c]; b[c] = b[piv]; b[piv] = t;
-        }
-        for (int r = c + 1; r < 5; ++r) {
-            const T m = a[r][c] / a[c][c];
-            for (int k = c; k < 5; ++k) a[r][k] = a[r][k] - m * a[c][k];
-            b[r] = b[r] - m * b[c];
-        }
-    }
-    for (int r = 4; r >= 0; --r) {
-        T acc = b[r];
-        for (int k = r + 1; k < 5; ++k) acc = acc - a[r][k] * x[k];
-        x[r] = acc / a[r][r];
-    }
-}
-
 // Exponents of the 13 inspiral phase basis functions in v (ln-terms get special handling).
 __device__ constexpr double kPh1Pow[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
 
@@ -390,35 +362,43 @@ __device__ __forceinline__ bool build_record(const Source<T>& s, const T lam[kNu
     const T fa2 = 0.5 * (fa1 + fa3);
     T ains, fdains;
     amp_ins_eval(am1, fa1, ains, fdains);
-    T A[5][5], rhs[5], dl[5];
+    // Intermediate amplitude: the quartic matching value and slope at fa1, the value v2 at fa2,
+    // and value and slope at fa3 is the Hermite interpolant on the nodes (fa1, fa1, fa2, fa3,
+    // fa3): confluent divided differences give its Newton form, expanded here to monomial
+    // coefficients (no pivoting and no dynamic indexing, so every value stays in registers).
+    T dl[5];
     {
-        const T* fs[3] = {&fa1, &fa2, &fa3};
-        // rows: value at fa1, slope at fa1, value at fa2, value at fa3, slope at fa3
-        const int kind[5] = {0, 1, 0, 0, 1};
-        const int which[5] = {0, 0, 1, 2, 2};
-        for (int r = 0; r < 5; ++r) {
-            const T f = *fs[which[r]];
-            if (kind[r] == 0) {
-                A[r][0] = K<T>(1.0);
-                A[r][1] = f;
-                A[r][2] = f * f;
-                A[r][3] = A[r][2] * f;
-                A[r][4] = A[r][3] * f;
-            } else {
-                A[r][0] = K<T>(0.0);
-                A[r][1] = K<T>(1.0);
-                A[r][2] = 2.0 * f;
-                A[r][3] = 3.0 * f * f;
-                A[r][4] = 4.0 * f * f * f;
-            }
-        }
-        rhs[0] = ains;
-        rhs[1] = fdains / fa1;
-        rhs[2] = lam[L_V2];
-        rhs[3] = amp_mrd(fa3);
-        rhs[4] = damp_mrd(fa3);
+        const T y1 = ains, d1 = fdains / fa1, y2 = lam[L_V2], y3 = amp_mrd(fa3), d3 = damp_mrd(fa3);
+        const T h12 = fa2 - fa1, h23 = fa3 - fa2, h13 = fa3 - fa1;
+        const T f12 = (y2 - y1) / h12, f23 = (y3 - y2) / h23;
+        const T f112 = (f12 - d1) / h12;          // [a, a, b]
+        const T f123 = (f23 - f12) / h13;         // [a, b, c]
+        const T f233 = (d3 - f23) / h23;          // [b, c, c]
+        const T f1123 = (f123 - f112) / h13;      // [a, a, b, c]
+        const T f1233 = (f233 - f123) / h13;      // [a, b, c, c]
+        const T f11233 = (f1233 - f1123) / h13;   // [a, a, b, c, c]
+        // P(x) = y1 + (x - a)(d1 + (x - a)(f112 + (x - b)(f1123 + (x - c) f11233)))
+        T q[5];
+        q[0] = f11233;                                       // degree 0
+        // q <- f1123 + (x - c) q
+        q[1] = q[0];
+        q[0] = f1123 - fa3 * q[1];
+        // q <- f112 + (x - b) q
+        q[2] = q[1];
+        q[1] = q[0] - fa2 * q[2];
+        q[0] = f112 - fa2 * q[0];
+        // q <- d1 + (x - a) q
+        q[3] = q[2];
+        q[2] = q[1] - fa1 * q[3];
+        q[1] = q[0] - fa1 * q[1];
+        q[0] = d1 - fa1 * q[0];
+        // P <- y1 + (x - a) q
+        dl[4] = q[3];
+        dl[3] = q[2] - fa1 * q[3];
+        dl[2] = q[1] - fa1 * q[2];
+        dl[1] = q[0] - fa1 * q[1];
+        dl[0] = y1 - fa1 * q[0];
     }
-    solve5(A, rhs, dl);
 
     // ---- alignment ----------------------------------------------------------------------
     const T t0 = dphi_mrd_raw(f_peak) + c2_mrd;
