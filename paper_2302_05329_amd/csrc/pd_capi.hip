@@ -96,7 +96,7 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.tan = off;
             off = align_up(off + N * 7 * pd::REC_N * sizeof(double));
             L.partial = off;
-            off = align_up(off + 3 * N * L.chunks * 28 * sizeof(double));
+            off = align_up(off + 3 * N * L.chunks * pd::kFisherSlots * sizeof(double));
             L.seg = off;
             off = align_up(off + N * L.chunks * pd::kSegInts * sizeof(int));
             break;
@@ -263,7 +263,7 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, co
     if (e != hipSuccess) return fail_hip(e, "setup tangents");
     e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
     if (e != hipSuccess) return fail_hip(e, "tables");
-    e = pd::launch_fisher(recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, F, s);
+    e = pd::launch_fisher(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, F, s);
     if (e != hipSuccess) return fail_hip(e, "fisher");
     return PD_OK;
 }

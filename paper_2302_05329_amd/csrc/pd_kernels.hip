@@ -397,27 +397,37 @@ __global__ void __launch_bounds__(128) k_loglike_grad_epilogue(const double* __r
 // Fisher matrices
 // ==================================================================================
 
+// Per-bin derivatives of Psi and ln A along the four intrinsic directions (record tangents in
+// LDS).  The extrinsic directions need no tangents: d ln A / d(D or ln D) is a per-point
+// constant, d Psi / d tc = 2 pi f and d Psi / d phic = -2, so their Fisher entries come from
+// weighted moments (see kFisherAcc).
+constexpr int kFisherDirs = 4;
 struct FisherVis {
-    const double* T;   // [7][REC_N] tangents in LDS
+    const double* T;   // [4][REC_N] tangents in LDS
     double ims;
-    double dpsi[7], dlna[7];
+    double dpsi[kFisherDirs], dlna[kFisherDirs];
     __device__ __forceinline__ void ph(int s, double b) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) dpsi[q] = fma(T[q * REC_N + s], b, dpsi[q]);
+        for (int q = 0; q < kFisherDirs; ++q) dpsi[q] = fma(T[q * REC_N + s], b, dpsi[q]);
     }
     __device__ __forceinline__ void am(int s, double b) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) dlna[q] = fma(T[q * REC_N + s], b, dlna[q]);
+        for (int q = 0; q < kFisherDirs; ++q) dlna[q] = fma(T[q * REC_N + s], b, dlna[q]);
     }
     __device__ __forceinline__ void fd(double fpsi, double fa) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) {
+        for (int q = 0; q < kFisherDirs; ++q) {
             const double m = T[q * REC_N + R_MS] * ims;
             dpsi[q] = fma(m, fpsi, dpsi[q]);
             dlna[q] = fma(m, fa, dlna[q]);
         }
     }
 };
+
+// Per point and chunk: [0, 10) sum W (dlna_a dlna_b + dpsi_a dpsi_b), a <= b < 4;
+// [10, 14) sum W dlna_a; [14, 18) sum W f dpsi_a; [18, 22) sum W dpsi_a; 22..24: sum W, W f, W f^2,
+// with W = w |h|^2 and f the frequency in Hz.
+constexpr int kFisherAcc = kFisherSlots;
 
 struct FisherSegment {
     const double* __restrict__ rec;
@@ -426,7 +436,7 @@ struct FisherSegment {
     GridArgs g;
     int64_t k0, k1;
     int lane;
-    double F[28];
+    double F[kFisherAcc];
 
     template <int PR, int AR>
     __device__ __forceinline__ void run() {
@@ -443,30 +453,41 @@ struct FisherSegment {
             vis.T = Tl;
             vis.ims = rec[R_IMS];
 #pragma unroll
-            for (int q = 0; q < 7; ++q) vis.dpsi[q] = vis.dlna[q] = 0.0;
+            for (int q = 0; q < kFisherDirs; ++q) vis.dpsi[q] = vis.dlna[q] = 0.0;
             visit_bin_t<PR, AR>(rec, bv, vis);
             int s = 0;
 #pragma unroll
-            for (int a = 0; a < 7; ++a) {
+            for (int a = 0; a < kFisherDirs; ++a) {
                 const double wa = W * vis.dlna[a], wp = W * vis.dpsi[a];
 #pragma unroll
-                for (int b = a; b < 7; ++b) {
+                for (int b = a; b < kFisherDirs; ++b) {
                     F[s] = fma(wa, vis.dlna[b], fma(wp, vis.dpsi[b], F[s]));
                     ++s;
                 }
             }
+            const double f = bin_freq(g, k);
+            const double Wf = W * f;
+#pragma unroll
+            for (int a = 0; a < kFisherDirs; ++a) {
+                F[10 + a] = fma(W, vis.dlna[a], F[10 + a]);
+                F[14 + a] = fma(Wf, vis.dpsi[a], F[14 + a]);
+                F[18 + a] = fma(W, vis.dpsi[a], F[18 + a]);
+            }
+            F[22] += W;
+            F[23] += Wf;
+            F[24] = fma(Wf, f, F[24]);
         }
     }
 };
 
 template <int PRG>
-__global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict__ recs,
+__global__ void __launch_bounds__(256, (PRG == 1) ? 1 : 3) k_fisher_partial(const double* __restrict__ recs,
                                                         const double* __restrict__ tans, int64_t n, int chunks,
                                                         GridArgs g, const double* __restrict__ tab,
                                                         const int* __restrict__ segs,
                                                         double* __restrict__ partial_all) {
-    double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * 28;
-    __shared__ double lds[4][7 * REC_N];
+    double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * kFisherAcc;
+    __shared__ double lds[4][kFisherDirs * REC_N];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + wib));
@@ -475,14 +496,14 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
     const bool live = p < n;
     double* T = lds[wib];
     if (live) {
-        for (int j = lane; j < 7 * REC_N; j += 64) T[j] = tans[p * 7 * REC_N + j];
+        for (int j = lane; j < kFisherDirs * REC_N; j += 64) T[j] = tans[p * 7 * REC_N + j];
     }
     __syncthreads();
     if (!live) return;
     const double* __restrict__ rec = recs + p * REC_N;
-    double* __restrict__ out = partial + (p * chunks + c) * 28;
+    double* __restrict__ out = partial + (p * chunks + c) * kFisherAcc;
     if (rec[R_VALID] == 0.0) {
-        if (lane < 28) out[lane] = 0.0;
+        if (lane < kFisherAcc) out[lane] = 0.0;
         return;
     }
     Segs S;
@@ -494,7 +515,7 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
     seg.g = g;
     seg.lane = lane;
 #pragma unroll
-    for (int s = 0; s < 28; ++s) seg.F[s] = 0.0;
+    for (int s = 0; s < kFisherAcc; ++s) seg.F[s] = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         if (uniform_i(S.k[i + 1]) > uniform_i(S.k[i]) && uniform_i(S.pr[i]) == PRG) {
@@ -503,12 +524,13 @@ __global__ void __launch_bounds__(256) k_fisher_partial(const double* __restrict
             dispatch_amp_region<PRG>(uniform_i(S.ar[i]), seg);
         }
     }
-    const double r = halving_reduce<28>(seg.F, lane);
-    const int entry = halving_entry<28>(lane);
-    if (entry < 28) out[entry] = r;
+    const double r = halving_reduce<kFisherAcc>(seg.F, lane);
+    const int entry = halving_entry<kFisherAcc>(lane);
+    if (entry < kFisherAcc) out[entry] = r;
 }
 
-__global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restrict__ recs, int64_t n, int chunks,
+__global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restrict__ theta, int param,
+                                                         const double* __restrict__ recs, int64_t n, int chunks,
                                                          const double* __restrict__ partial,
                                                          double* __restrict__ F) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -518,17 +540,39 @@ __global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restric
         for (int j = 0; j < 49; ++j) out[j] = __builtin_nan("");
         return;
     }
-    double acc[28];
-    for (int s = 0; s < 28; ++s) acc[s] = 0.0;
+    double acc[kFisherAcc];
+#pragma unroll
+    for (int s = 0; s < kFisherAcc; ++s) acc[s] = 0.0;
     for (int grp = 0; grp < 3; ++grp)
         for (int c = 0; c < chunks; ++c)
-            for (int s = 0; s < 28; ++s) acc[s] += partial[((grp * n + p) * chunks + c) * 28 + s];
+#pragma unroll
+            for (int s = 0; s < kFisherAcc; ++s) acc[s] += partial[((grp * n + p) * chunks + c) * kFisherAcc + s];
+    // d ln A / d theta_4 (distance or its logarithm); d Psi / d tc = 2 pi f; d Psi / d phic = -2
+    const double e4 = (param == 1) ? -1.0 : -1.0 / theta[p * 7 + 4];
+    double M[7][7];
     int s = 0;
+#pragma unroll
+    for (int a = 0; a < kFisherDirs; ++a)
+#pragma unroll
+        for (int b = a; b < kFisherDirs; ++b) M[a][b] = acc[s++];
+#pragma unroll
+    for (int a = 0; a < kFisherDirs; ++a) {
+        M[a][4] = e4 * acc[10 + a];
+        M[a][5] = 2.0 * kPi * acc[14 + a];
+        M[a][6] = -2.0 * acc[18 + a];
+    }
+    M[4][4] = e4 * e4 * acc[22];
+    M[4][5] = 0.0;
+    M[4][6] = 0.0;
+    M[5][5] = 4.0 * kPi * kPi * acc[24];
+    M[5][6] = -4.0 * kPi * acc[23];
+    M[6][6] = 4.0 * acc[22];
+#pragma unroll
     for (int a = 0; a < 7; ++a)
+#pragma unroll
         for (int b = a; b < 7; ++b) {
-            out[a * 7 + b] = acc[s];
-            out[b * 7 + a] = acc[s];
-            ++s;
+            out[a * 7 + b] = M[a][b];
+            out[b * 7 + a] = M[a][b];
         }
 }
 
@@ -641,8 +685,9 @@ hipError_t launch_loglike(const double* theta, int param, const double* lam, con
     return hipGetLastError();
 }
 
-hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                         const double* tab, int* segs, double* partial, double* F, hipStream_t s) {
+hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
+                         int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* F,
+                         hipStream_t s) {
     const int64_t waves = n * chunks;
     hipLaunchKernelGGL(k_segments, dim3(blocks_for(waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
     {
@@ -654,7 +699,8 @@ hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int 
         hipLaunchKernelGGL(k_fisher_partial<1>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
                            g, tab, segs, partial);
     }
-    hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks, partial, F);
+    hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, param, recs, n, chunks,
+                       partial, F);
     return hipGetLastError();
 }
 

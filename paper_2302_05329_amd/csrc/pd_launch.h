@@ -10,6 +10,7 @@
 namespace pd {
 
 constexpr int kNSlot = 2 + REC_N;   // (d|h), (h|h), then one moment per record entry
+constexpr int kFisherSlots = 25;    // per-chunk Fisher sums (4 intrinsic directions + moments)
 
 // Bin-chunking policy: enough wavefronts to fill the chip even for small batches.
 inline int chunks_for(int64_t n, int64_t n_bins) {
@@ -36,8 +37,9 @@ hipError_t launch_loglike(const double* theta, int param, const double* lam, con
                           const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl, double* grad,
                           hipStream_t s);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
-hipError_t launch_fisher(const double* recs, const double* tans, int64_t n, int chunks, const GridArgs& g,
-                         const double* tab, int* segs, double* partial, double* F, hipStream_t s);
+hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
+                         int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* F,
+                         hipStream_t s);
 
 int posterior_check(const pd_posterior* post);
 size_t posterior_ws_bytes(const pd_posterior* post, int64_t n);

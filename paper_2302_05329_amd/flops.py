@@ -30,10 +30,12 @@ LNL_EPILOGUE = 1 + 5 + 5                                          # w_k, (d|h), 
 GRAD_COMMON = 2 + 8 + 1 + 5                                       # d - h, zr, zi, lnA0 moment, Mf moment
 PHASE_GRAD = {1: 63, 2: 13, 3: 25}
 AMP_GRAD = {1: 48, 2: 23, 3: 16}
-# Fisher: per-bin tangents along 7 directions + 28 entries --------------------------------
-FISHER_COMMON = 1 + 2 + 7 * 4 + 28 * 4                            # W, explicit-Mf terms, accumulation
-PHASE_FISHER = {1: 8 + 7 * 26 + 26, 2: 7 * 8 + 5, 3: 2 + 7 * 14 + 8}
-AMP_FISHER = {1: 1 + 9 + 7 * 20 + 18, 2: 1 + 4 + 7 * 10 + 8, 3: 5 + 7 * 8 + 2}
+# Fisher: per-bin tangents along the 4 intrinsic directions (the extrinsic ones are closed
+# form: d ln A / d ln D constant, d Psi / d tc = 2 pi f, d Psi / d phic = -2), 10 intrinsic
+# products and 15 weighted moments for the mixed and extrinsic entries ---------------------
+FISHER_COMMON = 3 + 1 + 4 * 5 + 10 * 4 + 12 * 2 + 4               # W, W f, explicit-Mf terms, products, moments
+PHASE_FISHER = {1: 8 + 4 * 26 + 26, 2: 4 * 8 + 5, 3: 2 + 4 * 14 + 8}
+AMP_FISHER = {1: 1 + 9 + 4 * 20 + 18, 2: 1 + 4 + 4 * 10 + 8, 3: 5 + 4 * 8 + 2}
 # mismatch adjoint: per-bin weights from the overlap (twiddle, R_k) + moments --------------
 MM_ADJ_COMMON = 1 + T_SINCOS + 6 + 4 + 8 + 4 + GRAD_COMMON - 10
 
