@@ -55,24 +55,36 @@ __global__ void k_ov_prep(GridArgs g, const double* __restrict__ data, int64_t n
     bp[idx] = v;
 }
 
+// Tiles of the block's output: 4 row tiles (16 templates each) x CT column tiles (16 real
+// columns each).  Wave w owns RT row tiles x CB column tiles: all four rows and CT/4 columns when
+// CT >= 4 (each wave then fetches a quarter of the data operand), otherwise CT rows of one column.
+template <int CT>
+struct OvTiling {
+    static constexpr int RT = CT >= 4 ? 4 : CT;
+    static constexpr int CB = CT >= 4 ? CT / 4 : 1;
+    __device__ static int row0(int w) { return CT >= 4 ? 0 : (w * CT) % 4; }
+    __device__ static int col0(int w) { return (w * CT) / 4; }
+};
+
 template <int CT>
 __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs, int64_t nt, GridArgs g,
                                                  const double* __restrict__ tab, const double* __restrict__ bp,
                                                  int nsp, int64_t ns, double* __restrict__ out,
                                                  double* __restrict__ hh) {
-    // per wave 16 template rows x 128 real k; element (j, kk) sits at column kk ^ (4 j), so the
+    using TL = OvTiling<CT>;
+    constexpr int RT = TL::RT, CB = TL::CB;
+    // 64 template rows x 128 real k; element (r, kk) sits at column kk ^ (4 (r % 16)), so the
     // MFMA reads (16 rows x 4 consecutive kk) and the generation writes (one row, 64 kk) both
     // touch 64 distinct columns
-    __shared__ double As[4][16][kKR];
+    __shared__ double As[kTT][kKR];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * kTT + 16 * w;
+    const int64_t tb = static_cast<int64_t>(blockIdx.x) * kTT;
     const Tabs T(tab, g.nb);
 
     // the block's bin range: union of its 64 templates' active ranges (every wave computes the
     // same wave-uniform values, so no exchange is needed)
     int klo = static_cast<int>(g.nb), khi = 0;
-    const int64_t tb = static_cast<int64_t>(blockIdx.x) * kTT;
     for (int j = 0; j < kTT; ++j) {
         const int64_t t = tb + j;
         if (t >= nt) break;
@@ -88,22 +100,29 @@ __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs
     const int c0 = klo / kKC;
     const int c1 = (khi > klo) ? (khi + kKC - 1) / kKC : c0;
 
-    d4 acc[CT];
+    const int rt0 = TL::row0(w), cb0 = TL::col0(w);
+    const bool hh_wave = (cb0 == 0);                 // the waves holding column tile 0 also sum (h|h)
+    d4 acc[CB][RT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
-    double hsum = 0.0;                      // (h|h) terms of template ia over this lane's bins
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[c][r] = d4{0.0, 0.0, 0.0, 0.0};
+    double hsum[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) hsum[r] = 0.0;
 
     const int ia = lane & 15, ka4 = lane >> 4;     // MFMA operand coordinates of this lane
     const int64_t bstride = 2 * nsp;
     for (int ch = c0; ch < c1; ++ch) {
-        // generate a = h / (A0 f^-7/6) for 16 templates x 64 bins (lane = bin)
+        // generate a = h / (A0 f^-7/6): wave w fills rows 16 w .. 16 w + 15 (lane = bin)
         {
             const int64_t k = static_cast<int64_t>(ch) * kKC + lane;
             const bool kin = k < g.nb;
             const double f = bin_freq(g, kin ? k : g.nb - 1);
 #pragma unroll 1
             for (int j = 0; j < 16; ++j) {
-                const int64_t t = t0 + j;
+                const int row = 16 * w + j;
+                const int64_t t = tb + row;
                 double ar = 0.0, ai = 0.0;
                 if (t < nt) {
                     const double* rec = recs + t * REC_N;
@@ -118,33 +137,37 @@ __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs
                         ai = -amp * sn;
                     }
                 }
-                As[w][j][lane ^ (4 * j)] = ar;
-                As[w][j][(kKC + lane) ^ (4 * j)] = ai;
+                As[row][lane ^ (4 * j)] = ar;
+                As[row][(kKC + lane) ^ (4 * j)] = ai;
             }
         }
         __syncthreads();
-        // contract with B' of this chunk: C[16 templates][16 real columns] per column tile;
-        // B' values are fetched two k-steps ahead of their use
-        const double* __restrict__ bch = bp + static_cast<int64_t>(ch) * kKR * bstride + ia;
+        // contract: each k-step reads RT operand values from LDS and CB from the data operand;
+        // data values are fetched two k-steps ahead of their use
+        const double* __restrict__ bch = bp + static_cast<int64_t>(ch) * kKR * bstride + 16 * cb0 + ia;
         const double* __restrict__ wwc = T.p[T_WW] + static_cast<int64_t>(ch) * kKC;
         const int64_t kmax = g.nb - static_cast<int64_t>(ch) * kKC;    // bins of this chunk inside the grid
-        double b0[2][CT], b1[2][CT];
-        auto fetch = [&](double (&dst)[2][CT], int sg) {
+        double b0[2][CB], b1[2][CB];
+        auto fetch = [&](double (&dst)[2][CB], int sg) {
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int c = 0; c < CT; ++c) dst[u][c] = bch[(8 * sg + 4 * u + ka4) * bstride + 16 * c];
+                for (int c = 0; c < CB; ++c) dst[u][c] = bch[(8 * sg + 4 * u + ka4) * bstride + 16 * c];
         };
-        auto step = [&](const double (&src)[2][CT], int sg) {
+        auto step = [&](const double (&src)[2][CB], int sg) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int kk = 8 * sg + 4 * u + ka4;
-                const double a = As[w][ia][kk ^ (4 * ia)];
                 const int kb = kk & (kKC - 1);
-                const double ww = (kb < kmax) ? wwc[kb] : 0.0;
-                hsum = fma(ww * a, a, hsum);
+                const double ww = (hh_wave && kb < kmax) ? wwc[kb] : 0.0;
 #pragma unroll
-                for (int c = 0; c < CT; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, src[u][c], acc[c], 0, 0, 0);
+                for (int r = 0; r < RT; ++r) {
+                    const double a = As[16 * (rt0 + r) + ia][kk ^ (4 * ia)];
+                    hsum[r] = fma(ww * a, a, hsum[r]);
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        acc[c][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, src[u][c], acc[c][r], 0, 0, 0);
+                }
             }
         };
         fetch(b0, 0);
@@ -158,25 +181,32 @@ __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs
         __syncthreads();
     }
 
-    // (h|h): the four lanes holding template ia (ka4 = 0..3) together saw all its bins twice
-    // (real and imaginary part)
-    hsum += __shfl_xor(hsum, 16, 64);
-    hsum += __shfl_xor(hsum, 32, 64);
-    if (ka4 == 0 && hh && t0 + ia < nt) {
-        const int64_t t = t0 + ia;
-        hh[t] = (recs[t * REC_N + R_VALID] != 0.0) ? hsum : __builtin_nan("");
+    // (h|h): the four lanes holding row ia of a row tile (ka4 = 0..3) together saw all its bins
+    // twice (real and imaginary part)
+    if (hh_wave) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            double v = hsum[r];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            const int64_t t = tb + 16 * (rt0 + r) + ia;
+            if (ka4 == 0 && hh && t < nt) hh[t] = (recs[t * REC_N + R_VALID] != 0.0) ? v : __builtin_nan("");
+        }
     }
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-        const int col = 16 * c + ia;
+    for (int c = 0; c < CB; ++c) {
+        const int col = 16 * (cb0 + c) + ia;
         const bool im = col >= nsp;
         const int64_t s = im ? col - nsp : col;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t t = t0 + ka4 + 4 * r;
-            if (t < nt && s < ns) {
-                const bool ok = recs[t * REC_N + R_VALID] != 0.0;
-                out[(t * ns + s) * 2 + (im ? 1 : 0)] = ok ? acc[c][r] : __builtin_nan("");
+        for (int r = 0; r < RT; ++r) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t t = tb + 16 * (rt0 + r) + ka4 + 4 * q;
+                if (t < nt && s < ns) {
+                    const bool ok = recs[t * REC_N + R_VALID] != 0.0;
+                    out[(t * ns + s) * 2 + (im ? 1 : 0)] = ok ? acc[c][r][q] : __builtin_nan("");
+                }
             }
         }
     }
