@@ -246,3 +246,52 @@ def test_results_are_bitwise_reproducible(gpu, lam0):
     b = gpu.api.loglike_and_grad(cfg["theta"], P, cfg["grid"], lam0, cfg["data"], cfg["inv_psd"])
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_fisher_full_c3_sampled(gpu, lam0):
+    """The full Fisher workload (16384 sources, 16065 bins, (ln Mc, eta, chi1, chi2, ln D, tc,
+    phic)) in one call: sampled matrices against the oracle, all symmetric and finite."""
+    import torch
+    cfg = W.config3()
+    g = cfg["grid"].as_tuple()
+    th = W.to_param(cfg["theta"], O.PARAM_LNMC_ETA_LND)
+    _say(f"fisher full C3 n={len(th)} nb={g[2]}")
+    F, st = gpu.api.fisher(th, O.PARAM_LNMC_ETA_LND, cfg["grid"], lam0, cfg["inv_psd"])
+    torch.cuda.synchronize()
+    F, st = F.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0) and np.all(np.isfinite(F))
+    assert np.array_equal(F, np.swapaxes(F, 1, 2))
+    rng = np.random.default_rng(4)
+    for i in sorted({0, len(th) - 1} | set(int(x) for x in rng.choice(len(th), 3, replace=False))):
+        ref = O.fisher(th[i], O.PARAM_LNMC_ETA_LND, lam0, g, cfg["inv_psd"])
+        scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+        assert np.all(np.abs(F[i] - ref) <= 1e-10 * scale), (i, np.max(np.abs(F[i] - ref) / scale))
+
+
+def test_mismatch_full_c4(gpu, lam0):
+    """The full mismatch workload (512 targets x 2^16 bins) in one call.  At the targets' own
+    coefficients lambda* the mismatches and the summed gradient vanish (a property that holds at
+    any size); at lambda0 sampled mismatches and lags match the oracle."""
+    import torch
+    cfg = W.config4()
+    g = cfg["grid"].as_tuple()
+    th = cfg["theta"]
+    w = cfg["inv_psd"]
+    lam_star = cfg["lam_star"]
+    targets, _ = gpu.api.waveform_eval(th, P, cfg["grid"], lam_star)
+    _say(f"mismatch full C4 nt={len(th)} nb={g[2]}")
+    mm0, dl0, lag0 = gpu.api.mismatch_grad(th, P, cfg["grid"], lam0, targets, w)
+    mms, dls, _ = gpu.api.mismatch_grad(th, P, cfg["grid"], lam_star, targets, w)
+    torch.cuda.synchronize()
+    mm0, dl0, lag0 = mm0.cpu().numpy(), dl0.cpu().numpy(), lag0.cpu().numpy()
+    mms, dls = mms.cpu().numpy(), dls.cpu().numpy()
+    assert np.all(np.isfinite(mm0)) and np.all(mm0 > 0)
+    assert np.max(np.abs(mms)) <= 1e-12
+    assert np.max(np.abs(dls * lam_star)) <= 1e-6 * np.max(np.abs(dl0 * lam0))
+    tg = targets.cpu().numpy()
+    rng = np.random.default_rng(5)
+    for i in sorted({0, len(th) - 1} | set(int(x) for x in rng.choice(len(th), 2, replace=False))):
+        m_ref, j_ref, gap = O.mismatch(th[i], P, lam0, g, tg[i], 4 * g[1] * w)
+        if gap > 1e-12:
+            assert lag0[i] == j_ref
+        assert abs(mm0[i] - m_ref) <= 1e-12, (i, mm0[i], m_ref)
