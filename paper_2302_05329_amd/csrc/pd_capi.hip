@@ -86,6 +86,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             break;
         case PD_OP_LOGLIKE_GRAD:
             L.chunks = pd::chunks_for(n, nb);
+            L.tan = off;
+            off = align_up(off + N * 4 * pd::REC_N * sizeof(double));
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * pd::kNSlot * sizeof(double));
             L.seg = off;
@@ -111,6 +113,34 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
     }
     L.total = off;
     return L;
+}
+
+// A side stream (default priority) per host thread and device, with fork and join events: the
+// record tangents of the gradient depend only on theta, so they run there while the records,
+// tables and moment pass run on the caller's stream.  Without it everything runs in order on the
+// caller's stream.
+struct SideStream {
+    int dev = -1;
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+SideStream* side_stream() {
+    thread_local std::vector<SideStream> pool;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    for (auto& e : pool)
+        if (e.dev == dev) return e.s ? &e : nullptr;
+    SideStream e;
+    e.dev = dev;
+    if (hipStreamCreateWithFlags(&e.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e.join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        e.s = nullptr;
+    }
+    pool.push_back(e);
+    return pool.back().s ? &pool.back() : nullptr;
 }
 
 int check_common(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
@@ -231,12 +261,25 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
     double* recs = at<double>(workspace, L.rec);
     double* partial = at<double>(workspace, L.partial);
     double* tab = at<double>(workspace, L.tab);
-    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
+    double* tans = grad ? at<double>(workspace, L.tan) : nullptr;
+    hipError_t e = hipSuccess;
+    SideStream* side = grad ? side_stream() : nullptr;
+    if (grad) {
+        hipStream_t ts = s;
+        if (side && hipEventRecord(side->fork, s) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
+            ts = side->s;
+        else
+            side = nullptr;
+        e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, 4, tans, ts);
+        if (e != hipSuccess) return fail_hip(e, "setup tangents");
+        if (side && hipEventRecord(side->join, side->s) != hipSuccess) return fail_hip(hipGetLastError(), "join");
+    }
+    e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
     if (e != hipSuccess) return fail_hip(e, "setup");
     e = pd::launch_tables(g, data, inv_psd, tab, s);
     if (e != hipSuccess) return fail_hip(e, "tables");
-    e = pd::launch_loglike(theta, param, lambda, recs, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl,
-                           grad, s);
+    e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl,
+                           grad, side ? side->join : nullptr, s);
     if (e != hipSuccess) return fail_hip(e, "loglike");
     return PD_OK;
 }
@@ -259,7 +302,7 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, co
     double* tab = at<double>(workspace, L.tab);
     hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
     if (e != hipSuccess) return fail_hip(e, "setup");
-    e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, recs, tans, s);
+    e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, 7, tans, s);
     if (e != hipSuccess) return fail_hip(e, "setup tangents");
     e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
     if (e != hipSuccess) return fail_hip(e, "tables");

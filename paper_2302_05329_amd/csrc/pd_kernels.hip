@@ -92,27 +92,24 @@ __device__ __forceinline__ double intrinsic_tangent(const double* __restrict__ t
 // extrinsic ones enter the record in closed form: D (or ln D) only through ln A0, tc only
 // through the Mf-linear phase coefficient (2 pi tc / Ms), phic only through the constant
 // phase term (-2 phic).  Thread (point, 0) also writes the three extrinsic rows.
+// ROWS 7: all seven rows (the Fisher kernels' layout); ROWS 4: the intrinsic rows only.  Thread
+// (point, dir) does not read the record, so this can run while the records are being built.
+template <int ROWS>
 __global__ void __launch_bounds__(64) k_setup_theta_tangent(const double* __restrict__ theta, int64_t n,
                                                             int param, double f_ref,
                                                             const double* __restrict__ lam,
-                                                            const double* __restrict__ recs,
                                                             double* __restrict__ tans) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= n * 4) return;
     const int64_t i = t >> 2;
     const int dir = static_cast<int>(t & 3);
-    double* out = tans + i * 7 * REC_N;
-    const bool valid = recs[i * REC_N + R_VALID] != 0.0;
-    if (dir == 0)
+    double* out = tans + i * ROWS * REC_N;
+    if (ROWS == 7 && dir == 0)
         for (int j = 4 * REC_N; j < 7 * REC_N; ++j) out[j] = 0.0;
-    if (!valid) {
-        for (int j = 0; j < REC_N; ++j) out[dir * REC_N + j] = 0.0;
-        return;
-    }
     double tg[REC_N];
     const double ms = intrinsic_tangent(theta + i * 7, param, f_ref, lam, dir, tg);
     for (int j = 0; j < REC_N; ++j) out[dir * REC_N + j] = tg[j];
-    if (dir != 0) return;
+    if (ROWS != 7 || dir != 0) return;
     out[4 * REC_N + R_LNA0] = (param == 1) ? -1.0 : -1.0 / theta[i * 7 + 4];
     const double dlin = 2.0 * kPi / ms;
     out[5 * REC_N + R_PH1 + 9] = dlin / kPi;
@@ -348,49 +345,51 @@ __global__ void __launch_bounds__(128) k_loglike_epilogue(const double* __restri
     }
 }
 
-// Four threads per point (intrinsic direction dir): the record tangent along that direction is
-// computed here (forward mode) and contracted with the moment sums straight away, so no tangent
-// array is stored; thread dir 0 also writes ln L and the three extrinsic entries, whose record
-// tangents are closed-form (D or ln D only through ln A0, tc only through the Mf-linear phase
-// coefficient 2 pi tc / Ms, phic only through the constant phase term -2 phic).
+// One thread per point: sum the moment partials once, contract them with the four intrinsic
+// record tangents (computed concurrently by k_setup_theta_tangent<4>), and add the three
+// extrinsic entries, whose record tangents are closed-form (D or ln D only through ln A0, tc
+// only through the Mf-linear phase coefficient 2 pi tc / Ms, phic only through the constant
+// phase term -2 phic).
 __global__ void __launch_bounds__(128) k_loglike_grad_epilogue(const double* __restrict__ theta, int64_t n,
-                                                               int param, double f_ref,
-                                                               const double* __restrict__ lam,
-                                                               const double* __restrict__ recs, int chunks,
+                                                               int param, const double* __restrict__ recs,
+                                                               const double* __restrict__ tans, int chunks,
                                                                const double* __restrict__ partial,
                                                                double* __restrict__ lnl, double* __restrict__ grad) {
     constexpr int NS = kNSlot;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n * 4) return;
-    const int64_t p = t >> 2;
-    const int dir = static_cast<int>(t & 3);
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
     const double* rec = recs + p * REC_N;
     if (rec[R_VALID] == 0.0) {
         const double nan = __builtin_nan("");
-        if (dir == 0) {
-            lnl[p] = nan;
-            for (int q = 0; q < 7; ++q) grad[p * 7 + q] = nan;
-        }
+        lnl[p] = nan;
+        for (int q = 0; q < 7; ++q) grad[p * 7 + q] = nan;
         return;
     }
-    auto msum = [&](int slot) {
-        double a = 0.0;
-        for (int grp = 0; grp < 3; ++grp)
-            for (int c = 0; c < chunks; ++c) a += partial[((grp * n + p) * chunks + c) * NS + slot];
-        return a;
-    };
-    double tg[REC_N];
-    const double ms = intrinsic_tangent(theta + p * 7, param, f_ref, lam, dir, tg);
-    double gq = tg[R_MS] / ms * msum(2 + R_MS) + tg[R_LNA0] * msum(2 + R_LNA0);
+    // partial rows are contiguous per point: sum them first (vector loads), then contract
+    double acc[NS];
 #pragma unroll
-    for (int s = R_PH1; s < R_VALID; ++s) gq += tg[s] * msum(2 + s);
-    grad[p * 7 + dir] = gq;
-    if (dir != 0) return;
-    lnl[p] = msum(0) - 0.5 * msum(1);
+    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+    for (int grp = 0; grp < 3; ++grp)
+        for (int c = 0; c < chunks; ++c) {
+            const double* src = partial + ((grp * n + p) * chunks + c) * NS;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) acc[k] += src[k];
+        }
+    const double* mom = acc + 2;
+    const double ms = rec[R_MS];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const double* tg = tans + (p * 4 + d) * REC_N;
+        double gq = tg[R_MS] / ms * mom[R_MS] + tg[R_LNA0] * mom[R_LNA0];
+#pragma unroll
+        for (int k = R_PH1; k < R_VALID; ++k) gq = fma(tg[k], mom[k], gq);
+        grad[p * 7 + d] = gq;
+    }
+    lnl[p] = acc[0] - 0.5 * acc[1];
     const double dlin = 2.0 * kPi / ms;
-    grad[p * 7 + 4] = ((param == 1) ? -1.0 : -1.0 / theta[p * 7 + 4]) * msum(2 + R_LNA0);
-    grad[p * 7 + 5] = dlin * (msum(2 + R_PH1 + 9) / kPi + msum(2 + R_PH2 + 1) + msum(2 + R_PH3 + 1));
-    grad[p * 7 + 6] = -2.0 * (msum(2 + R_PH1 + 4) + msum(2 + R_PH2 + 0) + msum(2 + R_PH3 + 0));
+    grad[p * 7 + 4] = ((param == 1) ? -1.0 : -1.0 / theta[p * 7 + 4]) * mom[R_LNA0];
+    grad[p * 7 + 5] = dlin * (mom[R_PH1 + 9] / kPi + mom[R_PH2 + 1] + mom[R_PH3 + 1]);
+    grad[p * 7 + 6] = -2.0 * (mom[R_PH1 + 4] + mom[R_PH2 + 0] + mom[R_PH3 + 0]);
 }
 
 // ==================================================================================
@@ -624,9 +623,13 @@ hipError_t launch_setup_value(const double* theta, int64_t n, int param, double 
 }
 
 hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param, double f_ref,
-                                      const double* lam, const double* recs, double* tans, hipStream_t s) {
-    hipLaunchKernelGGL(k_setup_theta_tangent, dim3(blocks_for(4 * n, 64)), dim3(64), 0, s, theta, n, param, f_ref,
-                       lam, recs, tans);
+                                      const double* lam, int rows, double* tans, hipStream_t s) {
+    if (rows == 4)
+        hipLaunchKernelGGL(k_setup_theta_tangent<4>, dim3(blocks_for(4 * n, 64)), dim3(64), 0, s, theta, n, param,
+                           f_ref, lam, tans);
+    else
+        hipLaunchKernelGGL(k_setup_theta_tangent<7>, dim3(blocks_for(4 * n, 64)), dim3(64), 0, s, theta, n, param,
+                           f_ref, lam, tans);
     return hipGetLastError();
 }
 
@@ -657,9 +660,9 @@ hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, con
     return hipGetLastError();
 }
 
-hipError_t launch_loglike(const double* theta, int param, const double* lam, const double* recs, int64_t n, int chunks,
-                          const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl, double* grad,
-                          hipStream_t s) {
+hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
+                          int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl,
+                          double* grad, hipEvent_t before_epilogue, hipStream_t s) {
     const int64_t waves = n * chunks;
     const unsigned nblk = blocks_for(waves, 4);
     hipLaunchKernelGGL(k_segments, dim3(blocks_for(waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
@@ -670,8 +673,12 @@ hipError_t launch_loglike(const double* theta, int param, const double* lam, con
             hipLaunchKernelGGL((k_loglike_moments<1, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
             hipLaunchKernelGGL((k_loglike_moments<1, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
         }
-        hipLaunchKernelGGL(k_loglike_grad_epilogue, dim3(blocks_for(4 * n, 128)), dim3(128), 0, s, theta, n, param,
-                           g.fref, lam, recs, chunks, partial, lnl, grad);
+        if (before_epilogue) {
+            const hipError_t e = hipStreamWaitEvent(s, before_epilogue, 0);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_loglike_grad_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, n, param, recs,
+                           tans, chunks, partial, lnl, grad);
     } else {
         {
             ProfRange pr(PD_K_LOGLIKE, s);

@@ -26,16 +26,16 @@ inline int chunks_for(int64_t n, int64_t n_bins) {
 hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
                               double* recs, int32_t* status, hipStream_t s);
 hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param, double f_ref,
-                                      const double* lam, const double* recs, double* tans, hipStream_t s);
+                                      const double* lam, int rows, double* tans, hipStream_t s);
 hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, double f_ref, const double* lam,
                                     const double* recs, double* tans, hipStream_t s);
 hipError_t launch_tables(const GridArgs& g, const double* data, const double* inv_psd, double* tab,
                          hipStream_t s);
 hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
                            double* h, hipStream_t s);
-hipError_t launch_loglike(const double* theta, int param, const double* lam, const double* recs, int64_t n, int chunks,
-                          const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl, double* grad,
-                          hipStream_t s);
+hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
+                          int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl,
+                          double* grad, hipEvent_t before_epilogue, hipStream_t s);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                          int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* F,
