@@ -272,7 +272,7 @@ struct LnlSegment {
 // PRG: the phase region (1 inspiral, 2 intermediate, 3 merger-ringdown) whose segments this
 // instantiation handles; the three are separate launches so each gets its own register budget.
 template <int MODE, int PRG>
-__global__ void __launch_bounds__(256) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
+__global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
                                                          GridArgs g, const double* __restrict__ tab,
                                                          const int* __restrict__ segs,
                                                          double* __restrict__ partial_all) {
@@ -308,41 +308,25 @@ __global__ void __launch_bounds__(256) k_loglike_moments(const double* __restric
     if (MODE == 1 && lane < REC_N) out[2 + lane] = seg.tot;
 }
 
-// One thread per point: sum the chunks, write lnL and (MODE 1) the gradient.
-template <int MODE>
-__global__ void __launch_bounds__(128) k_loglike_epilogue(const double* __restrict__ recs,
-                                                          const double* __restrict__ tans, int64_t n,
-                                                          int chunks, const double* __restrict__ partial,
-                                                          double* __restrict__ lnl, double* __restrict__ grad) {
-    constexpr int NS = (MODE == 0) ? 2 : kNSlot;
+// Value-only likelihood: one thread per point sums its (d|h), (h|h) partials over the region
+// groups and chunks.
+__global__ void __launch_bounds__(128) k_loglike_value_epilogue(const double* __restrict__ recs, int64_t n,
+                                                                int chunks, const double* __restrict__ partial,
+                                                                double* __restrict__ lnl) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const double* rec = recs + p * REC_N;
-    const double nan = __builtin_nan("");
-    if (rec[R_VALID] == 0.0) {
-        lnl[p] = nan;
-        if (MODE == 1)
-            for (int q = 0; q < 7; ++q) grad[p * 7 + q] = nan;
+    if (recs[p * REC_N + R_VALID] == 0.0) {
+        lnl[p] = __builtin_nan("");
         return;
     }
-    double acc[NS];
-    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    double dh = 0.0, hh = 0.0;
     for (int grp = 0; grp < 3; ++grp)
         for (int c = 0; c < chunks; ++c) {
-            const double* src = partial + ((grp * n + p) * chunks + c) * NS;
-            for (int s = 0; s < NS; ++s) acc[s] += src[s];
+            const double* src = partial + ((grp * n + p) * chunks + c) * 2;
+            dh += src[0];
+            hh += src[1];
         }
-    lnl[p] = acc[0] - 0.5 * acc[1];
-    if (MODE == 1) {
-        const double* mom = acc + 2;
-        const double ms = rec[R_MS];
-        for (int q = 0; q < 7; ++q) {
-            const double* t = tans + (p * 7 + q) * REC_N;
-            double gq = t[R_MS] / ms * mom[R_MS] + t[R_LNA0] * mom[R_LNA0];
-            for (int s = R_PH1; s < R_VALID; ++s) gq += t[s] * mom[s];
-            grad[p * 7 + q] = gq;
-        }
-    }
+    lnl[p] = dh - 0.5 * hh;
 }
 
 // One thread per point: sum the moment partials once, contract them with the four intrinsic
@@ -686,8 +670,8 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
             hipLaunchKernelGGL((k_loglike_moments<0, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
             hipLaunchKernelGGL((k_loglike_moments<0, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
         }
-        hipLaunchKernelGGL(k_loglike_epilogue<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, nullptr, n,
-                           chunks, partial, lnl, grad);
+        hipLaunchKernelGGL(k_loglike_value_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks,
+                           partial, lnl);
     }
     return hipGetLastError();
 }
