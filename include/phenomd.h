@@ -6,8 +6,8 @@
  * Wave Data Analysis" (arXiv:2302.05329).  The waveform is the aligned-spin IMRPhenomD
  * model the paper re-implements (Sec. 2); the products are the noise-weighted inner
  * product (Eq. 1), the Gaussian likelihood of the HMC study (Sec. 3.3), the Fisher matrix
- * (Sec. 3.2, Eq. fisher) and the mismatch over the 209 fit coefficients (Sec. 3.1,
- * Eqs. mismatch and multi_loss).
+ * (Sec. 3.2, Eq. 8) and the mismatch over the 209 fit coefficients (Sec. 3.1, Eqs. 2-5
+ * and 7).
  *
  * Conventions shared by every entry point
  *   - Every array argument is a DEVICE pointer owned by the caller, unless stated.
@@ -17,6 +17,10 @@
  *   - The library allocates no device memory.  Calls that need scratch take a
  *     caller-owned `workspace` of at least the size the matching *_workspace_bytes()
  *     query returns; two calls that run concurrently must not share a workspace.
+ *   - pd_loglike_and_grad with a gradient runs the record tangents on a side stream
+ *     (default priority) created once per host thread and device, forked from and joined
+ *     back to `stream` with events inside the call; the call stays asynchronous and its
+ *     results are ordered on `stream` as for any other call.
  *   - A negative return value is a batch-level error (bad pointer, size, grid or
  *     enum); nothing is launched and pd_last_error() describes it.  Nothing throws.
  *   - Per-point physical-domain errors (non-finite input, masses <= 0, eta outside

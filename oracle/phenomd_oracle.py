@@ -562,7 +562,7 @@ def loglike_grad(theta, param, lam, grid, data, inv_psd):
 
 
 def fisher(theta, param, lam, grid, inv_psd):
-    """F_pq = (d_p h | d_q h) with d_p h = h (d_p ln A - i d_p Psi)  (Eq. fisher, one detector)."""
+    """F_pq = (d_p h | d_q h) with d_p h = h (d_p ln A - i d_p Psi)  (Eq. 8, one detector)."""
     amp, phase, dlna, dpsi, act = amp_phase_derivatives(theta, param, lam, grid)
     h = amp * np.exp(-1j * phase)
     dh = h[None, :] * (dlna - 1j * dpsi)
@@ -576,7 +576,7 @@ def fisher(theta, param, lam, grid, inv_psd):
 
 
 # ====================================================================================
-# match and mismatch (Eqs. match, mismatch) and the gradient over the 209 coefficients
+# match and mismatch (Eqs. 3-4) and the gradient over the 209 coefficients
 # ====================================================================================
 
 def overlap_series(h1, h2, w):

@@ -1,5 +1,5 @@
 // Mismatch against fixed targets and its adjoint over the 209 fit coefficients
-// (paper Sec. 3.1: Eq. mismatch, averaged over targets in Eq. multi_loss; the maximum
+// (paper Sec. 3.1: Eq. 5, averaged over targets in Eq. 7; the maximum
 // over the coalescence time is taken with a Fourier transform, Sec. 2).
 //
 // Pipeline per target (N = 65536 = 256 x 256):
