@@ -45,6 +45,23 @@ struct Tabs {
     }
 };
 
+// The grid-table values one bin's evaluation reads, held in registers: a kernel that evaluates
+// the same bin for many parameter points loads them once.
+struct BinTabs {
+    double cb, icb, lf, f34, inf;
+    __device__ __forceinline__ void load(const Tabs& T, int64_t k) {
+        cb = T.at(T_CB, k);
+        icb = T.at(T_ICB, k);
+        lf = T.at(T_LF, k);
+        f34 = T.at(T_F34, k);
+        inf = T.at(T_INF, k);
+    }
+    template <class KI>
+    __device__ __forceinline__ double at(int which, KI) const {
+        return which == T_CB ? cb : which == T_ICB ? icb : which == T_LF ? lf : which == T_F34 ? f34 : inf;
+    }
+};
+
 // Frequency of bin k, rounded exactly as f0 + k*df (two roundings, no fused multiply-add).
 __device__ __forceinline__ double bin_freq(const GridArgs& g, int64_t k) {
     return __dadd_rn(g.f0, __dmul_rn(static_cast<double>(k), g.df));
@@ -164,8 +181,9 @@ struct BinVals {
 
 // HAVE_EX: the merger-ringdown amplitude exponential exp(-c3 (Mf - f_RD)) is supplied by the
 // caller (a per-lane recurrence along a segment) instead of evaluated here.
-template <int PR, int AR, bool HAVE_EX = false, class KI>
-__device__ __forceinline__ void eval_bin_t(const double* __restrict__ c, const Tabs& T, KI k, double mf,
+// RC: the record (a pointer, or any type whose operator[] reads entry i); TB: the grid tables.
+template <int PR, int AR, bool HAVE_EX = false, class RC, class TB, class KI>
+__device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
                                            BinVals& b, double ex = 0.0) {
     b.mf = mf;
     if (PR == 1 || AR == 1) {
@@ -262,7 +280,8 @@ struct ExpRec {
 };
 
 // Runtime region dispatch for one-bin-per-thread kernels.
-__device__ __forceinline__ void eval_bin_rt(const double* __restrict__ rec, const Tabs& T, int64_t k, double mf,
+template <class RC, class TB>
+__device__ __forceinline__ void eval_bin_rt(RC rec, const TB& T, int64_t k, double mf,
                                             BinVals& b) {
     const int pr = (mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3);
     const int ar = (mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3);

@@ -7,7 +7,7 @@
 // As a real GEMM over the bins:  [Re O | Im O] = [a_r | a_i] * [[D_r, D_i], [D_i, -D_r]]
 // with a = h / (A0 f^-7/6) (the per-template part of the strain) and D = w f^-7/6 d (the
 // per-bin part, prepared once per call).  The template operand is never stored: each block
-// generates its 64 templates x 64 bins into LDS chunk by chunk and contracts them at once
+// generates its 32 templates x 64 bins into LDS chunk by chunk and contracts them at once
 // with v_mfma_f64_16x16x4f64 (lane layout checked on gfx950: with A[i][k] from lane
 // (i + 16 k) and B[k][j] from lane (j + 16 k), register r of lane l holds C[l/16 + 4 r][l%16]).
 #include <hip/hip_runtime.h>
@@ -27,7 +27,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kKC = 64;              // bins per chunk
 constexpr int kKR = 2 * kKC;         // real contraction length per chunk
-constexpr int kTT = 64;              // templates per block (4 waves x 16)
+constexpr int kTT = 32;              // templates per block
+constexpr int kRTT = kTT / 16;       // row tiles of the block's output
+constexpr int kRPW = kTT / 4;        // template rows each of the 4 waves generates
+static_assert(kTT == 32 || kTT == 64, "block tiling covers 32 or 64 templates");
 
 // B' [chunk][128][2 nsp]: rows k < 64 carry (D_r | D_i) of bin chunk*64 + k, rows 64 + k carry
 // (D_i | -D_r); columns s and nsp + s belong to stream s; zero beyond n_bins and ns.
@@ -55,53 +58,102 @@ __global__ void k_ov_prep(GridArgs g, const double* __restrict__ data, int64_t n
     bp[idx] = v;
 }
 
-// Tiles of the block's output: 4 row tiles (16 templates each) x CT column tiles (16 real
-// columns each).  Wave w owns RT row tiles x CB column tiles: all four rows and CT/4 columns when
-// CT >= 4 (each wave then fetches a quarter of the data operand), otherwise CT rows of one column.
+// A record spread over the wave: lane e holds entry e (lanes past the record hold zero), and
+// entry i is read with two lane reads into scalar registers.  Loaded one template ahead of its
+// use, so the per-template coefficients never stall the generation on memory.
+struct LaneRec {
+    double v;
+    __device__ __forceinline__ double operator[](int i) const {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(b)), i);
+        const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(b >> 32)), i);
+        return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+    }
+};
+
+// Region pair (phase region, amplitude region) of frequency Mf, coded 4 pr + ar; the amplitude
+// join (Mf = 0.014) lies below the phase join (0.018), so pr >= 2 implies ar >= 2.
+template <class RC>
+__device__ __forceinline__ int region_pair(const RC& rec, double mf) {
+    const int pr = (mf < kFPhaseJoin) ? 1 : ((mf < rec[R_FP2]) ? 2 : 3);
+    const int ar = (mf < kFAmpJoin) ? 1 : ((mf < rec[R_FA2]) ? 2 : 3);
+    return 4 * pr + ar;
+}
+
+__device__ __forceinline__ void store_a(double* __restrict__ arow, int kk, int sw, bool on, double amp, double psi) {
+    double sn, cs;
+    pd_sincos(psi, &sn, &cs);
+    arow[kk ^ sw] = on ? amp * cs : 0.0;
+    arow[(kKC + kk) ^ sw] = on ? -amp * sn : 0.0;
+}
+
+// One bin of one template whose active bins in this chunk all lie in region pair (PR, AR); an
+// inactive bin goes through the same formulas and is stored as zero.
+template <int PR, int AR, class RC>
+__device__ __forceinline__ void gen_bin(const RC& rec, const BinTabs& bt, int64_t k, double mf,
+                                        bool on, double* __restrict__ arow, int kk, int sw) {
+    BinVals bv;
+    eval_bin_t<PR, AR>(rec, bt, k, mf, bv);
+    store_a(arow, kk, sw, on, rec[R_A0P] * bv.ahat, bv.psi);
+}
+
+// Tiles of the block's output: kRTT row tiles (16 templates each) x CT column tiles (16 real
+// columns each).  Wave w owns RT row tiles x CB column tiles: every row tile and CT/4 column tiles
+// when CT >= 4 (each wave then fetches a quarter of the data operand), otherwise RT rows of one
+// column; waves whose column would lie past CT take no part in the contraction.
 template <int CT>
 struct OvTiling {
-    static constexpr int RT = CT >= 4 ? 4 : CT;
+    static constexpr int RT = CT >= 4 ? kRTT : (kRTT * CT >= 4 ? kRTT * CT / 4 : 1);
     static constexpr int CB = CT >= 4 ? CT / 4 : 1;
-    __device__ static int row0(int w) { return CT >= 4 ? 0 : (w * CT) % 4; }
-    __device__ static int col0(int w) { return (w * CT) / 4; }
+    __device__ static int row0(int w) { return CT >= 4 ? 0 : (w * RT) % kRTT; }
+    __device__ static int col0(int w) { return CT >= 4 ? w * CB : (w * RT) / kRTT; }
+    __device__ static bool active(int w) { return col0(w) < CT; }
 };
 
 template <int CT>
-__global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs, int64_t nt, GridArgs g,
+__global__ void __launch_bounds__(256, 4) k_ov_gemm(const double* __restrict__ recs, int64_t nt, GridArgs g,
                                                  const double* __restrict__ tab, const double* __restrict__ bp,
                                                  int nsp, int64_t ns, double* __restrict__ out,
                                                  double* __restrict__ hh) {
     using TL = OvTiling<CT>;
     constexpr int RT = TL::RT, CB = TL::CB;
-    // 64 template rows x 128 real k; element (r, kk) sits at column kk ^ (4 (r % 16)), so the
+    // kTT template rows x 128 real k (32 KB: with four waves per SIMD, four blocks share a CU's
+    // LDS); element (r, kk) sits at column kk ^ (4 (r % 16)), so the
     // MFMA reads (16 rows x 4 consecutive kk) and the generation writes (one row, 64 kk) both
     // touch 64 distinct columns
     __shared__ double As[kTT][kKR];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: records via the scalar cache
     const int64_t tb = static_cast<int64_t>(blockIdx.x) * kTT;
     const Tabs T(tab, g.nb);
 
-    // the block's bin range: union of its 64 templates' active ranges (every wave computes the
-    // same wave-uniform values, so no exchange is needed)
+    // active bin range [ka, kz) of each of the block's templates (empty for padding rows and
+    // invalid points), then the block's range: their union
+    __shared__ __attribute__((aligned(8))) int Kr[kTT][2];
+    if (threadIdx.x < kTT) {
+        const int64_t t = tb + threadIdx.x;
+        int64_t ka = 0, kz = 0;
+        if (t < nt && recs[t * REC_N + R_VALID] != 0.0) active_range(recs[t * REC_N + R_MS], g, ka, kz);
+        Kr[threadIdx.x][0] = static_cast<int>(ka);
+        Kr[threadIdx.x][1] = static_cast<int>(kz);
+    }
+    __syncthreads();
     int klo = static_cast<int>(g.nb), khi = 0;
     for (int j = 0; j < kTT; ++j) {
-        const int64_t t = tb + j;
-        if (t >= nt) break;
-        const double* rec = recs + t * REC_N;
-        if (rec[R_VALID] == 0.0) continue;
-        int64_t ka, kz;
-        active_range(rec[R_MS], g, ka, kz);
+        const int ka = Kr[j][0], kz = Kr[j][1];
         if (kz > ka) {
-            klo = min(klo, uniform_i(ka));
-            khi = max(khi, uniform_i(kz));
+            klo = min(klo, ka);
+            khi = max(khi, kz);
         }
     }
+    klo = __builtin_amdgcn_readfirstlane(klo);
+    khi = __builtin_amdgcn_readfirstlane(khi);
     const int c0 = klo / kKC;
     const int c1 = (khi > klo) ? (khi + kKC - 1) / kKC : c0;
 
     const int rt0 = TL::row0(w), cb0 = TL::col0(w);
-    const bool hh_wave = (cb0 == 0);                 // the waves holding column tile 0 also sum (h|h)
+    const bool mma_wave = TL::active(w);
+    const bool hh_wave = mma_wave && (cb0 == 0);     // the waves holding column tile 0 also sum (h|h)
     d4 acc[CB][RT];
 #pragma unroll
     for (int c = 0; c < CB; ++c)
@@ -114,36 +166,76 @@ __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs
     const int ia = lane & 15, ka4 = lane >> 4;     // MFMA operand coordinates of this lane
     const int64_t bstride = 2 * nsp;
     for (int ch = c0; ch < c1; ++ch) {
-        // generate a = h / (A0 f^-7/6): wave w fills rows 16 w .. 16 w + 15 (lane = bin)
+        // generate a = h / (A0 f^-7/6): wave w fills rows kRPW w .. kRPW w + kRPW - 1 (lane = bin); the
+        // bin's table values are loaded once for all of them
         {
-            const int64_t k = static_cast<int64_t>(ch) * kKC + lane;
-            const bool kin = k < g.nb;
-            const double f = bin_freq(g, kin ? k : g.nb - 1);
+            const int64_t kch = static_cast<int64_t>(ch) * kKC;
+            const int64_t k = kch + lane;
+            const int64_t kc = (k < g.nb) ? k : g.nb - 1;
+            const double f = bin_freq(g, kc);
+            BinTabs bt;
+            bt.load(T, kc);
+            // the next row's record and active range are fetched while this row is evaluated
+            const int64_t t0 = tb + kRPW * w;
+            auto rec_fetch = [&](int j) -> double {
+                const int64_t t = t0 + j;
+                return (t < nt && lane < REC_N) ? recs[t * REC_N + lane] : 0.0;
+            };
+            double rec_next = rec_fetch(0);
+            int2 kr_next = *reinterpret_cast<const int2*>(&Kr[kRPW * w][0]);
 #pragma unroll 1
-            for (int j = 0; j < 16; ++j) {
-                const int row = 16 * w + j;
-                const int64_t t = tb + row;
-                double ar = 0.0, ai = 0.0;
-                if (t < nt) {
-                    const double* rec = recs + t * REC_N;
-                    const double mf = rec[R_MS] * f;
-                    if (kin && rec[R_VALID] != 0.0 && bin_active(g, f, mf)) {
-                        BinVals bv;
-                        eval_bin_rt(rec, T, k, mf, bv);
-                        const double amp = rec[R_A0P] * bv.ahat;
-                        double sn, cs;
-                        pd_sincos(bv.psi, &sn, &cs);
-                        ar = amp * cs;
-                        ai = -amp * sn;
+            for (int j = 0; j < kRPW; ++j) {
+                const int row = kRPW * w + j;
+                const LaneRec rec{rec_next};
+                const int ka = __builtin_amdgcn_readfirstlane(kr_next.x);
+                const int kz = __builtin_amdgcn_readfirstlane(kr_next.y);
+                rec_next = rec_fetch(min(j + 1, kRPW - 1));
+                kr_next = *reinterpret_cast<const int2*>(&Kr[kRPW * w + min(j + 1, kRPW - 1)][0]);
+                const int lo = max(static_cast<int>(kch), ka), hi = min(static_cast<int>(kch) + kKC, kz);
+                double* __restrict__ arow = &As[row][0];
+                const int sw = 4 * (row & 15);
+                const bool on = k >= lo && k < hi;
+                // region pair of the row's active bins in this chunk: one pair for all of them lets the
+                // wave run the evaluation instantiated for it; -1 if it changes, -2 if none is active
+                int code = -2;
+                if (hi > lo) {
+                    const double ms = rec[R_MS];
+                    const int c_lo = region_pair(rec, ms * bin_freq(g, static_cast<int64_t>(lo)));
+                    const int c_hi = region_pair(rec, ms * bin_freq(g, static_cast<int64_t>(hi - 1)));
+                    code = (c_lo == c_hi) ? c_lo : -1;
+                }
+                code = __builtin_amdgcn_readfirstlane(code);
+                if (code == -2) {
+                    arow[lane ^ sw] = 0.0;
+                    arow[(kKC + lane) ^ sw] = 0.0;
+                    continue;
+                }
+                const double mf = rec[R_MS] * f;
+                switch (code) {
+                    case 4 * 1 + 1: gen_bin<1, 1>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 1 + 2: gen_bin<1, 2>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 1 + 3: gen_bin<1, 3>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 2 + 2: gen_bin<2, 2>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 2 + 3: gen_bin<2, 3>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 3 + 2: gen_bin<3, 2>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 3 + 3: gen_bin<3, 3>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    default: {
+                        double amp = 0.0, psi = 0.0;
+                        if (on) {
+                            BinVals bv;
+                            eval_bin_rt(rec, bt, kc, mf, bv);
+                            amp = rec[R_A0P] * bv.ahat;
+                            psi = bv.psi;
+                        }
+                        store_a(arow, lane, sw, on, amp, psi);
                     }
                 }
-                As[row][lane ^ (4 * j)] = ar;
-                As[row][(kKC + lane) ^ (4 * j)] = ai;
             }
         }
         __syncthreads();
         // contract: each k-step reads RT operand values from LDS and CB from the data operand;
         // data values are fetched two k-steps ahead of their use
+        if (mma_wave) {
         const double* __restrict__ bch = bp + static_cast<int64_t>(ch) * kKR * bstride + 16 * cb0 + ia;
         const double* __restrict__ wwc = T.p[T_WW] + static_cast<int64_t>(ch) * kKC;
         const int64_t kmax = g.nb - static_cast<int64_t>(ch) * kKC;    // bins of this chunk inside the grid
@@ -178,8 +270,10 @@ __global__ void __launch_bounds__(256) k_ov_gemm(const double* __restrict__ recs
             if (sg + 2 < kKR / 8) fetch(b0, sg + 2);
             step(b1, sg + 1);
         }
+        }
         __syncthreads();
     }
+    if (!mma_wave) return;
 
     // (h|h): the four lanes holding row ia of a row tile (ka4 = 0..3) together saw all its bins
     // twice (real and imaginary part)
