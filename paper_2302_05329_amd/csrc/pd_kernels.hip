@@ -329,51 +329,60 @@ __global__ void __launch_bounds__(128) k_loglike_value_epilogue(const double* __
     lnl[p] = dh - 0.5 * hh;
 }
 
-// One thread per point: sum the moment partials once, contract them with the four intrinsic
-// record tangents (computed concurrently by k_setup_theta_tangent<4>), and add the three
-// extrinsic entries, whose record tangents are closed-form (D or ln D only through ln A0, tc
-// only through the Mf-linear phase coefficient 2 pi tc / Ms, phic only through the constant
-// phase term -2 phic).
-__global__ void __launch_bounds__(128) k_loglike_grad_epilogue(const double* __restrict__ theta, int64_t n,
+// One wave per point: lane j (< 62) sums partial slot j over the three region groups and the
+// point's chunks (each row is contiguous, so every load is coalesced), the four intrinsic
+// directions are contracted lane-wise with the record tangents (computed concurrently by
+// k_setup_theta_tangent<4>) and summed over the wave in a fixed order, and the three extrinsic
+// entries use closed-form record tangents (D or ln D only through ln A0, tc only through the
+// Mf-linear phase coefficient 2 pi tc / Ms, phic only through the constant phase term -2 phic).
+__global__ void __launch_bounds__(256) k_loglike_grad_epilogue(const double* __restrict__ theta, int64_t n,
                                                                int param, const double* __restrict__ recs,
                                                                const double* __restrict__ tans, int chunks,
                                                                const double* __restrict__ partial,
                                                                double* __restrict__ lnl, double* __restrict__ grad) {
     constexpr int NS = kNSlot;
-    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    static_assert(NS <= 64, "one lane per partial slot");
+    const int lane = threadIdx.x & 63;
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (p >= n) return;
-    const double* rec = recs + p * REC_N;
+    const double* __restrict__ rec = recs + p * REC_N;
     if (rec[R_VALID] == 0.0) {
-        const double nan = __builtin_nan("");
-        lnl[p] = nan;
-        for (int q = 0; q < 7; ++q) grad[p * 7 + q] = nan;
+        if (lane == 0) lnl[p] = __builtin_nan("");
+        if (lane < 7) grad[p * 7 + lane] = __builtin_nan("");
         return;
     }
-    // partial rows are contiguous per point: sum them first (vector loads), then contract
-    double acc[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-    for (int grp = 0; grp < 3; ++grp)
-        for (int c = 0; c < chunks; ++c) {
-            const double* src = partial + ((grp * n + p) * chunks + c) * NS;
-#pragma unroll
-            for (int k = 0; k < NS; ++k) acc[k] += src[k];
-        }
-    const double* mom = acc + 2;
-    const double ms = rec[R_MS];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        const double* tg = tans + (p * 4 + d) * REC_N;
-        double gq = tg[R_MS] / ms * mom[R_MS] + tg[R_LNA0] * mom[R_LNA0];
-#pragma unroll
-        for (int k = R_PH1; k < R_VALID; ++k) gq = fma(tg[k], mom[k], gq);
-        grad[p * 7 + d] = gq;
+    double m = 0.0;     // lane 0: (d|h), lane 1: (h|h), lane 2 + j: moment j
+    if (lane < NS) {
+        for (int grp = 0; grp < 3; ++grp)
+            for (int c = 0; c < chunks; ++c) m += partial[((grp * n + p) * chunks + c) * NS + lane];
     }
-    lnl[p] = acc[0] - 0.5 * acc[1];
+    auto at = [&](int slot) {   // wave-uniform copy of one lane's sum
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, m);
+        const unsigned lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(b)), slot);
+        const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(b >> 32)), slot);
+        return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+    };
+    const double ms = rec[R_MS];
+    // record entries the moments are contracted over: Ms (through ln Ms), ln A0 and the phase and
+    // amplitude coefficients
+    const int j = lane - 2;
+    const bool used = j == R_MS || j == R_LNA0 || (j >= R_PH1 && j < R_VALID);
+    const double wj = used ? ((j == R_MS) ? m / ms : m) : 0.0;
+    double gd[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) gd[d] = used ? tans[(p * 4 + d) * REC_N + j] * wj : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) gd[d] += __shfl_xor(gd[d], off, 64);
     const double dlin = 2.0 * kPi / ms;
-    grad[p * 7 + 4] = ((param == 1) ? -1.0 : -1.0 / theta[p * 7 + 4]) * mom[R_LNA0];
-    grad[p * 7 + 5] = dlin * (mom[R_PH1 + 9] / kPi + mom[R_PH2 + 1] + mom[R_PH3 + 1]);
-    grad[p * 7 + 6] = -2.0 * (mom[R_PH1 + 4] + mom[R_PH2 + 0] + mom[R_PH3 + 0]);
+    double out = 0.0;
+    if (lane < 4) out = (lane == 0) ? gd[0] : (lane == 1) ? gd[1] : (lane == 2) ? gd[2] : gd[3];
+    if (lane == 4) out = ((param == 1) ? -1.0 : -1.0 / theta[p * 7 + 4]) * at(2 + R_LNA0);
+    if (lane == 5) out = dlin * (at(2 + R_PH1 + 9) / kPi + at(2 + R_PH2 + 1) + at(2 + R_PH3 + 1));
+    if (lane == 6) out = -2.0 * (at(2 + R_PH1 + 4) + at(2 + R_PH2 + 0) + at(2 + R_PH3 + 0));
+    if (lane < 7) grad[p * 7 + lane] = out;
+    if (lane == 0) lnl[p] = at(0) - 0.5 * at(1);
 }
 
 // ==================================================================================
@@ -661,7 +670,7 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
             const hipError_t e = hipStreamWaitEvent(s, before_epilogue, 0);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(k_loglike_grad_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, n, param, recs,
+        hipLaunchKernelGGL(k_loglike_grad_epilogue, dim3(blocks_for(n, 4)), dim3(256), 0, s, theta, n, param, recs,
                            tans, chunks, partial, lnl, grad);
     } else {
         {
