@@ -442,7 +442,12 @@ struct FisherSegment {
             eval_bin_t<PR, AR, AR == 3>(rec, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
             const double W = (a0p * a0p) * T.at(T_WW, k) * bv.ahat * bv.ahat;
             FisherVis vis;
-            vis.T = Tl;
+            // the tangents are re-read from LDS in every bin (broadcast reads): an opaque offset
+            // keeps the compiler from hoisting 4 x REC_N of them into vector registers, which
+            // would cut the occupancy to one or two waves per SIMD
+            int toff = 0;
+            asm volatile("" : "+s"(toff));
+            vis.T = Tl + toff;
             vis.ims = rec[R_IMS];
 #pragma unroll
             for (int q = 0; q < kFisherDirs; ++q) vis.dpsi[q] = vis.dlna[q] = 0.0;
@@ -473,7 +478,7 @@ struct FisherSegment {
 };
 
 template <int PRG>
-__global__ void __launch_bounds__(256, (PRG == 1) ? 1 : 3) k_fisher_partial(const double* __restrict__ recs,
+__global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restrict__ recs,
                                                         const double* __restrict__ tans, int64_t n, int chunks,
                                                         GridArgs g, const double* __restrict__ tab,
                                                         const int* __restrict__ segs,
