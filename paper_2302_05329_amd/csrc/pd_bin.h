@@ -401,6 +401,34 @@ __device__ __forceinline__ void chunk_range(double ms, const GridArgs& g, int c,
     if (ke > kz) ke = kz;
 }
 
+// Chunk `c` of `chunks` of the bins of phase region PRG inside the active range: region 1 is
+// [ka, b1), region 2 [b1, max(b1, b2)), region 3 [max(b1, b2), kz), where b1 and b2 are the first
+// bins at or above the phase joins Mf = 0.018 and rec[R_FP2], found with the same test as the
+// segment boundaries, so every segment of the chunk lies in region PRG.  Splitting each region
+// separately gives every region launch all of its waves.
+template <int PRG>
+__device__ __forceinline__ void region_chunk_range(const double* __restrict__ rec, const GridArgs& g, int c,
+                                                   int chunks, int64_t& kb, int64_t& ke) {
+    const double ms = rec[R_MS];
+    int64_t ka, kz;
+    active_range(ms, g, ka, kz);
+    auto bound = [&](double t) {
+        auto ge = [&](int64_t k) { return ms * bin_freq(g, k) >= t; };
+        return first_true(ge, clamp_est(ceil((t / ms - g.f0) / g.df), ka, kz), ka, kz);
+    };
+    const int64_t b1 = bound(kFPhaseJoin);
+    const int64_t b2 = max(b1, bound(rec[R_FP2]));
+    const int64_t rs = (PRG == 1) ? ka : (PRG == 2) ? b1 : b2;
+    const int64_t re = (PRG == 1) ? b1 : (PRG == 2) ? b2 : kz;
+    const int64_t len = re - rs;
+    int64_t per = (len + chunks - 1) / chunks;
+    per = (per + 63) & ~static_cast<int64_t>(63);
+    kb = rs + static_cast<int64_t>(c) * per;
+    ke = kb + per;
+    if (kb > re) kb = re;
+    if (ke > re) ke = re;
+}
+
 // ---- deterministic wavefront reduction (fixed butterfly order) ---------------------
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
