@@ -253,7 +253,15 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     ks = {name: kernel_avg_ms(api, k)[0] for name, k in (("input", L.PD_K_MISMATCH_INPUT),
                                                            ("fft", L.PD_K_MISMATCH_FFT),
                                                            ("adjoint", L.PD_K_MISMATCH_ADJ))}
-    extra["C4_mismatch_grad"] = {"targets_per_s": th4.shape[0] / t, "ms": 1e3 * t, "kernel_ms": ks}
+    # input: reads the targets, writes the weighted products; FFT: column pass reads and writes
+    # the 2^16-point series, row pass reads it (complex128 throughout)
+    series = th4.shape[0] * c4["grid"].n_bins * 16.0
+    trans4 = api.transition_frequencies(th4, P, c4["grid"], lam, ws=ws).cpu().numpy()
+    fl4, _ = flops.batch_flops("mismatch_adjoint", trans4, c4["grid"].as_tuple())
+    extra["C4_mismatch_grad"] = {"targets_per_s": th4.shape[0] / t, "ms": 1e3 * t, "kernel_ms": ks,
+                                 "input_hbm_GBs": 2 * series / (ks["input"] * 1e-3) / 1e9,
+                                 "fft_hbm_GBs": 3 * series / (ks["fft"] * 1e-3) / 1e9,
+                                 "adjoint_tflops_algorithmic": fl4 / (ks["adjoint"] * 1e-3) / 1e12}
     api.profile_enable(False)
 
     # template-bank overlaps on the FP64 matrix cores: the C2 bank (ordered by total mass)
