@@ -387,28 +387,13 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
     vis.fd(fpsi, fa - sk(7.0 / 6.0));
 }
 
-// Chunk of the active range [kb, ke) handled by wavefront `c` of `chunks` for one point.
-__device__ __forceinline__ void chunk_range(double ms, const GridArgs& g, int c, int chunks, int64_t& kb,
-                                            int64_t& ke) {
-    int64_t ka, kz;
-    active_range(ms, g, ka, kz);
-    const int64_t len = kz - ka;
-    int64_t per = (len + chunks - 1) / chunks;
-    per = (per + 63) & ~static_cast<int64_t>(63);
-    kb = ka + static_cast<int64_t>(c) * per;
-    ke = kb + per;
-    if (kb > kz) kb = kz;
-    if (ke > kz) ke = kz;
-}
-
-// Chunk `c` of `chunks` of the bins of phase region PRG inside the active range: region 1 is
+// Chunk `c` of `chunks` of the bins of phase region prg inside the active range: region 1 is
 // [ka, b1), region 2 [b1, max(b1, b2)), region 3 [max(b1, b2), kz), where b1 and b2 are the first
 // bins at or above the phase joins Mf = 0.018 and rec[R_FP2], found with the same test as the
-// segment boundaries, so every segment of the chunk lies in region PRG.  Splitting each region
+// segment boundaries, so every segment of the chunk lies in region prg.  Splitting each region
 // separately gives every region launch all of its waves.
-template <int PRG>
-__device__ __forceinline__ void region_chunk_range(const double* __restrict__ rec, const GridArgs& g, int c,
-                                                   int chunks, int64_t& kb, int64_t& ke) {
+__device__ __forceinline__ void region_chunk_range(const double* __restrict__ rec, const GridArgs& g, int prg,
+                                                   int c, int chunks, int64_t& kb, int64_t& ke) {
     const double ms = rec[R_MS];
     int64_t ka, kz;
     active_range(ms, g, ka, kz);
@@ -418,8 +403,8 @@ __device__ __forceinline__ void region_chunk_range(const double* __restrict__ re
     };
     const int64_t b1 = bound(kFPhaseJoin);
     const int64_t b2 = max(b1, bound(rec[R_FP2]));
-    const int64_t rs = (PRG == 1) ? ka : (PRG == 2) ? b1 : b2;
-    const int64_t re = (PRG == 1) ? b1 : (PRG == 2) ? b2 : kz;
+    const int64_t rs = (prg == 1) ? ka : (prg == 2) ? b1 : b2;
+    const int64_t re = (prg == 1) ? b1 : (prg == 2) ? b2 : kz;
     const int64_t len = re - rs;
     int64_t per = (len + chunks - 1) / chunks;
     per = (per + 63) & ~static_cast<int64_t>(63);

@@ -82,7 +82,7 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * 2 * sizeof(double));
             L.seg = off;
-            off = align_up(off + N * L.chunks * pd::kSegInts * sizeof(int));
+            off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
             break;
         case PD_OP_LOGLIKE_GRAD:
             L.chunks = pd::chunks_for(n, nb);
@@ -91,7 +91,7 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * pd::kNSlot * sizeof(double));
             L.seg = off;
-            off = align_up(off + N * L.chunks * pd::kSegInts * sizeof(int));
+            off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
             break;
         case PD_OP_FISHER:
             L.chunks = pd::chunks_for(n, nb);
@@ -100,7 +100,7 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.partial = off;
             off = align_up(off + 3 * N * L.chunks * pd::kFisherSlots * sizeof(double));
             L.seg = off;
-            off = align_up(off + N * L.chunks * pd::kSegInts * sizeof(int));
+            off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
             break;
         case PD_OP_MISMATCH_GRAD:
             L.tan = off;

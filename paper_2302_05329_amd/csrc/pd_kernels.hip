@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
         return;
     }
     Segs S;
-    load_segments(segs + (p * chunks + c) * kSegInts, S);
+    load_segments(segs + ((PRG - 1) * n * chunks + p * chunks + c) * kSegInts, S);
     LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, 0, 0, lane, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restr
         return;
     }
     Segs S;
-    load_segments(segs + (p * chunks + c) * kSegInts, S);
+    load_segments(segs + ((PRG - 1) * n * chunks + p * chunks + c) * kSegInts, S);
     FisherSegment seg;
     seg.rec = rec;
     seg.Tl = T;
@@ -588,12 +588,17 @@ __global__ void k_transitions(const double* __restrict__ recs, int64_t n, double
 // ==================================================================================
 
 // Region segments of every (point, chunk), once per call.
+// Segment tables [3 phase regions][n][chunks]: chunk c of region r covers the c-th piece of that
+// region's own bins, so each region launch spreads its work over all of its waves.
 __global__ void k_segments(const double* __restrict__ recs, int64_t n, int chunks, GridArgs g,
                            int* __restrict__ segs) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n * chunks) return;
-    const int64_t p = t / chunks;
-    const int c = static_cast<int>(t - p * chunks);
+    const int64_t per_region = n * chunks;
+    if (t >= 3 * per_region) return;
+    const int prg = static_cast<int>(t / per_region) + 1;
+    const int64_t pc = t - (prg - 1) * per_region;
+    const int64_t p = pc / chunks;
+    const int c = static_cast<int>(pc - p * chunks);
     const double* __restrict__ rec = recs + p * REC_N;
     Segs S;
     if (rec[R_VALID] == 0.0) {
@@ -603,7 +608,7 @@ __global__ void k_segments(const double* __restrict__ recs, int64_t n, int chunk
         for (int i = 0; i < 5; ++i) S.pr[i] = S.ar[i] = 0;
     } else {
         int64_t kb, ke;
-        chunk_range(rec[R_MS], g, c, chunks, kb, ke);
+        region_chunk_range(rec, g, prg, c, chunks, kb, ke);
         make_segments(rec, g, kb, ke, S);
     }
     store_segments(S, segs + t * kSegInts);
@@ -663,7 +668,7 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
                           double* grad, hipEvent_t before_epilogue, hipStream_t s) {
     const int64_t waves = n * chunks;
     const unsigned nblk = blocks_for(waves, 4);
-    hipLaunchKernelGGL(k_segments, dim3(blocks_for(waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
+    hipLaunchKernelGGL(k_segments, dim3(blocks_for(3 * waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
     if (grad) {
         {
             ProfRange pr(PD_K_LOGLIKE_GRAD, s);
@@ -694,7 +699,7 @@ hipError_t launch_fisher(const double* theta, int param, const double* recs, con
                          int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* F,
                          hipStream_t s) {
     const int64_t waves = n * chunks;
-    hipLaunchKernelGGL(k_segments, dim3(blocks_for(waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
+    hipLaunchKernelGGL(k_segments, dim3(blocks_for(3 * waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
     {
         ProfRange pr(PD_K_FISHER, s);
         hipLaunchKernelGGL(k_fisher_partial<3>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,

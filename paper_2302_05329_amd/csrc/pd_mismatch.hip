@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     seg.lane = lane;
     seg.tot = 0.0;
     int64_t kb, ke;
-    region_chunk_range<PRG>(rec, g, c, chunks, kb, ke);
+    region_chunk_range(rec, g, PRG, c, chunks, kb, ke);
     Segs S;
     make_segments(rec, g, kb, ke, S);
 #pragma unroll
