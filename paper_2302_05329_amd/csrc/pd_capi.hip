@@ -274,13 +274,19 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
         if (e != hipSuccess) return fail_hip(e, "setup tangents");
         if (side && hipEventRecord(side->join, side->s) != hipSuccess) return fail_hip(hipGetLastError(), "join");
     }
+    // a failure past this point still joins the side stream, so that no kernel of this call
+    // writes into the workspace after the error is returned
+    auto fail_joined = [&](hipError_t err, const char* what) {
+        if (side) (void)hipStreamWaitEvent(s, side->join, 0);
+        return fail_hip(err, what);
+    };
     e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
-    if (e != hipSuccess) return fail_hip(e, "setup");
+    if (e != hipSuccess) return fail_joined(e, "setup");
     e = pd::launch_tables(g, data, inv_psd, tab, s);
-    if (e != hipSuccess) return fail_hip(e, "tables");
+    if (e != hipSuccess) return fail_joined(e, "tables");
     e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl,
                            grad, side ? side->join : nullptr, s);
-    if (e != hipSuccess) return fail_hip(e, "loglike");
+    if (e != hipSuccess) return fail_joined(e, "loglike");
     return PD_OK;
 }
 
