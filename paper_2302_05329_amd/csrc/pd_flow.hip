@@ -14,7 +14,7 @@
 // Parameter layout (float32): per layer W1[7][128], b1[128], W2[128][128], b2[128],
 // W3[128][14], b3[14] (19342 floats), 8 layers, then mu[7], isd[7].
 //
-// Kernels: one block of 256 threads per tile of samples, all 8 layers fused, activations
+// Kernels: one block of 1024 threads per tile of samples, all 8 layers fused, activations
 // in LDS, weights read through the caches.  Training saves each layer's input, hidden
 // activations and outputs; the backward kernel writes one row of weight-gradient partial
 // sums per tile, reduced in a fixed order (no atomics).
@@ -42,13 +42,15 @@ constexpr float kSC = 2.0f;                 // bound of the log-scale
 constexpr int kSave = 8 + kH + kH + 16;     // per sample per layer: y_in, h1, h2, o
 constexpr int kTF = 16;                     // samples per tile, forward / inverse
 constexpr int kTB = 32;                     // samples per tile, backward
+constexpr int kNTF = 1024;                  // threads per block of the FP32 kernels
+static_assert((kTF * kH) % kNTF == 0 && (kTB * kH) % kNTF == 0, "whole samples per thread");
 constexpr float kHalfLog2Pi = 0.91893853320467274178f;
 
 __device__ __forceinline__ bool cond_dim(int layer, int d) { return (layer & 1) ? (d >= 3) : (d < 3); }
 
 // Fused 8-layer pass over one tile.  INV: latent -> data.  SAVE: keep activations.
 template <bool INV, bool SAVE>
-__global__ void __launch_bounds__(256) k_flow(const float* __restrict__ P, const double* __restrict__ in, int64_t n,
+__global__ void __launch_bounds__(kNTF) k_flow(const float* __restrict__ P, const double* __restrict__ in, int64_t n,
                                               double* __restrict__ out, double* __restrict__ logq,
                                               float* __restrict__ saved) {
     __shared__ float y[kTF][8];
@@ -84,7 +86,7 @@ __global__ void __launch_bounds__(256) k_flow(const float* __restrict__ P, const
             if (s0 + s < n) saved[((s0 + s) * kLayers + layer) * kSave + d] = y[s][d];
         }
         // hidden layer 1
-        for (int idx = t; idx < kTF * kH; idx += 256) {
+        for (int idx = t; idx < kTF * kH; idx += kNTF) {
             const int s = idx / kH, j = idx % kH;
             float a = B1[j];
 #pragma unroll
@@ -93,19 +95,20 @@ __global__ void __launch_bounds__(256) k_flow(const float* __restrict__ P, const
             h1[s][j] = tanhf(a);
         }
         __syncthreads();
-        // hidden layer 2: thread -> column j, 8 samples
+        // hidden layer 2: thread -> column j, kSF samples
         {
-            const int j = t % kH, sg = (t / kH) * 8;
-            float acc[8];
+            constexpr int kSF = kTF * kH / kNTF;
+            const int j = t % kH, sg = (t / kH) * kSF;
+            float acc[kSF];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) acc[r] = B2[j];
+            for (int r = 0; r < kSF; ++r) acc[r] = B2[j];
             for (int k = 0; k < kH; ++k) {
                 const float w = W2[k * kH + j];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) acc[r] = fmaf(w, h1[sg + r][k], acc[r]);
+                for (int r = 0; r < kSF; ++r) acc[r] = fmaf(w, h1[sg + r][k], acc[r]);
             }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) h2[sg + r][j] = tanhf(acc[r]);
+            for (int r = 0; r < kSF; ++r) h2[sg + r][j] = tanhf(acc[r]);
         }
         __syncthreads();
         // output layer
@@ -117,7 +120,7 @@ __global__ void __launch_bounds__(256) k_flow(const float* __restrict__ P, const
         }
         __syncthreads();
         if (SAVE) {
-            for (int idx = t; idx < kTF * (2 * kH + 16); idx += 256) {
+            for (int idx = t; idx < kTF * (2 * kH + 16); idx += kNTF) {
                 const int s = idx / (2 * kH + 16), r = idx % (2 * kH + 16);
                 if (s0 + s >= n) continue;
                 float v;
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(256) k_flow(const float* __restrict__ P, const
 
 // Backward pass of loss = -mean(log q) over one tile of kTB samples; writes this tile's
 // weight-gradient partial sums partial[tile][P].
-__global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__ P, int64_t n,
+__global__ void __launch_bounds__(kNTF) k_flow_backward(const float* __restrict__ P, int64_t n,
                                                        const double* __restrict__ z, const float* __restrict__ saved,
                                                        float* __restrict__ partial) {
     __shared__ float yin[kTB][8];
@@ -182,7 +185,7 @@ __global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__
         const int s = t / 8, d = t % 8;
         gy[s][d] = (d < kD && s0 + s < n) ? static_cast<float>(z[(s0 + s) * kD + d]) * invB : 0.0f;
     }
-    for (int i = t; i < 2 * kD; i += 256) gp[kOffStd + i] = 0.0f;
+    for (int i = t; i < 2 * kD; i += kNTF) gp[kOffStd + i] = 0.0f;
     __syncthreads();
     for (int layer = kLayers - 1; layer >= 0; --layer) {
         const float* W1 = P + layer * kLayerP + kOffW1;
@@ -190,7 +193,7 @@ __global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__
         const float* W3 = P + layer * kLayerP + kOffW3;
         float* G = gp + layer * kLayerP;
         // load the saved activations of this layer
-        for (int idx = t; idx < kTB * kSave; idx += 256) {
+        for (int idx = t; idx < kTB * kSave; idx += kNTF) {
             const int s = idx / kSave, r = idx % kSave;
             const float v = (s0 + s < n) ? saved[((s0 + s) * kLayers + layer) * kSave + r] : 0.0f;
             if (r < 8)
@@ -223,7 +226,7 @@ __global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__
         }
         __syncthreads();
         // output layer: gW3, gb3, gh2 = W3 go
-        for (int idx = t; idx < kH * kO + kO; idx += 256) {
+        for (int idx = t; idx < kH * kO + kO; idx += kNTF) {
             float a = 0.0f;
             if (idx < kH * kO) {
                 const int k = idx / kO, c = idx % kO;
@@ -235,7 +238,7 @@ __global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__
                 G[kOffB3 + c] = a;
             }
         }
-        for (int idx = t; idx < kTB * kH; idx += 256) {
+        for (int idx = t; idx < kTB * kH; idx += kNTF) {
             const int s = idx / kH, k = idx % kH;
             float a = 0.0f;
 #pragma unroll
@@ -244,7 +247,7 @@ __global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__
         }
         __syncthreads();
         // hidden layer 2: gW2[k][j] = sum_s h1[s][k] ga2[s][j], gb2, then gh1 = W2 ga2
-        for (int idx = t; idx < kH * kH; idx += 256) {
+        for (int idx = t; idx < kH * kH; idx += kNTF) {
             const int k = idx / kH, j = idx % kH;
             float a = 0.0f;
             for (int s = 0; s < kTB; ++s) a = fmaf(h1[s][k], gh[s][j], a);
@@ -255,24 +258,25 @@ __global__ void __launch_bounds__(256) k_flow_backward(const float* __restrict__
             for (int s = 0; s < kTB; ++s) a += gh[s][t];
             G[kOffB2 + t] = a;
         }
-        // gh1 into h2's storage (h2 no longer needed): thread -> row k, 16 samples
+        // gh1 into h2's storage (h2 no longer needed): thread -> row k, kSB samples
         {
-            const int k = t % kH, sg = (t / kH) * (kTB / 2);
-            float acc[kTB / 2];
+            constexpr int kSB = kTB * kH / kNTF;
+            const int k = t % kH, sg = (t / kH) * kSB;
+            float acc[kSB];
 #pragma unroll
-            for (int r = 0; r < kTB / 2; ++r) acc[r] = 0.0f;
+            for (int r = 0; r < kSB; ++r) acc[r] = 0.0f;
             for (int j = 0; j < kH; ++j) {
                 const float w = W2[k * kH + j];
 #pragma unroll
-                for (int r = 0; r < kTB / 2; ++r) acc[r] = fmaf(w, gh[sg + r][j], acc[r]);
+                for (int r = 0; r < kSB; ++r) acc[r] = fmaf(w, gh[sg + r][j], acc[r]);
             }
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kTB / 2; ++r) h2[sg + r][k] = acc[r] * (1.0f - h1[sg + r][k] * h1[sg + r][k]);
+            for (int r = 0; r < kSB; ++r) h2[sg + r][k] = acc[r] * (1.0f - h1[sg + r][k] * h1[sg + r][k]);
         }
         __syncthreads();
         // hidden layer 1 (ga1 in h2): gW1[d][j] = sum_s in[s][d] ga1[s][j], gb1, gin = W1 ga1
-        for (int idx = t; idx < kD * kH + kH; idx += 256) {
+        for (int idx = t; idx < kD * kH + kH; idx += kNTF) {
             float a = 0.0f;
             if (idx < kD * kH) {
                 const int d = idx / kH, j = idx % kH;
@@ -310,6 +314,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTM = 32;   // samples per block in the matrix-core kernels
+constexpr int kNT = 1024;  // threads per block in the matrix-core kernels (16 waves share a tile)
+constexpr int kNW = kNT / 64;
 
 // One 16 x 16 output tile C[mt][nt] += A[16 mt.., 0..K) B[0..K, 16 nt..] with A(i, k) and
 // B(k, j) supplied as FP32 and rounded to bfloat16.  K is a multiple of 32.
@@ -335,7 +341,7 @@ __device__ __forceinline__ int tile_row(int mt, int lane, int r) { return 16 * m
 __device__ __forceinline__ int tile_col(int nt, int lane) { return 16 * nt + (lane & 15); }
 
 template <bool INV, bool SAVE>
-__global__ void __launch_bounds__(256) k_flow_mf(const float* __restrict__ P, const double* __restrict__ in, int64_t n,
+__global__ void __launch_bounds__(kNT) k_flow_mf(const float* __restrict__ P, const double* __restrict__ in, int64_t n,
                                                  double* __restrict__ out, double* __restrict__ logq,
                                                  float* __restrict__ saved) {
     __shared__ float y[kTM][8];
@@ -348,8 +354,8 @@ __global__ void __launch_bounds__(256) k_flow_mf(const float* __restrict__ P, co
     const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kTM;
     const float* mu = P + kOffStd;
     const float* isd = mu + kD;
-    {
-        const int s = t / 8, d = t % 8;   // 256 threads cover 32 x 8
+    if (t < kTM * 8) {
+        const int s = t / 8, d = t % 8;
         float v = 0.0f;
         if (d < kD && s0 + s < n) {
             const float xv = static_cast<float>(in[(s0 + s) * kD + d]);
@@ -367,12 +373,12 @@ __global__ void __launch_bounds__(256) k_flow_mf(const float* __restrict__ P, co
         const float* B2 = P + layer * kLayerP + kOffB2;
         const float* W3 = P + layer * kLayerP + kOffW3;
         const float* B3 = P + layer * kLayerP + kOffB3;
-        if (SAVE) {
+        if (SAVE && t < kTM * 8) {
             const int s = t / 8, d = t % 8;
             if (s0 + s < n) saved[((s0 + s) * kLayers + layer) * kSave + d] = y[s][d];
         }
         // input layer (FP32)
-        for (int idx = t; idx < kTM * kH; idx += 256) {
+        for (int idx = t; idx < kTM * kH; idx += kNT) {
             const int s = idx / kH, j = idx % kH;
             float a = B1[j];
 #pragma unroll
@@ -382,7 +388,7 @@ __global__ void __launch_bounds__(256) k_flow_mf(const float* __restrict__ P, co
         }
         __syncthreads();
         // hidden layer on the matrix cores: 2 x 8 tiles, 4 per wave
-        for (int tt = w; tt < 16; tt += 4) {
+        for (int tt = w; tt < 16; tt += kNW) {
             const int mt = tt >> 3, nt = tt & 7;
             const f4 acc = mfma_tile<kH>([&](int i, int k) { return h1[i][k]; },
                                          [&](int k, int j) { return W2[k * kH + j]; }, mt, nt, lane);
@@ -401,7 +407,7 @@ __global__ void __launch_bounds__(256) k_flow_mf(const float* __restrict__ P, co
         }
         __syncthreads();
         if (SAVE) {
-            for (int idx = t; idx < kTM * (2 * kH + 16); idx += 256) {
+            for (int idx = t; idx < kTM * (2 * kH + 16); idx += kNT) {
                 const int s = idx / (2 * kH + 16), r = idx % (2 * kH + 16);
                 if (s0 + s >= n) continue;
                 const float v = (r < kH) ? h1[s][r] : ((r < 2 * kH) ? h2[s][r - kH] : o[s][r - 2 * kH]);
@@ -443,7 +449,7 @@ __global__ void __launch_bounds__(256) k_flow_mf(const float* __restrict__ P, co
 
 // Backward pass of loss = -mean(log q) over one tile of kTM samples with the GEMMs of the
 // hidden and output layers on the matrix cores; writes the tile's weight-gradient row.
-__global__ void __launch_bounds__(256) k_flow_backward_mf(const float* __restrict__ P, int64_t n,
+__global__ void __launch_bounds__(kNT) k_flow_backward_mf(const float* __restrict__ P, int64_t n,
                                                           const double* __restrict__ z,
                                                           const float* __restrict__ saved,
                                                           float* __restrict__ partial) {
@@ -458,18 +464,18 @@ __global__ void __launch_bounds__(256) k_flow_backward_mf(const float* __restric
     const int64_t s0 = static_cast<int64_t>(blockIdx.x) * kTM;
     float* gp = partial + static_cast<int64_t>(blockIdx.x) * kP;
     const float invB = 1.0f / static_cast<float>(n);
-    {
+    if (t < kTM * 8) {
         const int s = t / 8, d = t % 8;
         gy[s][d] = (d < kD && s0 + s < n) ? static_cast<float>(z[(s0 + s) * kD + d]) * invB : 0.0f;
     }
-    for (int i = t; i < 2 * kD; i += 256) gp[kOffStd + i] = 0.0f;
+    for (int i = t; i < 2 * kD; i += kNT) gp[kOffStd + i] = 0.0f;
     __syncthreads();
     for (int layer = kLayers - 1; layer >= 0; --layer) {
         const float* W1 = P + layer * kLayerP + kOffW1;
         const float* W2 = P + layer * kLayerP + kOffW2;
         const float* W3 = P + layer * kLayerP + kOffW3;
         float* G = gp + layer * kLayerP;
-        for (int idx = t; idx < kTM * kSave; idx += 256) {
+        for (int idx = t; idx < kTM * kSave; idx += kNT) {
             const int s = idx / kSave, r = idx % kSave;
             const float v = (s0 + s < n) ? saved[((s0 + s) * kLayers + layer) * kSave + r] : 0.0f;
             if (r < 8)
@@ -507,7 +513,7 @@ __global__ void __launch_bounds__(256) k_flow_backward_mf(const float* __restric
         __syncthreads();
         // output layer: gW3 = H2^T go (8 x 1 tiles, K = 32 samples), gb3, and
         // gh2 = go W3^T (2 x 8 tiles, K = 16 padded to 32)
-        for (int tt = w; tt < 8; tt += 4) {
+        for (int tt = w; tt < 8; tt += kNW) {
             const f4 acc = mfma_tile<kTM>([&](int k, int s) { return h2[s][k]; },
                                           [&](int s, int c) { return go[s][c]; }, tt, 0, lane);
             const int c = tile_col(0, lane);
@@ -520,7 +526,7 @@ __global__ void __launch_bounds__(256) k_flow_backward_mf(const float* __restric
             for (int s = 0; s < kTM; ++s) a += go[s][t];
             G[kOffB3 + t] = a;
         }
-        for (int tt = w; tt < 16; tt += 4) {
+        for (int tt = w; tt < 16; tt += kNW) {
             const int mt = tt >> 3, nt = tt & 7;
             const f4 acc = mfma_tile<32>([&](int s, int c) { return c < 16 ? go[s][c] : 0.0f; },
                                          [&](int c, int j) { return c < kO ? W3[j * kO + c] : 0.0f; }, mt, nt, lane);
@@ -533,7 +539,7 @@ __global__ void __launch_bounds__(256) k_flow_backward_mf(const float* __restric
         }
         __syncthreads();
         // hidden layer: gW2 = H1^T ga2 (8 x 8 tiles, K = 32 samples), gb2
-        for (int tt = w; tt < 64; tt += 4) {
+        for (int tt = w; tt < 64; tt += kNW) {
             const int mt = tt >> 3, nt = tt & 7;
             const f4 acc = mfma_tile<kTM>([&](int k, int s) { return h1[s][k]; },
                                           [&](int s, int j) { return gh[s][j]; }, mt, nt, lane);
@@ -547,7 +553,7 @@ __global__ void __launch_bounds__(256) k_flow_backward_mf(const float* __restric
             G[kOffB2 + t] = a;
         }
         // gh1 = ga2 W2^T (2 x 8 tiles, K = 128), into h2's storage (h2 is no longer needed)
-        for (int tt = w; tt < 16; tt += 4) {
+        for (int tt = w; tt < 16; tt += kNW) {
             const int mt = tt >> 3, nt = tt & 7;
             const f4 acc = mfma_tile<kH>([&](int s, int j) { return gh[s][j]; },
                                          [&](int j, int k) { return W2[k * kH + j]; }, mt, nt, lane);
@@ -560,7 +566,7 @@ __global__ void __launch_bounds__(256) k_flow_backward_mf(const float* __restric
         }
         __syncthreads();
         // input layer (FP32): gW1, gb1, and the part of gy through the conditioning dims
-        for (int idx = t; idx < kD * kH + kH; idx += 256) {
+        for (int idx = t; idx < kD * kH + kH; idx += kNT) {
             float a = 0.0f;
             if (idx < kD * kH) {
                 const int d = idx / kH, j = idx % kH;
@@ -639,10 +645,10 @@ size_t flow_ws_bytes(int64_t n) {
 
 int flow_forward(const float* params, const double* x, int64_t n, double* z, double* logq, int mode, hipStream_t s) {
     if (mode == PD_FLOW_BF16) {
-        hipLaunchKernelGGL((k_flow_mf<false, false>), dim3(static_cast<unsigned>((n + kTM - 1) / kTM)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_flow_mf<false, false>), dim3(static_cast<unsigned>((n + kTM - 1) / kTM)), dim3(kNT), 0, s,
                            params, x, n, z, logq, nullptr);
     } else {
-        hipLaunchKernelGGL((k_flow<false, false>), dim3(static_cast<unsigned>((n + kTF - 1) / kTF)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_flow<false, false>), dim3(static_cast<unsigned>((n + kTF - 1) / kTF)), dim3(kNTF), 0, s,
                            params, x, n, z, logq, nullptr);
     }
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
@@ -650,10 +656,10 @@ int flow_forward(const float* params, const double* x, int64_t n, double* z, dou
 
 int flow_sample(const float* params, const double* z, int64_t n, double* x, double* logq, int mode, hipStream_t s) {
     if (mode == PD_FLOW_BF16) {
-        hipLaunchKernelGGL((k_flow_mf<true, false>), dim3(static_cast<unsigned>((n + kTM - 1) / kTM)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_flow_mf<true, false>), dim3(static_cast<unsigned>((n + kTM - 1) / kTM)), dim3(kNT), 0, s,
                            params, z, n, x, logq, nullptr);
     } else {
-        hipLaunchKernelGGL((k_flow<true, false>), dim3(static_cast<unsigned>((n + kTF - 1) / kTF)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_flow<true, false>), dim3(static_cast<unsigned>((n + kTF - 1) / kTF)), dim3(kNTF), 0, s,
                            params, z, n, x, logq, nullptr);
     }
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
@@ -675,12 +681,12 @@ int flow_loss_grad(const float* params, const double* x, int64_t n, float* grad,
     const int tiles = static_cast<int>((n + kTB - 1) / kTB);
     static_assert(kTM == kTB, "both backward kernels write one gradient row per 32-sample tile");
     if (mode == PD_FLOW_BF16) {
-        hipLaunchKernelGGL((k_flow_mf<false, true>), dim3(static_cast<unsigned>((n + kTM - 1) / kTM)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_flow_mf<false, true>), dim3(static_cast<unsigned>((n + kTM - 1) / kTM)), dim3(kNT), 0, s,
                            params, x, n, z, lq, saved);
-        hipLaunchKernelGGL(k_flow_backward_mf, dim3(tiles), dim3(256), 0, s, params, n, z, saved, partial);
+        hipLaunchKernelGGL(k_flow_backward_mf, dim3(tiles), dim3(kNT), 0, s, params, n, z, saved, partial);
     } else {
-        hipLaunchKernelGGL((k_flow<false, true>), dim3(fblocks), dim3(256), 0, s, params, x, n, z, lq, saved);
-        hipLaunchKernelGGL(k_flow_backward, dim3(tiles), dim3(256), 0, s, params, n, z, saved, partial);
+        hipLaunchKernelGGL((k_flow<false, true>), dim3(fblocks), dim3(kNTF), 0, s, params, x, n, z, lq, saved);
+        hipLaunchKernelGGL(k_flow_backward, dim3(tiles), dim3(kNTF), 0, s, params, n, z, saved, partial);
     }
     hipLaunchKernelGGL(k_grad_reduce, dim3((kP + 255) / 256), dim3(256), 0, s, partial, tiles, grad);
     if (loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, lq, n, loss);
