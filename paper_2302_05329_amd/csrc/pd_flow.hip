@@ -591,12 +591,19 @@ __global__ void __launch_bounds__(kNT) k_flow_backward_mf(const float* __restric
     }
 }
 
+// Sum of the tiles' gradient rows in a fixed order: eight interleaved running sums (tile i goes
+// to sum i mod 8, so eight loads are in flight per thread), then those eight in order.
 __global__ void k_grad_reduce(const float* __restrict__ partial, int tiles, float* __restrict__ grad) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= kP) return;
-    float a = 0.0f;
-    for (int i = 0; i < tiles; ++i) a += partial[static_cast<int64_t>(i) * kP + p];
-    grad[p] = a;
+    float a[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    int i = 0;
+    for (; i + 8 <= tiles; i += 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) a[r] += partial[static_cast<int64_t>(i + r) * kP + p];
+    }
+    for (int r = 0; i < tiles; ++i, ++r) a[r] += partial[static_cast<int64_t>(i) * kP + p];
+    grad[p] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 __global__ void k_loss(const double* __restrict__ logq, int64_t n, double* __restrict__ loss) {
