@@ -323,13 +323,24 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         const double w2 = w * w, w3 = w2 * w, w5 = w3 * w2;
         const double v2 = v * v, v3 = v2 * v, v4 = v3 * v, v5 = v4 * v, v6 = v5 * v;
         const double bs[13] = {w5, w3, w2, w, 1.0, lv, v, v * lv, v2, v3, v4, v5, v6};
-        const double pw[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
-        fpsi = fma(c[R_PH1 + 7], v, c[R_PH1 + 5]) * sk(1.0 / 3.0);
+        const int pw[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
+        // Mf dPsi/dMf = (1/3) [c5 + c7 v + sum_j pw_j c_j b_j]: each term is (c_j b_j) times a small
+        // integer, so no coefficient is multiplied by a constant in the bin loop
+        double s3 = fma(c[R_PH1 + 7], v, c[R_PH1 + 5]);
 #pragma unroll
         for (int j = 0; j < 13; ++j) {
             vis.ph(R_PH1 + j, bs[j]);
-            if (pw[j] != 0.0) fpsi = fma(c[R_PH1 + j] * sk(pw[j] * (1.0 / 3.0)), bs[j], fpsi);
+            if (pw[j] != 0) {
+                const double cb = c[R_PH1 + j] * bs[j];
+                if (pw[j] == 1)
+                    s3 += cb;
+                else if (pw[j] == -1)
+                    s3 -= cb;
+                else
+                    s3 = fma(static_cast<double>(pw[j]), cb, s3);
+            }
         }
+        fpsi = s3 * sk(1.0 / 3.0);
     } else if (PR == 2) {
         const double i3 = b.invf * b.invf * b.invf;
         vis.ph(R_PH2 + 0, 1.0);
@@ -359,9 +370,9 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         for (int i = 1; i < 10; ++i) {
             p *= b.v;
             vis.am(R_AM1 + i, p);
-            acc = fma(c[R_AM1 + i] * sk(i * (1.0 / 3.0)), p, acc);
+            acc = fma(static_cast<double>(i), c[R_AM1 + i] * p, acc);
         }
-        fa = acc;
+        fa = acc * sk(1.0 / 3.0);
     } else if (AR == 2) {
         const double ia = pd_rcp(b.ahat);
         const double f = b.mf;
@@ -372,7 +383,7 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         for (int i = 1; i < 5; ++i) {
             p *= f;
             vis.am(R_AM2 + i, p);
-            acc = fma(c[R_AM2 + i] * sk(static_cast<double>(i)), p, acc);
+            acc = fma(static_cast<double>(i), c[R_AM2 + i] * p, acc);
         }
         fa = acc;
     } else {
