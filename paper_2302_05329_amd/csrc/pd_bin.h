@@ -347,7 +347,7 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         vis.ph(R_PH2 + 1, b.mf);
         vis.ph(R_PH2 + 2, b.lnf);
         vis.ph(R_PH2 + 3, i3);
-        fpsi = fma(c[R_PH2 + 1], b.mf, fma(sk(-3.0) * c[R_PH2 + 3], i3, c[R_PH2 + 2]));
+        fpsi = fma(c[R_PH2 + 1], b.mf, fma(c[R_PH2 + 3] * i3, sk(-3.0), c[R_PH2 + 2]));
     } else {
         const double t = c[R_PH3 + 4] * b.iu2 * c[R_ID];
         vis.ph(R_PH3 + 0, 1.0);
@@ -357,7 +357,7 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         vis.ph(R_PH3 + 4, b.at);
         vis.ph(R_PH3 + 5, -t);
         vis.ph(R_PH3 + 6, -t * b.u);
-        fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(sk(0.75) * c[R_PH3 + 3], b.f34, t * b.mf)));
+        fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(c[R_PH3 + 3] * b.f34, sk(0.75), t * b.mf)));
     }
     double fa;
     vis.am(R_LNA0, 1.0);
