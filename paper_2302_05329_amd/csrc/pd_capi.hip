@@ -246,6 +246,19 @@ int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* g
 int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
                         const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
                         int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    return pd::loglike_and_grad(theta, n, param, grid, lambda, data, inv_psd, precision, lnl, grad, status, workspace,
+                                workspace_bytes, static_cast<hipStream_t>(stream), false);
+}
+
+}  // extern "C"
+
+// tables_ready: the workspace already holds this grid's tables for the same data and noise
+// weights (a caller that evaluates many parameter batches against one data set, such as the
+// leapfrog steps of one HMC transition, computes them once).
+int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                         const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
+                         int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s,
+                         bool tables_ready) {
     pd::GridArgs g;
     int rc = check_common(theta, n, param, grid, lambda, &g);
     if (rc) return rc;
@@ -257,7 +270,6 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
     Layout L;
     rc = check_ws(op, n, g.nb, workspace, workspace_bytes, &L);
     if (rc) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     double* recs = at<double>(workspace, L.rec);
     double* partial = at<double>(workspace, L.partial);
     double* tab = at<double>(workspace, L.tab);
@@ -282,13 +294,17 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
     };
     e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
     if (e != hipSuccess) return fail_joined(e, "setup");
-    e = pd::launch_tables(g, data, inv_psd, tab, s);
-    if (e != hipSuccess) return fail_joined(e, "tables");
+    if (!tables_ready) {
+        e = pd::launch_tables(g, data, inv_psd, tab, s);
+        if (e != hipSuccess) return fail_joined(e, "tables");
+    }
     e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl,
                            grad, side ? side->join : nullptr, s);
     if (e != hipSuccess) return fail_joined(e, "loglike");
     return PD_OK;
 }
+
+extern "C" {
 
 int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
               const double* inv_psd, double* F, int32_t* status, void* workspace, size_t workspace_bytes,

@@ -44,8 +44,11 @@ hipError_t launch_fisher(const double* theta, int param, const double* recs, con
 int posterior_check(const pd_posterior* post);
 size_t posterior_ws_bytes(const pd_posterior* post, int64_t n);
 size_t hmc_workspace_bytes(const pd_posterior* post, int64_t n);
+int loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                     const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
+                     int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s, bool tables_ready);
 int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
-                   hipStream_t s);
+                   hipStream_t s, bool tables_ready = false);
 int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
              const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
              void* ws, hipStream_t s);

@@ -254,7 +254,7 @@ int posterior_check(const pd_posterior* post) {
 }
 
 int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
-                   hipStream_t s) {
+                   hipStream_t s, bool tables_ready) {
     if (post->kind == PD_TARGET_GAUSS) {
         hipLaunchKernelGGL(k_gauss, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, logp, grad);
         return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
@@ -262,9 +262,9 @@ int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double*
     PostWs w = post_ws(post, n, ws);
     hipLaunchKernelGGL(k_transform, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx, w.lj, w.dlj);
     if (hipGetLastError() != hipSuccess) return PD_EHIP;
-    const int rc = pd_loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data,
-                                       post->inv_psd, PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll,
-                                       w.ll_bytes, s);
+    const int rc = loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data,
+                                    post->inv_psd, PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes,
+                                    s, tables_ready);
     if (rc != PD_OK) return rc;
     hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 128)), dim3(128), 0, s, n, w.lnl, w.gth, w.dtdx, w.lj, w.dlj,
                        logp, grad);
@@ -287,7 +287,8 @@ int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, doubl
         return PD_EHIP;
     for (int l = 0; l < n_leapfrog; ++l) {
         hipLaunchKernelGGL(k_hmc_drift, dim3(b7), dim3(256), 0, s, n, a, w.x1, w.p);
-        const int rc = posterior_logp(post, w.x1, n, w.logp1, w.grad1, w.post, s);
+        // the grid tables depend only on the data and noise: computed by the first leapfrog step
+        const int rc = posterior_logp(post, w.x1, n, w.logp1, w.grad1, w.post, s, l > 0);
         if (rc != PD_OK) return rc;
         const double weps = (l + 1 < n_leapfrog) ? eps : 0.5 * eps;
         hipLaunchKernelGGL(k_hmc_kick, dim3(b7), dim3(256), 0, s, n, weps, w.p, w.grad1);
