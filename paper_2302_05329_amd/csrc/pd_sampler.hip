@@ -26,14 +26,26 @@ __device__ __forceinline__ double sigmoid(double x) {
     return (x >= 0.0) ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x));
 }
 
-// x -> theta, d theta / d x, and the log-Jacobian with its derivative.
-__global__ void k_transform(const double* __restrict__ x, int64_t n, pd_posterior post, double* __restrict__ theta,
-                            double* __restrict__ dtdx, double* __restrict__ lj, double* __restrict__ dlj) {
+// x -> theta, d theta / d x, and the log-Jacobian with its derivative.  DRIFT: first the leapfrog
+// drift x += eps p / m (x updated in place).
+struct Drift {
+    double eps;
+    double mass[7];
+    const double* p;
+};
+
+template <bool DRIFT>
+__global__ void k_transform(double* __restrict__ x, int64_t n, pd_posterior post, double* __restrict__ theta,
+                            double* __restrict__ dtdx, double* __restrict__ lj, double* __restrict__ dlj, Drift dr) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
     for (int j = 0; j < 7; ++j) {
-        const double xv = x[i * 7 + j];
+        double xv = x[i * 7 + j];
+        if (DRIFT) {
+            xv = fma(dr.eps / dr.mass[j], dr.p[i * 7 + j], xv);
+            x[i * 7 + j] = xv;
+        }
         const double s = sigmoid(xv);
         const double w = post.hi[j] - post.lo[j];
         theta[i * 7 + j] = post.lo[j] + w * s;
@@ -47,15 +59,21 @@ __global__ void k_transform(const double* __restrict__ x, int64_t n, pd_posterio
     lj[i] = acc;
 }
 
+// log posterior and its gradient in x; with p given, then the leapfrog kick p += weps grad.
 __global__ void k_assemble(int64_t n, const double* __restrict__ lnl, const double* __restrict__ gth,
                            const double* __restrict__ dtdx, const double* __restrict__ lj,
-                           const double* __restrict__ dlj, double* __restrict__ logp, double* __restrict__ grad) {
+                           const double* __restrict__ dlj, double* __restrict__ logp, double* __restrict__ grad,
+                           double weps, double* __restrict__ p) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const bool ok = isfinite(lnl[i]);
     logp[i] = ok ? lnl[i] + lj[i] : -INFINITY;
     if (grad) {
-        for (int j = 0; j < 7; ++j) grad[i * 7 + j] = ok ? fma(gth[i * 7 + j], dtdx[i * 7 + j], dlj[i * 7 + j]) : 0.0;
+        for (int j = 0; j < 7; ++j) {
+            const double gj = ok ? fma(gth[i * 7 + j], dtdx[i * 7 + j], dlj[i * 7 + j]) : 0.0;
+            grad[i * 7 + j] = gj;
+            if (p) p[i * 7 + j] = fma(weps, gj, p[i * 7 + j]);
+        }
     }
 }
 
@@ -253,22 +271,37 @@ int posterior_check(const pd_posterior* post) {
     return PD_OK;
 }
 
-int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
-                   hipStream_t s, bool tables_ready) {
-    if (post->kind == PD_TARGET_GAUSS) {
-        hipLaunchKernelGGL(k_gauss, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, logp, grad);
-        return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
-    }
+// Log posterior (and gradient) at x.  Inside a leapfrog step (GW target): `drift` moves x first
+// (x is then updated in place) and `kick_p` receives p += kick_weps grad afterwards, each fused into
+// the neighbouring per-chain kernel.
+int posterior_logp_step(const pd_posterior* post, double* x, int64_t n, double* logp, double* grad, void* ws,
+                        hipStream_t s, bool tables_ready, const Drift* drift, double kick_weps, double* kick_p) {
     PostWs w = post_ws(post, n, ws);
-    hipLaunchKernelGGL(k_transform, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx, w.lj, w.dlj);
+    if (drift)
+        hipLaunchKernelGGL(k_transform<true>, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx, w.lj,
+                           w.dlj, *drift);
+    else
+        hipLaunchKernelGGL(k_transform<false>, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx,
+                           w.lj, w.dlj, Drift{});
     if (hipGetLastError() != hipSuccess) return PD_EHIP;
     const int rc = loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data,
                                     post->inv_psd, PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes,
                                     s, tables_ready);
     if (rc != PD_OK) return rc;
     hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 128)), dim3(128), 0, s, n, w.lnl, w.gth, w.dtdx, w.lj, w.dlj,
-                       logp, grad);
+                       logp, grad, kick_weps, kick_p);
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
+                   hipStream_t s, bool tables_ready) {
+    if (post->kind == PD_TARGET_GAUSS) {
+        hipLaunchKernelGGL(k_gauss, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, logp, grad);
+        return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+    }
+    // without a drift the transform only reads x
+    return posterior_logp_step(post, const_cast<double*>(x), n, logp, grad, ws, s, tables_ready, nullptr, 0.0,
+                               nullptr);
 }
 
 size_t posterior_ws_bytes(const pd_posterior* post, int64_t n) { return post_ws_bytes(post, n); }
@@ -285,13 +318,23 @@ int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, doubl
     hipLaunchKernelGGL(k_hmc_begin, dim3(b1), dim3(128), 0, s, n, a, xi, logp, grad, w.p, w.h0);
     if (hipMemcpyAsync(w.x1, x, static_cast<size_t>(n) * 7 * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return PD_EHIP;
+    Drift dr;
+    dr.eps = eps;
+    for (int j = 0; j < 7; ++j) dr.mass[j] = mass[j];
+    dr.p = w.p;
     for (int l = 0; l < n_leapfrog; ++l) {
-        hipLaunchKernelGGL(k_hmc_drift, dim3(b7), dim3(256), 0, s, n, a, w.x1, w.p);
-        // the grid tables depend only on the data and noise: computed by the first leapfrog step
-        const int rc = posterior_logp(post, w.x1, n, w.logp1, w.grad1, w.post, s, l > 0);
-        if (rc != PD_OK) return rc;
         const double weps = (l + 1 < n_leapfrog) ? eps : 0.5 * eps;
-        hipLaunchKernelGGL(k_hmc_kick, dim3(b7), dim3(256), 0, s, n, weps, w.p, w.grad1);
+        if (post->kind == PD_TARGET_GW) {
+            // drift fused into the coordinate transform, kick into the posterior assembly; the grid
+            // tables depend only on the data and noise and are computed by the first step
+            const int rc = posterior_logp_step(post, w.x1, n, w.logp1, w.grad1, w.post, s, l > 0, &dr, weps, w.p);
+            if (rc != PD_OK) return rc;
+        } else {
+            hipLaunchKernelGGL(k_hmc_drift, dim3(b7), dim3(256), 0, s, n, a, w.x1, w.p);
+            const int rc = posterior_logp(post, w.x1, n, w.logp1, w.grad1, w.post, s);
+            if (rc != PD_OK) return rc;
+            hipLaunchKernelGGL(k_hmc_kick, dim3(b7), dim3(256), 0, s, n, weps, w.p, w.grad1);
+        }
     }
     hipLaunchKernelGGL(k_hmc_accept, dim3(b1), dim3(128), 0, s, n, a, u, w.h0, w.x1, w.p, w.logp1, w.grad1, x, logp,
                        grad, accepted, dh);
