@@ -570,29 +570,6 @@ __device__ __forceinline__ void flush_touched(const double (&mom)[REC_N], int la
     if (c >= 0) tot += got;
 }
 
-// Dispatch a functor templated on the (phase, amplitude) region pair.
-template <class F>
-__device__ __forceinline__ void dispatch_region(int pr, int ar, F& f) {
-    if (pr == 1) {
-        if (ar == 1)
-            f.template run<1, 1>();
-        else if (ar == 2)
-            f.template run<1, 2>();
-        else
-            f.template run<1, 3>();
-    } else if (pr == 2) {
-        if (ar == 3)
-            f.template run<2, 3>();
-        else
-            f.template run<2, 2>();
-    } else {
-        if (ar == 3)
-            f.template run<3, 3>();
-        else
-            f.template run<3, 2>();
-    }
-}
-
 // Dispatch over the amplitude region for a fixed phase region.
 template <int PR, class F>
 __device__ __forceinline__ void dispatch_amp_region(int ar, F& f) {
