@@ -91,6 +91,52 @@ def test_hmc_step_parity_gw(gpu, lam0):
             assert np.max(np.abs(xg[i] - xr)) <= 1e-9 * (1 + np.max(np.abs(xr)))
 
 
+def test_posterior_and_hmc_full_c5_sampled(gpu, lam0):
+    """The learned-proposal workload at its full size (4096 chains x 8033 bins, the chunked
+    small-batch launch configuration) in one call: log posterior and gradient of sampled chains, and
+    one HMC transition of 10 leapfrog steps, against the oracle."""
+    import torch
+    from paper_2302_05329_amd import sampling
+    pb = _c5_problem(lam0)
+    post = sampling.Posterior(0, grid=pb["grid"], lam=lam0, data=pb["data"], inv_psd=pb["inv_psd"], lo=pb["lo"],
+                              hi=pb["hi"])
+    n = 4096
+    rng = np.random.default_rng(13)
+    x0 = post.to_x(pb["theta_inj"]) + 0.02 * rng.standard_normal((n, 7))
+    mass = np.array([400.0, 50.0, 20.0, 20.0, 10.0, 4e3, 4.0])
+    eps, L = 0.02, 10
+    xi = rng.standard_normal((n, 7))
+    u = rng.uniform(size=n)
+    _say(f"posterior logp + HMC step GW n={n} nb={pb['grid'].n_bins} L={L}")
+    lp, g = sampling.logp(post, x0)
+    hmc = sampling.HMC(post, x0, eps, L, mass)
+    acc = hmc.step(torch.as_tensor(xi, device="cuda"), torch.as_tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    xg, dhg, accg = hmc.x.cpu().numpy(), hmc.dh.cpu().numpy(), acc.cpu().numpy()
+    gr = pb["grid"].as_tuple()
+
+    def lpf(x):
+        return S.logp_gw(x, lam0, gr, pb["data"], pb["inv_psd"], pb["lo"], pb["hi"])
+
+    rows = sorted({0, n - 1} | set(int(i) for i in rng.choice(n, 2, replace=False)))
+    for i in rows:
+        ref_lp, ref_g = lpf(x0[i])
+        assert abs(lp[i] - ref_lp) <= 1e-10 * max(1.0, abs(ref_lp) / 1e3), (i, lp[i], ref_lp)
+        th, d, _, _ = S.transform(x0[i], pb["lo"], pb["hi"])
+        F = O.fisher(th, O.PARAM_MC_Q, lam0, gr, pb["inv_psd"])
+        r = pb["data"] - O.waveform(th, O.PARAM_MC_Q, lam0, gr)
+        scale = np.sqrt(O.inner(r, r, pb["inv_psd"], gr[1]) * np.diag(F)) * d + 1.0
+        assert np.all(np.abs(g[i] - ref_g) <= 1e-9 * scale), (i, g[i], ref_g)
+    for i in rows[:2]:
+        lp0, g0 = lpf(x0[i])
+        xr, _, _, ar, dhr = S.hmc_step(lpf, x0[i], lp0, g0, xi[i], u[i], L, eps, mass)
+        assert abs(dhg[i] - dhr) <= 1e-8 * max(1.0, abs(dhr)), (i, dhg[i], dhr)
+        if abs(-dhr - math.log(u[i])) > 1e-6:
+            assert accg[i] == ar
+            assert np.max(np.abs(xg[i] - xr)) <= 1e-9 * (1 + np.max(np.abs(xr)))
+
+
 def test_hmc_recovers_gaussian_target_on_gpu(gpu):
     import torch
     from paper_2302_05329_amd import sampling
