@@ -34,7 +34,7 @@ def _setup(n, seed=11, out_scale=0.5):
     return p, x, sd
 
 
-@pytest.mark.parametrize("n", [1, 16, 100, 1000])
+@pytest.mark.parametrize("n", [1, 16, 100, 1000, 4096])
 def test_forward_and_sample_parity(gpu, n):
     from paper_2302_05329_amd import flow
     p, x, sd = _setup(n)
@@ -53,7 +53,7 @@ def test_forward_and_sample_parity(gpu, n):
     assert np.all(np.abs(lqs - lqsr.numpy()) <= LQ_TOL * (1 + np.abs(lqsr.numpy()) / 10))
 
 
-@pytest.mark.parametrize("n", [7, 100, 513])
+@pytest.mark.parametrize("n", [7, 100, 513, 4096])
 def test_loss_and_gradient_parity(gpu, n):
     from paper_2302_05329_amd import flow
     p, x, _ = _setup(n, seed=12, out_scale=0.7)
@@ -177,7 +177,7 @@ def test_flow_proposal_mh_keeps_the_target(gpu):
 # the bf16 flow an exact proposal.
 
 
-@pytest.mark.parametrize("n", [1, 33, 1000])
+@pytest.mark.parametrize("n", [1, 33, 1000, 4096])
 def test_bf16_forward_sample_parity_and_self_consistency(gpu, n):
     from paper_2302_05329_amd import flow
     p, x, sd = _setup(n)
@@ -202,7 +202,7 @@ def test_bf16_forward_sample_parity_and_self_consistency(gpu, n):
     assert np.all(np.abs(lq2 - lqs) <= 0.5)
 
 
-@pytest.mark.parametrize("n", [7, 100, 513])
+@pytest.mark.parametrize("n", [7, 100, 513, 4096])
 def test_bf16_loss_and_gradient_parity(gpu, n):
     from paper_2302_05329_amd import flow
     p, x, _ = _setup(n, seed=12, out_scale=0.7)
