@@ -92,8 +92,8 @@ def main():
                     help="only run one plain 1 GiB device-to-device copy (the reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "the path shards by parameter points without communication, see the design notes.",
+        print(f"bench.py: the benchmark measures one GPU only (got --gpus {args.gpus}); "
+              "the path shards over parameter points with no communication between GPUs.",
               file=sys.stderr)
         sys.exit(2)
 
