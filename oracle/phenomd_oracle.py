@@ -17,13 +17,12 @@ print, so its structure is restated here from those model papers):
                       merger-ringdown Lorentzian; joined C1 at Mf = 0.014 and f_peak
   * strain            h(f) = A(f) exp(-i Psi(f)), zero above Mf = 0.2
   * inner product     Eq. (1) as a Riemann sum on the grid; likelihood ln L = (d|h) - (h|h)/2
-  * Fisher matrix     Eq. (fisher): F_ij = (d_i h | d_j h)
-  * match / mismatch  max over lag (discrete FFT lag) and phase (modulus), Eqs. (match), (mismatch)
+  * Fisher matrix     Eq. 8: F_ij = (d_i h | d_j h)
+  * match / mismatch  max over lag (discrete FFT lag) and phase (modulus), Eqs. 2-4
   * derivatives       complex-step differentiation of the real amplitude and phase
                       (a technique unrelated to the GPU's hand-written tangents)
 
-Readings where the paper is silent are listed in the design notes; the ones that
-matter for reading this file are repeated at the point of use.
+Where the paper is silent, the reading taken is stated at the point of use.
 
 Parity pins (tests/test_oracle_pins.py): C1 continuity at every join, the leading
 TaylorF2 term and its O(v^2) residual, the non-spinning TaylorF2 coefficients derived
