@@ -95,7 +95,7 @@ int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* g
                      const double* lambda, int precision, double* h_out, int32_t* status,
                      void* workspace, size_t workspace_bytes, void* stream);
 
-/* Gaussian log-likelihood of Sec. 3.3 with the inner product of Eq. (1) as a Riemann sum:
+/* Gaussian log-likelihood of Sec. 3.3 with the inner product of Eq. 1 as a Riemann sum:
  *   lnL = (d|h) - (h|h)/2,  (a|b) = 4 df Re sum_k conj(a_k) b_k / S_k,
  * fused so the strain is never written, and optionally its gradient w.r.t. theta
  * (hand-written forward-mode tangents of the per-point coefficients contracted with
@@ -110,7 +110,7 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
                         int precision, double* lnl, double* grad, int32_t* status,
                         void* workspace, size_t workspace_bytes, void* stream);
 
-/* Fisher information of one detector, Sec. 3.2 Eq. (fisher): F_pq = (d_p h | d_q h),
+/* Fisher information of one detector, Sec. 3.2 Eq. 8: F_pq = (d_p h | d_q h),
  * p, q over the 7 entries of theta in layout `param`.
  * F       [n][7][7]           output, symmetric
  */
@@ -119,7 +119,7 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid,
               void* workspace, size_t workspace_bytes, void* stream);
 
 /* Mismatch against fixed targets and its gradient w.r.t. the 209 fit coefficients,
- * Sec. 3.1 Eqs. (mismatch) and (multi_loss):
+ * Sec. 3.1 Eqs. 5 and 7:
  *   z_j = sum_k w_k conj(h_k) t_k exp(+2 pi i k j / N), j < N = n_bins = 65536,
  *   m = max_j |z_j| / sqrt((h|h)(t|t)),  M = 1 - m   (max over lag and phase),
  *   dsum_dlambda = sum over targets of dM / dlambda at the maximising lag.

@@ -16,7 +16,7 @@ print, so its structure is restated here from those model papers):
   * amplitude         inspiral (PN + rho terms), intermediate quartic (5 conditions),
                       merger-ringdown Lorentzian; joined C1 at Mf = 0.014 and f_peak
   * strain            h(f) = A(f) exp(-i Psi(f)), zero above Mf = 0.2
-  * inner product     Eq. (1) as a Riemann sum on the grid; likelihood ln L = (d|h) - (h|h)/2
+  * inner product     Eq. 1 as a Riemann sum on the grid; likelihood ln L = (d|h) - (h|h)/2
   * Fisher matrix     Eq. 8: F_ij = (d_i h | d_j h)
   * match / mismatch  max over lag (discrete FFT lag) and phase (modulus), Eqs. 2-4
   * derivatives       complex-step differentiation of the real amplitude and phase
