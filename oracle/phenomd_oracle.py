@@ -490,7 +490,7 @@ def waveforms(thetas, param, lam, grid):
 
 
 # ====================================================================================
-# inner products, likelihood, Fisher (Eq. 1, Eq. fisher)
+# inner products, likelihood, Fisher (Eq. 1, Eq. 8)
 # ====================================================================================
 
 def inner(a, b, inv_psd, df):
