@@ -63,7 +63,9 @@ typedef enum {
 } pd_param;
 
 /* Uniform frequency grid f_k = f0 + k*df (k < n_bins), f in Hz.  Bins with f_k < f_min
- * carry no signal; f_ref is the physical frequency where the phase is referenced. */
+ * carry no signal; f_ref is the physical frequency where the phase is referenced.
+ * 1 <= n_bins <= 2^28 (the per-bin tables are addressed with 32-bit byte offsets); a grid
+ * outside that range is a batch-level error (PD_EINVAL). */
 typedef struct {
     double f0;
     double df;

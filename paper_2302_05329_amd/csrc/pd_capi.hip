@@ -154,6 +154,7 @@ int check_common(const double* theta, int64_t n, int param, const pd_grid* grid,
     if (!(grid->df > 0.0) || !std::isfinite(grid->df)) return fail(PD_EINVAL, "grid df must be finite and > 0");
     if (!std::isfinite(grid->f0) || grid->f0 < 0.0) return fail(PD_EINVAL, "grid f0 must be finite and >= 0");
     if (grid->n_bins <= 0) return fail(PD_EINVAL, "grid n_bins must be > 0");
+    if (grid->n_bins > (int64_t(1) << 28)) return fail(PD_EINVAL, "grid n_bins must be <= 2^28");
     if (!std::isfinite(grid->f_min) || !(grid->f_min > 0.0))
         return fail(PD_EINVAL, "grid f_min must be finite and > 0");
     if (!std::isfinite(grid->f_ref) || !(grid->f_ref > 0.0))
@@ -451,7 +452,6 @@ int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, 
     if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
     if (!overlap) return fail(PD_EINVAL, "overlap is NULL");
     if (ns <= 0 || ns > PD_OVERLAP_MAX_STREAMS) return fail(PD_EINVAL, "ns must be in [1, 64]");
-    if (g.nb > (int64_t(1) << 30)) return fail(PD_EINVAL, "n_bins too large");
     Layout L;
     rc = check_ws(PD_OP_WAVEFORM, nt, g.nb, workspace, workspace_bytes, &L);
     if (rc) return rc;

@@ -63,6 +63,7 @@ def _call_waveform(lib, theta=1, n=1, param=3, grid=None, lam=1, prec=0, out=1, 
     (dict(wsb=16), L.PD_ENOMEM),
     (dict(grid=L.make_grid(20.0, 0.0, 100, 20.0, 20.0)), L.PD_EINVAL),
     (dict(grid=L.make_grid(20.0, 0.25, 0, 20.0, 20.0)), L.PD_EINVAL),
+    (dict(grid=L.make_grid(20.0, 0.25, (1 << 28) + 1, 20.0, 20.0)), L.PD_EINVAL),
     (dict(grid=L.make_grid(20.0, 0.25, 100, 0.0, 20.0)), L.PD_EINVAL),
     (dict(grid=L.make_grid(20.0, 0.25, 100, 20.0, float("nan"))), L.PD_EINVAL),
 ])
