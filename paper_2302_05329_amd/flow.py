@@ -60,13 +60,13 @@ class Flow:
         L.check(L.lib().pd_flow_sample(_ptr(self.params), _ptr(z), n, _ptr(x), _ptr(lq), self.mode, _stream()))
         return x, lq
 
-    def loss_grad(self, x):
-        """Fills self.grad with d(-mean log q)/d params and self.loss with the loss."""
+    def loss_grad(self, x, want_loss=True):
+        """Fills self.grad with d(-mean log q)/d params and, if want_loss, self.loss with the loss."""
         x = _x(x)
         n = x.shape[0]
         wp, wb = self.ws.get(L.lib().pd_flow_workspace_bytes(n))
-        L.check(L.lib().pd_flow_loss_grad(_ptr(self.params), _ptr(x), n, _ptr(self.grad), _ptr(self.loss), wp, wb,
-                                          self.mode, _stream()))
+        L.check(L.lib().pd_flow_loss_grad(_ptr(self.params), _ptr(x), n, _ptr(self.grad),
+                                          _ptr(self.loss) if want_loss else None, wp, wb, self.mode, _stream()))
         return self.loss
 
     def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):
@@ -82,9 +82,10 @@ class Flow:
         hist = []
         for k in range(steps):
             idx = torch.randint(0, x.shape[0], (batch,), device="cuda", generator=generator)
-            self.loss_grad(x.index_select(0, idx))
+            logged = bool(log_every) and (k % log_every == 0 or k == steps - 1)
+            self.loss_grad(x.index_select(0, idx), want_loss=logged)
             self.adam(lr)
-            if log_every and (k % log_every == 0 or k == steps - 1):
+            if logged:
                 hist.append(float(self.loss.item()))
         return hist
 
