@@ -15,6 +15,8 @@
 // No atomics anywhere: results are bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/phenomd.h"
 #include "pd_bin.h"
 #include "pd_launch.h"
@@ -663,6 +665,58 @@ hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, con
     return hipGetLastError();
 }
 
+// Two side streams (default priority) per host thread and device on which the intermediate and
+// inspiral launches of a moment pass run concurrently with the merger-ringdown launch, so that
+// the short launches fill the long one's tail instead of each draining the GPU in turn.
+struct RegionStreams {
+    int dev = -1;
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    bool ok = false;
+};
+
+static RegionStreams* region_streams() {
+    thread_local std::vector<RegionStreams> pool;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    for (auto& e : pool)
+        if (e.dev == dev) return e.ok ? &e : nullptr;
+    RegionStreams e;
+    e.dev = dev;
+    e.ok = hipStreamCreateWithFlags(&e.s[0], hipStreamNonBlocking) == hipSuccess &&
+           hipStreamCreateWithFlags(&e.s[1], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&e.fork, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&e.join[0], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&e.join[1], hipEventDisableTiming) == hipSuccess;
+    if (!e.ok) (void)hipGetLastError();
+    pool.push_back(e);
+    return pool.back().ok ? &pool.back() : nullptr;
+}
+
+// The three phase-region launches of one moment pass: merger-ringdown on s, intermediate and
+// inspiral on the side streams, joined back into s (sequential on s if the streams are missing).
+template <int MODE>
+static void launch_region_moments(unsigned nblk, const double* recs, int64_t n, int chunks, const GridArgs& g,
+                                  const double* tab, const int* segs, double* partial, hipStream_t s) {
+    RegionStreams* rs = region_streams();
+    const bool conc = rs && hipEventRecord(rs->fork, s) == hipSuccess &&
+                      hipStreamWaitEvent(rs->s[0], rs->fork, 0) == hipSuccess &&
+                      hipStreamWaitEvent(rs->s[1], rs->fork, 0) == hipSuccess;
+    const hipStream_t s2 = conc ? rs->s[0] : s, s1 = conc ? rs->s[1] : s;
+    hipLaunchKernelGGL((k_loglike_moments<MODE, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs,
+                       partial);
+    hipLaunchKernelGGL((k_loglike_moments<MODE, 2>), dim3(nblk), dim3(256), 0, s2, recs, n, chunks, g, tab, segs,
+                       partial);
+    hipLaunchKernelGGL((k_loglike_moments<MODE, 1>), dim3(nblk), dim3(256), 0, s1, recs, n, chunks, g, tab, segs,
+                       partial);
+    if (conc) {
+        (void)hipEventRecord(rs->join[0], rs->s[0]);
+        (void)hipEventRecord(rs->join[1], rs->s[1]);
+        (void)hipStreamWaitEvent(s, rs->join[0], 0);
+        (void)hipStreamWaitEvent(s, rs->join[1], 0);
+    }
+}
+
 hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                           int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl,
                           double* grad, hipEvent_t before_epilogue, hipStream_t s) {
@@ -672,9 +726,7 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
     if (grad) {
         {
             ProfRange pr(PD_K_LOGLIKE_GRAD, s);
-            hipLaunchKernelGGL((k_loglike_moments<1, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
-            hipLaunchKernelGGL((k_loglike_moments<1, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
-            hipLaunchKernelGGL((k_loglike_moments<1, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
+            launch_region_moments<1>(nblk, recs, n, chunks, g, tab, segs, partial, s);
         }
         if (before_epilogue) {
             const hipError_t e = hipStreamWaitEvent(s, before_epilogue, 0);
@@ -685,9 +737,7 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
     } else {
         {
             ProfRange pr(PD_K_LOGLIKE, s);
-            hipLaunchKernelGGL((k_loglike_moments<0, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
-            hipLaunchKernelGGL((k_loglike_moments<0, 2>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
-            hipLaunchKernelGGL((k_loglike_moments<0, 1>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs, partial);
+            launch_region_moments<0>(nblk, recs, n, chunks, g, tab, segs, partial, s);
         }
         hipLaunchKernelGGL(k_loglike_value_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks,
                            partial, lnl);
