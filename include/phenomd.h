@@ -17,11 +17,11 @@
  *   - The library allocates no device memory.  Calls that need scratch take a
  *     caller-owned `workspace` of at least the size the matching *_workspace_bytes()
  *     query returns; two calls that run concurrently must not share a workspace.
- *   - pd_loglike_and_grad runs the record tangents (with a gradient) and two of the three
- *     phase-region launches of its moment pass on side streams (default priority) created
- *     once per host thread and device, forked from and joined back to `stream` with events
- *     inside the call; the call stays asynchronous and its results are ordered on `stream`
- *     as for any other call.
+ *   - pd_loglike_and_grad and pd_mismatch_grad run two of the three phase-region
+ *     launches of their per-bin pass, and pd_loglike_and_grad with a gradient also the record
+ *     tangents, on side streams (default priority) created once per host thread and device,
+ *     forked from and joined back to `stream` with events inside the call; the calls stay
+ *     asynchronous and their results are ordered on `stream` as for any other call.
  *   - A negative return value is a batch-level error (bad pointer, size, grid or
  *     enum); nothing is launched and pd_last_error() describes it.  Nothing throws.
  *   - Per-point physical-domain errors (non-finite input, masses <= 0, eta outside

@@ -665,17 +665,8 @@ hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, con
     return hipGetLastError();
 }
 
-// Two side streams (default priority) per host thread and device on which the intermediate and
-// inspiral launches of a moment pass run concurrently with the merger-ringdown launch, so that
-// the short launches fill the long one's tail instead of each draining the GPU in turn.
-struct RegionStreams {
-    int dev = -1;
-    hipStream_t s[2] = {nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
-    bool ok = false;
-};
-
-static RegionStreams* region_streams() {
+// Two side streams (default priority) per host thread and device for the region launches.
+RegionStreams* region_streams() {
     thread_local std::vector<RegionStreams> pool;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
@@ -693,28 +684,20 @@ static RegionStreams* region_streams() {
     return pool.back().ok ? &pool.back() : nullptr;
 }
 
-// The three phase-region launches of one moment pass: merger-ringdown on s, intermediate and
-// inspiral on the side streams, joined back into s (sequential on s if the streams are missing).
 template <int MODE>
 static void launch_region_moments(unsigned nblk, const double* recs, int64_t n, int chunks, const GridArgs& g,
                                   const double* tab, const int* segs, double* partial, hipStream_t s) {
-    RegionStreams* rs = region_streams();
-    const bool conc = rs && hipEventRecord(rs->fork, s) == hipSuccess &&
-                      hipStreamWaitEvent(rs->s[0], rs->fork, 0) == hipSuccess &&
-                      hipStreamWaitEvent(rs->s[1], rs->fork, 0) == hipSuccess;
-    const hipStream_t s2 = conc ? rs->s[0] : s, s1 = conc ? rs->s[1] : s;
-    hipLaunchKernelGGL((k_loglike_moments<MODE, 3>), dim3(nblk), dim3(256), 0, s, recs, n, chunks, g, tab, segs,
-                       partial);
-    hipLaunchKernelGGL((k_loglike_moments<MODE, 2>), dim3(nblk), dim3(256), 0, s2, recs, n, chunks, g, tab, segs,
-                       partial);
-    hipLaunchKernelGGL((k_loglike_moments<MODE, 1>), dim3(nblk), dim3(256), 0, s1, recs, n, chunks, g, tab, segs,
-                       partial);
-    if (conc) {
-        (void)hipEventRecord(rs->join[0], rs->s[0]);
-        (void)hipEventRecord(rs->join[1], rs->s[1]);
-        (void)hipStreamWaitEvent(s, rs->join[0], 0);
-        (void)hipStreamWaitEvent(s, rs->join[1], 0);
-    }
+    launch_regions(s, [&](int region, hipStream_t rs) {
+        if (region == 3)
+            hipLaunchKernelGGL((k_loglike_moments<MODE, 3>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
+                               segs, partial);
+        else if (region == 2)
+            hipLaunchKernelGGL((k_loglike_moments<MODE, 2>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
+                               segs, partial);
+        else
+            hipLaunchKernelGGL((k_loglike_moments<MODE, 1>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
+                               segs, partial);
+    });
 }
 
 hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
@@ -751,13 +734,13 @@ hipError_t launch_fisher(const double* theta, int param, const double* recs, con
     const int64_t waves = n * chunks;
     hipLaunchKernelGGL(k_segments, dim3(blocks_for(3 * waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs);
     {
+        // sequential: run concurrently, the three launches (three waves per SIMD each, LDS-resident
+        // tangents) measured 1.7x slower
         ProfRange pr(PD_K_FISHER, s);
-        hipLaunchKernelGGL(k_fisher_partial<3>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
-                           g, tab, segs, partial);
-        hipLaunchKernelGGL(k_fisher_partial<2>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
-                           g, tab, segs, partial);
-        hipLaunchKernelGGL(k_fisher_partial<1>, dim3(blocks_for(waves, 4)), dim3(256), 0, s, recs, tans, n, chunks,
-                           g, tab, segs, partial);
+        const dim3 grid(blocks_for(waves, 4));
+        hipLaunchKernelGGL(k_fisher_partial<3>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, partial);
+        hipLaunchKernelGGL(k_fisher_partial<2>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, partial);
+        hipLaunchKernelGGL(k_fisher_partial<1>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, partial);
     }
     hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, param, recs, n, chunks,
                        partial, F);

@@ -13,6 +13,36 @@ constexpr int kNSlot = 2 + REC_N;   // (d|h), (h|h), then one moment per record 
 constexpr int kFisherSlots = 25;    // per-chunk Fisher sums (4 intrinsic directions + moments)
 
 // Bin-chunking policy: enough wavefronts to fill the chip even for small batches.
+// Side streams (default priority, one pair per host thread and device) on which the intermediate
+// and inspiral launches of a three-region pass run concurrently with the merger-ringdown launch,
+// so that the short launches fill the long one's tail instead of each draining the GPU in turn.
+struct RegionStreams {
+    int dev = -1;
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    bool ok = false;
+};
+RegionStreams* region_streams();
+
+// launch(r, stream) for the phase regions r = 3, 2, 1: region 3 on s, regions 2 and 1 on the side
+// streams, forked from and joined back into s by events (all on s if the side streams are missing).
+template <class F>
+inline void launch_regions(hipStream_t s, F&& launch) {
+    RegionStreams* rs = region_streams();
+    const bool conc = rs && hipEventRecord(rs->fork, s) == hipSuccess &&
+                      hipStreamWaitEvent(rs->s[0], rs->fork, 0) == hipSuccess &&
+                      hipStreamWaitEvent(rs->s[1], rs->fork, 0) == hipSuccess;
+    launch(3, s);
+    launch(2, conc ? rs->s[0] : s);
+    launch(1, conc ? rs->s[1] : s);
+    if (conc) {
+        (void)hipEventRecord(rs->join[0], rs->s[0]);
+        (void)hipEventRecord(rs->join[1], rs->s[1]);
+        (void)hipStreamWaitEvent(s, rs->join[0], 0);
+        (void)hipStreamWaitEvent(s, rs->join[1], 0);
+    }
+}
+
 inline int chunks_for(int64_t n, int64_t n_bins) {
     const int64_t want = (16384 + n - 1) / n;
     int64_t cap = n_bins / 512;

@@ -509,12 +509,17 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
         {
             ProfRange pr(PD_K_MISMATCH_ADJ, s);
             const dim3 grid(static_cast<unsigned>((waves + 3) / 4));
-            hipLaunchKernelGGL(k_mm_adjoint<3>, grid, dim3(256), 0, s, recs, nt, m.chunks, g, tab, targets, inv_psd,
-                               m.scal, m.mom);
-            hipLaunchKernelGGL(k_mm_adjoint<2>, grid, dim3(256), 0, s, recs, nt, m.chunks, g, tab, targets, inv_psd,
-                               m.scal, m.mom);
-            hipLaunchKernelGGL(k_mm_adjoint<1>, grid, dim3(256), 0, s, recs, nt, m.chunks, g, tab, targets, inv_psd,
-                               m.scal, m.mom);
+            launch_regions(s, [&](int region, hipStream_t rs) {
+                if (region == 3)
+                    hipLaunchKernelGGL(k_mm_adjoint<3>, grid, dim3(256), 0, rs, recs, nt, m.chunks, g, tab, targets,
+                                       inv_psd, m.scal, m.mom);
+                else if (region == 2)
+                    hipLaunchKernelGGL(k_mm_adjoint<2>, grid, dim3(256), 0, rs, recs, nt, m.chunks, g, tab, targets,
+                                       inv_psd, m.scal, m.mom);
+                else
+                    hipLaunchKernelGGL(k_mm_adjoint<1>, grid, dim3(256), 0, rs, recs, nt, m.chunks, g, tab, targets,
+                                       inv_psd, m.scal, m.mom);
+            });
         }
         hipLaunchKernelGGL(k_mm_reduce, dim3(static_cast<unsigned>(nt)), dim3(64), 0, s, recs, nt, m.chunks, m.mom,
                            m.mred);
