@@ -293,6 +293,26 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     log("[bench] C5 flow-MH vs HMC")
     for key, mode in (("C5_flow_mh_vs_hmc", "bf16"), ("C5_flow_mh_vs_hmc_fp32_flow", "fp32")):
         extra[key] = c5_summary(LP.compare(lam, n_chains=4096, log=log, flow_mode=mode))
+
+    # random-walk baseline, C5: HMC 300 steps against 2250 random-walk steps from the same states
+    from paper_2302_05329_amd import rwmh_baseline as RB
+    log("[bench] C5 HMC vs random-walk MH")
+    r = RB.compare(lam, n_chains=4096, log=log)
+    nm = r["names"]
+    extra["C5_hmc_vs_rwmh"] = {
+        "ess_ratio_at_paper_steps": dict(zip(nm, np.round(r["ess_ratio_paper_steps"], 3).tolist())),
+        "ess_ratio_equal_time": dict(zip(nm, np.round(r["ess_ratio_equal_time"], 3).tolist())),
+        "tau_steps_hmc": dict(zip(nm, np.round(r["hmc"]["tau_steps"], 1).tolist())),
+        "tau_steps_rwmh": dict(zip(nm, np.round(r["rwmh"]["tau_steps"], 1).tolist())),
+        "min_ess_per_s_hmc": min(r["hmc"]["ess_per_s"]), "min_ess_per_s_rwmh": min(r["rwmh"]["ess_per_s"]),
+        "ms_per_step_hmc": 1e3 * r["hmc"]["s_per_step"], "ms_per_step_rwmh": 1e3 * r["rwmh"]["s_per_step"],
+        "steps_hmc": r["hmc"]["steps"], "steps_rwmh": r["rwmh"]["steps"], "n_leapfrog": r["n_leapfrog"],
+        "acceptance_hmc": r["hmc"]["acceptance"], "acceptance_rwmh": r["rwmh"]["acceptance"],
+        "step_factor_rwmh": r["rwmh"]["step_factor"], "lags": r["lags"],
+        "autocorr_hmc_max_over_params": np.round(np.max(r["hmc"]["autocorr"], axis=1), 4).tolist(),
+        "autocorr_rwmh_max_over_params": np.round(np.max(r["rwmh"]["autocorr"], axis=1), 4).tolist(),
+        "chains": r["n_chains"], "chains_in_diagnostics": r["chains_in_diagnostics"],
+        "note": "tau ~ lag / (1 - rho(lag)) at lag 100 (diffusive regime); ESS per second = chains / tau / time per step"}
     return extra
 
 

@@ -213,6 +213,22 @@ int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, do
                 const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted,
                 double* dh, void* workspace, size_t workspace_bytes, void* stream);
 
+size_t pd_rwmh_workspace_bytes(const pd_posterior* post, int64_t n);
+
+/* One random-walk Metropolis-Hastings transition for n independent chains: the baseline
+ * sampler that Sec. 3.3 compares HMC with (Metropolis et al. 1953, Gaussian steps):
+ *   x' = x + scale * xi (per coordinate);  accept if log u < log pi(x') - log pi(x).
+ * A non-finite log pi(x') rejects; a chain whose log pi is not finite takes any finite x'.
+ * x [n][7], logp [n]   in/out: the chains' state and its cached log pi (from
+ *                      pd_posterior_logp or a previous step)
+ * xi [n][7]      standard-normal step draws;  u [n] uniform(0,1) draws
+ * scale [7]      HOST array, step standard deviation per coordinate (finite, >= 0)
+ * accepted [n]   out (or NULL): 1 accepted, 0 rejected
+ * Uses log pi only (value-only likelihood); a cached gradient of the chains is not updated.
+ */
+int pd_rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
+                 const double* scale, int32_t* accepted, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Independence Metropolis-Hastings accept (the learned proposal of the sampler): for each
  * chain, accept x' (drawn from q) with probability min(1, pi(x') q(x) / (pi(x) q(x'))).
  * x [n][7], logp [n], logq [n]   in/out current state, log pi and log q at it

@@ -11,10 +11,13 @@ Sec. 3.3 of the paper samples the 7-parameter posterior with Hamiltonian Monte C
   * HMC (Neal 2011): p = sqrt(m) xi, H = -log pi(x) + p^2/(2m) summed, leapfrog with a half
     kick at each end, accept if log u < -(H_end - H_start); non-finite or |dH| > 1000 is
     rejected as divergent;
+  * random-walk Metropolis-Hastings, the baseline Sec. 3.3 compares HMC with (Metropolis et al.
+    1953): a Gaussian step x' = x + s xi, accepted with probability min(1, pi(x') / pi(x));
   * independence Metropolis-Hastings with a proposal density q:
     accept x' with probability min(1, pi(x') q(x) / (pi(x) q(x'))).
 Pinned by tests/test_sampler_oracle.py (reversibility, O(eps^2) energy error, the log-Jacobian
-against finite differences, recovery of a Gaussian target's moments).
+against finite differences, recovery of a Gaussian target's moments, the closed-form stationary
+acceptance rate of the random walk on a normal target).
 """
 import math
 
@@ -86,6 +89,17 @@ def hmc_step(logp_fn, x, lp, grad, xi, u, n_steps, eps, mass):
     if math.log(u) < -dh:
         return x1, lp1, g1, 1, dh
     return x, lp, grad, 0, dh
+
+
+def rwmh_step(logp_fn, x, lp, xi, u, scale):
+    """One random-walk MH transition with step x' = x + scale * xi; returns (x, logp, accepted).
+    logp_fn returns log pi at a point (a non-finite value rejects the proposal; a current
+    state with non-finite log pi takes any finite proposal)."""
+    xp = np.asarray(x, dtype=np.float64) + np.asarray(scale, dtype=np.float64) * np.asarray(xi, dtype=np.float64)
+    lpp = logp_fn(xp)
+    if np.isfinite(lpp) and (math.log(u) < lpp - lp or not np.isfinite(lp)):
+        return xp, lpp, 1
+    return np.array(x, dtype=np.float64), lp, 0
 
 
 def independence_mh(x, lp, lq, xp, lpp, lqp, u):

@@ -424,6 +424,25 @@ int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, do
     return PD_OK;
 }
 
+size_t pd_rwmh_workspace_bytes(const pd_posterior* post, int64_t n) {
+    if (pd::posterior_check(post) != PD_OK || n <= 0) return 0;
+    return pd::rwmh_workspace_bytes(post, n);
+}
+
+int pd_rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
+                 const double* scale, int32_t* accepted, void* workspace, size_t workspace_bytes, void* stream) {
+    if (pd::posterior_check(post) != PD_OK) return fail(PD_EINVAL, "invalid posterior description");
+    if (!x || !logp || !xi || !u || !scale) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    for (int j = 0; j < 7; ++j)
+        if (!(scale[j] >= 0.0) || !std::isfinite(scale[j])) return fail(PD_EINVAL, "scale must be finite and >= 0");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    if (workspace_bytes < pd::rwmh_workspace_bytes(post, n)) return fail(PD_ENOMEM, "workspace too small");
+    const int rc = pd::rwmh_step(post, n, x, logp, xi, u, scale, accepted, workspace, static_cast<hipStream_t>(stream));
+    if (rc != PD_OK) return fail(rc, "random-walk step failed");
+    return PD_OK;
+}
+
 int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, double* grad, const double* xp,
                        const double* logp_p, const double* logq_p, const double* grad_p, const double* u,
                        int32_t* accepted, void* stream) {

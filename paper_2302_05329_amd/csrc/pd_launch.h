@@ -74,6 +74,9 @@ hipError_t launch_fisher(const double* theta, int param, const double* recs, con
 int posterior_check(const pd_posterior* post);
 size_t posterior_ws_bytes(const pd_posterior* post, int64_t n);
 size_t hmc_workspace_bytes(const pd_posterior* post, int64_t n);
+size_t rwmh_workspace_bytes(const pd_posterior* post, int64_t n);
+int rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
+              const double* scale, int32_t* accepted, void* ws, hipStream_t s);
 int loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
                      const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
                      int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s, bool tables_ready);

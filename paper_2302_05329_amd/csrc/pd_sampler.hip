@@ -1,5 +1,6 @@
 // Samplers on the GPU (paper Sec. 3.3): posterior log-density and gradient in
-// unconstrained coordinates, Hamiltonian Monte Carlo with a diagonal mass matrix, and
+// unconstrained coordinates, Hamiltonian Monte Carlo with a diagonal mass matrix, the
+// random-walk Metropolis-Hastings baseline the paper compares it with (Gaussian steps), and
 // the Metropolis-Hastings accept step of an independence proposal (the learned flow).
 //
 // Coordinates.  The sampler moves x in R^7.  For the gravitational-wave target the
@@ -169,6 +170,35 @@ __global__ void k_imh(int64_t n, double* __restrict__ x, double* __restrict__ lo
     if (accepted) accepted[i] = acc ? 1 : 0;
 }
 
+struct RwArgs {
+    double scale[7];
+};
+
+// Gaussian random-walk proposal: x' = x + scale * xi, per coordinate.
+__global__ void k_rw_propose(int64_t n, RwArgs a, const double* __restrict__ x, const double* __restrict__ xi,
+                             double* __restrict__ xp) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * 7) return;
+    const int j = static_cast<int>(t % 7);
+    xp[t] = fma(a.scale[j], xi[t], x[t]);
+}
+
+// Metropolis accept for a symmetric proposal: accept x' with probability min(1, pi(x') / pi(x)).
+// A non-finite log pi(x') rejects; a chain whose current log pi is not finite takes any finite proposal.
+__global__ void k_rw_accept(int64_t n, const double* __restrict__ xp, const double* __restrict__ logp_p,
+                            const double* __restrict__ u, double* __restrict__ x, double* __restrict__ logp,
+                            int32_t* __restrict__ accepted) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double lpp = logp_p[i];
+    const bool acc = isfinite(lpp) && (log(u[i]) < lpp - logp[i] || !isfinite(logp[i]));
+    if (acc) {
+        for (int j = 0; j < 7; ++j) x[i * 7 + j] = xp[i * 7 + j];
+        logp[i] = lpp;
+    }
+    if (accepted) accepted[i] = acc ? 1 : 0;
+}
+
 inline unsigned nblk(int64_t threads, int per) { return static_cast<unsigned>((threads + per - 1) / per); }
 
 constexpr size_t kAl = 256;
@@ -250,6 +280,12 @@ HmcWs hmc_ws(int64_t n, void* base) {
     off = al(off + N * 7 * 8);
     w.post = p + off;
     return w;
+}
+
+// random-walk workspace: xp [n][7]; logp_p [n]; then the posterior workspace
+size_t rw_ws_bytes(const pd_posterior* post, int64_t n) {
+    const size_t N = static_cast<size_t>(n);
+    return al(N * 7 * 8) + al(N * 8) + post_ws_bytes(post, n);
 }
 
 }  // namespace
@@ -338,6 +374,26 @@ int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, doubl
     }
     hipLaunchKernelGGL(k_hmc_accept, dim3(b1), dim3(128), 0, s, n, a, u, w.h0, w.x1, w.p, w.logp1, w.grad1, x, logp,
                        grad, accepted, dh);
+    return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
+}
+
+size_t rwmh_workspace_bytes(const pd_posterior* post, int64_t n) { return rw_ws_bytes(post, n); }
+
+int rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
+              const double* scale, int32_t* accepted, void* ws, hipStream_t s) {
+    const size_t N = static_cast<size_t>(n);
+    char* base = static_cast<char*>(ws);
+    double* xp = reinterpret_cast<double*>(base);
+    double* lpp = reinterpret_cast<double*>(base + al(N * 7 * 8));
+    void* pws = base + al(N * 7 * 8) + al(N * 8);
+    RwArgs a;
+    for (int j = 0; j < 7; ++j) a.scale[j] = scale[j];
+    hipLaunchKernelGGL(k_rw_propose, dim3(nblk(n * 7, 256)), dim3(256), 0, s, n, a, x, xi, xp);
+    if (hipGetLastError() != hipSuccess) return PD_EHIP;
+    // value only: the random walk uses no gradient
+    const int rc = posterior_logp(post, xp, n, lpp, nullptr, pws, s);
+    if (rc != PD_OK) return rc;
+    hipLaunchKernelGGL(k_rw_accept, dim3(nblk(n, 128)), dim3(128), 0, s, n, xp, lpp, u, x, logp, accepted);
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
 }
 

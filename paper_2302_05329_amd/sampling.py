@@ -1,5 +1,6 @@
-"""Samplers of Sec. 3.3 on the GPU: posterior log-density, HMC transitions, independence
-Metropolis-Hastings.  Marshalling only; the transitions run in the HIP library.
+"""Samplers of Sec. 3.3 on the GPU: posterior log-density, HMC transitions, the random-walk
+Metropolis-Hastings baseline, independence Metropolis-Hastings.  Marshalling only; the
+transitions run in the HIP library.
 """
 import ctypes
 
@@ -97,6 +98,32 @@ class HMC:
         L.check(L.lib().pd_hmc_step(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(self.grad),
                                     _ptr(xi), _ptr(u), self.L, self.eps, self.mass, _ptr(self.accepted),
                                     _ptr(self.dh), wp, wb, _stream()))
+        return self.accepted
+
+
+class RWMH:
+    """n parallel random-walk Metropolis-Hastings chains (Gaussian steps of standard deviation
+    `scale` per coordinate) with cached log-density (all tensors on the GPU)."""
+
+    def __init__(self, post, x0, scale):
+        self.post = post
+        self.x = torch.as_tensor(x0, dtype=torch.float64, device="cuda").clone().contiguous()
+        if self.x.dim() != 2 or self.x.shape[1] != 7:
+            raise ValueError("x0 must be [n, 7]")
+        self.n = self.x.shape[0]
+        self.scale = (ctypes.c_double * 7)(*[float(s) for s in scale])
+        self.ws = Workspace()
+        self.logp, _ = logp(post, self.x, want_grad=False, ws=self.ws)
+        self.accepted = torch.empty(self.n, dtype=torch.int32, device="cuda")
+
+    def step(self, xi, u):
+        """One transition; xi [n, 7] standard normals, u [n] uniforms (FP64 device tensors)."""
+        for t, shape in ((xi, (self.n, 7)), (u, (self.n,))):
+            if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("random draws have the wrong shape or type")
+        wp, wb = self.ws.get(L.lib().pd_rwmh_workspace_bytes(self.post.ref(), self.n))
+        L.check(L.lib().pd_rwmh_step(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(xi), _ptr(u),
+                                     self.scale, _ptr(self.accepted), wp, wb, _stream()))
         return self.accepted
 
 

@@ -78,3 +78,30 @@ def test_mismatch_requires_fft_length(lib):
     rc = lib.pd_mismatch_grad(vp(256), 1, 3, ctypes.byref(g), vp(512), vp(768), vp(1024), vp(1280), None, None,
                               vp(2048), 1 << 40, None)
     assert rc == L.PD_EUNSUPPORTED
+
+
+def _gauss_post():
+    st = L.PdPosterior()
+    st.kind = L.PD_TARGET_GAUSS
+    for j in range(7):
+        st.mu[j], st.isig2[j] = 0.0, 1.0
+    return st
+
+
+@pytest.mark.parametrize("bad", ["scale_neg", "scale_nan", "xi", "n", "ws", "wsb"])
+def test_rwmh_rejects_bad_arguments(lib, bad):
+    st = _gauss_post()
+    vp = ctypes.c_void_p
+    n = 0 if bad == "n" else 16
+    need = lib.pd_rwmh_workspace_bytes(ctypes.byref(st), 16)
+    assert need > 0 and need % 256 == 0
+    sc = [0.1] * 7
+    if bad == "scale_neg":
+        sc[3] = -0.1
+    if bad == "scale_nan":
+        sc[6] = float("nan")
+    scale = (ctypes.c_double * 7)(*sc)
+    rc = lib.pd_rwmh_step(ctypes.byref(st), n, vp(256), vp(512), None if bad == "xi" else vp(768), vp(1024), scale,
+                          None, None if bad == "ws" else vp(2048), 16 if bad == "wsb" else need, None)
+    assert rc == (L.PD_ENOMEM if bad == "wsb" else L.PD_EINVAL)
+    assert len(lib.pd_last_error()) > 0

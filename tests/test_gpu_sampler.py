@@ -137,6 +137,100 @@ def test_posterior_and_hmc_full_c5_sampled(gpu, lam0):
             assert np.max(np.abs(xg[i] - xr)) <= 1e-9 * (1 + np.max(np.abs(xr)))
 
 
+def _rwmh_parity(pb, lam0, n, rows, seed):
+    import torch
+    from paper_2302_05329_amd import sampling
+    post = sampling.Posterior(0, grid=pb["grid"], lam=lam0, data=pb["data"], inv_psd=pb["inv_psd"], lo=pb["lo"],
+                              hi=pb["hi"])
+    rng = np.random.default_rng(seed)
+    x0 = post.to_x(pb["theta_inj"]) + 0.02 * rng.standard_normal((n, 7))
+    scale = np.array([0.02, 0.05, 0.1, 0.1, 0.05, 0.01, 0.2])
+    xi = rng.standard_normal((n, 7))
+    u = rng.uniform(size=n)
+    _say(f"random-walk MH step GW n={n} nb={pb['grid'].n_bins}")
+    rw = sampling.RWMH(post, x0, scale)
+    lp0 = rw.logp.cpu().numpy()
+    acc = rw.step(torch.as_tensor(xi, device="cuda"), torch.as_tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    xg, lpg, accg = rw.x.cpu().numpy(), rw.logp.cpu().numpy(), acc.cpu().numpy()
+    gr = pb["grid"].as_tuple()
+
+    def lpf(x):
+        return S.logp_gw(x, lam0, gr, pb["data"], pb["inv_psd"], pb["lo"], pb["hi"], want_grad=False)[0]
+
+    checked = 0
+    for i in rows:
+        ref0 = lpf(x0[i])
+        assert abs(lp0[i] - ref0) <= 1e-10 * max(1.0, abs(ref0) / 1e3), (i, lp0[i], ref0)
+        xr, lpr, ar = S.rwmh_step(lpf, x0[i], ref0, xi[i], u[i], scale)
+        lpp = lpf(x0[i] + scale * xi[i])
+        if abs(lpp - ref0 - math.log(u[i])) > 1e-6:
+            assert accg[i] == ar, (i, accg[i], ar)
+            assert np.max(np.abs(xg[i] - xr)) <= 1e-14 * (1 + np.max(np.abs(xr))), (i, xg[i], xr)
+            assert abs(lpg[i] - lpr) <= 1e-10 * max(1.0, abs(lpr) / 1e3), (i, lpg[i], lpr)
+            checked += 1
+    assert checked >= len(rows) - 1
+    return accg
+
+
+def test_rwmh_step_parity_gw(gpu, lam0):
+    pb = _c5_problem(lam0, n_bins=4001)
+    acc = _rwmh_parity(pb, lam0, 24, range(24), 15)
+    assert 0 < acc.sum() < 24
+
+
+def test_rwmh_full_c5_sampled(gpu, lam0):
+    """One random-walk transition of the learned-proposal workload at its full size (4096 chains x
+    8033 bins) against the oracle on sampled chains."""
+    pb = _c5_problem(lam0)
+    rng = np.random.default_rng(16)
+    rows = sorted({0, 4095} | set(int(i) for i in rng.choice(4096, 3, replace=False)))
+    _rwmh_parity(pb, lam0, 4096, rows, 16)
+
+
+def test_rwmh_on_gaussian_target_gpu(gpu):
+    """Closed-form stationary acceptance (2/pi) arctan(2/s) of a one-coordinate walk, the target's
+    moments kept over 30 steps, and a zero step accepting every chain."""
+    import torch
+    from paper_2302_05329_amd import sampling
+    mu = np.array([0.3, -1.0, 2.0, 0.0, 0.5, -0.2, 1.1])
+    sig = np.array([0.5, 1.0, 2.0, 0.1, 1.5, 0.7, 0.3])
+    post = sampling.Posterior(1, mu=mu, isig2=1 / sig**2)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(17)
+    mu_t = torch.as_tensor(mu, device="cuda")
+    sig_t = torch.as_tensor(sig, device="cuda")
+    n = 1 << 18
+    _say(f"random-walk MH gaussian n={n}")
+    for s in (1.0, 2.4):
+        x0 = mu_t + sig_t * torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen)
+        scale = np.zeros(7)
+        scale[0] = s * sig[0]
+        rw = sampling.RWMH(post, x0, scale)
+        xi = torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen)
+        u = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+        rate = float((rw.step(xi, u) == 1).double().mean())
+        expect = 2.0 / math.pi * math.atan(2.0 / s)
+        assert abs(rate - expect) < 0.005, (s, rate, expect)
+        assert torch.equal(rw.x[:, 1:], x0[:, 1:])
+    n = 8192
+    x0 = mu_t + sig_t * torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen)
+    rw = sampling.RWMH(post, x0, 0.8 * sig)
+    for _ in range(30):
+        rw.step(torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen),
+                torch.rand(n, dtype=torch.float64, device="cuda", generator=gen))
+    x = rw.x.cpu().numpy()
+    assert np.all(np.abs(x.mean(axis=0) - mu) < 5 * sig / math.sqrt(n))
+    assert np.all(np.abs(x.std(axis=0) / sig - 1) < 0.05)
+    u = torch.full((n,), 0.999, dtype=torch.float64, device="cuda")
+    a = rw.step(torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen), u)
+    assert int((a == 1).sum()) < n  # a non-zero step rejects some chains at u = 0.999
+    rw.scale = type(rw.scale)(*([0.0] * 7))
+    x1 = rw.x.clone()
+    a = rw.step(torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen), u)
+    assert int((a == 1).sum()) == n and torch.equal(rw.x, x1)
+
+
 def test_hmc_recovers_gaussian_target_on_gpu(gpu):
     import torch
     from paper_2302_05329_amd import sampling

@@ -109,6 +109,73 @@ def test_independence_mh_exactness_on_gaussian():
     assert out[3] == 1
 
 
+def test_rwmh_stationary_acceptance_matches_closed_form():
+    """Random walk on a normal target N(mu, sig^2) with steps N(0, (s sig)^2), started in
+    stationarity: the expected acceptance rate is (2/pi) arctan(2/s) (the one-dimensional
+    result of Gelman, Roberts and Gilks 1996).  Only coordinate 0 moves (zero step elsewhere)."""
+    rng = np.random.default_rng(8)
+    mu = np.array([0.7, -0.3, 0.0, 1.0, 2.0, -1.0, 0.5])
+    sig = np.array([1.3, 1.0, 0.5, 2.0, 1.0, 0.7, 1.0])
+    isig2 = 1.0 / sig**2
+
+    def lpf(x):
+        return S.logp_gauss(x, mu, isig2)[0]
+
+    n = 60000
+    for s in (1.0, 2.4):
+        scale = np.zeros(7)
+        scale[0] = s * sig[0]
+        x = mu + sig * rng.standard_normal((n, 7))
+        xi = rng.standard_normal((n, 7))
+        u = rng.uniform(size=n)
+        acc = 0
+        for i in range(n):
+            xn, _, a = S.rwmh_step(lpf, x[i], lpf(x[i]), xi[i], u[i], scale)
+            acc += a
+            assert np.array_equal(xn[1:], x[i][1:])
+        expect = 2.0 / math.pi * math.atan(2.0 / s)
+        assert abs(acc / n - expect) < 0.01, (s, acc / n, expect)
+
+
+def test_rwmh_keeps_gaussian_target():
+    """From stationarity, 30 random-walk steps keep a 7-D normal target's mean and spread."""
+    rng = np.random.default_rng(9)
+    mu = np.array([0.3, -1.0, 2.0, 0.0, 0.5, -0.2, 1.1])
+    sig = np.array([0.5, 1.0, 2.0, 0.1, 1.5, 0.7, 0.3])
+    isig2 = 1.0 / sig**2
+
+    def lpf(x):
+        return S.logp_gauss(x, mu, isig2)[0]
+
+    n = 2000
+    x = mu + sig * rng.standard_normal((n, 7))
+    lp = np.array([lpf(r) for r in x])
+    for _ in range(30):
+        xi = rng.standard_normal((n, 7))
+        u = rng.uniform(size=n)
+        for i in range(n):
+            x[i], lp[i], _ = S.rwmh_step(lpf, x[i], lp[i], xi[i], u[i], 0.8 * sig)
+    se = sig / math.sqrt(n)
+    assert np.all(np.abs(x.mean(axis=0) - mu) < 5 * se)
+    assert np.all(np.abs(x.std(axis=0) / sig - 1) < 0.08)
+
+
+def test_rwmh_special_cases():
+    def lpf(x):
+        return S.logp_gauss(x, np.zeros(7), np.ones(7))[0]
+
+    x = np.linspace(-1, 1, 7)
+    # a zero step proposes the current point: log pi(x') - log pi(x) = 0 > log u always
+    xn, lpn, a = S.rwmh_step(lpf, x, lpf(x), np.ones(7), 0.999, np.zeros(7))
+    assert a == 1 and np.array_equal(xn, x) and lpn == lpf(x)
+    # a proposal outside the support (log pi = -inf) is rejected, even for a tiny u
+    xn, lpn, a = S.rwmh_step(lambda y: -np.inf, x, -1.0, np.ones(7), 1e-300, np.ones(7))
+    assert a == 0 and np.array_equal(xn, x) and lpn == -1.0
+    # a chain outside the support takes any finite proposal, even for u close to 1
+    xn, lpn, a = S.rwmh_step(lpf, x, -np.inf, np.ones(7), 1 - 1e-16, np.full(7, 50.0))
+    assert a == 1 and np.allclose(xn, x + 50.0)
+
+
 def test_ess_of_ar1_matches_closed_form():
     """AR(1) with coefficient rho: ESS = N (1 - rho) / (1 + rho)."""
     rng = np.random.default_rng(6)
@@ -129,3 +196,18 @@ def test_autocorr_of_white_noise():
     ac = D.autocorr(rng.standard_normal(100000))
     assert ac[0] == pytest.approx(1.0)
     assert np.max(np.abs(ac[1:50])) < 0.02
+
+
+def test_ensemble_autocorr_of_ar1():
+    """The lag autocorrelation reported for the HMC/random-walk comparison, on stationary AR(1)
+    chains: rho^lag."""
+    from paper_2302_05329_amd import rwmh_baseline as RB
+    rng = np.random.default_rng(10)
+    m, n, rho = 64, 4000, 0.9
+    x = np.zeros((m, n, 7))
+    x[:, 0] = rng.standard_normal((m, 7))
+    for t in range(1, n):
+        x[:, t] = rho * x[:, t - 1] + math.sqrt(1 - rho**2) * rng.standard_normal((m, 7))
+    ac = RB.mean_autocorr(x)
+    for k, lag in enumerate(RB.LAGS):
+        assert np.all(np.abs(ac[k] - rho**lag) < 0.02), (lag, ac[k])
