@@ -226,6 +226,22 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
                                     "paper_gpu_ms_per_waveform": 0.02, "paper_gpu": "NVIDIA Quadro 6000 (JAX)"}
     del th1
 
+    # the Fig. 1 precision-sweep workload: 10^4 sources (masses 1-100 Msun, spins -1..1) on
+    # 32-1024 Hz, df = 0.0125 Hz: 79361 bins, 12.7 GB of strain per call
+    fs = W.fig1_sweep()
+    thf = torch.as_tensor(fs["theta"], device=dev)
+    api.profile_read(L.PD_K_WAVEFORM)
+    t = timed_calls(lambda: api.waveform_eval(thf, P, fs["grid"], lam, ws=ws), 5, 1)
+    kms, _ = kernel_avg_ms(api, L.PD_K_WAVEFORM)
+    transf = api.transition_frequencies(thf, P, fs["grid"], lam, ws=ws).cpu().numpy()
+    fl, _ = flops.batch_flops("waveform", transf, fs["grid"].as_tuple())
+    nbytes = thf.shape[0] * fs["grid"].n_bins * 16
+    extra["fig1_sweep_waveform"] = {"waveforms_per_s": thf.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
+                                    "n_bins": fs["grid"].n_bins, "hbm_write_GBs": nbytes / (kms * 1e-3) / 1e9,
+                                    "tflops_algorithmic": fl / (kms * 1e-3) / 1e12}
+    del thf
+    torch.cuda.empty_cache()
+
     # Fisher matrices, C3: 16384 x 16065 in (ln Mc, eta, chi1, chi2, ln D, tc, phic)
     c3 = W.config3()
     th3 = torch.as_tensor(W.to_param(c3["theta"], api.PARAM_LNMC_ETA_LND), device=dev)
