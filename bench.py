@@ -278,6 +278,27 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
                                  "input_hbm_GBs": 2 * series / (ks["input"] * 1e-3) / 1e9,
                                  "fft_hbm_GBs": 3 * series / (ks["fft"] * 1e-3) / 1e9,
                                  "adjoint_tflops_algorithmic": fl4 / (ks["adjoint"] * 1e-3) / 1e12}
+
+    # the coefficient fit of Sec. 3.1 on the same targets: gradient descent, one library call per
+    # step (mismatch, gradient, update).  With the paper's learning rate alpha = 1e-6 and with a
+    # step scaled to lower the mean mismatch by 1% to first order (alpha = 0.01 L / |grad L|^2)
+    probe = api.LambdaFit(th4, P, c4["grid"], lam, targets, ip4, 0.0, ws=ws4)
+    probe.step()
+    loss0 = float(probe.mismatch.mean())
+    gnorm2 = float((probe.dsum / th4.shape[0]).square().sum())
+    runs = {}
+    n_gd = 300
+    for name, alpha in (("paper_alpha", 1e-6), ("scaled_alpha", 0.01 * loss0 / gnorm2)):
+        fit = api.LambdaFit(th4, P, c4["grid"], lam, targets, ip4, alpha, ws=ws4)
+        t = timed_calls(fit.step, n_gd, 0)
+        fit.step()
+        runs[name] = {"alpha": alpha, "mean_mismatch_after": float(fit.mismatch.mean()), "ms_per_step": 1e3 * t}
+    extra["C4_lambda_descent"] = {"steps_per_s": 1e3 / runs["paper_alpha"]["ms_per_step"],
+                                  "ms_per_step": runs["paper_alpha"]["ms_per_step"], "targets": int(th4.shape[0]),
+                                  "steps": n_gd, "mean_mismatch_start": loss0, "grad_norm": gnorm2 ** 0.5,
+                                  "runs": runs, "paper_steps": 30000,
+                                  "projected_s_for_paper_steps": 30.0 * runs["paper_alpha"]["ms_per_step"]}
+    del probe, fit
     api.profile_enable(False)
 
     # template-bank overlaps on the FP64 matrix cores: the C2 bank (ordered by total mass)

@@ -138,6 +138,21 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
                      double* mismatch, double* dsum_dlambda, int32_t* lag,
                      void* workspace, size_t workspace_bytes, void* stream);
 
+/* One gradient-descent step on the 209 fit coefficients (Sec. 3.1, Eq. 6 on the mean loss of
+ * Eq. 7):  L = (1/nt) sum_i M_i,  lambda <- lambda - alpha dL/dlambda.
+ * Arguments as for pd_mismatch_grad, except:
+ * lambda       [209] device, in/out: read by the mismatch pass, then updated in place
+ * alpha        learning rate (finite, >= 0)
+ * mismatch     [nt]  output: M_i at the coefficients on entry
+ * dsum_dlambda [209] output (required, must not alias lambda): sum over targets of dM/dlambda
+ *              at the coefficients on entry
+ * Workspace as for PD_OP_MISMATCH_GRAD.  Steps issued on one stream run in order, so a loop
+ * of calls is the descent of Sec. 3.1 with no host synchronisation.
+ */
+int pd_fit_lambda_step(const double* theta, int64_t nt, int param, const pd_grid* grid, double* lambda,
+                       const double* targets, const double* inv_psd, double alpha, double* mismatch,
+                       double* dsum_dlambda, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Per-point model quantities used to account the work of a batch (Sec. 2): for each row,
  * out[i] = {M T_sun [s], Mf of the phase join intermediate->merger-ringdown (f_RD / 2),
  *           Mf of the amplitude join intermediate->merger-ringdown (f_peak), valid (1/0)}.

@@ -19,6 +19,7 @@ print, so its structure is restated here from those model papers):
   * inner product     Eq. 1 as a Riemann sum on the grid; likelihood ln L = (d|h) - (h|h)/2
   * Fisher matrix     Eq. 8: F_ij = (d_i h | d_j h)
   * match / mismatch  max over lag (discrete FFT lag) and phase (modulus), Eqs. 2-4
+  * coefficient fit   one gradient-descent step on the mean mismatch over targets, Eqs. 6-7
   * derivatives       complex-step differentiation of the real amplitude and phase
                       (a technique unrelated to the GPU's hand-written tangents)
 
@@ -30,7 +31,8 @@ independently from PN energy and flux, the Newtonian amplitude limit, exact 1/D
 scaling, exact linear tc/phic terms, m1<->m2 swap symmetry, Fisher closed forms and
 positive definiteness, gradients against central differences, noise-free likelihood
 stationarity, FFT match against a brute-force DFT, lag invariance and total-mass
-invariance of the match on an Mf grid with a flat PSD.
+invariance of the match on an Mf grid with a flat PSD, the first-order decrease of the mean
+mismatch under a small descent step.
 Parity unpinned (model fidelity): the spin-dependent PN phase and amplitude terms, the
 PN amplitude coefficients beyond 1PN, the final-spin / radiated-energy / ring-down
 stand-ins and the placeholder coefficient table — nothing available here fixes their
@@ -640,3 +642,17 @@ def mismatch_grad_lambda(theta, param, lam, grid, target, w):
         mm_c = 1.0 - (zr * zr + zi * zi) ** 0.5 / (aa * b) ** 0.5
         grad[i] = np.imag(mm_c) / hstep
     return mm, j, gap, grad
+
+
+def fit_lambda_step(thetas, param, lam, grid, targets, w, alpha):
+    """One step of the coefficient fit of Sec. 3.1: the loss is the mean mismatch over the
+    targets (Eq. 7) and the step is lambda - alpha * dL/dlambda (Eq. 6).  Returns (the updated
+    coefficients, the mismatches [nt] and the summed gradient [209] at the coefficients given)."""
+    lam = np.asarray(lam, dtype=np.float64).reshape(-1)
+    mms = []
+    gsum = np.zeros(lam.size)
+    for th, tg in zip(thetas, targets):
+        mm, _, _, g = mismatch_grad_lambda(th, param, lam, grid, tg, w)
+        mms.append(mm)
+        gsum += g
+    return lam - alpha * (gsum / len(mms)), np.array(mms), gsum

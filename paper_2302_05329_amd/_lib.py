@@ -78,6 +78,7 @@ SIGNATURES = {
     "pd_loglike_and_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _INT, _P, _P, _P, _P, _SZ, _P]),
     "pd_fisher": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_mismatch_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pd_fit_lambda_step": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, ctypes.c_double, _P, _P, _P, _SZ, _P]),
     "pd_posterior_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
     "pd_posterior_logp": (_INT, [ctypes.c_void_p, _P, _I64, _P, _P, _P, _SZ, _P]),
     "pd_hmc_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),

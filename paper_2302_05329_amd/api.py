@@ -153,6 +153,34 @@ def mismatch_grad(theta, param, grid, lam, targets, inv_psd, want_grad=True, ws=
     return mm, dl, lag
 
 
+class LambdaFit:
+    """Gradient descent on the 209 fit coefficients against fixed targets (Sec. 3.1): each
+    `step` is one library call that evaluates the mismatches and their summed gradient at the
+    current coefficients and then updates them in place on the device."""
+
+    def __init__(self, theta, param, grid, lam0, targets, inv_psd, alpha, ws=None):
+        self.ws = ws or Workspace()
+        self.g = _grid(grid)
+        self.th = _dev(theta)
+        self.lam = _dev(lam0).clone().contiguous()
+        self.tg = _dev(targets)
+        self.ip = _dev(inv_psd)
+        _check_shapes(self.th, self.lam, self.g.n_bins, inv_psd=self.ip, targets=self.tg)
+        self.param = int(param)
+        self.alpha = float(alpha)
+        self.nt = self.th.shape[0]
+        self.mismatch = torch.empty(self.nt, dtype=torch.float64, device="cuda")
+        self.dsum = torch.empty(209, dtype=torch.float64, device="cuda")
+
+    def step(self):
+        """One descent step; afterwards `mismatch` and `dsum` hold the values at the coefficients
+        before the update and `lam` the updated coefficients."""
+        wp, wb = self.ws.get(workspace_bytes(L.PD_OP_MISMATCH_GRAD, self.nt, self.g.n_bins))
+        L.check(L.lib().pd_fit_lambda_step(_ptr(self.th), self.nt, self.param, ctypes.byref(self.g), _ptr(self.lam),
+                                           _ptr(self.tg), _ptr(self.ip), self.alpha, _ptr(self.mismatch),
+                                           _ptr(self.dsum), wp, wb, _stream()))
+
+
 def overlap(theta, param, grid, lam, streams, inv_psd, want_hh=True, ws=None):
     """Template-bank overlaps: O [nt, ns] complex128 with O[t, s] = sum_k w_k conj(h_t,k) d_s,k,
     (h_t|h_t) [nt] (or None) and status [nt].  streams: [ns, n_bins] complex, ns <= 64."""

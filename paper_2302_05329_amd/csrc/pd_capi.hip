@@ -384,6 +384,21 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
     return PD_OK;
 }
 
+int pd_fit_lambda_step(const double* theta, int64_t nt, int param, const pd_grid* grid, double* lambda,
+                       const double* targets, const double* inv_psd, double alpha, double* mismatch,
+                       double* dsum_dlambda, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!dsum_dlambda) return fail(PD_EINVAL, "dsum_dlambda is NULL");
+    if (dsum_dlambda == lambda) return fail(PD_EINVAL, "dsum_dlambda must not alias lambda");
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(PD_EINVAL, "alpha must be finite and >= 0");
+    const int rc = pd_mismatch_grad(theta, nt, param, grid, lambda, targets, inv_psd, mismatch, dsum_dlambda,
+                                    nullptr, workspace, workspace_bytes, stream);
+    if (rc != PD_OK) return rc;
+    const hipError_t e = pd::launch_lambda_update(lambda, dsum_dlambda, alpha / static_cast<double>(nt),
+                                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "coefficient update");
+    return PD_OK;
+}
+
 size_t pd_posterior_workspace_bytes(const pd_posterior* post, int64_t n) {
     if (pd::posterior_check(post) != PD_OK || n <= 0) return 0;
     return pd::posterior_ws_bytes(post, n);

@@ -291,7 +291,66 @@ def test_mismatch_full_c4(gpu, lam0):
     tg = targets.cpu().numpy()
     rng = np.random.default_rng(5)
     for i in sorted({0, len(th) - 1} | set(int(x) for x in rng.choice(len(th), 2, replace=False))):
-        m_ref, j_ref, gap = O.mismatch(th[i], P, lam0, g, tg[i], 4 * g[1] * w)
+        # the oracle works on its own target strain, which the library's matches to 1e-10
+        tg_ref = O.waveform(th[i], P, lam_star, g)
+        assert _strain_err(tg[i], tg_ref) <= 1e-10, i
+        m_ref, j_ref, gap = O.mismatch(th[i], P, lam0, g, tg_ref, 4 * g[1] * w)
         if gap > 1e-12:
             assert lag0[i] == j_ref
         assert abs(mm0[i] - m_ref) <= 1e-12, (i, mm0[i], m_ref)
+
+
+def test_fit_lambda_step_parity_config4_shape(gpu, lam0):
+    """One coefficient-descent step (Sec. 3.1, Eqs. 6-7) against the oracle: mismatches, summed
+    gradient and the updated coefficients; a zero step leaves the coefficients bit-identical."""
+    import torch
+    from paper_2302_05329_amd import api
+    cfg = W.config4(n=2)
+    g = cfg["grid"].as_tuple()
+    th, w = cfg["theta"], cfg["inv_psd"]
+    targets = np.stack([O.waveform(t, P, cfg["lam_star"], g) for t in th])
+    _say(f"fit_lambda_step C4-shape nt=2 nb={g[2]}")
+    fit0 = api.LambdaFit(th, P, cfg["grid"], lam0, targets, w, 0.0)
+    fit0.step()
+    alpha = 3e-3
+    fit = api.LambdaFit(th, P, cfg["grid"], lam0, targets, w, alpha)
+    fit.step()
+    torch.cuda.synchronize()
+    assert np.array_equal(fit0.lam.cpu().numpy(), lam0)
+    lam1, mm, dl = fit.lam.cpu().numpy(), fit.mismatch.cpu().numpy(), fit.dsum.cpu().numpy()
+    lam_ref, mm_ref, g_ref = O.fit_lambda_step(th, P, lam0, g, targets, 4 * g[1] * w, alpha)
+    assert np.max(np.abs(mm - mm_ref)) <= 1e-12, (mm, mm_ref)
+    scale = np.max(np.abs(g_ref))
+    assert np.max(np.abs(dl - g_ref)) <= 1e-8 * scale
+    step_tol = alpha / len(th) * 1e-8 * scale + 4 * np.spacing(np.abs(lam0))
+    assert np.all(np.abs(lam1 - lam_ref) <= step_tol), np.max(np.abs(lam1 - lam_ref) / step_tol)
+
+
+def test_fit_lambda_descent_full_c4(gpu, lam0):
+    """The descent loop at the full mismatch workload (512 targets x 2^16 bins, one library call per
+    step with no host synchronisation): with a step that lowers the mean mismatch by 1% to first
+    order, 20 steps lower it monotonically, each step by between a half of that first-order
+    prediction and (allowing for rounding and higher orders) 1.05 times it."""
+    import torch
+    from paper_2302_05329_amd import api
+    cfg = W.config4()
+    th, w = cfg["theta"], cfg["inv_psd"]
+    targets, _ = api.waveform_eval(th, P, cfg["grid"], cfg["lam_star"])
+    probe = api.LambdaFit(th, P, cfg["grid"], lam0, targets, w, 0.0)
+    probe.step()
+    loss0 = float(probe.mismatch.mean())
+    grad = probe.dsum.cpu().numpy() / len(th)
+    alpha = 0.01 * loss0 / float(grad @ grad)
+    _say(f"fit_lambda descent C4 nt={len(th)} 20 steps alpha={alpha:.3g}")
+    fit = api.LambdaFit(th, P, cfg["grid"], lam0, targets, w, alpha)
+    losses, pred = [], []
+    for _ in range(20):
+        fit.step()
+        losses.append(fit.mismatch.mean())
+        pred.append(alpha * (fit.dsum / len(th)).square().sum())
+    torch.cuda.synchronize()
+    losses = np.array([float(x) for x in losses])
+    pred = np.array([float(x) for x in pred])
+    assert losses[0] == pytest.approx(loss0, rel=1e-12)
+    drop = losses[:-1] - losses[1:]
+    assert np.all(drop > 0.5 * pred[:-1]) and np.all(drop <= 1.05 * pred[:-1]), (drop / pred[:-1])

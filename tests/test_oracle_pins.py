@@ -451,6 +451,33 @@ def test_mismatch_vanishes_at_target_coefficients(lam0):
     assert np.max(np.abs(g1 * lam_star)) <= 1e-6 * np.max(np.abs(g0 * lam0))
 
 
+def test_fit_step_decreases_mean_mismatch_to_first_order(lam0):
+    """A small descent step lowers the mean mismatch of Eq. 7 by alpha |grad L|^2 to first order
+    (the lag of each target stays at its arg-max), and a step of zero changes nothing."""
+    n = 1024
+    g = _mf_grid(n)
+    w = np.ones(n)
+    rng = np.random.default_rng(13)
+    lam_star = lam0 * (1.0 + 0.01 * rng.standard_normal(lam0.shape))
+    ths = [np.array([28.0, 22.0, 0.3, -0.2, 440.0, 0.0, 0.0]), np.array([35.0, 15.0, -0.4, 0.1, 440.0, 0.0, 0.0])]
+    tgs = [O.waveform(th, P, lam_star, g) for th in ths]
+    lam1, mm0, gsum = O.fit_lambda_step(ths, P, lam0, g, tgs, w, 0.0)
+    assert np.array_equal(lam1, lam0)
+    grad = gsum / len(ths)
+    loss0 = mm0.mean()
+    dev = []
+    for alpha in (1e-3, 1e-4):
+        # a step that lowers the loss by the fraction alpha to first order
+        a = alpha * loss0 / float(grad @ grad)
+        lam_a, _, _ = O.fit_lambda_step(ths, P, lam0, g, tgs, w, a)
+        loss_a = np.mean([O.mismatch(th, P, lam_a, g, tg, w)[0] for th, tg in zip(ths, tgs)])
+        ratio = (loss0 - loss_a) / (a * float(grad @ grad))
+        dev.append(1.0 - ratio)
+        assert 0.0 < 1.0 - ratio < 50 * alpha, (alpha, ratio)
+    # the deviation is the second-order term: it shrinks in proportion to the step
+    assert 7.0 < dev[0] / dev[1] < 13.0, dev
+
+
 # ---------------------------------------------------------------------------------
 # the placeholder coefficient table gives a sane model over the configs' priors
 # ---------------------------------------------------------------------------------
