@@ -210,6 +210,50 @@ def config5(seed=1005):
                 psd=psd, inv_psd=1.0 / psd, noise=noise, n_chains=4096, snr=20.0)
 
 
+# Detector geometry in Earth-fixed Cartesian coordinates (metres; arm directions are unit
+# vectors): the published site descriptions of LIGO Hanford (H1), LIGO Livingston (L1) and Virgo
+# (V1), as compiled for the LIGO/Virgo analysis libraries (Althouse, Jones and Lazzarini,
+# LIGO-P000006; the Virgo values from the same compilation).  Inputs only: vertex, x arm, y arm.
+DETECTORS = {
+    "H1": ((-2.16141492636e+06, -3.83469517889e+06, 4.60035022664e+06),
+           (-0.22389266154, 0.79983062746, 0.55690487831),
+           (-0.91397818574, 0.02609403989, -0.40492342125)),
+    "L1": ((-7.42760447238e+04, -5.49628371971e+06, 3.22425701744e+06),
+           (-0.95457412153, -0.14158077340, -0.26218911324),
+           (0.29774156894, -0.48791033647, -0.82054461286)),
+    "V1": ((4.54637409900e+06, 8.42989697626e+05, 4.37857696241e+06),
+           (-0.70045821479, 0.20848948619, 0.68256166277),
+           (-0.05379255368, -0.96908180549, 0.24080451708)),
+}
+
+
+def network_sources(n, seed, d_range=(100.0, 2000.0)):
+    """Rows of 11 parameters for the detector network: the 7 of `draw_sources` (m1, m2, chi1, chi2,
+    D, tc, phic) followed by inclination iota (cos iota uniform in [-1, 1]), polarisation psi
+    (uniform in [0, pi)), right ascension alpha (uniform in [0, 2 pi)) and declination delta
+    (sin delta uniform in [-1, 1]): isotropic orientation and sky position."""
+    base = draw_sources(n, seed, d_range=d_range, tc_range=(-0.1, 0.1), phic_random=True)
+    rng = _rng(seed + 50000)
+    iota = np.arccos(rng.uniform(-1.0, 1.0, n))
+    psi = rng.uniform(0.0, np.pi, n)
+    alpha = rng.uniform(0.0, 2.0 * np.pi, n)
+    delta = np.arcsin(rng.uniform(-1.0, 1.0, n))
+    return np.concatenate([base, np.stack([iota, psi, alpha, delta], axis=1)], axis=1)
+
+
+def network_config(n=65536, dets=("H1", "L1", "V1"), seed=1007, n_bins=16225, df=0.125, gmst=1.234):
+    """Detector-network likelihood: C2's grid and source priors with isotropic orientation and sky
+    position, one noise realisation per detector (analytic PSD stand-in for every site), and a
+    fixed Greenwich sidereal angle gmst (rad) at the reference time."""
+    grid = Grid(20.0, df, n_bins, f_min=20.0, f_ref=20.0)
+    theta = network_sources(n, seed)
+    psd = psd_aligo_zdhp_fit(grid.freqs())
+    data = np.stack([complex_noise(psd, grid.df, seed + 10 * k) for k in range(len(dets))])
+    return dict(name=f"network lnL+grad {n}x{n_bins}x{len(dets)}", theta=theta, grid=grid, dets=tuple(dets),
+                geometry=[DETECTORS[d] for d in dets], psd=psd, inv_psd=np.stack([1.0 / psd] * len(dets)),
+                data=data, gmst=gmst)
+
+
 def fig1_sweep(n=10000, seed=1006):
     """Precision sweep shaped like the paper's Fig. 1 comparison: component masses uniform in
     (1, 100) Msun and aligned spins uniform in (-1, 1), D = 440 Mpc, on 32-1024 Hz with
