@@ -205,6 +205,25 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     extra["C2_loglike_value"] = {"evals_per_s": th2.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
                                  "tflops_algorithmic": fl / (kms * 1e-3) / 1e12}
 
+    # detector network (H1, L1, V1): 65536 points x 16225 bins x 3 sites, ln L + 11-parameter gradient
+    net = W.network_config()
+    thn = torch.as_tensor(net["theta"], device=dev)
+    dn = torch.as_tensor(net["data"], device=dev)
+    ipn = torch.as_tensor(net["inv_psd"], device=dev)
+    wsn = api.Workspace()
+    api.profile_read(L.PD_K_LOGLIKE_GRAD)
+    t = timed_calls(lambda: api.network_loglike_and_grad(thn, P, net["grid"], lam, net["geometry"], net["gmst"], dn,
+                                                         ipn, ws=wsn), iters, 1)
+    kms, cnt = kernel_avg_ms(api, L.PD_K_LOGLIKE_GRAD)
+    # each site's pass covers the same active bins (they depend on the masses only)
+    trn = api.transition_frequencies(np.ascontiguousarray(net["theta"][:, :7]), P, net["grid"], lam, ws=ws).cpu().numpy()
+    fl_site = flops.batch_flops("loglike_grad", trn, net["grid"].as_tuple())[0]
+    extra["network_loglike_grad_3sites"] = {
+        "evals_per_s": thn.shape[0] / t, "ms": 1e3 * t, "sites": len(net["dets"]), "points": int(thn.shape[0]),
+        "n_bins": net["grid"].n_bins, "site_pass_ms": kms, "site_passes": cnt,
+        "tflops_algorithmic_site_pass": fl_site / (kms * 1e-3) / 1e12}
+    del thn, dn, ipn, wsn
+
     # strain output, C1: 1024 x 4017 complex128
     c1 = W.config1()
     th1 = torch.as_tensor(c1["theta"], device=dev)

@@ -153,6 +153,45 @@ int pd_fit_lambda_step(const double* theta, int64_t nt, int param, const pd_grid
                        const double* targets, const double* inv_psd, double alpha, double* mismatch,
                        double* dsum_dlambda, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Detector network: the two-detector injection of Sec. 3.3 and the network setups of the
+ * Fisher forecasts (Sec. 3.2).  The paper does not print the detector response; the one used
+ * is the standard response to the dominant (2,2) mode:
+ *   h_d(f) = (F+ h+ + Fx hx) exp(-2 pi i f dt_d),  h+ = h0 (1 + cos^2 iota)/2,  hx = -i cos iota h0,
+ * with h0 the face-on, optimally oriented strain of pd_waveform_eval, the antenna patterns
+ *   F+ = D : (XX - YY),  Fx = D : (XY + YX),  D = (x x^T - y y^T)/2  (unit arm vectors x, y),
+ * in the Earth-fixed frame: source direction n = (cos dec cos l, cos dec sin l, sin dec),
+ * l = ra - gmst; a = (sin l, -cos l, 0), b = n x a; X = cos psi a + sin psi b,
+ * Y = -sin psi a + cos psi b; and the arrival delay dt_d = -(r_d . n)/c at the site vertex r_d.
+ * Network ln L = sum over sites of (d_d|h_d) - (h_d|h_d)/2 (Eq. 1 per site).
+ * ------------------------------------------------------------------------------------- */
+#define PD_NETWORK_MAX_DETECTORS 8
+
+typedef struct {
+    double vertex[3];   /* site position, Earth-fixed Cartesian, metres */
+    double xarm[3];     /* unit vector along the x arm */
+    double yarm[3];     /* unit vector along the y arm */
+} pd_detector;
+
+size_t pd_network_workspace_bytes(int64_t n, int64_t n_bins, int n_det);
+
+/* Network ln L and its gradient over 11 parameters for n points.
+ * theta     [n][11]          the 7 entries of layout `param`, then (iota, psi, ra, dec) in rad
+ * n_det     1..PD_NETWORK_MAX_DETECTORS;  detectors [n_det] HOST array
+ * gmst      Greenwich sidereal angle at the reference time (rad)
+ * data      [n_det][n_bins][2]  complex128 data of each site;  inv_psd [n_det][n_bins]
+ * lnl [n]; grad [n][11] or NULL (value only); status [n] or NULL (PD_OK / PD_EDOMAIN, NaN
+ *           outputs for a point invalid at any site, e.g. a zero response |F+ (1+cos^2 iota)/2
+ *           - i Fx cos iota| that makes its effective distance infinite)
+ * Each site runs one fused pass of pd_loglike_and_grad at the site's effective parameters
+ * (D / |c|, tc + dt, phic + arg(c)/2 with c the complex response above), one after another on
+ * `stream`.  Workspace: pd_network_workspace_bytes(n, n_bins, n_det), 256-byte aligned.
+ */
+int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid,
+                                const double* lambda, int n_det, const pd_detector* detectors, double gmst,
+                                const double* data, const double* inv_psd, double* lnl, double* grad,
+                                int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Per-point model quantities used to account the work of a batch (Sec. 2): for each row,
  * out[i] = {M T_sun [s], Mf of the phase join intermediate->merger-ringdown (f_RD / 2),
  *           Mf of the amplitude join intermediate->merger-ringdown (f_peak), valid (1/0)}.

@@ -59,6 +59,13 @@ class PdPosterior(ctypes.Structure):
                 ("mu", ctypes.c_double * 7), ("isig2", ctypes.c_double * 7)]
 
 
+PD_NETWORK_MAX_DETECTORS = 8
+
+
+class PdDetector(ctypes.Structure):
+    _fields_ = [("vertex", ctypes.c_double * 3), ("xarm", ctypes.c_double * 3), ("yarm", ctypes.c_double * 3)]
+
+
 class PdError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"phenomd error {code}: {msg}")
@@ -78,6 +85,9 @@ SIGNATURES = {
     "pd_loglike_and_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _INT, _P, _P, _P, _P, _SZ, _P]),
     "pd_fisher": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_mismatch_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pd_network_workspace_bytes": (_SZ, [_I64, _I64, _INT]),
+    "pd_network_loglike_and_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _INT, ctypes.POINTER(PdDetector), ctypes.c_double,
+                                           _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_fit_lambda_step": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, ctypes.c_double, _P, _P, _P, _SZ, _P]),
     "pd_posterior_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
     "pd_posterior_logp": (_INT, [ctypes.c_void_p, _P, _I64, _P, _P, _P, _SZ, _P]),

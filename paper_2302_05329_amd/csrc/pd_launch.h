@@ -91,6 +91,22 @@ int independence_mh(int64_t n, double* x, double* logp, double* logq, double* gr
 
 hipError_t launch_elementary(int fn, const double* x, int64_t n, double* out, hipStream_t s);
 
+// Detector network (pd_network.hip): 11 parameters per point, per-site geometry.
+constexpr int kNetParams = 11;
+constexpr int kNetJac = 13;
+struct NetSite {
+    double vertex[3], xarm[3], yarm[3];
+};
+struct NetArgs {
+    int n_det;
+    double gmst;
+    NetSite site[PD_NETWORK_MAX_DETECTORS];
+};
+hipError_t launch_net_setup(const double* theta, int64_t n, int param, const NetArgs& na, double* eff, double* jac,
+                            hipStream_t s);
+hipError_t launch_net_combine(int64_t n, int n_det, const double* lnl_d, const double* grad_d, const int32_t* status_d,
+                              const double* jac, double* lnl, double* grad, int32_t* status, hipStream_t s);
+
 constexpr int kOverlapMaxStreams = PD_OVERLAP_MAX_STREAMS;
 size_t overlap_bprime_bytes(int64_t nb, int64_t ns);
 hipError_t launch_overlap(const double* recs, int64_t nt, const GridArgs& g, const double* tab, const double* data,

@@ -105,3 +105,33 @@ def test_rwmh_rejects_bad_arguments(lib, bad):
                           None, None if bad == "ws" else vp(2048), 16 if bad == "wsb" else need, None)
     assert rc == (L.PD_ENOMEM if bad == "wsb" else L.PD_EINVAL)
     assert len(lib.pd_last_error()) > 0
+
+
+@pytest.mark.parametrize("bad", ["ndet0", "ndet9", "gmst", "dets", "wsb"])
+def test_network_rejects_bad_arguments(lib, bad):
+    vp = ctypes.c_void_p
+    g = L.make_grid(20.0, 0.25, 100, 20.0, 20.0)
+    nd = {"ndet0": 0, "ndet9": 9}.get(bad, 2)
+    dets = (L.PdDetector * 2)()
+    for k in range(2):
+        dets[k].xarm[0], dets[k].yarm[1] = 1.0, 1.0
+    need = lib.pd_network_workspace_bytes(4, 100, 2)
+    assert need > lib.pd_workspace_bytes(2, 4, 100) and need % 256 == 0
+    assert lib.pd_network_workspace_bytes(4, 100, 0) == 0
+    rc = lib.pd_network_loglike_and_grad(vp(256), 4, 3, ctypes.byref(g), vp(512), nd, None if bad == "dets" else dets,
+                                         float("nan") if bad == "gmst" else 0.5, vp(768), vp(1024), vp(1280), None,
+                                         None, vp(2048), 16 if bad == "wsb" else need, None)
+    assert rc == (L.PD_ENOMEM if bad == "wsb" else L.PD_EINVAL)
+    assert len(lib.pd_last_error()) > 0
+
+
+@pytest.mark.parametrize("bad", ["alpha_neg", "alpha_nan", "dsum", "alias"])
+def test_fit_lambda_step_rejects_bad_arguments(lib, bad):
+    vp = ctypes.c_void_p
+    g = L.make_grid(0.0, 0.01, 65536, 1.0, 20.0)
+    alpha = {"alpha_neg": -1e-6, "alpha_nan": float("nan")}.get(bad, 1e-6)
+    dsum = None if bad == "dsum" else (512 if bad == "alias" else 4096)
+    rc = lib.pd_fit_lambda_step(vp(256), 1, 3, ctypes.byref(g), vp(512), vp(768), vp(1024), alpha, vp(1280),
+                                vp(dsum) if dsum else None, vp(2048), 1 << 40, None)
+    assert rc == L.PD_EINVAL
+    assert len(lib.pd_last_error()) > 0
