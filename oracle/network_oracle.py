@@ -20,12 +20,14 @@ definitions (e.g. Schutz 2011, Anderson et al. 2001), with these readings:
     face-on, optimally oriented strain of the single-detector model;
   * detector strain h_d(f) = (F+ h+ + Fx hx) exp(-2 pi i f dt_d);
   * network log-likelihood: the sum over detectors of (d_d|h_d) - (h_d|h_d)/2 (Eq. 1 per
-    detector, each with its own noise PSD).
+    detector, each with its own noise PSD);
+  * network Fisher matrix: the sum over detectors of (d_p h_d | d_q h_d) (Eq. 8 per detector).
 Parameters: the 7 of the single-detector model (layout `param`) followed by (iota, psi, alpha,
 delta).  Pinned by tests/test_network_oracle.py (the antenna-pattern sum against its closed form
 for a detector with arms along x and y, polarisation-rotation identities, arrival delays against
 the site baselines, reduction to the single-detector likelihood, the effective-parameter identity,
-gradients against central differences).
+gradients against central differences, the Fisher matrix against minus the Hessian of the
+noise-free network likelihood).
 """
 import math
 
@@ -86,29 +88,56 @@ def loglike(theta, param, lam, grid, dets, data, inv_psd, gmst):
     return total
 
 
-def loglike_grad(theta, param, lam, grid, dets, data, inv_psd, gmst):
-    """d lnL / d theta (11) by complex step through a real-analytic form of the network ln L:
+def _strain_parts(tp, param, lam, grid, act, det, gmst):
+    """Real and imaginary parts of one detector's strain on the active bins, written in
+    real-analytic form so that complex-step perturbations of tp pass through:
     with c = F+ (1 + cos^2 iota)/2 - i Fx cos iota = cr + i ci and Phi = Psi + 2 pi f dt,
     Re h_d = A (cr cos Phi + ci sin Phi) and Im h_d = A (ci cos Phi - cr sin Phi)."""
+    a_c, ph_c, _ = O.amp_phase(tp[:7], param, lam, grid, act)
+    iota, psi, alpha, delta = tp[7:11]
+    f = O.grid_freqs(grid)[act]
+    fp, fx = antenna(det, alpha, delta, psi, gmst)
+    cr = fp * (1.0 + np.cos(iota) ** 2) / 2.0
+    ci = -fx * np.cos(iota)
+    phi = ph_c + 2.0 * math.pi * f * delay(det, alpha, delta, gmst)
+    return a_c * (cr * np.cos(phi) + ci * np.sin(phi)), a_c * (ci * np.cos(phi) - cr * np.sin(phi))
+
+
+def fisher(theta, param, lam, grid, dets, inv_psd, gmst):
+    """F_pq = sum over detectors of (d_p h_d | d_q h_d), the strain derivatives by complex step
+    (11 x 11)."""
     theta = np.asarray(theta, dtype=np.float64)
     act = O.active_mask(theta[:7], param, grid)
-    f = O.grid_freqs(grid)[act]
+    df = grid[1]
+    F = np.zeros((11, 11))
+    for k, det in enumerate(dets):
+        dh = []
+        for p in range(11):
+            hstep = O._cs_step(theta[p])
+            tp = theta.astype(np.complex128)
+            tp[p] += 1j * hstep
+            hr, hi = _strain_parts(tp, param, lam, grid, act, det, gmst)
+            dh.append(np.imag(hr) / hstep + 1j * (np.imag(hi) / hstep))
+        w = inv_psd[k][act]
+        for p in range(11):
+            for q in range(p, 11):
+                F[p, q] += O.inner(dh[p], dh[q], w, df)
+    return np.triu(F) + np.triu(F, 1).T
+
+
+def loglike_grad(theta, param, lam, grid, dets, data, inv_psd, gmst):
+    """d lnL / d theta (11) by complex step through the real-analytic strain of each detector."""
+    theta = np.asarray(theta, dtype=np.float64)
+    act = O.active_mask(theta[:7], param, grid)
     df = grid[1]
     g = np.zeros(11)
     for p in range(11):
         hstep = O._cs_step(theta[p])
         tp = theta.astype(np.complex128)
         tp[p] += 1j * hstep
-        a_c, ph_c, _ = O.amp_phase(tp[:7], param, lam, grid, act)
-        iota, psi, alpha, delta = tp[7:11]
         lnl = 0.0
         for k, det in enumerate(dets):
-            fp, fx = antenna(det, alpha, delta, psi, gmst)
-            cr = fp * (1.0 + np.cos(iota) ** 2) / 2.0
-            ci = -fx * np.cos(iota)
-            phi = ph_c + 2.0 * math.pi * f * delay(det, alpha, delta, gmst)
-            hr = a_c * (cr * np.cos(phi) + ci * np.sin(phi))
-            hi = a_c * (ci * np.cos(phi) - cr * np.sin(phi))
+            hr, hi = _strain_parts(tp, param, lam, grid, act, det, gmst)
             w = inv_psd[k][act]
             d = data[k][act]
             lnl = lnl + 4.0 * df * np.sum(w * (d.real * hr + d.imag * hi)) - 2.0 * df * np.sum(w * (hr * hr + hi * hi))

@@ -130,3 +130,45 @@ def test_network_gradient_against_central_differences(lam0):
         tm[p] -= h
         fd = (N.loglike(tp, P, lam0, g, dets, data, ip, 0.4) - N.loglike(tm, P, lam0, g, dets, data, ip, 0.4)) / (2 * h)
         assert abs(fd - grad[p]) <= 1e-5 * max(abs(grad[p]), 1.0), (p, fd, grad[p])
+
+
+def test_network_fisher_is_negative_hessian_of_noise_free_loglike(lam0):
+    """F = -Hessian of the network ln L at theta0 for noise-free data (Richardson-extrapolated
+    central differences of the gradient); symmetric positive definite."""
+    dets = [W.DETECTORS["H1"], W.DETECTORS["L1"], W.DETECTORS["V1"]]
+    grid = W.Grid(20.0, 0.25, 2001, 20.0, 20.0)
+    g = grid.as_tuple()
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    ip = np.stack([1 / psd] * 3)
+    th = W.network_sources(1, 51)[0]
+    th[4] = 400.0
+    data = np.stack([N.strain(th, P, lam0, g, det, 0.9) for det in dets])
+    F = N.fisher(th, P, lam0, g, dets, ip, 0.9)
+    assert np.array_equal(F, F.T)
+    assert np.all(np.linalg.eigvalsh(F / np.sqrt(np.outer(np.diag(F), np.diag(F)))) > 0)
+
+    def central(p, h):
+        tp, tm = th.copy(), th.copy()
+        tp[p] += h
+        tm[p] -= h
+        return (N.loglike_grad(tp, P, lam0, g, dets, data, ip, 0.9) - N.loglike_grad(tm, P, lam0, g, dets, data, ip, 0.9)) / (2 * h)
+
+    H = np.zeros((11, 11))
+    for p in range(11):
+        h = 1e-5 * max(abs(th[p]), 1.0)
+        H[p] = (4.0 * central(p, h / 2) - central(p, h)) / 3.0
+    scale = np.sqrt(np.outer(np.diag(F), np.diag(F)))
+    assert np.max(np.abs(-H - F) / scale) < 1e-6
+
+
+def test_network_fisher_one_optimal_site_is_the_single_detector_fisher(lam0):
+    det = ((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0))
+    grid = W.Grid(20.0, 0.25, 2001, 20.0, 20.0)
+    g = grid.as_tuple()
+    w = 1 / W.psd_aligo_zdhp_fit(grid.freqs())
+    th = W.network_sources(1, 52)[0]
+    a = 0.8
+    th[7:11] = (0.0, math.pi / 2 - a, a, math.pi / 2)
+    F = N.fisher(th, P, lam0, g, [det], w[None], 0.0)
+    F7 = O.fisher(th[:7], P, lam0, g, w)
+    assert np.max(np.abs(F[:7, :7] - F7) / np.sqrt(np.outer(np.diag(F7), np.diag(F7)))) < 1e-12
