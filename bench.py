@@ -224,6 +224,20 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
         "tflops_algorithmic_site_pass": fl_site / (kms * 1e-3) / 1e12}
     del thn, dn, ipn, wsn
 
+    # network Fisher matrices (11 x 11) on C3's grid: 16384 points x 16065 bins x 3 sites
+    netf = W.network_config(n=16384, n_bins=16065, df=0.0625)
+    thf = torch.as_tensor(netf["theta"], device=dev)
+    ipf = torch.as_tensor(netf["inv_psd"], device=dev)
+    wsf = api.Workspace()
+    api.profile_read(L.PD_K_FISHER)
+    t = timed_calls(lambda: api.network_fisher(thf, P, netf["grid"], lam, netf["geometry"], netf["gmst"], ipf, ws=wsf),
+                    iters, 1)
+    kms, cnt = kernel_avg_ms(api, L.PD_K_FISHER)
+    extra["network_fisher_3sites"] = {"fishers_per_s": thf.shape[0] / t, "ms": 1e3 * t, "sites": len(netf["dets"]),
+                                      "points": int(thf.shape[0]), "n_bins": netf["grid"].n_bins,
+                                      "site_pass_ms": kms, "site_passes": cnt}
+    del thf, ipf, wsf
+
     # strain output, C1: 1024 x 4017 complex128
     c1 = W.config1()
     th1 = torch.as_tensor(c1["theta"], device=dev)

@@ -192,6 +192,20 @@ int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const
                                 const double* data, const double* inv_psd, double* lnl, double* grad,
                                 int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
 
+size_t pd_network_fisher_workspace_bytes(int64_t n, int64_t n_bins, int n_det);
+
+/* Network Fisher matrix over the same 11 parameters (Eq. 8 summed over sites):
+ *   F_pq = sum over sites of (d_p h_d | d_q h_d),
+ * computed as sum over sites of J^T F_d J with F_d the single-site Fisher matrix (pd_fisher) at
+ * the site's effective parameters and J the 7 x 11 Jacobian of those parameters.
+ * theta [n][11], detectors, gmst, inv_psd [n_det][n_bins] as for pd_network_loglike_and_grad;
+ * F [n][11][11] output (symmetric); status [n] or NULL.
+ * Workspace: pd_network_fisher_workspace_bytes(n, n_bins, n_det), 256-byte aligned.
+ */
+int pd_network_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                      int n_det, const pd_detector* detectors, double gmst, const double* inv_psd, double* F,
+                      int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Per-point model quantities used to account the work of a batch (Sec. 2): for each row,
  * out[i] = {M T_sun [s], Mf of the phase join intermediate->merger-ringdown (f_RD / 2),
  *           Mf of the amplitude join intermediate->merger-ringdown (f_peak), valid (1/0)}.

@@ -117,26 +117,44 @@ def loglike_and_grad(theta, param, grid, lam, data, inv_psd, want_grad=True, pre
     return lnl, grad, status
 
 
-def network_loglike_and_grad(theta, param, grid, lam, detectors, gmst, data, inv_psd, want_grad=True, ws=None):
-    """Detector-network ln L [n], d lnL / d theta [n, 11] (or None) and status [n].  theta: [n, 11]
-    (the 7 entries of `param`, then iota, psi, ra, dec); detectors: sequence of (vertex, x arm,
-    y arm); data: complex [n_det, n_bins]; inv_psd: [n_det, n_bins]."""
-    ws = ws or _default_ws
+def _net_args(theta, lam, grid, detectors, inv_psd):
     g = _grid(grid)
     th = _dev(theta)
     lam = _dev(lam)
-    d = _dev(data)
     ip = _dev(inv_psd)
     nd = len(detectors)
     _need(1 <= nd <= L.PD_NETWORK_MAX_DETECTORS, f"1..{L.PD_NETWORK_MAX_DETECTORS} detectors, got {nd}")
     _need(th.dim() == 2 and th.shape[1] == 11 and th.shape[0] > 0, f"theta must be [n, 11], got {tuple(th.shape)}")
     _need(lam.numel() == 209, f"lambda must hold 209 coefficients, got {lam.numel()}")
-    _need(tuple(d.shape) == (nd, g.n_bins, 2), f"data must be complex [{nd}, {g.n_bins}], got {tuple(d.shape)}")
     _need(tuple(ip.shape) == (nd, g.n_bins), f"inv_psd must be [{nd}, {g.n_bins}], got {tuple(ip.shape)}")
     dets = (L.PdDetector * nd)()
     for k, (v, x, y) in enumerate(detectors):
         for j in range(3):
             dets[k].vertex[j], dets[k].xarm[j], dets[k].yarm[j] = float(v[j]), float(x[j]), float(y[j])
+    return g, th, lam, ip, nd, dets
+
+
+def network_fisher(theta, param, grid, lam, detectors, gmst, inv_psd, ws=None):
+    """Network Fisher matrices [n, 11, 11] and status [n] (theta [n, 11], inv_psd [n_det, n_bins])."""
+    ws = ws or _default_ws
+    g, th, lam, ip, nd, dets = _net_args(theta, lam, grid, detectors, inv_psd)
+    n = th.shape[0]
+    F = torch.empty((n, 11, 11), dtype=torch.float64, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    wp, wb = ws.get(L.lib().pd_network_fisher_workspace_bytes(n, g.n_bins, nd))
+    L.check(L.lib().pd_network_fisher(_ptr(th), n, param, ctypes.byref(g), _ptr(lam), nd, dets, float(gmst), _ptr(ip),
+                                      _ptr(F), _ptr(status), wp, wb, _stream()))
+    return F, status
+
+
+def network_loglike_and_grad(theta, param, grid, lam, detectors, gmst, data, inv_psd, want_grad=True, ws=None):
+    """Detector-network ln L [n], d lnL / d theta [n, 11] (or None) and status [n].  theta: [n, 11]
+    (the 7 entries of `param`, then iota, psi, ra, dec); detectors: sequence of (vertex, x arm,
+    y arm); data: complex [n_det, n_bins]; inv_psd: [n_det, n_bins]."""
+    ws = ws or _default_ws
+    g, th, lam, ip, nd, dets = _net_args(theta, lam, grid, detectors, inv_psd)
+    d = _dev(data)
+    _need(tuple(d.shape) == (nd, g.n_bins, 2), f"data must be complex [{nd}, {g.n_bins}], got {tuple(d.shape)}")
     n = th.shape[0]
     lnl = torch.empty(n, dtype=torch.float64, device="cuda")
     grad = torch.empty((n, 11), dtype=torch.float64, device="cuda") if want_grad else None

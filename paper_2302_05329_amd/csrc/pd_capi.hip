@@ -392,10 +392,13 @@ struct NetLayout {
     size_t ll = 0, eff = 0, jac = 0, lnl = 0, grad = 0, status = 0, total = 0;
 };
 
-NetLayout net_layout(int64_t n, int64_t nb, int n_det) {
+// Network workspace: the single-site workspace of `op` (reused by every site in turn), then per
+// (site, point) the effective rows, their derivatives, and the site results (ln L in `lnl` and
+// the gradient in `grad` for PD_OP_LOGLIKE_GRAD; the 7x7 Fisher matrix in `grad` for PD_OP_FISHER).
+NetLayout net_layout(int64_t n, int64_t nb, int n_det, int op = PD_OP_LOGLIKE_GRAD) {
     NetLayout L;
     const size_t M = static_cast<size_t>(n) * static_cast<size_t>(n_det);
-    size_t off = align_up(layout_for(PD_OP_LOGLIKE_GRAD, n, nb).total);
+    size_t off = align_up(layout_for(op, n, nb).total);
     L.eff = off;
     off = align_up(off + M * 7 * sizeof(double));
     L.jac = off;
@@ -403,7 +406,7 @@ NetLayout net_layout(int64_t n, int64_t nb, int n_det) {
     L.lnl = off;
     off = align_up(off + M * sizeof(double));
     L.grad = off;
-    off = align_up(off + M * 7 * sizeof(double));
+    off = align_up(off + M * (op == PD_OP_FISHER ? 49 : 7) * sizeof(double));
     L.status = off;
     off = align_up(off + M * sizeof(int32_t));
     L.total = off;
@@ -419,28 +422,44 @@ size_t pd_network_workspace_bytes(int64_t n, int64_t n_bins, int n_det) {
     return net_layout(n, n_bins, n_det).total;
 }
 
-int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
-                                int n_det, const pd_detector* detectors, double gmst, const double* data,
-                                const double* inv_psd, double* lnl, double* grad, int32_t* status, void* workspace,
-                                size_t workspace_bytes, void* stream) {
-    pd::GridArgs g;
-    int rc = check_common(theta, n, param, grid, lambda, &g);
+}  // extern "C"
+
+namespace {
+
+int net_check(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda, int n_det,
+              const pd_detector* detectors, double gmst, const double* inv_psd, pd::GridArgs* g, pd::NetArgs* na) {
+    int rc = check_common(theta, n, param, grid, lambda, g);
     if (rc) return rc;
     if (n_det < 1 || n_det > PD_NETWORK_MAX_DETECTORS) return fail(PD_EINVAL, "n_det out of range");
-    if (!detectors || !data || !inv_psd || !lnl) return fail(PD_EINVAL, "NULL argument");
+    if (!detectors || !inv_psd) return fail(PD_EINVAL, "NULL argument");
     if (!std::isfinite(gmst)) return fail(PD_EINVAL, "gmst must be finite");
-    pd::NetArgs na;
-    na.n_det = n_det;
-    na.gmst = gmst;
+    na->n_det = n_det;
+    na->gmst = gmst;
     for (int d = 0; d < n_det; ++d)
         for (int k = 0; k < 3; ++k) {
             const double v[3] = {detectors[d].vertex[k], detectors[d].xarm[k], detectors[d].yarm[k]};
             if (!std::isfinite(v[0]) || !std::isfinite(v[1]) || !std::isfinite(v[2]))
                 return fail(PD_EINVAL, "detector geometry must be finite");
-            na.site[d].vertex[k] = v[0];
-            na.site[d].xarm[k] = v[1];
-            na.site[d].yarm[k] = v[2];
+            na->site[d].vertex[k] = v[0];
+            na->site[d].xarm[k] = v[1];
+            na->site[d].yarm[k] = v[2];
         }
+    return PD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                                int n_det, const pd_detector* detectors, double gmst, const double* data,
+                                const double* inv_psd, double* lnl, double* grad, int32_t* status, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+    pd::GridArgs g;
+    pd::NetArgs na;
+    int rc = net_check(theta, n, param, grid, lambda, n_det, detectors, gmst, inv_psd, &g, &na);
+    if (rc) return rc;
+    if (!data || !lnl) return fail(PD_EINVAL, "NULL argument");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
     const NetLayout L = net_layout(n, g.nb, n_det);
     if (workspace_bytes < L.total) return fail(PD_ENOMEM, "workspace too small (see pd_network_workspace_bytes)");
@@ -463,6 +482,41 @@ int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const
     }
     e = pd::launch_net_combine(n, n_det, lnl_d, grad_d, st_d, jac, lnl, grad, status, s);
     if (e != hipSuccess) return fail_hip(e, "network combine");
+    return PD_OK;
+}
+
+size_t pd_network_fisher_workspace_bytes(int64_t n, int64_t n_bins, int n_det) {
+    if (n <= 0 || n_bins <= 0 || n_det < 1 || n_det > PD_NETWORK_MAX_DETECTORS) return 0;
+    return net_layout(n, n_bins, n_det, PD_OP_FISHER).total;
+}
+
+int pd_network_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda, int n_det,
+                      const pd_detector* detectors, double gmst, const double* inv_psd, double* F, int32_t* status,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+    pd::GridArgs g;
+    pd::NetArgs na;
+    int rc = net_check(theta, n, param, grid, lambda, n_det, detectors, gmst, inv_psd, &g, &na);
+    if (rc) return rc;
+    if (!F) return fail(PD_EINVAL, "F is NULL");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    const NetLayout L = net_layout(n, g.nb, n_det, PD_OP_FISHER);
+    if (workspace_bytes < L.total) return fail(PD_ENOMEM, "workspace too small (see pd_network_fisher_workspace_bytes)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* eff = at<double>(workspace, L.eff);
+    double* jac = at<double>(workspace, L.jac);
+    double* F_d = at<double>(workspace, L.grad);
+    int32_t* st_d = at<int32_t>(workspace, L.status);
+    hipError_t e = pd::launch_net_setup(theta, n, param, na, eff, jac, s);
+    if (e != hipSuccess) return fail_hip(e, "network setup");
+    const size_t f_bytes = layout_for(PD_OP_FISHER, n, g.nb).total;
+    for (int d = 0; d < n_det; ++d) {
+        const int64_t off = static_cast<int64_t>(d) * n;
+        rc = pd_fisher(eff + off * 7, n, param, grid, lambda, inv_psd + static_cast<int64_t>(d) * g.nb, F_d + off * 49,
+                       st_d + off, workspace, f_bytes, stream);
+        if (rc != PD_OK) return rc;
+    }
+    e = pd::launch_net_fisher_combine(n, n_det, F_d, st_d, jac, F, status, s);
+    if (e != hipSuccess) return fail_hip(e, "network Fisher combine");
     return PD_OK;
 }
 

@@ -106,6 +106,8 @@ hipError_t launch_net_setup(const double* theta, int64_t n, int param, const Net
                             hipStream_t s);
 hipError_t launch_net_combine(int64_t n, int n_det, const double* lnl_d, const double* grad_d, const int32_t* status_d,
                               const double* jac, double* lnl, double* grad, int32_t* status, hipStream_t s);
+hipError_t launch_net_fisher_combine(int64_t n, int n_det, const double* F_d, const int32_t* status_d, const double* jac,
+                                     double* F, int32_t* status, hipStream_t s);
 
 constexpr int kOverlapMaxStreams = PD_OVERLAP_MAX_STREAMS;
 size_t overlap_bprime_bytes(int64_t nb, int64_t ns);

@@ -11,7 +11,9 @@
 // so each site is one fused likelihood pass of the single-detector kernels at its effective
 // parameters and its own data and noise.  This file holds the two per-point kernels around those
 // passes: the effective parameters with their derivatives, and the sum over sites with the chain
-// rule to the 11 parameters.
+// rule to the 11 parameters.  The network Fisher matrix (Eq. 8 summed over sites) is built the same
+// way from one single-site Fisher pass per site: F = sum over sites of J^T F_d J, with J the
+// Jacobian of the site's effective row.
 //
 // Frame: Earth-fixed; source direction n = (cos d cos l, cos d sin l, sin d), l = alpha - gmst;
 // wave axes a = (sin l, -cos l, 0), b = n x a = (sin d cos l, sin d sin l, -cos d), and
@@ -143,6 +145,50 @@ __global__ void __launch_bounds__(128) k_net_combine(int64_t n, int n_det, const
     if (status) status[i] = ok ? PD_OK : PD_EDOMAIN;
 }
 
+// Nonzero entries of column p of the 7 x 11 Jacobian d(effective row) / d(theta) of one site:
+// the identity on the first 7 columns (with d row4 / d theta4 at (4, 4)), rows 4-6 on the last 4.
+__device__ __forceinline__ int jac_col(int p, const double* __restrict__ J, int* rows, double* vals) {
+    if (p < 7) {
+        rows[0] = p;
+        vals[0] = (p == 4) ? J[0] : 1.0;
+        return 1;
+    }
+    const int m = p - 7;
+    for (int k = 0; k < 3; ++k) {
+        rows[k] = 4 + k;
+        vals[k] = J[1 + 4 * k + m];
+    }
+    return 3;
+}
+
+// Network Fisher matrix: F = sum over sites of J^T F_d J, one thread per (point, entry).
+__global__ void __launch_bounds__(128) k_net_fisher_combine(int64_t n, int n_det, const double* __restrict__ F_d,
+                                                            const int32_t* __restrict__ status_d,
+                                                            const double* __restrict__ jac, double* __restrict__ F,
+                                                            int32_t* __restrict__ status) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * kNetParams * kNetParams) return;
+    const int64_t i = t / (kNetParams * kNetParams);
+    const int e = static_cast<int>(t % (kNetParams * kNetParams));
+    // both (p, q) and (q, p) are summed in the order of (min, max): the result is exactly symmetric
+    const int p = min(e / kNetParams, e % kNetParams), q = max(e / kNetParams, e % kNetParams);
+    double s = 0.0;
+    bool ok = true;
+    for (int d = 0; d < n_det; ++d) {
+        const int64_t r = static_cast<int64_t>(d) * n + i;
+        ok = ok && status_d[r] == 0;
+        const double* J = jac + r * kNetJac;
+        const double* Fd = F_d + r * 49;
+        int ra[3], rb[3];
+        double va[3], vb[3];
+        const int na = jac_col(p, J, ra, va), nb = jac_col(q, J, rb, vb);
+        for (int a = 0; a < na; ++a)
+            for (int b = 0; b < nb; ++b) s += va[a] * Fd[ra[a] * 7 + rb[b]] * vb[b];
+    }
+    F[i * kNetParams * kNetParams + e] = ok ? s : __builtin_nan("");
+    if (status && e == 0) status[i] = ok ? PD_OK : PD_EDOMAIN;
+}
+
 inline unsigned nblk(int64_t threads, int per) { return static_cast<unsigned>((threads + per - 1) / per); }
 
 }  // namespace
@@ -157,6 +203,13 @@ hipError_t launch_net_combine(int64_t n, int n_det, const double* lnl_d, const d
                               const double* jac, double* lnl, double* grad, int32_t* status, hipStream_t s) {
     hipLaunchKernelGGL(k_net_combine, dim3(nblk(n, 128)), dim3(128), 0, s, n, n_det, lnl_d, grad_d, status_d, jac, lnl,
                        grad, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_fisher_combine(int64_t n, int n_det, const double* F_d, const int32_t* status_d, const double* jac,
+                                     double* F, int32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_net_fisher_combine, dim3(nblk(n * kNetParams * kNetParams, 128)), dim3(128), 0, s, n, n_det,
+                       F_d, status_d, jac, F, status);
     return hipGetLastError();
 }
 

@@ -107,3 +107,43 @@ def test_network_full_size_sampled(gpu, lam0):
     rng = np.random.default_rng(7)
     rows = sorted({0, th.shape[0] - 1} | set(int(i) for i in rng.choice(th.shape[0], 2, replace=False)))
     _check_rows(rows, th, lnl, grad, lam0, g, cfg["geometry"], cfg["data"], cfg["inv_psd"], cfg["gmst"])
+
+
+def _fisher_rows(rows, th, F, lam, g, dets, ip, gmst):
+    for i in rows:
+        ref = N.fisher(th[i], P, lam, g, dets, ip, gmst)
+        scale = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+        assert np.all(np.abs(F[i] - ref) <= 1e-9 * scale), (i, np.max(np.abs(F[i] - ref) / scale))
+        assert np.array_equal(F[i], F[i].T)
+
+
+def test_network_fisher_parity_three_sites(gpu, lam0):
+    import torch
+    grid = W.Grid(20.0, 0.25, 4001, 20.0, 20.0)
+    g = grid.as_tuple()
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    ip = np.stack([1 / psd] * 3)
+    th = W.network_sources(8, 73)
+    _say("network Fisher 3 sites n=8 nb=4001")
+    F, st = gpu.api.network_fisher(th, P, grid, lam0, DETS, 0.4, ip)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    _fisher_rows(range(8), th, F.cpu().numpy(), lam0, g, DETS, ip, 0.4)
+
+
+def test_network_fisher_full_c3_sampled(gpu, lam0):
+    """The network Fisher workload of the benchmark (16384 points x 16065 bins x 3 sites, one call)
+    on sampled points against the oracle."""
+    import torch
+    cfg = W.network_config(n=16384, n_bins=16065, df=0.0625)
+    g = cfg["grid"].as_tuple()
+    th = cfg["theta"]
+    _say(f"network Fisher full n={th.shape[0]} nb={g[2]} sites={len(cfg['dets'])}")
+    F, st = gpu.api.network_fisher(th, P, cfg["grid"], lam0, cfg["geometry"], cfg["gmst"], cfg["inv_psd"])
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    F = F.cpu().numpy()
+    assert np.all(np.isfinite(F))
+    rng = np.random.default_rng(8)
+    rows = sorted({0, th.shape[0] - 1} | set(int(i) for i in rng.choice(th.shape[0], 2, replace=False)))
+    _fisher_rows(rows, th, F, lam0, g, cfg["geometry"], cfg["inv_psd"], cfg["gmst"])
