@@ -364,6 +364,13 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     for key, mode in (("C5_flow_mh_vs_hmc", "bf16"), ("C5_flow_mh_vs_hmc_fp32_flow", "fp32")):
         extra[key] = c5_summary(LP.compare(lam, n_chains=4096, log=log, flow_mode=mode))
 
+    # the paper's two-detector posterior (H1, L1, orientation fixed), HMC on 4096 chains x 8033 bins
+    log("[bench] C5 two-site HMC")
+    r2 = LP.two_site_hmc(lam, log=log)
+    extra["C5_two_site_hmc"] = {k: r2[k] for k in ("ms_per_step", "acceptance", "min_ess_per_s_tau", "steps",
+                                                    "n_leapfrog", "n_chains", "sites", "n_bins")}
+    extra["C5_two_site_hmc"]["tau_steps"] = dict(zip(LP.NAMES, np.round(r2["tau_steps"], 1).tolist()))
+
     # random-walk baseline, C5: HMC 300 steps against 2250 random-walk steps from the same states
     from paper_2302_05329_amd import rwmh_baseline as RB
     log("[bench] C5 HMC vs random-walk MH")

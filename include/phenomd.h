@@ -192,6 +192,16 @@ int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const
                                 const double* data, const double* inv_psd, double* lnl, double* grad,
                                 int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
 
+size_t pd_network_strain_workspace_bytes(int64_t n, int64_t n_bins);
+
+/* Strain recorded at one site, h_d(f) = (F+ h+ + Fx hx) exp(-2 pi i f dt) (the response above),
+ * for n rows theta [n][11]; h_out [n][n_bins][2] complex128 (zeros on inactive bins); status [n]
+ * or NULL.  Computed as pd_waveform_eval at the site's effective parameters.
+ * Workspace: pd_network_strain_workspace_bytes(n, n_bins), 256-byte aligned. */
+int pd_network_strain(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                      const pd_detector* detector, double gmst, double* h_out, int32_t* status, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
 size_t pd_network_fisher_workspace_bytes(int64_t n, int64_t n_bins, int n_det);
 
 /* Network Fisher matrix over the same 11 parameters (Eq. 8 summed over sites):
@@ -240,22 +250,31 @@ int pd_profile_read(int kernel, double* total_ms, int64_t* launches);
  *                    (hi_i - lo_i) sigmoid(x_i) for i < 6 (uniform priors) and phic = x_6;
  *                    log pi(x) = lnL(theta(x)) + log |d theta / d x|, lnL as in
  *                    pd_loglike_and_grad (FP64).
+ *   PD_TARGET_GW_NETWORK  as PD_TARGET_GW with lnL the network likelihood of
+ *                    pd_network_loglike_and_grad over n_det sites, the orientation and sky
+ *                    position (iota, psi, ra, dec) held at `orient` (the two-detector
+ *                    injection of Sec. 3.3 fixes them); data [n_det][n_bins][2] and
+ *                    inv_psd [n_det][n_bins].
  *   PD_TARGET_GAUSS  log pi(x) = -1/2 sum_j (x_j - mu_j)^2 isig2_j (tests the samplers
  *                    against a known answer).
  * Random numbers are inputs: every call is a deterministic function of its arguments.
  * ------------------------------------------------------------------------------------- */
-typedef enum { PD_TARGET_GW = 0, PD_TARGET_GAUSS = 1 } pd_target;
+typedef enum { PD_TARGET_GW = 0, PD_TARGET_GAUSS = 1, PD_TARGET_GW_NETWORK = 2 } pd_target;
 
 typedef struct {
     int kind;                 /* pd_target */
     pd_grid grid;             /* GW: frequency grid of data and inv_psd */
     const double* lambda;     /* GW: [209] device */
-    const double* data;       /* GW: [n_bins][2] device */
-    const double* inv_psd;    /* GW: [n_bins] device */
+    const double* data;       /* GW: [n_bins][2] device (GW_NETWORK: [n_det][n_bins][2]) */
+    const double* inv_psd;    /* GW: [n_bins] device (GW_NETWORK: [n_det][n_bins]) */
     double lo[7], hi[7];      /* GW: prior bounds of (Mc, q, chi1, chi2, D, tc, phic); 0 < q <= 1.
                                  The likelihood has period pi in phic, so a phic interval of
                                  length pi is the whole circle. */
     double mu[7], isig2[7];   /* GAUSS: means and inverse variances */
+    int n_det;                /* GW_NETWORK: number of sites, 1..PD_NETWORK_MAX_DETECTORS */
+    pd_detector detectors[PD_NETWORK_MAX_DETECTORS];  /* GW_NETWORK: site geometry */
+    double gmst;              /* GW_NETWORK: Greenwich sidereal angle at the reference time */
+    double orient[4];         /* GW_NETWORK: fixed (iota, psi, ra, dec) */
 } pd_posterior;
 
 size_t pd_posterior_workspace_bytes(const pd_posterior* post, int64_t n);

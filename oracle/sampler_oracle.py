@@ -11,6 +11,8 @@ Sec. 3.3 of the paper samples the 7-parameter posterior with Hamiltonian Monte C
   * HMC (Neal 2011): p = sqrt(m) xi, H = -log pi(x) + p^2/(2m) summed, leapfrog with a half
     kick at each end, accept if log u < -(H_end - H_start); non-finite or |dH| > 1000 is
     rejected as divergent;
+  * the two-detector posterior of the paper's injection: the network likelihood of
+    network_oracle with (iota, psi, ra, dec) held fixed;
   * random-walk Metropolis-Hastings, the baseline Sec. 3.3 compares HMC with (Metropolis et al.
     1953): a Gaussian step x' = x + s xi, accepted with probability min(1, pi(x') / pi(x));
   * independence Metropolis-Hastings with a proposal density q:
@@ -23,6 +25,7 @@ import math
 
 import numpy as np
 
+from . import network_oracle as N
 from . import phenomd_oracle as O
 
 
@@ -55,6 +58,20 @@ def logp_gw(x, lam, grid, data, inv_psd, lo, hi, want_grad=True):
     if not want_grad:
         return lnl + lj, None
     g = O.loglike_grad(theta, O.PARAM_MC_Q, lam, grid, data, inv_psd)
+    return lnl + lj, g * d + dl
+
+
+def logp_gw_network(x, lam, grid, dets, data, inv_psd, lo, hi, gmst, orient, want_grad=True):
+    """The same posterior with the network likelihood over `dets`, the orientation and sky
+    position held at `orient` = (iota, psi, ra, dec)."""
+    theta, d, lj, dl = transform(x, lo, hi)
+    if not O.domain_ok(theta, O.PARAM_MC_Q):
+        return -np.inf, np.zeros(7)
+    th11 = np.concatenate([theta, np.asarray(orient, dtype=np.float64)])
+    lnl = N.loglike(th11, O.PARAM_MC_Q, lam, grid, dets, data, inv_psd, gmst)
+    if not want_grad:
+        return lnl + lj, None
+    g = N.loglike_grad(th11, O.PARAM_MC_Q, lam, grid, dets, data, inv_psd, gmst)[:7]
     return lnl + lj, g * d + dl
 
 

@@ -49,21 +49,24 @@ class PdGrid(ctypes.Structure):
                 ("f_min", ctypes.c_double), ("f_ref", ctypes.c_double)]
 
 
-PD_TARGET_GW = 0
-PD_TARGET_GAUSS = 1
-
-
-class PdPosterior(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("grid", PdGrid), ("lam", ctypes.c_void_p), ("data", ctypes.c_void_p),
-                ("inv_psd", ctypes.c_void_p), ("lo", ctypes.c_double * 7), ("hi", ctypes.c_double * 7),
-                ("mu", ctypes.c_double * 7), ("isig2", ctypes.c_double * 7)]
-
-
 PD_NETWORK_MAX_DETECTORS = 8
 
 
 class PdDetector(ctypes.Structure):
     _fields_ = [("vertex", ctypes.c_double * 3), ("xarm", ctypes.c_double * 3), ("yarm", ctypes.c_double * 3)]
+
+
+PD_TARGET_GW = 0
+PD_TARGET_GAUSS = 1
+PD_TARGET_GW_NETWORK = 2
+
+
+class PdPosterior(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("grid", PdGrid), ("lam", ctypes.c_void_p), ("data", ctypes.c_void_p),
+                ("inv_psd", ctypes.c_void_p), ("lo", ctypes.c_double * 7), ("hi", ctypes.c_double * 7),
+                ("mu", ctypes.c_double * 7), ("isig2", ctypes.c_double * 7), ("n_det", ctypes.c_int),
+                ("detectors", PdDetector * PD_NETWORK_MAX_DETECTORS), ("gmst", ctypes.c_double),
+                ("orient", ctypes.c_double * 4)]
 
 
 class PdError(RuntimeError):
@@ -88,6 +91,9 @@ SIGNATURES = {
     "pd_network_workspace_bytes": (_SZ, [_I64, _I64, _INT]),
     "pd_network_loglike_and_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _INT, ctypes.POINTER(PdDetector), ctypes.c_double,
                                            _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pd_network_strain_workspace_bytes": (_SZ, [_I64, _I64]),
+    "pd_network_strain": (_INT, [_P, _I64, _INT, _GRID, _P, ctypes.POINTER(PdDetector), ctypes.c_double, _P, _P, _P,
+                                 _SZ, _P]),
     "pd_network_fisher_workspace_bytes": (_SZ, [_I64, _I64, _INT]),
     "pd_network_fisher": (_INT, [_P, _I64, _INT, _GRID, _P, _INT, ctypes.POINTER(PdDetector), ctypes.c_double, _P, _P,
                                  _P, _P, _SZ, _P]),

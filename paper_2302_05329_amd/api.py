@@ -9,6 +9,7 @@ import torch
 from . import _lib as L
 
 FP64 = L.PD_FP64
+PD_TARGET_GW_NETWORK = L.PD_TARGET_GW_NETWORK
 MIXED = L.PD_MIXED
 PARAM_MC_ETA = L.PD_PARAM_MC_ETA
 PARAM_LNMC_ETA_LND = L.PD_PARAM_LNMC_ETA_LND
@@ -121,17 +122,29 @@ def _net_args(theta, lam, grid, detectors, inv_psd):
     g = _grid(grid)
     th = _dev(theta)
     lam = _dev(lam)
-    ip = _dev(inv_psd)
+    ip = None if inv_psd is None else _dev(inv_psd)
     nd = len(detectors)
     _need(1 <= nd <= L.PD_NETWORK_MAX_DETECTORS, f"1..{L.PD_NETWORK_MAX_DETECTORS} detectors, got {nd}")
     _need(th.dim() == 2 and th.shape[1] == 11 and th.shape[0] > 0, f"theta must be [n, 11], got {tuple(th.shape)}")
     _need(lam.numel() == 209, f"lambda must hold 209 coefficients, got {lam.numel()}")
-    _need(tuple(ip.shape) == (nd, g.n_bins), f"inv_psd must be [{nd}, {g.n_bins}], got {tuple(ip.shape)}")
+    _need(ip is None or tuple(ip.shape) == (nd, g.n_bins), f"inv_psd must be [{nd}, {g.n_bins}]")
     dets = (L.PdDetector * nd)()
     for k, (v, x, y) in enumerate(detectors):
         for j in range(3):
             dets[k].vertex[j], dets[k].xarm[j], dets[k].yarm[j] = float(v[j]), float(x[j]), float(y[j])
     return g, th, lam, ip, nd, dets
+
+
+def network_strain(theta, param, grid, lam, detector, gmst, ws=None):
+    """Strain recorded at one site: complex128 [n, n_bins] (theta [n, 11])."""
+    ws = ws or _default_ws
+    g, th, lam, _, _, dets = _net_args(theta, lam, grid, [detector], None)
+    n = th.shape[0]
+    h = torch.empty((n, g.n_bins, 2), dtype=torch.float64, device="cuda")
+    wp, wb = ws.get(L.lib().pd_network_strain_workspace_bytes(n, g.n_bins))
+    L.check(L.lib().pd_network_strain(_ptr(th), n, param, ctypes.byref(g), _ptr(lam), dets, float(gmst), _ptr(h), None,
+                                      wp, wb, _stream()))
+    return torch.view_as_complex(h)
 
 
 def network_fisher(theta, param, grid, lam, detectors, gmst, inv_psd, ws=None):

@@ -314,7 +314,7 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, co
     int rc = check_common(theta, n, param, grid, lambda, &g);
     if (rc) return rc;
     if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
-    if (!F) return fail(PD_EINVAL, "F is NULL");
+    if (!F || !inv_psd) return fail(PD_EINVAL, "NULL argument");
     Layout L;
     rc = check_ws(PD_OP_FISHER, n, g.nb, workspace, workspace_bytes, &L);
     if (rc) return rc;
@@ -427,11 +427,11 @@ size_t pd_network_workspace_bytes(int64_t n, int64_t n_bins, int n_det) {
 namespace {
 
 int net_check(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda, int n_det,
-              const pd_detector* detectors, double gmst, const double* inv_psd, pd::GridArgs* g, pd::NetArgs* na) {
+              const pd_detector* detectors, double gmst, pd::GridArgs* g, pd::NetArgs* na) {
     int rc = check_common(theta, n, param, grid, lambda, g);
     if (rc) return rc;
     if (n_det < 1 || n_det > PD_NETWORK_MAX_DETECTORS) return fail(PD_EINVAL, "n_det out of range");
-    if (!detectors || !inv_psd) return fail(PD_EINVAL, "NULL argument");
+    if (!detectors) return fail(PD_EINVAL, "detectors is NULL");
     if (!std::isfinite(gmst)) return fail(PD_EINVAL, "gmst must be finite");
     na->n_det = n_det;
     na->gmst = gmst;
@@ -457,9 +457,9 @@ int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const
                                 size_t workspace_bytes, void* stream) {
     pd::GridArgs g;
     pd::NetArgs na;
-    int rc = net_check(theta, n, param, grid, lambda, n_det, detectors, gmst, inv_psd, &g, &na);
+    int rc = net_check(theta, n, param, grid, lambda, n_det, detectors, gmst, &g, &na);
     if (rc) return rc;
-    if (!data || !lnl) return fail(PD_EINVAL, "NULL argument");
+    if (!data || !inv_psd || !lnl) return fail(PD_EINVAL, "NULL argument");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
     const NetLayout L = net_layout(n, g.nb, n_det);
     if (workspace_bytes < L.total) return fail(PD_ENOMEM, "workspace too small (see pd_network_workspace_bytes)");
@@ -485,6 +485,30 @@ int pd_network_loglike_and_grad(const double* theta, int64_t n, int param, const
     return PD_OK;
 }
 
+size_t pd_network_strain_workspace_bytes(int64_t n, int64_t n_bins) {
+    if (n <= 0 || n_bins <= 0) return 0;
+    return net_layout(n, n_bins, 1, PD_OP_WAVEFORM).total;
+}
+
+int pd_network_strain(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
+                      const pd_detector* detector, double gmst, double* h_out, int32_t* status, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+    pd::GridArgs g;
+    pd::NetArgs na;
+    int rc = net_check(theta, n, param, grid, lambda, 1, detector, gmst, &g, &na);
+    if (rc) return rc;
+    if (!h_out) return fail(PD_EINVAL, "h_out is NULL");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    const NetLayout L = net_layout(n, g.nb, 1, PD_OP_WAVEFORM);
+    if (workspace_bytes < L.total) return fail(PD_ENOMEM, "workspace too small (see pd_network_strain_workspace_bytes)");
+    double* eff = at<double>(workspace, L.eff);
+    hipError_t e = pd::launch_net_setup(theta, n, param, na, eff, at<double>(workspace, L.jac),
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "network setup");
+    return pd_waveform_eval(eff, n, param, grid, lambda, PD_FP64, h_out, status, workspace,
+                            layout_for(PD_OP_WAVEFORM, n, g.nb).total, stream);
+}
+
 size_t pd_network_fisher_workspace_bytes(int64_t n, int64_t n_bins, int n_det) {
     if (n <= 0 || n_bins <= 0 || n_det < 1 || n_det > PD_NETWORK_MAX_DETECTORS) return 0;
     return net_layout(n, n_bins, n_det, PD_OP_FISHER).total;
@@ -495,7 +519,7 @@ int pd_network_fisher(const double* theta, int64_t n, int param, const pd_grid* 
                       void* workspace, size_t workspace_bytes, void* stream) {
     pd::GridArgs g;
     pd::NetArgs na;
-    int rc = net_check(theta, n, param, grid, lambda, n_det, detectors, gmst, inv_psd, &g, &na);
+    int rc = net_check(theta, n, param, grid, lambda, n_det, detectors, gmst, &g, &na);
     if (rc) return rc;
     if (!F) return fail(PD_EINVAL, "F is NULL");
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");

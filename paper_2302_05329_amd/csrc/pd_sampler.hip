@@ -3,7 +3,8 @@
 // random-walk Metropolis-Hastings baseline the paper compares it with (Gaussian steps), and
 // the Metropolis-Hastings accept step of an independence proposal (the learned flow).
 //
-// Coordinates.  The sampler moves x in R^7.  For the gravitational-wave target the
+// Coordinates.  The sampler moves x in R^7.  For the gravitational-wave targets (one detector, or
+// a network of sites with the orientation and sky position held fixed) the
 // source parameters are theta = (Mc, q, chi1, chi2, D, tc, phic) with
 //   theta_i = lo_i + (hi_i - lo_i) * sigmoid(x_i)   (bounded uniform priors; for phic an
 //   interval of length pi is one full period of the likelihood),
@@ -37,9 +38,13 @@ struct Drift {
 
 template <bool DRIFT>
 __global__ void k_transform(double* __restrict__ x, int64_t n, pd_posterior post, double* __restrict__ theta,
-                            double* __restrict__ dtdx, double* __restrict__ lj, double* __restrict__ dlj, Drift dr) {
+                            double* __restrict__ dtdx, double* __restrict__ lj, double* __restrict__ dlj, Drift dr,
+                            int ts) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // ts = 11: network rows, the fixed orientation appended after the 7 sampled parameters
+    if (ts == 11)
+        for (int k = 0; k < 4; ++k) theta[i * 11 + 7 + k] = post.orient[k];
     double acc = 0.0;
     for (int j = 0; j < 7; ++j) {
         double xv = x[i * 7 + j];
@@ -49,7 +54,7 @@ __global__ void k_transform(double* __restrict__ x, int64_t n, pd_posterior post
         }
         const double s = sigmoid(xv);
         const double w = post.hi[j] - post.lo[j];
-        theta[i * 7 + j] = post.lo[j] + w * s;
+        theta[i * ts + j] = post.lo[j] + w * s;
         const double d = w * s * (1.0 - s);
         dtdx[i * 7 + j] = d;
         // log(w s (1-s)) = log w - softplus(-x) - softplus(x)
@@ -61,7 +66,7 @@ __global__ void k_transform(double* __restrict__ x, int64_t n, pd_posterior post
 }
 
 // log posterior and its gradient in x; with p given, then the leapfrog kick p += weps grad.
-__global__ void k_assemble(int64_t n, const double* __restrict__ lnl, const double* __restrict__ gth,
+__global__ void k_assemble(int64_t n, const double* __restrict__ lnl, const double* __restrict__ gth, int gs,
                            const double* __restrict__ dtdx, const double* __restrict__ lj,
                            const double* __restrict__ dlj, double* __restrict__ logp, double* __restrict__ grad,
                            double weps, double* __restrict__ p) {
@@ -71,7 +76,7 @@ __global__ void k_assemble(int64_t n, const double* __restrict__ lnl, const doub
     logp[i] = ok ? lnl[i] + lj[i] : -INFINITY;
     if (grad) {
         for (int j = 0; j < 7; ++j) {
-            const double gj = ok ? fma(gth[i * 7 + j], dtdx[i * 7 + j], dlj[i * 7 + j]) : 0.0;
+            const double gj = ok ? fma(gth[i * gs + j], dtdx[i * 7 + j], dlj[i * 7 + j]) : 0.0;
             grad[i * 7 + j] = gj;
             if (p) p[i * 7 + j] = fma(weps, gj, p[i * 7 + j]);
         }
@@ -211,26 +216,36 @@ struct PostWs {
     size_t ll_bytes;
 };
 
+// parameter-row width: 11 for the network target (orientation appended), else 7
+inline int row_width(const pd_posterior* post) { return post->kind == PD_TARGET_GW_NETWORK ? 11 : 7; }
+
+size_t likelihood_ws_bytes(const pd_posterior* post, int64_t n) {
+    if (post->kind == PD_TARGET_GW) return pd_workspace_bytes(PD_OP_LOGLIKE_GRAD, n, post->grid.n_bins);
+    if (post->kind == PD_TARGET_GW_NETWORK) return pd_network_workspace_bytes(n, post->grid.n_bins, post->n_det);
+    return 0;
+}
+
 size_t post_ws_bytes(const pd_posterior* post, int64_t n) {
     const size_t N = static_cast<size_t>(n);
+    const size_t R = static_cast<size_t>(row_width(post));
     size_t off = 0;
-    off = al(off + N * 7 * 8) ;
+    off = al(off + N * R * 8);
     off = al(off + N * 7 * 8);
     off = al(off + N * 7 * 8);
     off = al(off + N * 8);
     off = al(off + N * 8);
-    off = al(off + N * 7 * 8);
-    if (post->kind == PD_TARGET_GW) off = al(off + pd_workspace_bytes(PD_OP_LOGLIKE_GRAD, n, post->grid.n_bins));
-    return off;
+    off = al(off + N * R * 8);
+    return al(off + likelihood_ws_bytes(post, n));
 }
 
 PostWs post_ws(const pd_posterior* post, int64_t n, void* base) {
     const size_t N = static_cast<size_t>(n);
+    const size_t R = static_cast<size_t>(row_width(post));
     char* p = static_cast<char*>(base);
     size_t off = 0;
     PostWs w;
     w.theta = reinterpret_cast<double*>(p + off);
-    off = al(off + N * 7 * 8);
+    off = al(off + N * R * 8);
     w.dtdx = reinterpret_cast<double*>(p + off);
     off = al(off + N * 7 * 8);
     w.dlj = reinterpret_cast<double*>(p + off);
@@ -240,9 +255,9 @@ PostWs post_ws(const pd_posterior* post, int64_t n, void* base) {
     w.lnl = reinterpret_cast<double*>(p + off);
     off = al(off + N * 8);
     w.gth = reinterpret_cast<double*>(p + off);
-    off = al(off + N * 7 * 8);
+    off = al(off + N * R * 8);
     w.ll = p + off;
-    w.ll_bytes = (post->kind == PD_TARGET_GW) ? pd_workspace_bytes(PD_OP_LOGLIKE_GRAD, n, post->grid.n_bins) : 0;
+    w.ll_bytes = likelihood_ws_bytes(post, n);
     return w;
 }
 
@@ -292,8 +307,19 @@ size_t rw_ws_bytes(const pd_posterior* post, int64_t n) {
 
 int posterior_check(const pd_posterior* post) {
     if (!post) return PD_EINVAL;
-    if (post->kind != PD_TARGET_GW && post->kind != PD_TARGET_GAUSS) return PD_EINVAL;
-    if (post->kind == PD_TARGET_GW) {
+    if (post->kind != PD_TARGET_GW && post->kind != PD_TARGET_GAUSS && post->kind != PD_TARGET_GW_NETWORK)
+        return PD_EINVAL;
+    if (post->kind == PD_TARGET_GW_NETWORK) {
+        if (post->n_det < 1 || post->n_det > PD_NETWORK_MAX_DETECTORS || !std::isfinite(post->gmst)) return PD_EINVAL;
+        for (int d = 0; d < post->n_det; ++d)
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(post->detectors[d].vertex[k]) || !std::isfinite(post->detectors[d].xarm[k]) ||
+                    !std::isfinite(post->detectors[d].yarm[k]))
+                    return PD_EINVAL;
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(post->orient[k])) return PD_EINVAL;
+    }
+    if (post->kind != PD_TARGET_GAUSS) {
         if (!post->lambda || !post->data || !post->inv_psd) return PD_EINVAL;
         for (int j = 0; j < 7; ++j)
             if (!(post->hi[j] > post->lo[j]) || !std::isfinite(post->hi[j] - post->lo[j])) return PD_EINVAL;
@@ -313,18 +339,24 @@ int posterior_check(const pd_posterior* post) {
 int posterior_logp_step(const pd_posterior* post, double* x, int64_t n, double* logp, double* grad, void* ws,
                         hipStream_t s, bool tables_ready, const Drift* drift, double kick_weps, double* kick_p) {
     PostWs w = post_ws(post, n, ws);
+    const int ts = row_width(post);
     if (drift)
         hipLaunchKernelGGL(k_transform<true>, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx, w.lj,
-                           w.dlj, *drift);
+                           w.dlj, *drift, ts);
     else
         hipLaunchKernelGGL(k_transform<false>, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx,
-                           w.lj, w.dlj, Drift{});
+                           w.lj, w.dlj, Drift{}, ts);
     if (hipGetLastError() != hipSuccess) return PD_EHIP;
-    const int rc = loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data,
-                                    post->inv_psd, PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes,
-                                    s, tables_ready);
+    int rc;
+    if (post->kind == PD_TARGET_GW_NETWORK)
+        rc = pd_network_loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->n_det,
+                                         post->detectors, post->gmst, post->data, post->inv_psd, w.lnl,
+                                         grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes, s);
+    else
+        rc = loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data, post->inv_psd,
+                              PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes, s, tables_ready);
     if (rc != PD_OK) return rc;
-    hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 128)), dim3(128), 0, s, n, w.lnl, w.gth, w.dtdx, w.lj, w.dlj,
+    hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 128)), dim3(128), 0, s, n, w.lnl, w.gth, ts, w.dtdx, w.lj, w.dlj,
                        logp, grad, kick_weps, kick_p);
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
 }
@@ -360,9 +392,10 @@ int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, doubl
     dr.p = w.p;
     for (int l = 0; l < n_leapfrog; ++l) {
         const double weps = (l + 1 < n_leapfrog) ? eps : 0.5 * eps;
-        if (post->kind == PD_TARGET_GW) {
+        if (post->kind != PD_TARGET_GAUSS) {
             // drift fused into the coordinate transform, kick into the posterior assembly; the grid
-            // tables depend only on the data and noise and are computed by the first step
+            // tables depend only on the data and noise and are computed by the first step (the
+            // network target recomputes them per site)
             const int rc = posterior_logp_step(post, w.x1, n, w.logp1, w.grad1, w.post, s, l > 0, &dr, weps, w.p);
             if (rc != PD_OK) return rc;
         } else {

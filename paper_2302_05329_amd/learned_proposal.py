@@ -41,6 +41,40 @@ def gw_problem(lam, snr=20.0, n_bins=None):
     return dict(post=post, theta_inj=theta, grid=grid, lo=lo, hi=hi, d_inj=inj[4], inv_psd=inv_psd, lam=lam)
 
 
+def gw_network_problem(lam, snr=20.0, dets=("H1", "L1"), orient=None, gmst=1.234, n_bins=None):
+    """The paper's two-detector version of the injection (Sec. 3.3): the same source seen by the
+    LIGO sites with inclination, polarisation and sky position fixed (each pi/3, as in the paper),
+    the distance set for network SNR `snr`, independent noise per site.  Built on the GPU."""
+    cfg = W.config5()
+    grid = cfg["grid"] if n_bins is None else W.Grid(cfg["grid"].f0, cfg["grid"].df, n_bins, cfg["grid"].f_min,
+                                                     cfg["grid"].f_ref)
+    orient = np.full(4, math.pi / 3) if orient is None else np.asarray(orient, dtype=np.float64)
+    geo = [W.DETECTORS[d] for d in dets]
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    inv_psd = torch.as_tensor(np.stack([1.0 / psd] * len(dets)), device="cuda")
+    inj = cfg["inj_unit_distance"].copy()
+    th11 = np.concatenate([inj, orient])[None]
+    zero = torch.zeros((len(dets), grid.n_bins), dtype=torch.complex128, device="cuda")
+    lnl, _, _ = api.network_loglike_and_grad(th11, api.PARAM_M1M2, grid, lam, geo, gmst, zero, inv_psd,
+                                             want_grad=False)
+    inj[4] = math.sqrt(-2.0 * float(lnl[0])) / snr
+    th11 = np.concatenate([inj, orient])[None]
+    # each site's noise-free strain is the model at the site's effective parameters
+    # (the network call with zero data gives -(h|h)/2 only, so the strains are built per site)
+    data = []
+    for k, det in enumerate(geo):
+        h = api.network_strain(th11, api.PARAM_M1M2, grid, lam, det, gmst)
+        data.append(torch.as_tensor(W.complex_noise(psd, grid.df, 1105 + k), device="cuda") + h[0])
+    data = torch.stack(data)
+    theta = W.to_param(inj[None], api.PARAM_MC_Q)[0]
+    lo = np.array([20.0, 0.125, -0.9, -0.9, 0.2 * inj[4], -0.1, -0.5 * math.pi])
+    hi = np.array([40.0, 1.0, 0.9, 0.9, 3.0 * inj[4], 0.1, 0.5 * math.pi])
+    post = sampling.Posterior(api.PD_TARGET_GW_NETWORK, grid=grid, lam=lam, data=data, inv_psd=inv_psd, lo=lo, hi=hi,
+                              detectors=geo, gmst=gmst, orient=orient)
+    return dict(post=post, theta_inj=theta, grid=grid, lo=lo, hi=hi, d_inj=inj[4], inv_psd=inv_psd, lam=lam,
+                geometry=geo, gmst=gmst, orient=orient)
+
+
 def fisher_ball(pb, n, rng, prior_precision=0.3):
     """Starting states: x ~ N(x_inj, (J F J + c I)^-1) in the unconstrained coordinates, with F
     the library's Fisher matrix at the injection, J = d theta / d x, and c a weak precision that
@@ -48,8 +82,14 @@ def fisher_ball(pb, n, rng, prior_precision=0.3):
     states and the inverse of the ball's marginal variances (a first mass matrix)."""
     post = pb["post"]
     th0 = pb["theta_inj"]
-    F, st = api.fisher(th0[None], api.PARAM_MC_Q, pb["grid"], pb["lam"], pb["inv_psd"])
-    F = F[0].cpu().numpy()
+    if "geometry" in pb:
+        # the sampled 7 parameters' block of the network Fisher matrix (orientation fixed)
+        F, st = api.network_fisher(np.r_[th0, pb["orient"]][None], api.PARAM_MC_Q, pb["grid"], pb["lam"],
+                                   pb["geometry"], pb["gmst"], pb["inv_psd"])
+        F = F[0, :7, :7].cpu().numpy()
+    else:
+        F, st = api.fisher(th0[None], api.PARAM_MC_Q, pb["grid"], pb["lam"], pb["inv_psd"])
+        F = F[0].cpu().numpy()
     s = (th0 - pb["lo"]) / (pb["hi"] - pb["lo"])
     J = (pb["hi"] - pb["lo"]) * s * (1.0 - s)
     Fx = J[:, None] * F * J[None, :] + prior_precision * np.eye(7)
@@ -217,3 +257,25 @@ def compare(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, rounds=6, pe
                       acceptance_hmc=acc_bh, acceptance_flow=acc_bm, training_phase_seconds=t_train),
         mean_diff_sigma=(np.abs(ma - mb) / sa).tolist(), std_diff_sigma=(np.abs(sa - sb) / sa).tolist(),
         theta_inj=th0.tolist(), mean=ma.tolist(), std=sa.tolist())
+
+
+def two_site_hmc(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, seed=1105, log=None):
+    """HMC on the paper's two-detector posterior (H1 and L1, orientation and sky position fixed):
+    warm-up as for the one-detector workload, then `steps` transitions from the warmed-up states.
+    Returns time per transition, acceptance, the bulk ESS (chain-count floor for runs this short)
+    and the autocorrelation-time estimate of ESS per second (tau ~ l / (1 - rho(l)), l = 100)."""
+    from . import rwmh_baseline as RB
+    pb = gw_network_problem(lam)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    rng = np.random.default_rng(seed)
+    x0, mass0 = fisher_ball(pb, n_chains, rng)
+    hmc, eps, mass = warmup(pb["post"], x0, gen, steps=warm, n_leapfrog=n_leapfrog, mass0=mass0, log=log)
+    run = sampling.HMC(pb["post"], hmc.x.clone(), eps, n_leapfrog, mass)
+    draws, sec, acc = RB._run(run, gen, steps, 512)
+    ac = RB.mean_autocorr(draws)
+    tau = RB.TAU_LAG / (1.0 - ac[RB.LAGS.index(RB.TAU_LAG)])
+    return dict(n_chains=n_chains, steps=steps, n_leapfrog=n_leapfrog, eps=eps, ms_per_step=1e3 * sec / steps,
+                acceptance=acc, min_bulk_ess_512=min_ess(draws), tau_steps=tau.tolist(),
+                min_ess_per_s_tau=float(np.min(n_chains / tau / (sec / steps))), snr=20.0,
+                n_bins=pb["grid"].n_bins, sites=2)

@@ -14,12 +14,13 @@ from .api import Workspace, _grid, _ptr, _stream
 class Posterior:
     """A pd_posterior description plus the device arrays it points at."""
 
-    def __init__(self, kind, grid=None, lam=None, data=None, inv_psd=None, lo=None, hi=None, mu=None, isig2=None):
+    def __init__(self, kind, grid=None, lam=None, data=None, inv_psd=None, lo=None, hi=None, mu=None, isig2=None,
+                 detectors=None, gmst=0.0, orient=None):
         self.kind = kind
         self._keep = []
         st = L.PdPosterior()
         st.kind = kind
-        if kind == L.PD_TARGET_GW:
+        if kind in (L.PD_TARGET_GW, L.PD_TARGET_GW_NETWORK):
             g = _grid(grid)
             lam = torch.as_tensor(lam, dtype=torch.float64, device="cuda").contiguous()
             d = torch.as_tensor(data, device="cuda")
@@ -27,7 +28,22 @@ class Posterior:
                 d = torch.view_as_real(d.to(torch.complex128))
             d = d.to(torch.float64).contiguous()
             ip = torch.as_tensor(inv_psd, dtype=torch.float64, device="cuda").contiguous()
-            if lam.numel() != 209 or tuple(d.shape) != (g.n_bins, 2) or tuple(ip.shape) != (g.n_bins,):
+            lead = ()
+            if kind == L.PD_TARGET_GW_NETWORK:
+                nd = len(detectors)
+                if not 1 <= nd <= L.PD_NETWORK_MAX_DETECTORS or orient is None or len(orient) != 4:
+                    raise ValueError("network posterior: 1..8 detectors and orient = (iota, psi, ra, dec)")
+                lead = (nd,)
+                st.n_det = nd
+                st.gmst = float(gmst)
+                for k, (v, x, y) in enumerate(detectors):
+                    for j in range(3):
+                        st.detectors[k].vertex[j] = float(v[j])
+                        st.detectors[k].xarm[j] = float(x[j])
+                        st.detectors[k].yarm[j] = float(y[j])
+                for j in range(4):
+                    st.orient[j] = float(orient[j])
+            if lam.numel() != 209 or tuple(d.shape) != lead + (g.n_bins, 2) or tuple(ip.shape) != lead + (g.n_bins,):
                 raise ValueError("posterior arrays do not match the grid")
             self._keep += [lam, d, ip]
             st.grid = g

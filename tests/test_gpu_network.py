@@ -147,3 +147,19 @@ def test_network_fisher_full_c3_sampled(gpu, lam0):
     rng = np.random.default_rng(8)
     rows = sorted({0, th.shape[0] - 1} | set(int(i) for i in rng.choice(th.shape[0], 2, replace=False)))
     _fisher_rows(rows, th, F, lam0, g, cfg["geometry"], cfg["inv_psd"], cfg["gmst"])
+
+
+def test_network_strain_parity(gpu, lam0):
+    """The strain one site records against the oracle's (F+ h+ + Fx hx) exp(-2 pi i f dt)."""
+    import torch
+    grid = W.Grid(20.0, 0.125, 8033, 20.0, 20.0)
+    g = grid.as_tuple()
+    th = W.network_sources(16, 74)
+    _say("network strain 3 sites n=16 nb=8033")
+    for det in DETS:
+        h = gpu.api.network_strain(th, P, grid, lam0, det, 0.9)
+        torch.cuda.synchronize()
+        h = h.cpu().numpy()
+        for i in range(0, 16, 3):
+            ref = N.strain(th[i], P, lam0, g, det, 0.9)
+            assert np.max(np.abs(h[i] - ref)) <= 1e-10 * np.max(np.abs(ref)), i

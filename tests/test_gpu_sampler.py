@@ -231,6 +231,112 @@ def test_rwmh_on_gaussian_target_gpu(gpu):
     assert int((a == 1).sum()) == n and torch.equal(rw.x, x1)
 
 
+def _two_site_problem(lam, n_bins, seed=1105):
+    """The two-detector injection (H1, L1; iota = psi = ra = dec = pi/3), built with the oracle."""
+    from oracle import network_oracle as N
+    cfg = W.config5()
+    grid = W.Grid(20.0, 0.125, n_bins)
+    g = grid.as_tuple()
+    dets = [W.DETECTORS["H1"], W.DETECTORS["L1"]]
+    orient = np.full(4, math.pi / 3)
+    gmst = 1.234
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    inj = cfg["inj_unit_distance"].copy()
+    inj[4] = 500.0
+    data = np.stack([W.complex_noise(psd, grid.df, seed + k) + N.strain(np.r_[inj, orient], O.PARAM_M1M2, lam, g, d,
+                                                                          gmst) for k, d in enumerate(dets)])
+    mc_q = W.to_param(inj[None, :], O.PARAM_MC_Q)[0]
+    lo = np.array([20.0, 0.125, -0.9, -0.9, 100.0, -0.1, -0.5 * math.pi])
+    hi = np.array([40.0, 1.0, 0.9, 0.9, 1500.0, 0.1, 0.5 * math.pi])
+    return dict(grid=grid, data=data, inv_psd=np.stack([1 / psd] * 2), lo=lo, hi=hi, theta_inj=mc_q, dets=dets,
+                orient=orient, gmst=gmst)
+
+
+def _two_site_post(pb, lam):
+    from paper_2302_05329_amd import sampling
+    return sampling.Posterior(2, grid=pb["grid"], lam=lam, data=pb["data"], inv_psd=pb["inv_psd"], lo=pb["lo"],
+                              hi=pb["hi"], detectors=pb["dets"], gmst=pb["gmst"], orient=pb["orient"])
+
+
+def _two_site_lpf(pb, lam):
+    gr = pb["grid"].as_tuple()
+
+    def lpf(x):
+        return S.logp_gw_network(x, lam, gr, pb["dets"], pb["data"], pb["inv_psd"], pb["lo"], pb["hi"], pb["gmst"],
+                                 pb["orient"])
+    return lpf
+
+
+def _two_site_grad_scale(pb, lam, x):
+    """Per coordinate, the Cauchy-Schwarz bound sqrt(sum_d (r_d|r_d) F_pp) on the likelihood term of
+    the gradient (F the network Fisher matrix), times d theta / d x, plus 1."""
+    from oracle import network_oracle as N
+    gr = pb["grid"].as_tuple()
+    th, d, _, _ = S.transform(x, pb["lo"], pb["hi"])
+    th11 = np.r_[th, pb["orient"]]
+    F = N.fisher(th11, O.PARAM_MC_Q, lam, gr, pb["dets"], pb["inv_psd"], pb["gmst"])
+    rr = 0.0
+    for k, det in enumerate(pb["dets"]):
+        r = pb["data"][k] - N.strain(th11, O.PARAM_MC_Q, lam, gr, det, pb["gmst"])
+        rr += O.inner(r, r, pb["inv_psd"][k], gr[1])
+    return np.sqrt(rr * np.diag(F)[:7]) * d + 1.0
+
+
+def test_two_site_posterior_and_hmc_parity(gpu, lam0):
+    """The two-detector posterior (network likelihood, fixed orientation) and one HMC transition
+    against the oracle."""
+    import torch
+    from paper_2302_05329_amd import sampling
+    pb = _two_site_problem(lam0, 4001)
+    post = _two_site_post(pb, lam0)
+    rng = np.random.default_rng(18)
+    x0 = post.to_x(pb["theta_inj"]) + 0.02 * rng.standard_normal((6, 7))
+    _say("two-site posterior logp + HMC step n=6 nb=4001")
+    lp, g = sampling.logp(post, x0)
+    mass = np.array([400.0, 50.0, 20.0, 20.0, 10.0, 4e3, 4.0])
+    eps, L = 0.02, 4
+    xi = rng.standard_normal((6, 7))
+    u = rng.uniform(size=6)
+    hmc = sampling.HMC(post, x0, eps, L, mass)
+    acc = hmc.step(torch.as_tensor(xi, device="cuda"), torch.as_tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    xg, dhg, accg = hmc.x.cpu().numpy(), hmc.dh.cpu().numpy(), acc.cpu().numpy()
+    lpf = _two_site_lpf(pb, lam0)
+    for i in range(6):
+        ref_lp, ref_g = lpf(x0[i])
+        assert abs(lp[i] - ref_lp) <= 1e-10 * max(1.0, abs(ref_lp) / 1e3), (i, lp[i], ref_lp)
+        assert np.all(np.abs(g[i] - ref_g) <= 1e-9 * _two_site_grad_scale(pb, lam0, x0[i])), (i, g[i], ref_g)
+    for i in range(2):
+        lp0, g0 = lpf(x0[i])
+        xr, _, _, ar, dhr = S.hmc_step(lpf, x0[i], lp0, g0, xi[i], u[i], L, eps, mass)
+        assert abs(dhg[i] - dhr) <= 1e-8 * max(1.0, abs(dhr)), (i, dhg[i], dhr)
+        if abs(-dhr - math.log(u[i])) > 1e-6:
+            assert accg[i] == ar
+            assert np.max(np.abs(xg[i] - xr)) <= 1e-9 * (1 + np.max(np.abs(xr)))
+
+
+def test_two_site_posterior_full_c5_sampled(gpu, lam0):
+    """The two-detector posterior at the learned-proposal workload's size (4096 chains x 8033 bins x
+    2 sites, one call) on sampled chains against the oracle."""
+    import torch
+    from paper_2302_05329_amd import sampling
+    pb = _two_site_problem(lam0, 8033)
+    post = _two_site_post(pb, lam0)
+    n = 4096
+    rng = np.random.default_rng(19)
+    x0 = post.to_x(pb["theta_inj"]) + 0.02 * rng.standard_normal((n, 7))
+    _say(f"two-site posterior logp n={n} nb=8033")
+    lp, g = sampling.logp(post, x0)
+    torch.cuda.synchronize()
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    lpf = _two_site_lpf(pb, lam0)
+    for i in sorted({0, n - 1} | set(int(k) for k in rng.choice(n, 2, replace=False))):
+        ref_lp, ref_g = lpf(x0[i])
+        assert abs(lp[i] - ref_lp) <= 1e-10 * max(1.0, abs(ref_lp) / 1e3), (i, lp[i], ref_lp)
+        assert np.all(np.abs(g[i] - ref_g) <= 1e-9 * _two_site_grad_scale(pb, lam0, x0[i])), (i, g[i], ref_g)
+
+
 def test_hmc_recovers_gaussian_target_on_gpu(gpu):
     import torch
     from paper_2302_05329_amd import sampling

@@ -211,3 +211,23 @@ def test_ensemble_autocorr_of_ar1():
     ac = RB.mean_autocorr(x)
     for k, lag in enumerate(RB.LAGS):
         assert np.all(np.abs(ac[k] - rho**lag) < 0.02), (lag, ac[k])
+
+
+def test_network_posterior_with_one_optimal_site_is_the_single_detector_posterior(lam0):
+    """One site at the geocentre with the source overhead, face-on, F+ = 1 (fixed orientation):
+    the network posterior and its gradient are the single-detector ones."""
+    from paper_2302_05329_amd import workloads as W
+    det = ((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0))
+    grid = W.Grid(20.0, 0.25, 1001, 20.0, 20.0)
+    g = grid.as_tuple()
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    data = W.complex_noise(psd, grid.df, 3)
+    lo = np.array([10.0, 0.2, -0.9, -0.9, 100.0, -0.1, -1.6])
+    hi = np.array([40.0, 1.0, 0.9, 0.9, 900.0, 0.1, 1.6])
+    a = 0.8
+    orient = (0.0, math.pi / 2 - a, a, math.pi / 2)
+    x = np.array([0.1, -0.2, 0.3, 0.0, 0.5, -0.1, 0.2])
+    lp1, g1 = S.logp_gw(x, lam0, g, data, 1 / psd, lo, hi)
+    lpn, gn = S.logp_gw_network(x, lam0, g, [det], data[None], (1 / psd)[None], lo, hi, 0.0, orient)
+    assert lpn == pytest.approx(lp1, rel=1e-12)
+    assert np.allclose(gn, g1, rtol=1e-9, atol=1e-9 * np.max(np.abs(g1)))
