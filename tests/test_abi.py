@@ -135,3 +135,27 @@ def test_fit_lambda_step_rejects_bad_arguments(lib, bad):
                                 vp(dsum) if dsum else None, vp(2048), 1 << 40, None)
     assert rc == L.PD_EINVAL
     assert len(lib.pd_last_error()) > 0
+
+
+def test_network_posterior_validation(lib):
+    """A network posterior needs 1..8 sites and finite geometry, sidereal angle and orientation;
+    its workspace holds the network likelihood's."""
+    st = L.PdPosterior()
+    st.kind = L.PD_TARGET_GW_NETWORK
+    st.grid = L.make_grid(20.0, 0.25, 100, 20.0, 20.0)
+    st.lam, st.data, st.inv_psd = 256, 512, 768
+    for j, (lo, hi) in enumerate([(20, 40), (0.125, 1), (-0.9, 0.9), (-0.9, 0.9), (100, 900), (-0.1, 0.1), (-1.6, 1.6)]):
+        st.lo[j], st.hi[j] = lo, hi
+    st.n_det = 2
+    for k in range(2):
+        st.detectors[k].xarm[0], st.detectors[k].yarm[1] = 1.0, 1.0
+    need = lib.pd_posterior_workspace_bytes(ctypes.byref(st), 10)
+    assert need >= lib.pd_network_workspace_bytes(10, 100, 2)
+    assert lib.pd_hmc_workspace_bytes(ctypes.byref(st), 10) > need
+    for field, bad in (("n_det", 0), ("n_det", 9), ("gmst", float("nan"))):
+        old = getattr(st, field)
+        setattr(st, field, bad)
+        assert lib.pd_posterior_workspace_bytes(ctypes.byref(st), 10) == 0
+        setattr(st, field, old)
+    st.orient[2] = float("inf")
+    assert lib.pd_posterior_workspace_bytes(ctypes.byref(st), 10) == 0
