@@ -370,6 +370,9 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     extra["C5_two_site_hmc"] = {k: r2[k] for k in ("ms_per_step", "acceptance", "min_ess_per_s_tau", "steps",
                                                     "n_leapfrog", "n_chains", "sites", "n_bins")}
     extra["C5_two_site_hmc"]["tau_steps"] = dict(zip(LP.NAMES, np.round(r2["tau_steps"], 1).tolist()))
+    log("[bench] C5 two-site flow-MH vs HMC")
+    extra["C5_two_site_flow_mh_vs_hmc"] = c5_summary(LP.compare(lam, n_chains=4096, log=log, flow_mode="bf16",
+                                                                two_site=True))
 
     # random-walk baseline, C5: HMC 300 steps against 2250 random-walk steps from the same states
     from paper_2302_05329_amd import rwmh_baseline as RB

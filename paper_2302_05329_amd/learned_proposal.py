@@ -222,14 +222,14 @@ def min_ess(draws):
 
 
 def compare(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, rounds=6, per_round=50, seed=1005,
-            n_bins=None, log=None, flow_mode="bf16"):
+            n_bins=None, log=None, flow_mode="bf16", two_site=False):
     """The full comparison; returns a dict of rates, acceptance and moment agreement.
 
     Chains start in a Fisher-scaled ball around the injection and are warmed up by HMC (mass
     matrix and step size adapted); a training phase then refits the flow on the chains' states while
     flow MH helps them mix.  Production starts both samplers from the same states at the end
     of that phase, with the flow frozen, so both are exact MCMC from the same start."""
-    pb = gw_problem(lam, n_bins=n_bins)
+    pb = gw_network_problem(lam, n_bins=n_bins) if two_site else gw_problem(lam, n_bins=n_bins)
     post = pb["post"]
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
