@@ -287,6 +287,32 @@ class LogLike(torch.autograd.Function):
         return g_out[:, None] * grad, None, None, None, None, None
 
 
+class Mismatch(torch.autograd.Function):
+    """Mismatch of each target [nt] as a function of the 209 coefficients lambda (Sec. 3.1).
+
+    forward evaluates the mismatches only; backward recomputes them with the adjoint pass, which
+    returns the gradient summed over targets.  The incoming gradient must therefore weight every
+    target equally (as the mean or the sum of the mismatches does); other weightings raise.
+    """
+
+    @staticmethod
+    def forward(ctx, lam, theta, param, grid, targets, inv_psd):
+        mm, _, _ = mismatch_grad(theta, param, grid, lam.detach(), targets, inv_psd, want_grad=False)
+        ctx.save_for_backward(lam.detach())
+        ctx.args = (theta, param, grid, targets, inv_psd)
+        return mm
+
+    @staticmethod
+    def backward(ctx, g_out):
+        (lam,) = ctx.saved_tensors
+        theta, param, grid, targets, inv_psd = ctx.args
+        w = g_out.detach()
+        if not bool(torch.all(w == w[0])):
+            raise NotImplementedError("Mismatch.backward: the adjoint sums over targets; weight them equally")
+        _, dsum, _ = mismatch_grad(theta, param, grid, lam, targets, inv_psd, want_grad=True)
+        return w[0] * dsum, None, None, None, None, None
+
+
 def transition_frequencies(theta, param, grid, lam, ws=None):
     """Per point: (M T_sun [s], Mf of the phase join f_RD/2, Mf of the amplitude join f_peak, valid)."""
     ws = ws or _default_ws

@@ -354,3 +354,35 @@ def test_fit_lambda_descent_full_c4(gpu, lam0):
     assert losses[0] == pytest.approx(loss0, rel=1e-12)
     drop = losses[:-1] - losses[1:]
     assert np.all(drop > 0.5 * pred[:-1]) and np.all(drop <= 1.05 * pred[:-1]), (drop / pred[:-1])
+
+
+def test_autograd_wrappers(gpu, lam0):
+    """LogLike returns ln L and, through torch.autograd, the weighted gradient of the same fused call;
+    Mismatch returns the mismatches and, for an equally weighted loss, the adjoint gradient over the
+    coefficients recomputed in its backward."""
+    import torch
+    from paper_2302_05329_amd import api
+    cfg = W.config2(n=16)
+    th = torch.as_tensor(cfg["theta"], device="cuda").requires_grad_(True)
+    _say("autograd LogLike n=16 nb=16225")
+    lnl = api.LogLike.apply(th, P, cfg["grid"], lam0, cfg["data"], cfg["inv_psd"])
+    wts = torch.linspace(0.5, 2.0, 16, dtype=torch.float64, device="cuda")
+    (lnl * wts).sum().backward()
+    ref_l, ref_g, _ = api.loglike_and_grad(cfg["theta"], P, cfg["grid"], lam0, cfg["data"], cfg["inv_psd"])
+    torch.cuda.synchronize()
+    assert torch.equal(lnl.detach(), ref_l)
+    assert torch.equal(th.grad, wts[:, None] * ref_g)
+    c4 = W.config4(n=4)
+    targets = np.stack([O.waveform(t, P, c4["lam_star"], c4["grid"].as_tuple()) for t in c4["theta"]])
+    lam = torch.as_tensor(lam0, device="cuda").requires_grad_(True)
+    _say("autograd Mismatch nt=4 nb=65536")
+    mm = api.Mismatch.apply(lam, c4["theta"], P, c4["grid"], targets, c4["inv_psd"])
+    mm.mean().backward()
+    ref_m, ref_d, _ = api.mismatch_grad(c4["theta"], P, c4["grid"], lam0, targets, c4["inv_psd"])
+    torch.cuda.synchronize()
+    assert torch.equal(mm.detach(), ref_m)
+    assert torch.allclose(lam.grad, ref_d / 4, rtol=1e-14, atol=0)
+    lam.grad = None
+    mm = api.Mismatch.apply(lam, c4["theta"], P, c4["grid"], targets, c4["inv_psd"])
+    with pytest.raises(NotImplementedError):
+        (mm * torch.arange(4, dtype=torch.float64, device="cuda")).sum().backward()
