@@ -192,30 +192,44 @@ __global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __rest
 // strain output
 // ==================================================================================
 
+// One block covers 256 * PT consecutive bins of one point; each thread writes PT bins strided by
+// 256, so every store instruction of a wave is one contiguous 1 KB run.  Large batches take PT = 8
+// (the per-point record loads and branch set-up shared by eight bins: 2.9 -> 4.0 TB/s of strain
+// written at 10^4 points x 79361 bins; 4 and 16 measured 3.5 and 3.9 TB/s); small ones PT = 1,
+// which keeps more blocks in flight.
+template <int PT>
 __global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ recs, int64_t n, int64_t blocks_per_point,
                                                   GridArgs g, const double* __restrict__ tab, double* __restrict__ h) {
+    constexpr int64_t kWfPerThread = PT;
     const int64_t b = blockIdx.x;
     const int64_t p = b / blocks_per_point;
-    const int64_t k = (b % blocks_per_point) * 256 + threadIdx.x;
-    if (p >= n || k >= g.nb) return;
+    if (p >= n) return;
+    const int64_t k0 = (b % blocks_per_point) * (256 * kWfPerThread) + threadIdx.x;
     const double* __restrict__ rec = recs + p * REC_N;
     const Tabs T(tab, g.nb);
-    double2 out = make_double2(0.0, 0.0);
-    if (rec[R_VALID] == 0.0) {
-        out = make_double2(__builtin_nan(""), __builtin_nan(""));
-    } else {
-        const double f = bin_freq(g, k);
-        const double mf = rec[R_MS] * f;
-        if (bin_active(g, f, mf)) {
-            BinVals bv;
-            eval_bin_rt(rec, T, k, mf, bv);
-            const double A = rec[R_A0P] * T.at(T_F76, k) * bv.ahat;
-            double s, c;
-            pd_sincos(bv.psi, &s, &c);
-            out = make_double2(A * c, -A * s);
+    double2* __restrict__ hp = reinterpret_cast<double2*>(h) + p * g.nb;
+    const bool valid = rec[R_VALID] != 0.0;
+#pragma unroll 1
+    for (int j = 0; j < kWfPerThread; ++j) {
+        const int64_t k = k0 + j * 256;
+        if (k >= g.nb) break;
+        double2 out = make_double2(0.0, 0.0);
+        if (!valid) {
+            out = make_double2(__builtin_nan(""), __builtin_nan(""));
+        } else {
+            const double f = bin_freq(g, k);
+            const double mf = rec[R_MS] * f;
+            if (bin_active(g, f, mf)) {
+                BinVals bv;
+                eval_bin_rt(rec, T, k, mf, bv);
+                const double A = rec[R_A0P] * T.at(T_F76, k) * bv.ahat;
+                double s, c;
+                pd_sincos(bv.psi, &s, &c);
+                out = make_double2(A * c, -A * s);
+            }
         }
+        hp[k] = out;
     }
-    reinterpret_cast<double2*>(h)[p * g.nb + k] = out;
 }
 
 // ==================================================================================
@@ -658,9 +672,14 @@ hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStr
 
 hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
                            double* h, hipStream_t s) {
-    const int64_t bpp = (g.nb + 255) / 256;
+    const bool wide = n * g.nb >= (int64_t(1) << 24);
+    const int64_t per_block = wide ? 8 * 256 : 256;
+    const int64_t bpp = (g.nb + per_block - 1) / per_block;
     ProfRange pr(PD_K_WAVEFORM, s);
-    hipLaunchKernelGGL(k_waveform, dim3(static_cast<unsigned>(bpp * n)), dim3(256), 0, s, recs, n, bpp, g, tab, h);
+    if (wide)
+        hipLaunchKernelGGL(k_waveform<8>, dim3(static_cast<unsigned>(bpp * n)), dim3(256), 0, s, recs, n, bpp, g, tab, h);
+    else
+        hipLaunchKernelGGL(k_waveform<1>, dim3(static_cast<unsigned>(bpp * n)), dim3(256), 0, s, recs, n, bpp, g, tab, h);
     (void)precision;
     return hipGetLastError();
 }
