@@ -21,7 +21,9 @@
  *     launches of their per-bin pass, and pd_loglike_and_grad with a gradient also the record
  *     tangents, on side streams (default priority) created once per host thread and device,
  *     forked from and joined back to `stream` with events inside the call; the calls stay
- *     asynchronous and their results are ordered on `stream` as for any other call.
+ *     asynchronous and their results are ordered on `stream` as for any other call.  The calls
+ *     built on them (the network, posterior, HMC, random-walk and coefficient-descent entries)
+ *     inherit this.
  *   - A negative return value is a batch-level error (bad pointer, size, grid or
  *     enum); nothing is launched and pd_last_error() describes it.  Nothing throws.
  *   - Per-point physical-domain errors (non-finite input, masses <= 0, eta outside
