@@ -182,9 +182,9 @@ size_t pd_network_workspace_bytes(int64_t n, int64_t n_bins, int n_det);
  * n_det     1..PD_NETWORK_MAX_DETECTORS;  detectors [n_det] HOST array
  * gmst      Greenwich sidereal angle at the reference time (rad)
  * data      [n_det][n_bins][2]  complex128 data of each site;  inv_psd [n_det][n_bins]
- * lnl [n]; grad [n][11] or NULL (value only); status [n] or NULL (PD_OK / PD_EDOMAIN, NaN
- *           outputs for a point invalid at any site, e.g. a zero response |F+ (1+cos^2 iota)/2
- *           - i Fx cos iota| that makes its effective distance infinite)
+ * lnl [n]; grad [n][11] or NULL (value only); status [n] or NULL (PD_OK / PD_EDOMAIN with NaN
+ *           outputs for a point outside the model's domain).  A site whose response
+ *           F+ (1+cos^2 iota)/2 - i Fx cos iota is exactly zero records no signal and adds nothing.
  * Each site runs one fused pass of pd_loglike_and_grad at the site's effective parameters
  * (D / |c|, tc + dt, phic + arg(c)/2 with c the complex response above), one after another on
  * `stream`.  Workspace: pd_network_workspace_bytes(n, n_bins, n_det), 256-byte aligned.

@@ -87,19 +87,27 @@ __global__ void __launch_bounds__(128) k_net_setup(const double* __restrict__ th
             dci[m + 1] = -dfx[m] * ci;
         }
         const double c2 = cr * cr + cim * cim;
+        double* e = eff + (static_cast<int64_t>(d) * n + i) * 7;
+        double* J = jac + (static_cast<int64_t>(d) * n + i) * kNetJac;
+        for (int k = 0; k < 4; ++k) e[k] = th[k];
+        if (c2 == 0.0) {
+            // a site with no response to this source records no signal: it contributes nothing to
+            // ln L, its gradient or the Fisher matrix (J[0] = 0 marks it; its pass runs on the
+            // unshifted row and is ignored)
+            for (int k = 4; k < 7; ++k) e[k] = th[k];
+            for (int k = 0; k < kNetJac; ++k) J[k] = 0.0;
+            continue;
+        }
         const double ic2 = 1.0 / c2;
         const double lnc = 0.5 * log(c2);
         const double argc = atan2(cim, cr);
         const double dt = -dot3(st.vertex, nv) / kCLight;
         const double dt_a = -dot3(st.vertex, nl) / kCLight, dt_d = -dot3(st.vertex, nd) / kCLight;
-        double* e = eff + (static_cast<int64_t>(d) * n + i) * 7;
-        for (int k = 0; k < 4; ++k) e[k] = th[k];
         const bool lnd = (param == PD_PARAM_LNMC_ETA_LND);
         const double row4 = lnd ? th[4] - lnc : th[4] * exp(-lnc);
         e[4] = row4;
         e[5] = th[5] + dt;
         e[6] = th[6] + 0.5 * argc;
-        double* J = jac + (static_cast<int64_t>(d) * n + i) * kNetJac;
         J[0] = lnd ? 1.0 : exp(-lnc);
         for (int m = 0; m < 4; ++m) {
             const double dlnc = (cr * dcr[m] + cim * dci[m]) * ic2;
@@ -126,11 +134,16 @@ __global__ void __launch_bounds__(128) k_net_combine(int64_t n, int n_det, const
     bool ok = true;
     for (int d = 0; d < n_det; ++d) {
         const int64_t r = static_cast<int64_t>(d) * n + i;
+        const double* J = jac + r * kNetJac;
+        if (J[0] == 0.0) {
+            // a silent site: only the validity of the source itself (its status) matters
+            ok = ok && status_d[r] == 0;
+            continue;
+        }
         ok = ok && status_d[r] == 0;
         s += lnl_d[r];
         if (grad) {
             const double* gd = grad_d + r * 7;
-            const double* J = jac + r * kNetJac;
             for (int p = 0; p < 4; ++p) g[p] += gd[p];
             g[4] += gd[4] * J[0];
             g[5] += gd[5];
@@ -178,6 +191,7 @@ __global__ void __launch_bounds__(128) k_net_fisher_combine(int64_t n, int n_det
         const int64_t r = static_cast<int64_t>(d) * n + i;
         ok = ok && status_d[r] == 0;
         const double* J = jac + r * kNetJac;
+        if (J[0] == 0.0) continue;  // a silent site adds nothing
         const double* Fd = F_d + r * 49;
         int ra[3], rb[3];
         double va[3], vb[3];

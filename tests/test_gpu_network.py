@@ -163,3 +163,28 @@ def test_network_strain_parity(gpu, lam0):
         for i in range(0, 16, 3):
             ref = N.strain(th[i], P, lam0, g, det, 0.9)
             assert np.max(np.abs(h[i] - ref)) <= 1e-10 * np.max(np.abs(ref)), i
+
+
+def test_network_site_without_response_adds_nothing(gpu, lam0):
+    """A site with zero arms has no response: it adds nothing to ln L, the gradient or the Fisher
+    matrix (the oracle's strain for it is identically zero), and the point stays valid."""
+    import torch
+    deaf = ((1.0e6, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    grid = W.Grid(20.0, 0.25, 2001, 20.0, 20.0)
+    g = grid.as_tuple()
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    th = W.network_sources(4, 75)
+    dets = [DETS[0], deaf]
+    data = np.stack([W.complex_noise(psd, grid.df, 95 + k) for k in range(2)])
+    ip = np.stack([1 / psd] * 2)
+    _say("network with a site of zero response n=4")
+    lnl, grad, st = gpu.api.network_loglike_and_grad(th, P, grid, lam0, dets, 0.3, data, ip)
+    l1, g1, _ = gpu.api.network_loglike_and_grad(th, P, grid, lam0, dets[:1], 0.3, data[:1], ip[:1])
+    F, stf = gpu.api.network_fisher(th, P, grid, lam0, dets, 0.3, ip)
+    F1, _ = gpu.api.network_fisher(th, P, grid, lam0, dets[:1], 0.3, ip[:1])
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0) and np.all(stf.cpu().numpy() == 0)
+    assert torch.equal(lnl, l1) and torch.equal(grad, g1) and torch.equal(F, F1)
+    assert np.all(N.strain(th[0], P, lam0, g, deaf, 0.3) == 0)
+    ref = N.loglike(th[0], P, lam0, g, dets, data, ip, 0.3)
+    assert abs(float(lnl[0]) - ref) <= 1e-10 * max(1.0, abs(ref) / 1e3)
