@@ -62,7 +62,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t rec = 0, tab = 0, tan = 0, partial = 0, seg = 0, extra = 0, total = 0;
+    size_t rec = 0, tab = 0, tan = 0, partial = 0, seg = 0, order = 0, extra = 0, total = 0;
     int chunks = 1;
 };
 
@@ -83,6 +83,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             off = align_up(off + 3 * N * L.chunks * 2 * sizeof(double));
             L.seg = off;
             off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
+            L.order = off;
+            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int));
             break;
         case PD_OP_LOGLIKE_GRAD:
             L.chunks = pd::chunks_for(n, nb);
@@ -92,6 +94,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             off = align_up(off + 3 * N * L.chunks * pd::kNSlot * sizeof(double));
             L.seg = off;
             off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
+            L.order = off;
+            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int));
             break;
         case PD_OP_FISHER:
             L.chunks = pd::chunks_for(n, nb);
@@ -299,7 +303,8 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
         e = pd::launch_tables(g, data, inv_psd, tab, s);
         if (e != hipSuccess) return fail_joined(e, "tables");
     }
-    e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, lnl,
+    e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg),
+                           at<int>(workspace, L.order), partial, lnl,
                            grad, side ? side->join : nullptr, s);
     if (e != hipSuccess) return fail_joined(e, "loglike");
     return PD_OK;

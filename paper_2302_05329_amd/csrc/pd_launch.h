@@ -43,6 +43,8 @@ inline void launch_regions(hipStream_t s, F&& launch) {
     }
 }
 
+constexpr int kOrderBuckets = 256;  // work buckets of the point ordering (one per thread of a block)
+
 inline int chunks_for(int64_t n, int64_t n_bins) {
     const int64_t want = (16384 + n - 1) / n;
     int64_t cap = n_bins / 512;
@@ -64,8 +66,8 @@ hipError_t launch_tables(const GridArgs& g, const double* data, const double* in
 hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
                            double* h, hipStream_t s);
 hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
-                          int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* lnl,
-                          double* grad, hipEvent_t before_epilogue, hipStream_t s);
+                          int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
+                          double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                          int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* F,
