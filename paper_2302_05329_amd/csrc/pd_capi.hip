@@ -105,6 +105,8 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             off = align_up(off + 3 * N * L.chunks * pd::kFisherSlots * sizeof(double));
             L.seg = off;
             off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
+            L.order = off;
+            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int));
             break;
         case PD_OP_MISMATCH_GRAD:
             L.tan = off;
@@ -334,7 +336,8 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, co
     if (e != hipSuccess) return fail_hip(e, "setup tangents");
     e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
     if (e != hipSuccess) return fail_hip(e, "tables");
-    e = pd::launch_fisher(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg), partial, F, s);
+    e = pd::launch_fisher(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg),
+                          at<int>(workspace, L.order), partial, F, s);
     if (e != hipSuccess) return fail_hip(e, "fisher");
     return PD_OK;
 }

@@ -501,15 +501,18 @@ __global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restr
                                                         const double* __restrict__ tans, int64_t n, int chunks,
                                                         GridArgs g, const double* __restrict__ tab,
                                                         const int* __restrict__ segs,
+                                                        const int* __restrict__ perm,
                                                         double* __restrict__ partial_all) {
     double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * kFisherAcc;
     __shared__ double lds[4][kFisherDirs * REC_N];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + wib));
-    const int64_t p = wave / chunks;
-    const int c = static_cast<int>(wave - p * chunks);
-    const bool live = p < n;
+    const int64_t pi = wave / chunks;
+    const int c = static_cast<int>(wave - pi * chunks);
+    const bool live = pi < n;
+    // points in order of decreasing work, as in the likelihood passes
+    const int64_t p = live ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
     double* T = lds[wib];
     if (live) {
         for (int j = lane; j < kFisherDirs * REC_N; j += 64) T[j] = tans[p * 7 * REC_N + j];
@@ -822,19 +825,28 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
 }
 
 hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
-                         int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* F,
-                         hipStream_t s) {
+                         int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
+                         double* F, hipStream_t s) {
     const int64_t waves = n * chunks;
-    hipLaunchKernelGGL(k_segments, dim3(blocks_for(3 * waves, 128)), dim3(128), 0, s, recs, n, chunks, g, segs,
-                       nullptr);
+    int* counts = order;
+    int* perm = order + 2 * kOrderBuckets;
+    const int64_t seg_threads = 3 * waves > 2 * kOrderBuckets ? 3 * waves : 2 * kOrderBuckets;
+    hipLaunchKernelGGL(k_segments, dim3(blocks_for(seg_threads, 128)), dim3(128), 0, s, recs, n, chunks, g, segs,
+                       counts);
+    hipLaunchKernelGGL(k_order_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts);
+    hipLaunchKernelGGL(k_order_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts,
+                       counts + kOrderBuckets, perm);
     {
         // sequential: run concurrently, the three launches (three waves per SIMD each, LDS-resident
         // tangents) measured 1.7x slower
         ProfRange pr(PD_K_FISHER, s);
         const dim3 grid(blocks_for(waves, 4));
-        hipLaunchKernelGGL(k_fisher_partial<3>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, partial);
-        hipLaunchKernelGGL(k_fisher_partial<2>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, partial);
-        hipLaunchKernelGGL(k_fisher_partial<1>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, partial);
+        hipLaunchKernelGGL(k_fisher_partial<3>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
+                           partial);
+        hipLaunchKernelGGL(k_fisher_partial<2>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
+                           partial);
+        hipLaunchKernelGGL(k_fisher_partial<1>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
+                           partial);
     }
     hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, param, recs, n, chunks,
                        partial, F);

@@ -70,8 +70,8 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
                           double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
-                         int chunks, const GridArgs& g, const double* tab, int* segs, double* partial, double* F,
-                         hipStream_t s);
+                         int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
+                         double* F, hipStream_t s);
 
 int posterior_check(const pd_posterior* post);
 size_t posterior_ws_bytes(const pd_posterior* post, int64_t n);
