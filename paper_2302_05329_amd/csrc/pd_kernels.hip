@@ -300,8 +300,8 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
     const int64_t pi = wave / chunks;
     const int c = static_cast<int>(wave - pi * chunks);
     if (pi >= n) return;
-    // waves visit the points in order of decreasing work (see k_order_scatter)
-    const int64_t p = __builtin_amdgcn_readfirstlane(perm[pi]);
+    // waves visit the points in order of decreasing work (see k_order_scatter), or in index order
+    const int64_t p = perm ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
     const double* __restrict__ rec = recs + p * REC_N;
     double* __restrict__ out = partial + (p * chunks + c) * NS;
     if (rec[R_VALID] == 0.0) {
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restr
     const int c = static_cast<int>(wave - pi * chunks);
     const bool live = pi < n;
     // points in order of decreasing work, as in the likelihood passes
-    const int64_t p = live ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
+    const int64_t p = (live && perm) ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
     double* T = lds[wib];
     if (live) {
         for (int j = lane; j < kFisherDirs * REC_N; j += 64) T[j] = tans[p * 7 * REC_N + j];
@@ -770,6 +770,29 @@ RegionStreams* region_streams() {
     return pool.back().ok ? &pool.back() : nullptr;
 }
 
+// Segments of every (region, point, chunk), then, for batches of at least kOrderMinPoints points,
+// the work ordering (order: [0, 256) bucket sizes, [256, 512) fill cursors, then the permutation
+// [n]).  Returns the permutation, or nullptr for index order: below that size the two extra
+// launches cost more than the ordering gains (4096 chains x 8033 bins, one HMC leapfrog step).
+constexpr int64_t kOrderMinPoints = 16384;
+
+static int* launch_order(const double* recs, int64_t n, int chunks, const GridArgs& g, int* segs, int* order,
+                         hipStream_t s) {
+    const int64_t waves = n * chunks;
+    const bool ordered = n >= kOrderMinPoints;
+    int* counts = ordered ? order : nullptr;
+    // the grid also covers the 512 counters it clears when 3 x waves is smaller
+    const int64_t seg_threads = 3 * waves > 2 * kOrderBuckets ? 3 * waves : 2 * kOrderBuckets;
+    hipLaunchKernelGGL(k_segments, dim3(blocks_for(seg_threads, 128)), dim3(128), 0, s, recs, n, chunks, g, segs,
+                       counts);
+    if (!ordered) return nullptr;
+    int* perm = order + 2 * kOrderBuckets;
+    hipLaunchKernelGGL(k_order_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts);
+    hipLaunchKernelGGL(k_order_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts,
+                       counts + kOrderBuckets, perm);
+    return perm;
+}
+
 template <int MODE>
 static void launch_region_moments(unsigned nblk, const double* recs, int64_t n, int chunks, const GridArgs& g,
                                   const double* tab, const int* segs, const int* perm, double* partial,
@@ -792,16 +815,7 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
                           double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s) {
     const int64_t waves = n * chunks;
     const unsigned nblk = blocks_for(waves, 4);
-    // order: [0, 256) bucket sizes, [256, 512) fill cursors, then the permutation [n]
-    int* counts = order;
-    int* perm = order + 2 * kOrderBuckets;
-    // the grid also covers the 512 counters it clears when 3 x waves is smaller
-    const int64_t seg_threads = 3 * waves > 2 * kOrderBuckets ? 3 * waves : 2 * kOrderBuckets;
-    hipLaunchKernelGGL(k_segments, dim3(blocks_for(seg_threads, 128)), dim3(128), 0, s, recs, n, chunks, g, segs,
-                       counts);
-    hipLaunchKernelGGL(k_order_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts);
-    hipLaunchKernelGGL(k_order_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts,
-                       counts + kOrderBuckets, perm);
+    int* perm = launch_order(recs, n, chunks, g, segs, order, s);
     if (grad) {
         {
             ProfRange pr(PD_K_LOGLIKE_GRAD, s);
@@ -828,14 +842,7 @@ hipError_t launch_fisher(const double* theta, int param, const double* recs, con
                          int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
                          double* F, hipStream_t s) {
     const int64_t waves = n * chunks;
-    int* counts = order;
-    int* perm = order + 2 * kOrderBuckets;
-    const int64_t seg_threads = 3 * waves > 2 * kOrderBuckets ? 3 * waves : 2 * kOrderBuckets;
-    hipLaunchKernelGGL(k_segments, dim3(blocks_for(seg_threads, 128)), dim3(128), 0, s, recs, n, chunks, g, segs,
-                       counts);
-    hipLaunchKernelGGL(k_order_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts);
-    hipLaunchKernelGGL(k_order_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts,
-                       counts + kOrderBuckets, perm);
+    int* perm = launch_order(recs, n, chunks, g, segs, order, s);
     {
         // sequential: run concurrently, the three launches (three waves per SIMD each, LDS-resident
         // tangents) measured 1.7x slower
