@@ -92,6 +92,15 @@ def draw_masses(rng, n, lo=5.0, hi=50.0):
     return np.maximum(a, b), np.minimum(a, b)
 
 
+def lambda_gamma2_above_one():
+    """The placeholder table with the constant term of gamma2 raised by 0.35, so that
+    1.1 < gamma2 < 1.2 over the configs' priors: the merger-ringdown amplitude then has no
+    stationary point and the amplitude peak takes the other branch of its definition."""
+    lam = load_lambda().reshape(19, 11).copy()
+    lam[5, 0] += 0.35
+    return lam.reshape(-1)
+
+
 def draw_sources(n, seed, *, d_range=None, d_fixed=440.0, tc_range=None, phic_random=False,
                  chi_max=0.9):
     """n parameter rows (m1, m2, chi1, chi2, D, tc, phic) with the configs' priors."""

@@ -102,11 +102,12 @@ def test_newtonian_amplitude_limit(src, lam0):
     assert abs(m.amp0 * f ** (-7.0 / 6.0) / expect - 1.0) < 1e-14
 
 
-def _taylorf2_from_energy_flux(eta):
-    """Non-spinning TaylorF2 coefficients derived with the stationary-phase approximation
-    from the 3PN binding energy and the 3.5PN flux (textbook PN inputs), independently of
-    the oracle's tabulated phi_k.  Series in v are dicts {(power, power of ln v): coef}.
-    Returns phi[k], phil[k] in units of 3/(128 eta) v^(k-5)."""
+def _taylorf2_from_energy_flux(eta, e_spin=None, f_spin=None, order=7):
+    """TaylorF2 coefficients derived with the stationary-phase approximation from the 3PN
+    binding energy and the 3.5PN flux (textbook PN inputs), independently of the oracle's
+    tabulated phi_k.  e_spin / f_spin add terms {k: coefficient of v^k} to the brackets of
+    E = -(eta v^2 / 2)[1 + ...] and F = (32/5) eta^2 v^10 [1 + ...].  Series in v are dicts
+    {(power, power of ln v): coef}.  Returns phi[k], phil[k] in units of 3/(128 eta) v^(k-5)."""
     pi, gam = math.pi, EULER
     e2 = -(3.0 / 4.0 + eta / 12.0)
     e4 = -(27.0 / 8.0 - 19.0 / 8.0 * eta + eta**2 / 24.0)
@@ -122,7 +123,12 @@ def _taylorf2_from_energy_flux(eta):
           - 775.0 / 324.0 * eta**3)
     f6l = -1712.0 / 105.0          # -856/105 ln(16 v^2) = const - 1712/105 ln v
     f7 = (-16285.0 / 504.0 + 214745.0 / 1728.0 * eta + 193385.0 / 3024.0 * eta**2) * pi
-    order = 7
+    e = {2: e2, 4: e4, 6: e6}
+    f = {2: f2, 3: f3, 4: f4, 5: f5, 6: f6, 7: f7}
+    for k, c in (e_spin or {}).items():
+        e[k] = e.get(k, 0.0) + c
+    for k, c in (f_spin or {}).items():
+        f[k] = f.get(k, 0.0) + c
 
     def mul(a, b):
         out = {}
@@ -133,9 +139,14 @@ def _taylorf2_from_energy_flux(eta):
                     out[key] = out.get(key, 0.0) + ca * cb
         return out
 
-    # -dE/dv / (eta v) with E = -(eta/2) v^2 (1 + e2 v^2 + e4 v^4 + e6 v^6)
-    num = {(0, 0): 1.0, (2, 0): 2 * e2, (4, 0): 3 * e4, (6, 0): 4 * e6}
-    den_minus_1 = {(2, 0): f2, (3, 0): f3, (4, 0): f4, (5, 0): f5, (6, 0): f6, (6, 1): f6l, (7, 0): f7}
+    # -dE/dv / (eta v) with E = -(eta/2) v^2 (1 + sum_k e_k v^k): coefficient (k + 2)/2 e_k
+    num = {(0, 0): 1.0}
+    for k, c in e.items():
+        if k <= order:
+            num[(k, 0)] = (k + 2) / 2.0 * c
+    den_minus_1 = {(k, 0): c for k, c in f.items() if k <= order}
+    if order >= 6:
+        den_minus_1[(6, 1)] = f6l
     inv = {(0, 0): 1.0}
     for _ in range(order + 1):                      # 1/(1+x) = 1 - x (1/(1+x)), iterated
         prod = mul(den_minus_1, inv)
@@ -511,3 +522,266 @@ def test_overlaps_hermitian_linear_and_phase_covariant(lam0):
     assert abs(out[3] - (out[1] + 2.0 * out[2])) <= 1e-12 * (abs(out[1]) + 2 * abs(out[2]) + math.sqrt(hh))
     assert abs(out[4] - hh * np.exp(1j * phi)) <= 1e-13 * hh
     assert abs(hh - O.inner(h, h, ip, g[1])) == 0.0
+
+
+# ---------------------------------------------------------------------------------
+# spin terms of the TaylorF2 phase, derived from textbook PN energy and flux (not from the
+# oracle's tabulated phi_k).  Spin variables for aligned spins (G = c = 1, total mass 1):
+#   S = X1^2 chi1 + X2^2 chi2,  Sigma = X2 chi2 - X1 chi1,  X1,2 = (1 +- delta)/2.
+# Spin-orbit: binding energy E = -(eta v^2 / 2)[1 + ... + e3 v^3 + e5 v^5 + e7 v^7] with
+#   e3 = 14/3 S + 2 delta Sigma,  e5 = (11 - 61 eta/9) S + delta (3 - 10 eta/3) Sigma,
+#   e7 = (135/4 - 367 eta/4 + 29 eta^2/12) S + delta (27/4 - 39 eta + 5 eta^2/4) Sigma,
+# and flux F = (32/5) eta^2 v^10 [1 + ... + f3 v^3 + f5 v^5 + f6 v^6 + f7 v^7] with
+#   f3 = -4 S - 5/4 delta Sigma,  f5 = (-9/2 + 272 eta/9) S + (-13/16 + 43 eta/4) delta Sigma,
+#   f6 = -16 pi S - 31 pi/6 delta Sigma (tail),
+#   f7 = (476645/6804 + 6172 eta/189 - 2810 eta^2/27) S + (9535/336 + 1849 eta/126 - 1501 eta^2/36) delta Sigma
+# (Blanchet, Living Rev. Relativ. 17, 2 (2014), spin-orbit sections).  Spin-spin at 2PN between
+# the two bodies (Kidder, PRD 52, 821 (1995)), aligned spins: e4 gets -2 eta chi1 chi2 (from
+# [S1.S2 - 3 (L.S1)(L.S2)] / (eta M^4)) and f4 gets 31/8 eta chi1 chi2 (from
+# [-103 S1.S2 + 289 (L.S1)(L.S2)] / (48 eta M^4)).
+# ---------------------------------------------------------------------------------
+def _spin_energy_flux(eta, chis, chia, parts=("so", "ss")):
+    delta = math.sqrt(max(0.0, 1.0 - 4.0 * eta))
+    x1, x2 = (1.0 + delta) / 2.0, (1.0 - delta) / 2.0
+    c1, c2 = chis + chia, chis - chia
+    S = x1**2 * c1 + x2**2 * c2
+    dS = delta * (x2 * c2 - x1 * c1)
+    pi = math.pi
+    e, f = {}, {}
+    if "so" in parts:
+        e = {3: 14.0 / 3.0 * S + 2.0 * dS,
+             5: (11.0 - 61.0 * eta / 9.0) * S + (3.0 - 10.0 * eta / 3.0) * dS,
+             7: (135.0 / 4.0 - 367.0 * eta / 4.0 + 29.0 * eta**2 / 12.0) * S
+                + (27.0 / 4.0 - 39.0 * eta + 5.0 * eta**2 / 4.0) * dS}
+        f = {3: -4.0 * S - 5.0 / 4.0 * dS,
+             5: (-9.0 / 2.0 + 272.0 * eta / 9.0) * S + (-13.0 / 16.0 + 43.0 * eta / 4.0) * dS,
+             6: -16.0 * pi * S - 31.0 * pi / 6.0 * dS,
+             7: (476645.0 / 6804.0 + 6172.0 * eta / 189.0 - 2810.0 * eta**2 / 27.0) * S
+                + (9535.0 / 336.0 + 1849.0 * eta / 126.0 - 1501.0 * eta**2 / 36.0) * dS}
+    if "ss" in parts:
+        e[4] = -2.0 * eta * c1 * c2
+        f[4] = 31.0 / 8.0 * eta * c1 * c2
+    return e, f
+
+
+def _oracle_phi(eta, chis, chia):
+    return O.taylorf2_phase_coefficients(eta, math.sqrt(max(0.0, 1.0 - 4.0 * eta)), chis, chia)
+
+
+SPIN_CASES = [(0.25, 0.7, 0.0), (0.2, 0.3, -0.1), (0.1, -0.5, 0.4), (0.05, 0.2, 0.6), (0.16, -0.8, -0.1)]
+
+
+@pytest.mark.parametrize("eta,chis,chia", SPIN_CASES)
+def test_taylorf2_spin_orbit_terms_from_energy_flux(eta, chis, chia):
+    """The part of each phase coefficient odd in the spins (spin-orbit: 1.5, 2.5 incl. its
+    log, 3 and 3.5PN) equals the stationary-phase derivation from the spin-orbit energy and
+    flux; a dropped term, a wrong sign or a swapped delta*chia / chis pairing fails.  (The
+    model's phase has no terms cubic in the spins, so spin-spin energy and flux terms, whose
+    products with spin-orbit ones are cubic, are left out of this derivation.)"""
+    def odd(fn):
+        a, al = fn(chis, chia)
+        b, bl = fn(-chis, -chia)
+        return [(x - y) / 2.0 for x, y in zip(a, b)], [(x - y) / 2.0 for x, y in zip(al, bl)]
+
+    def derived(cs, ca):
+        e, f = _spin_energy_flux(eta, cs, ca, parts=("so",))
+        return _taylorf2_from_energy_flux(eta, e_spin=e, f_spin=f)
+
+    o, ol = odd(lambda cs, ca: _oracle_phi(eta, cs, ca))
+    d, dl = odd(derived)
+    assert abs(o[3]) > 1.0
+    for k in range(8):
+        assert abs(o[k] - d[k]) <= 1e-11 * max(1.0, abs(d[k])), (k, o[k], d[k])
+        assert abs(ol[k] - dl[k]) <= 1e-11 * max(1.0, abs(dl[k])), (k, ol[k], dl[k])
+
+
+@pytest.mark.parametrize("eta", [0.25, 0.2, 0.1, 0.02])
+def test_taylorf2_spin_spin_2pn_interaction_from_energy_flux(eta):
+    """The chi1*chi2 part of the 2PN coefficient (the spin-spin interaction of the two bodies)
+    equals the derivation from the interaction energy and flux."""
+    def bilinear(fn, c1, c2):
+        g = lambda a, b: fn((a + b) / 2.0, (a - b) / 2.0)  # noqa: E731
+        return g(c1, c2) - g(c1, 0.0) - g(0.0, c2) + g(0.0, 0.0)
+
+    def derived(cs, ca):
+        e, f = _spin_energy_flux(eta, cs, ca)
+        return _taylorf2_from_energy_flux(eta, e_spin=e, f_spin=f)[0][4]
+
+    for c1, c2 in ((0.6, -0.7), (0.9, 0.9), (-0.3, 0.5)):
+        o = bilinear(lambda cs, ca: _oracle_phi(eta, cs, ca)[0][4], c1, c2)
+        d = bilinear(derived, c1, c2)
+        assert abs(o - d) <= 1e-10 * max(1.0, abs(d)), (eta, c1, c2, o, d)
+
+
+def _kerr_circular_energy_series(q, order=7):
+    """Binding energy per unit mass of a circular equatorial prograde orbit around a Kerr black
+    hole of spin q (Bardeen, Press & Teukolsky 1972), E = (1 - 2u^2 + q u^3) / sqrt(1 - 3u^2 +
+    2 q u^3) - 1 with u = sqrt(M/r), written as a power series in v = (M Omega)^(1/3):
+    Omega = M^(1/2) / (r^(3/2) + q M^(3/2)) gives u^3 = v^3 / (1 - q v^3).  Returns e_k of
+    E = -(v^2/2)[1 + sum_k e_k v^k] as [1, e_1, e_2, ...]."""
+    n = order + 3
+
+    def mul(a, b):
+        return np.convolve(a, b)[:n]
+
+    def binom(x, p):            # (1 + x)^p for a series x with x[0] = 0
+        out = np.zeros(n)
+        out[0] = 1.0
+        term = out.copy()
+        for j in range(1, n):
+            term = mul(term, x) * ((p - j + 1) / j)
+            out = out + term
+        return out
+
+    qv3 = np.zeros(n)
+    qv3[3] = -q
+    u_over_v = binom(qv3, -1.0 / 3.0)                 # (1 - q v^3)^(-1/3)
+    u = np.zeros(n)
+    u[1:] = u_over_v[:n - 1]                          # u = v (1 - q v^3)^(-1/3)
+    u2, u3 = mul(u, u), mul(mul(u, u), u)
+    num = np.zeros(n)
+    num[0] = 1.0
+    num = num - 2.0 * u2 + q * u3
+    x = -3.0 * u2 + 2.0 * q * u3
+    e = mul(num, binom(x, -0.5))
+    e[0] -= 1.0
+    return -2.0 * e[2:]                               # E = -(v^2/2)(1 + e_1 v + ...): e_k = -2 E_{k+2}
+
+
+@pytest.mark.parametrize("q", [0.9, 0.4, -0.6])
+def test_taylorf2_test_mass_limit_from_kerr(q):
+    """eta -> 0: the 1.5PN spin-orbit and the 2PN spin-squared phase terms of a test mass
+    around a Kerr black hole of spin chi1 = q follow from the exact circular-orbit energy above
+    and the test-mass flux F/F_N = 1 - 1247/336 v^2 + (4 pi - 11 q/4) v^3 + (-44711/9072 +
+    33 q^2/16) v^4 (Shibata, Sasaki, Tagoshi & Tanaka 1995).  The oracle's coefficients at
+    eta = 0 must match (the small body's spin drops out)."""
+    ek = _kerr_circular_energy_series(q)
+    assert abs(ek[0] - 1.0) < 1e-15 and abs(ek[1]) < 1e-15
+    assert abs(ek[2] + 0.75) < 1e-15                                  # Schwarzschild 1PN: -3/4
+    assert abs(ek[3] - 8.0 * q / 3.0) < 1e-14                         # spin-orbit 1.5PN
+    assert abs(ek[4] - (-27.0 / 8.0 - q * q)) < 1e-13                 # 2PN incl. spin^2
+    # spin parts relative to the non-spinning test-mass energy and flux
+    e_spin = {3: ek[3], 4: ek[4] + 27.0 / 8.0}
+    f_spin = {3: -11.0 * q / 4.0, 4: 33.0 * q * q / 16.0}
+    eta = 1e-9
+    d, _ = _taylorf2_from_energy_flux(eta, e_spin=e_spin, f_spin=f_spin, order=4)
+    for chi2 in (0.0, 0.8):
+        o, _ = O.taylorf2_phase_coefficients(0.0, 1.0, (q + chi2) / 2.0, (q - chi2) / 2.0)
+        for k in (3, 4):
+            assert abs(o[k] - d[k]) <= 1e-6 * max(1.0, abs(d[k])), (k, o[k], d[k])
+
+
+@pytest.mark.parametrize("eta", [0.24, 0.16, 0.09, 0.01])
+def test_taylorf2_self_spin_scales_with_component_mass(eta):
+    """The 2PN terms quadratic in one body's spin (quadrupole-monopole and self-spin) scale with
+    that body's mass fraction squared, X_i^2 chi_i^2, with the test-mass coefficient of the
+    Kerr limit: -10 (3 e4 - f4) = -405/8 for e4 = -q^2, f4 = 33 q^2 / 16."""
+    delta = math.sqrt(1.0 - 4.0 * eta)
+    x1, x2 = (1.0 + delta) / 2.0, (1.0 - delta) / 2.0
+    kerr = 10.0 * (3.0 * (-1.0) - 33.0 / 16.0)
+    for x, sign in ((x1, 1.0), (x2, -1.0)):
+        c = 0.6
+        g = lambda a, b: _oracle_phi(eta, (a + b) / 2.0, (a - b) / 2.0)[0][4]  # noqa: E731
+        a, b = (c, 0.0) if sign > 0 else (0.0, c)
+        quad = (g(a, b) + g(-a, -b) - 2.0 * g(0.0, 0.0)) / 2.0 / (c * c)
+        assert abs(quad / x**2 - kerr) <= 1e-10 * abs(kerr), (eta, sign, quad / x**2)
+
+
+# ---------------------------------------------------------------------------------
+# time and phase alignment (the reading: Psi(f) = Phi(Mf) - t0 (Mf - Mf_ref) - Phi(Mf_ref)
+# + 2 pi f tc - 2 phic with t0 the merger-ringdown phase slope at the amplitude peak)
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("src", SOURCES)
+def test_phase_reference_at_f_ref(src, lam0):
+    """At f = f_ref the phase reduces to 2 pi f_ref tc - 2 phic (the reference convention)."""
+    th = np.array(src)
+    f_ref = 20.0
+    g = (f_ref, 0.25, 3, f_ref, f_ref)       # bin 0 is exactly f_ref
+    amp, psi, act = O.amp_phase(th, P, lam0, g)
+    assert act[0]
+    want = 2.0 * math.pi * f_ref * th[5] - 2.0 * th[6]
+    assert abs(psi[0] - want) <= 4.0 * np.spacing(max(1.0, abs(want)))
+
+
+@pytest.mark.parametrize("src", SOURCES)
+def test_phase_stationary_at_amplitude_peak(src, lam0):
+    """d(Psi - 2 pi f tc)/df = 0 at the amplitude peak f = f_peak / M: the stationary-phase time
+    of the peak is tc.  Taking t0 at f_RD (or at any other frequency) fails this."""
+    th = np.array(src)
+    m = O.Model(th, P, lam0, 20.0)
+    fp = float(np.real(m.f_peak)) / m.Ms
+    h = fp * 1e-6
+    g = (fp - h, h, 3, 1.0, 20.0)
+    amp, psi, act = O.amp_phase(th, P, lam0, g)
+    assert np.all(act)
+    slope = (psi[2] - psi[0]) / (2.0 * h) - 2.0 * math.pi * th[5]
+    # compare with the phase slope a decade below the peak (it is many times larger there)
+    g2 = (0.1 * fp - h, h, 3, 1.0, 20.0)
+    _, psi2, _ = O.amp_phase(th, P, lam0, g2)
+    ref = abs((psi2[2] - psi2[0]) / (2.0 * h) - 2.0 * math.pi * th[5])
+    assert abs(slope) <= 1e-6 * ref, (slope, ref)
+    # and the peak is the maximum of the merger-ringdown amplitude it is defined from
+    mf = np.real(m.f_peak) * np.array([1 - 1e-4, 1.0, 1 + 1e-4])
+    ar = m.amp_mrd(mf)
+    assert ar[1] >= ar[0] and ar[1] >= ar[2]
+
+
+# ---------------------------------------------------------------------------------
+# the noise model: Re n_k, Im n_k i.i.d. N(0, S_k / (4 df)), so (n|n) has mean 2N and
+# standard deviation 2 sqrt(N), and the whitened parts are standard normal
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [1002, 1005, 31])
+def test_noise_scale_and_whitened_normality(seed):
+    from scipy import stats
+    grid = W.Grid(20.0, 0.125, 16225)
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    n = W.complex_noise(psd, grid.df, seed)
+    N = grid.n_bins
+    nn = O.inner(n, n, 1.0 / psd, grid.df)
+    assert abs(nn - 2.0 * N) <= 5.0 * 2.0 * math.sqrt(N), (nn, 2 * N)
+    z = n * np.sqrt(4.0 * grid.df / psd)
+    for part in (z.real, z.imag):
+        assert stats.kstest(part, "norm").pvalue > 1e-3
+    assert abs(np.mean(z.real * z.imag)) <= 5.0 / math.sqrt(N)
+
+
+def test_noise_gives_standard_normal_overlap(lam0):
+    """(n|h) ~ N(0, (h|h)) over noise realisations: the SNR convention the injections use."""
+    grid = W.Grid(20.0, 0.25, 2001)
+    psd = W.psd_aligo_zdhp_fit(grid.freqs())
+    th = np.array(SOURCES[0])
+    h = O.waveform(th, P, lam0, grid.as_tuple())
+    hh = O.inner(h, h, 1.0 / psd, grid.df)
+    x = np.array([O.inner(W.complex_noise(psd, grid.df, 500 + s), h, 1.0 / psd, grid.df) for s in range(400)])
+    z = x / math.sqrt(hh)
+    assert abs(np.mean(z)) <= 4.0 / math.sqrt(len(z))
+    assert abs(np.var(z) - 1.0) <= 5.0 * math.sqrt(2.0 / len(z))
+
+
+# ---------------------------------------------------------------------------------
+# the gamma2 > 1 branch of the amplitude peak (the merger-ringdown amplitude has no
+# stationary point; the reading takes the real part of the complex one)
+# ---------------------------------------------------------------------------------
+def test_peak_frequency_gamma2_above_one():
+    lam = W.lambda_gamma2_above_one()
+    rows = W.draw_sources(40, 91)
+    seen = 0
+    for th in rows:
+        m = O.Model(th, P, lam, 20.0)
+        g2 = m.p["gamma2"]
+        assert g2 > 1.0
+        g = m.p["gamma3"] * m.f_damp
+        # stationary points of ln A_MR: gamma2 x^2 + 2 g x + gamma2 g^2 = 0, x = Mf - f_RD
+        root = complex(-g, g * math.sqrt(g2 * g2 - 1.0)) / g2
+        assert abs(g2 * root * root + 2.0 * g * root + g2 * g * g) <= 1e-12 * g * g
+        assert abs(m.f_peak - (m.f_rd + root.real)) <= 1e-14 * m.f_rd
+        # no real stationary point: the amplitude ratio falls monotonically past f_RD - g
+        mf = np.linspace(0.5 * m.f_rd, 0.2, 400)
+        assert np.all(np.diff(m.amp_mrd(mf)) < 0)
+        if m.valid:
+            seen += 1
+            for f0 in (O.F_AMP_JOIN, float(np.real(m.f_peak))):
+                for fn in (m.amplitude_ratio,):
+                    lo, hi = fn(np.array([f0 * (1 - 1e-9)]))[0], fn(np.array([f0]))[0]
+                    assert abs(hi - lo) <= 1e-8 * abs(hi)
+    assert seen >= 30
