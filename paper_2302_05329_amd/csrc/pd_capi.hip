@@ -84,7 +84,7 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.seg = off;
             off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
             L.order = off;
-            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int));
+            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int) + N);
             break;
         case PD_OP_LOGLIKE_GRAD:
             L.chunks = pd::chunks_for(n, nb);
@@ -95,7 +95,7 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.seg = off;
             off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
             L.order = off;
-            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int));
+            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int) + N);
             break;
         case PD_OP_FISHER:
             L.chunks = pd::chunks_for(n, nb);
@@ -106,7 +106,7 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.seg = off;
             off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
             L.order = off;
-            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int));
+            off = align_up(off + (2 * pd::kOrderBuckets + N) * sizeof(int) + N);
             break;
         case PD_OP_MISMATCH_GRAD:
             L.tan = off;
@@ -195,6 +195,13 @@ size_t pd_workspace_bytes(int op, int64_t n, int64_t n_bins) {
     return layout_for(op, n, n_bins).total;
 }
 
+}  // extern "C"
+
+size_t pd::op_workspace_bytes(int op, int64_t n, int64_t n_bins) { return pd_workspace_bytes(op, n, n_bins); }
+void pd::set_last_error(const char* msg) { g_last_error = msg; }
+
+extern "C" {
+
 const char* pd_last_error(void) { return g_last_error.c_str(); }
 
 int pd_profile_enable(int on) {
@@ -265,7 +272,7 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
 int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
                          const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
                          int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s,
-                         bool tables_ready) {
+                         bool tables_ready, bool concurrent) {
     pd::GridArgs g;
     int rc = check_common(theta, n, param, grid, lambda, &g);
     if (rc) return rc;
@@ -282,7 +289,7 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
     double* tab = at<double>(workspace, L.tab);
     double* tans = grad ? at<double>(workspace, L.tan) : nullptr;
     hipError_t e = hipSuccess;
-    SideStream* side = grad ? side_stream() : nullptr;
+    SideStream* side = (grad && concurrent) ? side_stream() : nullptr;
     if (grad) {
         hipStream_t ts = s;
         if (side && hipEventRecord(side->fork, s) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
@@ -307,7 +314,7 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
     }
     e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg),
                            at<int>(workspace, L.order), partial, lnl,
-                           grad, side ? side->join : nullptr, s);
+                           grad, side ? side->join : nullptr, s, concurrent);
     if (e != hipSuccess) return fail_joined(e, "loglike");
     return PD_OK;
 }

@@ -654,18 +654,24 @@ __device__ __forceinline__ int work_bucket(const double* __restrict__ rec, const
     return kOrderBuckets - 1 - b;
 }
 
+// Each point's bucket is computed once, here, and stored: the scatter reads it back, so the two
+// kernels cannot disagree on a bucket and the permutation is always a bijection of [0, n).
 __global__ void __launch_bounds__(256) k_order_count(const double* __restrict__ recs, int64_t n, GridArgs g,
-                                                     int* __restrict__ counts) {
+                                                     int* __restrict__ counts, unsigned char* __restrict__ bucket) {
     __shared__ int hist[kOrderBuckets];
     hist[threadIdx.x] = 0;
     __syncthreads();
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p < n) atomicAdd(&hist[work_bucket(recs + p * REC_N, g)], 1);
+    if (p < n) {
+        const int b = work_bucket(recs + p * REC_N, g);
+        bucket[p] = static_cast<unsigned char>(b);
+        atomicAdd(&hist[b], 1);
+    }
     __syncthreads();
     if (hist[threadIdx.x] > 0) atomicAdd(&counts[threadIdx.x], hist[threadIdx.x]);
 }
 
-__global__ void __launch_bounds__(256) k_order_scatter(const double* __restrict__ recs, int64_t n, GridArgs g,
+__global__ void __launch_bounds__(256) k_order_scatter(const unsigned char* __restrict__ bucket, int64_t n,
                                                        const int* __restrict__ counts, int* __restrict__ fill,
                                                        int* __restrict__ perm) {
     __shared__ int base[kOrderBuckets], lcnt[kOrderBuckets], lbase[kOrderBuckets];
@@ -688,7 +694,7 @@ __global__ void __launch_bounds__(256) k_order_scatter(const double* __restrict_
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     int b = 0, r = 0;
     if (p < n) {
-        b = work_bucket(recs + p * REC_N, g);
+        b = bucket[p];
         r = atomicAdd(&lcnt[b], 1);
     }
     __syncthreads();
@@ -787,8 +793,9 @@ static int* launch_order(const double* recs, int64_t n, int chunks, const GridAr
                        counts);
     if (!ordered) return nullptr;
     int* perm = order + 2 * kOrderBuckets;
-    hipLaunchKernelGGL(k_order_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts);
-    hipLaunchKernelGGL(k_order_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts,
+    unsigned char* bucket = reinterpret_cast<unsigned char*>(perm + n);
+    hipLaunchKernelGGL(k_order_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, recs, n, g, counts, bucket);
+    hipLaunchKernelGGL(k_order_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, bucket, n, counts,
                        counts + kOrderBuckets, perm);
     return perm;
 }
@@ -796,7 +803,7 @@ static int* launch_order(const double* recs, int64_t n, int chunks, const GridAr
 template <int MODE>
 static void launch_region_moments(unsigned nblk, const double* recs, int64_t n, int chunks, const GridArgs& g,
                                   const double* tab, const int* segs, const int* perm, double* partial,
-                                  hipStream_t s) {
+                                  hipStream_t s, bool concurrent) {
     launch_regions(s, [&](int region, hipStream_t rs) {
         if (region == 3)
             hipLaunchKernelGGL((k_loglike_moments<MODE, 3>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
@@ -807,19 +814,19 @@ static void launch_region_moments(unsigned nblk, const double* recs, int64_t n, 
         else
             hipLaunchKernelGGL((k_loglike_moments<MODE, 1>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
                                segs, perm, partial);
-    });
+    }, concurrent);
 }
 
 hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                           int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
-                          double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s) {
+                          double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s, bool concurrent) {
     const int64_t waves = n * chunks;
     const unsigned nblk = blocks_for(waves, 4);
     int* perm = launch_order(recs, n, chunks, g, segs, order, s);
     if (grad) {
         {
             ProfRange pr(PD_K_LOGLIKE_GRAD, s);
-            launch_region_moments<1>(nblk, recs, n, chunks, g, tab, segs, perm, partial, s);
+            launch_region_moments<1>(nblk, recs, n, chunks, g, tab, segs, perm, partial, s, concurrent);
         }
         if (before_epilogue) {
             const hipError_t e = hipStreamWaitEvent(s, before_epilogue, 0);
@@ -830,7 +837,7 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
     } else {
         {
             ProfRange pr(PD_K_LOGLIKE, s);
-            launch_region_moments<0>(nblk, recs, n, chunks, g, tab, segs, perm, partial, s);
+            launch_region_moments<0>(nblk, recs, n, chunks, g, tab, segs, perm, partial, s, concurrent);
         }
         hipLaunchKernelGGL(k_loglike_value_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks,
                            partial, lnl);

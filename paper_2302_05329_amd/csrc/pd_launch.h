@@ -25,10 +25,11 @@ struct RegionStreams {
 RegionStreams* region_streams();
 
 // launch(r, stream) for the phase regions r = 3, 2, 1: region 3 on s, regions 2 and 1 on the side
-// streams, forked from and joined back into s by events (all on s if the side streams are missing).
+// streams, forked from and joined back into s by events (all on s if the side streams are missing,
+// or when `concurrent` is false: then no stream or event is created or used).
 template <class F>
-inline void launch_regions(hipStream_t s, F&& launch) {
-    RegionStreams* rs = region_streams();
+inline void launch_regions(hipStream_t s, F&& launch, bool concurrent = true) {
+    RegionStreams* rs = concurrent ? region_streams() : nullptr;
     const bool conc = rs && hipEventRecord(rs->fork, s) == hipSuccess &&
                       hipStreamWaitEvent(rs->s[0], rs->fork, 0) == hipSuccess &&
                       hipStreamWaitEvent(rs->s[1], rs->fork, 0) == hipSuccess;
@@ -67,7 +68,8 @@ hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, con
                            double* h, hipStream_t s);
 hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                           int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
-                          double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s);
+                          double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s,
+                          bool concurrent = true);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                          int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
@@ -79,9 +81,14 @@ size_t hmc_workspace_bytes(const pd_posterior* post, int64_t n);
 size_t rwmh_workspace_bytes(const pd_posterior* post, int64_t n);
 int rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
               const double* scale, int32_t* accepted, void* ws, hipStream_t s);
+// concurrent: run the record tangents and two of the three region launches on side streams (created
+// once per host thread and device); false keeps every launch on `s` and creates nothing.
 int loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
                      const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
-                     int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s, bool tables_ready);
+                     int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s, bool tables_ready,
+                     bool concurrent = true);
+size_t op_workspace_bytes(int op, int64_t n, int64_t n_bins);
+void set_last_error(const char* msg);
 int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
                    hipStream_t s, bool tables_ready = false);
 int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
