@@ -115,6 +115,22 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
                         int precision, double* lnl, double* grad, int32_t* status,
                         void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pd_loglike_and_grad with its workspace in a fixed
+ * device array of PD_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on (one
+ * copy per GPU, kept until the process ends).  Arguments and results as for pd_loglike_and_grad,
+ * without the workspace; every launch is enqueued on `stream` (no side streams).
+ * The call allocates nothing (no hipMalloc, hipFree, stream or event creation).  A batch whose
+ * pd_loglike_and_grad workspace (pd_workspace_bytes) exceeds the array, e.g. more than about
+ * 16 000 points on a 16 225-bin grid (4096 points x 8033 bins need 38 MB), returns
+ * PD_EUNSUPPORTED and launches nothing.  All calls on one GPU share that GPU's array: calls
+ * that overlap on one GPU (other streams, other host threads) race and must be serialised by
+ * the caller.  Nothing in the array needs to be cleared between calls. */
+#define PD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pd_loglike_and_grad_noalloc(const double* theta, int64_t n, int param, const pd_grid* grid,
+                                const double* lambda, const double* data, const double* inv_psd, int precision,
+                                double* lnl, double* grad, int32_t* status, void* stream);
+
 /* Fisher information of one detector, Sec. 3.2 Eq. 8: F_pq = (d_p h | d_q h),
  * p, q over the 7 entries of theta in layout `param`.
  * F       [n][7][7]           output, symmetric

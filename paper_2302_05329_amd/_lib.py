@@ -41,6 +41,7 @@ PD_K_MISMATCH_FFT = 5
 PD_K_MISMATCH_ADJ = 6
 PD_K_OVERLAP = 7
 PD_OVERLAP_MAX_STREAMS = 64
+PD_NOALLOC_SCRATCH_BYTES = 64 << 20
 PD_FLOW_FP32, PD_FLOW_BF16 = 0, 1
 
 
@@ -86,6 +87,7 @@ SIGNATURES = {
     "pd_workspace_bytes": (_SZ, [_INT, _I64, _I64]),
     "pd_waveform_eval": (_INT, [_P, _I64, _INT, _GRID, _P, _INT, _P, _P, _P, _SZ, _P]),
     "pd_loglike_and_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _INT, _P, _P, _P, _P, _SZ, _P]),
+    "pd_loglike_and_grad_noalloc": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _INT, _P, _P, _P, _P]),
     "pd_fisher": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_mismatch_grad": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "pd_network_workspace_bytes": (_SZ, [_I64, _I64, _INT]),

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphenomd_hip.so")
-SOURCES = ["pd_kernels.hip", "pd_mismatch.hip", "pd_capi.hip", "pd_sampler.hip", "pd_flow.hip", "pd_overlap.hip", "pd_network.hip"]
+SOURCES = ["pd_kernels.hip", "pd_mismatch.hip", "pd_capi.hip", "pd_sampler.hip", "pd_flow.hip", "pd_overlap.hip", "pd_network.hip",
+           "pd_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
