@@ -403,9 +403,10 @@ int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, 
                int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Diagnostic: the kernels' own FP64 elementary functions applied elementwise, out[i] = fn(x[i])
- * for x [n], out [n] (device).  fn: PD_FN_SIN, PD_FN_COS (one shared argument reduction,
- * Cody-Waite with a three-part pi/2), PD_FN_ATAN, PD_FN_EXP, PD_FN_RCP (hardware estimate +
- * two Newton steps).  Exposed so that their ulp error can be measured against a
+ * for x [n], out [n] (device).  fn: PD_FN_SIN, PD_FN_COS (one shared argument reduction by
+ * pi/256 with a three-part split, then a 512-entry (sin, cos) table and short polynomials;
+ * |x| > 2^24 falls back to the device library), PD_FN_ATAN, PD_FN_EXP, PD_FN_RCP (hardware
+ * estimate + two Newton steps).  Exposed so that their ulp error can be measured against a
  * high-precision reference. */
 typedef enum { PD_FN_SIN = 0, PD_FN_COS = 1, PD_FN_ATAN = 2, PD_FN_EXP = 3, PD_FN_RCP = 4 } pd_fn;
 int pd_elementary_eval(int fn, const double* x, int64_t n, double* out, void* stream);

@@ -167,6 +167,48 @@ __device__ __forceinline__ void load_segments(const int* __restrict__ src, Segs&
     }
 }
 
+// Record accessor for the merger-ringdown loops of the fused likelihood: the record plus products of
+// its entries formed once per segment (FP64 products of two per-point constants would otherwise be
+// recomputed in every bin, as there is no scalar FP64 arithmetic).  The merger-ringdown amplitude
+// numerator R_AM3 is folded into the exponential recurrence by the caller.
+struct RecMRD {
+    const double* __restrict__ p;
+    double q_id;   // R_PH3+5 * R_ID: u = Mf R_ID - q_id
+    double g2;     // R_AM3+2 ^ 2
+    double c4id;   // R_PH3+4 * R_ID
+    double c3q;    // 3/4 R_PH3+3
+    double m2g;    // -2 R_AM3+2
+    __device__ __forceinline__ double operator[](int i) const { return p[i]; }
+};
+
+template <class RC>
+struct IsRecMRD {
+    static constexpr bool value = false;
+};
+template <>
+struct IsRecMRD<RecMRD> {
+    static constexpr bool value = true;
+};
+
+// Wave-uniform copy of a double (both halves from the first active lane).
+__device__ __forceinline__ double uniform_d(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<int>(static_cast<unsigned>(b)));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<int>(static_cast<unsigned>(b >> 32)));
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ RecMRD rec_mrd(const double* __restrict__ c) {
+    RecMRD r;
+    r.p = c;
+    r.q_id = uniform_d(c[R_PH3 + 5] * c[R_ID]);
+    r.g2 = uniform_d(c[R_AM3 + 2] * c[R_AM3 + 2]);
+    r.c4id = uniform_d(c[R_PH3 + 4] * c[R_ID]);
+    r.c3q = uniform_d(0.75 * c[R_PH3 + 3]);
+    r.m2g = uniform_d(-2.0 * c[R_AM3 + 2]);
+    return r;
+}
+
 // Everything one bin computes on the way to Ahat and Psi, kept for the visitors.
 struct BinVals {
     double mf;
@@ -213,16 +255,25 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
         // merger-ringdown phase: atan(u) needs one division (after its argument reduction), the
         // phase derivative 1/(1 + u^2), and in amplitude region 3 the Lorentzian 1/(x^2 + g^2):
         // all three come from one reciprocal of their product
+        constexpr bool D = IsRecMRD<RC>::value;
         const double invf = c[R_IMS] * T.at(T_INF, k);
         const double f34 = c[R_MS34] * T.at(T_F34, k);
-        const double u = (mf - c[R_PH3 + 5]) * c[R_ID];
+        double u;
+        if constexpr (D)
+            u = fma(mf, c[R_ID], -c.q_id);
+        else
+            u = (mf - c[R_PH3 + 5]) * c[R_ID];
         AtanParts ap = pd_atan_reduce(u);
         const double d1 = fma(u, u, 1.0);
         double d2 = 1.0, x = 0.0;
         if (AR == 3) {
             x = mf - c[R_AM3 + 1];
-            const double g = c[R_AM3 + 2];
-            d2 = fma(x, x, g * g);
+            if constexpr (D) {
+                d2 = fma(x, x, c.g2);
+            } else {
+                const double g = c[R_AM3 + 2];
+                d2 = fma(x, x, g * g);
+            }
         }
         const double p12 = d1 * d2;
         const double r = pd_rcp(ap.den * p12);
@@ -239,7 +290,10 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
             const double iden = rd * d1;
             b.x = x;
             b.iden = iden;
-            b.ahat = c[R_AM3 + 0] * iden * (HAVE_EX ? ex : pd_exp(-c[R_AM3 + 3] * x));
+            if constexpr (D && HAVE_EX)
+                b.ahat = iden * ex;   // ex carries the numerator R_AM3
+            else
+                b.ahat = c[R_AM3 + 0] * iden * (HAVE_EX ? ex : pd_exp(-c[R_AM3 + 3] * x));
         }
     }
     if (AR == 1) {
@@ -267,9 +321,10 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
 // multiply per bin; the relative drift after n steps is at most about n ulp.
 struct ExpRec {
     double e, r;
-    __device__ __forceinline__ void init(const double* __restrict__ c, const GridArgs& g, unsigned k_first) {
+    __device__ __forceinline__ void init(const double* __restrict__ c, const GridArgs& g, unsigned k_first,
+                                         double scale = 1.0) {
         const double c3 = c[R_AM3 + 3];
-        e = pd_exp(-c3 * (c[R_MS] * bin_freq(g, k_first) - c[R_AM3 + 1]));
+        e = scale * pd_exp(-c3 * (c[R_MS] * bin_freq(g, k_first) - c[R_AM3 + 1]));
         r = pd_exp(-c3 * (c[R_MS] * (64.0 * g.df)));
     }
     __device__ __forceinline__ double next() {
@@ -315,8 +370,9 @@ __host__ __device__ constexpr bool slot_touched(int pr, int ar, int s) {
 
 // Visit d Psi / d rec[s] (vis.ph), d ln A / d rec[s] (vis.am) and the explicit
 // Mf-dependence: Mf dPsi/dMf and Mf d lnA/dMf (vis.fd), for one bin.
-template <int PR, int AR, class V>
-__device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const BinVals& b, V& vis) {
+template <int PR, int AR, class V, class RC = const double*>
+__device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
+    constexpr bool D = IsRecMRD<RC>::value;
     double fpsi;
     if (PR == 1) {
         const double v = b.v, w = b.w, lv = b.lv;
@@ -349,7 +405,11 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         vis.ph(R_PH2 + 3, i3);
         fpsi = fma(c[R_PH2 + 1], b.mf, fma(c[R_PH2 + 3] * i3, sk(-3.0), c[R_PH2 + 2]));
     } else {
-        const double t = c[R_PH3 + 4] * b.iu2 * c[R_ID];
+        double t;
+        if constexpr (D)
+            t = c.c4id * b.iu2;
+        else
+            t = c[R_PH3 + 4] * b.iu2 * c[R_ID];
         vis.ph(R_PH3 + 0, 1.0);
         vis.ph(R_PH3 + 1, b.mf);
         vis.ph(R_PH3 + 2, b.invf);
@@ -357,7 +417,10 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
         vis.ph(R_PH3 + 4, b.at);
         vis.ph(R_PH3 + 5, -t);
         vis.ph(R_PH3 + 6, -t * b.u);
-        fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(c[R_PH3 + 3] * b.f34, sk(0.75), t * b.mf)));
+        if constexpr (D)
+            fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(c.c3q, b.f34, t * b.mf)));
+        else
+            fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(c[R_PH3 + 3] * b.f34, sk(0.75), t * b.mf)));
     }
     double fa;
     vis.am(R_LNA0, 1.0);
@@ -386,6 +449,14 @@ __device__ __forceinline__ void visit_bin_t(const double* __restrict__ c, const 
             acc = fma(static_cast<double>(i), c[R_AM2 + i] * p, acc);
         }
         fa = acc;
+    } else if constexpr (D) {
+        // the R_AM3 moment is R_IANUM times the ln A0 moment; the caller forms it after the loop
+        const double x = b.x, r = c[R_AM3 + 3];
+        const double txr = fma(x + x, b.iden, r);
+        vis.am(R_AM3 + 1, txr);
+        vis.am(R_AM3 + 2, c.m2g * b.iden);
+        vis.am(R_AM3 + 3, -x);
+        fa = -b.mf * txr;
     } else {
         const double x = b.x, g = c[R_AM3 + 2], r = c[R_AM3 + 3];
         const double tx = 2.0 * x * b.iden;

@@ -244,31 +244,43 @@ struct MomVis {
     __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] = fma(zi, fpsi, fma(zr, fa, mom[R_MS])); }
 };
 
-// One region segment of the likelihood loop.  MODE 0: (d|h), (h|h); MODE 1: + moments.
+// One region segment of the likelihood loop.  MODE 0: (d|h), (h|h); MODE 1: + moments.  The
+// moments are accumulated without the per-point amplitude factor a0p, which the caller applies
+// once to the wave totals.
 template <int MODE>
 struct LnlSegment {
     const double* __restrict__ rec;
     Tabs T;
     GridArgs g;
+    const double2* __restrict__ sct;   // (sin, cos) table in LDS
     int64_t k0, k1;
     int lane;
     double dh, hh, tot;
 
     template <int PR, int AR>
     __device__ __forceinline__ void run() {
+        if constexpr (PR == 3)
+            run_with<PR, AR>(rec_mrd(rec));
+        else
+            run_with<PR, AR>(rec);
+    }
+
+    template <int PR, int AR, class RC>
+    __device__ __forceinline__ void run_with(RC c) {
+        constexpr bool D = IsRecMRD<RC>::value;
         const double ms = rec[R_MS];
         const double a0p = rec[R_A0P];
         double mom[REC_N];
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
         ExpRec er{};
-        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane));
+        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane), D ? rec[R_AM3 + 0] : 1.0);
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
-            eval_bin_t<PR, AR, AR == 3>(rec, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
+            eval_bin_t<PR, AR, AR == 3>(c, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
             double sn, cs;
-            pd_sincos(bv.psi, &sn, &cs);
+            pd_sincos(bv.psi, &sn, &cs, sct);
             const double hr = bv.ahat * cs, hi = -bv.ahat * sn;
             const double dwr = T.at(T_DWR, k), dwi = T.at(T_DWI, k);
             const double px = fma(dwr, hr, dwi * hi);
@@ -277,11 +289,14 @@ struct LnlSegment {
             hh += q;
             if (MODE == 1) {
                 const double py = fma(dwr, hi, -dwi * hr);
-                MomVis vis{mom, a0p * fma(-a0p, q, px), a0p * py};
-                visit_bin_t<PR, AR>(rec, bv, vis);
+                MomVis vis{mom, fma(-a0p, q, px), py};
+                visit_bin_t<PR, AR>(c, bv, vis);
             }
         }
-        if (MODE == 1) flush_touched<PR, AR>(mom, lane, tot);
+        if (MODE == 1) {
+            if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
+            flush_touched<PR, AR>(mom, lane, tot);
+        }
     }
 };
 
@@ -294,6 +309,9 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
                                                          const int* __restrict__ perm,
                                                          double* __restrict__ partial_all) {
     constexpr int NS = (MODE == 0) ? 2 : kNSlot;
+    __shared__ double2 sct[kSinCosN];
+    stage_sincos_table(sct);
+    __syncthreads();
     double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * NS;
     const int lane = threadIdx.x & 63;
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
@@ -310,7 +328,7 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
     }
     Segs S;
     load_segments(segs + ((PRG - 1) * n * chunks + p * chunks + c) * kSegInts, S);
-    LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, 0, 0, lane, 0.0, 0.0, 0.0};
+    LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, sct, 0, 0, lane, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         if (uniform_i(S.k[i + 1]) > uniform_i(S.k[i]) && uniform_i(S.pr[i]) == PRG) {
@@ -324,7 +342,7 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
     const double r = halving_reduce<2>(dv, lane);
     if (lane == halving_lane<2>(0)) out[0] = r * a0p;
     if (lane == halving_lane<2>(1)) out[1] = r * (a0p * a0p);
-    if (MODE == 1 && lane < REC_N) out[2 + lane] = seg.tot;
+    if (MODE == 1 && lane < REC_N) out[2 + lane] = seg.tot * a0p;
 }
 
 // Value-only likelihood: one thread per point sums its (d|h), (h|h) partials over the region

@@ -7,8 +7,8 @@
 // correctly rounded values (fit_elementary.py, next to this file, writes both); the
 // measured worst error of each function is about 1 ulp.
 //
-//   pd_sincos  |x| <= 1e8 : q = rint(64x/pi), r = x - q pi/64 (three-part pi/64), short
-//              polynomials on |r| <= pi/128 combined with a 128-entry (sin, cos) table.
+//   pd_sincos  |x| <= 2^24: q = rint(256x/pi), r = x - q pi/256 (three-part pi/256), short
+//              polynomials on |r| <= pi/512 combined with a 512-entry (sin, cos) table.
 //              Larger |x| falls back to the device library's sincos.
 //   pd_atan    |u| > 1 uses pi/2 - atan(1/u); t > tan(pi/12) uses atan(t) = pi/6 +
 //              atan((sqrt3 t - 1)/(t + sqrt3)); both reductions share one division.
@@ -29,37 +29,48 @@ __device__ __forceinline__ double sk(double c) {
     return c;
 }
 
-// Table-driven sin and cos of one argument: x = k pi/64 + r with |r| <= pi/128 (three-part
-// pi/64, fused multiply-adds), j = k mod 128, and
+// Table-driven sin and cos of one argument: x = q pi/256 + r with |r| <= pi/512 (three-part
+// pi/256, fused multiply-adds), j = q mod 512, and
 //   sin x = S_j + (S_j (cos r - 1) + C_j sin r),  cos x = C_j + (C_j (cos r - 1) - S_j sin r)
-// with (S_j, C_j) = (sin, cos)(j pi/64) correctly rounded (pd_sincos_table.h) and Taylor
-// polynomials on the small interval (sin r through r^9, cos r - 1 through r^8; the first omitted
-// terms are below 1e-19 relative).  About 1 ulp.  |x| > 1e8 uses the device library.
-constexpr double kTs1 = -1.0 / 6.0, kTs2 = 1.0 / 120.0, kTs3 = -1.0 / 5040.0, kTs4 = 1.0 / 362880.0;
-constexpr double kTc1 = -0.5, kTc2 = 1.0 / 24.0, kTc3 = -1.0 / 720.0, kTc4 = 1.0 / 40320.0;
+// with (S_j, C_j) = (sin, cos)(j pi/256) correctly rounded (pd_sincos_table.h) and Taylor
+// polynomials on the small interval (sin r through r^5, cos r - 1 through r^6; the first omitted
+// terms are below 1.1e-17 and 2e-22 relative).  About 1 ulp.  |x| > 2^24 uses the device library.
+constexpr double kTs1 = -1.0 / 6.0, kTs2 = 1.0 / 120.0;
+constexpr double kTc1 = -0.5, kTc2 = 1.0 / 24.0, kTc3 = -1.0 / 720.0;
 
-__device__ __forceinline__ void pd_sincos(double x, double* s_out, double* c_out) {
-    if (!(fabs(x) <= sk(1e8))) {
+// TAB: the (sin, cos) table, in constant memory (default) or a copy staged in LDS by the caller.
+// The quotient is rounded with the 1.5 * 2^52 shift: fma(x, 256/pi, 1.5 * 2^52) rounds x 256/pi to
+// the nearest integer (ties to even, the product unrounded) and leaves it in the low mantissa bits,
+// so the table index is a bit mask of the low word; |x| <= 2^24 keeps it far inside 2^51.
+constexpr double kRoundShift = 6755399441055744.0;   // 1.5 * 2^52
+
+__device__ __forceinline__ void pd_sincos(double x, double* s_out, double* c_out,
+                                          const double2* __restrict__ tab = reinterpret_cast<const double2*>(kSinCosTab)) {
+    if (!(fabs(x) <= sk(16777216.0))) {
         sincos(x, s_out, c_out);
         return;
     }
-    const double q = rint(x * sk(k64OverPi));
-    double r = fma(-q, sk(kPi64_1), x);
-    r = fma(-q, sk(kPi64_2), r);
-    r = fma(-q, sk(kPi64_3), r);
-    const unsigned j = static_cast<unsigned>(static_cast<int>(q)) & 127u;
-    const double2 sc = reinterpret_cast<const double2*>(kSinCosTab)[j];
+    const double qs = fma(x, sk(kInvPiStep), sk(kRoundShift));
+    const double q = qs - sk(kRoundShift);
+    double r = fma(-q, sk(kPiStep_1), x);
+    r = fma(-q, sk(kPiStep_2), r);
+    r = fma(-q, sk(kPiStep_3), r);
+    const unsigned j = static_cast<unsigned>(__builtin_bit_cast(unsigned long long, qs)) &
+                       static_cast<unsigned>(kSinCosN - 1);
+    const double2 sc = tab[j];
     const double z = r * r;
-    double ps = fma(sk(kTs4), z, sk(kTs3));
-    ps = fma(ps, z, sk(kTs2));
-    ps = fma(ps, z, sk(kTs1));
-    const double sr = fma(r * z, ps, r);
-    double pc = fma(sk(kTc4), z, sk(kTc3));
-    pc = fma(pc, z, sk(kTc2));
+    const double sr = fma(r * z, fma(sk(kTs2), z, sk(kTs1)), r);
+    double pc = fma(sk(kTc3), z, sk(kTc2));
     pc = fma(pc, z, sk(kTc1));
     const double cm = z * pc;
     *s_out = sc.x + fma(sc.y, sr, sc.x * cm);
     *c_out = sc.y + fma(-sc.x, sr, sc.y * cm);
+}
+
+// Copy of the (sin, cos) table in LDS, filled cooperatively by a block.
+__device__ __forceinline__ void stage_sincos_table(double2* __restrict__ lds) {
+    for (unsigned i = threadIdx.x; i < static_cast<unsigned>(kSinCosN); i += blockDim.x)
+        lds[i] = reinterpret_cast<const double2*>(kSinCosTab)[i];
 }
 
 // Reciprocal and quotient for normal-range operands: hardware reciprocal estimate, two
