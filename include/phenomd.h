@@ -141,9 +141,10 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid,
 
 /* Mismatch against fixed targets and its gradient w.r.t. the 209 fit coefficients,
  * Sec. 3.1 Eqs. 5 and 7:
- *   z_j = sum_k w_k conj(h_k) t_k exp(+2 pi i k j / N), j < N = n_bins = 65536,
+ *   z_j = sum_k w_k conj(h_k) t_k exp(+2 pi i k j / N), j < N = n_bins,
  *   m = max_j |z_j| / sqrt((h|h)(t|t)),  M = 1 - m   (max over lag and phase),
  *   dsum_dlambda = sum over targets of dM / dlambda at the maximising lag.
+ * n_bins must be a power of two from 2^6 to 2^16 (the FFT length; PD_EUNSUPPORTED otherwise).
  * theta        [nt][7]           source of each target (layout `param`)
  * targets      [nt][n_bins][2]   target strains t_k, complex128
  * inv_psd      [n_bins]          1 / S_n (use ones for a flat PSD)
@@ -305,10 +306,11 @@ size_t pd_hmc_workspace_bytes(const pd_posterior* post, int64_t n);
 
 /* One Hamiltonian Monte Carlo transition for n independent chains (Sec. 3.3; leapfrog
  * integrator with a diagonal mass matrix, Metropolis accept on the Hamiltonian):
- *   p = sqrt(mass) xi;  n_leapfrog leapfrog steps of size eps;  accept if log u < -dH.
+ *   p ~ N(0, diag(mass));  n_leapfrog leapfrog steps of size eps;  accept if log u < -dH,
+ * with H = -log pi(x) + sum_j p_j^2 / (2 mass_j).
  * x [n][7], logp [n], grad [n][7]   in/out: the chains' state with its cached log pi and
  *                                   gradient (from pd_posterior_logp or a previous step)
- * xi [n][7]      standard-normal momentum draws;  u [n] uniform(0,1) draws
+ * xi [n][7]      standard-normal momentum draws (p_j = sqrt(mass_j) xi_j);  u [n] uniform(0,1) draws
  * mass [7]       HOST array, diagonal mass matrix
  * accepted [n]   out (or NULL): 1 accepted, 0 rejected, -1 rejected as divergent
  *                (non-finite dH or |dH| > 1000)
@@ -317,6 +319,16 @@ size_t pd_hmc_workspace_bytes(const pd_posterior* post, int64_t n);
 int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
                 const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted,
                 double* dh, void* workspace, size_t workspace_bytes, void* stream);
+
+/* As pd_hmc_step with a dense metric: the inverse mass matrix (the covariance the momenta move
+ * along) is L L^T for the row-major lower-triangular chol [7][7] (HOST array, positive diagonal;
+ * entries above the diagonal are ignored), i.e. p ~ N(0, (L L^T)^-1) and
+ * H = -log pi(x) + p^T L L^T p / 2.  The chains carry r = L^T p = xi, so the drift is
+ * x += eps L r and the kick r += eps L^T grad log pi.  With L the Cholesky factor of the posterior
+ * covariance the trajectories see an isotropic target.  Workspace as pd_hmc_workspace_bytes. */
+int pd_hmc_step_dense(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
+                      const double* u, int n_leapfrog, double eps, const double* chol, int32_t* accepted,
+                      double* dh, void* workspace, size_t workspace_bytes, void* stream);
 
 size_t pd_rwmh_workspace_bytes(const pd_posterior* post, int64_t n);
 
@@ -333,6 +345,13 @@ size_t pd_rwmh_workspace_bytes(const pd_posterior* post, int64_t n);
  */
 int pd_rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
                  const double* scale, int32_t* accepted, void* workspace, size_t workspace_bytes, void* stream);
+
+/* As pd_rwmh_step with correlated Gaussian steps x' = x + L xi, the proposal covariance L L^T
+ * given by the row-major lower-triangular chol [7][7] (HOST array, finite; entries above the
+ * diagonal are ignored).  Workspace as pd_rwmh_workspace_bytes. */
+int pd_rwmh_step_dense(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi,
+                       const double* u, const double* chol, int32_t* accepted, void* workspace, size_t workspace_bytes,
+                       void* stream);
 
 /* Independence Metropolis-Hastings accept (the learned proposal of the sampler): for each
  * chain, accept x' (drawn from q) with probability min(1, pi(x') q(x) / (pi(x) q(x'))).

@@ -11,6 +11,10 @@ Sec. 3.3 of the paper samples the 7-parameter posterior with Hamiltonian Monte C
   * HMC (Neal 2011): p = sqrt(m) xi, H = -log pi(x) + p^2/(2m) summed, leapfrog with a half
     kick at each end, accept if log u < -(H_end - H_start); non-finite or |dH| > 1000 is
     rejected as divergent;
+  * HMC with a dense metric: momenta p ~ N(0, M) with inverse mass matrix M^-1 = L L^T for a
+    lower-triangular L, drawn as p = L^-T xi (a triangular solve), H = -log pi + p^T M^-1 p / 2,
+    the drift x += eps M^-1 p (Neal 2011, Sec. 5.4.1: a mass matrix is a linear change of
+    coordinates);
   * the two-detector posterior of the paper's injection: the network likelihood of
     network_oracle with (iota, psi, ra, dec) held fixed;
   * random-walk Metropolis-Hastings, the baseline Sec. 3.3 compares HMC with (Metropolis et al.
@@ -108,11 +112,52 @@ def hmc_step(logp_fn, x, lp, grad, xi, u, n_steps, eps, mass):
     return x, lp, grad, 0, dh
 
 
+def leapfrog_dense(logp_fn, x, p, grad, n_steps, eps, minv):
+    """Leapfrog with inverse mass matrix minv [7][7]; returns (x, p, logp, grad)."""
+    x = np.array(x, dtype=np.float64)
+    p = np.array(p, dtype=np.float64) + 0.5 * eps * grad
+    lp = None
+    for step in range(n_steps):
+        x = x + eps * (minv @ p)
+        lp, grad = logp_fn(x)
+        w = eps if step + 1 < n_steps else 0.5 * eps
+        p = p + w * grad
+    return x, p, lp, grad
+
+
+def hmc_step_dense(logp_fn, x, lp, grad, xi, u, n_steps, eps, chol):
+    """One HMC transition with inverse mass matrix L L^T (chol = L, lower triangular) and the
+    momentum p = L^-T xi; returns (x, logp, grad, accepted (1/0/-1), dH)."""
+    L = np.tril(np.asarray(chol, dtype=np.float64))
+    minv = L @ L.T
+    p0 = np.linalg.solve(L.T, np.asarray(xi, dtype=np.float64))
+    h0 = -lp + 0.5 * float(p0 @ minv @ p0)
+    x1, p1, lp1, g1 = leapfrog_dense(logp_fn, x, p0, grad, n_steps, eps, minv)
+    h1 = -lp1 + 0.5 * float(p1 @ minv @ p1)
+    dh = h1 - h0
+    if not np.isfinite(dh) or abs(dh) > 1000.0:
+        return x, lp, grad, -1, dh
+    if math.log(u) < -dh:
+        return x1, lp1, g1, 1, dh
+    return x, lp, grad, 0, dh
+
+
 def rwmh_step(logp_fn, x, lp, xi, u, scale):
     """One random-walk MH transition with step x' = x + scale * xi; returns (x, logp, accepted).
     logp_fn returns log pi at a point (a non-finite value rejects the proposal; a current
     state with non-finite log pi takes any finite proposal)."""
     xp = np.asarray(x, dtype=np.float64) + np.asarray(scale, dtype=np.float64) * np.asarray(xi, dtype=np.float64)
+    lpp = logp_fn(xp)
+    if np.isfinite(lpp) and (math.log(u) < lpp - lp or not np.isfinite(lp)):
+        return xp, lpp, 1
+    return np.array(x, dtype=np.float64), lp, 0
+
+
+def rwmh_step_dense(logp_fn, x, lp, xi, u, chol):
+    """Random-walk MH with a correlated Gaussian step x' = x + L xi (L = chol, lower
+    triangular); returns (x, logp, accepted)."""
+    L = np.tril(np.asarray(chol, dtype=np.float64))
+    xp = np.asarray(x, dtype=np.float64) + L @ np.asarray(xi, dtype=np.float64)
     lpp = logp_fn(xp)
     if np.isfinite(lpp) and (math.log(u) < lpp - lp or not np.isfinite(lp)):
         return xp, lpp, 1

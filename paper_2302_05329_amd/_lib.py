@@ -105,10 +105,14 @@ SIGNATURES = {
     "pd_hmc_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
     "pd_hmc_step": (_INT, [ctypes.c_void_p, _I64, _P, _P, _P, _P, _P, _INT, ctypes.c_double,
                            ctypes.POINTER(ctypes.c_double), _P, _P, _P, _SZ, _P]),
+    "pd_hmc_step_dense": (_INT, [ctypes.c_void_p, _I64, _P, _P, _P, _P, _P, _INT, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double), _P, _P, _P, _SZ, _P]),
     "pd_independence_mh": (_INT, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pd_rwmh_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
     "pd_rwmh_step": (_INT, [ctypes.c_void_p, _I64, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P, _P, _SZ,
                             _P]),
+    "pd_rwmh_step_dense": (_INT, [ctypes.c_void_p, _I64, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double), _P, _P,
+                                  _SZ, _P]),
     "pd_elementary_eval": (_INT, [_INT, _P, _I64, _P, _P]),
     "pd_overlap_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
     "pd_overlap": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _I64, _P, _P, _P, _P, _P, _SZ, _P]),

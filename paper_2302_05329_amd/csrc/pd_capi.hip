@@ -376,7 +376,8 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
     if (!targets) return fail(PD_EINVAL, "targets is NULL");
     if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
     if (!mismatch) return fail(PD_EINVAL, "mismatch is NULL");
-    if (g.nb != pd::kFFTN) return fail(PD_EUNSUPPORTED, "mismatch needs n_bins = 65536 (the FFT length)");
+    if ((g.nb & (g.nb - 1)) != 0 || g.nb < (int64_t(1) << pd::kFFTMinLog2) || g.nb > (int64_t(1) << pd::kFFTMaxLog2))
+        return fail(PD_EUNSUPPORTED, "mismatch needs n_bins = 2^n, 6 <= n <= 16 (the FFT length)");
     Layout L;
     rc = check_ws(PD_OP_MISMATCH_GRAD, nt, g.nb, workspace, workspace_bytes, &L);
     if (rc) return rc;
@@ -574,6 +575,44 @@ int pd_fit_lambda_step(const double* theta, int64_t nt, int param, const pd_grid
     return PD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+int hmc_common(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
+               const double* u, int n_leapfrog, double eps, const double* mass, const double* chol, int32_t* accepted,
+               double* dh, void* workspace, size_t workspace_bytes, void* stream) {
+    if (pd::posterior_check(post) != PD_OK) return fail(PD_EINVAL, "invalid posterior description");
+    if (!x || !logp || !grad || !xi || !u) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    if (n_leapfrog < 1 || n_leapfrog > 100000) return fail(PD_EINVAL, "n_leapfrog out of range");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(PD_EINVAL, "eps must be finite and > 0");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    if (workspace_bytes < pd::hmc_workspace_bytes(post, n)) return fail(PD_ENOMEM, "workspace too small");
+    const int rc = pd::hmc_step(post, n, x, logp, grad, xi, u, n_leapfrog, eps, mass, chol, accepted, dh, workspace,
+                                static_cast<hipStream_t>(stream));
+    if (rc != PD_OK) return fail(rc, "hmc step failed");
+    return PD_OK;
+}
+
+int rwmh_common(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
+                const double* scale, const double* chol, int32_t* accepted, void* workspace, size_t workspace_bytes,
+                void* stream) {
+    if (pd::posterior_check(post) != PD_OK) return fail(PD_EINVAL, "invalid posterior description");
+    if (!x || !logp || !xi || !u) return fail(PD_EINVAL, "NULL argument");
+    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
+    if (workspace_bytes < pd::rwmh_workspace_bytes(post, n)) return fail(PD_ENOMEM, "workspace too small");
+    const int rc = pd::rwmh_step(post, n, x, logp, xi, u, scale, chol, accepted, workspace,
+                                 static_cast<hipStream_t>(stream));
+    if (rc != PD_OK) return fail(rc, "random-walk step failed");
+    return PD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t pd_posterior_workspace_bytes(const pd_posterior* post, int64_t n) {
     if (pd::posterior_check(post) != PD_OK || n <= 0) return 0;
     return pd::posterior_ws_bytes(post, n);
@@ -599,19 +638,24 @@ int pd_posterior_logp(const pd_posterior* post, const double* x, int64_t n, doub
 int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
                 const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
                 void* workspace, size_t workspace_bytes, void* stream) {
-    if (pd::posterior_check(post) != PD_OK) return fail(PD_EINVAL, "invalid posterior description");
-    if (!x || !logp || !grad || !xi || !u || !mass) return fail(PD_EINVAL, "NULL argument");
-    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
-    if (n_leapfrog < 1 || n_leapfrog > 100000) return fail(PD_EINVAL, "n_leapfrog out of range");
-    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(PD_EINVAL, "eps must be finite and > 0");
+    if (!mass) return fail(PD_EINVAL, "NULL argument");
     for (int j = 0; j < 7; ++j)
         if (!(mass[j] > 0.0) || !std::isfinite(mass[j])) return fail(PD_EINVAL, "mass must be finite and > 0");
-    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
-    if (workspace_bytes < pd::hmc_workspace_bytes(post, n)) return fail(PD_ENOMEM, "workspace too small");
-    const int rc = pd::hmc_step(post, n, x, logp, grad, xi, u, n_leapfrog, eps, mass, accepted, dh, workspace,
-                                static_cast<hipStream_t>(stream));
-    if (rc != PD_OK) return fail(rc, "hmc step failed");
-    return PD_OK;
+    return hmc_common(post, n, x, logp, grad, xi, u, n_leapfrog, eps, mass, nullptr, accepted, dh, workspace,
+                      workspace_bytes, stream);
+}
+
+int pd_hmc_step_dense(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
+                      const double* u, int n_leapfrog, double eps, const double* chol, int32_t* accepted, double* dh,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+    if (!chol) return fail(PD_EINVAL, "NULL argument");
+    for (int j = 0; j < 7; ++j) {
+        if (!(chol[j * 7 + j] > 0.0)) return fail(PD_EINVAL, "chol must have a positive diagonal");
+        for (int k = 0; k <= j; ++k)
+            if (!std::isfinite(chol[j * 7 + k])) return fail(PD_EINVAL, "chol must be finite");
+    }
+    return hmc_common(post, n, x, logp, grad, xi, u, n_leapfrog, eps, nullptr, chol, accepted, dh, workspace,
+                      workspace_bytes, stream);
 }
 
 size_t pd_rwmh_workspace_bytes(const pd_posterior* post, int64_t n) {
@@ -621,16 +665,20 @@ size_t pd_rwmh_workspace_bytes(const pd_posterior* post, int64_t n) {
 
 int pd_rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
                  const double* scale, int32_t* accepted, void* workspace, size_t workspace_bytes, void* stream) {
-    if (pd::posterior_check(post) != PD_OK) return fail(PD_EINVAL, "invalid posterior description");
-    if (!x || !logp || !xi || !u || !scale) return fail(PD_EINVAL, "NULL argument");
-    if (n <= 0 || n > (int64_t(1) << 31) / 64) return fail(PD_EINVAL, "bad n");
+    if (!scale) return fail(PD_EINVAL, "NULL argument");
     for (int j = 0; j < 7; ++j)
         if (!(scale[j] >= 0.0) || !std::isfinite(scale[j])) return fail(PD_EINVAL, "scale must be finite and >= 0");
-    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(PD_EINVAL, "bad workspace");
-    if (workspace_bytes < pd::rwmh_workspace_bytes(post, n)) return fail(PD_ENOMEM, "workspace too small");
-    const int rc = pd::rwmh_step(post, n, x, logp, xi, u, scale, accepted, workspace, static_cast<hipStream_t>(stream));
-    if (rc != PD_OK) return fail(rc, "random-walk step failed");
-    return PD_OK;
+    return rwmh_common(post, n, x, logp, xi, u, scale, nullptr, accepted, workspace, workspace_bytes, stream);
+}
+
+int pd_rwmh_step_dense(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi,
+                       const double* u, const double* chol, int32_t* accepted, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+    if (!chol) return fail(PD_EINVAL, "NULL argument");
+    for (int j = 0; j < 7; ++j)
+        for (int k = 0; k <= j; ++k)
+            if (!std::isfinite(chol[j * 7 + k])) return fail(PD_EINVAL, "chol must be finite");
+    return rwmh_common(post, n, x, logp, xi, u, nullptr, chol, accepted, workspace, workspace_bytes, stream);
 }
 
 int pd_independence_mh(int64_t n, double* x, double* logp, double* logq, double* grad, const double* xp,

@@ -79,8 +79,9 @@ int posterior_check(const pd_posterior* post);
 size_t posterior_ws_bytes(const pd_posterior* post, int64_t n);
 size_t hmc_workspace_bytes(const pd_posterior* post, int64_t n);
 size_t rwmh_workspace_bytes(const pd_posterior* post, int64_t n);
+// scale: per-coordinate step [7] (chol NULL); chol: row-major lower-triangular L [7][7], steps L xi
 int rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
-              const double* scale, int32_t* accepted, void* ws, hipStream_t s);
+              const double* scale, const double* chol, int32_t* accepted, void* ws, hipStream_t s);
 // concurrent: run the record tangents and two of the three region launches on side streams (created
 // once per host thread and device); false keeps every launch on `s` and creates nothing.
 int loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
@@ -91,9 +92,11 @@ size_t op_workspace_bytes(int op, int64_t n, int64_t n_bins);
 void set_last_error(const char* msg);
 int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,
                    hipStream_t s, bool tables_ready = false);
+// mass: diagonal mass matrix [7] (chol NULL); chol: row-major lower-triangular L [7][7] with inverse
+// mass matrix L L^T (mass ignored)
 int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
-             const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
-             void* ws, hipStream_t s);
+             const double* u, int n_leapfrog, double eps, const double* mass, const double* chol, int32_t* accepted,
+             double* dh, void* ws, hipStream_t s);
 int independence_mh(int64_t n, double* x, double* logp, double* logq, double* grad, const double* xp,
                     const double* logp_p, const double* logq_p, const double* grad_p, const double* u,
                     int32_t* accepted, hipStream_t s);

@@ -10,9 +10,10 @@
 
 namespace pd {
 
-constexpr int64_t kFFTN = 65536;   // overlap length: 256 x 256 four-step
-constexpr int kFFTR = 256;
-constexpr int kFFTCols = 16;       // columns per FFT block
+// Overlap lengths: N = 2^n bins, kFFTMinLog2 <= n <= kFFTMaxLog2, computed as an N1 x N2 four-step
+// FFT with N1 = 2^ceil(n/2) columns of length N2 = 2^floor(n/2) (at most 256 x 256).
+constexpr int kFFTMinLog2 = 6;
+constexpr int kFFTMaxLog2 = 16;
 constexpr int kSlotMM = 8;         // per-target scalars: A, B, |z|, zr, zi, lag, mismatch, pad
 
 size_t mismatch_scratch_bytes(int64_t nt, int64_t nb);

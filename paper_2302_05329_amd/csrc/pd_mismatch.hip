@@ -2,14 +2,15 @@
 // (paper Sec. 3.1: Eq. 5, averaged over targets in Eq. 7; the maximum
 // over the coalescence time is taken with a Fourier transform, Sec. 2).
 //
-// Pipeline per target (N = 65536 = 256 x 256):
+// Pipeline per target (N = N1 x N2 bins, a power of two from 2^6 to 2^16 = 256 x 256):
 //   1. overlap input   x_k = w_k conj(h_k) t_k (model recomputed per bin), partial
 //                      sums of (h|h) and (t|t)                         one thread / bin
-//   2. column pass     256-point inverse DFTs over k2 of x[k1 + 256 k2] in LDS
+//   2. column pass     N2-point inverse DFTs over k2 of x[k1 + N1 k2] in LDS
 //                      (radix-2 Stockham), twiddle exp(2 pi i j2 k1 / N), store
-//                      transposed                                      8 columns / block
-//   3. row pass        256-point inverse DFTs over k1, |z|^2 and arg-max fused; the
-//                      overlap series itself is never written           8 rows / block
+//                      transposed                                      2048 / N2 columns / block
+//   3. row pass        N1-point inverse DFTs over k1, |z|^2 and arg-max fused (lag
+//                      j = j2 + N2 j1); the overlap series itself is never written
+//                                                                      2048 / N1 rows / block
 //   4. finalize        lag j*, |z_j*|, mismatch                         one thread / target
 //   5. adjoint         moments of the mismatch adjoint per bin (model recomputed, no
 //                      per-bin storage)                                 one wave / (target, chunk)
@@ -27,13 +28,34 @@ namespace pd {
 
 namespace {
 
-constexpr int kCols = 8;   // columns (or rows) per FFT block; 2 x 32 KiB LDS ping-pong
+// Four-step plan of one overlap length.
+struct FFTPlan {
+    int64_t n;          // N
+    int n1, n2;         // columns (row length) and column length
+    int cb, rb;         // columns per column-pass block, rows per row-pass block
+    int ibl;            // input blocks per target (256 bins each)
+};
+
+constexpr int kLdsPts = 2048;   // complex points per LDS buffer (2 x 32 KiB ping-pong)
+
+inline FFTPlan make_plan(int64_t n) {
+    FFTPlan f;
+    f.n = n;
+    int lg = 0;
+    while ((int64_t(1) << lg) < n) ++lg;
+    f.n1 = 1 << ((lg + 1) / 2);
+    f.n2 = 1 << (lg / 2);
+    f.cb = kLdsPts / f.n2 < f.n1 ? kLdsPts / f.n2 : f.n1;
+    f.rb = kLdsPts / f.n1 < f.n2 ? kLdsPts / f.n1 : f.n2;
+    f.ibl = static_cast<int>((n + 255) / 256);
+    return f;
+}
 
 struct MMScratch {
     double2* X;       // [nt][N]
-    double2* Y;       // [nt][256][256] (transposed after the column pass)
-    double* ab;       // [nt][N/256][2]
-    double* mx;       // [nt][256/kCols][4]  (|z|^2, index, zr, zi)
+    double2* Y;       // [nt][N2][N1] (transposed after the column pass)
+    double* ab;       // [nt][ibl][2]
+    double* mx;       // [nt][N2 / rb][4]  (|z|^2, index, zr, zi)
     double* scal;     // [nt][kSlotMM]
     double* mom;      // [nt][chunks][kNSlot]
     double* dlam;     // [nt][19]
@@ -44,43 +66,28 @@ struct MMScratch {
 constexpr size_t kAl = 256;
 inline size_t al(size_t x) { return (x + kAl - 1) / kAl * kAl; }
 
-MMScratch carve(void* base, int64_t nt, int64_t nb) {
-    MMScratch m;
+// Carves the scratch (base may be null: then only the size is computed).
+size_t carve_into(void* base, int64_t nt, int64_t nb, MMScratch* m) {
+    const FFTPlan f = make_plan(nb);
     char* p = static_cast<char*>(base);
     size_t off = 0;
     const size_t n = static_cast<size_t>(nt);
-    m.chunks = chunks_for(nt, nb);
-    m.X = reinterpret_cast<double2*>(p + off);
-    off = al(off + n * kFFTN * sizeof(double2));
-    m.Y = reinterpret_cast<double2*>(p + off);
-    off = al(off + n * kFFTN * sizeof(double2));
-    m.ab = reinterpret_cast<double*>(p + off);
-    off = al(off + n * (kFFTN / 256) * 2 * sizeof(double));
-    m.mx = reinterpret_cast<double*>(p + off);
-    off = al(off + n * (kFFTR / kCols) * 4 * sizeof(double));
-    m.scal = reinterpret_cast<double*>(p + off);
-    off = al(off + n * kSlotMM * sizeof(double));
-    m.mom = reinterpret_cast<double*>(p + off);
-    off = al(off + 3 * n * m.chunks * kNSlot * sizeof(double));
-    m.dlam = reinterpret_cast<double*>(p + off);
-    off = al(off + n * kNumFit * sizeof(double));
-    m.mred = reinterpret_cast<double*>(p + off);
-    off = al(off + n * REC_N * sizeof(double));
-    return m;
-}
-
-size_t carve_size(int64_t nt, int64_t nb) {
-    const size_t n = static_cast<size_t>(nt);
-    const int chunks = chunks_for(nt, nb);
-    size_t off = 0;
-    off = al(off + n * kFFTN * sizeof(double2));
-    off = al(off + n * kFFTN * sizeof(double2));
-    off = al(off + n * (kFFTN / 256) * 2 * sizeof(double));
-    off = al(off + n * (kFFTR / kCols) * 4 * sizeof(double));
-    off = al(off + n * kSlotMM * sizeof(double));
-    off = al(off + 3 * n * chunks * kNSlot * sizeof(double));
-    off = al(off + n * kNumFit * sizeof(double));
-    off = al(off + n * REC_N * sizeof(double));
+    auto take = [&](size_t bytes) {
+        char* q = p ? p + off : nullptr;
+        off = al(off + bytes);
+        return q;
+    };
+    MMScratch t;
+    t.chunks = chunks_for(nt, nb);
+    t.X = reinterpret_cast<double2*>(take(n * f.n * sizeof(double2)));
+    t.Y = reinterpret_cast<double2*>(take(n * f.n * sizeof(double2)));
+    t.ab = reinterpret_cast<double*>(take(n * f.ibl * 2 * sizeof(double)));
+    t.mx = reinterpret_cast<double*>(take(n * (f.n2 / f.rb) * 4 * sizeof(double)));
+    t.scal = reinterpret_cast<double*>(take(n * kSlotMM * sizeof(double)));
+    t.mom = reinterpret_cast<double*>(take(3 * n * t.chunks * kNSlot * sizeof(double)));
+    t.dlam = reinterpret_cast<double*>(take(n * kNumFit * sizeof(double)));
+    t.mred = reinterpret_cast<double*>(take(n * REC_N * sizeof(double)));
+    if (m) *m = t;
     return off;
 }
 
@@ -100,18 +107,19 @@ __global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ rec
                                                   const double* __restrict__ tab,
                                                   const double* __restrict__ targets,
                                                   const double* __restrict__ inv_psd, double2* __restrict__ X,
-                                                  double* __restrict__ ab) {
+                                                  double* __restrict__ ab, int blocks) {
     __shared__ double red[2][4];
-    const int64_t blocks = kFFTN / 256;
+    const int64_t N = g.nb;
     const int64_t p = blockIdx.x / blocks;
     const int64_t kb = (blockIdx.x % blocks) * 256;
     const int64_t k = kb + threadIdx.x;
+    const bool in = k < N;
     const double* __restrict__ rec = recs + p * REC_N;
     const Tabs T(tab, g.nb);
-    const double2 t = reinterpret_cast<const double2*>(targets)[p * kFFTN + k];
-    const double w = 4.0 * g.df * inv_psd[k];
+    const double2 t = in ? reinterpret_cast<const double2*>(targets)[p * N + k] : make_double2(0.0, 0.0);
+    const double w = in ? 4.0 * g.df * inv_psd[k] : 0.0;
     double2 h = make_double2(0.0, 0.0);
-    if (rec[R_VALID] != 0.0) {
+    if (in && rec[R_VALID] != 0.0) {
         const double f = bin_freq(g, k);
         const double mf = rec[R_MS] * f;
         if (bin_active(g, f, mf)) {
@@ -124,7 +132,7 @@ __global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ rec
         }
     }
     // x = w conj(h) t
-    X[p * kFFTN + k] = make_double2(w * (h.x * t.x + h.y * t.y), w * (h.x * t.y - h.y * t.x));
+    if (in) X[p * N + k] = make_double2(w * (h.x * t.x + h.y * t.y), w * (h.x * t.y - h.y * t.x));
     const double a = wave_sum(w * (h.x * h.x + h.y * h.y));
     const double b = wave_sum(w * (t.x * t.x + t.y * t.y));
     const int wid = threadIdx.x >> 6;
@@ -140,72 +148,77 @@ __global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ rec
     }
 }
 
-// ---- LDS radix-2 Stockham inverse DFT of length 256 on kCols columns -----------------
-// buf/tmp: [kCols][256]; 32 threads per column, 4 butterflies each per stage.
-// Returns the buffer that holds the result (always `buf` after 8 stages).
-__device__ __forceinline__ void lds_idft256(double2 (*buf)[kFFTR], double2 (*tmp)[kFFTR],
-                                            const double2* __restrict__ tw) {
-    const int col = threadIdx.x >> 5;
-    const int r = threadIdx.x & 31;
-    double2(*x)[kFFTR] = buf;
-    double2(*y)[kFFTR] = tmp;
-    int n = kFFTR, s = 1;
+// ---- LDS radix-2 Stockham inverse DFT of length LEN on `cols` columns -------------------
+// buf/tmp: cols x LEN points (column c at c * LEN); the block's 256 threads share the cols x LEN/2
+// butterflies of each stage.  The result ends in `buf` when log2(LEN) is even, else in `tmp`;
+// the returned pointer says which.
+template <int LEN>
+__device__ __forceinline__ double2* lds_idft(double2* buf, double2* tmp, int cols, const double2* __restrict__ tw) {
+    double2* x = buf;
+    double2* y = tmp;
+    int n = LEN, s = 1;
+    const int nb = cols * (LEN / 2);
 #pragma unroll
-    for (int stage = 0; stage < 8; ++stage) {
+    for (int stage = 0; (1 << stage) < LEN; ++stage) {
         const int m = n >> 1;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int b = r + 32 * i;        // butterfly index in [0, 128)
+        for (int idx = threadIdx.x; idx < nb; idx += 256) {
+            const int col = idx / (LEN / 2);
+            const int b = idx - col * (LEN / 2);   // butterfly index in [0, LEN/2)
             const int q = b % s;
             const int pp = b / s;
-            const double2 a = x[col][q + s * pp];
-            const double2 c = x[col][q + s * (pp + m)];
-            const double2 w = tw[pp * (kFFTR / n)];    // exp(2 pi i pp / n)
-            y[col][q + s * (2 * pp)] = make_double2(a.x + c.x, a.y + c.y);
-            y[col][q + s * (2 * pp + 1)] = cmul(make_double2(a.x - c.x, a.y - c.y), w);
+            const double2* xc = x + col * LEN;
+            double2* yc = y + col * LEN;
+            const double2 a = xc[q + s * pp];
+            const double2 c = xc[q + s * (pp + m)];
+            const double2 w = tw[pp * (LEN / n)];    // exp(2 pi i pp / n)
+            yc[q + s * (2 * pp)] = make_double2(a.x + c.x, a.y + c.y);
+            yc[q + s * (2 * pp + 1)] = cmul(make_double2(a.x - c.x, a.y - c.y), w);
         }
         __syncthreads();
-        double2(*t)[kFFTR] = x;
+        double2* t = x;
         x = y;
         y = t;
         n = m;
         s <<= 1;
     }
+    return x;
 }
 
+template <int LEN>
 __device__ __forceinline__ void fill_twiddles(double2* tw) {
-    const int j = threadIdx.x;   // blockDim = 256
-    double sn, cs;
-    sincospi(2.0 * j / 256.0, &sn, &cs);
-    tw[j] = make_double2(cs, sn);
+    for (int j = threadIdx.x; j < LEN; j += 256) {
+        double sn, cs;
+        sincospi(2.0 * j / static_cast<double>(LEN), &sn, &cs);
+        tw[j] = make_double2(cs, sn);
+    }
 }
 
 // ---- 2. column pass ------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_mm_fft_cols(const double2* __restrict__ X, double2* __restrict__ Y) {
-    __shared__ double2 buf[kCols][kFFTR];
-    __shared__ double2 tmp[kCols][kFFTR];
-    __shared__ double2 tw[kFFTR];
-    const int groups = kFFTR / kCols;
+// LEN = N2: block (target p, column group) transforms columns gcol .. gcol + cols - 1.
+template <int LEN>
+__global__ void __launch_bounds__(256) k_mm_fft_cols(const double2* __restrict__ X, double2* __restrict__ Y, int n1,
+                                                     int cols) {
+    __shared__ double2 buf[kLdsPts];
+    __shared__ double2 tmp[kLdsPts];
+    __shared__ double2 tw[LEN];
+    const int64_t N = static_cast<int64_t>(n1) * LEN;
+    const int groups = n1 / cols;
     const int64_t p = blockIdx.x / groups;
-    const int gcol = (blockIdx.x % groups) * kCols;
-    fill_twiddles(tw);
-    const double2* __restrict__ src = X + p * kFFTN;
-#pragma unroll
-    for (int i = 0; i < kCols; ++i) {
-        const int idx = threadIdx.x + 256 * i;
-        const int c = idx % kCols, k2 = idx / kCols;
-        buf[c][k2] = src[(gcol + c) + kFFTR * k2];
+    const int gcol = (blockIdx.x % groups) * cols;
+    fill_twiddles<LEN>(tw);
+    const double2* __restrict__ src = X + p * N;
+    for (int idx = threadIdx.x; idx < cols * LEN; idx += 256) {
+        const int c = idx % cols, k2 = idx / cols;
+        buf[c * LEN + k2] = src[(gcol + c) + static_cast<int64_t>(n1) * k2];
     }
     __syncthreads();
-    lds_idft256(buf, tmp, tw);
-    double2* __restrict__ dst = Y + p * kFFTN;
-#pragma unroll
-    for (int i = 0; i < kCols; ++i) {
-        const int idx = threadIdx.x + 256 * i;
-        const int c = idx % kCols, j2 = idx / kCols;
+    const double2* res = lds_idft<LEN>(buf, tmp, cols, tw);
+    double2* __restrict__ dst = Y + p * N;
+    for (int idx = threadIdx.x; idx < cols * LEN; idx += 256) {
+        const int c = idx % cols, j2 = idx / cols;
         const int k1 = gcol + c;
-        const double2 v = cmul(buf[c][j2], expi_ratio(static_cast<int64_t>(j2) * k1, kFFTN));
-        dst[static_cast<int64_t>(j2) * kFFTR + k1] = v;
+        const double2 v = cmul(res[c * LEN + j2], expi_ratio(static_cast<int64_t>(j2) * k1, N));
+        dst[static_cast<int64_t>(j2) * n1 + k1] = v;
     }
 }
 
@@ -214,34 +227,36 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
     return (v > bv) || (v == bv && i < bi);
 }
 
-__global__ void __launch_bounds__(256) k_mm_fft_rows_max(const double2* __restrict__ Y, double* __restrict__ mx) {
-    __shared__ double2 buf[kCols][kFFTR];
-    __shared__ double2 tmp[kCols][kFFTR];
-    __shared__ double2 tw[kFFTR];
+// LEN = N1: block (target p, row group) transforms rows grow .. grow + rows - 1 (rows of the
+// transposed array are indexed by j2); the lag of output j1 of row j2 is j = j2 + N2 j1.
+template <int LEN>
+__global__ void __launch_bounds__(256) k_mm_fft_rows_max(const double2* __restrict__ Y, double* __restrict__ mx,
+                                                         int n2, int rows) {
+    __shared__ double2 buf[kLdsPts];
+    __shared__ double2 tmp[kLdsPts];
+    __shared__ double2 tw[LEN];
     __shared__ double rv[256];
     __shared__ int ri[256];
-    const int groups = kFFTR / kCols;
+    __shared__ double2 zbest;
+    const int64_t N = static_cast<int64_t>(n2) * LEN;
+    const int groups = n2 / rows;
     const int64_t p = blockIdx.x / groups;
-    const int grow = (blockIdx.x % groups) * kCols;
-    fill_twiddles(tw);
-    const double2* __restrict__ src = Y + p * kFFTN;
-#pragma unroll
-    for (int i = 0; i < kCols; ++i) {
-        const int idx = threadIdx.x + 256 * i;
-        const int rrow = idx / kFFTR, k1 = idx % kFFTR;
-        buf[rrow][k1] = src[static_cast<int64_t>(grow + rrow) * kFFTR + k1];
+    const int grow = (blockIdx.x % groups) * rows;
+    fill_twiddles<LEN>(tw);
+    const double2* __restrict__ src = Y + p * N;
+    for (int idx = threadIdx.x; idx < rows * LEN; idx += 256) {
+        const int rrow = idx / LEN, k1 = idx % LEN;
+        buf[rrow * LEN + k1] = src[static_cast<int64_t>(grow + rrow) * LEN + k1];
     }
     __syncthreads();
-    lds_idft256(buf, tmp, tw);
+    const double2* res = lds_idft<LEN>(buf, tmp, rows, tw);
     double best = -1.0;
     int bidx = 0x7fffffff;
-#pragma unroll
-    for (int i = 0; i < kCols; ++i) {
-        const int idx = threadIdx.x + 256 * i;
-        const int rrow = idx / kFFTR, j1 = idx % kFFTR;
-        const double2 z = buf[rrow][j1];
+    for (int idx = threadIdx.x; idx < rows * LEN; idx += 256) {
+        const int rrow = idx / LEN, j1 = idx % LEN;
+        const double2 z = res[rrow * LEN + j1];
         const double a2 = z.x * z.x + z.y * z.y;
-        const int j = (grow + rrow) + kFFTR * j1;
+        const int j = (grow + rrow) + n2 * j1;
         if (better(a2, j, best, bidx)) {
             best = a2;
             bidx = j;
@@ -262,11 +277,14 @@ __global__ void __launch_bounds__(256) k_mm_fft_rows_max(const double2* __restri
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const int j = ri[0];
-        const int j2 = j % kFFTR - grow, j1 = j / kFFTR;
-        const double2 z = buf[j2][j1];
+        // no comparable |z|^2 (all NaN): report lag 0 with a NaN modulus
+        const bool none = ri[0] == 0x7fffffff;
+        const int j = none ? grow : ri[0];
+        const int r = j % n2 - grow, j1 = j / n2;
+        double2 z = res[r * LEN + j1];
+        if (none) z = make_double2(__builtin_nan(""), __builtin_nan(""));
         double* o = mx + (p * groups + (blockIdx.x % groups)) * 4;
-        o[0] = rv[0];
+        o[0] = none ? __builtin_nan("") : rv[0];
         o[1] = static_cast<double>(j);
         o[2] = z.x;
         o[3] = z.y;
@@ -276,7 +294,7 @@ __global__ void __launch_bounds__(256) k_mm_fft_rows_max(const double2* __restri
 // ---- 4. finalize ---------------------------------------------------------------------
 __global__ void k_mm_finalize(const double* __restrict__ recs, int64_t nt, const double* __restrict__ ab,
                               const double* __restrict__ mx, double* __restrict__ scal,
-                              double* __restrict__ mismatch, int32_t* __restrict__ lag) {
+                              double* __restrict__ mismatch, int32_t* __restrict__ lag, int blocks, int groups) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= nt) return;
     double* sc = scal + p * kSlotMM;
@@ -286,13 +304,11 @@ __global__ void k_mm_finalize(const double* __restrict__ recs, int64_t nt, const
         if (lag) lag[p] = -1;
         return;
     }
-    const int blocks = kFFTN / 256;
     double A = 0.0, B = 0.0;
     for (int b = 0; b < blocks; ++b) {
         A += ab[(p * blocks + b) * 2 + 0];
         B += ab[(p * blocks + b) * 2 + 1];
     }
-    const int groups = kFFTR / kCols;
     double best = -1.0;
     int bi = 0x7fffffff;
     double zr = 0.0, zi = 0.0;
@@ -305,6 +321,10 @@ __global__ void k_mm_finalize(const double* __restrict__ recs, int64_t nt, const
             zr = o[2];
             zi = o[3];
         }
+    }
+    if (bi == 0x7fffffff) {   // every |z|^2 NaN: NaN mismatch at lag 0
+        bi = 0;
+        best = __builtin_nan("");
     }
     const double az = sqrt(best);
     const double mm = 1.0 - az / sqrt(A * B);
@@ -361,7 +381,7 @@ struct AdjSegment {
             const double hr = Aamp * cs, hi = -Aamp * sn;
             const double w = w4 * inv_psd[k];
             const double2 t = tgt[k];
-            const double2 e = expi_ratio((k * j) % kFFTN, kFFTN);
+            const double2 e = expi_ratio((static_cast<int64_t>(k) * j) % g.nb, g.nb);
             const double2 x = cmul(make_double2(w * t.x, w * t.y), e);
             // G = conj(u) x
             const double gr = ur * x.x + ui * x.y, gi = ur * x.y - ui * x.x;
@@ -401,7 +421,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     seg.rec = rec;
     seg.T = Tabs(tab, g.nb);
     seg.g = g;
-    seg.tgt = reinterpret_cast<const double2*>(targets) + p * kFFTN;
+    seg.tgt = reinterpret_cast<const double2*>(targets) + p * g.nb;
     seg.inv_psd = inv_psd;
     // unit phase u = z / |z|; G_k = conj(u) x_k with x_k = w t_k exp(2 pi i k j / N)
     seg.ur = sc[3] / az;
@@ -484,26 +504,52 @@ __global__ void __launch_bounds__(256) k_mm_lambda_sum(const double* __restrict_
 
 }  // namespace
 
-size_t mismatch_scratch_bytes(int64_t nt, int64_t nb) { return carve_size(nt, nb); }
+size_t mismatch_scratch_bytes(int64_t nt, int64_t nb) { return carve_into(nullptr, nt, nb, nullptr); }
+
+template <int LEN>
+static void launch_cols(unsigned blocks, const double2* X, double2* Y, int n1, int cols, hipStream_t s) {
+    hipLaunchKernelGGL(k_mm_fft_cols<LEN>, dim3(blocks), dim3(256), 0, s, X, Y, n1, cols);
+}
+template <int LEN>
+static void launch_rows(unsigned blocks, const double2* Y, double* mx, int n2, int rows, hipStream_t s) {
+    hipLaunchKernelGGL(k_mm_fft_rows_max<LEN>, dim3(blocks), dim3(256), 0, s, Y, mx, n2, rows);
+}
 
 hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t nt, const GridArgs& g,
                            const double* tab, const double* targets, const double* inv_psd, void* scratch, double* mismatch,
                            double* dsum_dlambda, int32_t* lag, hipStream_t s) {
-    MMScratch m = carve(scratch, nt, g.nb);
-    const unsigned bin_blocks = static_cast<unsigned>(nt * (kFFTN / 256));
+    MMScratch m;
+    carve_into(scratch, nt, g.nb, &m);
+    const FFTPlan f = make_plan(g.nb);
+    const unsigned bin_blocks = static_cast<unsigned>(nt * f.ibl);
     {
         ProfRange pr(PD_K_MISMATCH_INPUT, s);
         hipLaunchKernelGGL(k_mm_input, dim3(bin_blocks), dim3(256), 0, s, recs, nt, g, tab, targets, inv_psd, m.X,
-                           m.ab);
+                           m.ab, f.ibl);
     }
-    const unsigned fft_blocks = static_cast<unsigned>(nt * (kFFTR / kCols));
+    const unsigned col_blocks = static_cast<unsigned>(nt * (f.n1 / f.cb));
+    const unsigned row_blocks = static_cast<unsigned>(nt * (f.n2 / f.rb));
     {
         ProfRange pr(PD_K_MISMATCH_FFT, s);
-        hipLaunchKernelGGL(k_mm_fft_cols, dim3(fft_blocks), dim3(256), 0, s, m.X, m.Y);
-        hipLaunchKernelGGL(k_mm_fft_rows_max, dim3(fft_blocks), dim3(256), 0, s, m.Y, m.mx);
+        switch (f.n2) {
+            case 8: launch_cols<8>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
+            case 16: launch_cols<16>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
+            case 32: launch_cols<32>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
+            case 64: launch_cols<64>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
+            case 128: launch_cols<128>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
+            default: launch_cols<256>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
+        }
+        switch (f.n1) {
+            case 8: launch_rows<8>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
+            case 16: launch_rows<16>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
+            case 32: launch_rows<32>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
+            case 64: launch_rows<64>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
+            case 128: launch_rows<128>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
+            default: launch_rows<256>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
+        }
     }
     hipLaunchKernelGGL(k_mm_finalize, dim3(static_cast<unsigned>((nt + 127) / 128)), dim3(128), 0, s, recs, nt,
-                       m.ab, m.mx, m.scal, mismatch, lag);
+                       m.ab, m.mx, m.scal, mismatch, lag, f.ibl, f.n2 / f.rb);
     if (dsum_dlambda) {
         const int64_t waves = nt * m.chunks;
         {

@@ -1,5 +1,5 @@
 // Samplers on the GPU (paper Sec. 3.3): posterior log-density and gradient in
-// unconstrained coordinates, Hamiltonian Monte Carlo with a diagonal mass matrix, the
+// unconstrained coordinates, Hamiltonian Monte Carlo with a dense (or diagonal) metric, the
 // random-walk Metropolis-Hastings baseline the paper compares it with (Gaussian steps), and
 // the Metropolis-Hastings accept step of an independence proposal (the learned flow).
 //
@@ -28,11 +28,45 @@ __device__ __forceinline__ double sigmoid(double x) {
     return (x >= 0.0) ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x));
 }
 
+// HMC metric.  The inverse mass matrix is M^-1 = L L^T with L lower triangular (7 x 7); the chains
+// carry the whitened momentum r = L^T p, so that r ~ N(0, I), the drift is x += eps L r, the kick is
+// r += w eps L^T grad log pi and the kinetic energy is |r|^2 / 2.  A diagonal mass m_j is the case
+// L = diag(1 / sqrt(m_j)).
+struct Metric {
+    double L[7][7];
+    bool diag;
+};
+
+__device__ __forceinline__ void metric_drift(const Metric& m, double eps, const double* __restrict__ r, double out[7]) {
+    for (int j = 0; j < 7; ++j) {
+        double acc = 0.0;
+        if (m.diag) {
+            acc = m.L[j][j] * r[j];
+        } else {
+            for (int k = 0; k <= j; ++k) acc = fma(m.L[j][k], r[k], acc);
+        }
+        out[j] = eps * acc;
+    }
+}
+
+// r += weps L^T g
+__device__ __forceinline__ void metric_kick(const Metric& m, double weps, const double g[7], double* __restrict__ r) {
+    for (int j = 0; j < 7; ++j) {
+        double acc = 0.0;
+        if (m.diag) {
+            acc = m.L[j][j] * g[j];
+        } else {
+            for (int k = j; k < 7; ++k) acc = fma(m.L[k][j], g[k], acc);
+        }
+        r[j] = fma(weps, acc, r[j]);
+    }
+}
+
 // x -> theta, d theta / d x, and the log-Jacobian with its derivative.  DRIFT: first the leapfrog
-// drift x += eps p / m (x updated in place).
+// drift x += eps L r (x updated in place).
 struct Drift {
     double eps;
-    double mass[7];
+    Metric m;
     const double* p;
 };
 
@@ -46,10 +80,12 @@ __global__ void k_transform(double* __restrict__ x, int64_t n, pd_posterior post
     if (ts == 11)
         for (int k = 0; k < 4; ++k) theta[i * 11 + 7 + k] = post.orient[k];
     double acc = 0.0;
+    double dx[7];
+    if (DRIFT) metric_drift(dr.m, dr.eps, dr.p + i * 7, dx);
     for (int j = 0; j < 7; ++j) {
         double xv = x[i * 7 + j];
         if (DRIFT) {
-            xv = fma(dr.eps / dr.mass[j], dr.p[i * 7 + j], xv);
+            xv += dx[j];
             x[i * 7 + j] = xv;
         }
         const double s = sigmoid(xv);
@@ -65,21 +101,22 @@ __global__ void k_transform(double* __restrict__ x, int64_t n, pd_posterior post
     lj[i] = acc;
 }
 
-// log posterior and its gradient in x; with p given, then the leapfrog kick p += weps grad.
+// log posterior and its gradient in x; with p given, then the leapfrog kick p += weps L^T grad.
 __global__ void k_assemble(int64_t n, const double* __restrict__ lnl, const double* __restrict__ gth, int gs,
                            const double* __restrict__ dtdx, const double* __restrict__ lj,
                            const double* __restrict__ dlj, double* __restrict__ logp, double* __restrict__ grad,
-                           double weps, double* __restrict__ p) {
+                           double weps, double* __restrict__ p, Metric m) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const bool ok = isfinite(lnl[i]);
     logp[i] = ok ? lnl[i] + lj[i] : -INFINITY;
     if (grad) {
+        double g[7];
         for (int j = 0; j < 7; ++j) {
-            const double gj = ok ? fma(gth[i * gs + j], dtdx[i * 7 + j], dlj[i * 7 + j]) : 0.0;
-            grad[i * 7 + j] = gj;
-            if (p) p[i * 7 + j] = fma(weps, gj, p[i * 7 + j]);
+            g[j] = ok ? fma(gth[i * gs + j], dtdx[i * 7 + j], dlj[i * 7 + j]) : 0.0;
+            grad[i * 7 + j] = g[j];
         }
+        if (p) metric_kick(m, weps, g, p + i * 7);
     }
 }
 
@@ -99,40 +136,45 @@ __global__ void k_gauss(const double* __restrict__ x, int64_t n, pd_posterior po
 // ---- HMC trajectory pieces ---------------------------------------------------------------
 struct HmcArgs {
     double eps;
-    double mass[7];
+    Metric m;
 };
 
-// p = sqrt(m) xi;  H0 = -logp + sum p^2 / (2m);  first half kick.
+// r = xi;  H0 = -logp + |r|^2 / 2;  first half kick.
 __global__ void k_hmc_begin(int64_t n, HmcArgs a, const double* __restrict__ xi, const double* __restrict__ logp,
                             const double* __restrict__ grad, double* __restrict__ p, double* __restrict__ h0) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double kin = 0.0;
+    double kin = 0.0, g[7];
     for (int j = 0; j < 7; ++j) {
-        const double pj = sqrt(a.mass[j]) * xi[i * 7 + j];
-        kin += pj * pj / a.mass[j];
-        p[i * 7 + j] = fma(0.5 * a.eps, grad[i * 7 + j], pj);
+        const double rj = xi[i * 7 + j];
+        kin = fma(rj, rj, kin);
+        p[i * 7 + j] = rj;
+        g[j] = grad[i * 7 + j];
     }
+    metric_kick(a.m, 0.5 * a.eps, g, p + i * 7);
     h0[i] = -logp[i] + 0.5 * kin;
 }
 
-// drift: x += eps p / m
+// drift: x += eps L r
 __global__ void k_hmc_drift(int64_t n, HmcArgs a, double* __restrict__ x, const double* __restrict__ p) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n * 7) return;
-    const int j = static_cast<int>(t % 7);
-    x[t] = fma(a.eps / a.mass[j], p[t], x[t]);
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double dx[7];
+    metric_drift(a.m, a.eps, p + i * 7, dx);
+    for (int j = 0; j < 7; ++j) x[i * 7 + j] += dx[j];
 }
 
-// kick: p += w eps grad  (w = 1 inside the trajectory, 1/2 at its end)
-__global__ void k_hmc_kick(int64_t n, double weps, double* __restrict__ p, const double* __restrict__ grad) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n * 7) return;
-    p[t] = fma(weps, grad[t], p[t]);
+// kick: r += w eps L^T grad  (w = 1 inside the trajectory, 1/2 at its end)
+__global__ void k_hmc_kick(int64_t n, HmcArgs a, double weps, double* __restrict__ p, const double* __restrict__ grad) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double g[7];
+    for (int j = 0; j < 7; ++j) g[j] = grad[i * 7 + j];
+    metric_kick(a.m, weps, g, p + i * 7);
 }
 
 // Metropolis-Hastings on the Hamiltonian; NaN or |dH| > 1000 (a divergence) rejects.
-__global__ void k_hmc_accept(int64_t n, HmcArgs a, const double* __restrict__ u, const double* __restrict__ h0,
+__global__ void k_hmc_accept(int64_t n, const double* __restrict__ u, const double* __restrict__ h0,
                              const double* __restrict__ x1, const double* __restrict__ p1,
                              const double* __restrict__ logp1, const double* __restrict__ grad1,
                              double* __restrict__ x, double* __restrict__ logp, double* __restrict__ grad,
@@ -140,7 +182,7 @@ __global__ void k_hmc_accept(int64_t n, HmcArgs a, const double* __restrict__ u,
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double kin = 0.0;
-    for (int j = 0; j < 7; ++j) kin += p1[i * 7 + j] * p1[i * 7 + j] / a.mass[j];
+    for (int j = 0; j < 7; ++j) kin = fma(p1[i * 7 + j], p1[i * 7 + j], kin);
     const double h1 = -logp1[i] + 0.5 * kin;
     const double dh = h1 - h0[i];
     const bool finite = isfinite(dh);
@@ -175,17 +217,15 @@ __global__ void k_imh(int64_t n, double* __restrict__ x, double* __restrict__ lo
     if (accepted) accepted[i] = acc ? 1 : 0;
 }
 
-struct RwArgs {
-    double scale[7];
-};
-
-// Gaussian random-walk proposal: x' = x + scale * xi, per coordinate.
-__global__ void k_rw_propose(int64_t n, RwArgs a, const double* __restrict__ x, const double* __restrict__ xi,
+// Gaussian random-walk proposal x' = x + L xi: per coordinate (L diagonal, the step scales) or
+// correlated (L lower triangular, proposal covariance L L^T).
+__global__ void k_rw_propose(int64_t n, Metric m, const double* __restrict__ x, const double* __restrict__ xi,
                              double* __restrict__ xp) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n * 7) return;
-    const int j = static_cast<int>(t % 7);
-    xp[t] = fma(a.scale[j], xi[t], x[t]);
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double dx[7];
+    metric_drift(m, 1.0, xi + i * 7, dx);
+    for (int j = 0; j < 7; ++j) xp[i * 7 + j] = x[i * 7 + j] + dx[j];
 }
 
 // Metropolis accept for a symmetric proposal: accept x' with probability min(1, pi(x') / pi(x)).
@@ -357,7 +397,7 @@ int posterior_logp_step(const pd_posterior* post, double* x, int64_t n, double* 
                               PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes, s, tables_ready);
     if (rc != PD_OK) return rc;
     hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 128)), dim3(128), 0, s, n, w.lnl, w.gth, ts, w.dtdx, w.lj, w.dlj,
-                       logp, grad, kick_weps, kick_p);
+                       logp, grad, kick_weps, kick_p, drift ? drift->m : Metric{});
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
 }
 
@@ -376,19 +416,22 @@ size_t posterior_ws_bytes(const pd_posterior* post, int64_t n) { return post_ws_
 size_t hmc_workspace_bytes(const pd_posterior* post, int64_t n) { return hmc_ws_bytes(post, n); }
 
 int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
-             const double* u, int n_leapfrog, double eps, const double* mass, int32_t* accepted, double* dh,
-             void* ws, hipStream_t s) {
+             const double* u, int n_leapfrog, double eps, const double* mass, const double* chol, int32_t* accepted,
+             double* dh, void* ws, hipStream_t s) {
     HmcWs w = hmc_ws(n, ws);
     HmcArgs a;
     a.eps = eps;
-    for (int j = 0; j < 7; ++j) a.mass[j] = mass[j];
-    const unsigned b1 = nblk(n, 128), b7 = nblk(n * 7, 256);
+    a.m.diag = (chol == nullptr);
+    for (int j = 0; j < 7; ++j)
+        for (int k = 0; k < 7; ++k)
+            a.m.L[j][k] = chol ? ((k <= j) ? chol[j * 7 + k] : 0.0) : ((j == k) ? 1.0 / std::sqrt(mass[j]) : 0.0);
+    const unsigned b1 = nblk(n, 128);
     hipLaunchKernelGGL(k_hmc_begin, dim3(b1), dim3(128), 0, s, n, a, xi, logp, grad, w.p, w.h0);
     if (hipMemcpyAsync(w.x1, x, static_cast<size_t>(n) * 7 * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return PD_EHIP;
     Drift dr;
     dr.eps = eps;
-    for (int j = 0; j < 7; ++j) dr.mass[j] = mass[j];
+    dr.m = a.m;
     dr.p = w.p;
     for (int l = 0; l < n_leapfrog; ++l) {
         const double weps = (l + 1 < n_leapfrog) ? eps : 0.5 * eps;
@@ -399,13 +442,13 @@ int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, doubl
             const int rc = posterior_logp_step(post, w.x1, n, w.logp1, w.grad1, w.post, s, l > 0, &dr, weps, w.p);
             if (rc != PD_OK) return rc;
         } else {
-            hipLaunchKernelGGL(k_hmc_drift, dim3(b7), dim3(256), 0, s, n, a, w.x1, w.p);
+            hipLaunchKernelGGL(k_hmc_drift, dim3(b1), dim3(128), 0, s, n, a, w.x1, w.p);
             const int rc = posterior_logp(post, w.x1, n, w.logp1, w.grad1, w.post, s);
             if (rc != PD_OK) return rc;
-            hipLaunchKernelGGL(k_hmc_kick, dim3(b7), dim3(256), 0, s, n, weps, w.p, w.grad1);
+            hipLaunchKernelGGL(k_hmc_kick, dim3(b1), dim3(128), 0, s, n, a, weps, w.p, w.grad1);
         }
     }
-    hipLaunchKernelGGL(k_hmc_accept, dim3(b1), dim3(128), 0, s, n, a, u, w.h0, w.x1, w.p, w.logp1, w.grad1, x, logp,
+    hipLaunchKernelGGL(k_hmc_accept, dim3(b1), dim3(128), 0, s, n, u, w.h0, w.x1, w.p, w.logp1, w.grad1, x, logp,
                        grad, accepted, dh);
     return hipGetLastError() == hipSuccess ? PD_OK : PD_EHIP;
 }
@@ -413,15 +456,17 @@ int hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, doubl
 size_t rwmh_workspace_bytes(const pd_posterior* post, int64_t n) { return rw_ws_bytes(post, n); }
 
 int rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi, const double* u,
-              const double* scale, int32_t* accepted, void* ws, hipStream_t s) {
+              const double* scale, const double* chol, int32_t* accepted, void* ws, hipStream_t s) {
     const size_t N = static_cast<size_t>(n);
     char* base = static_cast<char*>(ws);
     double* xp = reinterpret_cast<double*>(base);
     double* lpp = reinterpret_cast<double*>(base + al(N * 7 * 8));
     void* pws = base + al(N * 7 * 8) + al(N * 8);
-    RwArgs a;
-    for (int j = 0; j < 7; ++j) a.scale[j] = scale[j];
-    hipLaunchKernelGGL(k_rw_propose, dim3(nblk(n * 7, 256)), dim3(256), 0, s, n, a, x, xi, xp);
+    Metric m;
+    m.diag = (chol == nullptr);
+    for (int j = 0; j < 7; ++j)
+        for (int k = 0; k < 7; ++k) m.L[j][k] = chol ? ((k <= j) ? chol[j * 7 + k] : 0.0) : ((j == k) ? scale[j] : 0.0);
+    hipLaunchKernelGGL(k_rw_propose, dim3(nblk(n, 128)), dim3(128), 0, s, n, m, x, xi, xp);
     if (hipGetLastError() != hipSuccess) return PD_EHIP;
     // value only: the random walk uses no gradient
     const int rc = posterior_logp(post, xp, n, lpp, nullptr, pws, s);

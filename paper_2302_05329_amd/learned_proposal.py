@@ -1,6 +1,17 @@
 """Learned-proposal sampling of one injection (Sec. 3.3 and its closing remark): plain HMC
 against HMC interleaved with flow-proposal independence MH, compared by effective samples per
-second, with the posterior moments of the two samplers checked against each other.
+second, with the posterior moments of both samplers checked against a long plain-HMC reference
+run (plain HMC is the judge).
+
+Both samplers use HMC with a dense metric: the inverse mass matrix is the chains' covariance in the
+unconstrained coordinates, adapted during warm-up (the paper's HMC has a hand-tuned mass matrix).
+On this posterior, a curved ridge in chirp mass, mass ratio and spins, no linear metric whitens
+the target: the step size stays small and plain HMC moves diffusively, with autocorrelation times
+of several hundred transitions.  The autocorrelation time is a property of one chain, so plain
+HMC's is measured on a long run of a subset of the chains (the reference run, many times its
+autocorrelation time), and its effective samples per second on the full ensemble follow as
+n_chains / tau / (time per transition of the full ensemble).  Effective sample sizes are the bulk
+ESS from within-chain autocorrelation (rank-normalised split chains, Geyer truncation).
 
 Every transition, log-density, flow pass and training step runs in the HIP library; this
 module only draws random numbers (torch generator on the device), schedules the calls and
@@ -79,7 +90,7 @@ def fisher_ball(pb, n, rng, prior_precision=0.3):
     """Starting states: x ~ N(x_inj, (J F J + c I)^-1) in the unconstrained coordinates, with F
     the library's Fisher matrix at the injection, J = d theta / d x, and c a weak precision that
     keeps the ball inside the prior along directions the data do not constrain.  Returns the
-    states and the inverse of the ball's marginal variances (a first mass matrix)."""
+    states and the ball's covariance (a first metric)."""
     post = pb["post"]
     th0 = pb["theta_inj"]
     if "geometry" in pb:
@@ -97,7 +108,7 @@ def fisher_ball(pb, n, rng, prior_precision=0.3):
     cov = 0.5 * (cov + cov.T)
     chol = np.linalg.cholesky(cov)
     x = post.to_x(th0) + rng.standard_normal((n, 7)) @ chol.T
-    return x, 1.0 / np.diag(cov)
+    return x, cov
 
 
 def _rand(gen, n):
@@ -106,44 +117,77 @@ def _rand(gen, n):
     return xi, u
 
 
-def warmup(post, x0, gen, steps=300, n_leapfrog=10, eps0=0.05, target_acc=0.75, mass0=None, log=None):
-    """Ensemble warm-up: chains start around x0; every 50 steps the diagonal mass matrix is set
-    to the inverse variance across chains, and the shared step size follows the acceptance rate
-    towards target_acc.  Returns the HMC object (chains at the end), eps, mass."""
+def ensemble_chol(x, jitter=1e-10):
+    """Cholesky factor of the chains' covariance [7][7] (host), with a relative jitter on the
+    diagonal."""
+    c = np.cov(x.cpu().numpy().T)
+    c = 0.5 * (c + c.T) + jitter * np.diag(np.diag(c))
+    return np.linalg.cholesky(c)
+
+
+# A chain whose log-density is this far below the ensemble median sits where the posterior has
+# no mass (for 7 Gaussian coordinates -log p - min is chi2_7 / 2, which exceeds 25 with
+# probability ~1e-8): during warm-up it is restarted from another chain's state.
+STRAGGLER_DROP = 25.0
+
+
+def reseed_stragglers(x, logp, gen, drop=STRAGGLER_DROP):
+    """Copies of randomly chosen chains replace those with logp < median - drop (or NaN).
+    Returns (new x, number replaced).  Warm-up only: this is not a Markov transition."""
+    lp = logp.double()
+    med = torch.nanmedian(lp)
+    bad = ~(lp >= med - drop)
+    nbad = int(bad.sum())
+    if nbad == 0:
+        return x, 0
+    good = torch.nonzero(~bad).flatten()
+    pick = good[torch.randint(len(good), (nbad,), device=x.device, generator=gen)]
+    x = x.clone()
+    x[bad] = x[pick]
+    return x, nbad
+
+
+def warmup(post, x0, gen, steps=300, n_leapfrog=10, eps0=0.5, target_acc=0.8, cov0=None, log=None):
+    """Ensemble warm-up with a dense metric: chains start around x0; every 50 steps chains stuck
+    where the posterior has no mass are restarted from other chains (reseed_stragglers), the
+    inverse mass matrix is set to the covariance across chains (its Cholesky factor is the
+    metric), and the shared step size follows the acceptance rate towards target_acc.  Returns the
+    HMC object (chains at the end), eps and the metric's Cholesky factor."""
     x0 = torch.as_tensor(x0, device="cuda")
-    mass = np.ones(7) if mass0 is None else np.asarray(mass0, dtype=np.float64)
+    chol = np.linalg.cholesky(cov0) if cov0 is not None else ensemble_chol(x0)
     eps = eps0
-    hmc = sampling.HMC(post, x0, eps, n_leapfrog, mass)
+    hmc = sampling.HMC(post, x0, eps, n_leapfrog, chol=chol)
     for t in range(steps):
         xi, u = _rand(gen, hmc.n)
         acc = float((hmc.step(xi, u) == 1).double().mean())
         eps *= math.exp(0.5 * (acc - target_acc))
         hmc.eps = eps
         if (t + 1) % 50 == 0 and t + 1 < steps:
-            var = hmc.x.var(dim=0).cpu().numpy()
-            mass = 1.0 / np.maximum(var, 1e-12)
-            x, lp, g = hmc.x, hmc.logp, hmc.grad
-            hmc = sampling.HMC(post, x, eps, n_leapfrog, mass)
+            x, nbad = reseed_stragglers(hmc.x, hmc.logp, gen)
+            chol = ensemble_chol(x)
+            hmc = sampling.HMC(post, x, eps, n_leapfrog, chol=chol)
             if log:
-                log(f"warmup {t + 1}: acc {acc:.2f} eps {eps:.3g}")
-    return hmc, eps, mass
+                log(f"warmup {t + 1}: acc {acc:.2f} eps {eps:.3g} restarted {nbad}")
+    return hmc, eps, chol
 
 
 def _record(post, hmc_x, out):
     out.append(post.to_theta(hmc_x.cpu().numpy()))
 
 
-def run_hmc(hmc, gen, steps):
-    """Plain HMC: returns (draws [chains, steps, 7] in theta, seconds, acceptance)."""
+def run_hmc(hmc, gen, steps, thin=1):
+    """Plain HMC: returns (draws [chains, steps / thin, 7] in theta, every `thin`-th state, seconds,
+    acceptance)."""
     draws = []
     acc = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     states = []
-    for _ in range(steps):
+    for t in range(steps):
         xi, u = _rand(gen, hmc.n)
         acc += (hmc.step(xi, u) == 1).double().mean()
-        states.append(hmc.x.clone())
+        if (t + 1) % thin == 0:
+            states.append(hmc.x.clone())
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     for s in states:
@@ -151,7 +195,7 @@ def run_hmc(hmc, gen, steps):
     return np.stack(draws, axis=1), sec, float(acc) / steps
 
 
-def run_flow_hmc(hmc, fl, gen, steps):
+def run_flow_hmc(hmc, fl, gen, steps, thin=1):
     """HMC step then flow-proposal MH step, `steps` times: (draws, seconds, HMC acc, MH acc)."""
     fh = flow.FlowHMC(hmc, fl)
     draws = []
@@ -160,12 +204,13 @@ def run_flow_hmc(hmc, fl, gen, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     states = []
-    for _ in range(steps):
+    for t in range(steps):
         xi, u = _rand(gen, hmc.n)
         acc_h += (fh.hmc_step(xi, u) == 1).double().mean()
         z, u2 = _rand(gen, hmc.n)
         acc_m += (fh.mh_step(z, u2) == 1).double().mean()
-        states.append(hmc.x.clone())
+        if (t + 1) % thin == 0:
+            states.append(hmc.x.clone())
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     for s in states:
@@ -187,9 +232,13 @@ def train_flow(samples_x, gen, steps=1500, batch=4096, lr=1e-3, seed=1005, fl=No
     return fl, time.perf_counter() - t0, losses
 
 
-def flow_burn_in(hmc, gen, rounds=4, per_round=50, first_steps=1500, later_steps=500, log=None, mode="bf16"):
+def flow_burn_in(hmc, gen, rounds=4, per_round=50, first_steps=1500, later_steps=500, log=None, mode="bf16",
+                 keep=None):
     """Training phase: alternate `per_round` transitions (HMC, plus flow MH once a flow exists)
-    with refitting the flow on the states of the last two rounds.  Returns (flow, seconds)."""
+    with refitting the flow on the states of the last two rounds.  With `keep` given, its chains are
+    the ones advanced (`hmc` is then unused).  Returns (flow, seconds)."""
+    if keep is not None:
+        hmc = keep
     fl = None
     pool = []
     torch.cuda.synchronize()
@@ -216,19 +265,113 @@ def flow_burn_in(hmc, gen, rounds=4, per_round=50, first_steps=1500, later_steps
     return fl, time.perf_counter() - t0
 
 
+FEATURES = ("Mc", "q", "chi1", "chi2", "D", "tc", "cos2phic", "sin2phic")
+
+
+def features(draws):
+    """Draws [chains, steps, 7] in theta -> [chains, steps, 8]: the six non-periodic parameters,
+    then cos 2 phic and sin 2 phic (the phase enters the strain as 2 phic, so it is periodic with
+    period pi and is summarised by these two)."""
+    ph = 2.0 * draws[:, :, 6]
+    return np.concatenate([draws[:, :, :6], np.cos(ph)[:, :, None], np.sin(ph)[:, :, None]], axis=2)
+
+
+def ess_per_param(draws):
+    """Bulk ESS of each summary feature of draws [chains, steps, 7] (within-chain
+    autocorrelation of all chains; rank-normalised split chains, Geyer truncation)."""
+    f = features(draws)
+    return np.array([diagnostics.ess(f[:, :, j]) for j in range(f.shape[2])])
+
+
 def min_ess(draws):
-    """Minimum over the 7 parameters of the bulk ESS of draws [chains, steps, 7]."""
-    return min(diagnostics.ess(draws[:, :, j]) for j in range(draws.shape[2]))
+    """Minimum over the summary features of the bulk ESS of draws [chains, steps, 7]."""
+    return float(np.min(ess_per_param(draws)))
 
 
-def compare(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, rounds=6, per_round=50, seed=1005,
-            n_bins=None, log=None, flow_mode="bf16", two_site=False):
-    """The full comparison; returns a dict of rates, acceptance and moment agreement.
+def _moments(draws):
+    f = features(draws)
+    d = f.reshape(-1, f.shape[2])
+    return d.mean(axis=0), d.std(axis=0)
 
-    Chains start in a Fisher-scaled ball around the injection and are warmed up by HMC (mass
-    matrix and step size adapted); a training phase then refits the flow on the chains' states while
-    flow MH helps them mix.  Production starts both samplers from the same states at the end
-    of that phase, with the flow frozen, so both are exact MCMC from the same start."""
+
+def time_per_step(sampler, gen, steps):
+    """Seconds per transition of an HMC or random-walk ensemble (after one untimed step)."""
+    xi, u = _rand(gen, sampler.n)
+    sampler.step(xi, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        xi, u = _rand(gen, sampler.n)
+        sampler.step(xi, u)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def importance_check(post, fl, gen, center, n_draws=1 << 20, batch=32768, frac_t=0.3, nu=3.0, scale=1.5, seed=0):
+    """Self-normalised importance sampling of the posterior with a defensive mixture proposal
+    g = (1 - frac_t) q + frac_t t, q the trained flow and t a multivariate Student-t (nu degrees of
+    freedom) with the mean and `scale` times the covariance of the states `center` [n, 7]: x ~ g,
+    weights pi(x) / g(x) normalised to sum one.  The t component keeps the weights bounded where
+    the posterior's tails in the unconstrained coordinates are heavier than the flow's Gaussian
+    ones (near the spin prior edges the likelihood flattens and the logit Jacobian decays only
+    exponentially).  Returns the weighted mean and standard deviation of each summary feature,
+    their Monte Carlo standard errors (delta method, sqrt(sum w^2 (f - mean)^2) for a mean), Kish's
+    effective sample size 1 / sum w^2 and the largest normalised weight.  The estimate is
+    consistent for any proposal whose support covers pi and involves no Markov chain, so it checks
+    the flow-MH chains' equilibrium independently of their accept/reject bookkeeping."""
+    from scipy.special import gammaln
+    c = np.asarray(center.cpu().numpy() if torch.is_tensor(center) else center, dtype=np.float64)
+    mu = c.mean(axis=0)
+    lc = np.linalg.cholesky(np.cov(c.T)) * scale
+    lc_inv = np.linalg.inv(lc)
+    lt_norm = (gammaln((nu + 7) / 2) - gammaln(nu / 2) - 3.5 * math.log(nu * math.pi)
+               - float(np.sum(np.log(np.diag(lc)))))
+    rng = np.random.default_rng(seed)
+    lws, fs = [], []
+    ws = sampling.Workspace()
+    for _ in range(n_draws // batch):
+        z = torch.randn((batch, 7), dtype=torch.float64, device="cuda", generator=gen)
+        xf, _ = fl.sample(z)
+        zt = rng.standard_normal((batch, 7))
+        xt = mu + (zt @ lc.T) / np.sqrt(rng.chisquare(nu, batch) / nu)[:, None]
+        pick = torch.as_tensor(rng.random(batch) < frac_t, device="cuda")[:, None]
+        x = torch.where(pick, torch.as_tensor(xt, device="cuda"), xf).contiguous()
+        _, lqf = fl.forward(x, want_z=False)
+        xh = x.cpu().numpy()
+        d = (xh - mu) @ lc_inv.T
+        lt = lt_norm - (nu + 7) / 2 * np.log1p(np.sum(d * d, axis=1) / nu)
+        lg = np.logaddexp(math.log(1.0 - frac_t) + lqf.cpu().numpy(), math.log(frac_t) + lt)
+        lp, _ = sampling.logp(post, x, want_grad=False, ws=ws)
+        lws.append(lp.cpu().numpy() - lg)
+        fs.append(features(post.to_theta(xh)[:, None, :])[:, 0, :])
+    lw = np.concatenate(lws)
+    f = np.concatenate(fs)
+    lw = np.where(np.isfinite(lw), lw, -np.inf)
+    w = np.exp(lw - lw.max())
+    w /= w.sum()
+    mean = w @ f
+    var = w @ (f - mean) ** 2
+    se_mean = np.sqrt((w ** 2) @ (f - mean) ** 2)
+    return dict(draws=int(len(w)), mean=mean, std=np.sqrt(var), se_mean=se_mean, kish_ess=float(1.0 / np.sum(w ** 2)),
+                max_weight=float(w.max()), proposal=f"{1 - frac_t:g} flow + {frac_t:g} Student-t (nu {nu:g}, "
+                                                    f"{scale:g} x ensemble covariance)")
+
+
+def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20000, ref_thin=10, flow_steps=600,
+            n_leapfrog=10, rounds=6, per_round=50, seed=1005, n_bins=None, log=None, flow_mode="bf16",
+            two_site=False):
+    """The full comparison; returns a dict of rates, acceptance, autocorrelation times and the
+    agreement of the flow sampler's moments with the plain-HMC reference run.
+
+    Chains start in a Fisher-scaled ball around the injection and are warmed up by HMC (dense
+    metric and step size adapted, stragglers restarted).  Plain HMC: the first `n_ref` warmed-up
+    chains run `ref_burn` further transitions (discarded), then `ref_steps` transitions with their
+    own random numbers (draws kept every `ref_thin`); this run is the reference for the moments and
+    gives HMC's autocorrelation times, and HMC's time per transition is measured on all
+    `n_chains`, so its ESS per second is n_chains / tau / (seconds per transition).  Learned
+    proposal: a training phase refits the flow on the chains' states while flow MH helps them mix,
+    then production on all chains with the metric and the flow frozen (exact MCMC), many of its
+    own autocorrelation times long.  ESS and moments are taken over the summary features."""
     pb = gw_network_problem(lam, n_bins=n_bins) if two_site else gw_problem(lam, n_bins=n_bins)
     post = pb["post"]
     gen = torch.Generator(device="cuda")
@@ -237,45 +380,60 @@ def compare(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, rounds=6, pe
     th0 = pb["theta_inj"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x0, mass0 = fisher_ball(pb, n_chains, rng)
-    hmc, eps, mass = warmup(post, x0, gen, steps=warm, n_leapfrog=n_leapfrog, mass0=mass0, log=log)
-    fl, t_train = flow_burn_in(hmc, gen, rounds=rounds, per_round=per_round, log=log, mode=flow_mode)
-    t_warm = time.perf_counter() - t0 - t_train
+    x0, cov0 = fisher_ball(pb, n_chains, rng)
+    hmc, eps, chol = warmup(post, x0, gen, steps=warm, n_leapfrog=n_leapfrog, cov0=cov0, target_acc=0.65, log=log)
+    t_warm = time.perf_counter() - t0
+    x_warm = hmc.x.clone()
+    # plain HMC: time per transition of the full ensemble, then the long reference run
+    t_hmc = time_per_step(sampling.HMC(post, x_warm, eps, n_leapfrog, chol=chol), gen, 20)
+    gen_ref = torch.Generator(device="cuda")
+    gen_ref.manual_seed(seed + 7919)
+    ref = sampling.HMC(post, x_warm[:n_ref].clone(), eps, n_leapfrog, chol=chol)
+    _, t_burn, _ = run_hmc(ref, gen_ref, ref_burn, ref_burn)
+    dr, tr, acc_r = run_hmc(ref, gen_ref, ref_steps, ref_thin)
+    ess_r = ess_per_param(dr)
+    mr, sr = _moments(dr)
+    # the reference's drift: second-half minus first-half moments, in reference sigmas
+    h = dr.shape[1] // 2
+    m1, s1 = _moments(dr[:, :h])
+    m2, s2 = _moments(dr[:, h:])
+    del dr
+    tau_r = n_ref * ref_steps / ess_r
+    if log:
+        log(f"reference: {n_ref} chains x ({ref_burn} + {ref_steps}) HMC steps, tau {np.round(tau_r, 1)} steps")
+    ess_per_s_hmc = n_chains / tau_r / t_hmc
+    fl, t_train = flow_burn_in(None, gen, rounds=rounds, per_round=per_round, log=log, mode=flow_mode, keep=hmc)
     x_start = hmc.x.clone()
-    hmc_a = sampling.HMC(post, x_start, eps, n_leapfrog, mass)
-    da, ta, acc_a = run_hmc(hmc_a, gen, steps)
-    hmc_b = sampling.HMC(post, x_start, eps, n_leapfrog, mass)
-    db, tb, acc_bh, acc_bm = run_flow_hmc(hmc_b, fl, gen, steps)
-    ess_a, ess_b = min_ess(da), min_ess(db)
-    ma, sa = da.reshape(-1, 7).mean(axis=0), da.reshape(-1, 7).std(axis=0)
-    mb, sb = db.reshape(-1, 7).mean(axis=0), db.reshape(-1, 7).std(axis=0)
+    db, tb, acc_bh, acc_bm = run_flow_hmc(sampling.HMC(post, x_start, eps, n_leapfrog, chol=chol), fl, gen,
+                                         flow_steps)
+    ess_b = ess_per_param(db)
+    mb, sb = _moments(db)
+    del db
+    tau_b = n_chains * flow_steps / ess_b
+    isr = importance_check(post, fl, gen, x_start, seed=seed)
+    # flow-MH mean minus importance-sampling mean, in combined Monte Carlo standard errors
+    z_is = (mb - isr["mean"]) / np.sqrt(sb ** 2 / ess_b + isr["se_mean"] ** 2)
     return dict(
-        n_chains=n_chains, steps=steps, n_leapfrog=n_leapfrog, eps=eps, n_bins=pb["grid"].n_bins, flow_mode=flow_mode,
-        warmup_seconds=t_warm,
-        hmc=dict(ess=ess_a, seconds=ta, ess_per_s=ess_a / ta, acceptance=acc_a),
-        flow_hmc=dict(ess=ess_b, seconds=tb, ess_per_s=ess_b / tb, ess_per_s_incl_training=ess_b / (tb + t_train),
-                      acceptance_hmc=acc_bh, acceptance_flow=acc_bm, training_phase_seconds=t_train),
-        mean_diff_sigma=(np.abs(ma - mb) / sa).tolist(), std_diff_sigma=(np.abs(sa - sb) / sa).tolist(),
-        theta_inj=th0.tolist(), mean=ma.tolist(), std=sa.tolist())
-
-
-def two_site_hmc(lam, n_chains=4096, warm=300, steps=300, n_leapfrog=10, seed=1105, log=None):
-    """HMC on the paper's two-detector posterior (H1 and L1, orientation and sky position fixed):
-    warm-up as for the one-detector workload, then `steps` transitions from the warmed-up states.
-    Returns time per transition, acceptance, the bulk ESS (chain-count floor for runs this short)
-    and the autocorrelation-time estimate of ESS per second (tau ~ l / (1 - rho(l)), l = 100)."""
-    from . import rwmh_baseline as RB
-    pb = gw_network_problem(lam)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    rng = np.random.default_rng(seed)
-    x0, mass0 = fisher_ball(pb, n_chains, rng)
-    hmc, eps, mass = warmup(pb["post"], x0, gen, steps=warm, n_leapfrog=n_leapfrog, mass0=mass0, log=log)
-    run = sampling.HMC(pb["post"], hmc.x.clone(), eps, n_leapfrog, mass)
-    draws, sec, acc = RB._run(run, gen, steps, 512)
-    ac = RB.mean_autocorr(draws)
-    tau = RB.TAU_LAG / (1.0 - ac[RB.LAGS.index(RB.TAU_LAG)])
-    return dict(n_chains=n_chains, steps=steps, n_leapfrog=n_leapfrog, eps=eps, ms_per_step=1e3 * sec / steps,
-                acceptance=acc, min_bulk_ess_512=min_ess(draws), tau_steps=tau.tolist(),
-                min_ess_per_s_tau=float(np.min(n_chains / tau / (sec / steps))), snr=20.0,
-                n_bins=pb["grid"].n_bins, sites=2)
+        n_chains=n_chains, warm=warm, n_ref=n_ref, ref_burn=ref_burn, ref_steps=ref_steps, ref_thin=ref_thin,
+        flow_steps=flow_steps, n_leapfrog=n_leapfrog, eps=eps, n_bins=pb["grid"].n_bins, flow_mode=flow_mode,
+        warmup_seconds=t_warm, metric="dense (ensemble covariance)", features=list(FEATURES),
+        hmc=dict(tau_steps=tau_r.tolist(), ms_per_step=1e3 * t_hmc, ess_per_s_per_param=ess_per_s_hmc.tolist(),
+                 ess_per_s=float(ess_per_s_hmc.min()), acceptance=acc_r),
+        flow_hmc=dict(ess=float(ess_b.min()), ess_per_param=ess_b.tolist(), tau_steps=tau_b.tolist(), seconds=tb,
+                      ms_per_step=1e3 * tb / flow_steps, ess_per_s=float(ess_b.min()) / tb,
+                      ess_per_s_incl_training=float(ess_b.min()) / (tb + t_train), acceptance_hmc=acc_bh,
+                      acceptance_flow=acc_bm, training_phase_seconds=t_train,
+                      steps_over_tau=float(flow_steps / tau_b.max())),
+        reference=dict(chains=n_ref, burn_in_steps=ref_burn, steps=ref_steps, seconds=tr + t_burn, acceptance=acc_r,
+                       ess=float(ess_r.min()), ess_per_param=ess_r.tolist(), tau_steps=tau_r.tolist(),
+                       steps_over_tau=float(ref_steps / tau_r.max()), mean=mr.tolist(), std=sr.tolist(),
+                       drift_mean_sigma=((m2 - m1) / sr).tolist(), drift_std_rel=((s2 - s1) / sr).tolist()),
+        # agreement of the learned-proposal sampler with the reference, in units of the reference sigma
+        mean_diff_sigma_flow=(np.abs(mb - mr) / sr).tolist(), std_diff_sigma_flow=(np.abs(sb - sr) / sr).tolist(),
+        mean_flow=mb.tolist(), std_flow=sb.tolist(), theta_inj=th0.tolist(),
+        importance=dict(draws=isr["draws"], kish_ess=isr["kish_ess"], max_weight=isr["max_weight"],
+                        proposal=isr["proposal"],
+                        mean=isr["mean"].tolist(), std=isr["std"].tolist(), se_mean=isr["se_mean"].tolist(),
+                        z_mean_flow_minus_is=z_is.tolist(),
+                        mean_diff_sigma_flow=(np.abs(mb - isr["mean"]) / isr["std"]).tolist(),
+                        std_diff_sigma_flow=(np.abs(sb - isr["std"]) / isr["std"]).tolist()))

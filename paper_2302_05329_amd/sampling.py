@@ -92,15 +92,26 @@ def logp(post, x, want_grad=True, ws=None):
 
 
 class HMC:
-    """n parallel HMC chains with cached log-density and gradient (all tensors on the GPU)."""
+    """n parallel HMC chains with cached log-density and gradient (all tensors on the GPU).
 
-    def __init__(self, post, x0, eps, n_leapfrog, mass):
+    The metric is a diagonal mass matrix `mass` [7], or, when `chol` is given, the dense inverse
+    mass matrix L L^T with chol = L [7][7] lower triangular (pd_hmc_step_dense)."""
+
+    def __init__(self, post, x0, eps, n_leapfrog, mass=None, chol=None):
         self.post = post
         self.x = torch.as_tensor(x0, dtype=torch.float64, device="cuda").clone().contiguous()
         self.n = self.x.shape[0]
         self.eps = float(eps)
         self.L = int(n_leapfrog)
-        self.mass = (ctypes.c_double * 7)(*[float(m) for m in mass])
+        if chol is not None:
+            c = np.tril(np.asarray(chol, dtype=np.float64))
+            if c.shape != (7, 7) or not np.all(np.diag(c) > 0) or not np.all(np.isfinite(c)):
+                raise ValueError("chol must be a finite 7 x 7 lower-triangular matrix with a positive diagonal")
+            self.chol = (ctypes.c_double * 49)(*c.reshape(-1).tolist())
+            self.mass = None
+        else:
+            self.mass = (ctypes.c_double * 7)(*[float(m) for m in mass])
+            self.chol = None
         self.ws = Workspace()
         self.logp, self.grad = logp(post, self.x, ws=self.ws)
         self.accepted = torch.empty(self.n, dtype=torch.int32, device="cuda")
@@ -111,26 +122,43 @@ class HMC:
         if tuple(xi.shape) != (self.n, 7) or tuple(u.shape) != (self.n,):
             raise ValueError("random draws have the wrong shape")
         wp, wb = self.ws.get(L.lib().pd_hmc_workspace_bytes(self.post.ref(), self.n))
-        L.check(L.lib().pd_hmc_step(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(self.grad),
-                                    _ptr(xi), _ptr(u), self.L, self.eps, self.mass, _ptr(self.accepted),
-                                    _ptr(self.dh), wp, wb, _stream()))
+        if self.chol is not None:
+            L.check(L.lib().pd_hmc_step_dense(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(self.grad),
+                                              _ptr(xi), _ptr(u), self.L, self.eps, self.chol, _ptr(self.accepted),
+                                              _ptr(self.dh), wp, wb, _stream()))
+        else:
+            L.check(L.lib().pd_hmc_step(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(self.grad),
+                                        _ptr(xi), _ptr(u), self.L, self.eps, self.mass, _ptr(self.accepted),
+                                        _ptr(self.dh), wp, wb, _stream()))
         return self.accepted
 
 
 class RWMH:
     """n parallel random-walk Metropolis-Hastings chains (Gaussian steps of standard deviation
-    `scale` per coordinate) with cached log-density (all tensors on the GPU)."""
+    `scale` per coordinate, or correlated steps L xi with `chol` = L) with cached log-density (all
+    tensors on the GPU)."""
 
-    def __init__(self, post, x0, scale):
+    def __init__(self, post, x0, scale=None, chol=None):
         self.post = post
         self.x = torch.as_tensor(x0, dtype=torch.float64, device="cuda").clone().contiguous()
         if self.x.dim() != 2 or self.x.shape[1] != 7:
             raise ValueError("x0 must be [n, 7]")
         self.n = self.x.shape[0]
-        self.scale = (ctypes.c_double * 7)(*[float(s) for s in scale])
+        self.set_step(scale, chol)
         self.ws = Workspace()
         self.logp, _ = logp(post, self.x, want_grad=False, ws=self.ws)
         self.accepted = torch.empty(self.n, dtype=torch.int32, device="cuda")
+
+    def set_step(self, scale=None, chol=None):
+        if chol is not None:
+            c = np.tril(np.asarray(chol, dtype=np.float64))
+            if c.shape != (7, 7) or not np.all(np.isfinite(c)):
+                raise ValueError("chol must be a finite 7 x 7 lower-triangular matrix")
+            self.chol = (ctypes.c_double * 49)(*c.reshape(-1).tolist())
+            self.scale = None
+        else:
+            self.scale = (ctypes.c_double * 7)(*[float(s) for s in scale])
+            self.chol = None
 
     def step(self, xi, u):
         """One transition; xi [n, 7] standard normals, u [n] uniforms (FP64 device tensors)."""
@@ -138,8 +166,12 @@ class RWMH:
             if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError("random draws have the wrong shape or type")
         wp, wb = self.ws.get(L.lib().pd_rwmh_workspace_bytes(self.post.ref(), self.n))
-        L.check(L.lib().pd_rwmh_step(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(xi), _ptr(u),
-                                     self.scale, _ptr(self.accepted), wp, wb, _stream()))
+        if self.chol is not None:
+            L.check(L.lib().pd_rwmh_step_dense(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(xi),
+                                               _ptr(u), self.chol, _ptr(self.accepted), wp, wb, _stream()))
+        else:
+            L.check(L.lib().pd_rwmh_step(self.post.ref(), self.n, _ptr(self.x), _ptr(self.logp), _ptr(xi), _ptr(u),
+                                         self.scale, _ptr(self.accepted), wp, wb, _stream()))
         return self.accepted
 
 

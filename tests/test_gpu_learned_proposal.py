@@ -1,6 +1,6 @@
-"""The learned proposal on the gravitational-wave posterior: HMC interleaved with flow MH
-against plain HMC from the same post-training states (GPU)."""
-import math
+"""The learned proposal on the gravitational-wave posterior: HMC interleaved with flow MH against
+plain HMC from the same post-warm-up states, judged against importance sampling with the trained
+flow and against a long plain-HMC reference run (GPU)."""
 import sys
 
 import numpy as np
@@ -12,20 +12,35 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("two_site", [False, True])
-def test_flow_mh_gains_over_hmc_and_agrees(gpu, two_site):
-    """2048 chains, 250 production steps each, on the one-detector posterior and on the paper's
-    two-detector one: the trained flow raises the minimum ESS per second over plain HMC, and the
-    posterior means and standard deviations of the two samplers agree within 5 Monte Carlo
-    standard errors of the difference (MC error from the ESS)."""
+def test_flow_mh_gains_over_hmc_and_keeps_the_posterior(gpu, two_site):
+    """2048 chains on the one-detector posterior and on the paper's two-detector one.
+
+    * the trained flow raises the minimum ESS per second over plain dense-metric HMC;
+    * the flow-MH production run has ESS >= 1600 per feature and is >= 20 of its own
+      autocorrelation times long, and the plain-HMC reference has ESS >= 1600 per feature;
+    * flow-MH means agree with self-normalised importance sampling (a defensive mixture of the
+      trained flow and a Student-t; a consistent estimator with no Markov chain) within 5 combined
+      Monte Carlo standard errors;
+    * flow-MH means and standard deviations are within 0.25 sigma of the plain-HMC reference.
+      Plain HMC relaxes slowly along the spin directions (its ensemble, started from the warm-up,
+      is still drifting towards the flow-MH values after 10^5 transitions, by about 0.1 sigma), so
+      this bound is a sanity check of the judge and not the exactness test, which is the previous
+      one and the Gaussian-target test of flow MH.
+    """
     from paper_2302_05329_amd import learned_proposal as LP
     print(f"learned proposal: 2048 chains, two_site={two_site}", flush=True)
     sys.stdout.flush()
-    r = LP.compare(W.load_lambda(), n_chains=2048, warm=300, steps=250, rounds=5, per_round=50, seed=77,
-                   two_site=two_site)
+    r = LP.compare(W.load_lambda(), n_chains=2048, warm=600, n_ref=512, ref_burn=2000, ref_steps=16000, ref_thin=10,
+                   flow_steps=1000, rounds=5, per_round=50, seed=77, two_site=two_site)
+    print({k: r[k] for k in ("hmc", "flow_hmc", "reference", "importance")}, flush=True)
     gain = r["flow_hmc"]["ess_per_s"] / r["hmc"]["ess_per_s"]
     assert gain > 3.0, r
     assert r["flow_hmc"]["acceptance_flow"] > 0.4, r
-    se = math.sqrt(1.0 / r["hmc"]["ess"] + 1.0 / r["flow_hmc"]["ess"])
-    assert max(r["mean_diff_sigma"]) < 5 * se, (r["mean_diff_sigma"], se)
-    # the standard error of a standard deviation is about half that of a mean (Gaussian case)
-    assert max(r["std_diff_sigma"]) < 5 * se, (r["std_diff_sigma"], se)
+    assert min(r["flow_hmc"]["ess_per_param"]) >= 1600, r["flow_hmc"]["ess_per_param"]
+    assert r["flow_hmc"]["steps_over_tau"] >= 20.0, r["flow_hmc"]["steps_over_tau"]
+    assert min(r["reference"]["ess_per_param"]) >= 1600, r["reference"]["ess_per_param"]
+    imp = r["importance"]
+    assert imp["kish_ess"] > 1000, imp["kish_ess"]
+    assert np.all(np.abs(imp["z_mean_flow_minus_is"]) < 5.0), imp["z_mean_flow_minus_is"]
+    assert max(r["mean_diff_sigma_flow"]) < 0.25, r["mean_diff_sigma_flow"]
+    assert max(r["std_diff_sigma_flow"]) < 0.25, r["std_diff_sigma_flow"]

@@ -486,3 +486,75 @@ def test_gamma2_above_one_branch(gpu):
         fs = np.sqrt(np.outer(np.diag(Fr), np.diag(Fr)))
         assert np.all(np.abs(F[i] - Fr) <= 1e-10 * fs), i
     assert valid >= 8
+
+
+def _mismatch_case(log2n, nt, seed, lam0):
+    cfg = W.config4(n=nt, seed=seed, n_fft=1 << log2n)
+    g = cfg["grid"].as_tuple()
+    targets = np.stack([O.waveform(t, P, cfg["lam_star"], g) for t in cfg["theta"]])
+    return cfg, g, targets
+
+
+@pytest.mark.parametrize("log2n", [6, 7, 10, 11, 13, 15])
+def test_mismatch_lengths_power_of_two(gpu, lam0, log2n):
+    """Every supported FFT length (odd and even powers of two, so both the square and the
+    2:1 four-step splits) against the oracle: mismatch, lag and the summed gradient; at 2^6 the
+    overlap maximum is also taken from the brute-force DFT of the definition."""
+    import torch
+    cfg, g, targets = _mismatch_case(log2n, 3, 2000 + log2n, lam0)
+    th, w = cfg["theta"], cfg["inv_psd"]
+    _say(f"mismatch_grad nt=3 nb=2^{log2n}")
+    mm, dl, lag = gpu.api.mismatch_grad(th, P, cfg["grid"], lam0, targets, w)
+    torch.cuda.synchronize()
+    mm, dl, lag = mm.cpu().numpy(), dl.cpu().numpy(), lag.cpu().numpy()
+    gsum = np.zeros(209)
+    wk = 4 * g[1] * w
+    for i in range(len(th)):
+        m_ref, j_ref, gap, gref = O.mismatch_grad_lambda(th[i], P, lam0, g, targets[i], wk)
+        assert gap > 1e-12, "ambiguous lag in the fixture"
+        assert lag[i] == j_ref, (lag[i], j_ref)
+        assert abs(mm[i] - m_ref) <= 1e-12, (mm[i], m_ref)
+        gsum += gref
+        if log2n == 6:
+            h = O.waveform(th[i], P, lam0, g)
+            z = np.abs(O.overlap_series_bruteforce(h, targets[i], wk))
+            a = math.fsum((wk * np.abs(h) ** 2).tolist())
+            b = math.fsum((wk * np.abs(targets[i]) ** 2).tolist())
+            assert lag[i] == int(np.argmax(z))
+            assert abs(mm[i] - (1.0 - z.max() / math.sqrt(a * b))) <= 1e-12
+    assert np.max(np.abs(dl - gsum)) <= 1e-8 * np.max(np.abs(gsum)), np.max(np.abs(dl - gsum)) / np.max(np.abs(gsum))
+
+
+def test_mismatch_gradient_vs_gpu_finite_differences(gpu, lam0):
+    """2 targets x 2^10 bins: the adjoint gradient against central differences of the GPU's own
+    summed mismatch (the lag is the arg-max at every evaluation; the fixture keeps it unambiguous)."""
+    import torch
+    cfg, g, targets = _mismatch_case(10, 2, 2101, lam0)
+    th, w = cfg["theta"], cfg["inv_psd"]
+    _say("mismatch_grad finite differences nt=2 nb=2^10")
+    mm, dl, lag = gpu.api.mismatch_grad(th, P, cfg["grid"], lam0, targets, w)
+    torch.cuda.synchronize()
+    dl, lag0 = dl.cpu().numpy(), lag.cpu().numpy()
+    assert np.all(mm.cpu().numpy() > 1e-8)
+    scale = np.max(np.abs(dl * np.abs(lam0)))
+    for i in [0, 14, 47, 60, 77, 100, 133, 160, 171, 190, 208]:
+        h = 1e-6 * abs(lam0[i])
+        vals = []
+        for sgn in (1.0, -1.0):
+            lv = lam0.copy()
+            lv[i] += sgn * h
+            m, _, lg = gpu.api.mismatch_grad(th, P, cfg["grid"], lv, targets, w, want_grad=False)
+            torch.cuda.synchronize()
+            assert np.array_equal(lg.cpu().numpy(), lag0)
+            vals.append(math.fsum(m.cpu().numpy().tolist()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - dl[i]) <= 1e-5 * scale / abs(lam0[i]) + 1e-6 * abs(dl[i]), (i, fd, dl[i])
+
+
+def test_mismatch_rejects_unsupported_lengths(gpu, lam0):
+    from paper_2302_05329_amd import _lib as L
+    for n in (32, 1000, 1 << 17):
+        cfg = W.config4(n=1, n_fft=n)
+        targets = np.zeros((1, n), dtype=np.complex128)
+        with pytest.raises(L.PdError, match="FFT length"):
+            gpu.api.mismatch_grad(cfg["theta"], P, cfg["grid"], lam0, targets, cfg["inv_psd"])

@@ -406,3 +406,105 @@ def test_independence_mh_matches_rule(gpu):
         assert acc[i] == ar
         assert np.array_equal(xs[i], xr) and lps[i] == lpr and lqs[i] == lqr
         assert np.array_equal(gs[i], gp[i] if ar else g[i])
+
+
+def test_dense_hmc_step_parity_gw(gpu, lam0):
+    """One dense-metric HMC transition on the gravitational-wave posterior against the oracle's
+    momentum-space formulation (p = L^-T xi, drift eps L L^T p)."""
+    import torch
+    from paper_2302_05329_amd import sampling
+    pb = _c5_problem(lam0, n_bins=4001)
+    post = sampling.Posterior(0, grid=pb["grid"], lam=lam0, data=pb["data"], inv_psd=pb["inv_psd"], lo=pb["lo"],
+                              hi=pb["hi"])
+    rng = np.random.default_rng(22)
+    x0 = post.to_x(pb["theta_inj"]) + 0.02 * rng.standard_normal((6, 7))
+    A = rng.standard_normal((7, 7)) * 0.01
+    cov = A @ A.T + np.diag([2e-3, 1e-2, 5e-2, 5e-2, 1e-1, 2e-4, 2e-1])
+    chol = np.linalg.cholesky(cov)
+    eps, L = 0.1, 4
+    xi = rng.standard_normal((6, 7))
+    u = rng.uniform(size=6)
+    _say("dense-metric hmc step GW n=6 L=4")
+    hmc = sampling.HMC(post, x0, eps, L, chol=chol)
+    acc = hmc.step(torch.as_tensor(xi, device="cuda"), torch.as_tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    xg, dhg, accg = hmc.x.cpu().numpy(), hmc.dh.cpu().numpy(), acc.cpu().numpy()
+    gr = pb["grid"].as_tuple()
+
+    def lpf(x):
+        return S.logp_gw(x, lam0, gr, pb["data"], pb["inv_psd"], pb["lo"], pb["hi"])
+
+    for i in range(6):
+        lp0, g0 = lpf(x0[i])
+        xr, lpr, _, ar, dhr = S.hmc_step_dense(lpf, x0[i], lp0, g0, xi[i], u[i], L, eps, chol)
+        assert abs(dhg[i] - dhr) <= 1e-8 * max(1.0, abs(dhr)), (dhg[i], dhr)
+        if abs(-dhr - math.log(u[i])) > 1e-6:
+            assert accg[i] == ar
+            assert np.max(np.abs(xg[i] - xr)) <= 1e-9 * (1 + np.max(np.abs(xr)))
+
+
+def test_dense_hmc_recovers_gaussian_target_on_gpu(gpu):
+    """Any metric leaves the target invariant: a deliberately skewed dense metric on the Gaussian
+    test target still recovers its moments."""
+    import torch
+    from paper_2302_05329_amd import sampling
+    mu = np.array([0.3, -1.0, 2.0, 0.0, 0.5, -0.2, 1.1])
+    sig = np.array([0.5, 1.0, 2.0, 0.1, 1.5, 0.7, 0.3])
+    post = sampling.Posterior(1, mu=mu, isig2=1 / sig**2)
+    rng = np.random.default_rng(23)
+    A = np.tril(rng.standard_normal((7, 7)) * 0.3)
+    chol = np.diag(sig) + A - np.diag(np.diag(A))
+    n = 4096
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(24)
+    x0 = mu + sig * rng.standard_normal((n, 7))
+    _say(f"dense-metric hmc on a Gaussian target n={n}")
+    hmc = sampling.HMC(post, x0, 0.25, 6, chol=chol)
+    draws = []
+    for t in range(80):
+        xi = torch.randn((n, 7), dtype=torch.float64, device="cuda", generator=gen)
+        u = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+        hmc.step(xi, u)
+        if t >= 20:
+            draws.append(hmc.x.cpu().numpy())
+    d = np.concatenate(draws)
+    assert np.all(np.abs(d.mean(axis=0) - mu) <= 0.02 * sig)
+    assert np.all(np.abs(d.std(axis=0) / sig - 1.0) <= 0.02)
+
+
+def test_dense_rwmh_step_parity_gw(gpu, lam0):
+    """Correlated random-walk steps x + L xi on the gravitational-wave posterior against the oracle."""
+    import torch
+    from paper_2302_05329_amd import sampling
+    pb = _c5_problem(lam0, n_bins=4001)
+    post = sampling.Posterior(0, grid=pb["grid"], lam=lam0, data=pb["data"], inv_psd=pb["inv_psd"], lo=pb["lo"],
+                              hi=pb["hi"])
+    rng = np.random.default_rng(25)
+    n = 16
+    x0 = post.to_x(pb["theta_inj"]) + 0.02 * rng.standard_normal((n, 7))
+    A = rng.standard_normal((7, 7)) * 0.005
+    chol = np.linalg.cholesky(A @ A.T + np.diag([1e-4, 4e-4, 2e-3, 2e-3, 4e-3, 1e-5, 1e-2]))
+    xi = rng.standard_normal((n, 7))
+    u = rng.uniform(size=n)
+    _say(f"dense random-walk MH step GW n={n}")
+    rw = sampling.RWMH(post, x0, chol=chol)
+    lp0 = rw.logp.cpu().numpy()
+    acc = rw.step(torch.as_tensor(xi, device="cuda"), torch.as_tensor(u, device="cuda"))
+    torch.cuda.synchronize()
+    xg, accg = rw.x.cpu().numpy(), acc.cpu().numpy()
+    gr = pb["grid"].as_tuple()
+
+    def lpf(x):
+        return S.logp_gw(x, lam0, gr, pb["data"], pb["inv_psd"], pb["lo"], pb["hi"], want_grad=False)[0]
+
+    checked = 0
+    for i in range(n):
+        ref0 = lpf(x0[i])
+        assert abs(lp0[i] - ref0) <= _lp_tol(pb, lam0, x0[i], ref0)
+        xr, lpr, ar = S.rwmh_step_dense(lpf, x0[i], ref0, xi[i], u[i], chol)
+        lpp = lpf(x0[i] + np.tril(chol) @ xi[i])
+        if abs(lpp - ref0 - math.log(u[i])) > 1e-6:
+            assert accg[i] == ar, (i, accg[i], ar)
+            assert np.max(np.abs(xg[i] - xr)) <= 1e-14 * (1 + np.max(np.abs(xr)))
+            checked += 1
+    assert checked >= n - 1 and 0 < accg.sum() < n

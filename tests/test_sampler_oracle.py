@@ -200,7 +200,8 @@ def test_autocorr_of_white_noise():
 
 def test_ensemble_autocorr_of_ar1():
     """The lag autocorrelation reported for the HMC/random-walk comparison, on stationary AR(1)
-    chains: rho^lag."""
+    chains: rho^lag for the six non-periodic features (the phase enters through cos 2 phic and
+    sin 2 phic, which are not AR(1))."""
     from paper_2302_05329_amd import rwmh_baseline as RB
     rng = np.random.default_rng(10)
     m, n, rho = 64, 4000, 0.9
@@ -210,7 +211,7 @@ def test_ensemble_autocorr_of_ar1():
         x[:, t] = rho * x[:, t - 1] + math.sqrt(1 - rho**2) * rng.standard_normal((m, 7))
     ac = RB.mean_autocorr(x)
     for k, lag in enumerate(RB.LAGS):
-        assert np.all(np.abs(ac[k] - rho**lag) < 0.02), (lag, ac[k])
+        assert np.all(np.abs(ac[k][:6] - rho**lag) < 0.02), (lag, ac[k])
 
 
 def test_network_posterior_with_one_optimal_site_is_the_single_detector_posterior(lam0):
@@ -231,3 +232,75 @@ def test_network_posterior_with_one_optimal_site_is_the_single_detector_posterio
     lpn, gn = S.logp_gw_network(x, lam0, g, [det], data[None], (1 / psd)[None], lo, hi, 0.0, orient)
     assert lpn == pytest.approx(lp1, rel=1e-12)
     assert np.allclose(gn, g1, rtol=1e-9, atol=1e-9 * np.max(np.abs(g1)))
+
+
+# ---------------------------------------------------------------------------------
+# HMC with a dense metric
+# ---------------------------------------------------------------------------------
+def _corr_gauss(seed=3):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((7, 7))
+    cov = A @ A.T / 7.0 + 0.05 * np.eye(7)
+    mu = rng.standard_normal(7)
+    prec = np.linalg.inv(cov)
+
+    def lpf(x):
+        r = np.asarray(x) - mu
+        return -0.5 * float(r @ prec @ r), -(prec @ r)
+    return mu, cov, lpf
+
+
+def test_dense_hmc_with_diagonal_metric_is_the_diagonal_step():
+    """L = diag(1/sqrt(m)) reproduces the diagonal-mass transition."""
+    mu, cov, lpf = _corr_gauss()
+    rng = np.random.default_rng(4)
+    mass = rng.uniform(0.5, 3.0, 7)
+    x = mu + rng.standard_normal(7)
+    lp, g = lpf(x)
+    xi = rng.standard_normal(7)
+    a = S.hmc_step(lpf, x, lp, g, xi, 0.3, 7, 0.05, mass)
+    b = S.hmc_step_dense(lpf, x, lp, g, xi, 0.3, 7, 0.05, np.diag(1.0 / np.sqrt(mass)))
+    assert a[3] == b[3]
+    assert np.max(np.abs(a[0] - b[0])) <= 1e-13 and abs(a[4] - b[4]) <= 1e-12
+
+
+def test_dense_leapfrog_is_reversible_and_second_order():
+    mu, cov, lpf = _corr_gauss()
+    L = np.linalg.cholesky(cov)
+    minv = L @ L.T
+    rng = np.random.default_rng(5)
+    x0 = mu + L @ rng.standard_normal(7)
+    p0 = np.linalg.solve(L.T, rng.standard_normal(7))
+    lp0, g0 = lpf(x0)
+    x1, p1, lp1, g1 = S.leapfrog_dense(lpf, x0, p0, g0, 12, 0.1, minv)
+    x2, p2, _, _ = S.leapfrog_dense(lpf, x1, -p1, g1, 12, 0.1, minv)
+    assert np.max(np.abs(x2 - x0)) <= 1e-12 and np.max(np.abs(-p2 - p0)) <= 1e-12
+    errs = []
+    for eps in (0.2, 0.1, 0.05):
+        n = int(round(1.2 / eps))
+        x1, p1, lp1, _ = S.leapfrog_dense(lpf, x0, p0, g0, n, eps, minv)
+        errs.append(abs((-lp1 + 0.5 * p1 @ minv @ p1) - (-lp0 + 0.5 * p0 @ minv @ p0)))
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_dense_hmc_with_exact_metric_solves_a_correlated_gaussian():
+    """With M^-1 equal to the target covariance the dynamics is a rotation in whitened
+    coordinates: a trajectory of length pi/2 moves to an independent draw (eps -> 0 limit), so
+    chains recover the mean and covariance of a strongly correlated target quickly."""
+    mu, cov, lpf = _corr_gauss()
+    L = np.linalg.cholesky(cov)
+    rng = np.random.default_rng(6)
+    n_chain, steps = 200, 60
+    xs = mu + (L @ rng.standard_normal((7, n_chain))).T
+    draws = []
+    for t in range(steps):
+        for c in range(n_chain):
+            lp, g = lpf(xs[c])
+            xs[c], _, _, _, _ = S.hmc_step_dense(lpf, xs[c], lp, g, rng.standard_normal(7), rng.uniform(), 8,
+                                                 math.pi / 16, L)
+        if t >= 10:
+            draws.append(xs.copy())
+    d = np.concatenate(draws)
+    se = np.sqrt(np.diag(cov) / len(d)) * 3.0    # draws are nearly independent
+    assert np.all(np.abs(d.mean(axis=0) - mu) <= 6.0 * se)
+    assert np.max(np.abs(np.cov(d.T) - cov)) <= 0.08 * np.max(np.abs(cov))
