@@ -48,12 +48,17 @@ typedef enum {
     PD_EDOMAIN = -2,      /* per-point: parameters outside the model's domain */
     PD_EHIP = -3,         /* a HIP runtime call failed */
     PD_ENOMEM = -4,       /* workspace too small */
-    PD_EUNSUPPORTED = -5  /* valid but not supported (e.g. n_fft not 2^16) */
+    PD_EUNSUPPORTED = -5  /* valid but not supported (e.g. an FFT length that is not 2^6..2^16) */
 } pd_status;
 
+/* Arithmetic of the per-bin model.  Only PD_FP64 is implemented: the phase needs FP64 (its
+ * summands reach 1e5 rad and the likelihood is sensitive to 1e-6 rad), and the amplitude shares the
+ * phase's FP64 intermediates, so a separate FP32 amplitude path saves little on a pass bound by
+ * FP64 issue.  PD_MIXED is reserved for that path and every entry point taking a precision
+ * returns PD_EUNSUPPORTED for it, launching nothing. */
 typedef enum {
     PD_FP64 = 0,   /* everything in FP64 */
-    PD_MIXED = 1   /* FP64 phase, shifts, derivatives and accumulation; FP32 amplitude ratio */
+    PD_MIXED = 1   /* reserved (FP32 amplitude ratio): PD_EUNSUPPORTED */
 } pd_precision;
 
 /* Layout of one parameter row theta[7]; derivatives are taken w.r.t. the same 7 numbers.
@@ -158,10 +163,14 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
                      void* workspace, size_t workspace_bytes, void* stream);
 
 /* One gradient-descent step on the 209 fit coefficients (Sec. 3.1, Eq. 6 on the mean loss of
- * Eq. 7):  L = (1/nt) sum_i M_i,  lambda <- lambda - alpha dL/dlambda.
+ * Eq. 7):  L = (1/nt) sum_i M_i,  lambda_j <- lambda_j - alpha P_j dL/dlambda_j.
  * Arguments as for pd_mismatch_grad, except:
  * lambda       [209] device, in/out: read by the mismatch pass, then updated in place
  * alpha        learning rate (finite, >= 0)
+ * precond      [209] device or NULL: per-coefficient factors P_j (NULL: P_j = 1, Eq. 6 as
+ *              printed).  P_j = lambda0_j^2 makes the step Eq. 6 in the relative coordinates
+ *              u_j = lambda_j / lambda0_j - 1 (dL/du_j = lambda0_j dL/dlambda_j).  Must not alias
+ *              lambda or dsum_dlambda.
  * mismatch     [nt]  output: M_i at the coefficients on entry
  * dsum_dlambda [209] output (required, must not alias lambda): sum over targets of dM/dlambda
  *              at the coefficients on entry
@@ -169,8 +178,9 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
  * of calls is the descent of Sec. 3.1 with no host synchronisation.
  */
 int pd_fit_lambda_step(const double* theta, int64_t nt, int param, const pd_grid* grid, double* lambda,
-                       const double* targets, const double* inv_psd, double alpha, double* mismatch,
-                       double* dsum_dlambda, void* workspace, size_t workspace_bytes, void* stream);
+                       const double* targets, const double* inv_psd, double alpha, const double* precond,
+                       double* mismatch, double* dsum_dlambda, void* workspace, size_t workspace_bytes,
+                       void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Detector network: the two-detector injection of Sec. 3.3 and the network setups of the

@@ -99,7 +99,7 @@ SIGNATURES = {
     "pd_network_fisher_workspace_bytes": (_SZ, [_I64, _I64, _INT]),
     "pd_network_fisher": (_INT, [_P, _I64, _INT, _GRID, _P, _INT, ctypes.POINTER(PdDetector), ctypes.c_double, _P, _P,
                                  _P, _P, _SZ, _P]),
-    "pd_fit_lambda_step": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, ctypes.c_double, _P, _P, _P, _SZ, _P]),
+    "pd_fit_lambda_step": (_INT, [_P, _I64, _INT, _GRID, _P, _P, _P, ctypes.c_double, _P, _P, _P, _P, _SZ, _P]),
     "pd_posterior_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),
     "pd_posterior_logp": (_INT, [ctypes.c_void_p, _P, _I64, _P, _P, _P, _SZ, _P]),
     "pd_hmc_workspace_bytes": (_SZ, [ctypes.c_void_p, _I64]),

@@ -218,9 +218,11 @@ def mismatch_grad(theta, param, grid, lam, targets, inv_psd, want_grad=True, ws=
 class LambdaFit:
     """Gradient descent on the 209 fit coefficients against fixed targets (Sec. 3.1): each
     `step` is one library call that evaluates the mismatches and their summed gradient at the
-    current coefficients and then updates them in place on the device."""
+    current coefficients and then updates them in place on the device.  `precond` [209] (or
+    None) multiplies each coefficient's step; relative=True sets it to lam0^2, which is Eq. 6 in
+    the coordinates u = lam / lam0 - 1."""
 
-    def __init__(self, theta, param, grid, lam0, targets, inv_psd, alpha, ws=None):
+    def __init__(self, theta, param, grid, lam0, targets, inv_psd, alpha, ws=None, precond=None, relative=False):
         self.ws = ws or Workspace()
         self.g = _grid(grid)
         self.th = _dev(theta)
@@ -233,14 +235,44 @@ class LambdaFit:
         self.nt = self.th.shape[0]
         self.mismatch = torch.empty(self.nt, dtype=torch.float64, device="cuda")
         self.dsum = torch.empty(209, dtype=torch.float64, device="cuda")
+        if relative:
+            precond = self.lam.square()
+        self.precond = None if precond is None else _dev(precond).clone().contiguous()
+        if self.precond is not None and tuple(self.precond.shape) != (209,):
+            raise ValueError("precond must have 209 entries")
+
+    def _mean_grad(self, lam):
+        _, d, _ = mismatch_grad(self.th, self.param, self.g, lam, self.tg, self.ip, ws=self.ws)
+        return d / self.nt
+
+    def max_curvature(self, iters=25, rel_eps=1e-5, seed=0):
+        """Largest eigenvalue of P^1/2 H P^1/2 at the current coefficients (H the Hessian of the
+        mean mismatch, P the preconditioner or the identity) by power iteration, each
+        Hessian-vector product a difference of two gradients.  Eq. 6 decreases the local quadratic
+        model monotonically for alpha <= 1 / that value."""
+        lam = self.lam.clone()
+        ps = torch.ones_like(lam) if self.precond is None else self.precond.clamp_min(0.0).sqrt()
+        g0 = self._mean_grad(lam)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        v = torch.randn(209, dtype=torch.float64, device="cuda", generator=gen)
+        v /= v.norm()
+        lmax = 0.0
+        for _ in range(iters):
+            w = ps * v
+            e = rel_eps * float(lam.norm()) / max(float(w.norm()), 1e-300)
+            hv = ps * (self._mean_grad(lam + e * w) - g0) / e
+            lmax = float(v @ hv)
+            v = hv / hv.norm()
+        return lmax
 
     def step(self):
         """One descent step; afterwards `mismatch` and `dsum` hold the values at the coefficients
         before the update and `lam` the updated coefficients."""
         wp, wb = self.ws.get(workspace_bytes(L.PD_OP_MISMATCH_GRAD, self.nt, self.g.n_bins))
         L.check(L.lib().pd_fit_lambda_step(_ptr(self.th), self.nt, self.param, ctypes.byref(self.g), _ptr(self.lam),
-                                           _ptr(self.tg), _ptr(self.ip), self.alpha, _ptr(self.mismatch),
-                                           _ptr(self.dsum), wp, wb, _stream()))
+                                           _ptr(self.tg), _ptr(self.ip), self.alpha, _ptr(self.precond),
+                                           _ptr(self.mismatch), _ptr(self.dsum), wp, wb, _stream()))
 
 
 def overlap(theta, param, grid, lam, streams, inv_psd, want_hh=True, ws=None):

@@ -241,7 +241,8 @@ int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* g
     int rc = check_common(theta, n, param, grid, lambda, &g);
     if (rc) return rc;
     if (!h_out) return fail(PD_EINVAL, "h_out is NULL");
-    if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision");
+    if (precision == PD_MIXED) return fail(PD_EUNSUPPORTED, "PD_MIXED (FP32 amplitude) is not implemented; use PD_FP64");
+    if (precision != PD_FP64) return fail(PD_EINVAL, "unknown precision");
     Layout L;
     rc = check_ws(PD_OP_WAVEFORM, n, g.nb, workspace, workspace_bytes, &L);
     if (rc) return rc;
@@ -279,7 +280,8 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
     if (!data) return fail(PD_EINVAL, "data is NULL");
     if (!inv_psd) return fail(PD_EINVAL, "inv_psd is NULL");
     if (!lnl) return fail(PD_EINVAL, "lnl is NULL");
-    if (precision != PD_FP64 && precision != PD_MIXED) return fail(PD_EINVAL, "unknown precision");
+    if (precision == PD_MIXED) return fail(PD_EUNSUPPORTED, "PD_MIXED (FP32 amplitude) is not implemented; use PD_FP64");
+    if (precision != PD_FP64) return fail(PD_EINVAL, "unknown precision");
     const int op = grad ? PD_OP_LOGLIKE_GRAD : PD_OP_LOGLIKE;
     Layout L;
     rc = check_ws(op, n, g.nb, workspace, workspace_bytes, &L);
@@ -561,15 +563,18 @@ int pd_network_fisher(const double* theta, int64_t n, int param, const pd_grid* 
 }
 
 int pd_fit_lambda_step(const double* theta, int64_t nt, int param, const pd_grid* grid, double* lambda,
-                       const double* targets, const double* inv_psd, double alpha, double* mismatch,
-                       double* dsum_dlambda, void* workspace, size_t workspace_bytes, void* stream) {
+                       const double* targets, const double* inv_psd, double alpha, const double* precond,
+                       double* mismatch, double* dsum_dlambda, void* workspace, size_t workspace_bytes,
+                       void* stream) {
     if (!dsum_dlambda) return fail(PD_EINVAL, "dsum_dlambda is NULL");
     if (dsum_dlambda == lambda) return fail(PD_EINVAL, "dsum_dlambda must not alias lambda");
+    if (precond && (precond == lambda || precond == dsum_dlambda))
+        return fail(PD_EINVAL, "precond must not alias lambda or dsum_dlambda");
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(PD_EINVAL, "alpha must be finite and >= 0");
     const int rc = pd_mismatch_grad(theta, nt, param, grid, lambda, targets, inv_psd, mismatch, dsum_dlambda,
                                     nullptr, workspace, workspace_bytes, stream);
     if (rc != PD_OK) return rc;
-    const hipError_t e = pd::launch_lambda_update(lambda, dsum_dlambda, alpha / static_cast<double>(nt),
+    const hipError_t e = pd::launch_lambda_update(lambda, dsum_dlambda, precond, alpha / static_cast<double>(nt),
                                                   static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "coefficient update");
     return PD_OK;

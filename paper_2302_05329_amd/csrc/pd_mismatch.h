@@ -22,6 +22,7 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
                            const double* tab, const double* targets, const double* inv_psd, void* scratch, double* mismatch,
                            double* dsum_dlambda, int32_t* lag, hipStream_t s);
 
-hipError_t launch_lambda_update(double* lam, const double* dsum, double scale, hipStream_t s);
+hipError_t launch_lambda_update(double* lam, const double* dsum, const double* precond, double scale,
+                                hipStream_t s);
 
 }  // namespace pd

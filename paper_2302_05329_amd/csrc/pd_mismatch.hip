@@ -577,14 +577,19 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
 }
 
 // One gradient-descent step on the coefficients (Sec. 3.1, Eq. 6 with the mean loss of Eq. 7):
-// lambda -= scale * dsum, scale = alpha / n_targets.
-__global__ void k_lambda_update(double* __restrict__ lam, const double* __restrict__ dsum, double scale) {
+// lambda_i -= scale * P_i * dsum_i, scale = alpha / n_targets, P_i = precond[i] (1 without one).
+__global__ void k_lambda_update(double* __restrict__ lam, const double* __restrict__ dsum,
+                                const double* __restrict__ precond, double scale) {
     const int i = threadIdx.x;
-    if (i < kNumLambda) lam[i] = fma(-scale, dsum[i], lam[i]);
+    if (i < kNumLambda) {
+        const double step = precond ? scale * precond[i] : scale;
+        lam[i] = fma(-step, dsum[i], lam[i]);
+    }
 }
 
-hipError_t launch_lambda_update(double* lam, const double* dsum, double scale, hipStream_t s) {
-    hipLaunchKernelGGL(k_lambda_update, dim3(1), dim3(256), 0, s, lam, dsum, scale);
+hipError_t launch_lambda_update(double* lam, const double* dsum, const double* precond, double scale,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_lambda_update, dim3(1), dim3(256), 0, s, lam, dsum, precond, scale);
     return hipGetLastError();
 }
 

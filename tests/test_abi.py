@@ -125,14 +125,15 @@ def test_network_rejects_bad_arguments(lib, bad):
     assert len(lib.pd_last_error()) > 0
 
 
-@pytest.mark.parametrize("bad", ["alpha_neg", "alpha_nan", "dsum", "alias"])
+@pytest.mark.parametrize("bad", ["alpha_neg", "alpha_nan", "dsum", "alias", "precond_alias"])
 def test_fit_lambda_step_rejects_bad_arguments(lib, bad):
     vp = ctypes.c_void_p
     g = L.make_grid(0.0, 0.01, 65536, 1.0, 20.0)
     alpha = {"alpha_neg": -1e-6, "alpha_nan": float("nan")}.get(bad, 1e-6)
     dsum = None if bad == "dsum" else (512 if bad == "alias" else 4096)
-    rc = lib.pd_fit_lambda_step(vp(256), 1, 3, ctypes.byref(g), vp(512), vp(768), vp(1024), alpha, vp(1280),
-                                vp(dsum) if dsum else None, vp(2048), 1 << 40, None)
+    precond = vp(512) if bad == "precond_alias" else None
+    rc = lib.pd_fit_lambda_step(vp(256), 1, 3, ctypes.byref(g), vp(512), vp(768), vp(1024), alpha, precond,
+                                vp(1280), vp(dsum) if dsum else None, vp(2048), 1 << 40, None)
     assert rc == L.PD_EINVAL
     assert len(lib.pd_last_error()) > 0
 

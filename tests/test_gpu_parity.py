@@ -243,6 +243,40 @@ def test_batch_errors_raise_without_launch(gpu, lam0):
         gpu.api.waveform_eval(np.zeros((2, 6)), P, W.Grid(20, 0.25, 100), lam0)
 
 
+def test_mixed_precision_is_unsupported_and_launches_nothing(gpu, lam0):
+    """PD_MIXED is reserved: every entry point that takes a precision returns PD_EUNSUPPORTED and
+    leaves its outputs untouched."""
+    import ctypes
+    import torch
+    from paper_2302_05329_amd import _lib as L
+    from paper_2302_05329_amd.api import _ptr
+    cfg = W.config2(n=64)
+    g = cfg["grid"]
+    gr = L.make_grid(*g.as_tuple())
+    th = torch.as_tensor(cfg["theta"], device="cuda")
+    lam = torch.as_tensor(lam0, device="cuda")
+    d = torch.as_tensor(np.stack([cfg["data"].real, cfg["data"].imag], -1), device="cuda").contiguous()
+    ip = torch.as_tensor(cfg["inv_psd"], device="cuda")
+    lnl = torch.full((64,), 7.0, dtype=torch.float64, device="cuda")
+    grad = torch.full((64, 7), 7.0, dtype=torch.float64, device="cuda")
+    h = torch.full((64, g.n_bins, 2), 7.0, dtype=torch.float64, device="cuda")
+    nb = L.lib().pd_workspace_bytes(L.PD_OP_LOGLIKE_GRAD, 64, g.n_bins)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    lib = L.lib()
+    rcs = [lib.pd_loglike_and_grad(_ptr(th), 64, P, ctypes.byref(gr), _ptr(lam), _ptr(d), _ptr(ip), L.PD_MIXED,
+                                   _ptr(lnl), _ptr(grad), None, _ptr(ws), nb, None),
+           lib.pd_loglike_and_grad_noalloc(_ptr(th), 64, P, ctypes.byref(gr), _ptr(lam), _ptr(d), _ptr(ip),
+                                           L.PD_MIXED, _ptr(lnl), _ptr(grad), None, None)]
+    nbw = L.lib().pd_workspace_bytes(L.PD_OP_WAVEFORM, 64, g.n_bins)
+    wsw = torch.empty(nbw, dtype=torch.uint8, device="cuda")
+    rcs.append(lib.pd_waveform_eval(_ptr(th), 64, P, ctypes.byref(gr), _ptr(lam), L.PD_MIXED, _ptr(h), None,
+                                    _ptr(wsw), nbw, None))
+    torch.cuda.synchronize()
+    assert rcs == [L.PD_EUNSUPPORTED] * 3, rcs
+    assert b"PD_MIXED" in lib.pd_last_error()
+    assert bool(torch.all(lnl == 7.0)) and bool(torch.all(grad == 7.0)) and bool(torch.all(h == 7.0))
+
+
 def test_results_are_bitwise_reproducible(gpu, lam0):
     import torch
     cfg = W.config2(n=256)
@@ -359,6 +393,54 @@ def test_fit_lambda_descent_full_c4(gpu, lam0):
     assert losses[0] == pytest.approx(loss0, rel=1e-12)
     drop = losses[:-1] - losses[1:]
     assert np.all(drop > 0.5 * pred[:-1]) and np.all(drop <= 1.05 * pred[:-1]), (drop / pred[:-1])
+
+
+def test_fit_lambda_relative_step_parity(gpu, lam0):
+    """One preconditioned step (Eq. 6 in u = lam / lam0 - 1, i.e. the factor lam0^2 on each
+    coefficient's step) against the oracle's summed gradient."""
+    import torch
+    from paper_2302_05329_amd import api
+    cfg = W.config4(n=2, n_fft=1 << 12)
+    g = cfg["grid"].as_tuple()
+    th, w = cfg["theta"], cfg["inv_psd"]
+    targets = np.stack([O.waveform(t, P, cfg["lam_star"], g) for t in th])
+    _say("fit_lambda_step relative coordinates nt=2 nb=2^12")
+    alpha = 2e-3
+    fit = api.LambdaFit(th, P, cfg["grid"], lam0, targets, w, alpha, relative=True)
+    fit.step()
+    torch.cuda.synchronize()
+    lam1 = fit.lam.cpu().numpy()
+    _, _, g_ref = O.fit_lambda_step(th, P, lam0, g, targets, 4 * g[1] * w, 0.0)
+    l0 = lam0.reshape(-1)
+    lam_ref = l0 - alpha / len(th) * l0 ** 2 * g_ref
+    scale = np.max(np.abs(l0 ** 2 * g_ref))
+    tol = alpha / len(th) * 1e-8 * scale + 4 * np.spacing(np.abs(l0))
+    assert np.all(np.abs(lam1 - lam_ref) <= tol), np.max(np.abs(lam1 - lam_ref) / tol)
+
+
+def test_fit_lambda_descent_relative_full_c4(gpu, lam0):
+    """Eq. 6 in u = lam / lam0 - 1 at the full workload (512 targets x 2^16 bins) with alpha = 1 /
+    (largest Hessian eigenvalue in u, by power iteration): 300 steps lower the mean mismatch at
+    every step and end below 0.5 of the start."""
+    import torch
+    from paper_2302_05329_amd import api
+    cfg = W.config4()
+    th, w = cfg["theta"], cfg["inv_psd"]
+    targets, _ = api.waveform_eval(th, P, cfg["grid"], cfg["lam_star"])
+    fit = api.LambdaFit(th, P, cfg["grid"], lam0, targets, w, 0.0, relative=True)
+    lmax = fit.max_curvature()
+    assert lmax > 0
+    fit.alpha = 1.0 / lmax
+    _say(f"fit_lambda descent in u, C4 nt={len(th)}: 300 steps alpha={fit.alpha:.3g}")
+    losses = []
+    for _ in range(301):
+        fit.step()
+        losses.append(fit.mismatch.mean())
+    torch.cuda.synchronize()
+    losses = np.array([float(x) for x in losses])
+    _say(f"loss {losses[0]:.4e} -> {losses[-1]:.4e} ({losses[0] / losses[-1]:.2f}x)")
+    assert np.all(np.diff(losses) < 0), np.nonzero(np.diff(losses) >= 0)
+    assert losses[-1] < 0.5 * losses[0]
 
 
 def test_autograd_wrappers(gpu, lam0):
