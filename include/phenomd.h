@@ -264,8 +264,8 @@ enum {
     PD_K_LOGLIKE = 1,         /* fused lnL (value only) */
     PD_K_FISHER = 2,          /* Fisher accumulation */
     PD_K_WAVEFORM = 3,        /* strain output */
-    PD_K_MISMATCH_INPUT = 4,  /* overlap input (model per bin) */
-    PD_K_MISMATCH_FFT = 5,    /* both FFT passes with the fused arg-max */
+    PD_K_MISMATCH_INPUT = 4,  /* overlap input (model per bin) fused with the column FFT pass */
+    PD_K_MISMATCH_FFT = 5,    /* row FFT pass with the fused arg-max */
     PD_K_MISMATCH_ADJ = 6,    /* mismatch adjoint moments */
     PD_K_OVERLAP = 7,         /* template-bank overlap GEMM (generation + FP64 MFMA) */
     PD_K_COUNT = 8

@@ -3,18 +3,19 @@
 // over the coalescence time is taken with a Fourier transform, Sec. 2).
 //
 // Pipeline per target (N = N1 x N2 bins, a power of two from 2^6 to 2^16 = 256 x 256):
-//   1. overlap input   x_k = w_k conj(h_k) t_k (model recomputed per bin), partial
-//                      sums of (h|h) and (t|t)                         one thread / bin
-//   2. column pass     N2-point inverse DFTs over k2 of x[k1 + N1 k2] in LDS
-//                      (radix-2 Stockham), twiddle exp(2 pi i j2 k1 / N), store
-//                      transposed                                      2048 / N2 columns / block
-//   3. row pass        N1-point inverse DFTs over k1, |z|^2 and arg-max fused (lag
+//   0. twiddles        exp(2 pi i m / N) = hi[m >> 8] lo[m & 255] tables      one block / call
+//   1. column pass     the overlap input x_k = w_k conj(h_k) t_k (model recomputed per bin, never
+//                      stored) for the bins k1 + N1 k2 of a group of columns k1, partial sums of
+//                      (h|h) and (t|t), N2-point inverse DFTs over k2 in LDS (radix-4
+//                      Stockham, one buffer), twiddle exp(2 pi i j2 k1 / N), store transposed
+//                                                                      2048 / N2 columns / block
+//   2. row pass        N1-point inverse DFTs over k1, |z|^2 and arg-max fused (lag
 //                      j = j2 + N2 j1); the overlap series itself is never written
 //                                                                      2048 / N1 rows / block
-//   4. finalize        lag j*, |z_j*|, mismatch                         one thread / target
-//   5. adjoint         moments of the mismatch adjoint per bin (model recomputed, no
+//   3. finalize        lag j*, |z_j*|, mismatch                         one thread / target
+//   4. adjoint         moments of the mismatch adjoint per bin (model recomputed, no
 //                      per-bin storage)                                 one wave / (target, chunk)
-//   6. chain rule      record tangents along the 19 fitted parameters -> d M / d Lambda,
+//   5. chain rule      record tangents along the 19 fitted parameters -> d M / d Lambda,
 //                      times the 11 fit-basis values -> d M / d lambda, summed over
 //                      targets in a fixed order
 #include <hip/hip_runtime.h>
@@ -33,10 +34,11 @@ struct FFTPlan {
     int64_t n;          // N
     int n1, n2;         // columns (row length) and column length
     int cb, rb;         // columns per column-pass block, rows per row-pass block
-    int ibl;            // input blocks per target (256 bins each)
+    int gc, gr;         // column groups and row groups per target
 };
 
-constexpr int kLdsPts = 2048;   // complex points per LDS buffer (2 x 32 KiB ping-pong)
+constexpr int kLdsPts = 2048;   // complex points per block (one 32 KiB LDS buffer, plus padding)
+constexpr int kTw = 256;        // entries of each twiddle table
 
 inline FFTPlan make_plan(int64_t n) {
     FFTPlan f;
@@ -47,15 +49,16 @@ inline FFTPlan make_plan(int64_t n) {
     f.n2 = 1 << (lg / 2);
     f.cb = kLdsPts / f.n2 < f.n1 ? kLdsPts / f.n2 : f.n1;
     f.rb = kLdsPts / f.n1 < f.n2 ? kLdsPts / f.n1 : f.n2;
-    f.ibl = static_cast<int>((n + 255) / 256);
+    f.gc = f.n1 / f.cb;
+    f.gr = f.n2 / f.rb;
     return f;
 }
 
 struct MMScratch {
-    double2* X;       // [nt][N]
     double2* Y;       // [nt][N2][N1] (transposed after the column pass)
-    double* ab;       // [nt][ibl][2]
-    double* mx;       // [nt][N2 / rb][4]  (|z|^2, index, zr, zi)
+    double2* tw;      // [2][kTw]: lo[i] = exp(2 pi i i / N), hi[i] = exp(2 pi i 256 i / N)
+    double* ab;       // [nt][gc][2]
+    double* mx;       // [nt][gr][4]  (|z|^2, index, zr, zi)
     double* scal;     // [nt][kSlotMM]
     double* mom;      // [nt][chunks][kNSlot]
     double* dlam;     // [nt][19]
@@ -79,10 +82,10 @@ size_t carve_into(void* base, int64_t nt, int64_t nb, MMScratch* m) {
     };
     MMScratch t;
     t.chunks = chunks_for(nt, nb);
-    t.X = reinterpret_cast<double2*>(take(n * f.n * sizeof(double2)));
     t.Y = reinterpret_cast<double2*>(take(n * f.n * sizeof(double2)));
-    t.ab = reinterpret_cast<double*>(take(n * f.ibl * 2 * sizeof(double)));
-    t.mx = reinterpret_cast<double*>(take(n * (f.n2 / f.rb) * 4 * sizeof(double)));
+    t.tw = reinterpret_cast<double2*>(take(2 * kTw * sizeof(double2)));
+    t.ab = reinterpret_cast<double*>(take(n * f.gc * 2 * sizeof(double)));
+    t.mx = reinterpret_cast<double*>(take(n * f.gr * 4 * sizeof(double)));
     t.scal = reinterpret_cast<double*>(take(n * kSlotMM * sizeof(double)));
     t.mom = reinterpret_cast<double*>(take(3 * n * t.chunks * kNSlot * sizeof(double)));
     t.dlam = reinterpret_cast<double*>(take(n * kNumFit * sizeof(double)));
@@ -95,93 +98,102 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// exp(2 pi i num / den) for an exact rational argument
-__device__ __forceinline__ double2 expi_ratio(int64_t num, int64_t den) {
+// ---- 0. twiddle tables ------------------------------------------------------------------
+// exp(2 pi i m / N) for 0 <= m < N (N a power of two, N <= 2^16) as hi[m >> 8] * lo[m & 255]
+// with lo[i] = exp(2 pi i i / N) and hi[i] = exp(2 pi i 256 i / N), each from sincospi of an exact
+// argument; the product is within about two units in the last place.
+__global__ void k_mm_twiddles(int64_t n, double2* __restrict__ tw) {
+    const int i = threadIdx.x;
     double s, c;
-    sincospi(2.0 * static_cast<double>(num) / static_cast<double>(den), &s, &c);
-    return make_double2(c, s);
+    sincospi(2.0 * static_cast<double>(i) / static_cast<double>(n), &s, &c);
+    tw[i] = make_double2(c, s);
+    sincospi(2.0 * static_cast<double>(256 * i) / static_cast<double>(n), &s, &c);
+    tw[kTw + i] = make_double2(c, s);
 }
 
-// ---- 1. overlap input -----------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_mm_input(const double* __restrict__ recs, int64_t nt, GridArgs g,
-                                                  const double* __restrict__ tab,
-                                                  const double* __restrict__ targets,
-                                                  const double* __restrict__ inv_psd, double2* __restrict__ X,
-                                                  double* __restrict__ ab, int blocks) {
-    __shared__ double red[2][4];
-    const int64_t N = g.nb;
-    const int64_t p = blockIdx.x / blocks;
-    const int64_t kb = (blockIdx.x % blocks) * 256;
-    const int64_t k = kb + threadIdx.x;
-    const bool in = k < N;
-    const double* __restrict__ rec = recs + p * REC_N;
-    const Tabs T(tab, g.nb);
-    const double2 t = in ? reinterpret_cast<const double2*>(targets)[p * N + k] : make_double2(0.0, 0.0);
-    const double w = in ? 4.0 * g.df * inv_psd[k] : 0.0;
-    double2 h = make_double2(0.0, 0.0);
-    if (in && rec[R_VALID] != 0.0) {
-        const double f = bin_freq(g, k);
-        const double mf = rec[R_MS] * f;
-        if (bin_active(g, f, mf)) {
-            BinVals bv;
-            eval_bin_rt(rec, T, k, mf, bv);
-            const double A = rec[R_A0P] * T.at(T_F76, k) * bv.ahat;
-            double sn, cs;
-            pd_sincos(bv.psi, &sn, &cs);
-            h = make_double2(A * cs, -A * sn);
-        }
-    }
-    // x = w conj(h) t
-    if (in) X[p * N + k] = make_double2(w * (h.x * t.x + h.y * t.y), w * (h.x * t.y - h.y * t.x));
-    const double a = wave_sum(w * (h.x * h.x + h.y * h.y));
-    const double b = wave_sum(w * (t.x * t.x + t.y * t.y));
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[0][wid] = a;
-        red[1][wid] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double* o = ab + (p * blocks + (blockIdx.x % blocks)) * 2;
-        o[0] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
-        o[1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
-    }
+__device__ __forceinline__ double2 twiddle(const double2* __restrict__ tw, unsigned m) {
+    return cmul(tw[kTw + (m >> 8)], tw[m & 255u]);
 }
 
-// ---- LDS radix-2 Stockham inverse DFT of length LEN on `cols` columns -------------------
-// buf/tmp: cols x LEN points (column c at c * LEN); the block's 256 threads share the cols x LEN/2
-// butterflies of each stage.  The result ends in `buf` when log2(LEN) is even, else in `tmp`;
-// the returned pointer says which.
+// ---- LDS radix-4 Stockham inverse DFT of length LEN on `cols` columns ----------------------
+// Column c of `buf` starts at c * (LEN + 1) (one point of padding spreads the columns over the
+// banks; cols * LEN <= 2048, so the buffer holds 2048 + 2048 / LEN points).  Each stage: every thread loads the inputs of its butterflies into registers, the block
+// synchronises, the outputs are written, the block synchronises.  Stages of radix 4
+// (X_j = sum_k a_k i^(jk) for the inverse transform), then one of radix 2 when log2(LEN) is odd.
+// tw[j] = exp(2 pi i j / LEN).  The result is in natural order in `buf`.
 template <int LEN>
-__device__ __forceinline__ double2* lds_idft(double2* buf, double2* tmp, int cols, const double2* __restrict__ tw) {
-    double2* x = buf;
-    double2* y = tmp;
-    int n = LEN, s = 1;
-    const int nb = cols * (LEN / 2);
+__device__ __forceinline__ void lds_idft(double2* buf, int cols, const double2* __restrict__ tw) {
+    constexpr int kLog2 = __builtin_ctz(LEN);
+    constexpr int kR4 = kLog2 / 2;
+    constexpr int kLd = LEN + 1;
+    constexpr int kPer4 = (kLdsPts / 4 + 255) / 256;   // radix-4 butterflies per thread (at most)
+    const int nb4 = cols * (LEN / 4);
 #pragma unroll
-    for (int stage = 0; (1 << stage) < LEN; ++stage) {
-        const int m = n >> 1;
-        for (int idx = threadIdx.x; idx < nb; idx += 256) {
-            const int col = idx / (LEN / 2);
-            const int b = idx - col * (LEN / 2);   // butterfly index in [0, LEN/2)
-            const int q = b % s;
-            const int pp = b / s;
-            const double2* xc = x + col * LEN;
-            double2* yc = y + col * LEN;
-            const double2 a = xc[q + s * pp];
-            const double2 c = xc[q + s * (pp + m)];
-            const double2 w = tw[pp * (LEN / n)];    // exp(2 pi i pp / n)
-            yc[q + s * (2 * pp)] = make_double2(a.x + c.x, a.y + c.y);
-            yc[q + s * (2 * pp + 1)] = cmul(make_double2(a.x - c.x, a.y - c.y), w);
+    for (int st = 0; st < kR4; ++st) {
+        const int n = LEN >> (2 * st), s = 1 << (2 * st), m = n >> 2;
+        double2 a[kPer4][4];
+#pragma unroll
+        for (int r = 0; r < kPer4; ++r) {
+            const int idx = threadIdx.x + 256 * r;
+            if (idx < nb4) {
+                const int col = idx / (LEN / 4), b = idx - col * (LEN / 4);
+                const int q = b & (s - 1), pp = b >> (2 * st);
+                const double2* xc = buf + col * kLd + q + s * pp;
+                a[r][0] = xc[0];
+                a[r][1] = xc[s * m];
+                a[r][2] = xc[2 * s * m];
+                a[r][3] = xc[3 * s * m];
+            }
         }
         __syncthreads();
-        double2* t = x;
-        x = y;
-        y = t;
-        n = m;
-        s <<= 1;
+#pragma unroll
+        for (int r = 0; r < kPer4; ++r) {
+            const int idx = threadIdx.x + 256 * r;
+            if (idx < nb4) {
+                const int col = idx / (LEN / 4), b = idx - col * (LEN / 4);
+                const int q = b & (s - 1), pp = b >> (2 * st);
+                const double2 b0 = make_double2(a[r][0].x + a[r][2].x, a[r][0].y + a[r][2].y);
+                const double2 b1 = make_double2(a[r][0].x - a[r][2].x, a[r][0].y - a[r][2].y);
+                const double2 b2 = make_double2(a[r][1].x + a[r][3].x, a[r][1].y + a[r][3].y);
+                // i (a1 - a3)
+                const double2 b3 = make_double2(a[r][3].y - a[r][1].y, a[r][1].x - a[r][3].x);
+                const int ts = pp * (LEN / n);
+                double2* yc = buf + col * kLd + q + s * 4 * pp;
+                yc[0] = make_double2(b0.x + b2.x, b0.y + b2.y);
+                yc[s] = cmul(make_double2(b1.x + b3.x, b1.y + b3.y), tw[ts]);
+                yc[2 * s] = cmul(make_double2(b0.x - b2.x, b0.y - b2.y), tw[2 * ts]);
+                yc[3 * s] = cmul(make_double2(b1.x - b3.x, b1.y - b3.y), tw[3 * ts]);
+            }
+        }
+        __syncthreads();
     }
-    return x;
+    if constexpr (kLog2 & 1) {
+        // last stage: n = 2, s = LEN / 2, twiddle 1
+        constexpr int s = LEN / 2;
+        constexpr int kPer2 = (kLdsPts / 2 + 255) / 256;
+        const int nb2 = cols * (LEN / 2);
+        double2 a[kPer2][2];
+#pragma unroll
+        for (int r = 0; r < kPer2; ++r) {
+            const int idx = threadIdx.x + 256 * r;
+            if (idx < nb2) {
+                const int col = idx / (LEN / 2), q = idx - col * (LEN / 2);
+                a[r][0] = buf[col * kLd + q];
+                a[r][1] = buf[col * kLd + q + s];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kPer2; ++r) {
+            const int idx = threadIdx.x + 256 * r;
+            if (idx < nb2) {
+                const int col = idx / (LEN / 2), q = idx - col * (LEN / 2);
+                buf[col * kLd + q] = make_double2(a[r][0].x + a[r][1].x, a[r][0].y + a[r][1].y);
+                buf[col * kLd + q + s] = make_double2(a[r][0].x - a[r][1].x, a[r][0].y - a[r][1].y);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 template <int LEN>
@@ -193,36 +205,77 @@ __device__ __forceinline__ void fill_twiddles(double2* tw) {
     }
 }
 
-// ---- 2. column pass ------------------------------------------------------------------
-// LEN = N2: block (target p, column group) transforms columns gcol .. gcol + cols - 1.
+// ---- 1. column pass with the overlap input -------------------------------------------------
+// LEN = N2: block (target p, column group) computes x_k for the bins k = k1 + N1 k2 of the columns
+// k1 = gcol .. gcol + cols - 1 and transforms each column over k2.
 template <int LEN>
-__global__ void __launch_bounds__(256) k_mm_fft_cols(const double2* __restrict__ X, double2* __restrict__ Y, int n1,
-                                                     int cols) {
-    __shared__ double2 buf[kLdsPts];
-    __shared__ double2 tmp[kLdsPts];
+__global__ void __launch_bounds__(256) k_mm_cols(const double* __restrict__ recs, GridArgs g,
+                                                 const double* __restrict__ tab, const double* __restrict__ targets,
+                                                 const double* __restrict__ inv_psd,
+                                                 const double2* __restrict__ twg, double2* __restrict__ Y,
+                                                 double* __restrict__ ab, int n1, int cols) {
+    constexpr int kLd = LEN + 1;
+    __shared__ double2 buf[kLdsPts + kLdsPts / LEN];
     __shared__ double2 tw[LEN];
-    const int64_t N = static_cast<int64_t>(n1) * LEN;
+    __shared__ double red[2][4];
+    const int64_t N = g.nb;
     const int groups = n1 / cols;
     const int64_t p = blockIdx.x / groups;
     const int gcol = (blockIdx.x % groups) * cols;
     fill_twiddles<LEN>(tw);
-    const double2* __restrict__ src = X + p * N;
+    const double* __restrict__ rec = recs + p * REC_N;
+    const bool valid = rec[R_VALID] != 0.0;
+    const Tabs T(tab, g.nb);
+    const double2* __restrict__ tg = reinterpret_cast<const double2*>(targets) + p * N;
+    double a = 0.0, b = 0.0;
     for (int idx = threadIdx.x; idx < cols * LEN; idx += 256) {
         const int c = idx % cols, k2 = idx / cols;
-        buf[c * LEN + k2] = src[(gcol + c) + static_cast<int64_t>(n1) * k2];
+        const int64_t k = gcol + c + static_cast<int64_t>(n1) * k2;
+        const double2 t = tg[k];
+        const double w = 4.0 * g.df * inv_psd[k];
+        double2 h = make_double2(0.0, 0.0);
+        if (valid) {
+            const double f = bin_freq(g, k);
+            const double mf = rec[R_MS] * f;
+            if (bin_active(g, f, mf)) {
+                BinVals bv;
+                eval_bin_rt(rec, T, k, mf, bv);
+                const double A = rec[R_A0P] * T.at(T_F76, k) * bv.ahat;
+                double sn, cs;
+                pd_sincos(bv.psi, &sn, &cs);
+                h = make_double2(A * cs, -A * sn);
+            }
+        }
+        // x = w conj(h) t
+        buf[c * kLd + k2] = make_double2(w * (h.x * t.x + h.y * t.y), w * (h.x * t.y - h.y * t.x));
+        a = fma(w, h.x * h.x + h.y * h.y, a);
+        b = fma(w, t.x * t.x + t.y * t.y, b);
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wid] = a;
+        red[1][wid] = b;
     }
     __syncthreads();
-    const double2* res = lds_idft<LEN>(buf, tmp, cols, tw);
+    if (threadIdx.x == 0) {
+        double* o = ab + (p * groups + (blockIdx.x % groups)) * 2;
+        o[0] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        o[1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+    lds_idft<LEN>(buf, cols, tw);
     double2* __restrict__ dst = Y + p * N;
+    const unsigned mask = static_cast<unsigned>(N - 1);
     for (int idx = threadIdx.x; idx < cols * LEN; idx += 256) {
         const int c = idx % cols, j2 = idx / cols;
         const int k1 = gcol + c;
-        const double2 v = cmul(res[c * LEN + j2], expi_ratio(static_cast<int64_t>(j2) * k1, N));
+        const double2 v = cmul(buf[c * kLd + j2], twiddle(twg, (static_cast<unsigned>(j2) * k1) & mask));
         dst[static_cast<int64_t>(j2) * n1 + k1] = v;
     }
 }
 
-// ---- 3. row pass with fused arg-max of |z|^2 ------------------------------------------
+// ---- 2. row pass with fused arg-max of |z|^2 ------------------------------------------
 __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
     return (v > bv) || (v == bv && i < bi);
 }
@@ -230,31 +283,30 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
 // LEN = N1: block (target p, row group) transforms rows grow .. grow + rows - 1 (rows of the
 // transposed array are indexed by j2); the lag of output j1 of row j2 is j = j2 + N2 j1.
 template <int LEN>
-__global__ void __launch_bounds__(256) k_mm_fft_rows_max(const double2* __restrict__ Y, double* __restrict__ mx,
-                                                         int n2, int rows) {
-    __shared__ double2 buf[kLdsPts];
-    __shared__ double2 tmp[kLdsPts];
+__global__ void __launch_bounds__(256) k_mm_rows_max(const double2* __restrict__ Y, double* __restrict__ mx,
+                                                     int n2, int rows) {
+    constexpr int kLd = LEN + 1;
+    __shared__ double2 buf[kLdsPts + kLdsPts / LEN];
     __shared__ double2 tw[LEN];
     __shared__ double rv[256];
     __shared__ int ri[256];
-    __shared__ double2 zbest;
     const int64_t N = static_cast<int64_t>(n2) * LEN;
     const int groups = n2 / rows;
     const int64_t p = blockIdx.x / groups;
     const int grow = (blockIdx.x % groups) * rows;
     fill_twiddles<LEN>(tw);
-    const double2* __restrict__ src = Y + p * N;
+    const double2* __restrict__ src = Y + p * N + static_cast<int64_t>(grow) * LEN;
     for (int idx = threadIdx.x; idx < rows * LEN; idx += 256) {
         const int rrow = idx / LEN, k1 = idx % LEN;
-        buf[rrow * LEN + k1] = src[static_cast<int64_t>(grow + rrow) * LEN + k1];
+        buf[rrow * kLd + k1] = src[idx];
     }
     __syncthreads();
-    const double2* res = lds_idft<LEN>(buf, tmp, rows, tw);
+    lds_idft<LEN>(buf, rows, tw);
     double best = -1.0;
     int bidx = 0x7fffffff;
     for (int idx = threadIdx.x; idx < rows * LEN; idx += 256) {
         const int rrow = idx / LEN, j1 = idx % LEN;
-        const double2 z = res[rrow * LEN + j1];
+        const double2 z = buf[rrow * kLd + j1];
         const double a2 = z.x * z.x + z.y * z.y;
         const int j = (grow + rrow) + n2 * j1;
         if (better(a2, j, best, bidx)) {
@@ -281,7 +333,7 @@ __global__ void __launch_bounds__(256) k_mm_fft_rows_max(const double2* __restri
         const bool none = ri[0] == 0x7fffffff;
         const int j = none ? grow : ri[0];
         const int r = j % n2 - grow, j1 = j / n2;
-        double2 z = res[r * LEN + j1];
+        double2 z = buf[r * kLd + j1];
         if (none) z = make_double2(__builtin_nan(""), __builtin_nan(""));
         double* o = mx + (p * groups + (blockIdx.x % groups)) * 4;
         o[0] = none ? __builtin_nan("") : rv[0];
@@ -355,6 +407,7 @@ struct AdjSegment {
     GridArgs g;
     const double2* __restrict__ tgt;
     const double* __restrict__ inv_psd;
+    const double2* __restrict__ tw;
     double ur, ui, inv_sab, cfa;
     int64_t j;
     int64_t k0, k1;
@@ -381,7 +434,7 @@ struct AdjSegment {
             const double hr = Aamp * cs, hi = -Aamp * sn;
             const double w = w4 * inv_psd[k];
             const double2 t = tgt[k];
-            const double2 e = expi_ratio((static_cast<int64_t>(k) * j) % g.nb, g.nb);
+            const double2 e = twiddle(tw, (k * static_cast<unsigned>(j)) & static_cast<unsigned>(g.nb - 1));
             const double2 x = cmul(make_double2(w * t.x, w * t.y), e);
             // G = conj(u) x
             const double gr = ur * x.x + ui * x.y, gi = ur * x.y - ui * x.x;
@@ -402,6 +455,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
                                                     GridArgs g, const double* __restrict__ tab,
                                                     const double* __restrict__ targets,
                                                     const double* __restrict__ inv_psd,
+                                                    const double2* __restrict__ tw,
                                                     const double* __restrict__ scal, double* __restrict__ part_all) {
     double* __restrict__ part = part_all + static_cast<int64_t>(PRG - 1) * nt * chunks * kNSlot;
     const int lane = threadIdx.x & 63;
@@ -423,6 +477,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     seg.g = g;
     seg.tgt = reinterpret_cast<const double2*>(targets) + p * g.nb;
     seg.inv_psd = inv_psd;
+    seg.tw = tw;
     // unit phase u = z / |z|; G_k = conj(u) x_k with x_k = w t_k exp(2 pi i k j / N)
     seg.ur = sc[3] / az;
     seg.ui = sc[4] / az;
@@ -507,12 +562,15 @@ __global__ void __launch_bounds__(256) k_mm_lambda_sum(const double* __restrict_
 size_t mismatch_scratch_bytes(int64_t nt, int64_t nb) { return carve_into(nullptr, nt, nb, nullptr); }
 
 template <int LEN>
-static void launch_cols(unsigned blocks, const double2* X, double2* Y, int n1, int cols, hipStream_t s) {
-    hipLaunchKernelGGL(k_mm_fft_cols<LEN>, dim3(blocks), dim3(256), 0, s, X, Y, n1, cols);
+static void launch_cols(unsigned blocks, const double* recs, const GridArgs& g, const double* tab,
+                        const double* targets, const double* inv_psd, const double2* tw, double2* Y, double* ab,
+                        int n1, int cols, hipStream_t s) {
+    hipLaunchKernelGGL(k_mm_cols<LEN>, dim3(blocks), dim3(256), 0, s, recs, g, tab, targets, inv_psd, tw, Y, ab, n1,
+                       cols);
 }
 template <int LEN>
 static void launch_rows(unsigned blocks, const double2* Y, double* mx, int n2, int rows, hipStream_t s) {
-    hipLaunchKernelGGL(k_mm_fft_rows_max<LEN>, dim3(blocks), dim3(256), 0, s, Y, mx, n2, rows);
+    hipLaunchKernelGGL(k_mm_rows_max<LEN>, dim3(blocks), dim3(256), 0, s, Y, mx, n2, rows);
 }
 
 hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t nt, const GridArgs& g,
@@ -521,24 +579,22 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
     MMScratch m;
     carve_into(scratch, nt, g.nb, &m);
     const FFTPlan f = make_plan(g.nb);
-    const unsigned bin_blocks = static_cast<unsigned>(nt * f.ibl);
+    const unsigned col_blocks = static_cast<unsigned>(nt * f.gc);
+    const unsigned row_blocks = static_cast<unsigned>(nt * f.gr);
+    hipLaunchKernelGGL(k_mm_twiddles, dim3(1), dim3(kTw), 0, s, g.nb, m.tw);
     {
         ProfRange pr(PD_K_MISMATCH_INPUT, s);
-        hipLaunchKernelGGL(k_mm_input, dim3(bin_blocks), dim3(256), 0, s, recs, nt, g, tab, targets, inv_psd, m.X,
-                           m.ab, f.ibl);
+        switch (f.n2) {
+            case 8: launch_cols<8>(col_blocks, recs, g, tab, targets, inv_psd, m.tw, m.Y, m.ab, f.n1, f.cb, s); break;
+            case 16: launch_cols<16>(col_blocks, recs, g, tab, targets, inv_psd, m.tw, m.Y, m.ab, f.n1, f.cb, s); break;
+            case 32: launch_cols<32>(col_blocks, recs, g, tab, targets, inv_psd, m.tw, m.Y, m.ab, f.n1, f.cb, s); break;
+            case 64: launch_cols<64>(col_blocks, recs, g, tab, targets, inv_psd, m.tw, m.Y, m.ab, f.n1, f.cb, s); break;
+            case 128: launch_cols<128>(col_blocks, recs, g, tab, targets, inv_psd, m.tw, m.Y, m.ab, f.n1, f.cb, s); break;
+            default: launch_cols<256>(col_blocks, recs, g, tab, targets, inv_psd, m.tw, m.Y, m.ab, f.n1, f.cb, s); break;
+        }
     }
-    const unsigned col_blocks = static_cast<unsigned>(nt * (f.n1 / f.cb));
-    const unsigned row_blocks = static_cast<unsigned>(nt * (f.n2 / f.rb));
     {
         ProfRange pr(PD_K_MISMATCH_FFT, s);
-        switch (f.n2) {
-            case 8: launch_cols<8>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
-            case 16: launch_cols<16>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
-            case 32: launch_cols<32>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
-            case 64: launch_cols<64>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
-            case 128: launch_cols<128>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
-            default: launch_cols<256>(col_blocks, m.X, m.Y, f.n1, f.cb, s); break;
-        }
         switch (f.n1) {
             case 8: launch_rows<8>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
             case 16: launch_rows<16>(row_blocks, m.Y, m.mx, f.n2, f.rb, s); break;
@@ -549,7 +605,7 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
         }
     }
     hipLaunchKernelGGL(k_mm_finalize, dim3(static_cast<unsigned>((nt + 127) / 128)), dim3(128), 0, s, recs, nt,
-                       m.ab, m.mx, m.scal, mismatch, lag, f.ibl, f.n2 / f.rb);
+                       m.ab, m.mx, m.scal, mismatch, lag, f.gc, f.gr);
     if (dsum_dlambda) {
         const int64_t waves = nt * m.chunks;
         {
@@ -558,13 +614,13 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
             launch_regions(s, [&](int region, hipStream_t rs) {
                 if (region == 3)
                     hipLaunchKernelGGL(k_mm_adjoint<3>, grid, dim3(256), 0, rs, recs, nt, m.chunks, g, tab, targets,
-                                       inv_psd, m.scal, m.mom);
+                                       inv_psd, m.tw, m.scal, m.mom);
                 else if (region == 2)
                     hipLaunchKernelGGL(k_mm_adjoint<2>, grid, dim3(256), 0, rs, recs, nt, m.chunks, g, tab, targets,
-                                       inv_psd, m.scal, m.mom);
+                                       inv_psd, m.tw, m.scal, m.mom);
                 else
                     hipLaunchKernelGGL(k_mm_adjoint<1>, grid, dim3(256), 0, rs, recs, nt, m.chunks, g, tab, targets,
-                                       inv_psd, m.scal, m.mom);
+                                       inv_psd, m.tw, m.scal, m.mom);
             });
         }
         hipLaunchKernelGGL(k_mm_reduce, dim3(static_cast<unsigned>(nt)), dim3(64), 0, s, recs, nt, m.chunks, m.mom,
