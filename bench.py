@@ -60,7 +60,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only-c4", action="store_true",
                     help="only run the C4 mismatch pass (one warm-up and one timed call; for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -85,6 +84,14 @@ def main():
     from paper_2302_05329_amd import api, flops, workloads as W
     from paper_2302_05329_amd import _lib as L
 
+    # the CPU oracle baseline runs first: its process pool is forked before this process touches
+    # the GPU
+    cpu = None
+    if not args.no_cpu and not args.only_c4:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(W, W.config2())
+        log(f"[bench] CPU oracle: {cpu['value_single_process']:.1f} evals/s on one process, "
+            f"{cpu['value']:.1f} on {cpu['cores']}")
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
     lam = torch.as_tensor(W.load_lambda(), device=dev)
@@ -156,9 +163,6 @@ def main():
     if not args.no_extra:
         extra = run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2)
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(W, c2, args.cpu_seconds)
 
     out = {
         "metric": "IMRPhenomD loglike+grad evals/s (FP64 phase)",
@@ -481,22 +485,97 @@ def c5_summary(r):
     return out
 
 
-def cpu_baseline(W, c2, seconds):
-    """The CPU oracle (as it stands) on a bounded sample of the same C2 workload."""
+# ---------------- CPU oracle baseline ----------------
+# Worker processes for the all-core rate: the host's CPU share per GPU (16 on the GPU hosts used
+# here), or fewer if this process may run on fewer CPUs.
+CPU_POOL = 16
+_CPU = {}
+
+
+def _cpu_c2_points(idx):
     from oracle import phenomd_oracle as O
-    g = c2["grid"].as_tuple()
-    th, data, ip = c2["theta"], c2["data"], c2["inv_psd"]
-    lam = W.load_lambda()
-    t0 = time.perf_counter()
-    n = 0
-    while n < 4096 and (time.perf_counter() - t0) < seconds:
-        O.loglike(th[n], O.PARAM_M1M2, lam, g, data, ip)
-        O.loglike_grad(th[n], O.PARAM_M1M2, lam, g, data, ip)
-        n += 1
-    el = time.perf_counter() - t0
-    return {"value": n / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {th.shape[0]} C2 sources, full 16225-bin grid, lnL + complex-step "
-                      f"gradient (numpy, one process), {el:.1f} s"}
+    c = _CPU
+    for i in idx:
+        O.loglike(c["th2"][i], O.PARAM_M1M2, c["lam"], c["g2"], c["data"], c["ip2"])
+        O.loglike_grad(c["th2"][i], O.PARAM_M1M2, c["lam"], c["g2"], c["data"], c["ip2"])
+    return len(idx)
+
+
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def cpu_baseline(W, c2, runs=5, n_single=48, n_per_proc=48):
+    """The CPU oracle (as it stands, numpy in FP64) on this host, before the GPU is touched: the C2
+    likelihood + gradient per source (ln L and the complex-step gradient, full 16225-bin grid) on
+    one process and on a process pool, each the median of `runs` timed runs over a fixed seeded
+    sample of C2 sources; the full-C2 time is extrapolated from the rate (labelled).  Samples of
+    C1 (strain) and C3 (Fisher matrix) on one process are reported beside it."""
+    import multiprocessing
+    import statistics
+    from oracle import phenomd_oracle as O
+    model, ncpu, usable = _host_cpu()
+    procs = max(1, min(CPU_POOL, usable))
+    rng = np.random.default_rng(31)
+    n2 = c2["theta"].shape[0]
+    _CPU.update(th2=c2["theta"], g2=c2["grid"].as_tuple(), data=c2["data"], ip2=c2["inv_psd"], lam=W.load_lambda())
+    single_idx = rng.choice(n2, n_single, replace=False)
+    pool_idx = rng.choice(n2, n_per_proc * procs, replace=False)
+    t_single = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        _cpu_c2_points(single_idx)
+        t_single.append(time.perf_counter() - t0)
+    rate1 = n_single / statistics.median(t_single)
+    t_pool = []
+    ctx = multiprocessing.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        parts = [pool_idx[i::procs] for i in range(procs)]
+        pool.map(_cpu_c2_points, [p[:1] for p in parts])   # start-up outside the timing
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            pool.map(_cpu_c2_points, parts)
+            t_pool.append(time.perf_counter() - t0)
+    rate_all = len(pool_idx) / statistics.median(t_pool)
+    # C1 strain and C3 Fisher samples, one process
+    c1 = W.config1(n=64)
+    g1 = c1["grid"].as_tuple()
+    t1 = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        for th in c1["theta"][:32]:
+            O.waveform(th, O.PARAM_M1M2, _CPU["lam"], g1)
+        t1.append(time.perf_counter() - t0)
+    c3 = W.config3(n=8)
+    g3 = c3["grid"].as_tuple()
+    t3 = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        for th in c3["theta"][:4]:
+            O.fisher(th, O.PARAM_M1M2, _CPU["lam"], g3, c3["inv_psd"])
+        t3.append(time.perf_counter() - t0)
+    return {"value": rate_all, "unit": "evals/s", "cores": procs, "kind": "oracle",
+            "value_single_process": rate1,
+            "host": {"cpu_model": model, "nproc": ncpu, "usable_cpus": usable, "pool_processes": procs},
+            "runs": runs, "statistic": "median",
+            "sample": (f"C2 lnL + complex-step gradient on the full 16225-bin grid (numpy FP64): {n_single} seeded "
+                       f"sources on one process, {len(pool_idx)} on a pool of {procs} processes; median of {runs} runs"),
+            "full_c2_seconds_extrapolated": {"single_process": n2 / rate1, "all_core": n2 / rate_all},
+            "C1_waveforms_per_s_single_process": 32 / statistics.median(t1),
+            "C3_fishers_per_s_single_process": 4 / statistics.median(t3)}
 
 
 if __name__ == "__main__":
