@@ -474,6 +474,12 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
 // bins at or above the phase joins Mf = 0.018 and rec[R_FP2], found with the same test as the
 // segment boundaries, so every segment of the chunk lies in region prg.  Splitting each region
 // separately gives every region launch all of its waves.
+// Chunks of a point's bins in phase region prg when a pass splits each point over `chunks` waves:
+// the inspiral and intermediate regions are usually a small share of the bins, so they are split
+// into a quarter as many (at least one); the merger-ringdown region uses all.  Partial-sum slots
+// [point][chunk] keep the stride `chunks`; the reductions read the first region_chunks of them.
+__host__ __device__ inline int region_chunks(int prg, int chunks) { return prg == 3 ? chunks : (chunks + 3) / 4; }
+
 __device__ __forceinline__ void region_chunk_range(const double* __restrict__ rec, const GridArgs& g, int prg,
                                                    int c, int chunks, int64_t& kb, int64_t& ke) {
     const double ms = rec[R_MS];

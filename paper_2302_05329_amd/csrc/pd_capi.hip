@@ -273,7 +273,7 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
 int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
                          const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
                          int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s,
-                         bool tables_ready, bool concurrent) {
+                         bool tables_ready, bool concurrent, const pd::PostTail* tail, const pd::XForm* xf) {
     pd::GridArgs g;
     int rc = check_common(theta, n, param, grid, lambda, &g);
     if (rc) return rc;
@@ -292,7 +292,9 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
     double* tans = grad ? at<double>(workspace, L.tan) : nullptr;
     hipError_t e = hipSuccess;
     SideStream* side = (grad && concurrent) ? side_stream() : nullptr;
-    if (grad) {
+    // the record tangents run on the side stream, concurrently with the records and the pass (after
+    // the records when those compute theta from the sampler's coordinates)
+    auto launch_tangents = [&]() -> int {
         hipStream_t ts = s;
         if (side && hipEventRecord(side->fork, s) == hipSuccess && hipStreamWaitEvent(side->s, side->fork, 0) == hipSuccess)
             ts = side->s;
@@ -301,6 +303,11 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
         e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, 4, tans, ts);
         if (e != hipSuccess) return fail_hip(e, "setup tangents");
         if (side && hipEventRecord(side->join, side->s) != hipSuccess) return fail_hip(hipGetLastError(), "join");
+        return PD_OK;
+    };
+    if (grad && !xf) {
+        rc = launch_tangents();
+        if (rc) return rc;
     }
     // a failure past this point still joins the side stream, so that no kernel of this call
     // writes into the workspace after the error is returned
@@ -308,15 +315,19 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
         if (side) (void)hipStreamWaitEvent(s, side->join, 0);
         return fail_hip(err, what);
     };
-    e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
+    e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s, xf);
     if (e != hipSuccess) return fail_joined(e, "setup");
+    if (grad && xf) {
+        rc = launch_tangents();
+        if (rc) return rc;
+    }
     if (!tables_ready) {
         e = pd::launch_tables(g, data, inv_psd, tab, s);
         if (e != hipSuccess) return fail_joined(e, "tables");
     }
     e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg),
                            at<int>(workspace, L.order), partial, lnl,
-                           grad, side ? side->join : nullptr, s, concurrent);
+                           grad, side ? side->join : nullptr, s, concurrent, grad ? tail : nullptr);
     if (e != hipSuccess) return fail_joined(e, "loglike");
     return PD_OK;
 }

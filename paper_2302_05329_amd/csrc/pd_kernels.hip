@@ -45,13 +45,21 @@ __device__ __forceinline__ void fit_params(const double* __restrict__ lam, const
     }
 }
 
-__global__ void __launch_bounds__(128) k_setup_value(const double* __restrict__ theta, int64_t n, int param,
+// XF: theta is first computed from the sampler's coordinates (xform_point) and written out.
+template <bool XF>
+__global__ void __launch_bounds__(128) k_setup_value(double* __restrict__ theta, int64_t n, int param,
                                                      double f_ref, const double* __restrict__ lam,
-                                                     double* __restrict__ recs, int32_t* __restrict__ status) {
+                                                     double* __restrict__ recs, int32_t* __restrict__ status,
+                                                     XForm xf) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double th[7];
-    load_row(theta, i, th);
+    if (XF) {
+        xform_point(xf, i, th);
+        for (int j = 0; j < 7; ++j) theta[i * 7 + j] = th[j];
+    } else {
+        load_row(theta, i, th);
+    }
     double rec[REC_N];
     bool ok = domain_ok(th, param);
     if (ok) {
@@ -300,23 +308,19 @@ struct LnlSegment {
     }
 };
 
-// PRG: the phase region (1 inspiral, 2 intermediate, 3 merger-ringdown) whose segments this
-// instantiation handles; the three are separate launches so each gets its own register budget.
+// One wave's share of the fused pass: PRG is the phase region (1 inspiral, 2 intermediate,
+// 3 merger-ringdown) whose segments it handles, `wave` its index among that region's waves.
 template <int MODE, int PRG>
-__global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
-                                                         GridArgs g, const double* __restrict__ tab,
-                                                         const int* __restrict__ segs,
-                                                         const int* __restrict__ perm,
-                                                         double* __restrict__ partial_all) {
+__device__ __forceinline__ void moments_wave(int64_t wave, const double* __restrict__ recs, int64_t n, int chunks,
+                                             const GridArgs& g, const double* __restrict__ tab,
+                                             const int* __restrict__ segs, const int* __restrict__ perm,
+                                             double* __restrict__ partial_all, const double2* __restrict__ sct) {
     constexpr int NS = (MODE == 0) ? 2 : kNSlot;
-    __shared__ double2 sct[kSinCosN];
-    stage_sincos_table(sct);
-    __syncthreads();
     double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * NS;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
-    const int64_t pi = wave / chunks;
-    const int c = static_cast<int>(wave - pi * chunks);
+    const int cr = region_chunks(PRG, chunks);
+    const int64_t pi = wave / cr;
+    const int c = static_cast<int>(wave - pi * cr);
     if (pi >= n) return;
     // waves visit the points in order of decreasing work (see k_order_scatter), or in index order
     const int64_t p = perm ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
@@ -345,6 +349,44 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
     if (MODE == 1 && lane < REC_N) out[2 + lane] = seg.tot * a0p;
 }
 
+// One launch per phase region (concurrent on three streams, or in sequence).
+template <int MODE, int PRG>
+__global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __restrict__ recs, int64_t n, int chunks,
+                                                         GridArgs g, const double* __restrict__ tab,
+                                                         const int* __restrict__ segs,
+                                                         const int* __restrict__ perm,
+                                                         double* __restrict__ partial_all) {
+    __shared__ double2 sct[kSinCosN];
+    stage_sincos_table(sct);
+    __syncthreads();
+    const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    moments_wave<MODE, PRG>(wave, recs, n, chunks, g, tab, segs, perm, partial_all, sct);
+}
+
+// The three regions in one launch: blocks [0, nb3) take the merger-ringdown waves, the next nb2 the
+// intermediate ones, the rest the inspiral ones (no stream fork and join; for small batches).
+template <int MODE>
+__global__ void __launch_bounds__(256, 4) k_loglike_moments_all(const double* __restrict__ recs, int64_t n,
+                                                             int chunks, GridArgs g, const double* __restrict__ tab,
+                                                             const int* __restrict__ segs,
+                                                             const int* __restrict__ perm,
+                                                             double* __restrict__ partial_all, unsigned nb3,
+                                                             unsigned nb2) {
+    __shared__ double2 sct[kSinCosN];
+    stage_sincos_table(sct);
+    __syncthreads();
+    const unsigned b = blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    if (b < nb3)
+        moments_wave<MODE, 3>(static_cast<int64_t>(b) * 4 + w, recs, n, chunks, g, tab, segs, perm, partial_all, sct);
+    else if (b < nb3 + nb2)
+        moments_wave<MODE, 2>(static_cast<int64_t>(b - nb3) * 4 + w, recs, n, chunks, g, tab, segs, perm,
+                              partial_all, sct);
+    else
+        moments_wave<MODE, 1>(static_cast<int64_t>(b - nb3 - nb2) * 4 + w, recs, n, chunks, g, tab, segs, perm,
+                              partial_all, sct);
+}
+
 // Value-only likelihood: one thread per point sums its (d|h), (h|h) partials over the region
 // groups and chunks.
 __global__ void __launch_bounds__(128) k_loglike_value_epilogue(const double* __restrict__ recs, int64_t n,
@@ -358,7 +400,7 @@ __global__ void __launch_bounds__(128) k_loglike_value_epilogue(const double* __
     }
     double dh = 0.0, hh = 0.0;
     for (int grp = 0; grp < 3; ++grp)
-        for (int c = 0; c < chunks; ++c) {
+        for (int c = 0; c < region_chunks(grp + 1, chunks); ++c) {
             const double* src = partial + ((grp * n + p) * chunks + c) * 2;
             dh += src[0];
             hh += src[1];
@@ -376,7 +418,8 @@ __global__ void __launch_bounds__(256) k_loglike_grad_epilogue(const double* __r
                                                                int param, const double* __restrict__ recs,
                                                                const double* __restrict__ tans, int chunks,
                                                                const double* __restrict__ partial,
-                                                               double* __restrict__ lnl, double* __restrict__ grad) {
+                                                               double* __restrict__ lnl, double* __restrict__ grad,
+                                                               PostTail tail, int has_tail) {
     constexpr int NS = kNSlot;
     static_assert(NS <= 64, "one lane per partial slot");
     const int lane = threadIdx.x & 63;
@@ -386,12 +429,17 @@ __global__ void __launch_bounds__(256) k_loglike_grad_epilogue(const double* __r
     if (rec[R_VALID] == 0.0) {
         if (lane == 0) lnl[p] = __builtin_nan("");
         if (lane < 7) grad[p * 7 + lane] = __builtin_nan("");
+        if (has_tail) {
+            if (lane == 0) tail.logp[p] = -INFINITY;
+            if (lane < 7) tail.grad[p * 7 + lane] = 0.0;
+        }
         return;
     }
     double m = 0.0;     // lane 0: (d|h), lane 1: (h|h), lane 2 + j: moment j
     if (lane < NS) {
         for (int grp = 0; grp < 3; ++grp)
-            for (int c = 0; c < chunks; ++c) m += partial[((grp * n + p) * chunks + c) * NS + lane];
+            for (int c = 0; c < region_chunks(grp + 1, chunks); ++c)
+                m += partial[((grp * n + p) * chunks + c) * NS + lane];
     }
     auto at = [&](int slot) {   // wave-uniform copy of one lane's sum
         const unsigned long long b = __builtin_bit_cast(unsigned long long, m);
@@ -419,7 +467,37 @@ __global__ void __launch_bounds__(256) k_loglike_grad_epilogue(const double* __r
     if (lane == 5) out = dlin * (at(2 + R_PH1 + 9) / kPi + at(2 + R_PH2 + 1) + at(2 + R_PH3 + 1));
     if (lane == 6) out = -2.0 * (at(2 + R_PH1 + 4) + at(2 + R_PH2 + 0) + at(2 + R_PH3 + 0));
     if (lane < 7) grad[p * 7 + lane] = out;
-    if (lane == 0) lnl[p] = at(0) - 0.5 * at(1);
+    const double lv = at(0) - 0.5 * at(1);
+    if (lane == 0) lnl[p] = lv;
+    if (has_tail) {
+        const bool ok = isfinite(lv);
+        double gx = 0.0;
+        if (lane < 7) {
+            gx = ok ? fma(out, tail.dtdx[p * 7 + lane], tail.dlj[p * 7 + lane]) : 0.0;
+            tail.grad[p * 7 + lane] = gx;
+        }
+        if (lane == 0) tail.logp[p] = ok ? lv + tail.lj[p] : -INFINITY;
+        if (tail.p) {
+            double gk[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                const unsigned long long b = __builtin_bit_cast(unsigned long long, gx);
+                const unsigned lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(b)), k);
+                const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<unsigned>(b >> 32)), k);
+                gk[k] = __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+            }
+            // lane j: p_j += weps sum_{k >= j} L[k][j] g_k (the metric's kick)
+            if (lane < 7) {
+                double acc = 0.0;
+                if (tail.m.diag) {
+                    acc = tail.m.L[lane][lane] * gk[lane];
+                } else {
+                    for (int k = lane; k < 7; ++k) acc = fma(tail.m.L[k][lane], gk[k], acc);
+                }
+                tail.p[p * 7 + lane] = fma(tail.weps, acc, tail.p[p * 7 + lane]);
+            }
+        }
+    }
 }
 
 // ==================================================================================
@@ -525,9 +603,10 @@ __global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restr
     __shared__ double lds[4][kFisherDirs * REC_N];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
+    const int cr = region_chunks(PRG, chunks);
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + wib));
-    const int64_t pi = wave / chunks;
-    const int c = static_cast<int>(wave - pi * chunks);
+    const int64_t pi = wave / cr;
+    const int c = static_cast<int>(wave - pi * cr);
     const bool live = pi < n;
     // points in order of decreasing work, as in the likelihood passes
     const int64_t p = (live && perm) ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
@@ -581,7 +660,7 @@ __global__ void __launch_bounds__(128) k_fisher_epilogue(const double* __restric
 #pragma unroll
     for (int s = 0; s < kFisherAcc; ++s) acc[s] = 0.0;
     for (int grp = 0; grp < 3; ++grp)
-        for (int c = 0; c < chunks; ++c)
+        for (int c = 0; c < region_chunks(grp + 1, chunks); ++c)
 #pragma unroll
             for (int s = 0; s < kFisherAcc; ++s) acc[s] += partial[((grp * n + p) * chunks + c) * kFisherAcc + s];
     // d ln A / d theta_4 (distance or its logarithm); d Psi / d tc = 2 pi f; d Psi / d phic = -2
@@ -649,8 +728,10 @@ __global__ void k_segments(const double* __restrict__ recs, int64_t n, int chunk
 #pragma unroll
         for (int i = 0; i < 5; ++i) S.pr[i] = S.ar[i] = 0;
     } else {
-        int64_t kb, ke;
-        region_chunk_range(rec, g, prg, c, chunks, kb, ke);
+        // chunks past the region's own count are never read
+        const int cr = region_chunks(prg, chunks);
+        int64_t kb = 0, ke = 0;
+        if (c < cr) region_chunk_range(rec, g, prg, c, cr, kb, ke);
         make_segments(rec, g, kb, ke, S);
     }
     store_segments(S, segs + t * kSegInts);
@@ -726,9 +807,13 @@ static inline unsigned blocks_for(int64_t threads, int per_block) {
 }
 
 hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
-                              double* recs, int32_t* status, hipStream_t s) {
-    hipLaunchKernelGGL(k_setup_value, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, n, param, f_ref, lam,
-                       recs, status);
+                              double* recs, int32_t* status, hipStream_t s, const XForm* xf) {
+    if (xf)
+        hipLaunchKernelGGL(k_setup_value<true>, dim3(blocks_for(n, 128)), dim3(128), 0, s,
+                           const_cast<double*>(theta), n, param, f_ref, lam, recs, status, *xf);
+    else
+        hipLaunchKernelGGL(k_setup_value<false>, dim3(blocks_for(n, 128)), dim3(128), 0, s,
+                           const_cast<double*>(theta), n, param, f_ref, lam, recs, status, XForm{});
     return hipGetLastError();
 }
 
@@ -818,44 +903,55 @@ static int* launch_order(const double* recs, int64_t n, int chunks, const GridAr
     return perm;
 }
 
+// Below this many points the three region passes run as one launch (the fork and join of the
+// region streams cost more than the separate register budgets gain at sampler batch sizes).
+constexpr int64_t kMergedMaxPoints = 16384;
+
 template <int MODE>
-static void launch_region_moments(unsigned nblk, const double* recs, int64_t n, int chunks, const GridArgs& g,
+static void launch_region_moments(const double* recs, int64_t n, int chunks, const GridArgs& g,
                                   const double* tab, const int* segs, const int* perm, double* partial,
                                   hipStream_t s, bool concurrent) {
+    if (n < kMergedMaxPoints) {
+        const unsigned nb3 = blocks_for(n * region_chunks(3, chunks), 4);
+        const unsigned nb12 = blocks_for(n * region_chunks(1, chunks), 4);
+        hipLaunchKernelGGL((k_loglike_moments_all<MODE>), dim3(nb3 + 2 * nb12), dim3(256), 0, s, recs, n, chunks, g,
+                           tab, segs, perm, partial, nb3, nb12);
+        return;
+    }
     launch_regions(s, [&](int region, hipStream_t rs) {
+        const dim3 grid(blocks_for(n * region_chunks(region, chunks), 4));
         if (region == 3)
-            hipLaunchKernelGGL((k_loglike_moments<MODE, 3>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
+            hipLaunchKernelGGL((k_loglike_moments<MODE, 3>), grid, dim3(256), 0, rs, recs, n, chunks, g, tab,
                                segs, perm, partial);
         else if (region == 2)
-            hipLaunchKernelGGL((k_loglike_moments<MODE, 2>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
+            hipLaunchKernelGGL((k_loglike_moments<MODE, 2>), grid, dim3(256), 0, rs, recs, n, chunks, g, tab,
                                segs, perm, partial);
         else
-            hipLaunchKernelGGL((k_loglike_moments<MODE, 1>), dim3(nblk), dim3(256), 0, rs, recs, n, chunks, g, tab,
+            hipLaunchKernelGGL((k_loglike_moments<MODE, 1>), grid, dim3(256), 0, rs, recs, n, chunks, g, tab,
                                segs, perm, partial);
     }, concurrent);
 }
 
 hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                           int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
-                          double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s, bool concurrent) {
-    const int64_t waves = n * chunks;
-    const unsigned nblk = blocks_for(waves, 4);
+                          double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s, bool concurrent,
+                          const PostTail* tail) {
     int* perm = launch_order(recs, n, chunks, g, segs, order, s);
     if (grad) {
         {
             ProfRange pr(PD_K_LOGLIKE_GRAD, s);
-            launch_region_moments<1>(nblk, recs, n, chunks, g, tab, segs, perm, partial, s, concurrent);
+            launch_region_moments<1>(recs, n, chunks, g, tab, segs, perm, partial, s, concurrent);
         }
         if (before_epilogue) {
             const hipError_t e = hipStreamWaitEvent(s, before_epilogue, 0);
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(k_loglike_grad_epilogue, dim3(blocks_for(n, 4)), dim3(256), 0, s, theta, n, param, recs,
-                           tans, chunks, partial, lnl, grad);
+                           tans, chunks, partial, lnl, grad, tail ? *tail : PostTail{}, tail ? 1 : 0);
     } else {
         {
             ProfRange pr(PD_K_LOGLIKE, s);
-            launch_region_moments<0>(nblk, recs, n, chunks, g, tab, segs, perm, partial, s, concurrent);
+            launch_region_moments<0>(recs, n, chunks, g, tab, segs, perm, partial, s, concurrent);
         }
         hipLaunchKernelGGL(k_loglike_value_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, recs, n, chunks,
                            partial, lnl);
@@ -866,18 +962,18 @@ hipError_t launch_loglike(const double* theta, int param, const double* recs, co
 hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                          int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
                          double* F, hipStream_t s) {
-    const int64_t waves = n * chunks;
     int* perm = launch_order(recs, n, chunks, g, segs, order, s);
     {
         // sequential: run concurrently, the three launches (three waves per SIMD each, LDS-resident
         // tangents) measured 1.7x slower
         ProfRange pr(PD_K_FISHER, s);
-        const dim3 grid(blocks_for(waves, 4));
-        hipLaunchKernelGGL(k_fisher_partial<3>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
+        const dim3 grid3(blocks_for(n * region_chunks(3, chunks), 4));
+        const dim3 grid12(blocks_for(n * region_chunks(1, chunks), 4));
+        hipLaunchKernelGGL(k_fisher_partial<3>, grid3, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
                            partial);
-        hipLaunchKernelGGL(k_fisher_partial<2>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
+        hipLaunchKernelGGL(k_fisher_partial<2>, grid12, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
                            partial);
-        hipLaunchKernelGGL(k_fisher_partial<1>, grid, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
+        hipLaunchKernelGGL(k_fisher_partial<1>, grid12, dim3(256), 0, s, recs, tans, n, chunks, g, tab, segs, perm,
                            partial);
     }
     hipLaunchKernelGGL(k_fisher_epilogue, dim3(blocks_for(n, 128)), dim3(128), 0, s, theta, param, recs, n, chunks,

@@ -6,6 +6,7 @@
 
 #include "../../include/phenomd.h"
 #include "pd_bin.h"
+#include "pd_metric.h"
 
 namespace pd {
 
@@ -46,8 +47,11 @@ inline void launch_regions(hipStream_t s, F&& launch, bool concurrent = true) {
 
 constexpr int kOrderBuckets = 256;  // work buckets of the point ordering (one per thread of a block)
 
+// Waves per point of a region pass: enough for about 8192 merger-ringdown waves per launch (at 4096
+// points x 8033 bins, 2 chunks measured 0.167 ms per leapfrog against 0.180 with 4), at least 512
+// bins per chunk, between 1 and 64.
 inline int chunks_for(int64_t n, int64_t n_bins) {
-    const int64_t want = (16384 + n - 1) / n;
+    const int64_t want = (8192 + n - 1) / n;
     int64_t cap = n_bins / 512;
     if (cap < 1) cap = 1;
     int64_t c = want < cap ? want : cap;
@@ -56,8 +60,9 @@ inline int chunks_for(int64_t n, int64_t n_bins) {
     return static_cast<int>(c);
 }
 
+// xf (or NULL): theta is computed from the sampler's coordinates first and written to `theta`
 hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
-                              double* recs, int32_t* status, hipStream_t s);
+                              double* recs, int32_t* status, hipStream_t s, const XForm* xf = nullptr);
 hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param, double f_ref,
                                       const double* lam, int rows, double* tans, hipStream_t s);
 hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, double f_ref, const double* lam,
@@ -66,10 +71,11 @@ hipError_t launch_tables(const GridArgs& g, const double* data, const double* in
                          hipStream_t s);
 hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
                            double* h, hipStream_t s);
+// tail (gradient passes only, or NULL): the sampler's per-point tail applied by the epilogue
 hipError_t launch_loglike(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                           int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
                           double* lnl, double* grad, hipEvent_t before_epilogue, hipStream_t s,
-                          bool concurrent = true);
+                          bool concurrent = true, const PostTail* tail = nullptr);
 hipError_t launch_transitions(const double* recs, int64_t n, double* out, hipStream_t s);
 hipError_t launch_fisher(const double* theta, int param, const double* recs, const double* tans, int64_t n,
                          int chunks, const GridArgs& g, const double* tab, int* segs, int* order, double* partial,
@@ -84,10 +90,12 @@ int rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, cons
               const double* scale, const double* chol, int32_t* accepted, void* ws, hipStream_t s);
 // concurrent: run the record tangents and two of the three region launches on side streams (created
 // once per host thread and device); false keeps every launch on `s` and creates nothing.
+// tail: as for launch_loglike (with grad).  xf: theta [n][7] is an output, computed from the
+// sampler's coordinates by the record setup (the record tangents then start after it).
 int loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid* grid, const double* lambda,
                      const double* data, const double* inv_psd, int precision, double* lnl, double* grad,
                      int32_t* status, void* workspace, size_t workspace_bytes, hipStream_t s, bool tables_ready,
-                     bool concurrent = true);
+                     bool concurrent = true, const PostTail* tail = nullptr, const XForm* xf = nullptr);
 size_t op_workspace_bytes(int op, int64_t n, int64_t n_bins);
 void set_last_error(const char* msg);
 int posterior_logp(const pd_posterior* post, const double* x, int64_t n, double* logp, double* grad, void* ws,

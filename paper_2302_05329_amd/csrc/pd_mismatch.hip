@@ -459,9 +459,10 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
                                                     const double* __restrict__ scal, double* __restrict__ part_all) {
     double* __restrict__ part = part_all + static_cast<int64_t>(PRG - 1) * nt * chunks * kNSlot;
     const int lane = threadIdx.x & 63;
+    const int cr = region_chunks(PRG, chunks);
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    const int64_t p = wave / chunks;
-    const int c = static_cast<int>(wave - p * chunks);
+    const int64_t p = wave / cr;
+    const int c = static_cast<int>(wave - p * cr);
     if (p >= nt) return;
     const double* __restrict__ rec = recs + p * REC_N;
     double* __restrict__ out = part + (p * chunks + c) * kNSlot;
@@ -487,7 +488,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     seg.lane = lane;
     seg.tot = 0.0;
     int64_t kb, ke;
-    region_chunk_range(rec, g, PRG, c, chunks, kb, ke);
+    region_chunk_range(rec, g, PRG, c, cr, kb, ke);
     Segs S;
     make_segments(rec, g, kb, ke, S);
 #pragma unroll
@@ -514,7 +515,7 @@ __global__ void __launch_bounds__(64) k_mm_reduce(const double* __restrict__ rec
     if (p >= nt || s >= REC_N) return;
     double m = 0.0;
     for (int grp = 0; grp < 3; ++grp)
-        for (int c = 0; c < chunks; ++c) m += part[((grp * nt + p) * chunks + c) * kNSlot + 2 + s];
+        for (int c = 0; c < region_chunks(grp + 1, chunks); ++c) m += part[((grp * nt + p) * chunks + c) * kNSlot + 2 + s];
     const double* rec = recs + p * REC_N;
     if (s == R_MS) m /= rec[R_MS];
     const bool used = (s == R_MS || s == R_LNA0 || (s >= R_PH1 && s < R_VALID));
@@ -607,11 +608,10 @@ hipError_t launch_mismatch(const double* recs, const double* fit_tans, int64_t n
     hipLaunchKernelGGL(k_mm_finalize, dim3(static_cast<unsigned>((nt + 127) / 128)), dim3(128), 0, s, recs, nt,
                        m.ab, m.mx, m.scal, mismatch, lag, f.gc, f.gr);
     if (dsum_dlambda) {
-        const int64_t waves = nt * m.chunks;
         {
             ProfRange pr(PD_K_MISMATCH_ADJ, s);
-            const dim3 grid(static_cast<unsigned>((waves + 3) / 4));
             launch_regions(s, [&](int region, hipStream_t rs) {
+                const dim3 grid(static_cast<unsigned>((nt * region_chunks(region, m.chunks) + 3) / 4));
                 if (region == 3)
                     hipLaunchKernelGGL(k_mm_adjoint<3>, grid, dim3(256), 0, rs, recs, nt, m.chunks, g, tab, targets,
                                        inv_psd, m.tw, m.scal, m.mom);

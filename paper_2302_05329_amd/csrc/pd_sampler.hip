@@ -19,6 +19,7 @@
 
 #include "../../include/phenomd.h"
 #include "pd_launch.h"
+#include "pd_metric.h"
 
 namespace pd {
 
@@ -26,40 +27,6 @@ namespace {
 
 __device__ __forceinline__ double sigmoid(double x) {
     return (x >= 0.0) ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x));
-}
-
-// HMC metric.  The inverse mass matrix is M^-1 = L L^T with L lower triangular (7 x 7); the chains
-// carry the whitened momentum r = L^T p, so that r ~ N(0, I), the drift is x += eps L r, the kick is
-// r += w eps L^T grad log pi and the kinetic energy is |r|^2 / 2.  A diagonal mass m_j is the case
-// L = diag(1 / sqrt(m_j)).
-struct Metric {
-    double L[7][7];
-    bool diag;
-};
-
-__device__ __forceinline__ void metric_drift(const Metric& m, double eps, const double* __restrict__ r, double out[7]) {
-    for (int j = 0; j < 7; ++j) {
-        double acc = 0.0;
-        if (m.diag) {
-            acc = m.L[j][j] * r[j];
-        } else {
-            for (int k = 0; k <= j; ++k) acc = fma(m.L[j][k], r[k], acc);
-        }
-        out[j] = eps * acc;
-    }
-}
-
-// r += weps L^T g
-__device__ __forceinline__ void metric_kick(const Metric& m, double weps, const double g[7], double* __restrict__ r) {
-    for (int j = 0; j < 7; ++j) {
-        double acc = 0.0;
-        if (m.diag) {
-            acc = m.L[j][j] * g[j];
-        } else {
-            for (int k = j; k < 7; ++k) acc = fma(m.L[k][j], g[k], acc);
-        }
-        r[j] = fma(weps, acc, r[j]);
-    }
 }
 
 // x -> theta, d theta / d x, and the log-Jacobian with its derivative.  DRIFT: first the leapfrog
@@ -380,6 +347,25 @@ int posterior_logp_step(const pd_posterior* post, double* x, int64_t n, double* 
                         hipStream_t s, bool tables_ready, const Drift* drift, double kick_weps, double* kick_p) {
     PostWs w = post_ws(post, n, ws);
     const int ts = row_width(post);
+    if (post->kind == PD_TARGET_GW && grad) {
+        // one-detector gradient pass: the drift and the coordinate map run in the record setup and
+        // the log-density, gradient in x and kick in the likelihood epilogue
+        XForm xf;
+        xf.x = x;
+        xf.p = drift ? drift->p : nullptr;
+        xf.eps = drift ? drift->eps : 0.0;
+        xf.m = drift ? drift->m : Metric{};
+        for (int j = 0; j < 7; ++j) {
+            xf.lo[j] = post->lo[j];
+            xf.hi[j] = post->hi[j];
+        }
+        xf.dtdx = w.dtdx;
+        xf.lj = w.lj;
+        xf.dlj = w.dlj;
+        PostTail tail{w.dtdx, w.lj, w.dlj, logp, grad, kick_p, kick_weps, drift ? drift->m : Metric{}};
+        return loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data, post->inv_psd,
+                                PD_FP64, w.lnl, w.gth, nullptr, w.ll, w.ll_bytes, s, tables_ready, true, &tail, &xf);
+    }
     if (drift)
         hipLaunchKernelGGL(k_transform<true>, dim3(nblk(n, 128)), dim3(128), 0, s, x, n, *post, w.theta, w.dtdx, w.lj,
                            w.dlj, *drift, ts);
@@ -394,7 +380,7 @@ int posterior_logp_step(const pd_posterior* post, double* x, int64_t n, double* 
                                          grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes, s);
     else
         rc = loglike_and_grad(w.theta, n, PD_PARAM_MC_Q, &post->grid, post->lambda, post->data, post->inv_psd,
-                              PD_FP64, w.lnl, grad ? w.gth : nullptr, nullptr, w.ll, w.ll_bytes, s, tables_ready);
+                              PD_FP64, w.lnl, nullptr, nullptr, w.ll, w.ll_bytes, s, tables_ready);
     if (rc != PD_OK) return rc;
     hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 128)), dim3(128), 0, s, n, w.lnl, w.gth, ts, w.dtdx, w.lj, w.dlj,
                        logp, grad, kick_weps, kick_p, drift ? drift->m : Metric{});
