@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-hmc", action="store_true",
+                    help="only time dense-metric HMC transitions at the sampler size (4096 chains x 8033 bins)")
     ap.add_argument("--only-c4", action="store_true",
                     help="only run the C4 mismatch pass (one warm-up and one timed call; for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -87,7 +89,7 @@ def main():
     # the CPU oracle baseline runs first: its process pool is forked before this process touches
     # the GPU
     cpu = None
-    if not args.no_cpu and not args.only_c4:
+    if not args.no_cpu and not args.only_c4 and not args.only_hmc:
         log("[bench] CPU oracle baseline")
         cpu = cpu_baseline(W, W.config2())
         log(f"[bench] CPU oracle: {cpu['value_single_process']:.1f} evals/s on one process, "
@@ -98,6 +100,9 @@ def main():
     P = api.PARAM_M1M2
     if args.only_c4:
         print(json.dumps(c4_mismatch(api, flops, W, L, lam, api.Workspace(), P, 3)[-1]), flush=True)
+        return
+    if args.only_hmc:
+        print(json.dumps(hmc_step_timing(W)), flush=True)
         return
 
     # ---------------- main workload: fused lnL + gradient, 65536 x 16225 ----------------
@@ -384,6 +389,14 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
         "metric": r["metric"], "lags_rwmh_steps": r["lags_rwmh_steps"],
         "autocorr_rwmh_max_over_params": np.round(np.nanmax(r["rwmh"]["autocorr"], axis=1), 4).tolist(),
         "chains": r["n_chains"],
+        "hmc_long_trajectories": None if r["hmc_long"] is None else {
+            "n_leapfrog": r["hmc_long"]["n_leapfrog"], "eps": r["hmc_long"]["eps"],
+            "acceptance": r["hmc_long"]["acceptance"], "ms_per_step": 1e3 * r["hmc_long"]["s_per_step"],
+            "tau_steps": dict(zip(nm, np.round(r["hmc_long"]["tau_steps"], 1).tolist())),
+            "run": r["hmc_long"]["run"],
+            "ess_ratio_at_paper_steps": dict(zip(nm, np.round(r["hmc_long"]["ess_ratio_paper_steps"], 3).tolist())),
+            "ess_ratio_equal_time": dict(zip(nm, np.round(r["hmc_long"]["ess_ratio_equal_time"], 3).tolist())),
+            "min_ess_per_s": min(r["hmc_long"]["ess_per_s"])},
         "note": "autocorrelation times from long runs of chain subsets (bulk ESS of within-chain "
                 "autocorrelation); ESS per second = 4096 chains / tau / time per transition of 4096 chains"}
     return extra
@@ -442,6 +455,25 @@ def c4_mismatch(api, flops, W, L, lam, ws, P, iters):
     return c4, th4, targets, ip4, ws4, out
 
 
+def hmc_step_timing(W, n_leapfrog=10, steps=30):
+    """Dense-metric HMC transitions on the one-detector C5 posterior, 4096 chains and 512 chains
+    (the reference run's size), from a Fisher-scaled ball: milliseconds per transition and per
+    leapfrog step."""
+    import torch
+    from paper_2302_05329_amd import learned_proposal as LP, sampling
+    pb = LP.gw_problem(W.load_lambda())
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1005)
+    x0, cov0 = LP.fisher_ball(pb, 4096, np.random.default_rng(1005))
+    chol = np.linalg.cholesky(cov0)
+    out = {"n_leapfrog": n_leapfrog, "n_bins": pb["grid"].n_bins}
+    for n in (4096, 512):
+        h = sampling.HMC(pb["post"], torch.as_tensor(x0[:n], device="cuda"), 0.05, n_leapfrog, chol=chol)
+        t = LP.time_per_step(h, gen, steps)
+        out[f"chains_{n}"] = {"ms_per_transition": 1e3 * t, "ms_per_leapfrog": 1e3 * t / n_leapfrog}
+    return out
+
+
 def c5_summary(r):
     nm = r["features"]
     rd = lambda v, k=4: [round(float(x), k) for x in v]  # noqa: E731
@@ -462,6 +494,7 @@ def c5_summary(r):
         "runs": {"warmup_steps": r["warm"], "reference_chains": r["n_ref"], "reference_burn_in_steps": r["ref_burn"],
                  "reference_steps": r["ref_steps"], "flow_mh_chains": r["n_chains"], "flow_mh_steps": r["flow_steps"]},
         "ms_per_step": {"hmc": r["hmc"]["ms_per_step"], "flow_mh": r["flow_hmc"]["ms_per_step"]},
+        "ms_per_leapfrog_hmc": r["hmc"]["ms_per_step"] / r["n_leapfrog"],
         "acceptance_hmc": r["hmc"]["acceptance"], "acceptance_flow_mh": r["flow_hmc"]["acceptance_flow"],
         "mean_diff_sigma": dict(zip(nm, rd(r["mean_diff_sigma_flow"]))),
         "std_diff_sigma": dict(zip(nm, rd(r["std_diff_sigma_flow"]))),

@@ -77,12 +77,37 @@ def mean_autocorr(draws, lags=LAGS):
     return out
 
 
+def tuned_hmc(post, x_start, chol, eps0, gen, n_leapfrog, n_run, burn, steps, thin, log=None):
+    """HMC with longer trajectories (n_leapfrog steps, the step size re-tuned towards acceptance
+    0.7 on the ensemble): autocorrelation times from a long run of the first n_run chains, and the
+    time per transition of the full ensemble.  Returns (tau [8], seconds per transition,
+    acceptance, eps)."""
+    h = sampling.HMC(post, x_start.clone(), eps0, n_leapfrog, chol=chol)
+    eps = eps0
+    for _ in range(100):
+        xi, u = LP._rand(gen, h.n)
+        acc = float((h.step(xi, u) == 1).double().mean())
+        eps *= math.exp(0.5 * (acc - 0.7))
+        h.eps = eps
+    t_step = LP.time_per_step(sampling.HMC(post, h.x.clone(), eps, n_leapfrog, chol=chol), gen, 5)
+    r = sampling.HMC(post, h.x[:n_run].clone(), eps, n_leapfrog, chol=chol)
+    _run(r, gen, burn, n_run, burn)
+    d, _, acc = _run(r, gen, steps, n_run, thin)
+    tau = n_run * steps / LP.ess_per_param(d)
+    if log:
+        log(f"HMC with {n_leapfrog} leapfrog steps: eps {eps:.3g}, tau {np.round(tau, 1)} transitions")
+    return tau, t_step, acc, eps
+
+
 def compare(lam, n_chains=4096, warm=600, n_leapfrog=10, n_rw=256, rw_burn=20000, rw_steps=200000, rw_thin=100,
-            n_hmc=512, hmc_burn=4000, hmc_steps=20000, hmc_thin=10, hmc=None, seed=1005, n_bins=None, log=None):
+            n_hmc=512, hmc_burn=4000, hmc_steps=20000, hmc_thin=10, hmc=None, long_leapfrog=100, long_run=512,
+            long_burn=1000, long_steps=5000, long_thin=5, seed=1005, n_bins=None, log=None):
     """HMC against the random walk.  `hmc`, if given, is the "hmc" entry of
     learned_proposal.compare on the same workload (its autocorrelation times and time per
     transition); otherwise HMC's long run is made here.  Each long run discards its first
-    `*_burn` transitions."""
+    `*_burn` transitions.  The paper hand-tunes the trajectory length; HMC with `long_leapfrog`
+    leapfrog steps per transition (long_leapfrog=0 skips it) is compared too, at the paper's
+    step counts and at equal time."""
     pb = LP.gw_problem(lam, n_bins=n_bins)
     post = pb["post"]
     gen = torch.Generator(device="cuda")
@@ -105,6 +130,11 @@ def compare(lam, n_chains=4096, warm=600, n_leapfrog=10, n_rw=256, rw_burn=20000
         t_hmc = hmc["ms_per_step"] * 1e-3
         tau_a = np.asarray(hmc["tau_steps"])
         acc_a = hmc["acceptance"]
+    long = None
+    if long_leapfrog:
+        tau_l, t_l, acc_l, eps_l = tuned_hmc(post, x_start, chol, eps, gen, long_leapfrog, long_run, long_burn,
+                                             long_steps, long_thin, log=log)
+        long = (tau_l, t_l, acc_l, eps_l)
     f = tune_scale(post, x_start, chol, gen)
     if log:
         log(f"random-walk step factor {f:.4g} x the metric")
@@ -116,7 +146,17 @@ def compare(lam, n_chains=4096, warm=600, n_leapfrog=10, n_rw=256, rw_burn=20000
     tau_b = n_rw * rw_steps / ess_b
     ac_b = mean_autocorr(db)
     del db
+    out_long = None
+    if long is not None:
+        tau_l, t_l, acc_l, eps_l = long
+        out_long = dict(n_leapfrog=long_leapfrog, eps=eps_l, acceptance=acc_l, s_per_step=t_l,
+                        tau_steps=tau_l.tolist(), run=dict(chains=long_run, burn_in_steps=long_burn, steps=long_steps,
+                                                           steps_over_tau=float(long_steps / tau_l.max())),
+                        ess_per_s=(n_chains / tau_l / t_l).tolist(),
+                        ess_ratio_paper_steps=((PAPER_STEPS[0] / tau_l) / (PAPER_STEPS[1] / tau_b)).tolist(),
+                        ess_ratio_equal_time=((t_rw * tau_b) / (t_l * tau_l)).tolist())
     return dict(
+        hmc_long=out_long,
         n_chains=n_chains, n_bins=pb["grid"].n_bins, n_leapfrog=n_leapfrog,
         hmc=dict(s_per_step=t_hmc, acceptance=acc_a, eps=eps, tau_steps=tau_a.tolist(),
                  ess_per_s=(n_chains / tau_a / t_hmc).tolist(),
