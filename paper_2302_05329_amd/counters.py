@@ -91,6 +91,24 @@ def durations(d):
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
 
 
+def timeline(d, rx):
+    """Start offset, duration (us) and name of every dispatch from one dispatch of the kernel
+    matching `rx` to the next (the interval a quarter of the way through the trace)."""
+    rows = sorted(_csv(d, "kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    marks = [i for i, r in enumerate(rows) if re.search(rx, r["Kernel_Name"])]
+    if len(marks) < 2:
+        return ["# timeline: fewer than two dispatches of the marker kernel"]
+    m = max(1, len(marks) // 4)
+    i0, i1 = marks[m - 1], marks[m]
+    t0 = int(rows[i0]["Start_Timestamp"])
+    out = [f"timeline of one interval ({rx}), start_us duration_us kernel:"]
+    for r in rows[i0:i1 + 1]:
+        st = (int(r["Start_Timestamp"]) - t0) / 1e3
+        du = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        out.append(f"  {st:9.1f} {du:8.1f}  {r['Kernel_Name'][:90]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--title", required=True)
@@ -104,6 +122,8 @@ def main():
     ap.add_argument("--kernels", nargs="+", required=True, help="LABEL=REGEX on the kernel name")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--note", action="append", default=[])
+    ap.add_argument("--timeline", help="REGEX: list the dispatches between two consecutive dispatches of the "
+                                       "matching kernel (a quarter of the way through the trace)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     labels = [kv.split("=", 1) for kv in a.kernels]
@@ -158,6 +178,8 @@ def main():
         if f64:
             out.append(f"{label}_fp64_flops_per_call: {int(round(tf))}")
         out.append(f"{label}_avg_us_sum: {tus:.2f}")
+    if a.timeline:
+        out += [""] + timeline(a.trace, a.timeline)
     out += [f"# {n}" for n in a.note]
     with open(a.out, "w") as f:
         f.write("\n".join(out) + "\n")
