@@ -307,40 +307,64 @@ def time_per_step(sampler, gen, steps):
     return (time.perf_counter() - t0) / steps
 
 
-def importance_check(post, fl, gen, center, n_draws=1 << 20, batch=32768, frac_t=0.3, nu=3.0, scale=1.5, seed=0):
+def importance_check(post, fl, gen, center, n_draws=1 << 20, batch=32768, mix=(0.4, 0.4, 0.2), nu=3.0, scale=1.5,
+                     seed=0):
     """Self-normalised importance sampling of the posterior with a defensive mixture proposal
-    g = (1 - frac_t) q + frac_t t, q the trained flow and t a multivariate Student-t (nu degrees of
-    freedom) with the mean and `scale` times the covariance of the states `center` [n, 7]: x ~ g,
-    weights pi(x) / g(x) normalised to sum one.  The t component keeps the weights bounded where
-    the posterior's tails in the unconstrained coordinates are heavier than the flow's Gaussian
-    ones (near the spin prior edges the likelihood flattens and the logit Jacobian decays only
-    exponentially).  Returns the weighted mean and standard deviation of each summary feature,
-    their Monte Carlo standard errors (delta method, sqrt(sum w^2 (f - mean)^2) for a mean), Kish's
-    effective sample size 1 / sum w^2 and the largest normalised weight.  The estimate is
-    consistent for any proposal whose support covers pi and involves no Markov chain, so it checks
-    the flow-MH chains' equilibrium independently of their accept/reject bookkeeping."""
+    g = m_f q + m_k K + m_t t: q the trained flow; K a Gaussian kernel mixture centred on the states
+    `center` [n, 7] (kernel covariance h^2 C, C their covariance, h = (4 / (d + 2))^(1 / (d + 4))
+    n^(-1 / (d + 4)) with d = 7, the normal-reference bandwidth); t a multivariate Student-t (nu
+    degrees of freedom) with their mean and `scale` times C.  x ~ g, weights pi(x) / g(x) normalised
+    to sum one.  K covers the region the chains visit at its own local width (the flow can
+    under-weight parts of it, e.g. near the spin prior edges where the likelihood flattens), and t
+    keeps the weights bounded where the posterior's tails in the unconstrained coordinates are
+    heavier than Gaussian (the logit Jacobian decays only exponentially).  Returns the weighted mean
+    and standard deviation of each summary feature, their Monte Carlo standard errors (delta
+    method, sqrt(sum w^2 (f - mean)^2) for a mean), Kish's effective sample size 1 / sum w^2 and the
+    largest normalised weight.  The estimate is consistent for any proposal whose support covers pi
+    and involves no Markov chain, so it checks the flow-MH chains' equilibrium independently of
+    their accept/reject bookkeeping."""
     from scipy.special import gammaln
     c = np.asarray(center.cpu().numpy() if torch.is_tensor(center) else center, dtype=np.float64)
+    nc = c.shape[0]
     mu = c.mean(axis=0)
-    lc = np.linalg.cholesky(np.cov(c.T)) * scale
-    lc_inv = np.linalg.inv(lc)
+    cov_l = np.linalg.cholesky(np.cov(c.T))
+    lt_ = cov_l * scale
+    lt_inv = np.linalg.inv(lt_)
     lt_norm = (gammaln((nu + 7) / 2) - gammaln(nu / 2) - 3.5 * math.log(nu * math.pi)
-               - float(np.sum(np.log(np.diag(lc)))))
+               - float(np.sum(np.log(np.diag(lt_)))))
+    h = (4.0 / 9.0) ** (1.0 / 11.0) * nc ** (-1.0 / 11.0)
+    lk = cov_l * h
+    lk_inv = torch.as_tensor(np.linalg.inv(lk), device="cuda")
+    ck = torch.as_tensor(c, device="cuda") @ lk_inv.T
+    ck2 = (ck * ck).sum(dim=1)
+    lk_norm = -math.log(nc) - 3.5 * math.log(2.0 * math.pi) - float(np.sum(np.log(np.diag(lk))))
+    lmix = np.log(np.asarray(mix, dtype=np.float64))
     rng = np.random.default_rng(seed)
     lws, fs = [], []
     ws = sampling.Workspace()
     for _ in range(n_draws // batch):
+        comp = rng.choice(3, size=batch, p=np.asarray(mix) / np.sum(mix))
         z = torch.randn((batch, 7), dtype=torch.float64, device="cuda", generator=gen)
         xf, _ = fl.sample(z)
+        zk = rng.standard_normal((batch, 7))
+        xk = c[rng.integers(0, nc, batch)] + zk @ lk.T
         zt = rng.standard_normal((batch, 7))
-        xt = mu + (zt @ lc.T) / np.sqrt(rng.chisquare(nu, batch) / nu)[:, None]
-        pick = torch.as_tensor(rng.random(batch) < frac_t, device="cuda")[:, None]
-        x = torch.where(pick, torch.as_tensor(xt, device="cuda"), xf).contiguous()
+        xt = mu + (zt @ lt_.T) / np.sqrt(rng.chisquare(nu, batch) / nu)[:, None]
+        xo = np.where((comp == 1)[:, None], xk, xt)
+        x = torch.where(torch.as_tensor(comp == 0, device="cuda")[:, None], xf,
+                        torch.as_tensor(xo, device="cuda")).contiguous()
         _, lqf = fl.forward(x, want_z=False)
+        # kernel mixture density, in chunks of 4096 draws against all centres
+        lkd = []
+        for i0 in range(0, batch, 4096):
+            y = x[i0:i0 + 4096] @ lk_inv.T
+            d2 = ((y * y).sum(dim=1)[:, None] + ck2[None, :] - 2.0 * (y @ ck.T)).clamp_min(0.0)
+            lkd.append(torch.logsumexp(-0.5 * d2, dim=1))
+        lkd = torch.cat(lkd).cpu().numpy() + lk_norm
         xh = x.cpu().numpy()
-        d = (xh - mu) @ lc_inv.T
-        lt = lt_norm - (nu + 7) / 2 * np.log1p(np.sum(d * d, axis=1) / nu)
-        lg = np.logaddexp(math.log(1.0 - frac_t) + lqf.cpu().numpy(), math.log(frac_t) + lt)
+        d = (xh - mu) @ lt_inv.T
+        ltd = lt_norm - (nu + 7) / 2 * np.log1p(np.sum(d * d, axis=1) / nu)
+        lg = np.logaddexp(np.logaddexp(lmix[0] + lqf.cpu().numpy(), lmix[1] + lkd), lmix[2] + ltd)
         lp, _ = sampling.logp(post, x, want_grad=False, ws=ws)
         lws.append(lp.cpu().numpy() - lg)
         fs.append(features(post.to_theta(xh)[:, None, :])[:, 0, :])
@@ -353,8 +377,9 @@ def importance_check(post, fl, gen, center, n_draws=1 << 20, batch=32768, frac_t
     var = w @ (f - mean) ** 2
     se_mean = np.sqrt((w ** 2) @ (f - mean) ** 2)
     return dict(draws=int(len(w)), mean=mean, std=np.sqrt(var), se_mean=se_mean, kish_ess=float(1.0 / np.sum(w ** 2)),
-                max_weight=float(w.max()), proposal=f"{1 - frac_t:g} flow + {frac_t:g} Student-t (nu {nu:g}, "
-                                                    f"{scale:g} x ensemble covariance)")
+                max_weight=float(w.max()),
+                proposal=(f"{mix[0]:g} flow + {mix[1]:g} Gaussian kernels on {nc} chain states (bandwidth {h:.3f} x "
+                          f"their covariance) + {mix[2]:g} Student-t (nu {nu:g}, {scale:g} x their covariance)"))
 
 
 def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20000, ref_thin=10, flow_steps=600,
