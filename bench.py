@@ -510,8 +510,9 @@ def c5_summary(r):
     out["reference_drift_second_minus_first_half_sigma"] = dict(zip(nm, rd(r["reference"]["drift_mean_sigma"])))
     imp = r["importance"]
     out["importance_sampling"] = {
-        "proposal": imp["proposal"], "draws": imp["draws"], "kish_ess": round(imp["kish_ess"], 1),
-        "max_weight": imp["max_weight"],
+        "proposal": imp["proposal"], "draws": imp["draws"], "pareto_k_hat": round(imp["k_hat"], 3),
+        "kish_ess_smoothed": round(imp["kish_ess"], 1), "kish_ess_raw": round(imp["kish_ess_raw"], 1),
+        "max_raw_weight": imp["max_weight"],
         "z_flow_mh_minus_is": dict(zip(nm, rd(imp["z_mean_flow_minus_is"], 2))),
         "max_mean_diff_sigma_flow_mh_vs_is": max(imp["mean_diff_sigma_flow"]),
         "max_std_diff_sigma_flow_mh_vs_is": max(imp["std_diff_sigma_flow"])}

@@ -313,14 +313,14 @@ def importance_check(post, fl, gen, center, n_draws=1 << 20, batch=32768, mix=(0
     g = m_f q + m_k K + m_t t: q the trained flow; K a Gaussian kernel mixture centred on the states
     `center` [n, 7] (kernel covariance h^2 C, C their covariance, h = (4 / (d + 2))^(1 / (d + 4))
     n^(-1 / (d + 4)) with d = 7, the normal-reference bandwidth); t a multivariate Student-t (nu
-    degrees of freedom) with their mean and `scale` times C.  x ~ g, weights pi(x) / g(x) normalised
-    to sum one.  K covers the region the chains visit at its own local width (the flow can
+    degrees of freedom) with their mean and `scale` times C.  x ~ g, weights pi(x) / g(x),
+    Pareto-smoothed (diagnostics.psis) and normalised to sum one.  K covers the region the chains visit at its own local width (the flow can
     under-weight parts of it, e.g. near the spin prior edges where the likelihood flattens), and t
     keeps the weights bounded where the posterior's tails in the unconstrained coordinates are
     heavier than Gaussian (the logit Jacobian decays only exponentially).  Returns the weighted mean
     and standard deviation of each summary feature, their Monte Carlo standard errors (delta
-    method, sqrt(sum w^2 (f - mean)^2) for a mean), Kish's effective sample size 1 / sum w^2 and the
-    largest normalised weight.  The estimate is consistent for any proposal whose support covers pi
+    method, sqrt(sum w^2 (f - mean)^2) for a mean), Kish's effective sample size 1 / sum w^2 (smoothed
+    and raw), the Pareto shape k_hat (reliable below 0.7) and the largest raw normalised weight.  The estimate is consistent for any proposal whose support covers pi
     and involves no Markov chain, so it checks the flow-MH chains' equilibrium independently of
     their accept/reject bookkeeping."""
     from scipy.special import gammaln
@@ -371,13 +371,17 @@ def importance_check(post, fl, gen, center, n_draws=1 << 20, batch=32768, mix=(0
     lw = np.concatenate(lws)
     f = np.concatenate(fs)
     lw = np.where(np.isfinite(lw), lw, -np.inf)
-    w = np.exp(lw - lw.max())
+    w_raw = np.exp(lw - lw.max())
+    w_raw /= w_raw.sum()
+    # Pareto-smoothed weights (diagnostics.psis): k_hat < 0.7 marks a reliable estimate
+    lws, k_hat = diagnostics.psis(lw)
+    w = np.exp(lws - lws.max())
     w /= w.sum()
     mean = w @ f
     var = w @ (f - mean) ** 2
     se_mean = np.sqrt((w ** 2) @ (f - mean) ** 2)
     return dict(draws=int(len(w)), mean=mean, std=np.sqrt(var), se_mean=se_mean, kish_ess=float(1.0 / np.sum(w ** 2)),
-                max_weight=float(w.max()),
+                kish_ess_raw=float(1.0 / np.sum(w_raw ** 2)), k_hat=float(k_hat), max_weight=float(w_raw.max()),
                 proposal=(f"{mix[0]:g} flow + {mix[1]:g} Gaussian kernels on {nc} chain states (bandwidth {h:.3f} x "
                           f"their covariance) + {mix[2]:g} Student-t (nu {nu:g}, {scale:g} x their covariance)"))
 
@@ -456,7 +460,8 @@ def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20
         # agreement of the learned-proposal sampler with the reference, in units of the reference sigma
         mean_diff_sigma_flow=(np.abs(mb - mr) / sr).tolist(), std_diff_sigma_flow=(np.abs(sb - sr) / sr).tolist(),
         mean_flow=mb.tolist(), std_flow=sb.tolist(), theta_inj=th0.tolist(),
-        importance=dict(draws=isr["draws"], kish_ess=isr["kish_ess"], max_weight=isr["max_weight"],
+        importance=dict(draws=isr["draws"], kish_ess=isr["kish_ess"], kish_ess_raw=isr["kish_ess_raw"],
+                        k_hat=isr["k_hat"], max_weight=isr["max_weight"],
                         proposal=isr["proposal"],
                         mean=isr["mean"].tolist(), std=isr["std"].tolist(), se_mean=isr["se_mean"].tolist(),
                         z_mean_flow_minus_is=z_is.tolist(),

@@ -304,3 +304,45 @@ def test_dense_hmc_with_exact_metric_solves_a_correlated_gaussian():
     se = np.sqrt(np.diag(cov) / len(d)) * 3.0    # draws are nearly independent
     assert np.all(np.abs(d.mean(axis=0) - mu) <= 6.0 * se)
     assert np.max(np.abs(np.cov(d.T) - cov)) <= 0.08 * np.max(np.abs(cov))
+
+
+def test_psis_shape_matches_the_gaussian_tail_index():
+    """Target N(0, 1), proposal N(0, s^2) with s < 1: the ratio w = p / q satisfies
+    P(w > t) ~ t^(-1 / (1 - s^2)), so the generalised Pareto shape of its tail is k = 1 - s^2; with
+    s > 1 the ratio is bounded (k <= 0)."""
+    rng = np.random.default_rng(41)
+    for s2, lo, hi in ((0.25, 0.62, 0.88), (0.5, 0.38, 0.62)):
+        x = rng.normal(0.0, math.sqrt(s2), 200000)
+        lw = -0.5 * x * x + 0.5 * x * x / s2
+        _, k = D.psis(lw)
+        assert lo < k < hi, (s2, k)
+    x = rng.normal(0.0, 2.0, 200000)
+    _, k = D.psis(-0.5 * x * x + 0.5 * x * x / 4.0)
+    assert k < 0.2, k
+
+
+def test_psis_self_normalised_moments_are_consistent():
+    """Moments of N(1, 1) from a N(0, 1.5^2) proposal with smoothed weights: within a few standard
+    errors of the exact ones; smoothing leaves light-tailed weights almost unchanged."""
+    rng = np.random.default_rng(43)
+    x = rng.normal(0.0, 1.5, 400000)
+    lw = -0.5 * (x - 1.0) ** 2 + 0.5 * (x / 1.5) ** 2
+    lws, k = D.psis(lw)
+    w = np.exp(lws - lws.max())
+    w /= w.sum()
+    m = float(w @ x)
+    v = float(w @ (x - m) ** 2)
+    assert abs(m - 1.0) < 0.01 and abs(v - 1.0) < 0.02, (m, v, k)
+    w0 = np.exp(lw - lw.max())
+    w0 /= w0.sum()
+    assert abs(float(w0 @ x) - m) < 1e-3
+
+
+def test_gpd_fit_recovers_known_parameters():
+    """Exceedances drawn from a generalised Pareto distribution by inversion: the fitted shape and
+    scale are close to the generating ones (the prior pulls the shape towards 0.5 by 10 / (n + 10))."""
+    rng = np.random.default_rng(44)
+    for xi, sig in ((0.3, 2.0), (0.7, 0.5), (-0.2, 1.0)):
+        y = D.gpd_quantile(rng.random(20000), xi, sig)
+        xh, sh = D.gpd_fit(y)
+        assert abs(xh - xi) < 0.05 and abs(sh / sig - 1.0) < 0.06, (xi, sig, xh, sh)
