@@ -40,3 +40,49 @@ def test_committed_summaries_match_the_current_kernels():
     assert kv is not None, "C4 counter summary is stale"
     for key in ("columns_hbm_bytes_per_call", "rows_hbm_bytes_per_call", "adjoint_fp64_flops_per_call"):
         assert int(kv[key]) > 0
+
+
+def test_counter_summary_from_synthetic_profiler_output(tmp_path, monkeypatch):
+    """counters.py on tiny hand-written rocprofv3-style CSVs: per-kernel averages, the last
+    dispatch's FP64 flops (64 x (ADD + MUL + TRANS + 2 FMA)), bytes scaled by the copy calibration,
+    the summed keys and the timeline between two dispatches of a marker kernel."""
+    import csv as _csv
+    from paper_2302_05329_amd import counters
+
+    def write(d, name, rows):
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, name), "w", newline="") as f:
+            w = _csv.DictWriter(f, fieldnames=list(rows[0].keys()))
+            w.writeheader()
+            w.writerows(rows)
+
+    tr = tmp_path / "trace"
+    write(tr, "run_kernel_trace.csv", [
+        {"Kernel_Name": "k_begin", "Start_Timestamp": 0, "End_Timestamp": 1000},
+        {"Kernel_Name": "k_a", "Start_Timestamp": 2000, "End_Timestamp": 6000},
+        {"Kernel_Name": "k_begin", "Start_Timestamp": 7000, "End_Timestamp": 8000},
+        {"Kernel_Name": "k_a", "Start_Timestamp": 9000, "End_Timestamp": 11000}])
+    f64 = tmp_path / "f64"
+    rows = []
+    for disp, scale in ((1, 1), (2, 2)):
+        for c, v in (("SQ_INSTS_VALU_ADD_F64", 10), ("SQ_INSTS_VALU_MUL_F64", 20), ("SQ_INSTS_VALU_FMA_F64", 30),
+                     ("SQ_INSTS_VALU_TRANS_F64", 5)):
+            rows.append({"Dispatch_Id": disp, "Kernel_Name": "k_a", "Counter_Name": c, "Counter_Value": v * scale})
+    write(f64, "run_counter_collection.csv", rows)
+    fe, wr, cf, cw = (tmp_path / n for n in ("fe", "wr", "cf", "cw"))
+    write(fe, "run_counter_collection.csv", [{"Dispatch_Id": 2, "Kernel_Name": "k_a", "Counter_Name": "FETCH_SIZE", "Counter_Value": 100}])
+    write(wr, "run_counter_collection.csv", [{"Dispatch_Id": 2, "Kernel_Name": "k_a", "Counter_Name": "WRITE_SIZE", "Counter_Value": 50}])
+    write(cf, "run_counter_collection.csv", [{"Dispatch_Id": 1, "Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "FETCH_SIZE", "Counter_Value": 524288}])
+    write(cw, "run_counter_collection.csv", [{"Dispatch_Id": 1, "Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "WRITE_SIZE", "Counter_Value": 1048576}])
+    out = tmp_path / "s.txt"
+    monkeypatch.setattr(sys, "argv", ["counters", "--title", "t", "--trace", str(tr), "--fp64", str(f64), "--fetch", str(fe), "--write", str(wr),
+                "--cfetch", str(cf), "--cwrite", str(cw), "--group", "loglike", "--kernels", "a=k_a",
+                "--timeline", "k_begin", "--out", str(out)])
+    counters.main()
+    kv = counters.read_summary(str(out), "loglike")
+    # last dispatch: 64 x (20 + 40 + 10 + 2 x 60) = 12160 flops; bytes: 100 KiB x 2 + 50 KiB x 1
+    assert int(kv["a_fp64_flops_per_call"]) == 64 * (20 + 40 + 10 + 2 * 60)
+    assert int(kv["a_hbm_bytes_per_call"]) == 100 * 1024 * 2 + 50 * 1024
+    assert abs(float(kv["a_avg_us_sum"]) - 3.0) < 1e-9
+    text = out.read_text()
+    assert "timeline of one interval" in text and "k_a" in text.split("timeline")[1]
