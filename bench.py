@@ -508,6 +508,18 @@ def c5_summary(r):
     out["within_0.05_sigma"] = (out["max_mean_diff_sigma_flow_mh_vs_reference"] <= 0.05
                                 and out["max_std_diff_sigma_flow_mh_vs_reference"] <= 0.05)
     out["reference_drift_second_minus_first_half_sigma"] = dict(zip(nm, rd(r["reference"]["drift_mean_sigma"])))
+    st = r["stationarity"]
+    out["stationarity_plain_hmc_from_flow_mh_states"] = {
+        "chains": st["chains"], "n_leapfrog": st["n_leapfrog"], "steps": st["steps"], "acceptance": st["acceptance"],
+        "mean_diff_sigma": dict(zip(nm, rd(st["mean_diff_sigma"]))),
+        "std_diff_rel": dict(zip(nm, rd(st["std_diff_rel"]))),
+        "drift_second_minus_first_half_sigma": dict(zip(nm, rd(st["drift_mean_sigma"]))),
+        "mc_error_sigma": dict(zip(nm, rd(st["se_sigma"]))),
+        "max_abs_mean_diff_sigma": max(abs(v) for v in st["mean_diff_sigma"]),
+        "max_abs_std_diff_rel": max(abs(v) for v in st["std_diff_rel"]),
+        "tau_steps": dict(zip(nm, rd(st["tau_steps"], 1)))}
+    out["stationarity_within_0.05_sigma"] = (out["stationarity_plain_hmc_from_flow_mh_states"]["max_abs_mean_diff_sigma"] <= 0.05
+                                            and out["stationarity_plain_hmc_from_flow_mh_states"]["max_abs_std_diff_rel"] <= 0.05)
     imp = r["importance"]
     out["importance_sampling"] = {
         "proposal": imp["proposal"], "draws": imp["draws"], "pareto_k_hat": round(imp["k_hat"], 3),

@@ -386,9 +386,34 @@ def importance_check(post, fl, gen, center, n_draws=1 << 20, batch=32768, mix=(0
                           f"their covariance) + {mix[2]:g} Student-t (nu {nu:g}, {scale:g} x their covariance)"))
 
 
+def stationarity_check(post, x_flow, eps0, chol, gen, n_run=512, n_leapfrog=100, steps=3000, thin=5, log=None):
+    """Plain HMC (dense metric, `n_leapfrog` steps per transition, step size re-tuned towards
+    acceptance 0.7) started from the first `n_run` flow-MH end states.  HMC leaves the posterior
+    invariant, so if those states are posterior draws the ensemble's moments stay where they are;
+    a flow-MH bias would show as a drift towards the posterior.  Returns the moments of the whole
+    run and of its two halves, the ESS and autocorrelation times."""
+    h = sampling.HMC(post, x_flow[:n_run].clone(), eps0, n_leapfrog, chol=chol)
+    eps = eps0
+    for _ in range(60):
+        xi, u = _rand(gen, h.n)
+        acc = float((h.step(xi, u) == 1).double().mean())
+        eps *= math.exp(0.5 * (acc - 0.7))
+        h.eps = eps
+    d, sec, acc = run_hmc(h, gen, steps, thin)
+    m, s = _moments(d)
+    half = d.shape[1] // 2
+    m1, _ = _moments(d[:, :half])
+    m2, _ = _moments(d[:, half:])
+    ess = ess_per_param(d)
+    if log:
+        log(f"stationarity: plain HMC ({n_leapfrog} leapfrog steps) from flow-MH states, {n_run} x {steps}, "
+            f"{sec:.1f} s")
+    return dict(mean=m, std=s, mean1=m1, mean2=m2, ess=ess, tau=n_run * steps / ess, acceptance=acc, eps=eps)
+
+
 def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20000, ref_thin=10, flow_steps=600,
             n_leapfrog=10, rounds=6, per_round=50, seed=1005, n_bins=None, log=None, flow_mode="bf16",
-            two_site=False):
+            two_site=False, stat_chains=512, stat_leapfrog=100, stat_steps=3000):
     """The full comparison; returns a dict of rates, acceptance, autocorrelation times and the
     agreement of the flow sampler's moments with the plain-HMC reference run.
 
@@ -433,8 +458,8 @@ def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20
     ess_per_s_hmc = n_chains / tau_r / t_hmc
     fl, t_train = flow_burn_in(None, gen, rounds=rounds, per_round=per_round, log=log, mode=flow_mode, keep=hmc)
     x_start = hmc.x.clone()
-    db, tb, acc_bh, acc_bm = run_flow_hmc(sampling.HMC(post, x_start, eps, n_leapfrog, chol=chol), fl, gen,
-                                         flow_steps)
+    prod = sampling.HMC(post, x_start, eps, n_leapfrog, chol=chol)
+    db, tb, acc_bh, acc_bm = run_flow_hmc(prod, fl, gen, flow_steps)
     ess_b = ess_per_param(db)
     mb, sb = _moments(db)
     del db
@@ -442,6 +467,8 @@ def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20
     isr = importance_check(post, fl, gen, x_start, seed=seed)
     # flow-MH mean minus importance-sampling mean, in combined Monte Carlo standard errors
     z_is = (mb - isr["mean"]) / np.sqrt(sb ** 2 / ess_b + isr["se_mean"] ** 2)
+    st = stationarity_check(post, prod.x, eps, chol, gen, n_run=stat_chains, n_leapfrog=stat_leapfrog,
+                            steps=stat_steps, log=log)
     return dict(
         n_chains=n_chains, warm=warm, n_ref=n_ref, ref_burn=ref_burn, ref_steps=ref_steps, ref_thin=ref_thin,
         flow_steps=flow_steps, n_leapfrog=n_leapfrog, eps=eps, n_bins=pb["grid"].n_bins, flow_mode=flow_mode,
@@ -460,6 +487,12 @@ def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20
         # agreement of the learned-proposal sampler with the reference, in units of the reference sigma
         mean_diff_sigma_flow=(np.abs(mb - mr) / sr).tolist(), std_diff_sigma_flow=(np.abs(sb - sr) / sr).tolist(),
         mean_flow=mb.tolist(), std_flow=sb.tolist(), theta_inj=th0.tolist(),
+        stationarity=dict(chains=stat_chains, n_leapfrog=stat_leapfrog, steps=stat_steps, eps=st["eps"],
+                          acceptance=st["acceptance"], tau_steps=st["tau"].tolist(),
+                          mean_diff_sigma=((st["mean"] - mb) / sb).tolist(),
+                          std_diff_rel=((st["std"] - sb) / sb).tolist(),
+                          drift_mean_sigma=((st["mean2"] - st["mean1"]) / sb).tolist(),
+                          se_sigma=(1.0 / np.sqrt(st["ess"])).tolist()),
         importance=dict(draws=isr["draws"], kish_ess=isr["kish_ess"], kish_ess_raw=isr["kish_ess_raw"],
                         k_hat=isr["k_hat"], max_weight=isr["max_weight"],
                         proposal=isr["proposal"],
