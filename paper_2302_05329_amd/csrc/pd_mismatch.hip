@@ -288,8 +288,8 @@ __global__ void __launch_bounds__(256) k_mm_rows_max(const double2* __restrict__
     constexpr int kLd = LEN + 1;
     __shared__ double2 buf[kLdsPts + kLdsPts / LEN];
     __shared__ double2 tw[LEN];
-    __shared__ double rv[256];
-    __shared__ int ri[256];
+    __shared__ double rv[4];
+    __shared__ int ri[4];
     const int64_t N = static_cast<int64_t>(n2) * LEN;
     const int groups = n2 / rows;
     const int64_t p = blockIdx.x / groups;
@@ -314,21 +314,27 @@ __global__ void __launch_bounds__(256) k_mm_rows_max(const double2* __restrict__
             bidx = j;
         }
     }
-    rv[threadIdx.x] = best;
-    ri[threadIdx.x] = bidx;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            const double ov = rv[threadIdx.x + off];
-            const int oi = ri[threadIdx.x + off];
-            if (better(ov, oi, rv[threadIdx.x], ri[threadIdx.x])) {
-                rv[threadIdx.x] = ov;
-                ri[threadIdx.x] = oi;
-            }
+    // arg-max over the wave by lane exchanges, then over the block's four waves
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bidx, off, 64);
+        if (better(ov, oi, best, bidx)) {
+            best = ov;
+            bidx = oi;
         }
-        __syncthreads();
     }
+    if ((threadIdx.x & 63) == 0) {
+        rv[threadIdx.x >> 6] = best;
+        ri[threadIdx.x >> 6] = bidx;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w)
+            if (better(rv[w], ri[w], rv[0], ri[0])) {
+                rv[0] = rv[w];
+                ri[0] = ri[w];
+            }
         // no comparable |z|^2 (all NaN): report lag 0 with a NaN modulus
         const bool none = ri[0] == 0x7fffffff;
         const int j = none ? grow : ri[0];
