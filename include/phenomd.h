@@ -335,7 +335,8 @@ int pd_hmc_step(const pd_posterior* post, int64_t n, double* x, double* logp, do
  * entries above the diagonal are ignored), i.e. p ~ N(0, (L L^T)^-1) and
  * H = -log pi(x) + p^T L L^T p / 2.  The chains carry r = L^T p = xi, so the drift is
  * x += eps L r and the kick r += eps L^T grad log pi.  With L the Cholesky factor of the posterior
- * covariance the trajectories see an isotropic target.  Workspace as pd_hmc_workspace_bytes. */
+ * covariance the trajectories see an isotropic target.  Workspace as pd_hmc_workspace_bytes.
+ * PD_EINVAL (nothing launched) for a NULL chol, a non-finite entry or a non-positive diagonal. */
 int pd_hmc_step_dense(const pd_posterior* post, int64_t n, double* x, double* logp, double* grad, const double* xi,
                       const double* u, int n_leapfrog, double eps, const double* chol, int32_t* accepted,
                       double* dh, void* workspace, size_t workspace_bytes, void* stream);
@@ -358,7 +359,8 @@ int pd_rwmh_step(const pd_posterior* post, int64_t n, double* x, double* logp, c
 
 /* As pd_rwmh_step with correlated Gaussian steps x' = x + L xi, the proposal covariance L L^T
  * given by the row-major lower-triangular chol [7][7] (HOST array, finite; entries above the
- * diagonal are ignored).  Workspace as pd_rwmh_workspace_bytes. */
+ * diagonal are ignored).  Workspace as pd_rwmh_workspace_bytes.  PD_EINVAL (nothing launched)
+ * for a NULL chol or a non-finite entry. */
 int pd_rwmh_step_dense(const pd_posterior* post, int64_t n, double* x, double* logp, const double* xi,
                        const double* u, const double* chol, int32_t* accepted, void* workspace, size_t workspace_bytes,
                        void* stream);
