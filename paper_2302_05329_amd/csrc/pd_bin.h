@@ -368,6 +368,31 @@ __host__ __device__ constexpr bool slot_touched(int pr, int ar, int s) {
            (ar == 3 && s >= R_AM3 && s < R_AM3 + 4);
 }
 
+// Record entries a phase-region pass can touch: those of every (phase region, amplitude region)
+// pair that phase region meets (the inspiral meets amplitude regions 1-3, the others 2-3).
+__host__ __device__ constexpr bool region_slot(int prg, int s) {
+    return prg == 1 ? (slot_touched(1, 1, s) || slot_touched(1, 2, s) || slot_touched(1, 3, s))
+                    : (slot_touched(prg, 2, s) || slot_touched(prg, 3, s));
+}
+
+// Bit s set for each record entry s the pass of phase region prg can touch.
+__host__ __device__ constexpr unsigned long long region_slot_mask(int prg) {
+    unsigned long long m = 0;
+    for (int s = 0; s < REC_N; ++s)
+        if (region_slot(prg, s)) m |= 1ull << s;
+    return m;
+}
+
+// Width of phase region prg's compact partial row: (d|h), (h|h), then the region's entries in
+// record order; and the position of entry s (0 <= s < 64) among them (-1: not kept).
+// The masks are constants of the three regions, so both come down to a shift and a popcount.
+constexpr unsigned long long kRegionSlotMask[3] = {region_slot_mask(1), region_slot_mask(2), region_slot_mask(3)};
+__host__ __device__ constexpr int region_row_width(int prg) { return 2 + __builtin_popcountll(kRegionSlotMask[prg - 1]); }
+__host__ __device__ inline int region_slot_pos(int prg, int s) {
+    const unsigned long long m = prg == 1 ? kRegionSlotMask[0] : (prg == 2 ? kRegionSlotMask[1] : kRegionSlotMask[2]);
+    return ((m >> s) & 1ull) ? __builtin_popcountll(m & ((1ull << s) - 1ull)) : -1;
+}
+
 // Visit d Psi / d rec[s] (vis.ph), d ln A / d rec[s] (vis.am) and the explicit
 // Mf-dependence: Mf dPsi/dMf and Mf d lnA/dMf (vis.fd), for one bin.
 template <int PR, int AR, class V, class RC = const double*>

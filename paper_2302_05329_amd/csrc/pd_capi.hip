@@ -91,7 +91,9 @@ Layout layout_for(int op, int64_t n, int64_t nb) {
             L.tan = off;
             off = align_up(off + N * 4 * pd::REC_N * sizeof(double));
             L.partial = off;
-            off = align_up(off + 3 * N * L.chunks * pd::kNSlot * sizeof(double));
+            off = align_up(off + N * L.chunks *
+                                     (pd::region_row_width(1) + pd::region_row_width(2) + pd::region_row_width(3)) *
+                                     sizeof(double));
             L.seg = off;
             off = align_up(off + 3 * N * L.chunks * pd::kSegInts * sizeof(int));
             L.order = off;

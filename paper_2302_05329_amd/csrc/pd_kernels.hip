@@ -308,6 +308,17 @@ struct LnlSegment {
     }
 };
 
+// Start of phase region prg's partial rows [n][chunks][width]: value passes 2 entries per row,
+// gradient passes the compact row of region_row_width(prg) entries; the regions' blocks follow
+// one another.
+template <int MODE>
+__host__ __device__ inline int64_t grad_group_offset(int prg, int64_t n, int chunks) {
+    if (MODE == 0) return static_cast<int64_t>(prg - 1) * n * chunks * 2;
+    int64_t off = 0;
+    for (int r = 1; r < prg; ++r) off += n * chunks * region_row_width(r);
+    return off;
+}
+
 // One wave's share of the fused pass: PRG is the phase region (1 inspiral, 2 intermediate,
 // 3 merger-ringdown) whose segments it handles, `wave` its index among that region's waves.
 template <int MODE, int PRG>
@@ -315,8 +326,9 @@ __device__ __forceinline__ void moments_wave(int64_t wave, const double* __restr
                                              const GridArgs& g, const double* __restrict__ tab,
                                              const int* __restrict__ segs, const int* __restrict__ perm,
                                              double* __restrict__ partial_all, const double2* __restrict__ sct) {
-    constexpr int NS = (MODE == 0) ? 2 : kNSlot;
-    double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * NS;
+    // value passes keep (d|h), (h|h) per row; gradient passes a compact row of the region's entries
+    constexpr int NS = (MODE == 0) ? 2 : region_row_width(PRG);
+    double* __restrict__ partial = partial_all + grad_group_offset<MODE>(PRG, n, chunks);
     const int lane = threadIdx.x & 63;
     const int cr = region_chunks(PRG, chunks);
     const int64_t pi = wave / cr;
@@ -346,7 +358,10 @@ __device__ __forceinline__ void moments_wave(int64_t wave, const double* __restr
     const double r = halving_reduce<2>(dv, lane);
     if (lane == halving_lane<2>(0)) out[0] = r * a0p;
     if (lane == halving_lane<2>(1)) out[1] = r * (a0p * a0p);
-    if (MODE == 1 && lane < REC_N) out[2 + lane] = seg.tot * a0p;
+    if (MODE == 1 && lane < REC_N) {
+        const int pos = region_slot_pos(PRG, lane);
+        if (pos >= 0) out[2 + pos] = seg.tot * a0p;
+    }
 }
 
 // One launch per phase region (concurrent on three streams, or in sequence).
@@ -409,7 +424,7 @@ __global__ void __launch_bounds__(128) k_loglike_value_epilogue(const double* __
 }
 
 // One wave per point: lane j (< 62) sums partial slot j over the three region groups and the
-// point's chunks (each row is contiguous, so every load is coalesced), the four intrinsic
+// point's chunks (a region's rows keep only the entries it touches; each row is contiguous), the four intrinsic
 // directions are contracted lane-wise with the record tangents (computed concurrently by
 // k_setup_theta_tangent<4>) and summed over the wave in a fixed order, and the three extrinsic
 // entries use closed-form record tangents (D or ln D only through ln A0, tc only through the
@@ -437,9 +452,16 @@ __global__ void __launch_bounds__(256) k_loglike_grad_epilogue(const double* __r
     }
     double m = 0.0;     // lane 0: (d|h), lane 1: (h|h), lane 2 + j: moment j
     if (lane < NS) {
-        for (int grp = 0; grp < 3; ++grp)
-            for (int c = 0; c < region_chunks(grp + 1, chunks); ++c)
-                m += partial[((grp * n + p) * chunks + c) * NS + lane];
+        for (int grp = 0; grp < 3; ++grp) {
+            const int prg = grp + 1;
+            // this lane's entry in the region's compact row (rows hold only the entries it touches)
+            const int pos = (lane < 2) ? lane - 2 : region_slot_pos(prg, lane - 2);
+            if (lane >= 2 && pos < 0) continue;
+            const int col = 2 + pos;
+            const int w = region_row_width(prg);
+            const double* __restrict__ rows = partial + grad_group_offset<1>(prg, n, chunks);
+            for (int c = 0; c < region_chunks(prg, chunks); ++c) m += rows[(p * chunks + c) * w + col];
+        }
     }
     auto at = [&](int slot) {   // wave-uniform copy of one lane's sum
         const unsigned long long b = __builtin_bit_cast(unsigned long long, m);
