@@ -11,7 +11,7 @@
 //                                                                      2048 / N2 columns / block
 //   2. row pass        N1-point inverse DFTs over k1, |z|^2 and arg-max fused (lag
 //                      j = j2 + N2 j1); the overlap series itself is never written
-//                                                                      2048 / N1 rows / block
+//                                                                      1024 / N1 rows / block
 //   3. finalize        lag j*, |z_j*|, mismatch                         one thread / target
 //   4. adjoint         moments of the mismatch adjoint per bin (model recomputed, no
 //                      per-bin storage)                                 one wave / (target, chunk)
@@ -37,7 +37,11 @@ struct FFTPlan {
     int gc, gr;         // column groups and row groups per target
 };
 
-constexpr int kLdsPts = 2048;   // complex points per block (one 32 KiB LDS buffer, plus padding)
+// complex points per block (one LDS buffer, plus padding): the column pass evaluates the model
+// for its points, so it keeps fewer, larger blocks; the row pass only loads and transforms, and
+// more, smaller blocks per compute unit overlap its loads with other blocks' transforms
+constexpr int kColPts = 2048;
+constexpr int kRowPts = 1024;
 constexpr int kTw = 256;        // entries of each twiddle table
 
 inline FFTPlan make_plan(int64_t n) {
@@ -47,8 +51,8 @@ inline FFTPlan make_plan(int64_t n) {
     while ((int64_t(1) << lg) < n) ++lg;
     f.n1 = 1 << ((lg + 1) / 2);
     f.n2 = 1 << (lg / 2);
-    f.cb = kLdsPts / f.n2 < f.n1 ? kLdsPts / f.n2 : f.n1;
-    f.rb = kLdsPts / f.n1 < f.n2 ? kLdsPts / f.n1 : f.n2;
+    f.cb = kColPts / f.n2 < f.n1 ? kColPts / f.n2 : f.n1;
+    f.rb = kRowPts / f.n1 < f.n2 ? kRowPts / f.n1 : f.n2;
     f.gc = f.n1 / f.cb;
     f.gr = f.n2 / f.rb;
     return f;
@@ -117,82 +121,114 @@ __device__ __forceinline__ double2 twiddle(const double2* __restrict__ tw, unsig
 
 // ---- LDS radix-4 Stockham inverse DFT of length LEN on `cols` columns ----------------------
 // Column c of `buf` starts at c * (LEN + 1) (one point of padding spreads the columns over the
-// banks; cols * LEN <= 2048, so the buffer holds 2048 + 2048 / LEN points).  Each stage: every thread loads the inputs of its butterflies into registers, the block
-// synchronises, the outputs are written, the block synchronises.  Stages of radix 4
-// (X_j = sum_k a_k i^(jk) for the inverse transform), then one of radix 2 when log2(LEN) is odd.
-// tw[j] = exp(2 pi i j / LEN).  The result is in natural order in `buf`.
-template <int LEN>
-__device__ __forceinline__ void lds_idft(double2* buf, int cols, const double2* __restrict__ tw) {
+// banks; cols * LEN <= PTS, the block's tile, so the buffer holds PTS + PTS / LEN points).  Stages
+// of radix 4 (X_j = sum_k a_k i^(jk) for the inverse transform), then one of radix 2 when
+// log2(LEN) is odd; tw[j] = exp(2 pi i j / LEN).  A stage loads the inputs of each thread's
+// butterflies into registers, the block synchronises, the outputs are written in place, the block
+// synchronises.  Two ends can skip the buffer: with SRC the first stage reads its inputs through
+// src(col, index) (from global memory, say), and with SINK the last stage hands each output to
+// sink(col, index, value) instead of writing it back (and needs no synchronisation).  COLFAST
+// gives the last stage's butterflies to threads column-fastest, so that consecutive threads take
+// the same output index of consecutive columns (coalesced stores of a transposed layout).
+// Without SINK the result is in natural order in `buf`.
+template <int LEN, int PTS, bool SRC, bool SINK, bool COLFAST, class Src, class Sink>
+__device__ __forceinline__ void lds_idft_io(double2* buf, int cols, const double2* __restrict__ tw, Src&& src,
+                                            Sink&& sink) {
     constexpr int kLog2 = __builtin_ctz(LEN);
     constexpr int kR4 = kLog2 / 2;
+    constexpr bool kOdd = (kLog2 & 1) != 0;
     constexpr int kLd = LEN + 1;
-    constexpr int kPer4 = (kLdsPts / 4 + 255) / 256;   // radix-4 butterflies per thread (at most)
+    constexpr int kPer4 = (PTS / 4 + 255) / 256;   // radix-4 butterflies per thread (at most)
     const int nb4 = cols * (LEN / 4);
 #pragma unroll
     for (int st = 0; st < kR4; ++st) {
+        const bool from_src = SRC && st == 0;
+        const bool to_sink = SINK && !kOdd && st == kR4 - 1;
+        const bool colfast = COLFAST && !kOdd && st == kR4 - 1;
         const int n = LEN >> (2 * st), s = 1 << (2 * st), m = n >> 2;
         double2 a[kPer4][4];
+        int cl[kPer4], bb[kPer4];
 #pragma unroll
         for (int r = 0; r < kPer4; ++r) {
             const int idx = threadIdx.x + 256 * r;
+            cl[r] = colfast ? idx % cols : idx / (LEN / 4);
+            bb[r] = colfast ? idx / cols : idx % (LEN / 4);
             if (idx < nb4) {
-                const int col = idx / (LEN / 4), b = idx - col * (LEN / 4);
-                const int q = b & (s - 1), pp = b >> (2 * st);
-                const double2* xc = buf + col * kLd + q + s * pp;
-                a[r][0] = xc[0];
-                a[r][1] = xc[s * m];
-                a[r][2] = xc[2 * s * m];
-                a[r][3] = xc[3 * s * m];
+                const int q = bb[r] & (s - 1), pp = bb[r] >> (2 * st);
+                const int i0 = q + s * pp;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    a[r][t] = from_src ? src(cl[r], i0 + t * s * m) : buf[cl[r] * kLd + i0 + t * s * m];
             }
         }
-        __syncthreads();
+        // every read of this stage is done before any thread overwrites its inputs
+        if (!from_src && !to_sink) __syncthreads();
 #pragma unroll
         for (int r = 0; r < kPer4; ++r) {
             const int idx = threadIdx.x + 256 * r;
             if (idx < nb4) {
-                const int col = idx / (LEN / 4), b = idx - col * (LEN / 4);
-                const int q = b & (s - 1), pp = b >> (2 * st);
+                const int q = bb[r] & (s - 1), pp = bb[r] >> (2 * st);
                 const double2 b0 = make_double2(a[r][0].x + a[r][2].x, a[r][0].y + a[r][2].y);
                 const double2 b1 = make_double2(a[r][0].x - a[r][2].x, a[r][0].y - a[r][2].y);
                 const double2 b2 = make_double2(a[r][1].x + a[r][3].x, a[r][1].y + a[r][3].y);
                 // i (a1 - a3)
                 const double2 b3 = make_double2(a[r][3].y - a[r][1].y, a[r][1].x - a[r][3].x);
                 const int ts = pp * (LEN / n);
-                double2* yc = buf + col * kLd + q + s * 4 * pp;
-                yc[0] = make_double2(b0.x + b2.x, b0.y + b2.y);
-                yc[s] = cmul(make_double2(b1.x + b3.x, b1.y + b3.y), tw[ts]);
-                yc[2 * s] = cmul(make_double2(b0.x - b2.x, b0.y - b2.y), tw[2 * ts]);
-                yc[3 * s] = cmul(make_double2(b1.x - b3.x, b1.y - b3.y), tw[3 * ts]);
+                const int o = q + s * 4 * pp;
+                const double2 y0 = make_double2(b0.x + b2.x, b0.y + b2.y);
+                const double2 y1 = cmul(make_double2(b1.x + b3.x, b1.y + b3.y), tw[ts]);
+                const double2 y2 = cmul(make_double2(b0.x - b2.x, b0.y - b2.y), tw[2 * ts]);
+                const double2 y3 = cmul(make_double2(b1.x - b3.x, b1.y - b3.y), tw[3 * ts]);
+                if (to_sink) {
+                    sink(cl[r], o, y0);
+                    sink(cl[r], o + s, y1);
+                    sink(cl[r], o + 2 * s, y2);
+                    sink(cl[r], o + 3 * s, y3);
+                } else {
+                    double2* yc = buf + cl[r] * kLd + o;
+                    yc[0] = y0;
+                    yc[s] = y1;
+                    yc[2 * s] = y2;
+                    yc[3 * s] = y3;
+                }
             }
         }
-        __syncthreads();
+        if (!to_sink) __syncthreads();
     }
-    if constexpr (kLog2 & 1) {
+    if constexpr (kOdd) {
         // last stage: n = 2, s = LEN / 2, twiddle 1
         constexpr int s = LEN / 2;
-        constexpr int kPer2 = (kLdsPts / 2 + 255) / 256;
+        constexpr int kPer2 = (PTS / 2 + 255) / 256;
         const int nb2 = cols * (LEN / 2);
         double2 a[kPer2][2];
+        int cl[kPer2], qq[kPer2];
+#pragma unroll
+        for (int r = 0; r < kPer2; ++r) {
+            const int idx = threadIdx.x + 256 * r;
+            cl[r] = COLFAST ? idx % cols : idx / (LEN / 2);
+            qq[r] = COLFAST ? idx / cols : idx % (LEN / 2);
+            if (idx < nb2) {
+                a[r][0] = buf[cl[r] * kLd + qq[r]];
+                a[r][1] = buf[cl[r] * kLd + qq[r] + s];
+            }
+        }
+        if (!SINK) __syncthreads();
 #pragma unroll
         for (int r = 0; r < kPer2; ++r) {
             const int idx = threadIdx.x + 256 * r;
             if (idx < nb2) {
-                const int col = idx / (LEN / 2), q = idx - col * (LEN / 2);
-                a[r][0] = buf[col * kLd + q];
-                a[r][1] = buf[col * kLd + q + s];
+                const double2 y0 = make_double2(a[r][0].x + a[r][1].x, a[r][0].y + a[r][1].y);
+                const double2 y1 = make_double2(a[r][0].x - a[r][1].x, a[r][0].y - a[r][1].y);
+                if (SINK) {
+                    sink(cl[r], qq[r], y0);
+                    sink(cl[r], qq[r] + s, y1);
+                } else {
+                    buf[cl[r] * kLd + qq[r]] = y0;
+                    buf[cl[r] * kLd + qq[r] + s] = y1;
+                }
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kPer2; ++r) {
-            const int idx = threadIdx.x + 256 * r;
-            if (idx < nb2) {
-                const int col = idx / (LEN / 2), q = idx - col * (LEN / 2);
-                buf[col * kLd + q] = make_double2(a[r][0].x + a[r][1].x, a[r][0].y + a[r][1].y);
-                buf[col * kLd + q + s] = make_double2(a[r][0].x - a[r][1].x, a[r][0].y - a[r][1].y);
-            }
-        }
-        __syncthreads();
+        if (!SINK) __syncthreads();
     }
 }
 
@@ -215,7 +251,7 @@ __global__ void __launch_bounds__(256) k_mm_cols(const double* __restrict__ recs
                                                  const double2* __restrict__ twg, double2* __restrict__ Y,
                                                  double* __restrict__ ab, int n1, int cols) {
     constexpr int kLd = LEN + 1;
-    __shared__ double2 buf[kLdsPts + kLdsPts / LEN];
+    __shared__ double2 buf[kColPts + kColPts / LEN];
     __shared__ double2 tw[LEN];
     __shared__ double red[2][4];
     const int64_t N = g.nb;
@@ -264,15 +300,15 @@ __global__ void __launch_bounds__(256) k_mm_cols(const double* __restrict__ recs
         o[0] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
         o[1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
     }
-    lds_idft<LEN>(buf, cols, tw);
+    // the last stage's outputs go straight to the transposed store, times exp(2 pi i j2 k1 / N)
     double2* __restrict__ dst = Y + p * N;
     const unsigned mask = static_cast<unsigned>(N - 1);
-    for (int idx = threadIdx.x; idx < cols * LEN; idx += 256) {
-        const int c = idx % cols, j2 = idx / cols;
-        const int k1 = gcol + c;
-        const double2 v = cmul(buf[c * kLd + j2], twiddle(twg, (static_cast<unsigned>(j2) * k1) & mask));
-        dst[static_cast<int64_t>(j2) * n1 + k1] = v;
-    }
+    lds_idft_io<LEN, kColPts, false, true, true>(
+        buf, cols, tw, [](int, int) { return make_double2(0.0, 0.0); },
+        [&](int c, int j2, double2 v) {
+            const int k1 = gcol + c;
+            dst[static_cast<int64_t>(j2) * n1 + k1] = cmul(v, twiddle(twg, (static_cast<unsigned>(j2) * k1) & mask));
+        });
 }
 
 // ---- 2. row pass with fused arg-max of |z|^2 ------------------------------------------
@@ -285,48 +321,51 @@ __device__ __forceinline__ bool better(double v, int i, double bv, int bi) {
 template <int LEN>
 __global__ void __launch_bounds__(256) k_mm_rows_max(const double2* __restrict__ Y, double* __restrict__ mx,
                                                      int n2, int rows) {
-    constexpr int kLd = LEN + 1;
-    __shared__ double2 buf[kLdsPts + kLdsPts / LEN];
+    __shared__ double2 buf[kRowPts + kRowPts / LEN];
     __shared__ double2 tw[LEN];
     __shared__ double rv[4];
     __shared__ int ri[4];
+    __shared__ double2 rz[4];
     const int64_t N = static_cast<int64_t>(n2) * LEN;
     const int groups = n2 / rows;
     const int64_t p = blockIdx.x / groups;
     const int grow = (blockIdx.x % groups) * rows;
     fill_twiddles<LEN>(tw);
     const double2* __restrict__ src = Y + p * N + static_cast<int64_t>(grow) * LEN;
-    for (int idx = threadIdx.x; idx < rows * LEN; idx += 256) {
-        const int rrow = idx / LEN, k1 = idx % LEN;
-        buf[rrow * kLd + k1] = src[idx];
-    }
-    __syncthreads();
-    lds_idft<LEN>(buf, rows, tw);
+    __syncthreads();   // twiddles
+    // the first stage reads the rows from global memory; the last stage's outputs feed the
+    // arg-max of |z|^2 (ties to the smaller lag) in registers
     double best = -1.0;
     int bidx = 0x7fffffff;
-    for (int idx = threadIdx.x; idx < rows * LEN; idx += 256) {
-        const int rrow = idx / LEN, j1 = idx % LEN;
-        const double2 z = buf[rrow * kLd + j1];
-        const double a2 = z.x * z.x + z.y * z.y;
-        const int j = (grow + rrow) + n2 * j1;
-        if (better(a2, j, best, bidx)) {
-            best = a2;
-            bidx = j;
-        }
-    }
+    double2 bz = make_double2(0.0, 0.0);
+    lds_idft_io<LEN, kRowPts, true, true, false>(
+        buf, rows, tw, [&](int rrow, int k1) { return src[rrow * LEN + k1]; },
+        [&](int rrow, int j1, double2 z) {
+            const double a2 = z.x * z.x + z.y * z.y;
+            const int j = (grow + rrow) + n2 * j1;
+            if (better(a2, j, best, bidx)) {
+                best = a2;
+                bidx = j;
+                bz = z;
+            }
+        });
     // arg-max over the wave by lane exchanges, then over the block's four waves
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const double ov = __shfl_xor(best, off, 64);
         const int oi = __shfl_xor(bidx, off, 64);
+        const double ozx = __shfl_xor(bz.x, off, 64);
+        const double ozy = __shfl_xor(bz.y, off, 64);
         if (better(ov, oi, best, bidx)) {
             best = ov;
             bidx = oi;
+            bz = make_double2(ozx, ozy);
         }
     }
     if ((threadIdx.x & 63) == 0) {
         rv[threadIdx.x >> 6] = best;
         ri[threadIdx.x >> 6] = bidx;
+        rz[threadIdx.x >> 6] = bz;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -334,13 +373,12 @@ __global__ void __launch_bounds__(256) k_mm_rows_max(const double2* __restrict__
             if (better(rv[w], ri[w], rv[0], ri[0])) {
                 rv[0] = rv[w];
                 ri[0] = ri[w];
+                rz[0] = rz[w];
             }
         // no comparable |z|^2 (all NaN): report lag 0 with a NaN modulus
         const bool none = ri[0] == 0x7fffffff;
         const int j = none ? grow : ri[0];
-        const int r = j % n2 - grow, j1 = j / n2;
-        double2 z = buf[r * kLd + j1];
-        if (none) z = make_double2(__builtin_nan(""), __builtin_nan(""));
+        const double2 z = none ? make_double2(__builtin_nan(""), __builtin_nan("")) : rz[0];
         double* o = mx + (p * groups + (blockIdx.x % groups)) * 4;
         o[0] = none ? __builtin_nan("") : rv[0];
         o[1] = static_cast<double>(j);
