@@ -451,7 +451,8 @@ struct AdjSegment {
     GridArgs g;
     const double2* __restrict__ tgt;
     const double* __restrict__ inv_psd;
-    const double2* __restrict__ tw;
+    const double2* __restrict__ tw;    // twiddle tables in LDS
+    const double2* __restrict__ sct;   // (sin, cos) table in LDS
     double ur, ui, inv_sab, cfa;
     int64_t j;
     int64_t k0, k1;
@@ -460,6 +461,15 @@ struct AdjSegment {
 
     template <int PR, int AR>
     __device__ __forceinline__ void run() {
+        if constexpr (PR == 3)
+            run_with<PR, AR>(rec_mrd(rec));
+        else
+            run_with<PR, AR>(rec);
+    }
+
+    template <int PR, int AR, class RC>
+    __device__ __forceinline__ void run_with(RC c) {
+        constexpr bool D = IsRecMRD<RC>::value;
         const double ms = rec[R_MS];
         const double a0p = rec[R_A0P];
         const double w4 = 4.0 * g.df;
@@ -467,14 +477,14 @@ struct AdjSegment {
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
         ExpRec er{};
-        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane));
+        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane), D ? rec[R_AM3 + 0] : 1.0);
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
-            eval_bin_t<PR, AR, AR == 3>(rec, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
+            eval_bin_t<PR, AR, AR == 3>(c, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
             const double Aamp = a0p * T.at(T_F76, k) * bv.ahat;
             double sn, cs;
-            pd_sincos(bv.psi, &sn, &cs);
+            pd_sincos(bv.psi, &sn, &cs, sct);
             const double hr = Aamp * cs, hi = -Aamp * sn;
             const double w = w4 * inv_psd[k];
             const double2 t = tgt[k];
@@ -488,8 +498,9 @@ struct AdjSegment {
             // conj(h) R: weight of d ln A is Re, weight of d Psi is -Im
             const double cr = hr * rr + hi * ri, ci = hr * ri - hi * rr;
             MMVis vis{mom, cr, -ci};
-            visit_bin_t<PR, AR>(rec, bv, vis);
+            visit_bin_t<PR, AR>(c, bv, vis);
         }
+        if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
         flush_touched<PR, AR>(mom, lane, tot);
     }
 };
@@ -501,6 +512,12 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
                                                     const double* __restrict__ inv_psd,
                                                     const double2* __restrict__ tw,
                                                     const double* __restrict__ scal, double* __restrict__ part_all) {
+    // the (sin, cos) and twiddle tables every bin reads, staged in LDS by the whole block first
+    __shared__ double2 sct[kSinCosN];
+    __shared__ double2 twl[2 * kTw];
+    stage_sincos_table(sct);
+    for (int i = threadIdx.x; i < 2 * kTw; i += blockDim.x) twl[i] = tw[i];
+    __syncthreads();
     double* __restrict__ part = part_all + static_cast<int64_t>(PRG - 1) * nt * chunks * kNSlot;
     const int lane = threadIdx.x & 63;
     const int cr = region_chunks(PRG, chunks);
@@ -522,7 +539,8 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     seg.g = g;
     seg.tgt = reinterpret_cast<const double2*>(targets) + p * g.nb;
     seg.inv_psd = inv_psd;
-    seg.tw = tw;
+    seg.tw = twl;
+    seg.sct = sct;
     // unit phase u = z / |z|; G_k = conj(u) x_k with x_k = w t_k exp(2 pi i k j / N)
     seg.ur = sc[3] / az;
     seg.ui = sc[4] / az;
