@@ -127,7 +127,7 @@ int pd_loglike_and_grad(const double* theta, int64_t n, int param, const pd_grid
  * without the workspace; every launch is enqueued on `stream` (no side streams).
  * The call allocates nothing (no hipMalloc, hipFree, stream or event creation).  A batch whose
  * pd_loglike_and_grad workspace (pd_workspace_bytes) exceeds the array, e.g. more than about
- * 16 000 points on a 16 225-bin grid (4096 points x 8033 bins need 38 MB), returns
+ * 20 700 points on a 16 225-bin grid (4096 points x 8033 bins need 16.8 MB), returns
  * PD_EUNSUPPORTED and launches nothing.  All calls on one GPU share that GPU's array: calls
  * that overlap on one GPU (other streams, other host threads) race and must be serialised by
  * the caller.  Nothing in the array needs to be cleared between calls. */
