@@ -46,6 +46,9 @@ def timed_calls(fn, iters, warmup):
 
 COUNTERS_C2 = os.path.join(ROOT, "profiles", "k_loglike_moments_c2_counters.txt")
 COUNTERS_C4 = os.path.join(ROOT, "profiles", "k_mm_c4_counters.txt")
+COUNTERS_C1 = os.path.join(ROOT, "profiles", "k_waveform_c1_counters.txt")
+COUNTERS_C3 = os.path.join(ROOT, "profiles", "k_fisher_c3_counters.txt")
+COUNTERS_OV = os.path.join(ROOT, "profiles", "k_ov_gemm_overlap_counters.txt")
 
 
 def kernel_avg_ms(api, kid):
@@ -64,6 +67,9 @@ def main():
                     help="only time dense-metric HMC transitions at the sampler size (4096 chains x 8033 bins)")
     ap.add_argument("--only-c4", action="store_true",
                     help="only run the C4 mismatch pass (one warm-up and one timed call; for counter runs)")
+    ap.add_argument("--only", choices=("c1", "c3", "overlap"),
+                    help="only run one call of the C1 strain, C3 Fisher or overlap-bank workload after one "
+                         "warm-up (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one plain 1 GiB device-to-device copy (the reference for HBM counters)")
     args = ap.parse_args()
@@ -89,7 +95,7 @@ def main():
     # the CPU oracle baseline runs first: its process pool is forked before this process touches
     # the GPU
     cpu = None
-    if not args.no_cpu and not args.only_c4 and not args.only_hmc:
+    if not args.no_cpu and not args.only_c4 and not args.only_hmc and not args.only:
         log("[bench] CPU oracle baseline")
         cpu = cpu_baseline(W, W.config2())
         log(f"[bench] CPU oracle: {cpu['value_single_process']:.1f} evals/s on one process, "
@@ -103,6 +109,10 @@ def main():
         return
     if args.only_hmc:
         print(json.dumps(hmc_step_timing(W)), flush=True)
+        return
+    if args.only:
+        fn = {"c1": c1_waveform, "c3": c3_fisher, "overlap": overlap_bank}[args.only]
+        print(json.dumps(fn(api, flops, W, L, lam, api.Workspace(), P, 1)), flush=True)
         return
 
     # ---------------- main workload: fused lnL + gradient, 65536 x 16225 ----------------
@@ -241,17 +251,9 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     del thf, ipf, wsf
 
     # strain output, C1: 1024 x 4017 complex128
+    extra["C1_waveform"] = c1_waveform(api, flops, W, L, lam, ws, P, iters)
     c1 = W.config1()
     th1 = torch.as_tensor(c1["theta"], device=dev)
-    api.profile_read(L.PD_K_WAVEFORM)
-    t = timed_calls(lambda: api.waveform_eval(th1, P, c1["grid"], lam, ws=ws), iters, 1)
-    kms, _ = kernel_avg_ms(api, L.PD_K_WAVEFORM)
-    trans1 = api.transition_frequencies(th1, P, c1["grid"], lam, ws=ws).cpu().numpy()
-    fl, _ = flops.batch_flops("waveform", trans1, c1["grid"].as_tuple())
-    nbytes = th1.shape[0] * c1["grid"].n_bins * 16
-    extra["C1_waveform"] = {"waveforms_per_s": th1.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
-                            "hbm_write_GBs": nbytes / (kms * 1e-3) / 1e9,
-                            "tflops_algorithmic": fl / (kms * 1e-3) / 1e12}
 
     # the paper's timing grid (24-512 Hz, df = 0.2 Hz, 2441 bins), same 1024 sources
     gp = W.paper_timing_grid()
@@ -278,17 +280,7 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     torch.cuda.empty_cache()
 
     # Fisher matrices, C3: 16384 x 16065 in (ln Mc, eta, chi1, chi2, ln D, tc, phic)
-    c3 = W.config3()
-    th3 = torch.as_tensor(W.to_param(c3["theta"], api.PARAM_LNMC_ETA_LND), device=dev)
-    ip3 = torch.as_tensor(c3["inv_psd"], device=dev)
-    api.profile_read(L.PD_K_FISHER)
-    t = timed_calls(lambda: api.fisher(th3, api.PARAM_LNMC_ETA_LND, c3["grid"], lam, ip3, ws=ws), 3, 1)
-    kms, _ = kernel_avg_ms(api, L.PD_K_FISHER)
-    trans3 = api.transition_frequencies(th3, api.PARAM_LNMC_ETA_LND, c3["grid"], lam, ws=ws).cpu().numpy()
-    fl, _ = flops.batch_flops("fisher", trans3, c3["grid"].as_tuple())
-    extra["C3_fisher"] = {"fishers_per_s": th3.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
-                          "tflops_algorithmic": fl / (kms * 1e-3) / 1e12}
-    del th3
+    extra["C3_fisher"] = c3_fisher(api, flops, W, L, lam, ws, P, 3)
 
     # mismatch + gradient over the 209 coefficients, C4: 512 targets x 65536
     c4, th4, targets, ip4, ws4, extra["C4_mismatch_grad"] = c4_mismatch(api, flops, W, L, lam, ws, P, 3)
@@ -333,29 +325,9 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
     del fit, curve
     api.profile_enable(False)
 
-    # template-bank overlaps on the FP64 matrix cores: the C2 bank (ordered by total mass)
-    # against 32 seeded noise streams on the 16225-bin grid
-    c2 = W.config2()
-    rows = c2["theta"][np.argsort(c2["theta"][:, 0] + c2["theta"][:, 1])]
-    thb = torch.as_tensor(rows, device=dev)
-    psd2 = W.psd_aligo_zdhp_fit(g2.freqs())
-    streams = torch.as_tensor(np.stack([W.complex_noise(psd2, g2.df, 2000 + s) for s in range(32)]), device=dev)
-    ipb = torch.as_tensor(1.0 / psd2, device=dev)
-    wsb = api.Workspace()
-    api.profile_enable(True)
-    api.profile_read(L.PD_K_OVERLAP)
-    t = timed_calls(lambda: api.overlap(thb, P, g2, lam, streams, ipb, ws=wsb), 5, 1)
-    kms = kernel_avg_ms(api, L.PD_K_OVERLAP)[0]
+    # template-bank overlaps on the FP64 matrix cores
+    extra["overlap_bank_fp64_mfma"] = overlap_bank(api, flops, W, L, lam, ws, P, 5)
     api.profile_enable(False)
-    transb = api.transition_frequencies(thb, P, g2, lam, ws=wsb).cpu().numpy()
-    gen_fl, units_b = flops.batch_flops("waveform", transb, g2.as_tuple())
-    fl = gen_fl + units_b * (8 * 32 + 3)
-    extra["overlap_bank_fp64_mfma"] = {
-        "templates": int(thb.shape[0]), "streams": 32, "n_bins": g2.n_bins,
-        "template_stream_pairs_per_s": thb.shape[0] * 32 / t, "ms": 1e3 * t, "kernel_ms": kms,
-        "active_template_bins": units_b, "flops_per_call": fl,
-        "roofline": {"bound": "mfma", "achieved": round(fl / (kms * 1e-3) / 1e12, 3), "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(fl / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}}
 
     # learned proposal, C5: 4096 chains on one SNR-20 injection, 8033 bins; dense-metric plain HMC
     # as the judge (a long reference run of 512 chains, many autocorrelation times long)
@@ -400,6 +372,82 @@ def run_extras(api, flops, W, L, lam, ws, P, th2, d2, ip2, g2, trans2):
         "note": "autocorrelation times from long runs of chain subsets (bulk ESS of within-chain "
                 "autocorrelation); ESS per second = 4096 chains / tau / time per transition of 4096 chains"}
     return extra
+
+
+def _counted(path, group, label, kms, peak_tflops=None):
+    """Counted HBM bytes and FP64 flops of one call (committed summary, keyed to the kernel sources)
+    over the live kernel time kms, or None when the summary is missing or stale."""
+    from paper_2302_05329_amd import counters
+    cs = counters.read_summary(path, group)
+    if cs is None:
+        return None
+    b = int(cs[f"{label}_hbm_bytes_per_call"])
+    f = int(cs[f"{label}_fp64_flops_per_call"])
+    peak = FP64_PEAK_TFLOPS if peak_tflops is None else peak_tflops
+    return {"hbm_TBs": b / (kms * 1e-3) / 1e12, "hbm_frac": b / (kms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+            "fp64_TFLOPs": f / (kms * 1e-3) / 1e12, "fp64_frac": f / (kms * 1e-3) / (peak * 1e12),
+            "hbm_bytes_per_call": b, "fp64_flops_per_call": f, "summary": os.path.relpath(path, ROOT)}
+
+
+def c1_waveform(api, flops, W, L, lam, ws, P, iters):
+    """C1: 1024 sources x 4017 bins of complex128 strain."""
+    import torch
+    c1 = W.config1()
+    th1 = torch.as_tensor(c1["theta"], device="cuda")
+    api.profile_enable(True)
+    api.profile_read(L.PD_K_WAVEFORM)
+    t = timed_calls(lambda: api.waveform_eval(th1, P, c1["grid"], lam, ws=ws), iters, 1)
+    kms, _ = kernel_avg_ms(api, L.PD_K_WAVEFORM)
+    trans1 = api.transition_frequencies(th1, P, c1["grid"], lam, ws=ws).cpu().numpy()
+    fl, _ = flops.batch_flops("waveform", trans1, c1["grid"].as_tuple())
+    nbytes = th1.shape[0] * c1["grid"].n_bins * 16
+    return {"waveforms_per_s": th1.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
+            "hbm_write_GBs": nbytes / (kms * 1e-3) / 1e9, "tflops_algorithmic": fl / (kms * 1e-3) / 1e12,
+            "counters": _counted(COUNTERS_C1, "loglike", "waveform", kms)}
+
+
+def c3_fisher(api, flops, W, L, lam, ws, P, iters):
+    """C3: 16384 Fisher matrices on 16065 bins, in (ln Mc, eta, chi1, chi2, ln D, tc, phic)."""
+    import torch
+    c3 = W.config3()
+    th3 = torch.as_tensor(W.to_param(c3["theta"], api.PARAM_LNMC_ETA_LND), device="cuda")
+    ip3 = torch.as_tensor(c3["inv_psd"], device="cuda")
+    api.profile_enable(True)
+    api.profile_read(L.PD_K_FISHER)
+    t = timed_calls(lambda: api.fisher(th3, api.PARAM_LNMC_ETA_LND, c3["grid"], lam, ip3, ws=ws), iters, 1)
+    kms, _ = kernel_avg_ms(api, L.PD_K_FISHER)
+    trans3 = api.transition_frequencies(th3, api.PARAM_LNMC_ETA_LND, c3["grid"], lam, ws=ws).cpu().numpy()
+    fl, _ = flops.batch_flops("fisher", trans3, c3["grid"].as_tuple())
+    return {"fishers_per_s": th3.shape[0] / t, "ms": 1e3 * t, "kernel_ms": kms,
+            "tflops_algorithmic": fl / (kms * 1e-3) / 1e12,
+            "counters": _counted(COUNTERS_C3, "loglike", "fisher", kms)}
+
+
+def overlap_bank(api, flops, W, L, lam, ws, P, iters):
+    """Template-bank overlaps on the FP64 matrix cores: the C2 bank (ordered by total mass) against
+    32 seeded noise streams on the 16225-bin grid."""
+    import torch
+    c2 = W.config2()
+    g2 = c2["grid"]
+    rows = c2["theta"][np.argsort(c2["theta"][:, 0] + c2["theta"][:, 1])]
+    thb = torch.as_tensor(rows, device="cuda")
+    psd2 = W.psd_aligo_zdhp_fit(g2.freqs())
+    streams = torch.as_tensor(np.stack([W.complex_noise(psd2, g2.df, 2000 + s) for s in range(32)]), device="cuda")
+    ipb = torch.as_tensor(1.0 / psd2, device="cuda")
+    wsb = api.Workspace()
+    api.profile_enable(True)
+    api.profile_read(L.PD_K_OVERLAP)
+    t = timed_calls(lambda: api.overlap(thb, P, g2, lam, streams, ipb, ws=wsb), iters, 1)
+    kms = kernel_avg_ms(api, L.PD_K_OVERLAP)[0]
+    transb = api.transition_frequencies(thb, P, g2, lam, ws=wsb).cpu().numpy()
+    gen_fl, units_b = flops.batch_flops("waveform", transb, g2.as_tuple())
+    fl = gen_fl + units_b * (8 * 32 + 3)
+    return {"templates": int(thb.shape[0]), "streams": 32, "n_bins": g2.n_bins,
+            "template_stream_pairs_per_s": thb.shape[0] * 32 / t, "ms": 1e3 * t, "kernel_ms": kms,
+            "active_template_bins": units_b, "flops_per_call": fl,
+            "roofline": {"bound": "mfma", "achieved": round(fl / (kms * 1e-3) / 1e12, 3), "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(fl / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)},
+            "counters": _counted(COUNTERS_OV, "overlap", "gemm", kms)}
 
 
 def c4_mismatch(api, flops, W, L, lam, ws, P, iters):

@@ -6,7 +6,8 @@ A summary is a short text file: a header with the commands that produced it, one
 call), then `key: value` lines that the benchmark reads:
 
     source_sha256: <hash of the sources the kernels are built from>
-    <kernels label>_fp64_flops_per_call: N    (64 x (ADD + MUL + TRANS + 2 FMA) F64 instructions)
+    <kernels label>_fp64_flops_per_call: N    (64 x (ADD + MUL + TRANS + 2 FMA) F64 instructions,
+                                               plus 512 x SQ_INSTS_VALU_MFMA_MOPS_F64 when counted)
     <kernels label>_hbm_bytes_per_call: N     (calibrated FETCH_SIZE + WRITE_SIZE)
 
     python -m paper_2302_05329_amd.counters --title T --trace DIR [--fp64 DIR] [--fetch DIR
@@ -31,6 +32,7 @@ GROUPS = {
     "loglike": ["pd_kernels.hip", "pd_bin.h", "pd_math.h", "pd_model.h", "pd_dual.h", "pd_launch.h"],
     "mismatch": ["pd_mismatch.hip", "pd_mismatch.h", "pd_bin.h", "pd_math.h", "pd_model.h", "pd_dual.h",
                  "pd_launch.h"],
+    "overlap": ["pd_overlap.hip", "pd_bin.h", "pd_math.h", "pd_model.h", "pd_dual.h", "pd_launch.h"],
 }
 COPY_BYTES = 1 << 30
 F64 = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64")
@@ -162,6 +164,8 @@ def main():
                 c = f64[k]
                 fl = 64 * (c["SQ_INSTS_VALU_ADD_F64"] + c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_TRANS_F64"]
                            + 2 * c["SQ_INSTS_VALU_FMA_F64"])
+                # FP64 matrix-core work, when counted: the counter is in units of 512 flops
+                fl += 512 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
             gbs = b / ns if b is not None and ns == ns else float("nan")
             tfs = fl / ns / 1e3 if fl is not None and ns == ns else float("nan")
             out.append(f"{k[:44]:<44} {calls:>6} {ns / 1e3:>9.2f} {(b or 0):>12.0f} {gbs:>8.1f} {(fl or 0):>14.0f} "

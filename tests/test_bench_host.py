@@ -40,6 +40,11 @@ def test_committed_summaries_match_the_current_kernels():
     assert kv is not None, "C4 counter summary is stale"
     for key in ("columns_hbm_bytes_per_call", "rows_hbm_bytes_per_call", "adjoint_fp64_flops_per_call"):
         assert int(kv[key]) > 0
+    for path, group, label in ((bench.COUNTERS_C1, "loglike", "waveform"), (bench.COUNTERS_C3, "loglike", "fisher"),
+                               (bench.COUNTERS_OV, "overlap", "gemm")):
+        kv = counters.read_summary(path, group)
+        assert kv is not None, f"{os.path.basename(path)} is stale"
+        assert int(kv[f"{label}_fp64_flops_per_call"]) > 0 and int(kv[f"{label}_hbm_bytes_per_call"]) > 0
 
 
 def test_counter_summary_from_synthetic_profiler_output(tmp_path, monkeypatch):
