@@ -49,7 +49,8 @@ struct Tabs {
 // the same bin for many parameter points loads them once.
 struct BinTabs {
     double cb, icb, lf, f34, inf;
-    __device__ __forceinline__ void load(const Tabs& T, int64_t k) {
+    template <class KI>
+    __device__ __forceinline__ void load(const Tabs& T, KI k) {
         cb = T.at(T_CB, k);
         icb = T.at(T_ICB, k);
         lf = T.at(T_LF, k);

@@ -160,40 +160,49 @@ __global__ void __launch_bounds__(64) k_setup_fit_tangent(const double* __restri
 // per-grid tables
 // ==================================================================================
 
+// Four threads per bin, one per transcendental (cbrt; log; f^(3/4); f^(-7/6) with the weighted
+// data): the table launch is a few waves per SIMD, so its time is one thread's chain of calls,
+// which this cuts to one call.
 __global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __restrict__ data,
                                                 const double* __restrict__ inv_psd, double* __restrict__ tab) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t k = t >> 2;
+    const int part = static_cast<int>(t & 3);
     if (k >= g.nb) return;
     const double f = bin_freq(g, k);
-    double cb = 0.0, icb = 0.0, lf = 0.0, f34 = 0.0, inf = 0.0, f76 = 0.0;
-    if (f > 0.0) {
-        cb = cbrt(f);
-        icb = 1.0 / cb;
-        lf = log(f);
-        f34 = pow(f, 0.75);
-        inf = 1.0 / f;
-        f76 = pow(f, -7.0 / 6.0);
-    }
+    const bool pos = f > 0.0;
     const int64_t nb = g.nb;
-    tab[T_CB * nb + k] = cb;
-    tab[T_ICB * nb + k] = icb;
-    tab[T_LF * nb + k] = lf;
-    tab[T_F34 * nb + k] = f34;
-    tab[T_INF * nb + k] = inf;
-    tab[T_F76 * nb + k] = f76;
-    double dwr = 0.0, dwi = 0.0, ww = 0.0;
-    if (inv_psd) {
-        const double w = 4.0 * g.df * inv_psd[k];
-        ww = w * f76 * f76;
-        if (data) {
-            const double2 d = reinterpret_cast<const double2*>(data)[k];
-            dwr = w * f76 * d.x;
-            dwi = w * f76 * d.y;
+    if (part == 0) {
+        double cb = 0.0, icb = 0.0, inf = 0.0;
+        if (pos) {
+            cb = cbrt(f);
+            icb = 1.0 / cb;
+            inf = 1.0 / f;
         }
+        tab[T_CB * nb + k] = cb;
+        tab[T_ICB * nb + k] = icb;
+        tab[T_INF * nb + k] = inf;
+    } else if (part == 1) {
+        tab[T_LF * nb + k] = pos ? log(f) : 0.0;
+    } else if (part == 2) {
+        tab[T_F34 * nb + k] = pos ? pow(f, 0.75) : 0.0;
+    } else {
+        const double f76 = pos ? pow(f, -7.0 / 6.0) : 0.0;
+        tab[T_F76 * nb + k] = f76;
+        double dwr = 0.0, dwi = 0.0, ww = 0.0;
+        if (inv_psd) {
+            const double w = 4.0 * g.df * inv_psd[k];
+            ww = w * f76 * f76;
+            if (data) {
+                const double2 d = reinterpret_cast<const double2*>(data)[k];
+                dwr = w * f76 * d.x;
+                dwi = w * f76 * d.y;
+            }
+        }
+        tab[T_DWR * nb + k] = dwr;
+        tab[T_DWI * nb + k] = dwi;
+        tab[T_WW * nb + k] = ww;
     }
-    tab[T_DWR * nb + k] = dwr;
-    tab[T_DWI * nb + k] = dwi;
-    tab[T_WW * nb + k] = ww;
 }
 
 // ==================================================================================
@@ -284,19 +293,49 @@ struct LnlSegment {
         ExpRec er{};
         if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane), D ? rec[R_AM3 + 0] : 1.0);
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
+            // merger-ringdown: every grid-table value of the bin is loaded here, before the
+            // branches of the elementary functions, so all loads share one 32-bit offset from
+            // scalar bases (the entries the region does not use are never loaded); the other
+            // loops keep their loads at the uses (preloading the inspiral's six values spills)
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
-            eval_bin_t<PR, AR, AR == 3>(c, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
-            double sn, cs;
-            pd_sincos(bv.psi, &sn, &cs, sct);
-            const double hr = bv.ahat * cs, hi = -bv.ahat * sn;
-            const double dwr = T.at(T_DWR, k), dwi = T.at(T_DWI, k);
-            const double px = fma(dwr, hr, dwi * hi);
-            const double q = T.at(T_WW, k) * bv.ahat * bv.ahat;
+            double dwr, dwi, ww;
+            if constexpr (PR == 3) {
+                dwr = T.at(T_DWR, k);
+                dwi = T.at(T_DWI, k);
+                ww = T.at(T_WW, k);
+                BinTabs bt;
+                bt.load(T, k);
+                eval_bin_t<PR, AR, AR == 3>(c, bt, k, mf, bv, (AR == 3) ? er.next() : 0.0);
+            } else {
+                eval_bin_t<PR, AR, AR == 3>(c, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
+            }
+            // px = Re(conj(d) h), py = Im(conj(d) h) with h = Ahat exp(-i Psi) (weights folded in);
+            // the inspiral loop forms sin and cos first and loads the data after them (the fused
+            // rotation, or the data loaded earlier, spills there)
+            double px, py, hr = 0.0, hi = 0.0;
+            if constexpr (PR == 2) {
+                dwr = T.at(T_DWR, k);
+                dwi = T.at(T_DWI, k);
+                ww = T.at(T_WW, k);
+            }
+            if constexpr (PR != 1) {
+                pd_rotate_data(bv.psi, bv.ahat, dwr, dwi, sct, px, py);
+            } else {
+                double sn, cs;
+                pd_sincos(bv.psi, &sn, &cs, sct);
+                hr = bv.ahat * cs;
+                hi = -bv.ahat * sn;
+                dwr = T.at(T_DWR, k);
+                dwi = T.at(T_DWI, k);
+                ww = T.at(T_WW, k);
+                px = fma(dwr, hr, dwi * hi);
+            }
+            const double q = ww * bv.ahat * bv.ahat;
             dh += px;
             hh += q;
             if (MODE == 1) {
-                const double py = fma(dwr, hi, -dwi * hr);
+                if constexpr (PR == 1) py = fma(dwr, hi, -dwi * hr);
                 MomVis vis{mom, fma(-a0p, q, px), py};
                 visit_bin_t<PR, AR>(c, bv, vis);
             }
@@ -331,8 +370,10 @@ __device__ __forceinline__ void moments_wave(int64_t wave, const double* __restr
     double* __restrict__ partial = partial_all + grad_group_offset<MODE>(PRG, n, chunks);
     const int lane = threadIdx.x & 63;
     const int cr = region_chunks(PRG, chunks);
-    const int64_t pi = wave / cr;
-    const int c = static_cast<int>(wave - pi * cr);
+    // the wave's point and chunk are wave-uniform: kept in scalar registers, so the record pointer
+    // (and every record entry read through it) stays scalar inside the bin loops
+    const int64_t pi = uniform_i(wave / cr);
+    const int c = uniform_i(wave - pi * cr);
     if (pi >= n) return;
     // waves visit the points in order of decreasing work (see k_order_scatter), or in index order
     const int64_t p = perm ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
@@ -859,7 +900,7 @@ hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, d
 
 hipError_t launch_tables(const GridArgs& g, const double* data, const double* inv_psd, double* tab,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_tables, dim3(blocks_for(g.nb, 256)), dim3(256), 0, s, g, data, inv_psd, tab);
+    hipLaunchKernelGGL(k_tables, dim3(blocks_for(4 * g.nb, 256)), dim3(256), 0, s, g, data, inv_psd, tab);
     return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@
 // correctly rounded values (fit_elementary.py, next to this file, writes both); the
 // measured worst error of each function is about 1 ulp.
 //
-//   pd_sincos  |x| <= 2^24: q = rint(256x/pi), r = x - q pi/256 (three-part pi/256), short
+//   pd_sincos  |x| <= 2^24: q = rint(256x/pi), r = x - q pi/256 (two-part pi/256), short
 //              polynomials on |r| <= pi/512 combined with a 512-entry (sin, cos) table.
 //              Larger |x| falls back to the device library's sincos.
 //   pd_atan    |u| > 1 uses pi/2 - atan(1/u); t > tan(pi/12) uses atan(t) = pi/6 +
@@ -29,12 +29,15 @@ __device__ __forceinline__ double sk(double c) {
     return c;
 }
 
-// Table-driven sin and cos of one argument: x = q pi/256 + r with |r| <= pi/512 (three-part
+// Table-driven sin and cos of one argument: x = q pi/256 + r with |r| <= pi/512 (two-part
 // pi/256, fused multiply-adds), j = q mod 512, and
 //   sin x = S_j + (S_j (cos r - 1) + C_j sin r),  cos x = C_j + (C_j (cos r - 1) - S_j sin r)
 // with (S_j, C_j) = (sin, cos)(j pi/256) correctly rounded (pd_sincos_table.h) and Taylor
 // polynomials on the small interval (sin r through r^5, cos r - 1 through r^6; the first omitted
 // terms are below 1.1e-17 and 2e-22 relative).  About 1 ulp.  |x| > 2^24 uses the device library.
+// Two parts of pi/256 suffice: the first is pi/256 rounded to double and the second the rounded
+// remainder, so the part left out is below 1.2e-35 and |q| <= 2^24 * 256/pi < 1.4e9 puts at most
+// 1.7e-26 into r, where an ulp of r (|r| <= pi/512) is about 8.7e-19.
 constexpr double kTs1 = -1.0 / 6.0, kTs2 = 1.0 / 120.0;
 constexpr double kTc1 = -0.5, kTc2 = 1.0 / 24.0, kTc3 = -1.0 / 720.0;
 
@@ -44,27 +47,62 @@ constexpr double kTc1 = -0.5, kTc2 = 1.0 / 24.0, kTc3 = -1.0 / 720.0;
 // so the table index is a bit mask of the low word; |x| <= 2^24 keeps it far inside 2^51.
 constexpr double kRoundShift = 6755399441055744.0;   // 1.5 * 2^52
 
+// The pieces of the table construction for |x| <= 2^24: the table entry (S, C) and the small-angle
+// values sr = sin r and cm = cos r - 1.  Callers that rotate a complex number by the angle combine
+// them with it directly (one multiply-add per piece) instead of forming sin x and cos x first.
+struct SinCosParts {
+    double s, c, sr, cm;
+};
+
+__device__ __forceinline__ SinCosParts pd_sincos_parts(double x, const double2* __restrict__ tab) {
+    const double qs = fma(x, sk(kInvPiStep), sk(kRoundShift));
+    const double q = qs - sk(kRoundShift);
+    double r = fma(-q, sk(kPiStep_1), x);
+    r = fma(-q, sk(kPiStep_2), r);
+    const unsigned j = static_cast<unsigned>(__builtin_bit_cast(unsigned long long, qs)) &
+                       static_cast<unsigned>(kSinCosN - 1);
+    const double2 sc = tab[j];
+    const double z = r * r;
+    SinCosParts p;
+    p.s = sc.x;
+    p.c = sc.y;
+    p.sr = fma(r * z, fma(sk(kTs2), z, sk(kTs1)), r);
+    double pc = fma(sk(kTc3), z, sk(kTc2));
+    pc = fma(pc, z, sk(kTc1));
+    p.cm = z * pc;
+    return p;
+}
+
 __device__ __forceinline__ void pd_sincos(double x, double* s_out, double* c_out,
                                           const double2* __restrict__ tab = reinterpret_cast<const double2*>(kSinCosTab)) {
     if (!(fabs(x) <= sk(16777216.0))) {
         sincos(x, s_out, c_out);
         return;
     }
-    const double qs = fma(x, sk(kInvPiStep), sk(kRoundShift));
-    const double q = qs - sk(kRoundShift);
-    double r = fma(-q, sk(kPiStep_1), x);
-    r = fma(-q, sk(kPiStep_2), r);
-    r = fma(-q, sk(kPiStep_3), r);
-    const unsigned j = static_cast<unsigned>(__builtin_bit_cast(unsigned long long, qs)) &
-                       static_cast<unsigned>(kSinCosN - 1);
-    const double2 sc = tab[j];
-    const double z = r * r;
-    const double sr = fma(r * z, fma(sk(kTs2), z, sk(kTs1)), r);
-    double pc = fma(sk(kTc3), z, sk(kTc2));
-    pc = fma(pc, z, sk(kTc1));
-    const double cm = z * pc;
-    *s_out = sc.x + fma(sc.y, sr, sc.x * cm);
-    *c_out = sc.y + fma(-sc.x, sr, sc.y * cm);
+    const SinCosParts p = pd_sincos_parts(x, tab);
+    *s_out = p.s + fma(p.c, p.sr, p.s * p.cm);
+    *c_out = p.c + fma(-p.s, p.sr, p.c * p.cm);
+}
+
+// A exp(-i x) multiplied by conj(D), D = dr + i di: returns Re and Im of conj(D) A exp(-i x)
+// negated in the imaginary part as the likelihood loops use them,
+//   px = A (dr cos x - di sin x),  py = -A (dr sin x + di cos x).
+// With P + iQ = D (C + i S) (the data rotated by the table angle) and exp(i r) = 1 + cm + i sr:
+//   dr cos x - di sin x = P (1 + cm) - Q sr,  dr sin x + di cos x = Q (1 + cm) + P sr.
+__device__ __forceinline__ void pd_rotate_data(double x, double a, double dr, double di,
+                                               const double2* __restrict__ tab, double& px, double& py) {
+    SinCosParts p;
+    if (!(fabs(x) <= sk(16777216.0))) {
+        sincos(x, &p.s, &p.c);   // the whole angle from the library: r = 0
+        p.sr = 0.0;
+        p.cm = 0.0;
+    } else {
+        p = pd_sincos_parts(x, tab);
+    }
+    const double P = fma(dr, p.c, -di * p.s);
+    const double Q = fma(dr, p.s, di * p.c);
+    px = a * fma(P, p.cm, fma(-Q, p.sr, P));
+    py = -a * fma(Q, p.cm, fma(P, p.sr, Q));
 }
 
 // Copy of the (sin, cos) table in LDS, filled cooperatively by a block.
@@ -106,7 +144,8 @@ constexpr double kPi2_hi = 1.5707963267948966, kPi2_lo = 6.123233995736766e-17;
 // possibly sharing a reciprocal with other divisions) and returns atan(u).
 struct AtanParts {
     double num, den;
-    bool hi, inv, neg;
+    double u;   // the argument: its sign is copied onto atan(|u|) (one bit-field insert)
+    bool hi, inv;
 };
 
 __device__ __forceinline__ AtanParts pd_atan_reduce(double u) {
@@ -118,7 +157,7 @@ __device__ __forceinline__ AtanParts pd_atan_reduce(double u) {
     p.hi = num > sk(kTanPi12) * den;
     p.num = p.hi ? fma(sk(kSqrt3), num, -den) : num;
     p.den = p.hi ? fma(sk(kSqrt3), den, num) : den;
-    p.neg = u < 0.0;
+    p.u = u;
     return p;
 }
 
@@ -137,7 +176,7 @@ __device__ __forceinline__ double pd_atan_finish(const AtanParts& p, double t) {
     double r = fma(t * z, q, t);
     if (p.hi) r = (r + sk(kPi6_lo)) + sk(kPi6_hi);
     if (p.inv) r = (sk(kPi2_hi) - r) + sk(kPi2_lo);
-    return p.neg ? -r : r;
+    return copysign(r, p.u);   // r >= 0 here
 }
 
 __device__ __forceinline__ double pd_atan(double u) {
