@@ -435,11 +435,22 @@ int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, 
 
 /* Diagnostic: the kernels' own FP64 elementary functions applied elementwise, out[i] = fn(x[i])
  * for x [n], out [n] (device).  fn: PD_FN_SIN, PD_FN_COS (one shared argument reduction by
- * pi/256 with a three-part split, then a 512-entry (sin, cos) table and short polynomials;
- * |x| > 2^24 falls back to the device library), PD_FN_ATAN, PD_FN_EXP, PD_FN_RCP (hardware
- * estimate + two Newton steps).  Exposed so that their ulp error can be measured against a
- * high-precision reference. */
-typedef enum { PD_FN_SIN = 0, PD_FN_COS = 1, PD_FN_ATAN = 2, PD_FN_EXP = 3, PD_FN_RCP = 4 } pd_fn;
+ * pi/256 with a two-part split, then a 512-entry (sin, cos) table and short polynomials;
+ * |x| > 2^24 falls back to the device library), PD_FN_ATAN (two-level reduction: 1/u above 1,
+ * then pi/6 above tan(pi/12), and an 11-term polynomial), PD_FN_ATAN_TABLE (the form the fused
+ * likelihood's merger-ringdown loop uses: atan c + atan((|u| - c)/(1 + |u| c)) with c from a
+ * 321-entry table indexed by the exponent and top mantissa bits of |u|, and a 4-term
+ * polynomial), PD_FN_EXP, PD_FN_RCP (hardware estimate + two Newton steps).  Exposed so that
+ * their ulp error can be measured against a high-precision reference.  Unknown fn:
+ * PD_EINVAL. */
+typedef enum {
+    PD_FN_SIN = 0,
+    PD_FN_COS = 1,
+    PD_FN_ATAN = 2,
+    PD_FN_EXP = 3,
+    PD_FN_RCP = 4,
+    PD_FN_ATAN_TABLE = 5
+} pd_fn;
 int pd_elementary_eval(int fn, const double* x, int64_t n, double* out, void* stream);
 
 /* Text of the last batch-level error on the calling thread (library-owned, never NULL). */

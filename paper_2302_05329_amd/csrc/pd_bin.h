@@ -17,6 +17,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pd_math.h"
 #include "pd_model.h"
 
@@ -174,6 +176,7 @@ __device__ __forceinline__ void load_segments(const int* __restrict__ src, Segs&
 // numerator R_AM3 is folded into the exponential recurrence by the caller.
 struct RecMRD {
     const double* __restrict__ p;
+    const double2* __restrict__ atab;   // arc tangent table (c_j, atan c_j), staged in LDS
     double q_id;   // R_PH3+5 * R_ID: u = Mf R_ID - q_id
     double g2;     // R_AM3+2 ^ 2
     double c4id;   // R_PH3+4 * R_ID
@@ -199,9 +202,10 @@ __device__ __forceinline__ double uniform_d(double x) {
     return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
-__device__ __forceinline__ RecMRD rec_mrd(const double* __restrict__ c) {
+__device__ __forceinline__ RecMRD rec_mrd(const double* __restrict__ c, const double2* __restrict__ atab) {
     RecMRD r;
     r.p = c;
+    r.atab = atab;
     r.q_id = uniform_d(c[R_PH3 + 5] * c[R_ID]);
     r.g2 = uniform_d(c[R_AM3 + 2] * c[R_AM3 + 2]);
     r.c4id = uniform_d(c[R_PH3 + 4] * c[R_ID]);
@@ -264,7 +268,14 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
             u = fma(mf, c[R_ID], -c.q_id);
         else
             u = (mf - c[R_PH3 + 5]) * c[R_ID];
-        AtanParts ap = pd_atan_reduce(u);
+        // the fused likelihood's record carries an LDS arc tangent table: the table reduction
+        // (no branches, a shorter polynomial); the other callers keep the two-level reduction
+        using AP = std::conditional_t<D, AtanTabParts, AtanParts>;
+        AP ap;
+        if constexpr (D)
+            ap = pd_atan_tab_reduce(u, c.atab);
+        else
+            ap = pd_atan_reduce(u);
         const double d1 = fma(u, u, 1.0);
         double d2 = 1.0, x = 0.0;
         if (AR == 3) {
@@ -278,7 +289,11 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
         }
         const double p12 = d1 * d2;
         const double r = pd_rcp(ap.den * p12);
-        const double at = pd_atan_finish(ap, ap.num * (r * p12));
+        double at;
+        if constexpr (D)
+            at = pd_atan_tab_finish(ap, ap.num * (r * p12));
+        else
+            at = pd_atan_finish(ap, ap.num * (r * p12));
         const double rd = r * ap.den;
         b.iu2 = (AR == 3) ? rd * d2 : rd;
         b.invf = invf;

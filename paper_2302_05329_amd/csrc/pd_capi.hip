@@ -747,7 +747,7 @@ int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, 
 
 int pd_elementary_eval(int fn, const double* x, int64_t n, double* out, void* stream) {
     if (!x || !out) return fail(PD_EINVAL, "NULL argument");
-    if (fn < PD_FN_SIN || fn > PD_FN_RCP) return fail(PD_EINVAL, "unknown function");
+    if (fn < PD_FN_SIN || fn > PD_FN_ATAN_TABLE) return fail(PD_EINVAL, "unknown function");
     if (n <= 0 || n > (int64_t(1) << 31)) return fail(PD_EINVAL, "bad n");
     if (pd::launch_elementary(fn, x, n, out, static_cast<hipStream_t>(stream)) != hipSuccess)
         return fail(PD_EHIP, "launch failed");

@@ -277,7 +277,7 @@ struct LnlSegment {
     template <int PR, int AR>
     __device__ __forceinline__ void run() {
         if constexpr (PR == 3)
-            run_with<PR, AR>(rec_mrd(rec));
+            run_with<PR, AR>(rec_mrd(rec, sct + kSinCosN));
         else
             run_with<PR, AR>(rec);
     }
@@ -412,8 +412,9 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
                                                          const int* __restrict__ segs,
                                                          const int* __restrict__ perm,
                                                          double* __restrict__ partial_all) {
-    __shared__ double2 sct[kSinCosN];
+    __shared__ double2 sct[kSinCosN + kAtanN];   // (sin, cos) table, then the arc tangent table
     stage_sincos_table(sct);
+    stage_atan_table(sct + kSinCosN);
     __syncthreads();
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
     moments_wave<MODE, PRG>(wave, recs, n, chunks, g, tab, segs, perm, partial_all, sct);
@@ -428,8 +429,9 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments_all(const double* __
                                                              const int* __restrict__ perm,
                                                              double* __restrict__ partial_all, unsigned nb3,
                                                              unsigned nb2) {
-    __shared__ double2 sct[kSinCosN];
+    __shared__ double2 sct[kSinCosN + kAtanN];   // (sin, cos) table, then the arc tangent table
     stage_sincos_table(sct);
+    stage_atan_table(sct + kSinCosN);
     __syncthreads();
     const unsigned b = blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -1055,6 +1057,9 @@ __global__ void k_elementary(int fn, const double* __restrict__ x, int64_t n, do
         r = (fn == PD_FN_SIN) ? sn : cs;
     } else if (fn == PD_FN_ATAN) {
         r = pd_atan(v);
+    } else if (fn == PD_FN_ATAN_TABLE) {
+        const AtanTabParts ap = pd_atan_tab_reduce(v);
+        r = pd_atan_tab_finish(ap, pd_div(ap.num, ap.den));
     } else if (fn == PD_FN_EXP) {
         r = pd_exp(v);
     } else {

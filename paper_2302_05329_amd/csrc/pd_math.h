@@ -16,6 +16,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "pd_atan_table.h"
 #include "pd_sincos_table.h"
 
 namespace pd {
@@ -203,6 +204,51 @@ __device__ __forceinline__ double pd_atan(double u) {
     if (hi) r = (r + sk(kPi6_lo)) + sk(kPi6_hi);
     if (inv) r = (sk(kPi2_hi) - r) + sk(kPi2_lo);
     return (u < 0.0) ? -r : r;
+}
+
+// Table-reduced arc tangent.  With c the table centre nearest |u| (pd_atan_table.h: 16 buckets
+// per octave of |u| from 2^-10 to 2^10, indexed by the exponent and top mantissa bits of |u|;
+// c = 0 below, the last centre above),
+//   atan|u| = atan c + atan t,  t = (|u| - c) / (1 + |u| c),  |t| <= 1/64,
+// and atan t = t + t^3 B(t^2) with the Taylor terms through t^9 (the first omitted term is below
+// 8e-20 relative).  The quotient's one division is left to the caller (shared with other
+// reciprocals), as in the split form above; no branches, and about 1 ulp (atan c correctly
+// rounded, one rounding in the final sum).
+constexpr double kB0 = -1.0 / 3.0, kB1 = 1.0 / 5.0, kB2 = -1.0 / 7.0, kB3 = 1.0 / 9.0;
+
+struct AtanTabParts {
+    double num, den;   // t = num / den
+    double atc;        // atan c
+    double u;          // the argument (its sign goes onto the result)
+};
+
+// TAB: (c_j, atan c_j) pairs, in constant memory (default) or a copy staged in LDS by the caller.
+__device__ __forceinline__ AtanTabParts pd_atan_tab_reduce(double u, const double2* __restrict__ tab =
+                                                                        reinterpret_cast<const double2*>(kAtanTab)) {
+    const unsigned hw = static_cast<unsigned>(__builtin_bit_cast(unsigned long long, u) >> 32) & 0x7fffffffu;
+    const int j = min(max(static_cast<int>(hw >> kAtanShift) - kAtanBase, 0), kAtanN - 1);
+    const double2 e = tab[j];
+    const double a = fabs(u);
+    AtanTabParts p;
+    p.num = a - e.x;
+    p.den = fma(a, e.x, 1.0);
+    p.atc = e.y;
+    p.u = u;
+    return p;
+}
+
+__device__ __forceinline__ double pd_atan_tab_finish(const AtanTabParts& p, double t) {
+    const double z = t * t;
+    double q = fma(sk(kB3), z, sk(kB2));
+    q = fma(q, z, sk(kB1));
+    q = fma(q, z, sk(kB0));
+    return copysign(p.atc + fma(t * z, q, t), p.u);   // the sum is atan|u| >= 0
+}
+
+// Copy of the arc tangent table in LDS, filled cooperatively by a block.
+__device__ __forceinline__ void stage_atan_table(double2* __restrict__ lds) {
+    for (unsigned i = threadIdx.x; i < static_cast<unsigned>(kAtanN); i += blockDim.x)
+        lds[i] = reinterpret_cast<const double2*>(kAtanTab)[i];
 }
 
 // exp(r) = 1 + r + r^2 E(r) on |r| <= ln2/2

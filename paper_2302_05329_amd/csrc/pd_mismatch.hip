@@ -462,7 +462,7 @@ struct AdjSegment {
     template <int PR, int AR>
     __device__ __forceinline__ void run() {
         if constexpr (PR == 3)
-            run_with<PR, AR>(rec_mrd(rec));
+            run_with<PR, AR>(rec_mrd(rec, sct + kSinCosN));
         else
             run_with<PR, AR>(rec);
     }
@@ -513,9 +513,10 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
                                                     const double2* __restrict__ tw,
                                                     const double* __restrict__ scal, double* __restrict__ part_all) {
     // the (sin, cos) and twiddle tables every bin reads, staged in LDS by the whole block first
-    __shared__ double2 sct[kSinCosN];
+    __shared__ double2 sct[kSinCosN + kAtanN];   // (sin, cos) table, then the arc tangent table
     __shared__ double2 twl[2 * kTw];
     stage_sincos_table(sct);
+    stage_atan_table(sct + kSinCosN);
     for (int i = threadIdx.x; i < 2 * kTw; i += blockDim.x) twl[i] = tw[i];
     __syncthreads();
     double* __restrict__ part = part_all + static_cast<int64_t>(PRG - 1) * nt * chunks * kNSlot;
