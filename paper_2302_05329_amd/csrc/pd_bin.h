@@ -409,12 +409,24 @@ __host__ __device__ inline int region_slot_pos(int prg, int s) {
     return ((m >> s) & 1ull) ? __builtin_popcountll(m & ((1ull << s) - 1ull)) : -1;
 }
 
+// A visitor declares kFd = false when it only accumulates moments sum_k z_k b_k of the basis
+// values: the moment of the explicit Mf-dependence is then a fixed combination of those moments
+// (fd_from_moments), formed once after the bin loop, and the visit skips it per bin.  The
+// merger-ringdown regions add two sums that are not basis moments (vis.ph_x: sum zi t Mf;
+// vis.am_x: sum zr Mf (2 x / (x^2 + g^2) + c3)), and the phase entry R_PH3 + 6 is formed from
+// them as well.
+template <class V, class = void>
+struct VisitsFd : std::true_type {};
+template <class V>
+struct VisitsFd<V, std::void_t<decltype(V::kFd)>> : std::bool_constant<V::kFd> {};
+
 // Visit d Psi / d rec[s] (vis.ph), d ln A / d rec[s] (vis.am) and the explicit
 // Mf-dependence: Mf dPsi/dMf and Mf d lnA/dMf (vis.fd), for one bin.
 template <int PR, int AR, class V, class RC = const double*>
 __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
     constexpr bool D = IsRecMRD<RC>::value;
-    double fpsi;
+    constexpr bool FD = VisitsFd<V>::value;
+    double fpsi = 0.0;
     if (PR == 1) {
         const double v = b.v, w = b.w, lv = b.lv;
         const double w2 = w * w, w3 = w2 * w, w5 = w3 * w2;
@@ -423,11 +435,11 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         const int pw[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
         // Mf dPsi/dMf = (1/3) [c5 + c7 v + sum_j pw_j c_j b_j]: each term is (c_j b_j) times a small
         // integer, so no coefficient is multiplied by a constant in the bin loop
-        double s3 = fma(c[R_PH1 + 7], v, c[R_PH1 + 5]);
+        double s3 = FD ? fma(c[R_PH1 + 7], v, c[R_PH1 + 5]) : 0.0;
 #pragma unroll
         for (int j = 0; j < 13; ++j) {
             vis.ph(R_PH1 + j, bs[j]);
-            if (pw[j] != 0) {
+            if (FD && pw[j] != 0) {
                 const double cb = c[R_PH1 + j] * bs[j];
                 if (pw[j] == 1)
                     s3 += cb;
@@ -437,14 +449,14 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
                     s3 = fma(static_cast<double>(pw[j]), cb, s3);
             }
         }
-        fpsi = s3 * sk(1.0 / 3.0);
+        if (FD) fpsi = s3 * sk(1.0 / 3.0);
     } else if (PR == 2) {
         const double i3 = b.invf * b.invf * b.invf;
         vis.ph(R_PH2 + 0, 1.0);
         vis.ph(R_PH2 + 1, b.mf);
         vis.ph(R_PH2 + 2, b.lnf);
         vis.ph(R_PH2 + 3, i3);
-        fpsi = fma(c[R_PH2 + 1], b.mf, fma(c[R_PH2 + 3] * i3, sk(-3.0), c[R_PH2 + 2]));
+        if (FD) fpsi = fma(c[R_PH2 + 1], b.mf, fma(c[R_PH2 + 3] * i3, sk(-3.0), c[R_PH2 + 2]));
     } else {
         double t;
         if constexpr (D)
@@ -457,13 +469,18 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         vis.ph(R_PH3 + 3, b.f34);
         vis.ph(R_PH3 + 4, b.at);
         vis.ph(R_PH3 + 5, -t);
-        vis.ph(R_PH3 + 6, -t * b.u);
-        if constexpr (D)
-            fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(c.c3q, b.f34, t * b.mf)));
-        else
-            fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(c[R_PH3 + 3] * b.f34, sk(0.75), t * b.mf)));
+        if constexpr (FD) {
+            vis.ph(R_PH3 + 6, -t * b.u);
+            if constexpr (D)
+                fpsi = fma(c[R_PH3 + 1], b.mf, fma(-c[R_PH3 + 2], b.invf, fma(c.c3q, b.f34, t * b.mf)));
+            else
+                fpsi = fma(c[R_PH3 + 1], b.mf,
+                           fma(-c[R_PH3 + 2], b.invf, fma(c[R_PH3 + 3] * b.f34, sk(0.75), t * b.mf)));
+        } else {
+            vis.ph_x(t * b.mf);
+        }
     }
-    double fa;
+    double fa = 0.0;
     vis.am(R_LNA0, 1.0);
     if (AR == 1) {
         const double ia = pd_rcp(b.ahat);
@@ -474,9 +491,9 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         for (int i = 1; i < 10; ++i) {
             p *= b.v;
             vis.am(R_AM1 + i, p);
-            acc = fma(static_cast<double>(i), c[R_AM1 + i] * p, acc);
+            if (FD) acc = fma(static_cast<double>(i), c[R_AM1 + i] * p, acc);
         }
-        fa = acc * sk(1.0 / 3.0);
+        if (FD) fa = acc * sk(1.0 / 3.0);
     } else if (AR == 2) {
         const double ia = pd_rcp(b.ahat);
         const double f = b.mf;
@@ -487,7 +504,7 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         for (int i = 1; i < 5; ++i) {
             p *= f;
             vis.am(R_AM2 + i, p);
-            acc = fma(static_cast<double>(i), c[R_AM2 + i] * p, acc);
+            if (FD) acc = fma(static_cast<double>(i), c[R_AM2 + i] * p, acc);
         }
         fa = acc;
     } else if constexpr (D) {
@@ -497,7 +514,10 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         vis.am(R_AM3 + 1, txr);
         vis.am(R_AM3 + 2, c.m2g * b.iden);
         vis.am(R_AM3 + 3, -x);
-        fa = -b.mf * txr;
+        if constexpr (FD)
+            fa = -b.mf * txr;
+        else
+            vis.am_x(b.mf * txr);
     } else {
         const double x = b.x, g = c[R_AM3 + 2], r = c[R_AM3 + 3];
         const double tx = 2.0 * x * b.iden;
@@ -505,9 +525,49 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         vis.am(R_AM3 + 1, tx + r);
         vis.am(R_AM3 + 2, -2.0 * g * b.iden);
         vis.am(R_AM3 + 3, -x);
-        fa = -b.mf * (tx + r);
+        if constexpr (FD)
+            fa = -b.mf * (tx + r);
+        else
+            vis.am_x(b.mf * (tx + r));
     }
-    vis.fd(fpsi, fa - sk(7.0 / 6.0));
+    if constexpr (FD) vis.fd(fpsi, fa - sk(7.0 / 6.0));
+}
+
+// After a bin loop whose visitor skipped the Mf-derivative (kFd = false): its moment
+// mom[R_MS] = sum_k zi Mf dPsi/dMf + zr (Mf d lnA/dMf - 7/6) from the basis moments, following
+// the same per-region expressions as visit_bin_t, and in phase region 3 the entry R_PH3 + 6
+// (sum zi (-t u), u = Mf R_ID - R_PH3+5 R_ID) from stm = sum zi t Mf and the R_PH3 + 5 moment
+// (sum zi (-t)).  sam = sum zr Mf (2 x iden + c3) in amplitude region 3.  Once per segment.
+template <int PR, int AR, class RC>
+__device__ __forceinline__ void fd_from_moments(RC c, double (&mom)[REC_N], double stm, double sam) {
+    double fp;
+    if constexpr (PR == 1) {
+        const int pw[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};
+        double s3 = fma(c[R_PH1 + 5], mom[R_PH1 + 4], c[R_PH1 + 7] * mom[R_PH1 + 6]);
+#pragma unroll
+        for (int j = 0; j < 13; ++j)
+            if (pw[j] != 0) s3 = fma(static_cast<double>(pw[j]) * c[R_PH1 + j], mom[R_PH1 + j], s3);
+        fp = s3 * (1.0 / 3.0);
+    } else if constexpr (PR == 2) {
+        fp = fma(c[R_PH2 + 1], mom[R_PH2 + 1], fma(-3.0 * c[R_PH2 + 3], mom[R_PH2 + 3], c[R_PH2 + 2] * mom[R_PH2 + 0]));
+    } else {
+        fp = fma(c[R_PH3 + 1], mom[R_PH3 + 1],
+                 fma(-c[R_PH3 + 2], mom[R_PH3 + 2], fma(0.75 * c[R_PH3 + 3], mom[R_PH3 + 3], stm)));
+        const double id = c[R_ID];
+        mom[R_PH3 + 6] = fma(-id, stm, -(c[R_PH3 + 5] * id) * mom[R_PH3 + 5]);
+    }
+    double fa = 0.0;
+    if constexpr (AR == 1) {
+#pragma unroll
+        for (int i = 1; i < 10; ++i) fa = fma(static_cast<double>(i) * c[R_AM1 + i], mom[R_AM1 + i], fa);
+        fa *= 1.0 / 3.0;
+    } else if constexpr (AR == 2) {
+#pragma unroll
+        for (int i = 1; i < 5; ++i) fa = fma(static_cast<double>(i) * c[R_AM2 + i], mom[R_AM2 + i], fa);
+    } else {
+        fa = -sam;
+    }
+    mom[R_MS] = fma(-7.0 / 6.0, mom[R_LNA0], fp + fa);
 }
 
 // Chunk `c` of `chunks` of the bins of phase region prg inside the active range: region 1 is

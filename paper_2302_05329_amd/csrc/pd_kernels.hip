@@ -253,12 +253,17 @@ __global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ rec
 // fused likelihood / gradient moments
 // ==================================================================================
 
+// Moments sum_k z_k b_k of the basis values; the Mf-derivative moment is formed after the loop
+// (fd_from_moments) from them and the two extra sums x[0] (phase) and x[1] (amplitude).
 struct MomVis {
+    static constexpr bool kFd = false;
     double* mom;
+    double* x;
     double zr, zi;
     __device__ __forceinline__ void ph(int s, double b) { mom[s] = fma(zi, b, mom[s]); }
     __device__ __forceinline__ void am(int s, double b) { mom[s] = fma(zr, b, mom[s]); }
-    __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] = fma(zi, fpsi, fma(zr, fa, mom[R_MS])); }
+    __device__ __forceinline__ void ph_x(double b) { x[0] = fma(zi, b, x[0]); }
+    __device__ __forceinline__ void am_x(double b) { x[1] = fma(zr, b, x[1]); }
 };
 
 // One region segment of the likelihood loop.  MODE 0: (d|h), (h|h); MODE 1: + moments.  The
@@ -290,6 +295,7 @@ struct LnlSegment {
         double mom[REC_N];
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
+        double mx[2] = {0.0, 0.0};
         ExpRec er{};
         if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane), D ? rec[R_AM3 + 0] : 1.0);
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
@@ -336,11 +342,12 @@ struct LnlSegment {
             hh += q;
             if (MODE == 1) {
                 if constexpr (PR == 1) py = fma(dwr, hi, -dwi * hr);
-                MomVis vis{mom, fma(-a0p, q, px), py};
+                MomVis vis{mom, mx, fma(-a0p, q, px), py};
                 visit_bin_t<PR, AR>(c, bv, vis);
             }
         }
         if (MODE == 1) {
+            fd_from_moments<PR, AR>(rec, mom, mx[0], mx[1]);
             if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
             flush_touched<PR, AR>(mom, lane, tot);
         }

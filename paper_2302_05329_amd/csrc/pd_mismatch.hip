@@ -437,12 +437,17 @@ __global__ void k_mm_finalize(const double* __restrict__ recs, int64_t nt, const
 }
 
 // ---- 5. adjoint moments ------------------------------------------------------------------
+// Moments sum_k z_k b_k of the basis values; the Mf-derivative moment is formed after the loop
+// (fd_from_moments) from them and the two extra sums x[0] (phase) and x[1] (amplitude).
 struct MMVis {
+    static constexpr bool kFd = false;
     double* mom;
+    double* x;
     double zr, zi;
     __device__ __forceinline__ void ph(int s, double b) { mom[s] = fma(zi, b, mom[s]); }
     __device__ __forceinline__ void am(int s, double b) { mom[s] = fma(zr, b, mom[s]); }
-    __device__ __forceinline__ void fd(double fpsi, double fa) { mom[R_MS] = fma(zi, fpsi, fma(zr, fa, mom[R_MS])); }
+    __device__ __forceinline__ void ph_x(double b) { x[0] = fma(zi, b, x[0]); }
+    __device__ __forceinline__ void am_x(double b) { x[1] = fma(zr, b, x[1]); }
 };
 
 struct AdjSegment {
@@ -476,6 +481,7 @@ struct AdjSegment {
         double mom[REC_N];
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
+        double mx[2] = {0.0, 0.0};
         ExpRec er{};
         if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane), D ? rec[R_AM3 + 0] : 1.0);
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
@@ -497,9 +503,10 @@ struct AdjSegment {
             const double ri = -gi * inv_sab + cfa * w * hi;
             // conj(h) R: weight of d ln A is Re, weight of d Psi is -Im
             const double cr = hr * rr + hi * ri, ci = hr * ri - hi * rr;
-            MMVis vis{mom, cr, -ci};
+            MMVis vis{mom, mx, cr, -ci};
             visit_bin_t<PR, AR>(c, bv, vis);
         }
+        fd_from_moments<PR, AR>(rec, mom, mx[0], mx[1]);
         if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
         flush_touched<PR, AR>(mom, lane, tot);
     }
