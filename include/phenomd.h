@@ -439,7 +439,7 @@ int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, 
  * |x| > 2^24 falls back to the device library), PD_FN_ATAN (two-level reduction: 1/u above 1,
  * then pi/6 above tan(pi/12), and an 11-term polynomial), PD_FN_ATAN_TABLE (the form the fused
  * likelihood's merger-ringdown loop uses: atan c + atan((|u| - c)/(1 + |u| c)) with c from a
- * 321-entry table indexed by the exponent and top mantissa bits of |u|, and a 4-term
+ * 321-entry table indexed by the exponent and top mantissa bits of |u|, and a 3-term
  * polynomial), PD_FN_EXP, PD_FN_RCP (hardware estimate + two Newton steps).  Exposed so that
  * their ulp error can be measured against a high-precision reference.  Unknown fn:
  * PD_EINVAL. */

@@ -255,7 +255,7 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
         const double invf = c[R_IMS] * T.at(T_INF, k);
         b.lnf = lnf;
         b.invf = invf;
-        b.psi = fma(c[R_PH2 + 3], invf * invf * invf, fma(c[R_PH2 + 2], lnf, fma(c[R_PH2 + 1], mf, c[R_PH2 + 0])));
+        b.psi = fma(c[R_PH2 + 3], invf * invf * invf, fma(c[R_PH2 + 2], lnf, c[R_PH2 + 1] * mf)) + c[R_PH2 + 0];
     } else {
         // merger-ringdown phase: atan(u) needs one division (after its argument reduction), the
         // phase derivative 1/(1 + u^2), and in amplitude region 3 the Lorentzian 1/(x^2 + g^2):
@@ -300,8 +300,10 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
         b.f34 = f34;
         b.u = u;
         b.at = at;
-        b.psi = fma(c[R_PH3 + 4], at,
-                    fma(c[R_PH3 + 3], f34, fma(c[R_PH3 + 2], invf, fma(c[R_PH3 + 1], mf, c[R_PH3 + 0]))));
+        // the constant term last: every multiply-add then takes at most one record entry (a
+        // scalar operand), so no entry is first copied to a vector register
+        b.psi = fma(c[R_PH3 + 4], at, fma(c[R_PH3 + 3], f34, fma(c[R_PH3 + 2], invf, c[R_PH3 + 1] * mf))) +
+                c[R_PH3 + 0];
         if (AR == 3) {
             const double iden = rd * d1;
             b.x = x;

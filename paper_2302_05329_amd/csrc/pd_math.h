@@ -210,11 +210,12 @@ __device__ __forceinline__ double pd_atan(double u) {
 // per octave of |u| from 2^-10 to 2^10, indexed by the exponent and top mantissa bits of |u|;
 // c = 0 below, the last centre above),
 //   atan|u| = atan c + atan t,  t = (|u| - c) / (1 + |u| c),  |t| <= 1/64,
-// and atan t = t + t^3 B(t^2) with the Taylor terms through t^9 (the first omitted term is below
-// 8e-20 relative).  The quotient's one division is left to the caller (shared with other
-// reciprocals), as in the split form above; no branches, and about 1 ulp (atan c correctly
+// and atan t = t + t^3 B(t^2) with the Taylor terms through t^7: the first omitted term, t^9/9, is
+// below 6.9e-18 of atan|u| over the whole range (|t| <= |u| / (32 (1 + |u| c)); at most 1/64, and
+// then atan|u| is of order one).  The quotient's one division is left to the caller (shared with
+// other reciprocals), as in the split form above; no branches, and about 1 ulp (atan c correctly
 // rounded, one rounding in the final sum).
-constexpr double kB0 = -1.0 / 3.0, kB1 = 1.0 / 5.0, kB2 = -1.0 / 7.0, kB3 = 1.0 / 9.0;
+constexpr double kB0 = -1.0 / 3.0, kB1 = 1.0 / 5.0, kB2 = -1.0 / 7.0;
 
 struct AtanTabParts {
     double num, den;   // t = num / den
@@ -239,8 +240,7 @@ __device__ __forceinline__ AtanTabParts pd_atan_tab_reduce(double u, const doubl
 
 __device__ __forceinline__ double pd_atan_tab_finish(const AtanTabParts& p, double t) {
     const double z = t * t;
-    double q = fma(sk(kB3), z, sk(kB2));
-    q = fma(q, z, sk(kB1));
+    double q = fma(sk(kB2), z, sk(kB1));
     q = fma(q, z, sk(kB0));
     return copysign(p.atc + fma(t * z, q, t), p.u);   // the sum is atan|u| >= 0
 }

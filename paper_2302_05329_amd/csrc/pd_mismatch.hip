@@ -487,23 +487,37 @@ struct AdjSegment {
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
-            eval_bin_t<PR, AR, AR == 3>(c, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
-            const double Aamp = a0p * T.at(T_F76, k) * bv.ahat;
-            double sn, cs;
-            pd_sincos(bv.psi, &sn, &cs, sct);
-            const double hr = Aamp * cs, hi = -Aamp * sn;
-            const double w = w4 * inv_psd[k];
-            const double2 t = tgt[k];
+            double f76, ipsd;
+            double2 t;
+            if constexpr (PR == 3) {
+                // merger-ringdown: every per-bin load issued before the elementary functions'
+                // branches, sharing one 32-bit offset from scalar bases
+                f76 = T.at(T_F76, k);
+                ipsd = inv_psd[k];
+                t = tgt[k];
+                BinTabs bt;
+                bt.load(T, k);
+                eval_bin_t<PR, AR, AR == 3>(c, bt, k, mf, bv, (AR == 3) ? er.next() : 0.0);
+            } else {
+                eval_bin_t<PR, AR, AR == 3>(c, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
+                f76 = T.at(T_F76, k);
+                ipsd = inv_psd[k];
+                t = tgt[k];
+            }
+            const double Aamp = a0p * f76 * bv.ahat;
+            const double w = w4 * ipsd;
             const double2 e = twiddle(tw, (k * static_cast<unsigned>(j)) & static_cast<unsigned>(g.nb - 1));
             const double2 x = cmul(make_double2(w * t.x, w * t.y), e);
             // G = conj(u) x
             const double gr = ur * x.x + ui * x.y, gi = ur * x.y - ui * x.x;
-            // R = -G / sqrt(AB) + |z| w h / (A^(3/2) B^(1/2))
-            const double rr = -gr * inv_sab + cfa * w * hr;
-            const double ri = -gi * inv_sab + cfa * w * hi;
-            // conj(h) R: weight of d ln A is Re, weight of d Psi is -Im
-            const double cr = hr * rr + hi * ri, ci = hr * ri - hi * rr;
-            MMVis vis{mom, mx, cr, -ci};
+            // R = -G / sqrt(AB) + |z| w h / (A^(3/2) B^(1/2)), h = Aamp exp(-i Psi); the weights are
+            // conj(h) R: Re (of d ln A) = -inv_sab Re(conj(h) G) + cfa w Aamp^2, and -Im (of d Psi)
+            // = inv_sab Im(conj(h) G), with conj(h) G = Aamp G exp(i Psi) formed from the table
+            // angle directly: its real part is px and its imaginary part -py
+            double px, py;
+            pd_rotate_data(bv.psi, Aamp, gr, gi, sct, px, py);
+            const double cr = fma(-inv_sab, px, (cfa * w) * (Aamp * Aamp));
+            MMVis vis{mom, mx, cr, -inv_sab * py};
             visit_bin_t<PR, AR>(c, bv, vis);
         }
         fd_from_moments<PR, AR>(rec, mom, mx[0], mx[1]);
@@ -530,8 +544,9 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     const int lane = threadIdx.x & 63;
     const int cr = region_chunks(PRG, chunks);
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    const int64_t p = wave / cr;
-    const int c = static_cast<int>(wave - p * cr);
+    // wave-uniform point and chunk, kept in scalar registers (the record stays scalar in the loops)
+    const int64_t p = uniform_i(wave / cr);
+    const int c = uniform_i(wave - p * cr);
     if (p >= nt) return;
     const double* __restrict__ rec = recs + p * REC_N;
     double* __restrict__ out = part + (p * chunks + c) * kNSlot;

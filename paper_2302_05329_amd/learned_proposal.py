@@ -492,7 +492,10 @@ def compare(lam, n_chains=4096, warm=600, n_ref=512, ref_burn=4000, ref_steps=20
                           mean_diff_sigma=((st["mean"] - mb) / sb).tolist(),
                           std_diff_rel=((st["std"] - sb) / sb).tolist(),
                           drift_mean_sigma=((st["mean2"] - st["mean1"]) / sb).tolist(),
-                          se_sigma=(1.0 / np.sqrt(st["ess"])).tolist()),
+                          se_sigma=(1.0 / np.sqrt(st["ess"])).tolist(),
+                          # relative standard error of the difference of the two standard deviations
+                          # (a Gaussian marginal's sample std has relative variance 1 / (2 ESS))
+                          se_std_rel=np.sqrt(0.5 / st["ess"] + 0.5 / ess_b).tolist()),
         importance=dict(draws=isr["draws"], kish_ess=isr["kish_ess"], kish_ess_raw=isr["kish_ess_raw"],
                         k_hat=isr["k_hat"], max_weight=isr["max_weight"],
                         proposal=isr["proposal"],

@@ -23,7 +23,8 @@ def test_flow_mh_gains_over_hmc_and_keeps_the_posterior(gpu, two_site):
       Monte Carlo standard errors;
     * plain HMC (100 leapfrog steps per transition) started from the flow-MH end states leaves
       their moments where they are (HMC keeps the posterior invariant): means within 0.05 sigma
-      or 5 Monte Carlo standard errors, standard deviations within 5%;
+      or 5 Monte Carlo standard errors, standard deviations within 5% or 5 standard errors of
+      their difference (relative variance 1/(2 ESS) for each of the two estimates);
     * flow-MH means and standard deviations are within 0.25 sigma of the plain-HMC reference run
       started from the warm-up.  That run relaxes slowly along the spin directions (it settles
       about 0.05-0.1 sigma away, and HMC started from the flow-MH states stays there instead), so
@@ -49,6 +50,7 @@ def test_flow_mh_gains_over_hmc_and_keeps_the_posterior(gpu, two_site):
     print("stationarity", st, flush=True)
     lim = np.maximum(0.05, 5 * np.array(st["se_sigma"]))
     assert np.all(np.abs(st["mean_diff_sigma"]) < lim), (st["mean_diff_sigma"], lim)
-    assert np.all(np.abs(st["std_diff_rel"]) < 0.05), st["std_diff_rel"]
+    lim_s = np.maximum(0.05, 5 * np.array(st["se_std_rel"]))
+    assert np.all(np.abs(st["std_diff_rel"]) < lim_s), (st["std_diff_rel"], lim_s)
     assert max(r["mean_diff_sigma_flow"]) < 0.25, r["mean_diff_sigma_flow"]
     assert max(r["std_diff_sigma_flow"]) < 0.25, r["std_diff_sigma_flow"]
