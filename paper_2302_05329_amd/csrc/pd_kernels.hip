@@ -160,14 +160,14 @@ __global__ void __launch_bounds__(64) k_setup_fit_tangent(const double* __restri
 // per-grid tables
 // ==================================================================================
 
-// Four threads per bin, one per transcendental (cbrt; log; f^(3/4); f^(-7/6) with the weighted
-// data): the table launch is a few waves per SIMD, so its time is one thread's chain of calls,
-// which this cuts to one call.
+// Four parts per bin, one per transcendental (cbrt; log; f^(3/4); f^(-7/6) with the weighted
+// data), each part a separate range of blocks (blockIdx.y): the table launch is a few waves per
+// SIMD, so its time is one thread's chain of calls, which this cuts to one call, and every wave
+// runs a single part (no divergent branches).
 __global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __restrict__ data,
                                                 const double* __restrict__ inv_psd, double* __restrict__ tab) {
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t k = t >> 2;
-    const int part = static_cast<int>(t & 3);
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int part = static_cast<int>(blockIdx.y);
     if (k >= g.nb) return;
     const double f = bin_freq(g, k);
     const bool pos = f > 0.0;
@@ -677,8 +677,9 @@ __global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restr
     const int wib = threadIdx.x >> 6;
     const int cr = region_chunks(PRG, chunks);
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + wib));
-    const int64_t pi = wave / cr;
-    const int c = static_cast<int>(wave - pi * cr);
+    // wave-uniform point and chunk, kept in scalar registers (the record stays scalar in the loops)
+    const int64_t pi = uniform_i(wave / cr);
+    const int c = uniform_i(wave - pi * cr);
     const bool live = pi < n;
     // points in order of decreasing work, as in the likelihood passes
     const int64_t p = (live && perm) ? static_cast<int64_t>(__builtin_amdgcn_readfirstlane(perm[pi])) : pi;
@@ -909,7 +910,7 @@ hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, d
 
 hipError_t launch_tables(const GridArgs& g, const double* data, const double* inv_psd, double* tab,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_tables, dim3(blocks_for(4 * g.nb, 256)), dim3(256), 0, s, g, data, inv_psd, tab);
+    hipLaunchKernelGGL(k_tables, dim3(blocks_for(g.nb, 256), 4), dim3(256), 0, s, g, data, inv_psd, tab);
     return hipGetLastError();
 }
 
