@@ -459,6 +459,17 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         vis.ph(R_PH2 + 2, b.lnf);
         vis.ph(R_PH2 + 3, i3);
         if (FD) fpsi = fma(c[R_PH2 + 1], b.mf, fma(c[R_PH2 + 3] * i3, sk(-3.0), c[R_PH2 + 2]));
+    } else if constexpr (D && !FD) {
+        // t = R_PH3+4 R_ID / (1 + u^2) is a per-point constant times 1/(1 + u^2): the R_PH3 + 5
+        // moment and the extra phase sum take 1/(1 + u^2) and are scaled once after the loop
+        // (fd_from_moments)
+        vis.ph(R_PH3 + 0, 1.0);
+        vis.ph(R_PH3 + 1, b.mf);
+        vis.ph(R_PH3 + 2, b.invf);
+        vis.ph(R_PH3 + 3, b.f34);
+        vis.ph(R_PH3 + 4, b.at);
+        vis.ph(R_PH3 + 5, b.iu2);
+        vis.ph_x(b.iu2 * b.mf);
     } else {
         double t;
         if constexpr (D)
@@ -514,7 +525,9 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         const double x = b.x, r = c[R_AM3 + 3];
         const double txr = fma(x + x, b.iden, r);
         vis.am(R_AM3 + 1, txr);
-        vis.am(R_AM3 + 2, c.m2g * b.iden);
+        // -2 R_AM3+2 / (x^2 + g^2): without a moment visitor's after-loop scaling the per-point
+        // factor is applied per bin
+        vis.am(R_AM3 + 2, FD ? c.m2g * b.iden : b.iden);
         vis.am(R_AM3 + 3, -x);
         if constexpr (FD)
             fa = -b.mf * txr;
@@ -540,8 +553,17 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
 // the same per-region expressions as visit_bin_t, and in phase region 3 the entry R_PH3 + 6
 // (sum zi (-t u), u = Mf R_ID - R_PH3+5 R_ID) from stm = sum zi t Mf and the R_PH3 + 5 moment
 // (sum zi (-t)).  sam = sum zr Mf (2 x iden + c3) in amplitude region 3.  Once per segment.
-template <int PR, int AR, class RC>
+// With the merger-ringdown record (RecMRD) the visit accumulated 1/(1 + u^2) for the R_PH3 + 5
+// moment and in stm, and 1/(x^2 + g^2) for the R_AM3 + 2 moment; MRD selects the scaling by the
+// per-point factors here.
+template <int PR, int AR, bool MRD, class RC>
 __device__ __forceinline__ void fd_from_moments(RC c, double (&mom)[REC_N], double stm, double sam) {
+    if constexpr (MRD && PR == 3) {
+        const double c4id = c[R_PH3 + 4] * c[R_ID];
+        mom[R_PH3 + 5] *= -c4id;
+        stm *= c4id;
+    }
+    if constexpr (MRD && AR == 3) mom[R_AM3 + 2] *= -2.0 * c[R_AM3 + 2];
     double fp;
     if constexpr (PR == 1) {
         const int pw[13] = {-5, -3, -2, -1, 0, 0, 1, 1, 2, 3, 4, 5, 6};

@@ -347,7 +347,7 @@ struct LnlSegment {
             }
         }
         if (MODE == 1) {
-            fd_from_moments<PR, AR>(rec, mom, mx[0], mx[1]);
+            fd_from_moments<PR, AR, D>(rec, mom, mx[0], mx[1]);
             if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
             flush_touched<PR, AR>(mom, lane, tot);
         }

@@ -263,28 +263,34 @@ __global__ void __launch_bounds__(256) k_mm_cols(const double* __restrict__ recs
     const bool valid = rec[R_VALID] != 0.0;
     const Tabs T(tab, g.nb);
     const double2* __restrict__ tg = reinterpret_cast<const double2*>(targets) + p * N;
+    // the merger-ringdown record form: table-reduced arc tangent (table in constant memory)
+    const RecMRD rm = rec_mrd(rec, reinterpret_cast<const double2*>(kAtanTab));
+    const double2* __restrict__ sct = reinterpret_cast<const double2*>(kSinCosTab);
     double a = 0.0, b = 0.0;
     for (int idx = threadIdx.x; idx < cols * LEN; idx += 256) {
         const int c = idx % cols, k2 = idx / cols;
         const int64_t k = gcol + c + static_cast<int64_t>(n1) * k2;
         const double2 t = tg[k];
         const double w = 4.0 * g.df * inv_psd[k];
-        double2 h = make_double2(0.0, 0.0);
+        // x = w conj(h) t with h = A exp(-i Psi): conj(h) t = A t exp(i Psi), formed from the
+        // sin/cos table angle directly (its real part is px and its imaginary part -py)
+        double xr = 0.0, xi = 0.0, hh = 0.0;
         if (valid) {
             const double f = bin_freq(g, k);
             const double mf = rec[R_MS] * f;
             if (bin_active(g, f, mf)) {
                 BinVals bv;
-                eval_bin_rt(rec, T, k, mf, bv);
+                eval_bin_rt(rm, T, k, mf, bv);
                 const double A = rec[R_A0P] * T.at(T_F76, k) * bv.ahat;
-                double sn, cs;
-                pd_sincos(bv.psi, &sn, &cs);
-                h = make_double2(A * cs, -A * sn);
+                double px, py;
+                pd_rotate_data(bv.psi, A, t.x, t.y, sct, px, py);
+                xr = px;
+                xi = -py;
+                hh = A * A;
             }
         }
-        // x = w conj(h) t
-        buf[c * kLd + k2] = make_double2(w * (h.x * t.x + h.y * t.y), w * (h.x * t.y - h.y * t.x));
-        a = fma(w, h.x * h.x + h.y * h.y, a);
+        buf[c * kLd + k2] = make_double2(w * xr, w * xi);
+        a = fma(w, hh, a);
         b = fma(w, t.x * t.x + t.y * t.y, b);
     }
     a = wave_sum(a);
@@ -520,7 +526,7 @@ struct AdjSegment {
             MMVis vis{mom, mx, cr, -inv_sab * py};
             visit_bin_t<PR, AR>(c, bv, vis);
         }
-        fd_from_moments<PR, AR>(rec, mom, mx[0], mx[1]);
+        fd_from_moments<PR, AR, D>(rec, mom, mx[0], mx[1]);
         if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
         flush_touched<PR, AR>(mom, lane, tot);
     }
