@@ -275,6 +275,11 @@ struct LnlSegment {
     Tabs T;
     GridArgs g;
     const double2* __restrict__ sct;   // (sin, cos) table in LDS
+    // the wave's copy of the record in LDS, read by the code after each bin loop: the loop reloads
+    // the record's uniform entries on its trips, and a loop-loaded value used after a loop whose
+    // lanes leave at different trips is copied to vector registers on every trip; entries read
+    // from LDS after the loop are never merged with the loop's loads
+    const double* recl;
     int64_t k0, k1;
     int lane;
     double dh, hh, tot;
@@ -347,7 +352,8 @@ struct LnlSegment {
             }
         }
         if (MODE == 1) {
-            fd_from_moments<PR, AR, D>(rec, mom, mx[0], mx[1]);
+            // (the inspiral loops read the record itself: its copy there measured more vector copies)
+            fd_from_moments<PR, AR, D>(PR == 1 ? rec : recl, mom, mx[0], mx[1]);
             if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
             flush_touched<PR, AR>(mom, lane, tot);
         }
@@ -371,7 +377,8 @@ template <int MODE, int PRG>
 __device__ __forceinline__ void moments_wave(int64_t wave, const double* __restrict__ recs, int64_t n, int chunks,
                                              const GridArgs& g, const double* __restrict__ tab,
                                              const int* __restrict__ segs, const int* __restrict__ perm,
-                                             double* __restrict__ partial_all, const double2* __restrict__ sct) {
+                                             double* __restrict__ partial_all, const double2* __restrict__ sct,
+                                             double* recl) {
     // value passes keep (d|h), (h|h) per row; gradient passes a compact row of the region's entries
     constexpr int NS = (MODE == 0) ? 2 : region_row_width(PRG);
     double* __restrict__ partial = partial_all + grad_group_offset<MODE>(PRG, n, chunks);
@@ -390,9 +397,10 @@ __device__ __forceinline__ void moments_wave(int64_t wave, const double* __restr
         for (int s = lane; s < NS; s += 64) out[s] = 0.0;
         return;
     }
+    if (MODE == 1 && lane < REC_N) recl[lane] = rec[lane];
     Segs S;
     load_segments(segs + ((PRG - 1) * n * chunks + p * chunks + c) * kSegInts, S);
-    LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, sct, 0, 0, lane, 0.0, 0.0, 0.0};
+    LnlSegment<MODE> seg{rec, Tabs(tab, g.nb), g, sct, recl, 0, 0, lane, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         if (uniform_i(S.k[i + 1]) > uniform_i(S.k[i]) && uniform_i(S.pr[i]) == PRG) {
@@ -424,7 +432,8 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments(const double* __rest
     stage_atan_table(sct + kSinCosN);
     __syncthreads();
     const int64_t wave = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
-    moments_wave<MODE, PRG>(wave, recs, n, chunks, g, tab, segs, perm, partial_all, sct);
+    __shared__ double recl[4][REC_N];
+    moments_wave<MODE, PRG>(wave, recs, n, chunks, g, tab, segs, perm, partial_all, sct, recl[threadIdx.x >> 6]);
 }
 
 // The three regions in one launch: blocks [0, nb3) take the merger-ringdown waves, the next nb2 the
@@ -439,17 +448,19 @@ __global__ void __launch_bounds__(256, 4) k_loglike_moments_all(const double* __
     __shared__ double2 sct[kSinCosN + kAtanN];   // (sin, cos) table, then the arc tangent table
     stage_sincos_table(sct);
     stage_atan_table(sct + kSinCosN);
+    __shared__ double recl[4][REC_N];
     __syncthreads();
     const unsigned b = blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     if (b < nb3)
-        moments_wave<MODE, 3>(static_cast<int64_t>(b) * 4 + w, recs, n, chunks, g, tab, segs, perm, partial_all, sct);
+        moments_wave<MODE, 3>(static_cast<int64_t>(b) * 4 + w, recs, n, chunks, g, tab, segs, perm, partial_all, sct,
+                              recl[w]);
     else if (b < nb3 + nb2)
         moments_wave<MODE, 2>(static_cast<int64_t>(b - nb3) * 4 + w, recs, n, chunks, g, tab, segs, perm,
-                              partial_all, sct);
+                              partial_all, sct, recl[w]);
     else
         moments_wave<MODE, 1>(static_cast<int64_t>(b - nb3 - nb2) * 4 + w, recs, n, chunks, g, tab, segs, perm,
-                              partial_all, sct);
+                              partial_all, sct, recl[w]);
 }
 
 // Value-only likelihood: one thread per point sums its (d|h), (h|h) partials over the region

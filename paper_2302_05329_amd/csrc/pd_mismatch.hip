@@ -464,6 +464,9 @@ struct AdjSegment {
     const double* __restrict__ inv_psd;
     const double2* __restrict__ tw;    // twiddle tables in LDS
     const double2* __restrict__ sct;   // (sin, cos) table in LDS
+    // the wave's copy of the record in LDS, read after each bin loop (loop-loaded uniform entries
+    // used after a loop with a divergent exit are copied to vector registers on every trip)
+    const double* recl;
     double ur, ui, inv_sab, cfa;
     int64_t j;
     int64_t k0, k1;
@@ -526,7 +529,8 @@ struct AdjSegment {
             MMVis vis{mom, mx, cr, -inv_sab * py};
             visit_bin_t<PR, AR>(c, bv, vis);
         }
-        fd_from_moments<PR, AR, D>(rec, mom, mx[0], mx[1]);
+        // (the inspiral loops read the record itself: its copy there measured more vector copies)
+        fd_from_moments<PR, AR, D>(PR == 1 ? rec : recl, mom, mx[0], mx[1]);
         if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
         flush_touched<PR, AR>(mom, lane, tot);
     }
@@ -542,6 +546,7 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     // the (sin, cos) and twiddle tables every bin reads, staged in LDS by the whole block first
     __shared__ double2 sct[kSinCosN + kAtanN];   // (sin, cos) table, then the arc tangent table
     __shared__ double2 twl[2 * kTw];
+    __shared__ double recl[4][REC_N];
     stage_sincos_table(sct);
     stage_atan_table(sct + kSinCosN);
     for (int i = threadIdx.x; i < 2 * kTw; i += blockDim.x) twl[i] = tw[i];
@@ -570,6 +575,8 @@ __global__ void __launch_bounds__(256) k_mm_adjoint(const double* __restrict__ r
     seg.inv_psd = inv_psd;
     seg.tw = twl;
     seg.sct = sct;
+    if (lane < REC_N) recl[threadIdx.x >> 6][lane] = rec[lane];
+    seg.recl = recl[threadIdx.x >> 6];
     // unit phase u = z / |z|; G_k = conj(u) x_k with x_k = w t_k exp(2 pi i k j / N)
     seg.ur = sc[3] / az;
     seg.ui = sc[4] / az;
