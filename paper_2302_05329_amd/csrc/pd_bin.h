@@ -521,7 +521,9 @@ __device__ __forceinline__ void visit_bin_t(RC c, const BinVals& b, V& vis) {
         }
         fa = acc;
     } else if constexpr (D) {
-        // the R_AM3 moment is R_IANUM times the ln A0 moment; the caller forms it after the loop
+        // a moment visitor's R_AM3 moment is R_IANUM times its ln A0 moment, formed after the
+        // loop; a per-bin visitor gets the entry here
+        if constexpr (FD) vis.am(R_AM3 + 0, c[R_IANUM]);
         const double x = b.x, r = c[R_AM3 + 3];
         const double txr = fma(x + x, b.iden, r);
         vis.am(R_AM3 + 1, txr);

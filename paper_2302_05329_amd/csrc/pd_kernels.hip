@@ -622,22 +622,34 @@ constexpr int kFisherAcc = kFisherSlots;
 struct FisherSegment {
     const double* __restrict__ rec;
     const double* Tl;
+    const double2* __restrict__ atab;   // arc tangent table in LDS (merger-ringdown launch)
     Tabs T;
     GridArgs g;
     int64_t k0, k1;
     int lane;
     double F[kFisherAcc];
 
+    // merger-ringdown segments use the record form with the table-reduced arc tangent
     template <int PR, int AR>
     __device__ __forceinline__ void run() {
+        if constexpr (PR == 3)
+            run_with<PR, AR>(rec_mrd(rec, atab));
+        else
+            run_with<PR, AR>(rec);
+    }
+
+    template <int PR, int AR, class RC>
+    __device__ __forceinline__ void run_with(RC c) {
+        constexpr bool D = IsRecMRD<RC>::value;
         const double ms = rec[R_MS];
         const double a0p = rec[R_A0P];
         ExpRec er{};
-        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane));
+        // the merger-ringdown record form takes the amplitude numerator R_AM3 in the recurrence
+        if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane), D ? rec[R_AM3 + 0] : 1.0);
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
             const double mf = ms * bin_freq(g, k);
             BinVals bv;
-            eval_bin_t<PR, AR, AR == 3>(rec, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
+            eval_bin_t<PR, AR, AR == 3>(c, T, k, mf, bv, (AR == 3) ? er.next() : 0.0);
             const double W = (a0p * a0p) * T.at(T_WW, k) * bv.ahat * bv.ahat;
             FisherVis vis;
             // the tangents are re-read from LDS in every bin (broadcast reads): an opaque offset
@@ -649,7 +661,7 @@ struct FisherSegment {
             vis.ims = rec[R_IMS];
 #pragma unroll
             for (int q = 0; q < kFisherDirs; ++q) vis.dpsi[q] = vis.dlna[q] = 0.0;
-            visit_bin_t<PR, AR>(rec, bv, vis);
+            visit_bin_t<PR, AR>(c, bv, vis);
             int s = 0;
 #pragma unroll
             for (int a = 0; a < kFisherDirs; ++a) {
@@ -684,6 +696,8 @@ __global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restr
                                                         double* __restrict__ partial_all) {
     double* __restrict__ partial = partial_all + static_cast<int64_t>(PRG - 1) * n * chunks * kFisherAcc;
     __shared__ double lds[4][kFisherDirs * REC_N];
+    __shared__ double2 atl[PRG == 3 ? kAtanN : 1];
+    if (PRG == 3) stage_atan_table(atl);
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int cr = region_chunks(PRG, chunks);
@@ -711,6 +725,7 @@ __global__ void __launch_bounds__(256, 3) k_fisher_partial(const double* __restr
     FisherSegment seg;
     seg.rec = rec;
     seg.Tl = T;
+    seg.atab = atl;
     seg.T = Tabs(tab, g.nb);
     seg.g = g;
     seg.lane = lane;
