@@ -34,7 +34,7 @@ def test_flow_mh_gains_over_hmc_and_keeps_the_posterior(gpu, two_site):
     print(f"learned proposal: 2048 chains, two_site={two_site}", flush=True)
     sys.stdout.flush()
     r = LP.compare(W.load_lambda(), n_chains=2048, warm=600, n_ref=512, ref_burn=2000, ref_steps=16000, ref_thin=10,
-                   flow_steps=1500, rounds=5, per_round=50, seed=77, two_site=two_site, stat_steps=2000)
+                   flow_steps=3000, rounds=5, per_round=50, seed=77, two_site=two_site, stat_steps=2000)
     print({k: r[k] for k in ("hmc", "flow_hmc", "reference", "importance")}, flush=True)
     print("k_hat", r["importance"]["k_hat"], "kish", r["importance"]["kish_ess"], "z", r["importance"]["z_mean_flow_minus_is"], flush=True)
     gain = r["flow_hmc"]["ess_per_s"] / r["hmc"]["ess_per_s"]
