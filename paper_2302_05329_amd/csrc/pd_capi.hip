@@ -251,10 +251,10 @@ int pd_waveform_eval(const double* theta, int64_t n, int param, const pd_grid* g
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* recs = at<double>(workspace, L.rec);
     double* tab = at<double>(workspace, L.tab);
-    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
+    // records and grid tables in one launch
+    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s, nullptr, &g, nullptr,
+                                          nullptr, tab);
     if (e != hipSuccess) return fail_hip(e, "setup");
-    e = pd::launch_tables(g, nullptr, nullptr, tab, s);
-    if (e != hipSuccess) return fail_hip(e, "tables");
     e = pd::launch_waveform(recs, n, g, tab, precision, h_out, s);
     if (e != hipSuccess) return fail_hip(e, "waveform");
     return PD_OK;
@@ -317,15 +317,13 @@ int pd::loglike_and_grad(const double* theta, int64_t n, int param, const pd_gri
         if (side) (void)hipStreamWaitEvent(s, side->join, 0);
         return fail_hip(err, what);
     };
-    e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s, xf);
+    // records and (unless already built) grid tables in one launch
+    e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s, xf, tables_ready ? nullptr : &g,
+                               data, inv_psd, tab);
     if (e != hipSuccess) return fail_joined(e, "setup");
     if (grad && xf) {
         rc = launch_tangents();
         if (rc) return rc;
-    }
-    if (!tables_ready) {
-        e = pd::launch_tables(g, data, inv_psd, tab, s);
-        if (e != hipSuccess) return fail_joined(e, "tables");
     }
     e = pd::launch_loglike(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg),
                            at<int>(workspace, L.order), partial, lnl,
@@ -352,12 +350,12 @@ int pd_fisher(const double* theta, int64_t n, int param, const pd_grid* grid, co
     double* tans = at<double>(workspace, L.tan);
     double* partial = at<double>(workspace, L.partial);
     double* tab = at<double>(workspace, L.tab);
-    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s);
+    // records and grid tables in one launch
+    hipError_t e = pd::launch_setup_value(theta, n, param, g.fref, lambda, recs, status, s, nullptr, &g, nullptr,
+                                          inv_psd, tab);
     if (e != hipSuccess) return fail_hip(e, "setup");
     e = pd::launch_setup_theta_tangent(theta, n, param, g.fref, lambda, 7, tans, s);
     if (e != hipSuccess) return fail_hip(e, "setup tangents");
-    e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
-    if (e != hipSuccess) return fail_hip(e, "tables");
     e = pd::launch_fisher(theta, param, recs, tans, n, L.chunks, g, tab, at<int>(workspace, L.seg),
                           at<int>(workspace, L.order), partial, F, s);
     if (e != hipSuccess) return fail_hip(e, "fisher");
@@ -401,10 +399,10 @@ int pd_mismatch_grad(const double* theta, int64_t nt, int param, const pd_grid* 
     double* tans = at<double>(workspace, L.tan);
     void* scratch = at<void>(workspace, L.extra);
     double* tab = at<double>(workspace, L.tab);
-    hipError_t e = pd::launch_setup_value(theta, nt, param, g.fref, lambda, recs, nullptr, s);
+    // records and grid tables in one launch
+    hipError_t e = pd::launch_setup_value(theta, nt, param, g.fref, lambda, recs, nullptr, s, nullptr, &g, nullptr,
+                                          inv_psd, tab);
     if (e != hipSuccess) return fail_hip(e, "setup");
-    e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
-    if (e != hipSuccess) return fail_hip(e, "tables");
     if (dsum_dlambda) {
         e = pd::launch_setup_fit_tangent(theta, nt, param, g.fref, lambda, recs, tans, s);
         if (e != hipSuccess) return fail_hip(e, "setup fit tangents");
@@ -736,10 +734,10 @@ int pd_overlap(const double* theta, int64_t nt, int param, const pd_grid* grid, 
     double* recs = at<double>(workspace, L.rec);
     double* tab = at<double>(workspace, L.tab);
     double* bp = at<double>(workspace, L.total);
-    hipError_t e = pd::launch_setup_value(theta, nt, param, g.fref, lambda, recs, status, s);
+    // records and grid tables in one launch
+    hipError_t e = pd::launch_setup_value(theta, nt, param, g.fref, lambda, recs, status, s, nullptr, &g, nullptr,
+                                          inv_psd, tab);
     if (e != hipSuccess) return fail_hip(e, "setup");
-    e = pd::launch_tables(g, nullptr, inv_psd, tab, s);
-    if (e != hipSuccess) return fail_hip(e, "tables");
     e = pd::launch_overlap(recs, nt, g, tab, data, ns, inv_psd, bp, overlap, hh, s);
     if (e != hipSuccess) return fail_hip(e, "overlap");
     return PD_OK;

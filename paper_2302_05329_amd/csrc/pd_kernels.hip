@@ -45,12 +45,34 @@ __device__ __forceinline__ void fit_params(const double* __restrict__ lam, const
     }
 }
 
+__device__ void tables_bin(const GridArgs& g, const double* __restrict__ data,
+                           const double* __restrict__ inv_psd, double* __restrict__ tab, int64_t k, int part);
+
+// The per-grid table job of a record setup launch (bt = 0: none).
+struct TablesJob {
+    GridArgs g;
+    const double* data;
+    const double* inv_psd;
+    double* tab;
+    unsigned bs, bt;   // setup blocks, table blocks per part (0: no tables)
+};
+
 // XF: theta is first computed from the sampler's coordinates (xform_point) and written out.
+// Blocks at or above tj.bs fill the per-grid tables instead (tj.bt blocks per table part): the
+// tables do not depend on the points, so they are built in the same launch as the records, on the
+// CUs the records leave idle (one thread per point), without a second launch after them.
 template <bool XF>
 __global__ void __launch_bounds__(128) k_setup_value(double* __restrict__ theta, int64_t n, int param,
                                                      double f_ref, const double* __restrict__ lam,
                                                      double* __restrict__ recs, int32_t* __restrict__ status,
-                                                     XForm xf) {
+                                                     XForm xf, TablesJob tj) {
+    if (blockIdx.x >= tj.bs) {
+        const unsigned t = blockIdx.x - tj.bs;
+        const int part = static_cast<int>(t / tj.bt);
+        tables_bin(tj.g, tj.data, tj.inv_psd, tj.tab, static_cast<int64_t>(t % tj.bt) * blockDim.x + threadIdx.x,
+                   part);
+        return;
+    }
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double th[7];
@@ -164,10 +186,8 @@ __global__ void __launch_bounds__(64) k_setup_fit_tangent(const double* __restri
 // data), each part a separate range of blocks (blockIdx.y): the table launch is a few waves per
 // SIMD, so its time is one thread's chain of calls, which this cuts to one call, and every wave
 // runs a single part (no divergent branches).
-__global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __restrict__ data,
-                                                const double* __restrict__ inv_psd, double* __restrict__ tab) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int part = static_cast<int>(blockIdx.y);
+__device__ void tables_bin(const GridArgs& g, const double* __restrict__ data,
+                           const double* __restrict__ inv_psd, double* __restrict__ tab, int64_t k, int part) {
     if (k >= g.nb) return;
     const double f = bin_freq(g, k);
     const bool pos = f > 0.0;
@@ -203,6 +223,12 @@ __global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __rest
         tab[T_DWI * nb + k] = dwi;
         tab[T_WW * nb + k] = ww;
     }
+}
+
+__global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __restrict__ data,
+                                                const double* __restrict__ inv_psd, double* __restrict__ tab) {
+    tables_bin(g, data, inv_psd, tab, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x,
+               static_cast<int>(blockIdx.y));
 }
 
 // ==================================================================================
@@ -906,13 +932,25 @@ static inline unsigned blocks_for(int64_t threads, int per_block) {
 }
 
 hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
-                              double* recs, int32_t* status, hipStream_t s, const XForm* xf) {
+                              double* recs, int32_t* status, hipStream_t s, const XForm* xf, const GridArgs* tg,
+                              const double* data, const double* inv_psd, double* tab) {
+    TablesJob tj{};
+    tj.bs = blocks_for(n, 128);
+    unsigned blocks = tj.bs;
+    if (tg) {
+        tj.g = *tg;
+        tj.data = data;
+        tj.inv_psd = inv_psd;
+        tj.tab = tab;
+        tj.bt = blocks_for(tg->nb, 128);
+        blocks += 4 * tj.bt;
+    }
     if (xf)
-        hipLaunchKernelGGL(k_setup_value<true>, dim3(blocks_for(n, 128)), dim3(128), 0, s,
-                           const_cast<double*>(theta), n, param, f_ref, lam, recs, status, *xf);
+        hipLaunchKernelGGL(k_setup_value<true>, dim3(blocks), dim3(128), 0, s, const_cast<double*>(theta), n, param,
+                           f_ref, lam, recs, status, *xf, tj);
     else
-        hipLaunchKernelGGL(k_setup_value<false>, dim3(blocks_for(n, 128)), dim3(128), 0, s,
-                           const_cast<double*>(theta), n, param, f_ref, lam, recs, status, XForm{});
+        hipLaunchKernelGGL(k_setup_value<false>, dim3(blocks), dim3(128), 0, s, const_cast<double*>(theta), n, param,
+                           f_ref, lam, recs, status, XForm{}, tj);
     return hipGetLastError();
 }
 

@@ -60,9 +60,13 @@ inline int chunks_for(int64_t n, int64_t n_bins) {
     return static_cast<int>(c);
 }
 
-// xf (or NULL): theta is computed from the sampler's coordinates first and written to `theta`
+// xf (or NULL): theta is computed from the sampler's coordinates first and written to `theta`.
+// tg (or NULL): the same launch also fills the per-grid tables of grid *tg into tab (as
+// launch_tables with data, inv_psd), on blocks of their own.
 hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
-                              double* recs, int32_t* status, hipStream_t s, const XForm* xf = nullptr);
+                              double* recs, int32_t* status, hipStream_t s, const XForm* xf = nullptr,
+                              const GridArgs* tg = nullptr, const double* data = nullptr,
+                              const double* inv_psd = nullptr, double* tab = nullptr);
 hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param, double f_ref,
                                       const double* lam, int rows, double* tans, hipStream_t s);
 hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, double f_ref, const double* lam,
