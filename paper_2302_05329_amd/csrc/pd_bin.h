@@ -170,13 +170,14 @@ __device__ __forceinline__ void load_segments(const int* __restrict__ src, Segs&
     }
 }
 
-// Record accessor for the merger-ringdown loops of the fused likelihood: the record plus products of
-// its entries formed once per segment (FP64 products of two per-point constants would otherwise be
-// recomputed in every bin, as there is no scalar FP64 arithmetic).  The merger-ringdown amplitude
-// numerator R_AM3 is folded into the exponential recurrence by the caller.
+// Record accessor for the merger-ringdown loops (fused likelihood, Fisher pass, mismatch column
+// pass and adjoint): the record plus products of its entries formed once per segment (FP64
+// products of two per-point constants would otherwise be recomputed in every bin, as there is no
+// scalar FP64 arithmetic) and the arc tangent table.  With the exponential recurrence, the
+// merger-ringdown amplitude numerator R_AM3 is folded into the recurrence by the caller.
 struct RecMRD {
     const double* __restrict__ p;
-    const double2* __restrict__ atab;   // arc tangent table (c_j, atan c_j), staged in LDS
+    const double2* __restrict__ atab;   // arc tangent table (c_j, atan c_j): an LDS copy or kAtanTab
     double q_id;   // R_PH3+5 * R_ID: u = Mf R_ID - q_id
     double g2;     // R_AM3+2 ^ 2
     double c4id;   // R_PH3+4 * R_ID
@@ -268,8 +269,8 @@ __device__ __forceinline__ void eval_bin_t(RC c, const TB& T, KI k, double mf,
             u = fma(mf, c[R_ID], -c.q_id);
         else
             u = (mf - c[R_PH3 + 5]) * c[R_ID];
-        // the fused likelihood's record carries an LDS arc tangent table: the table reduction
-        // (no branches, a shorter polynomial); the other callers keep the two-level reduction
+        // the merger-ringdown record form (RecMRD) carries an arc tangent table: the table
+        // reduction (no branches, a shorter polynomial); a plain record keeps the two-level one
         using AP = std::conditional_t<D, AtanTabParts, AtanParts>;
         AP ap;
         if constexpr (D)

@@ -182,10 +182,10 @@ __global__ void __launch_bounds__(64) k_setup_fit_tangent(const double* __restri
 // per-grid tables
 // ==================================================================================
 
-// Four parts per bin, one per transcendental (cbrt; log; f^(3/4); f^(-7/6) with the weighted
-// data), each part a separate range of blocks (blockIdx.y): the table launch is a few waves per
-// SIMD, so its time is one thread's chain of calls, which this cuts to one call, and every wave
-// runs a single part (no divergent branches).
+// Bin k's part `part` of the per-grid tables: four parts per bin, one per transcendental (cbrt;
+// log; f^(3/4); f^(-7/6) with the weighted data), each taken by its own range of blocks of the
+// record setup launch: the table blocks are a few waves per SIMD, so their time is one thread's
+// chain of calls, which this cuts to one call, and every wave runs a single part (no divergence).
 __device__ void tables_bin(const GridArgs& g, const double* __restrict__ data,
                            const double* __restrict__ inv_psd, double* __restrict__ tab, int64_t k, int part) {
     if (k >= g.nb) return;
@@ -225,11 +225,6 @@ __device__ void tables_bin(const GridArgs& g, const double* __restrict__ data,
     }
 }
 
-__global__ void __launch_bounds__(256) k_tables(GridArgs g, const double* __restrict__ data,
-                                                const double* __restrict__ inv_psd, double* __restrict__ tab) {
-    tables_bin(g, data, inv_psd, tab, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x,
-               static_cast<int>(blockIdx.y));
-}
 
 // ==================================================================================
 // strain output
@@ -969,12 +964,6 @@ hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, d
                                     const double* recs, double* tans, hipStream_t s) {
     hipLaunchKernelGGL(k_setup_fit_tangent, dim3(blocks_for(n * kNumFit, 64)), dim3(64), 0, s, theta, n, param,
                        f_ref, lam, recs, tans);
-    return hipGetLastError();
-}
-
-hipError_t launch_tables(const GridArgs& g, const double* data, const double* inv_psd, double* tab,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_tables, dim3(blocks_for(g.nb, 256), 4), dim3(256), 0, s, g, data, inv_psd, tab);
     return hipGetLastError();
 }
 

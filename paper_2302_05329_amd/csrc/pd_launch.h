@@ -61,8 +61,8 @@ inline int chunks_for(int64_t n, int64_t n_bins) {
 }
 
 // xf (or NULL): theta is computed from the sampler's coordinates first and written to `theta`.
-// tg (or NULL): the same launch also fills the per-grid tables of grid *tg into tab (as
-// launch_tables with data, inv_psd), on blocks of their own.
+// tg (or NULL): the same launch also fills the per-grid tables of grid *tg into tab (from
+// data and inv_psd, either of which may be NULL), on blocks of their own.
 hipError_t launch_setup_value(const double* theta, int64_t n, int param, double f_ref, const double* lam,
                               double* recs, int32_t* status, hipStream_t s, const XForm* xf = nullptr,
                               const GridArgs* tg = nullptr, const double* data = nullptr,
@@ -71,8 +71,6 @@ hipError_t launch_setup_theta_tangent(const double* theta, int64_t n, int param,
                                       const double* lam, int rows, double* tans, hipStream_t s);
 hipError_t launch_setup_fit_tangent(const double* theta, int64_t n, int param, double f_ref, const double* lam,
                                     const double* recs, double* tans, hipStream_t s);
-hipError_t launch_tables(const GridArgs& g, const double* data, const double* inv_psd, double* tab,
-                         hipStream_t s);
 hipError_t launch_waveform(const double* recs, int64_t n, const GridArgs& g, const double* tab, int precision,
                            double* h, hipStream_t s);
 // tail (gradient passes only, or NULL): the sampler's per-point tail applied by the epilogue

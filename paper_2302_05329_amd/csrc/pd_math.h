@@ -3,15 +3,18 @@
 // Each is a textbook construction written for this project: Cody-Waite argument
 // reduction with split constants and fused multiply-adds, then a polynomial on the
 // reduced interval.  The atan and exp polynomial coefficients are Chebyshev interpolants
-// computed in 60-digit arithmetic and rounded to double, and the sin/cos table holds
-// correctly rounded values (fit_elementary.py, next to this file, writes both); the
+// computed in 60-digit arithmetic and rounded to double, and the sin/cos and arc tangent tables
+// hold correctly rounded values (fit_elementary.py, next to this file, writes them); the
 // measured worst error of each function is about 1 ulp.
 //
 //   pd_sincos  |x| <= 2^24: q = rint(256x/pi), r = x - q pi/256 (two-part pi/256), short
 //              polynomials on |r| <= pi/512 combined with a 512-entry (sin, cos) table.
-//              Larger |x| falls back to the device library's sincos.
+//              Larger |x| falls back to the device library's sincos.  pd_rotate_data applies
+//              the same pieces to a complex number directly.
 //   pd_atan    |u| > 1 uses pi/2 - atan(1/u); t > tan(pi/12) uses atan(t) = pi/6 +
 //              atan((sqrt3 t - 1)/(t + sqrt3)); both reductions share one division.
+//   pd_atan_tab_*  atan c + atan((|u| - c)/(1 + |u| c)) with c from a 321-entry table indexed
+//              by the exponent and top mantissa bits of |u|; no branches.
 //   pd_exp     y = k ln2 + r (two-part ln2), |r| <= ln2/2, exp(y) = 2^k exp(r).
 #pragma once
 #include <hip/hip_runtime.h>
