@@ -275,14 +275,18 @@ __global__ void __launch_bounds__(256) k_waveform(const double* __restrict__ rec
 // ==================================================================================
 
 // Moments sum_k z_k b_k of the basis values; the Mf-derivative moment is formed after the loop
-// (fd_from_moments) from them and the two extra sums x[0] (phase) and x[1] (amplitude).
+// (fd_from_moments) from them and the two extra sums x[0] (phase) and x[1] (amplitude).  The ln A0
+// moment, sum zr = sum (px - a0p q), is formed after the loop from the segment's (d|h) and (h|h)
+// sums, which the loop keeps anyway, so it is not accumulated per bin.
 struct MomVis {
     static constexpr bool kFd = false;
     double* mom;
     double* x;
     double zr, zi;
     __device__ __forceinline__ void ph(int s, double b) { mom[s] = fma(zi, b, mom[s]); }
-    __device__ __forceinline__ void am(int s, double b) { mom[s] = fma(zr, b, mom[s]); }
+    __device__ __forceinline__ void am(int s, double b) {
+        if (s != R_LNA0) mom[s] = fma(zr, b, mom[s]);
+    }
     __device__ __forceinline__ void ph_x(double b) { x[0] = fma(zi, b, x[0]); }
     __device__ __forceinline__ void am_x(double b) { x[1] = fma(zr, b, x[1]); }
 };
@@ -322,6 +326,7 @@ struct LnlSegment {
 #pragma unroll
         for (int s = 0; s < REC_N; ++s) mom[s] = 0.0;
         double mx[2] = {0.0, 0.0};
+        double dh_s = 0.0, hh_s = 0.0;   // this segment's (d|h) and (h|h) sums
         ExpRec er{};
         if (AR == 3) er.init(rec, g, static_cast<unsigned>(k0 + lane), D ? rec[R_AM3 + 0] : 1.0);
         for (unsigned k = static_cast<unsigned>(k0 + lane); k < static_cast<unsigned>(k1); k += 64u) {
@@ -364,15 +369,18 @@ struct LnlSegment {
                 px = fma(dwr, hr, dwi * hi);
             }
             const double q = ww * bv.ahat * bv.ahat;
-            dh += px;
-            hh += q;
+            dh_s += px;
+            hh_s += q;
             if (MODE == 1) {
                 if constexpr (PR == 1) py = fma(dwr, hi, -dwi * hr);
                 MomVis vis{mom, mx, fma(-a0p, q, px), py};
                 visit_bin_t<PR, AR>(c, bv, vis);
             }
         }
+        dh += dh_s;
+        hh += hh_s;
         if (MODE == 1) {
+            mom[R_LNA0] = fma(-a0p, hh_s, dh_s);
             // (the inspiral loops read the record itself: its copy there measured more vector copies)
             fd_from_moments<PR, AR, D>(PR == 1 ? rec : recl, mom, mx[0], mx[1]);
             if (D && AR == 3) mom[R_AM3 + 0] = rec[R_IANUM] * mom[R_LNA0];
