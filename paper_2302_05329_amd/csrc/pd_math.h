@@ -7,8 +7,8 @@
 // hold correctly rounded values (fit_elementary.py, next to this file, writes them); the
 // measured worst error of each function is about 1 ulp.
 //
-//   pd_sincos  |x| <= 2^24: q = rint(256x/pi), r = x - q pi/256 (two-part pi/256), short
-//              polynomials on |r| <= pi/512 combined with a 512-entry (sin, cos) table.
+//   pd_sincos  |x| <= 2^24: q = rint(512x/pi), r = x - q pi/512 (two-part pi/512), short
+//              polynomials on |r| <= pi/1024 combined with a 1024-entry (sin, cos) table.
 //              Larger |x| falls back to the device library's sincos.  pd_rotate_data applies
 //              the same pieces to a complex number directly.
 //   pd_atan    |u| > 1 uses pi/2 - atan(1/u); t > tan(pi/12) uses atan(t) = pi/6 +
@@ -33,20 +33,22 @@ __device__ __forceinline__ double sk(double c) {
     return c;
 }
 
-// Table-driven sin and cos of one argument: x = q pi/256 + r with |r| <= pi/512 (two-part
-// pi/256, fused multiply-adds), j = q mod 512, and
+// Table-driven sin and cos of one argument: x = q pi/512 + r with |r| <= pi/1024 (two-part
+// pi/512, fused multiply-adds), j = q mod 1024, and
 //   sin x = S_j + (S_j (cos r - 1) + C_j sin r),  cos x = C_j + (C_j (cos r - 1) - S_j sin r)
-// with (S_j, C_j) = (sin, cos)(j pi/256) correctly rounded (pd_sincos_table.h) and Taylor
-// polynomials on the small interval (sin r through r^5, cos r - 1 through r^6; the first omitted
-// terms are below 1.1e-17 and 2e-22 relative).  About 1 ulp.  |x| > 2^24 uses the device library.
-// Two parts of pi/256 suffice: the first is pi/256 rounded to double and the second the rounded
-// remainder, so the part left out is below 1.2e-35 and |q| <= 2^24 * 256/pi < 1.4e9 puts at most
-// 1.7e-26 into r, where an ulp of r (|r| <= pi/512) is about 8.7e-19.
+// with (S_j, C_j) = (sin, cos)(j pi/512) correctly rounded (pd_sincos_table.h) and Taylor
+// polynomials on the small interval: sin r through r^5 (the first omitted term is below 1.7e-19
+// of sin r) and cos r - 1 through r^4 (the omitted r^6/720 is below 1.2e-18, and enters cos x
+// times C_j).  About 1 ulp.  |x| > 2^24 uses the device library.  Two parts of pi/512 suffice:
+// the first is pi/512 rounded to double and the second the rounded remainder, so the part left
+// out is below 5.9e-36 and |q| <= 2^24 * 512/pi < 2.8e9 puts at most 1.6e-26 into r, where an ulp
+// of r (|r| <= pi/1024) is about 3.4e-19.  (The 1024-entry table, against 512, is what lets
+// cos r - 1 stop at r^4: one multiply-add whose constant -1/2 is an inline operand.)
 constexpr double kTs1 = -1.0 / 6.0, kTs2 = 1.0 / 120.0;
-constexpr double kTc1 = -0.5, kTc2 = 1.0 / 24.0, kTc3 = -1.0 / 720.0;
+constexpr double kTc2 = 1.0 / 24.0;
 
 // TAB: the (sin, cos) table, in constant memory (default) or a copy staged in LDS by the caller.
-// The quotient is rounded with the 1.5 * 2^52 shift: fma(x, 256/pi, 1.5 * 2^52) rounds x 256/pi to
+// The quotient is rounded with the 1.5 * 2^52 shift: fma(x, 512/pi, 1.5 * 2^52) rounds x 512/pi to
 // the nearest integer (ties to even, the product unrounded) and leaves it in the low mantissa bits,
 // so the table index is a bit mask of the low word; |x| <= 2^24 keeps it far inside 2^51.
 constexpr double kRoundShift = 6755399441055744.0;   // 1.5 * 2^52
@@ -71,9 +73,7 @@ __device__ __forceinline__ SinCosParts pd_sincos_parts(double x, const double2* 
     p.s = sc.x;
     p.c = sc.y;
     p.sr = fma(r * z, fma(sk(kTs2), z, sk(kTs1)), r);
-    double pc = fma(sk(kTc3), z, sk(kTc2));
-    pc = fma(pc, z, sk(kTc1));
-    p.cm = z * pc;
+    p.cm = z * fma(z, sk(kTc2), -0.5);
     return p;
 }
 

@@ -1,8 +1,8 @@
 """The generated constant tables the kernels read (host checks, no GPU).
 
-* the (sin, cos) table: entry j is (sin, cos)(j pi/256) correctly rounded (within 1e-60 at the
-  exact zeros), and the two parts
-  of pi/256 used by the argument reduction sum to pi/256 within 2e-34;
+* the (sin, cos) table: entry j is (sin, cos)(j pi/512) correctly rounded (within 1e-60 at the
+  exact zeros), and the two parts of pi/512 used by the argument reduction sum to pi/512
+  within 2e-34;
 * the arc tangent table: entry 0 is (0, 0); entry j >= 1 is the midpoint c of bucket j (16 per
   octave of |u| from 2^-10 to 2^10, exactly representable) and atan c correctly rounded; the
   kernels' index (bits 16-30 of the high word of |u|, minus the base, clamped) selects the bucket
@@ -38,7 +38,7 @@ def test_sincos_table_is_correctly_rounded():
     t = _header("pd_sincos_table.h")
     tab = _pairs(t)
     n = int(_const(t, "kSinCosN"))
-    assert tab.shape == (n, 2) and n == 512
+    assert tab.shape == (n, 2) and n == 1024
     with mp.workdps(60):
         for j in range(n):
             a = mp.mpf(j) * 2 * mp.pi / n
