@@ -23,7 +23,7 @@ n_k = (k - k_peak) / 64 steps at bin k past the first bin k_peak of that amplitu
     tol = 1e-10 + C_PSI sum_k w_k |d_k| |h_k| ulp(S_k)
                 + 2^-53 sum_k w_k (|d_k| + |h_k|) |h_k| (C_AMP + C_REC n_k)
 
-The sums over bins are the coherent worst case; 1e-10 is the absolute floor the benchmark spec sets.
+The sums over bins are the coherent worst case; 1e-10 is the absolute floor of the ln L parity target.
 
 Network.  A site's strain is the model at effective parameters (D/|c|, tc + dt, phic + arg(c)/2),
 so the network bound is the sum over sites of the bound above with S_k also covering
