@@ -33,8 +33,11 @@ positive definiteness, gradients against central differences, noise-free likelih
 stationarity, FFT match against a brute-force DFT, lag invariance and total-mass
 invariance of the match on an Mf grid with a flat PSD, the first-order decrease of the mean
 mismatch under a small descent step.
-Parity unpinned (model fidelity): the spin-dependent PN phase and amplitude terms, the
-PN amplitude coefficients beyond 1PN, the final-spin / radiated-energy / ring-down
+The spin-orbit parts of the phase coefficients (1.5, 2.5, 3 and 3.5PN) and the 2PN spin-spin
+terms (the two bodies' interaction, and each body's spin squared through the Kerr test-mass
+limit) are pinned by derivations from the spinning binding energy and flux.
+Parity unpinned (model fidelity): the 3PN spin-spin phase terms, the spin parts of the PN
+amplitude coefficients and those beyond 1PN, the final-spin / radiated-energy / ring-down
 stand-ins and the placeholder coefficient table — nothing available here fixes their
 published values.
 """
