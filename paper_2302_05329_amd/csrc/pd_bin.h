@@ -171,12 +171,15 @@ __device__ __forceinline__ void load_segments(const int* __restrict__ src, Segs&
 }
 
 // Record accessor for the merger-ringdown loops (fused likelihood, Fisher pass, mismatch column
-// pass and adjoint): the record plus products of its entries formed once per segment (FP64
-// products of two per-point constants would otherwise be recomputed in every bin, as there is no
-// scalar FP64 arithmetic) and the arc tangent table.  With the exponential recurrence, the
-// merger-ringdown amplitude numerator R_AM3 is folded into the recurrence by the caller.
-struct RecMRD {
-    const double* __restrict__ p;
+// pass and adjoint, template generation of the overlap bank): the record plus products of its
+// entries formed once per segment (FP64 products of two per-point constants would otherwise be
+// recomputed in every bin, as there is no scalar FP64 arithmetic) and the arc tangent table.
+// With the exponential recurrence, the merger-ringdown amplitude numerator R_AM3 is folded into
+// the recurrence by the caller.  R: how the record is read (a pointer, or any type whose
+// operator[] returns entry i).
+template <class R = const double*>
+struct RecMRDT {
+    R p;
     const double2* __restrict__ atab;   // arc tangent table (c_j, atan c_j): an LDS copy or kAtanTab
     double q_id;   // R_PH3+5 * R_ID: u = Mf R_ID - q_id
     double g2;     // R_AM3+2 ^ 2
@@ -185,13 +188,14 @@ struct RecMRD {
     double m2g;    // -2 R_AM3+2
     __device__ __forceinline__ double operator[](int i) const { return p[i]; }
 };
+using RecMRD = RecMRDT<>;
 
 template <class RC>
 struct IsRecMRD {
     static constexpr bool value = false;
 };
-template <>
-struct IsRecMRD<RecMRD> {
+template <class R>
+struct IsRecMRD<RecMRDT<R>> {
     static constexpr bool value = true;
 };
 
@@ -203,8 +207,9 @@ __device__ __forceinline__ double uniform_d(double x) {
     return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
-__device__ __forceinline__ RecMRD rec_mrd(const double* __restrict__ c, const double2* __restrict__ atab) {
-    RecMRD r;
+template <class R>
+__device__ __forceinline__ RecMRDT<R> rec_mrd(R c, const double2* __restrict__ atab) {
+    RecMRDT<R> r;
     r.p = c;
     r.atab = atab;
     r.q_id = uniform_d(c[R_PH3 + 5] * c[R_ID]);

@@ -177,6 +177,9 @@ __global__ void __launch_bounds__(256, 4) k_ov_gemm(const double* __restrict__ r
             bt.load(T, kc);
             // the next row's record and active range are fetched while this row is evaluated
             const int64_t t0 = tb + kRPW * w;
+            // merger-ringdown template bins: the record form with the table-reduced arc tangent
+            // (table in constant memory)
+            const double2* __restrict__ atab = reinterpret_cast<const double2*>(kAtanTab);
             auto rec_fetch = [&](int j) -> double {
                 const int64_t t = t0 + j;
                 return (t < nt && lane < REC_N) ? recs[t * REC_N + lane] : 0.0;
@@ -217,8 +220,8 @@ __global__ void __launch_bounds__(256, 4) k_ov_gemm(const double* __restrict__ r
                     case 4 * 1 + 3: gen_bin<1, 3>(rec, bt, kc, mf, on, arow, lane, sw); break;
                     case 4 * 2 + 2: gen_bin<2, 2>(rec, bt, kc, mf, on, arow, lane, sw); break;
                     case 4 * 2 + 3: gen_bin<2, 3>(rec, bt, kc, mf, on, arow, lane, sw); break;
-                    case 4 * 3 + 2: gen_bin<3, 2>(rec, bt, kc, mf, on, arow, lane, sw); break;
-                    case 4 * 3 + 3: gen_bin<3, 3>(rec, bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 3 + 2: gen_bin<3, 2>(rec_mrd(rec, atab), bt, kc, mf, on, arow, lane, sw); break;
+                    case 4 * 3 + 3: gen_bin<3, 3>(rec_mrd(rec, atab), bt, kc, mf, on, arow, lane, sw); break;
                     default: {
                         double amp = 0.0, psi = 0.0;
                         if (on) {
